@@ -1,0 +1,277 @@
+"""ORACLE -- test infrastructure only (Python side of the serial CPU oracle).
+
+Loads ``slpf_oracle.c`` (built with gcc into ``liboracle.so`` next to it) and
+adds, in plain Python on top of its set primitives, the quantities of the
+paper's parallel algorithm (Sect. 3.2: Eq. reacher, joiner, builder, merger)
+so that they can be checked against the worked example and against the GPU
+library's intermediate results.  Only tests, the smoke check and the
+benchmark's CPU-baseline leg import this module.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "slpf_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile the C oracle (plain gcc -O2, single-threaded)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-o", tmp, _SRC])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_LIB)
+        vp, u64p, i32p = ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_int32)
+        L.oracle_compile.argtypes = [ctypes.c_char_p, ctypes.c_size_t, ctypes.c_int,
+                                     ctypes.POINTER(vp), ctypes.POINTER(ctypes.c_size_t)]
+        L.oracle_compile.restype = ctypes.c_int
+        L.oracle_free.argtypes = [vp]
+        for f in ("oracle_num_segments", "oracle_words", "oracle_num_nodes"):
+            getattr(L, f).argtypes = [vp]
+            getattr(L, f).restype = ctypes.c_int
+        for f in ("oracle_initial", "oracle_final"):
+            getattr(L, f).argtypes = [vp, u64p]
+        L.oracle_folseg.argtypes = [vp, ctypes.c_int, u64p]
+        L.oracle_label.argtypes = [vp, ctypes.c_int]
+        L.oracle_label.restype = ctypes.c_int
+        L.oracle_segment_text.argtypes = [vp, ctypes.c_int, ctypes.c_char_p, ctypes.c_size_t]
+        L.oracle_segment_text.restype = ctypes.c_size_t
+        L.oracle_step_fwd.argtypes = [vp, u64p, ctypes.c_int, u64p]
+        L.oracle_step_bwd.argtypes = [vp, u64p, ctypes.c_int, u64p]
+        L.oracle_parse.argtypes = [vp, ctypes.c_char_p, ctypes.c_uint64, u64p, u64p]
+        L.oracle_parse.restype = ctypes.c_int
+        L.oracle_parse_dfa.argtypes = [vp, ctypes.c_char_p, ctypes.c_uint64, ctypes.c_int, u64p,
+                                       ctypes.c_uint64, u64p, u64p]
+        L.oracle_parse_dfa.restype = ctypes.c_int
+        L.oracle_powerset.argtypes = [vp, ctypes.c_int, u64p, ctypes.c_int, i32p, ctypes.c_int,
+                                      ctypes.c_int, u64p, i32p]
+        L.oracle_powerset.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _u64(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+
+
+class OracleError(Exception):
+    def __init__(self, status, offset=None):
+        super().__init__("oracle compile failed: status %d offset %s" % (status, offset))
+        self.status = status
+        self.offset = offset
+
+
+STATUS_SYNTAX, STATUS_INF_AMBIG, STATUS_TOO_LARGE = -2, -3, -4
+
+
+def _bytes(x):
+    if isinstance(x, str):
+        return x.encode("latin1")
+    if isinstance(x, np.ndarray):
+        return x.tobytes()
+    return bytes(x)
+
+
+class Oracle:
+    """The parser automaton of one RE plus the serial parsers over it."""
+
+    def __init__(self, re, max_segments: int = 1 << 16):
+        L = _load()
+        b = _bytes(re)
+        h = ctypes.c_void_p()
+        off = ctypes.c_size_t(0)
+        st = L.oracle_compile(b, len(b), max_segments, ctypes.byref(h), ctypes.byref(off))
+        if st != 0:
+            raise OracleError(st, off.value if st == STATUS_SYNTAX else None)
+        self._h = h
+        self._L = L
+        self.nseg = L.oracle_num_segments(h)
+        self.W = L.oracle_words(h)
+        self.segments = [self._seg_text(i) for i in range(self.nseg)]
+        self.labels = [L.oracle_label(h, i) for i in range(self.nseg)]
+        self.I = self._words(L.oracle_initial)
+        self.F = self._words(L.oracle_final)
+        self.folseg = []
+        for i in range(self.nseg):
+            w = np.zeros(self.W, np.uint64)
+            L.oracle_folseg(h, i, _u64(w))
+            self.folseg.append(self.to_set(w))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self._L.oracle_free(h)
+            self._h = None
+
+    def _seg_text(self, i):
+        need = self._L.oracle_segment_text(self._h, i, None, 0)
+        buf = ctypes.create_string_buffer(need + 1)
+        self._L.oracle_segment_text(self._h, i, buf, need + 1)
+        return buf.value.decode("utf-8")
+
+    def _words(self, fn):
+        w = np.zeros(self.W, np.uint64)
+        fn(self._h, _u64(w))
+        return self.to_set(w)
+
+    # -- sets <-> words
+    def to_words(self, s) -> np.ndarray:
+        w = np.zeros(self.W, np.uint64)
+        for i in s:
+            w[i >> 6] |= np.uint64(1) << np.uint64(i & 63)
+        return w
+
+    def to_set(self, w) -> frozenset:
+        out = []
+        for k, v in enumerate(np.asarray(w, dtype=np.uint64).tolist()):
+            while v:
+                b = (v & -v).bit_length() - 1
+                out.append(64 * k + b)
+                v &= v - 1
+        return frozenset(out)
+
+    def seg_id(self, text: str) -> int:
+        return self.segments.index(text)
+
+    # -- NFA steps (Eq. matrixmul)
+    def step_fwd(self, s, a: int) -> frozenset:
+        w = self.to_words(s)
+        o = np.zeros(self.W, np.uint64)
+        self._L.oracle_step_fwd(self._h, _u64(w), a, _u64(o))
+        return self.to_set(o)
+
+    def step_bwd(self, s, a: int) -> frozenset:
+        w = self.to_words(s)
+        o = np.zeros(self.W, np.uint64)
+        self._L.oracle_step_bwd(self._h, _u64(w), a, _u64(o))
+        return self.to_set(o)
+
+    # -- serial parsers
+    def parse(self, text):
+        """Serial NFA parser (Fig. serialparser): (cols[(n+1), W] uint64, accepted, count)."""
+        x = _bytes(text)
+        n = len(x)
+        cols = np.zeros((n + 1, self.W), np.uint64)
+        sc = np.zeros(2, np.uint64)
+        self._L.oracle_parse(self._h, x, n, _u64(cols), _u64(sc))
+        return cols, bool(sc[0]), int(sc[1])
+
+    def parse_dfa(self, text, win_starts=(), win_len: int = 0):
+        """DFA-lookup serial parser; returns (window columns [nwin, win_len, W], accepted, count)."""
+        x = _bytes(text) if not isinstance(text, np.ndarray) else text
+        if isinstance(x, np.ndarray):
+            n = x.size
+            xp = x.ctypes.data_as(ctypes.c_char_p)
+        else:
+            n = len(x)
+            xp = x
+        ws = np.ascontiguousarray(np.asarray(win_starts, dtype=np.uint64))
+        out = np.zeros((len(ws), max(win_len, 0), self.W), np.uint64)
+        sc = np.zeros(2, np.uint64)
+        st = self._L.oracle_parse_dfa(self._h, xp, n, len(ws), _u64(ws) if len(ws) else None,
+                                      win_len, _u64(out) if out.size else None, _u64(sc))
+        if st != 0:
+            raise MemoryError("oracle_parse_dfa failed")
+        return out, bool(sc[0]), int(sc[1])
+
+    def columns(self, text):
+        cols, acc, cnt = self.parse(text)
+        return [self.to_set(c) for c in cols], acc, cnt
+
+    # -- automata by powerset (Sect. 3.1)
+    def powerset(self, seeds, direction: int = 0, alphabet=None, max_states: int = 1 << 20):
+        """States (as frozensets, BFS order from the seeds) and transitions
+        {(state_index, byte): state_index or None}."""
+        if alphabet is None:
+            alphabet = sorted({a for a in self.labels if a >= 0})
+        seeds = list(seeds)
+        sw = np.stack([self.to_words(s) for s in seeds]) if seeds else np.zeros((0, self.W), np.uint64)
+        sw = np.ascontiguousarray(sw)
+        al = np.ascontiguousarray(np.asarray(alphabet, dtype=np.int32))
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        ns = self._L.oracle_powerset(self._h, direction, _u64(sw), len(seeds), al.ctypes.data_as(i32p),
+                                     len(alphabet), max_states, None, None)
+        if ns < 0:
+            raise OracleError(STATUS_TOO_LARGE)
+        sets = np.zeros((ns, self.W), np.uint64)
+        nxt = np.zeros((ns, len(alphabet)), np.int32)
+        self._L.oracle_powerset(self._h, direction, _u64(sw), len(seeds), al.ctypes.data_as(i32p),
+                                len(alphabet), max_states, _u64(sets), nxt.ctypes.data_as(i32p))
+        states = [self.to_set(s) for s in sets]
+        trans = {}
+        for i in range(ns):
+            for k, a in enumerate(alphabet):
+                t = int(nxt[i, k])
+                trans[(i, a)] = None if t < 0 else t
+        return states, trans
+
+    def dfa(self, alphabet=None):
+        """The parser DFA: powerset from I (forward)."""
+        return self.powerset([self.I], 0, alphabet)
+
+    def medfa(self, alphabet=None):
+        """The multi-entry DFA: powerset from every singleton {q_j} (forward)."""
+        return self.powerset([frozenset([j]) for j in range(self.nseg)], 0, alphabet)
+
+    # -- the parallel algorithm's quantities (Sect. 3.2), plain Python
+    def run_fwd(self, s, y):
+        for a in y:
+            s = self.step_fwd(s, a)
+        return s
+
+    def run_bwd(self, s, y):
+        for a in reversed(y):
+            s = self.step_bwd(s, a)
+        return s
+
+    def parallel_trace(self, text, k: int):
+        """R, R^, J, J^, B, B^, M and C of Eq. reacher/joiner/builder/merger for
+        chunks of length k (the last chunk may be shorter).
+
+        Chunks are 1-based as in the paper: y_1..y_c; J[0..c], Jh[1..c+1]
+        (index 0 unused); B[r], Bh[r], M[r] indexed by text position r = 1..n.
+        """
+        x = _bytes(text)
+        n = len(x)
+        chunks = [x[i:i + k] for i in range(0, n, k)]
+        c = len(chunks)
+        Q = range(self.nseg)
+        R = {(i + 1, j): self.run_fwd(frozenset([j]), y) for i, y in enumerate(chunks) for j in Q}
+        Rh = {(i + 1, j): self.run_bwd(frozenset([j]), y) for i, y in enumerate(chunks) for j in Q}
+        J = [self.I]
+        for i in range(1, c + 1):
+            J.append(frozenset().union(*[R[(i, j)] for j in J[i - 1]]))
+        Jh = [None] * (c + 2)
+        Jh[c + 1] = self.F
+        for i in range(c, 0, -1):
+            Jh[i] = frozenset().union(*[Rh[(i, j)] for j in Jh[i + 1]])
+        B, Bh, M = {}, {}, {}
+        for i, y in enumerate(chunks, start=1):
+            base = (i - 1) * k
+            s = J[i - 1]
+            for t, a in enumerate(y, start=1):
+                s = self.step_fwd(s, a)
+                B[base + t] = s
+            s = Jh[i + 1]
+            Bh[base + len(y)] = s
+            for t in range(len(y) - 1, 0, -1):
+                s = self.step_bwd(s, y[t])
+                Bh[base + t] = s
+            for t in range(1, len(y) + 1):
+                M[base + t] = B[base + t] & Bh[base + t]
+        C = [J[0] & Jh[1]] + [M[r] for r in range(1, n + 1)]
+        return dict(R=R, Rh=Rh, J=J, Jh=Jh, B=B, Bh=Bh, M=M, C=C)

@@ -1,0 +1,327 @@
+"""Pins of the CPU oracle against values fixed by the paper and by mathematics.
+
+Every check here is independent of the oracle's own code: worked-example
+values printed in arXiv 2503.06763 (tests/golden/*.yaml, each citing its
+source), a brute-force tree enumerator with its own RE reader
+(tests/lst_brute.py), Python's ``re`` module for acceptance, closed forms, and
+invariants of the SLPF.
+"""
+import itertools
+import os
+import re
+
+import numpy as np
+import pytest
+import yaml
+
+import lst_brute
+from gen import regen
+from oracle.oracle import Oracle, OracleError, STATUS_INF_AMBIG, STATUS_SYNTAX
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def load(name):
+    with open(os.path.join(GOLDEN, name), encoding="utf-8") as f:
+        return yaml.safe_load(f)
+
+
+# ------------------------------------------------------------ e2 (Sect. 2-3)
+
+@pytest.fixture(scope="module")
+def e2():
+    g = load("e2.yaml")
+    o = Oracle(g["re"])
+    # paper number -> oracle id, through the segment strings
+    pid = {int(k): o.seg_id(v) for k, v in g["segments"].items()}
+    return g, o, pid
+
+
+def _ids(pid, nums):
+    return frozenset(pid[int(x)] for x in nums)
+
+
+def test_e2_segments(e2):
+    g, o, pid = e2
+    assert sorted(o.segments) == sorted(g["segments"].values())
+    assert o.I == _ids(pid, g["initial"])
+    assert o.F == _ids(pid, g["final"])
+
+
+def test_e2_folseg(e2):
+    g, o, pid = e2
+    for p, fol in g["folseg"].items():
+        assert o.folseg[pid[int(p)]] == _ids(pid, fol), p
+
+
+def _check_automaton(o, pid, states, trans, gold):
+    named = {name: _ids(pid, segs) for name, segs in gold["states"].items()}
+    assert sorted(map(sorted, states)) == sorted(map(sorted, named.values()))
+    idx = {s: i for i, s in enumerate(states)}
+    for letter in "ab":
+        a = ord(letter)
+        expect = gold["delta"].get(letter, {})
+        for name, s in named.items():
+            t = trans[(idx[s], a)]
+            got = states[t] if t is not None else None
+            want = named[expect[name]] if name in expect else None
+            assert got == want, (letter, name)
+
+
+def test_e2_dfa(e2):
+    g, o, pid = e2
+    states, trans = o.dfa([ord("a"), ord("b")])
+    _check_automaton(o, pid, states, trans, g["dfa"])
+
+
+def test_e2_medfa(e2):
+    g, o, pid = e2
+    states, trans = o.medfa([ord("a"), ord("b")])
+    _check_automaton(o, pid, states, trans, g["medfa"])
+
+
+def test_e2_ex4_serial(e2):
+    g, o, pid = e2
+    ex = g["ex4"]
+    x = ex["text"].encode()
+    # forward and backward columns of Eq. matrixmul, one step at a time
+    fwd = [o.I]
+    for a in x:
+        fwd.append(o.step_fwd(fwd[-1], a))
+    bwd = [o.F]
+    for a in reversed(x):
+        bwd.append(o.step_bwd(bwd[-1], a))
+    bwd.reverse()
+    assert fwd == [_ids(pid, c) for c in ex["forward"]]
+    assert bwd == [_ids(pid, c) for c in ex["backward"]]
+    cols, acc, cnt = o.columns(x)
+    assert cols == [_ids(pid, c) for c in ex["clean"]]
+    assert acc and cnt == 1
+
+
+def test_e2_ex6_parallel(e2):
+    g, o, pid = e2
+    ex = g["ex6"]
+    tr = o.parallel_trace(ex["text"].encode(), ex["k"])
+    want_R = {tuple(map(int, k.split(","))): v for k, v in ex["R"].items()}
+    for (i, j), s in tr["R"].items():
+        paper_j = [p for p, q in pid.items() if q == j][0]
+        want = _ids(pid, want_R.get((i, paper_j), []))
+        assert s == want, (i, paper_j)
+    assert tr["J"] == [_ids(pid, c) for c in ex["J"]]
+    assert [tr["B"][r] for r in range(1, 7)] == [_ids(pid, c) for c in ex["B"]]
+    assert [tr["Bh"][r] for r in range(1, 7)] == [_ids(pid, c) for c in ex["Bh"]]
+    assert tr["C"] == [_ids(pid, c) for c in ex["C"]]
+    cols, acc, cnt = o.columns(ex["text"])
+    assert cols == tr["C"] and acc and cnt == ex["trees"]
+
+
+# ------------------------------------------------------------ e3, e1, e4
+
+def test_e3_nfa_and_slpf():
+    g = load("e3.yaml")
+    o = Oracle(g["re"])
+    assert sorted(o.segments) == sorted(g["segments"])
+    cols, acc, cnt = o.columns(b"abab")
+    got = [sorted(o.segments[i] for i in c) for c in cols]
+    assert got == [sorted(c) for c in g["abab"]["columns"]]
+    assert acc and cnt == len(g["abab"]["trees"]) == 4
+    assert sorted(" ".join(t) for t in lst_brute.lsts(g["re"].encode(), b"abab")) == sorted(g["abab"]["trees"])
+
+
+def test_e1_two_trees():
+    g = load("e1_e4.yaml")["e1"]
+    o = Oracle(g["re"])
+    cols, acc, cnt = o.columns(g["text"])
+    assert acc and cnt == 2
+    trees = lst_brute.lsts(g["re"].encode(), g["text"].encode())
+    assert sorted(" ".join(t) for t in trees) == sorted(g["trees"])
+
+
+def test_e4_epsilon_in_meta_prefix():
+    g = load("e1_e4.yaml")["e4"]
+    o = Oracle(g["re"])
+    cols, acc, cnt = o.columns(g["text"])
+    assert acc and cnt == 1
+    assert [o.segments[min(c)] for c in cols] == g["path"]
+    assert [" ".join(t) for t in lst_brute.lsts(g["re"].encode(), g["text"].encode())] == g["trees"]
+
+
+def test_ek_dfa_state_count():
+    g = load("ek_statecount.yaml")
+    for k, want in zip(g["k"], g["dfa_states"]):
+        o = Oracle("(a|b)*a" + "(a|b)" * k)
+        states, _ = o.dfa()
+        assert len(states) == want == 2 ** (k + 1) + 1
+        # the ME-DFA has one entry per segment: linear in k
+        assert o.nseg == 2 * k + 7
+
+
+# ------------------------------------------------------------ brute force
+
+def _tiny_random_re(rng):
+    """Random tree, depth <= 3, <= 6 operators, over {a, b, c} with epsilon."""
+    def leaf():
+        r = rng.random()
+        if r < 0.1:
+            return regen.EPS
+        return regen.lit("abc"[int(rng.integers(3))])
+
+    def grow(d, budget):
+        if d >= 3 or budget[0] <= 0 or rng.random() < 0.3:
+            return leaf()
+        budget[0] -= 1
+        k = ["cat", "alt", "star", "plus", "opt"][int(rng.integers(5))]
+        if k in ("cat", "alt"):
+            return (k, [grow(d + 1, budget) for _ in range(int(rng.integers(2, 4)))])
+        return (k, grow(d + 1, budget))
+    while True:
+        t = grow(0, [6])
+        if t[0] not in ("lit", "eps") and not regen.infinitely_ambiguous(t):
+            return t
+
+
+def _strings(alpha, maxlen):
+    for n in range(maxlen + 1):
+        for t in itertools.product(alpha, repeat=n):
+            yield "".join(t).encode()
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_oracle_equals_brute_force(seed):
+    rng = np.random.default_rng(1000 + seed)
+    tree = _tiny_random_re(rng)
+    pat = regen.to_re(tree)
+    o = Oracle(pat)
+    py = re.compile(pat.decode())
+    for x in _strings("abc", 5):
+        cols, acc, cnt = o.columns(x)
+        bcols, bcnt = lst_brute.clean_columns(pat, x)
+        assert [set(o.segments[i] for i in c) for c in cols] == bcols, (pat, x)
+        assert cnt == bcnt, (pat, x)
+        assert acc == (bcnt > 0) == (py.fullmatch(x.decode()) is not None), (pat, x)
+
+
+def test_brute_force_on_listed_res():
+    for pat in [b"(a|ab|b)*(c|bc)+(a|b)*", b"(a|b|ab)+", b"(ab|a)*", b"a(bc)", b"(a?b?)c",
+                b"((a|b)(c|()))+", b"(a*|b*)c", b"a|()", b"()"]:
+        o = Oracle(pat)
+        for x in _strings("abc", 5):
+            cols, acc, cnt = o.columns(x)
+            bcols, bcnt = lst_brute.clean_columns(pat, x)
+            assert [set(o.segments[i] for i in c) for c in cols] == bcols, (pat, x)
+            assert cnt == bcnt, (pat, x)
+
+
+# ------------------------------------------------------------ closed forms
+
+@pytest.mark.parametrize("pat", ["(a|ab|b)*", "(a|b|ab)+"])
+def test_count_is_two_to_the_ab_occurrences(pat):
+    o = Oracle(pat)
+    rng = np.random.default_rng(5)
+    for _ in range(60):
+        n = int(rng.integers(1, 40))
+        x = bytes(rng.choice([97, 98], size=n).tolist())
+        _, acc, cnt = o.columns(x)
+        assert acc and cnt == (2 ** x.count(b"ab")) % (1 << 64)
+    x = b"ab" * 70                      # 2^70 wraps to 0 modulo 2^64
+    _, acc, cnt = o.columns(x)
+    assert acc and cnt == 0
+    x = b"ab" * 63 + b"a"
+    _, acc, cnt = o.columns(x)
+    assert acc and cnt == 2 ** 63
+
+
+def test_unambiguous_counts_are_zero_or_one():
+    for pat in ["(ab|a)*", "(a|b)*a(a|b)(a|b)"]:
+        o = Oracle(pat)
+        for x in _strings("ab", 8):
+            _, acc, cnt = o.columns(x)
+            assert cnt == int(acc)
+
+
+# ------------------------------------------------------------ invariants
+
+@pytest.mark.parametrize("seed", range(6))
+def test_slpf_invariants(seed):
+    rng = np.random.default_rng(77 + seed)
+    tree = regen.random_re(seed, n_ops=12, max_depth=4, alphabet=b"abcd")
+    pat = regen.to_re(tree)
+    o = Oracle(pat)
+    from gen import textgen
+    for t in range(4):
+        x = textgen.sample_text(tree, 100 * seed + t, int(rng.integers(0, 300))).tobytes()
+        if t == 3 and x:
+            x = x[:-1] + b"z"          # a byte outside the alphabet: rejected, not an error
+        cols, acc, cnt = o.columns(x)
+        nonempty = [bool(c) for c in cols]
+        assert all(nonempty) == acc and (any(nonempty) == acc)
+        if acc:
+            assert cols[0] <= o.I and cols[-1] <= o.F
+            for r in range(len(x)):
+                assert all(o.labels[s] == x[r] for s in cols[r])
+        else:
+            assert cnt == 0
+        if t < 3:
+            assert acc, "sampled texts are in the language"
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_dfa_parser_equals_nfa_parser(seed):
+    tree = regen.random_re(50 + seed, n_ops=15, max_depth=5, alphabet=b"abc")
+    pat = regen.to_re(tree)
+    o = Oracle(pat)
+    from gen import textgen
+    x = textgen.sample_text(tree, seed, 2000).tobytes()
+    if seed % 2:
+        x = x[:len(x) // 2] + b"c" + x[len(x) // 2:]
+    cols, acc, cnt = o.parse(x)
+    n = len(x)
+    starts = [0, n // 3, max(n - 50, 0)]
+    win, acc2, cnt2 = o.parse_dfa(x, starts, 50)
+    assert acc == acc2 and cnt == cnt2
+    for i, s in enumerate(starts):
+        m = min(50, n + 1 - s)
+        assert np.array_equal(win[i, :m], cols[s:s + m])
+
+
+def test_parallel_trace_matches_serial_for_all_chunkings():
+    """Eq. reacher/joiner/builder/merger reproduce the serial SLPF for any k."""
+    o = Oracle("(a|ab|b)*(c|bc)+(a|b)*")
+    x = b"abbabcbcbccab"
+    cols = o.columns(x)[0]
+    for k in range(1, len(x) + 1):
+        tr = o.parallel_trace(x, k)
+        assert tr["C"] == cols, k
+        c = len(tr["J"]) - 1
+        for i in range(1, c + 1):          # M at a chunk edge is J_i cap Jh_{i+1}
+            r = min(i * k, len(x))
+            assert tr["M"][r] == tr["J"][i] & tr["Jh"][i + 1]
+
+
+# ------------------------------------------------------------ errors
+
+def test_rejects():
+    with pytest.raises(OracleError) as e:
+        Oracle("(a|b")
+    assert e.value.status == STATUS_SYNTAX
+    with pytest.raises(OracleError) as e:
+        Oracle("a)")
+    assert e.value.status == STATUS_SYNTAX
+    with pytest.raises(OracleError) as e:
+        Oracle("*a")
+    assert e.value.status == STATUS_SYNTAX
+    # App. A, infinitely ambiguous RE: an iterator over a nullable body
+    for pat in ["(a|())*", "(a*)*", "(a?b?)+", "(()|b*)+"]:
+        with pytest.raises(OracleError) as e:
+            Oracle(pat)
+        assert e.value.status == STATUS_INF_AMBIG, pat
+
+
+def test_empty_text():
+    o = Oracle("(ab|a)*")
+    cols, acc, cnt = o.columns(b"")
+    assert acc and cnt == 1 and cols == [o.I & o.F]
+    o = Oracle("a(b|c)")
+    cols, acc, cnt = o.columns(b"")
+    assert not acc and cnt == 0 and cols == [frozenset()]
