@@ -1,0 +1,205 @@
+/*
+ * slpf.h -- C ABI of the MI355X (gfx950) chunk-parallel RE parser.
+ *
+ * The library implements the parallel parser of "A parallel parser for
+ * regular expressions" (Borsotti, Breveglieri, Crespi Reghizzi, Morzenti,
+ * arXiv 2503.06763).  The paper states the problem as two steps: generate
+ * the parser automaton of an RE, then parse a text into the shared
+ * linearized parse forest (SLPF) of all its syntax trees (Sect. 2.1, "What is
+ * RE parsing"; Sect. 4.1, tool structure).  The two calls below follow that
+ * split: slpf_compile() on the host, slpf_parse() on the GPU.
+ *
+ * Conventions for every entry point:
+ *  - No exceptions cross the ABI; every call returns an slpf_status
+ *    (negative on failure) unless stated otherwise.
+ *  - "_dev" pointers are device (HIP global memory) pointers owned by the
+ *    caller; the library never frees them.
+ *  - Host pointers are only read during the call.
+ *  - Calls taking a hip_stream (a hipStream_t, NULL = the default stream)
+ *    are asynchronous and stream-ordered: results are valid once the stream
+ *    reaches the point of the call.
+ *  - A compiled parser is immutable and may be used concurrently from
+ *    several host threads and streams.
+ *
+ * RE syntax: bytes are terminals; metacharacters ( ) | * + ?; a backslash
+ * makes the next byte a terminal, with \n, \t and \xHH as shorthands; "()"
+ * and an empty alternative denote the empty string epsilon (App. A, "Empty
+ * string").  Iterators bind tighter than concatenation, concatenation
+ * tighter than union (Sect. 2.1).  A chain of the same operator written
+ * without parentheses is one n-ary node; a parenthesised operator
+ * subexpression is a node of its own (App. A, "Extra parenthesis").  e? is
+ * optionality, numbered like any operator (App. A, "Bounded repetition").
+ */
+#ifndef SLPF_H
+#define SLPF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SLPF_OK = 0,
+    SLPF_E_ARG = -1,        /* bad argument (NULL pointer, bad struct_size, misaligned text) */
+    SLPF_E_SYNTAX = -2,     /* RE syntax error; *err_offset = byte offset */
+    SLPF_E_INF_AMBIG = -3,  /* an iterator over a nullable body (App. A, "Infinite ambiguity") */
+    SLPF_E_TOO_LARGE = -4,  /* automaton beyond the limits (segments, states, entry lists) */
+    SLPF_E_NOMEM = -5,      /* host or device allocation failed */
+    SLPF_E_DEVICE = -6,     /* a HIP call failed */
+    SLPF_E_CAPACITY = -7,   /* output buffer smaller than slpf_forest_bytes() */
+    SLPF_E_INTERNAL = -8
+} slpf_status;
+
+typedef struct slpf_parser slpf_parser;   /* opaque, immutable after compile */
+
+/* ------------------------------------------------------------------ compile */
+
+enum {
+    SLPF_COMPILE_HOST_ONLY = 1u << 0   /* keep the tables on the host: inspection only, no parse */
+};
+
+typedef struct {
+    uint32_t struct_size;    /* sizeof(slpf_compile_opts) */
+    uint32_t flags;          /* SLPF_COMPILE_* */
+    uint32_t max_segments;   /* 0 = default and maximum: 2048 (32 words per column) */
+    uint32_t max_states;     /* per direction, 0 = default (65535, the u16 id range) */
+    int32_t device;          /* HIP device ordinal that will run the parses */
+} slpf_compile_opts;
+
+/*
+ * Compile an RE into its parser automaton (Sect. 2.2-3.1): number the RE,
+ * compute the classic followers, the segments (Fig. segmentalgo), the
+ * follower segments (Eq. folsegdef), and by powerset the forward and reverse
+ * tables.  Each direction's table is the union of the DFA started from the
+ * initial (resp. final) set and the multi-entry DFA started from every
+ * singleton segment, identical segment sets merged (Sect. 3.1 and the
+ * "Automaton optimization" paragraph of Sect. 3.3); the DFA is never
+ * minimized (Sect. 3.1).  The tables are uploaded to `device`.
+ *
+ * re/re_len: the RE bytes (not NUL-terminated; may contain NUL).
+ * opts: may be NULL for defaults.  With SLPF_COMPILE_HOST_ONLY nothing is
+ *   uploaded and no HIP call is made (a parse with such a parser returns
+ *   SLPF_E_ARG); the inspection calls below work as usual.
+ * out: receives the parser; *out = NULL on failure.
+ * err_offset: may be NULL; set to the failing byte offset on SLPF_E_SYNTAX.
+ */
+slpf_status slpf_compile(const char *re, size_t re_len, const slpf_compile_opts *opts,
+                         slpf_parser **out, size_t *err_offset);
+
+/* Free a parser and its device tables.  The caller must ensure no parse
+ * using it is still running on any stream.  NULL is ignored. */
+void slpf_parser_destroy(slpf_parser *p);
+
+typedef struct {
+    uint32_t num_segments;       /* l = |Q|, states of the parser NFA */
+    uint32_t words_per_column;   /* W = ceil(l / 64) */
+    uint32_t num_initial, num_final;
+    uint32_t fwd_states;         /* forward table, the empty set excluded */
+    uint32_t rev_states;         /* reverse table, the empty set excluded */
+    uint32_t dfa_states;         /* forward DFA from I (Sect. 3.2 "DFA") */
+    uint32_t medfa_states;       /* forward ME-DFA from the singletons */
+    uint32_t rdfa_states;        /* reverse DFA from F */
+    uint32_t rmedfa_states;      /* reverse ME-DFA from the singletons */
+    uint32_t num_classes;        /* byte classes, class 0 = bytes outside the RE */
+    uint32_t max_entries;        /* longest speculative entry list (<= 64) */
+    uint32_t placement;          /* 0 = transition tables staged in LDS, 1 = read through L2 */
+    uint32_t reserved;
+    uint64_t table_bytes;        /* device bytes of all tables */
+} slpf_parser_info;
+
+slpf_status slpf_parser_info_get(const slpf_parser *p, slpf_parser_info *info);
+
+/*
+ * Text of segment `seg` (0-based, canonical order: by end-letter number with
+ * the end mark last, then meta-prefix length, then the meta-prefix symbols
+ * compared as (number, kind) with "(" < leaf < ")").  Symbols are separated
+ * by one space: "k(" and ")k" for the numbered parentheses of operator k, a
+ * terminal as its letter followed by its number ("a4"; bytes other than
+ * ASCII letters as "\xHH" then the number), "ε" + number for an epsilon
+ * leaf, "⊣" (UTF-8) for the end mark.  Writes at most cap bytes including
+ * a terminating NUL; *need (may be NULL) receives the length without NUL.
+ */
+slpf_status slpf_segment_text(const slpf_parser *p, uint32_t seg, char *buf, size_t cap,
+                              size_t *need);
+
+/*
+ * Host copy of one direction's merged table (dir 0 forward, 1 reverse):
+ * sets: (states+1) x W words, row 0 the empty set; delta: (states+1) x
+ * num_classes ids; classmap: 256 class ids.  Any pointer may be NULL.
+ * Sizes come from slpf_parser_info_get.
+ */
+slpf_status slpf_table_dump(const slpf_parser *p, int dir, uint64_t *sets, uint32_t *delta,
+                            uint16_t *classmap);
+
+/* Bytes of the SLPF of an n-byte text: (n + 1) * W * 8. */
+uint64_t slpf_forest_bytes(const slpf_parser *p, uint64_t n);
+
+/* -------------------------------------------------------------------- parse */
+
+enum {
+    SLPF_PARSE_NO_COUNT = 1u << 0,      /* skip the tree count (scalars[1] = 0, [2] = 2) */
+    SLPF_PARSE_FORCE_L2 = 1u << 1       /* read transition tables through L2 even if LDS fits */
+};
+
+typedef struct {
+    uint32_t struct_size;     /* sizeof(slpf_parse_opts) */
+    uint32_t chunk_bytes;     /* bytes per lane chunk, a multiple of 64; 0 = automatic */
+    uint32_t flags;           /* SLPF_PARSE_* */
+    uint32_t reserved;
+    uint64_t *trace_dev;      /* optional: receives the join results, see below */
+    uint64_t trace_bytes;     /* capacity of trace_dev */
+} slpf_parse_opts;
+
+/*
+ * Output of a parse.  columns_dev: the SLPF, column r (0 <= r <= n) at
+ * words [r*W, (r+1)*W), bit j of the column set iff segment j is in the
+ * clean column C_r (Sect. 2.3.4; Boolean vectors as in Sect. 2.4).
+ * scalars_dev[0] = 1 if the text is in the language else 0;
+ * scalars_dev[1] = number of syntax trees modulo 2^64 (the number of
+ *                  accepting NFA runs, one per LST, Sect. 2.3.4);
+ * scalars_dev[2] = 0 if scalars_dev[1] is valid, 1 if the count was not
+ *                  computed because a clean column held more than 64
+ *                  segments, 2 if not requested (SLPF_PARSE_NO_COUNT).
+ */
+typedef struct {
+    uint64_t *columns_dev;     /* device, capacity_bytes >= slpf_forest_bytes(p, n) */
+    uint64_t capacity_bytes;
+    uint64_t *scalars_dev;     /* device, 3 words */
+} slpf_forest;
+
+/*
+ * Parse text_dev[0..n) into its clean SLPF (Sect. 3.2-3.3): split into lane
+ * chunks, speculative forward and backward reach from the reduced entry
+ * sets (Eq. reacher), join of the chunk maps (Eq. joiner), fused build and
+ * merge (Eq. builder, Eq. merger, Fig. builders&merger), composition of
+ * column 0, and the tree count.
+ *
+ * text_dev: device pointer, 16-byte aligned, n readable bytes.  Bytes
+ *   outside the RE's alphabet are not errors: the text is rejected, every
+ *   column is empty and the count is 0.
+ * opts: may be NULL for defaults.  If opts->trace_dev is set and
+ *   trace_bytes >= 2 * (c + 1) * W * 8 (c = number of lane chunks,
+ *   ceil(n / chunk_bytes)), the forward join sets J (the forward column at
+ *   every lane-chunk edge) and then the backward sets J^ (the backward
+ *   column at every edge) are written there, (c + 1) x W words each.
+ * forest: output buffers; SLPF_E_CAPACITY if too small.
+ * hip_stream: hipStream_t or NULL.
+ * Work buffers are allocated by the library and kept with the parser; a
+ * parse that needs a larger workspace than a previous one synchronizes the
+ * stream before reallocating.
+ */
+slpf_status slpf_parse(const slpf_parser *p, const uint8_t *text_dev, uint64_t n,
+                       const slpf_parse_opts *opts, const slpf_forest *forest, void *hip_stream);
+
+/* Number of lane chunks a parse of n bytes uses with the given options. */
+uint64_t slpf_num_chunks(const slpf_parser *p, uint64_t n, const slpf_parse_opts *opts);
+
+const char *slpf_status_str(slpf_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SLPF_H */

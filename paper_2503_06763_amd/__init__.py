@@ -1,0 +1,226 @@
+"""Python binding of the SLPF library (libslpf.so, HIP for gfx950).
+
+Argument marshalling only: every step of a parse runs in the library's HIP
+kernels.  Device buffers are torch tensors on a ROCm device; their
+``data_ptr()`` and the current torch stream are handed to the C ABI
+(include/slpf.h).  There is no CPU fallback: if the library is missing the
+import of :func:`lib` raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libslpf.so")
+
+SLPF_OK = 0
+STATUS = {0: "ok", -1: "invalid argument", -2: "RE syntax error", -3: "infinitely ambiguous RE",
+          -4: "automaton too large", -5: "out of memory", -6: "device error",
+          -7: "output buffer too small", -8: "internal error"}
+E_ARG, E_SYNTAX, E_INF_AMBIG, E_TOO_LARGE, E_NOMEM, E_DEVICE, E_CAPACITY, E_INTERNAL = range(-1, -9, -1)
+
+COMPILE_HOST_ONLY = 1
+
+PARSE_NO_COUNT = 1
+PARSE_FORCE_L2 = 2
+
+EXPORTS = ["slpf_compile", "slpf_parser_destroy", "slpf_parser_info_get", "slpf_segment_text",
+           "slpf_table_dump", "slpf_forest_bytes", "slpf_parse", "slpf_num_chunks", "slpf_status_str"]
+
+
+class SlpfError(RuntimeError):
+    def __init__(self, status, what="", offset=None):
+        super().__init__("%s: %s (%d)%s" % (what, STATUS.get(status, "?"), status,
+                                            "" if offset is None else " at offset %d" % offset))
+        self.status = status
+        self.offset = offset
+
+
+class CompileOpts(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("max_segments", ctypes.c_uint32), ("max_states", ctypes.c_uint32),
+                ("device", ctypes.c_int32)]
+
+
+class ParserInfo(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_uint32) for k in (
+        "num_segments", "words_per_column", "num_initial", "num_final", "fwd_states", "rev_states",
+        "dfa_states", "medfa_states", "rdfa_states", "rmedfa_states", "num_classes", "max_entries",
+        "placement", "reserved")] + [("table_bytes", ctypes.c_uint64)]
+
+
+class ParseOpts(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("chunk_bytes", ctypes.c_uint32),
+                ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("trace_dev", ctypes.c_void_p), ("trace_bytes", ctypes.c_uint64)]
+
+
+class Forest(ctypes.Structure):
+    _fields_ = [("columns_dev", ctypes.c_void_p), ("capacity_bytes", ctypes.c_uint64),
+                ("scalars_dev", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib(path: str = LIB_PATH):
+    """Load libslpf.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError("libslpf.so not built: run paper_2503_06763_amd/build.py (or __graft_entry__.build())")
+    # torch first: its HIP runtime (soname libamdhip64.so.7) is then the one
+    # the library binds to, so the process holds a single HIP runtime
+    import torch  # noqa: F401
+    L = ctypes.CDLL(path)
+    vp, sz = ctypes.c_void_p, ctypes.c_size_t
+    L.slpf_compile.argtypes = [ctypes.c_char_p, sz, ctypes.POINTER(CompileOpts), ctypes.POINTER(vp),
+                               ctypes.POINTER(sz)]
+    L.slpf_compile.restype = ctypes.c_int
+    L.slpf_parser_destroy.argtypes = [vp]
+    L.slpf_parser_destroy.restype = None
+    L.slpf_parser_info_get.argtypes = [vp, ctypes.POINTER(ParserInfo)]
+    L.slpf_parser_info_get.restype = ctypes.c_int
+    L.slpf_segment_text.argtypes = [vp, ctypes.c_uint32, ctypes.c_char_p, sz, ctypes.POINTER(sz)]
+    L.slpf_segment_text.restype = ctypes.c_int
+    L.slpf_table_dump.argtypes = [vp, ctypes.c_int, vp, vp, vp]
+    L.slpf_table_dump.restype = ctypes.c_int
+    L.slpf_forest_bytes.argtypes = [vp, ctypes.c_uint64]
+    L.slpf_forest_bytes.restype = ctypes.c_uint64
+    L.slpf_parse.argtypes = [vp, vp, ctypes.c_uint64, ctypes.POINTER(ParseOpts), ctypes.POINTER(Forest), vp]
+    L.slpf_parse.restype = ctypes.c_int
+    L.slpf_num_chunks.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ParseOpts)]
+    L.slpf_num_chunks.restype = ctypes.c_uint64
+    L.slpf_status_str.argtypes = [ctypes.c_int]
+    L.slpf_status_str.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(st, what, offset=None):
+    if st != SLPF_OK:
+        raise SlpfError(st, what, offset)
+
+
+@dataclass
+class Info:
+    num_segments: int
+    words_per_column: int
+    num_initial: int
+    num_final: int
+    fwd_states: int
+    rev_states: int
+    dfa_states: int
+    medfa_states: int
+    rdfa_states: int
+    rmedfa_states: int
+    num_classes: int
+    max_entries: int
+    placement: int
+    table_bytes: int
+
+
+class Parser:
+    """A compiled RE (slpf_compile); tables live on ``device``."""
+
+    def __init__(self, re, device: int = 0, max_segments: int = 0, max_states: int = 0,
+                 host_only: bool = False):
+        L = lib()
+        b = re.encode("latin1") if isinstance(re, str) else bytes(re)
+        o = CompileOpts(ctypes.sizeof(CompileOpts), COMPILE_HOST_ONLY if host_only else 0,
+                        max_segments, max_states, device)
+        h = ctypes.c_void_p()
+        off = ctypes.c_size_t(0)
+        st = L.slpf_compile(b, len(b), ctypes.byref(o), ctypes.byref(h), ctypes.byref(off))
+        _check(st, "slpf_compile", off.value if st == E_SYNTAX else None)
+        self._h = h
+        self._L = L
+        self.device = device
+        self.re = b
+        i = ParserInfo()
+        _check(L.slpf_parser_info_get(h, ctypes.byref(i)), "slpf_parser_info_get")
+        self.info = Info(*[getattr(i, f) for f in Info.__dataclass_fields__])
+        self.W = self.info.words_per_column
+        self.nseg = self.info.num_segments
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.slpf_parser_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def segment_text(self, seg: int) -> str:
+        need = ctypes.c_size_t(0)
+        _check(self._L.slpf_segment_text(self._h, seg, None, 0, ctypes.byref(need)), "slpf_segment_text")
+        buf = ctypes.create_string_buffer(need.value + 1)
+        _check(self._L.slpf_segment_text(self._h, seg, buf, need.value + 1, None), "slpf_segment_text")
+        return buf.value.decode("utf-8")
+
+    @property
+    def segments(self):
+        return [self.segment_text(i) for i in range(self.nseg)]
+
+    def table(self, direction: int):
+        """(sets [states+1, W] uint64, delta [states+1, C] uint32, classmap [256] uint16), host numpy."""
+        import numpy as np
+        ns = (self.info.fwd_states if direction == 0 else self.info.rev_states) + 1
+        sets = np.zeros((ns, self.W), np.uint64)
+        delta = np.zeros((ns, self.info.num_classes), np.uint32)
+        cm = np.zeros(256, np.uint16)
+        _check(self._L.slpf_table_dump(self._h, direction, sets.ctypes.data, delta.ctypes.data, cm.ctypes.data),
+               "slpf_table_dump")
+        return sets, delta, cm
+
+    def forest_bytes(self, n: int) -> int:
+        return int(self._L.slpf_forest_bytes(self._h, n))
+
+    def num_chunks(self, n: int, chunk_bytes: int = 0) -> int:
+        o = ParseOpts(ctypes.sizeof(ParseOpts), chunk_bytes, 0, 0, None, 0)
+        return int(self._L.slpf_num_chunks(self._h, n, ctypes.byref(o)))
+
+    def parse_into(self, text, n: int, columns, scalars, chunk_bytes: int = 0, flags: int = 0,
+                   trace=None, stream=None):
+        """Raw slpf_parse on torch device tensors (asynchronous on ``stream``)."""
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(text.device)
+        o = ParseOpts(ctypes.sizeof(ParseOpts), chunk_bytes, flags, 0,
+                      trace.data_ptr() if trace is not None else None,
+                      trace.numel() * trace.element_size() if trace is not None else 0)
+        f = Forest(columns.data_ptr(), columns.numel() * columns.element_size(), scalars.data_ptr())
+        st = self._L.slpf_parse(self._h, text.data_ptr() if n else None, n, ctypes.byref(o), ctypes.byref(f),
+                                ctypes.c_void_p(stream.cuda_stream))
+        _check(st, "slpf_parse")
+
+    def parse(self, text, chunk_bytes: int = 0, count: bool = True, force_l2: bool = False,
+              trace: bool = False, stream=None):
+        """Parse a uint8 device tensor; returns (columns [n+1, W] int64 view of uint64 words,
+        scalars [3]) on the device, plus the join trace if asked."""
+        import torch
+        n = text.numel()
+        dev = text.device
+        cols = torch.empty((n + 1, self.W), dtype=torch.int64, device=dev)
+        sc = torch.empty(3, dtype=torch.int64, device=dev)
+        tr = None
+        if trace:
+            c = self.num_chunks(n, chunk_bytes)
+            tr = torch.zeros((2, c + 1, self.W), dtype=torch.int64, device=dev)
+        flags = (0 if count else PARSE_NO_COUNT) | (PARSE_FORCE_L2 if force_l2 else 0)
+        self.parse_into(text, n, cols, sc, chunk_bytes, flags, tr, stream)
+        return (cols, sc, tr) if trace else (cols, sc)
+
+
+def status_str(st: int) -> str:
+    return lib().slpf_status_str(st).decode()

@@ -1,0 +1,461 @@
+// C ABI of the SLPF library: compile (host) and parse (device launches).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "../../include/slpf.h"
+#include "kernels.hpp"
+#include "slpf_internal.hpp"
+
+namespace {
+
+using namespace slpf;
+
+constexpr size_t kLdsBudget = 96 * 1024;   // transition tables staged in LDS up to this size
+constexpr uint32_t kBigPool = 1024;         // 64x64 transfer-matrix slots (32 KiB each)
+constexpr uint32_t kProdGroup = 256;
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+struct Workspace {
+    void *base = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace
+
+struct slpf_parser {
+    HostAutomaton A;
+    int device = 0;
+    void *blob = nullptr;
+    size_t blob_bytes = 0;
+    Tabs tabs{};
+    uint32_t placement = 0;
+    size_t lds_bytes = 0;
+    bool host_only = false;
+    std::mutex mu;
+    std::map<void *, Workspace> ws;   // per stream
+};
+
+namespace {
+
+slpf_status hip_ok(hipError_t e) { return e == hipSuccess ? SLPF_OK : SLPF_E_DEVICE; }
+
+// Device-side copy of the tables in one allocation.
+slpf_status upload(slpf_parser *p) {
+    const HostAutomaton &A = p->A;
+    struct Part {
+        const void *src;
+        size_t bytes;
+        size_t off;
+    };
+    std::vector<Part> parts = {
+        {A.classmap.data(), A.classmap.size() * 2, 0},
+        {A.fwd.delta.data(), A.fwd.delta.size() * 2, 0},
+        {A.rev.delta.data(), A.rev.delta.size() * 2, 0},
+        {A.fwd.bits.data(), A.fwd.bits.size() * 8, 0},
+        {A.rev.bits.data(), A.rev.bits.size() * 8, 0},
+        {A.xoff.data(), A.xoff.size() * 4, 0},
+        {A.xlist.data(), std::max<size_t>(A.xlist.size(), 1) * 2, 0},
+        {A.fwd.single.data(), A.fwd.single.size() * 2, 0},
+        {A.rev.single.data(), A.rev.single.size() * 2, 0},
+        {A.fwd.hash.data(), A.fwd.hash.size() * 4, 0},
+        {A.rev.hash.data(), A.rev.hash.size() * 4, 0},
+        {A.folseg.data(), A.folseg.size() * 8, 0},
+    };
+    size_t total = 0;
+    for (auto &pt : parts) {
+        pt.off = total;
+        total = align_up(total + pt.bytes, 256);
+    }
+    std::vector<uint8_t> host(total, 0);
+    for (auto &pt : parts)
+        if (pt.src && pt.bytes) std::memcpy(host.data() + pt.off, pt.src, pt.bytes);
+    if (hipSetDevice(p->device) != hipSuccess) return SLPF_E_DEVICE;
+    if (hipMalloc(&p->blob, total) != hipSuccess) {
+        p->blob = nullptr;
+        return SLPF_E_NOMEM;
+    }
+    if (hipMemcpy(p->blob, host.data(), total, hipMemcpyHostToDevice) != hipSuccess) return SLPF_E_DEVICE;
+    p->blob_bytes = total;
+    auto at = [&](int k) { return static_cast<uint8_t *>(p->blob) + parts[k].off; };
+    Tabs &t = p->tabs;
+    t.classmap = reinterpret_cast<const uint16_t *>(at(0));
+    t.fdelta = reinterpret_cast<const uint16_t *>(at(1));
+    t.rdelta = reinterpret_cast<const uint16_t *>(at(2));
+    t.fbits = reinterpret_cast<const uint64_t *>(at(3));
+    t.rbits = reinterpret_cast<const uint64_t *>(at(4));
+    t.xoff = reinterpret_cast<const uint32_t *>(at(5));
+    t.xlist = reinterpret_cast<const uint16_t *>(at(6));
+    t.fsingle = reinterpret_cast<const uint16_t *>(at(7));
+    t.rsingle = reinterpret_cast<const uint16_t *>(at(8));
+    t.fhash = reinterpret_cast<const uint32_t *>(at(9));
+    t.rhash = reinterpret_cast<const uint32_t *>(at(10));
+    t.folseg = reinterpret_cast<const uint64_t *>(at(11));
+    t.fhmask = static_cast<uint32_t>(A.fwd.hash.size() - 1);
+    t.rhmask = static_cast<uint32_t>(A.rev.hash.size() - 1);
+    t.C = A.C;
+    t.W = A.W;
+    t.NL = A.C + 1;
+    t.nf = A.fwd.nstates;
+    t.nr = A.rev.nstates;
+    t.fstart = A.fwd.start;
+    t.rstart = A.rev.start;
+    t.emax = std::max<uint32_t>(A.max_entries, 1);
+    return SLPF_OK;
+}
+
+void set_placement(slpf_parser *p) {
+    const HostAutomaton &A = p->A;
+    p->lds_bytes = 512 + (static_cast<size_t>(A.fwd.nstates) + A.rev.nstates) * A.C * 2;
+    size_t budget = kLdsBudget;
+    if (!p->host_only) {
+        int lim = 0;
+        if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device) == hipSuccess &&
+            lim > 0)
+            budget = std::min<size_t>(budget, static_cast<size_t>(lim));
+    }
+    p->placement = p->lds_bytes <= budget ? 0 : 1;
+}
+
+uint64_t chunk_bytes_for(uint64_t n, const slpf_parse_opts *o) {
+    if (o && o->chunk_bytes) return o->chunk_bytes;
+    // aim at ~64K lane chunks (one per lane of ~4 waves on each of 256 CUs)
+    uint64_t s = (n + 65535) / 65536;
+    s = (s + 63) / 64 * 64;
+    return std::min<uint64_t>(std::max<uint64_t>(s, 256), 1u << 20);
+}
+
+struct Layout {
+    size_t off[40];
+    int k = 0;
+    size_t total = 0;
+    size_t add(size_t bytes) {
+        off[k] = total;
+        total = align_up(total + std::max<size_t>(bytes, 8), 256);
+        return k++;
+    }
+};
+
+// join level sizes: N_0 = c, N_{L+1} = ceil(N_L / 64) until <= 64
+std::vector<uint32_t> join_levels(uint32_t c) {
+    std::vector<uint32_t> lv{c};
+    while (lv.back() > 64) lv.push_back((lv.back() + 63) / 64);
+    return lv;
+}
+
+std::vector<uint32_t> prod_levels(uint32_t c) {
+    std::vector<uint32_t> lv{c};
+    while (lv.back() > 1) lv.push_back((lv.back() + kProdGroup - 1) / kProdGroup);
+    return lv;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *slpf_status_str(slpf_status s) {
+    switch (s) {
+    case SLPF_OK: return "ok";
+    case SLPF_E_ARG: return "invalid argument";
+    case SLPF_E_SYNTAX: return "RE syntax error";
+    case SLPF_E_INF_AMBIG: return "infinitely ambiguous RE";
+    case SLPF_E_TOO_LARGE: return "automaton too large";
+    case SLPF_E_NOMEM: return "out of memory";
+    case SLPF_E_DEVICE: return "device error";
+    case SLPF_E_CAPACITY: return "output buffer too small";
+    case SLPF_E_INTERNAL: return "internal error";
+    }
+    return "unknown status";
+}
+
+slpf_status slpf_compile(const char *re, size_t re_len, const slpf_compile_opts *opts,
+                         slpf_parser **out, size_t *err_offset) {
+    if (!out) return SLPF_E_ARG;
+    *out = nullptr;
+    if (!re && re_len) return SLPF_E_ARG;
+    if (opts && opts->struct_size != sizeof(slpf_compile_opts)) return SLPF_E_ARG;
+    CompileLimits lim;
+    if (opts && opts->max_segments) lim.max_segments = std::min<uint32_t>(opts->max_segments, 64 * kMaxWords);
+    if (opts && opts->max_states) lim.max_states = std::min<uint32_t>(opts->max_states, 65535);
+    slpf_parser *p = new (std::nothrow) slpf_parser();
+    if (!p) return SLPF_E_NOMEM;
+    p->device = opts ? opts->device : 0;
+    int st;
+    try {
+        st = compile_re(reinterpret_cast<const uint8_t *>(re), re_len, lim, p->A, err_offset);
+    } catch (const std::bad_alloc &) {
+        st = SLPF_E_NOMEM;
+    } catch (...) {
+        st = SLPF_E_INTERNAL;
+    }
+    p->host_only = opts && (opts->flags & SLPF_COMPILE_HOST_ONLY);
+    if (st == SLPF_OK) set_placement(p);
+    if (st == SLPF_OK && !p->host_only) st = upload(p);
+    if (st != SLPF_OK) {
+        slpf_parser_destroy(p);
+        return static_cast<slpf_status>(st);
+    }
+    *out = p;
+    return SLPF_OK;
+}
+
+void slpf_parser_destroy(slpf_parser *p) {
+    if (!p) return;
+    if (p->host_only) {
+        delete p;
+        return;
+    }
+    hipSetDevice(p->device);
+    for (auto &kv : p->ws)
+        if (kv.second.base) hipFree(kv.second.base);
+    if (p->blob) hipFree(p->blob);
+    delete p;
+}
+
+slpf_status slpf_parser_info_get(const slpf_parser *p, slpf_parser_info *info) {
+    if (!p || !info) return SLPF_E_ARG;
+    const HostAutomaton &A = p->A;
+    std::memset(info, 0, sizeof(*info));
+    info->num_segments = A.nseg;
+    info->words_per_column = A.W;
+    info->num_initial = A.ninit;
+    info->num_final = A.nfinal;
+    info->fwd_states = A.fwd.nstates - 1;
+    info->rev_states = A.rev.nstates - 1;
+    info->dfa_states = A.fwd.dfa_states;
+    info->medfa_states = A.fwd.medfa_states;
+    info->rdfa_states = A.rev.dfa_states;
+    info->rmedfa_states = A.rev.medfa_states;
+    info->num_classes = A.C;
+    info->max_entries = A.max_entries;
+    info->placement = p->placement;
+    info->table_bytes = p->blob_bytes;
+    return SLPF_OK;
+}
+
+slpf_status slpf_segment_text(const slpf_parser *p, uint32_t seg, char *buf, size_t cap, size_t *need) {
+    if (!p || seg >= p->A.nseg) return SLPF_E_ARG;
+    const std::string &s = p->A.seg_text[seg];
+    if (need) *need = s.size();
+    if (buf && cap) {
+        size_t k = std::min(cap - 1, s.size());
+        std::memcpy(buf, s.data(), k);
+        buf[k] = 0;
+    }
+    return SLPF_OK;
+}
+
+slpf_status slpf_table_dump(const slpf_parser *p, int dir, uint64_t *sets, uint32_t *delta,
+                            uint16_t *classmap) {
+    if (!p || (dir != 0 && dir != 1)) return SLPF_E_ARG;
+    const HostTable &t = dir == 0 ? p->A.fwd : p->A.rev;
+    if (sets) std::memcpy(sets, t.bits.data(), t.bits.size() * 8);
+    if (delta)
+        for (size_t k = 0; k < t.delta.size(); ++k) delta[k] = t.delta[k];
+    if (classmap) std::memcpy(classmap, p->A.classmap.data(), 512);
+    return SLPF_OK;
+}
+
+uint64_t slpf_forest_bytes(const slpf_parser *p, uint64_t n) {
+    if (!p) return 0;
+    return (n + 1) * static_cast<uint64_t>(p->A.W) * 8;
+}
+
+uint64_t slpf_num_chunks(const slpf_parser *p, uint64_t n, const slpf_parse_opts *opts) {
+    if (!p || n == 0) return 0;
+    uint64_t s = chunk_bytes_for(n, opts);
+    return (n + s - 1) / s;
+}
+
+slpf_status slpf_parse(const slpf_parser *cp, const uint8_t *text, uint64_t n, const slpf_parse_opts *opts,
+                       const slpf_forest *forest, void *hip_stream) {
+    slpf_parser *p = const_cast<slpf_parser *>(cp);
+    if (!p || p->host_only || !forest || !forest->columns_dev || !forest->scalars_dev) return SLPF_E_ARG;
+    if (opts && opts->struct_size != sizeof(slpf_parse_opts)) return SLPF_E_ARG;
+    if (n && !text) return SLPF_E_ARG;
+    if (reinterpret_cast<uintptr_t>(text) % 16 != 0) return SLPF_E_ARG;
+    if (opts && opts->chunk_bytes && (opts->chunk_bytes % 64 != 0)) return SLPF_E_ARG;
+    if (forest->capacity_bytes < slpf_forest_bytes(p, n)) return SLPF_E_CAPACITY;
+    const uint32_t flags = opts ? opts->flags : 0;
+    const bool count = !(flags & SLPF_PARSE_NO_COUNT);
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    if (hipSetDevice(p->device) != hipSuccess) return SLPF_E_DEVICE;
+    Tabs tb = p->tabs;
+    Job jb{};
+    jb.text = text;
+    jb.n = n;
+    jb.out = forest->columns_dev;
+    jb.scalars = forest->scalars_dev;
+    if (n == 0) {
+        hipLaunchKernelGGL(k_empty, dim3(1), dim3(1), 0, stream, tb, jb, count ? 1 : 0);
+        return hip_ok(hipGetLastError());
+    }
+    const uint64_t s = chunk_bytes_for(n, opts);
+    const uint64_t c64 = (n + s - 1) / s;
+    if (c64 > 0x7fffffffull) return SLPF_E_ARG;
+    const uint32_t c = static_cast<uint32_t>(c64);
+    jb.s = s;
+    jb.c = c;
+    const uint32_t E = tb.emax, W = tb.W;
+    const std::vector<uint32_t> jl = join_levels(c);
+    const std::vector<uint32_t> pl = prod_levels(c);
+
+    Layout L;
+    int iR = L.add(size_t(E) * c * 2), iRh = L.add(size_t(E) * c * 2);
+    int iMf = L.add(size_t(c) * E * 8), iMb = L.add(size_t(c) * E * 8);
+    int inxf = L.add(c + 1), inxb = L.add(c + 1);
+    int ivf = L.add(size_t(c + 1) * 8), ivb = L.add(size_t(c + 1) * 8);
+    int ifid = L.add(size_t(c) * 2), irid = L.add(size_t(c) * 2);
+    int ickpt = L.add((n + 63) / 64 * 2);
+    int iflags = L.add(16);
+    // join levels >= 1: maps [N][64], nx [N+1], vectors [N+1], both directions
+    std::vector<int> jmf, jmb, jnxf, jnxb, jvf, jvb;
+    for (size_t l = 1; l < jl.size(); ++l) {
+        jmf.push_back(L.add(size_t(jl[l]) * 64 * 8));
+        jmb.push_back(L.add(size_t(jl[l]) * 64 * 8));
+        jnxf.push_back(L.add(jl[l] + 1));
+        jnxb.push_back(L.add(jl[l] + 1));
+        jvf.push_back(L.add(size_t(jl[l] + 1) * 8));
+        jvb.push_back(L.add(size_t(jl[l] + 1) * 8));
+    }
+    int idims = -1, itsmall = -1, itidx = -1, itbig = -1;
+    std::vector<int> pout, pdims;
+    if (count) {
+        idims = L.add(size_t(c) * 2);
+        itsmall = L.add(size_t(c) * kSmallT * kSmallT * 8);
+        itidx = L.add(size_t(c) * 4);
+        itbig = L.add(size_t(kBigPool) * kBigT * kBigT * 8);
+        for (size_t l = 1; l < pl.size(); ++l) {
+            pout.push_back(L.add(size_t(pl[l]) * kBigT * kBigT * 8));
+            pdims.push_back(L.add(size_t(pl[l]) * 2));
+        }
+    }
+
+    uint8_t *base;
+    {
+        std::lock_guard<std::mutex> g(p->mu);
+        Workspace &w = p->ws[hip_stream];
+        if (w.bytes < L.total) {
+            if (w.base) {
+                if (hipStreamSynchronize(stream) != hipSuccess) return SLPF_E_DEVICE;
+                hipFree(w.base);
+                w.base = nullptr;
+                w.bytes = 0;
+            }
+            size_t want = align_up(L.total + L.total / 4, 1 << 20);
+            if (hipMalloc(&w.base, want) != hipSuccess) {
+                w.base = nullptr;
+                return SLPF_E_NOMEM;
+            }
+            w.bytes = want;
+        }
+        base = static_cast<uint8_t *>(w.base);
+    }
+    auto ptr = [&](int k) { return base + L.off[k]; };
+    jb.R = reinterpret_cast<uint16_t *>(ptr(iR));
+    jb.Rh = reinterpret_cast<uint16_t *>(ptr(iRh));
+    jb.Mf = reinterpret_cast<uint64_t *>(ptr(iMf));
+    jb.MbR = reinterpret_cast<uint64_t *>(ptr(iMb));
+    jb.nxf = ptr(inxf);
+    jb.nxb = ptr(inxb);
+    jb.vf = reinterpret_cast<uint64_t *>(ptr(ivf));
+    jb.vb = reinterpret_cast<uint64_t *>(ptr(ivb));
+    jb.fid = reinterpret_cast<uint16_t *>(ptr(ifid));
+    jb.rid = reinterpret_cast<uint16_t *>(ptr(irid));
+    jb.ckpt = reinterpret_cast<uint16_t *>(ptr(ickpt));
+    jb.flags = reinterpret_cast<uint32_t *>(ptr(iflags));
+    jb.trace = nullptr;
+    if (opts && opts->trace_dev && opts->trace_bytes >= 2ull * (c + 1) * W * 8) jb.trace = opts->trace_dev;
+    if (count) {
+        jb.dims = ptr(idims);
+        jb.tsmall = reinterpret_cast<uint64_t *>(ptr(itsmall));
+        jb.tbig_idx = reinterpret_cast<uint32_t *>(ptr(itidx));
+        jb.tbig = reinterpret_cast<uint64_t *>(ptr(itbig));
+        jb.big_pool = kBigPool;
+    }
+
+    const bool lds = p->placement == 0 && !(flags & SLPF_PARSE_FORCE_L2);
+    const size_t lds_bytes = lds ? p->lds_bytes : 0;
+    const uint32_t blocks = (c + 255) / 256;
+
+    hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, stream, jb);
+
+    // reach
+    if (lds) hipLaunchKernelGGL(k_reach<true>, dim3(blocks), dim3(256), lds_bytes, stream, tb, jb);
+    else hipLaunchKernelGGL(k_reach<false>, dim3(blocks), dim3(256), 0, stream, tb, jb);
+
+    // join: forward maps (Mf, nxf) and reversed backward maps (MbR, nxb)
+    for (int dir = 0; dir < 2; ++dir) {
+        std::vector<const uint64_t *> M{dir == 0 ? jb.Mf : jb.MbR};
+        std::vector<uint32_t> stride{E};
+        std::vector<const uint8_t *> nx{dir == 0 ? jb.nxf : jb.nxb};
+        std::vector<uint64_t *> vec{dir == 0 ? jb.vf : jb.vb};
+        for (size_t l = 1; l < jl.size(); ++l) {
+            uint64_t *outM = reinterpret_cast<uint64_t *>(ptr(dir == 0 ? jmf[l - 1] : jmb[l - 1]));
+            uint8_t *outnx = ptr(dir == 0 ? jnxf[l - 1] : jnxb[l - 1]);
+            hipLaunchKernelGGL(k_compose, dim3(jl[l]), dim3(64), 0, stream, M.back(), stride.back(), jl[l - 1],
+                               nx.back(), outM, outnx);
+            M.push_back(outM);
+            stride.push_back(64);
+            nx.push_back(outnx);
+            vec.push_back(reinterpret_cast<uint64_t *>(ptr(dir == 0 ? jvf[l - 1] : jvb[l - 1])));
+        }
+        const size_t top = jl.size() - 1;
+        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1), 0, stream, M[top], stride[top], jl[top], nx[top],
+                           vec[top]);
+        for (size_t l = top; l-- > 0;) {
+            hipLaunchKernelGGL(k_expand, dim3((jl[l + 1] + 63) / 64), dim3(64), 0, stream, M[l], stride[l], jl[l],
+                               vec[l + 1], jl[l + 1], vec[l]);
+        }
+    }
+    hipLaunchKernelGGL(k_starts, dim3(blocks), dim3(256), 0, stream, tb, jb);
+
+    // build & merge
+    const uint32_t wt = W <= 1 ? 1 : W <= 2 ? 2 : W <= 4 ? 4 : W <= 8 ? 8 : W <= 16 ? 16 : 32;
+#define SLPF_BUILD(WT_)                                                                                \
+    do {                                                                                               \
+        if (lds) hipLaunchKernelGGL((k_build<WT_, true>), dim3(blocks), dim3(256), lds_bytes, stream, tb, jb); \
+        else hipLaunchKernelGGL((k_build<WT_, false>), dim3(blocks), dim3(256), 0, stream, tb, jb);    \
+    } while (0)
+    switch (wt) {
+    case 1: SLPF_BUILD(1); break;
+    case 2: SLPF_BUILD(2); break;
+    case 4: SLPF_BUILD(4); break;
+    case 8: SLPF_BUILD(8); break;
+    case 16: SLPF_BUILD(16); break;
+    default: SLPF_BUILD(32); break;
+    }
+#undef SLPF_BUILD
+
+    // tree count
+    if (count) {
+        hipLaunchKernelGGL(k_count_chunk, dim3(c), dim3(64), 0, stream, tb, jb);
+        const uint64_t *in = nullptr;
+        const uint8_t *indims = jb.dims;
+        for (size_t l = 1; l < pl.size(); ++l) {
+            const bool last = (l + 1 == pl.size());
+            uint64_t *o = reinterpret_cast<uint64_t *>(ptr(pout[l - 1]));
+            uint8_t *od = ptr(pdims[l - 1]);
+            hipLaunchKernelGGL(k_prod, dim3(pl[l]), dim3(64), 0, stream, jb, l == 1 ? 1 : 0, in, indims, pl[l - 1],
+                               kProdGroup, o, od, last ? 1 : 0);
+            in = o;
+            indims = od;
+        }
+        if (pl.size() == 1)   // a single chunk: its matrix is the product
+            hipLaunchKernelGGL(k_prod, dim3(1), dim3(64), 0, stream, jb, 1, static_cast<const uint64_t *>(nullptr),
+                               indims, 1u, kProdGroup, static_cast<uint64_t *>(nullptr),
+                               static_cast<uint8_t *>(nullptr), 1);
+    } else {
+        hipLaunchKernelGGL(k_set_scalars, dim3(1), dim3(1), 0, stream, jb, 0ull, 2ull);
+    }
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(1), 0, stream, jb);
+    return hip_ok(hipGetLastError());
+}
+
+}  // extern "C"

@@ -1,0 +1,117 @@
+"""Host-side checks of the C ABI library (no GPU needed).
+
+The library must load and export every symbol declared in include/slpf.h, and
+its host compiler (row a0: RE -> segments, FolSeg, merged DFA/ME-DFA tables)
+must agree with the oracle: same segment strings in the same canonical order,
+same initial/final sets, and table states whose segment sets and transitions
+are exactly the oracle's powerset DFA (from I) and ME-DFA (from the
+singletons), forward and reverse.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from gen import regen
+from oracle.oracle import Oracle
+
+S = pytest.importorskip("paper_2503_06763_amd")
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    with open(os.path.join(ROOT, "include", "slpf.h")) as f:
+        src = f.read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(slpf_[a-z_]+)\s*\(", src)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = S.lib()
+    names = declared_functions()
+    assert set(names) == set(S.EXPORTS)
+    for nm in names:
+        assert hasattr(lib, nm), nm
+    assert S.status_str(0) == "ok" and S.status_str(-3) == "infinitely ambiguous RE"
+
+
+def _sets(o, words):
+    return [o.to_set(w) for w in words]
+
+
+RES = ["(ab|a)*", "(a|b|ab)+", "(a|ab|b)*(c|bc)+(a|b)*", "(a|())b", "(a|ab|aba)+", "a", "()",
+       "(a|b)*a(a|b)(a|b)(a|b)", "x(y|z+)*w?", "(\\(|\\)|\\*)+", "\\x00(\\n|\\t)*"]
+
+
+@pytest.mark.parametrize("pat", RES + [regen.to_re(regen.random_re(s, n_ops=14, max_depth=5)).decode()
+                                       for s in range(8)])
+def test_compiler_matches_oracle(pat):
+    o = Oracle(pat)
+    p = S.Parser(pat, host_only=True)
+    assert p.segments == o.segments
+    info = p.info
+    assert info.num_segments == o.nseg and info.words_per_column == o.W
+    assert info.num_initial == len(o.I) and info.num_final == len(o.F)
+    alphabet = sorted({a for a in o.labels if a >= 0})
+    for d in (0, 1):
+        sets, delta, cm = p.table(d)
+        got = _sets(o, sets)
+        assert got[0] == frozenset()
+        start = o.I if d == 0 else o.F
+        dfa_states, _ = o.powerset([start], d, alphabet)
+        me_states, _ = o.powerset([frozenset([j]) for j in range(o.nseg)], d, alphabet)
+        assert set(got[1:]) == set(dfa_states) | set(me_states)
+        assert len(got) - 1 == len(set(dfa_states) | set(me_states))
+        if d == 0:
+            assert info.dfa_states == len(dfa_states) and info.medfa_states == len(me_states)
+        else:
+            assert info.rdfa_states == len(dfa_states) and info.rmedfa_states == len(me_states)
+        # every transition is the oracle's NFA step on the set
+        for sid in range(1, len(got)):
+            for a in alphabet:
+                want = o.step_fwd(got[sid], a) if d == 0 else o.step_bwd(got[sid], a)
+                assert got[delta[sid, cm[a]]] == want
+        assert all(cm[b] == 0 for b in range(256) if b not in alphabet)
+
+
+def test_ek_dfa_column():
+    for k in range(1, 10):
+        p = S.Parser("(a|b)*a" + "(a|b)" * k, host_only=True)
+        assert p.info.dfa_states == 2 ** (k + 1) + 1
+
+
+def test_compile_errors():
+    for pat, st, off in [("(a|b", S.E_SYNTAX, 4), ("a)", S.E_SYNTAX, 1), ("*a", S.E_SYNTAX, 0),
+                         ("ab\\", S.E_SYNTAX, 2), ("\\xZZ", S.E_SYNTAX, 0)]:
+        with pytest.raises(S.SlpfError) as e:
+            S.Parser(pat, host_only=True)
+        assert e.value.status == st and e.value.offset == off, pat
+    for pat in ["(a|())*", "(a*)*", "(a?b?)+", "(()|b*)+"]:
+        with pytest.raises(S.SlpfError) as e:
+            S.Parser(pat, host_only=True)
+        assert e.value.status == S.E_INF_AMBIG, pat
+    with pytest.raises(S.SlpfError) as e:   # state limit
+        S.Parser("(a|b)*a" + "(a|b)" * 9, host_only=True, max_states=500)
+    assert e.value.status == S.E_TOO_LARGE
+    with pytest.raises(S.SlpfError) as e:   # segment limit
+        S.Parser("(a|b|c|d)*" * 40, host_only=True, max_segments=64)
+    assert e.value.status == S.E_TOO_LARGE
+
+
+def test_parse_with_host_only_parser_is_an_argument_error():
+    p = S.Parser("(ab|a)*", host_only=True)
+    L = S.lib()
+    f = S.Forest(1, 1 << 20, 1)
+    o = S.ParseOpts(ctypes.sizeof(S.ParseOpts), 0, 0, 0, None, 0)
+    assert L.slpf_parse(p.handle, None, 0, ctypes.byref(o), ctypes.byref(f), None) == S.E_ARG
+
+
+def test_forest_bytes_and_chunks():
+    p = S.Parser("(a|ab|b)*(c|bc)+(a|b)*", host_only=True)
+    assert p.forest_bytes(65536) == 65537 * 8
+    assert p.num_chunks(65536, 8192) == 8
+    assert p.num_chunks(65537, 8192) == 9
+    assert p.num_chunks(0, 8192) == 0

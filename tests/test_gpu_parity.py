@@ -1,0 +1,153 @@
+"""Parity of the HIP path (through the C ABI) with the serial CPU oracle.
+
+Bit-exact on every column word, the accept flag and the tree count modulo
+2^64, over the paper's worked examples, the plain-small workload, random REs
+and texts (accepted and rejected), every lane-chunk size from one window to
+the whole text, both table placements, and the edge cases (empty text, one
+byte, ragged last chunk, bytes outside the alphabet).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from gen import regen, textgen
+from gpu_util import gpu_parse, to_device
+from oracle.oracle import Oracle
+
+S = pytest.importorskip("paper_2503_06763_amd")
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def check(pat, text, chunk_bytes=0, force_l2=False, o=None, p=None):
+    o = o or Oracle(pat)
+    p = p or S.Parser(pat)
+    say("case", pat[:60] if isinstance(pat, str) else pat[:60], "n=%d" % len(text), "k=%d" % chunk_bytes,
+        "l2=%d" % force_l2)
+    cols, acc, cnt = o.parse(text)
+    gcols, gacc, gcnt, gst = gpu_parse(p, text, chunk_bytes=chunk_bytes, force_l2=force_l2)
+    assert gcols.shape == cols.shape
+    bad = np.nonzero((gcols != cols).any(axis=1))[0]
+    assert bad.size == 0, "first differing column %d of %d" % (bad[0], len(text) + 1)
+    assert gacc == acc
+    assert gst == 0 and gcnt == cnt
+    return o, p
+
+
+def test_worked_examples():
+    check("(ab|a)*", b"abaaba")
+    check("(ab|a)*", b"ab")
+    check("(a|b|ab)+", b"abab")
+    check("(a|ab|aba)+", b"aba")
+    check("(a|())b", b"b")
+
+
+def test_empty_and_tiny_texts():
+    for pat in ["(ab|a)*", "a(b|c)", "(a|b|ab)+"]:
+        o, p = Oracle(pat), S.Parser(pat)
+        for t in [b"", b"a", b"b", b"ab", b"z"]:
+            check(pat, t, o=o, p=p)
+
+
+def test_plain_small_workload():
+    tree = regen.plain_small_re()
+    pat = regen.to_re(tree).decode()
+    text = textgen.sample_text(tree, 1, 65536).tobytes()
+    o, p = Oracle(pat), S.Parser(pat)
+    check(pat, text, chunk_bytes=((len(text) + 7) // 8 + 63) // 64 * 64, o=o, p=p)   # 8 chunks
+    for k in (64, 128, 1024, 4096, 65536, 1 << 17):
+        check(pat, text, chunk_bytes=k, o=o, p=p)
+    check(pat, text, chunk_bytes=256, force_l2=True, o=o, p=p)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_res_and_texts(seed):
+    rng = np.random.default_rng(seed)
+    alpha = [b"ab", b"abc", b"abcdefghijklmnopqrstuvwxyz"][seed % 3]
+    depth = int(rng.integers(4, 8))
+    tree = regen.random_re(200 + seed, n_ops=int(rng.integers(6, 4 * depth)), max_depth=depth, alphabet=alpha)
+    pat = regen.to_re(tree)
+    try:
+        p = S.Parser(pat)
+    except S.SlpfError as e:   # entry lists beyond 64 segments: a documented limit
+        assert e.status == S.E_TOO_LARGE
+        pytest.skip("automaton beyond the library limits")
+    o = Oracle(pat)
+    n = int(rng.integers(1, 20000))
+    text = textgen.sample_text(tree, seed, n).tobytes()
+    check(pat, text, chunk_bytes=64 * int(rng.integers(1, 40)), o=o, p=p)
+    # corrupted: one byte flipped (usually rejected), and a byte outside the alphabet
+    bad = bytearray(text)
+    if bad:
+        bad[int(rng.integers(len(bad)))] = alpha[int(rng.integers(len(alpha)))]
+        check(pat, bytes(bad), chunk_bytes=128, o=o, p=p)
+        bad[len(bad) // 2] = 0xff
+        check(pat, bytes(bad), chunk_bytes=64, o=o, p=p)
+
+
+def test_motif_re_counts():
+    tree = regen.motif_re()
+    pat = regen.to_re(tree)
+    text = textgen.sample_text(tree, 3, 30000).tobytes()
+    o, p = Oracle(pat), S.Parser(pat)
+    for k in (64, 448, 4096):
+        check(pat, text, chunk_bytes=k, o=o, p=p)
+
+
+def test_join_trace_matches_oracle_columns():
+    """J and J^ at every lane-chunk edge equal the serial forward and backward
+    columns there (Eq. joiner reproduces Eq. matrixmul at the chunk edges)."""
+    tree = regen.plain_small_re()
+    pat = regen.to_re(tree).decode()
+    text = textgen.sample_text(tree, 7, 5000).tobytes()
+    o, p = Oracle(pat), S.Parser(pat)
+    k = 192
+    gcols, gacc, gcnt, gst, tr = gpu_parse(p, text, chunk_bytes=k, trace=True)
+    n = len(text)
+    fwd = [o.I]
+    for a in text:
+        fwd.append(o.step_fwd(fwd[-1], a))
+    bwd = [o.F]
+    for a in reversed(text):
+        bwd.append(o.step_bwd(bwd[-1], a))
+    bwd.reverse()
+    c = (n + k - 1) // k
+    for b in range(c + 1):
+        pos = min(b * k, n)
+        assert o.to_set(tr[0, b]) == fwd[pos], b
+        assert o.to_set(tr[1, b]) == bwd[pos], b
+
+
+def test_chunking_invariance_all_sizes():
+    tree = regen.random_re(11, n_ops=20, max_depth=5, alphabet=b"abc")
+    pat = regen.to_re(tree)
+    text = textgen.sample_text(tree, 5, 3000).tobytes()
+    o, p = Oracle(pat), S.Parser(pat)
+    ref = gpu_parse(p, text, chunk_bytes=1 << 16)
+    for k in range(64, 3200, 64):
+        g = gpu_parse(p, text, chunk_bytes=k)
+        assert np.array_equal(g[0], ref[0]) and g[1:] == ref[1:], k
+    check(pat, text, chunk_bytes=64, o=o, p=p)
+
+
+def test_argument_errors():
+    import torch
+    p = S.Parser("(ab|a)*")
+    t = to_device(b"abab" * 10)
+    cols = torch.empty((41, p.W), dtype=torch.int64, device=t.device)
+    sc = torch.empty(3, dtype=torch.int64, device=t.device)
+    with pytest.raises(S.SlpfError) as e:       # capacity
+        p.parse_into(t, 40, cols[:10], sc)
+    assert e.value.status == S.E_CAPACITY
+    with pytest.raises(S.SlpfError) as e:       # chunk size not a multiple of 64
+        p.parse_into(t, 40, cols, sc, chunk_bytes=100)
+    assert e.value.status == S.E_ARG
+    big = torch.empty(64, dtype=torch.uint8, device=t.device)
+    with pytest.raises(S.SlpfError) as e:       # misaligned text
+        p.parse_into(big[1:], 40, cols, sc)
+    assert e.value.status == S.E_ARG
