@@ -150,7 +150,16 @@ typedef struct {
     uint32_t reserved;
     uint64_t *trace_dev;      /* optional: receives the join results, see below */
     uint64_t trace_bytes;     /* capacity of trace_dev */
+    void *const *events;      /* optional: SLPF_NUM_PHASE_EVENTS caller-created hipEvent_t */
+    uint32_t num_events;      /* 0, or SLPF_NUM_PHASE_EVENTS */
+    uint32_t reserved2;
 } slpf_parse_opts;
+
+/* Phase events: when opts->events is set, events[k] is recorded on the parse
+ * stream before reach (0), after reach (1), after the join scans (2), after
+ * the join start ids (3), after build & merge (4) and after the tree count
+ * (5), so that hipEventElapsedTime gives each phase's device time. */
+#define SLPF_NUM_PHASE_EVENTS 6
 
 /*
  * Output of a parse.  columns_dev: the SLPF, column r (0 <= r <= n) at

@@ -54,7 +54,12 @@ class ParserInfo(ctypes.Structure):
 class ParseOpts(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("chunk_bytes", ctypes.c_uint32),
                 ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
-                ("trace_dev", ctypes.c_void_p), ("trace_bytes", ctypes.c_uint64)]
+                ("trace_dev", ctypes.c_void_p), ("trace_bytes", ctypes.c_uint64),
+                ("events", ctypes.POINTER(ctypes.c_void_p)), ("num_events", ctypes.c_uint32),
+                ("reserved2", ctypes.c_uint32)]
+
+NUM_PHASE_EVENTS = 6
+PHASES = ["reach", "join", "starts", "build", "count"]
 
 
 class Forest(ctypes.Structure):
@@ -187,25 +192,36 @@ class Parser:
         return int(self._L.slpf_forest_bytes(self._h, n))
 
     def num_chunks(self, n: int, chunk_bytes: int = 0) -> int:
-        o = ParseOpts(ctypes.sizeof(ParseOpts), chunk_bytes, 0, 0, None, 0)
+        o = ParseOpts(ctypes.sizeof(ParseOpts), chunk_bytes, 0, 0, None, 0, None, 0, 0)
         return int(self._L.slpf_num_chunks(self._h, n, ctypes.byref(o)))
 
     def parse_into(self, text, n: int, columns, scalars, chunk_bytes: int = 0, flags: int = 0,
-                   trace=None, stream=None):
-        """Raw slpf_parse on torch device tensors (asynchronous on ``stream``)."""
+                   trace=None, stream=None, events=None):
+        """Raw slpf_parse on torch device tensors (asynchronous on ``stream``).
+
+        ``events``: optional list of NUM_PHASE_EVENTS torch.cuda.Event(enable_timing=True),
+        recorded on the parse stream at the phase boundaries."""
         import torch
         if stream is None:
             stream = torch.cuda.current_stream(text.device)
+        ev = None
+        if events is not None:
+            for e in events:
+                if not e.cuda_event:      # torch creates the HIP event on its first record
+                    e.record(stream)
+            ev = (ctypes.c_void_p * len(events))(*[e.cuda_event for e in events])
         o = ParseOpts(ctypes.sizeof(ParseOpts), chunk_bytes, flags, 0,
                       trace.data_ptr() if trace is not None else None,
-                      trace.numel() * trace.element_size() if trace is not None else 0)
+                      trace.numel() * trace.element_size() if trace is not None else 0,
+                      ctypes.cast(ev, ctypes.POINTER(ctypes.c_void_p)) if ev is not None else None,
+                      len(events) if events is not None else 0, 0)
         f = Forest(columns.data_ptr(), columns.numel() * columns.element_size(), scalars.data_ptr())
         st = self._L.slpf_parse(self._h, text.data_ptr() if n else None, n, ctypes.byref(o), ctypes.byref(f),
                                 ctypes.c_void_p(stream.cuda_stream))
         _check(st, "slpf_parse")
 
     def parse(self, text, chunk_bytes: int = 0, count: bool = True, force_l2: bool = False,
-              trace: bool = False, stream=None):
+              trace: bool = False, stream=None, events=None):
         """Parse a uint8 device tensor; returns (columns [n+1, W] int64 view of uint64 words,
         scalars [3]) on the device, plus the join trace if asked."""
         import torch
@@ -218,7 +234,7 @@ class Parser:
             c = self.num_chunks(n, chunk_bytes)
             tr = torch.zeros((2, c + 1, self.W), dtype=torch.int64, device=dev)
         flags = (0 if count else PARSE_NO_COUNT) | (PARSE_FORCE_L2 if force_l2 else 0)
-        self.parse_into(text, n, cols, sc, chunk_bytes, flags, tr, stream)
+        self.parse_into(text, n, cols, sc, chunk_bytes, flags, tr, stream, events)
         return (cols, sc, tr) if trace else (cols, sc)
 
 

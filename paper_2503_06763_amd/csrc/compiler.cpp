@@ -416,6 +416,7 @@ int compile_re(const uint8_t *re, size_t len, const CompileLimits &lim, HostAuto
             if (used[b]) A.classmap[b] = c++;
         A.C = c;
     }
+    if (A.C > 256) return SLPF_E_TOO_LARGE;   // class ids are packed into bytes on the device
     const uint32_t C = A.C;
 
     // per segment: end symbol, label class; I, F; followers grouped by end symbol

@@ -62,6 +62,7 @@ struct Tabs {
     uint32_t nf, nr;            // table sizes including id 0
     uint32_t fstart, rstart;    // ids of I and F
     uint32_t emax;
+    uint64_t wmagic;            // ceil(2^32 / W): e / W == (e * wmagic) >> 32 for e < 2^16
 };
 
 struct Job {
@@ -74,23 +75,30 @@ struct Job {
     uint8_t *nxf, *nxb;         // |X_b| for b = 0..c (nxb reversed: nxb[k] = |X_{c-k}|)
     uint64_t *vf, *vb;          // join vectors, vf[b] = J_b & X_b, vb[k] = J^_{c-k} & X_{c-k}
     uint16_t *fid, *rid;        // build start ids per chunk
-    uint16_t *ckpt;             // forward id every 64 bytes
+    uint16_t *ckpt;             // forward id at the left edge of every 64-byte window
+    uint16_t *bckpt;            // backward id at the right edge of every 64-byte window
     uint64_t *out;              // SLPF columns
     uint64_t *scalars;          // [0] accepted [1] count [2] count status
-    uint32_t *flags;            // [0] set not found, [1] big-slot counter, [2] count overflow
+    uint32_t *flags;            // [0] set not found, [1] big-slot counter, [2] count impossible,
+                                // [3] chunks for the general count kernel
     uint64_t *trace;            // optional J / J^ words
     // tree count
     uint8_t *dims;              // [c][2]: edge column sizes
-    uint64_t *tsmall;           // [c][8*8]
-    uint32_t *tbig_idx;         // [c], 0xffffffff = small slot
+    uint64_t *uv;               // [c][2][kVec]: u (right edge) then v (left edge) of a rank-1 chunk
+    uint64_t *pi;               // [c] scalar factor of a rank-1 chunk
+    uint64_t *factor;           // [c+1] per-edge factors of the count
+    uint32_t *tbig_idx;         // [c], kRank1, kOverflow or a pool slot of a full matrix
+    uint32_t *ovf;              // chunks left to the general count kernel (count in flags[3])
     uint64_t *tbig;             // [pool][64*64]
     uint32_t big_pool;
 };
 
 constexpr int kDedupEvery = 32;
 constexpr int kGroup = 8;
-constexpr int kSmallT = 8;
 constexpr int kBigT = 64;
+constexpr int kVec = 16;                      // clean-column segments handled by the fast count
+constexpr uint32_t kRank1 = 0xffffffffu;       // chunk matrix held as v * pi * u^T
+constexpr uint32_t kOverflow = 0xfffffffeu;    // chunk left to the general count kernel
 
 __device__ inline uint32_t boundary_list(const Tabs &tb, const uint16_t *cls, const uint8_t *text,
                                          uint64_t n, uint64_t s, uint32_t c, uint32_t b) {
@@ -192,19 +200,17 @@ __device__ inline void load_window(const uint8_t *text, uint64_t a0, uint32_t le
 
 // -------------------------------------------------------------------- reach
 
-// Runs kGroup ME-DFA runs in lockstep over `len` bytes starting at `base`
-// (forward) or ending at `base + len` (backward).  Runs that reach the same
-// state are merged (equal states have equal futures); `alias` maps entry k
-// of the group to the slot holding its run.
+// Runs kGroup ME-DFA runs in lockstep over text[lo, hi) (forward) or its
+// reverse (backward); lo is 16-byte aligned, so the body is read with 16-byte
+// loads.  Runs that reach the same state are merged (equal states have equal
+// futures); `alias` maps entry k of the group to the slot holding its run.
+// Slots dead in every lane of the wavefront are skipped.
 template <bool FWD>
 __device__ inline void run_group(const uint8_t *text, uint64_t lo, uint64_t hi, const uint16_t *cls,
                                  const uint16_t *delta, uint32_t C, uint32_t st[kGroup],
                                  uint32_t &alias) {
-    uint32_t nl = kGroup;   // wave-uniform bound on live slots
-    uint64_t len = hi - lo;
-    uint64_t done = 0;
-    while (done < len) {
-        // dedup + liveness, uniform across the wave
+    uint32_t nl = kGroup;
+    auto settle = [&]() -> bool {
 #pragma unroll
         for (int j = 1; j < kGroup; ++j) {
 #pragma unroll
@@ -222,22 +228,36 @@ __device__ inline void run_group(const uint8_t *text, uint64_t lo, uint64_t hi, 
 #pragma unroll
         for (int j = 0; j < kGroup; ++j)
             if (st[j]) top = j + 1;
-        // wave max of top
         nl = 0;
 #pragma unroll
         for (int j = kGroup; j >= 1; --j)
             if (nl == 0 && __any(top >= static_cast<uint32_t>(j))) nl = j;
-        if (nl == 0) return;
-        uint64_t step = len - done < kDedupEvery ? len - done : kDedupEvery;
-        for (uint64_t t = 0; t < step; ++t) {
-            uint64_t pos = FWD ? lo + done + t : hi - 1 - done - t;
-            uint32_t cl = cls[text[pos]];
+        return nl != 0;
+    };
+    auto step = [&](uint32_t byte) {
+        const uint32_t cl = cls[byte];
 #pragma unroll
-            for (int j = 0; j < kGroup; ++j)
-                if (j < static_cast<int>(nl)) st[j] = delta[st[j] * C + cl];
+        for (int j = 0; j < kGroup; ++j)
+            if (j < static_cast<int>(nl)) st[j] = delta[st[j] * C + cl];
+    };
+    const uint64_t body = (hi - lo) & ~15ull;
+    if (!settle()) return;
+    if (!FWD)
+        for (uint64_t p = hi; p-- > lo + body;) step(text[p]);
+    const uint64_t nblk = body >> 4;
+    const uint4 *vp = reinterpret_cast<const uint4 *>(text + lo);
+    for (uint64_t k = 0; k < nblk; ++k) {
+        if ((k & 3) == 3 && !settle()) return;
+        const uint4 v = vp[FWD ? k : nblk - 1 - k];
+        const uint32_t wd[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            const int tt = FWD ? t : 15 - t;
+            step((wd[tt >> 2] >> ((tt & 3) * 8)) & 0xffu);
         }
-        done += step;
     }
+    if (FWD)
+        for (uint64_t p = lo + body; p < hi; ++p) step(text[p]);
 }
 
 template <bool LDS>
@@ -444,65 +464,504 @@ __global__ __launch_bounds__(256) void k_starts(Tabs tb, Job jb) {
 
 // -------------------------------------------------------------------- build
 
-template <int WT, bool LDS>
-__global__ __launch_bounds__(256) void k_build(Tabs tb, Job jb) {
-    extern __shared__ __align__(16) uint8_t smem[];
-    Lookup<LDS> lk = stage_tables<LDS>(tb, smem, true, true);
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= jb.c) return;
-    const uint32_t C = tb.C, W = tb.W;
-    const uint64_t lo = static_cast<uint64_t>(i) * jb.s;
-    const uint64_t hi = (i + 1 == jb.c) ? jb.n : lo + jb.s;
-    const uint16_t *cls = lk.cls, *fd = lk.fd, *rd = lk.rd;
-    uint32_t xw[16];
 
-    // forward DFA run from J at P_i, one checkpoint per 64-byte window
-    uint32_t f = jb.fid[i];
-    for (uint64_t a0 = lo; a0 < hi; a0 += 64) {
-        const uint32_t len = static_cast<uint32_t>(hi - a0 < 64 ? hi - a0 : 64);
-        jb.ckpt[a0 >> 6] = static_cast<uint16_t>(f);
-        load_window(jb.text, a0, len, xw);
-#pragma unroll
-        for (int t = 0; t < 64; ++t)
-            if (t < static_cast<int>(len)) f = fd[f * C + cls[byte_of(xw, t)]];
-    }
+// Tables for the build and count kernels: class map and transition tables
+// (TAB_LDS) and the state bit sets (BITS_LDS) staged in LDS after `skip`
+// bytes of the dynamic LDS area, or read in place.
+template <bool TAB_LDS, bool BITS_LDS>
+struct BuildTabs {
+    const uint16_t *cls, *fd, *rd;
+    const uint64_t *fb, *rb;
+};
 
-    // backward reverse-DFA run from J^ at P_{i+1}; merge window by window
-    uint32_t b = jb.rid[i];
-    const uint64_t last = lo + ((hi - lo - 1) & ~63ull);
-    for (uint64_t a0 = last;; a0 -= 64) {
-        const uint32_t len = static_cast<uint32_t>(hi - a0 < 64 ? hi - a0 : 64);
-        load_window(jb.text, a0, len, xw);
-        uint32_t fw[64];
-        uint32_t g = jb.ckpt[a0 >> 6];
-#pragma unroll
-        for (int t = 0; t < 64; ++t) {
-            if (t < static_cast<int>(len)) g = fd[g * C + cls[byte_of(xw, t)]];
-            fw[t] = g;
-        }
-#pragma unroll
-        for (int t = 63; t >= 0; --t) {
-            if (t < static_cast<int>(len)) {
-                const uint64_t r = a0 + t + 1;
-                const uint64_t *fb = tb.fbits + static_cast<uint64_t>(fw[t]) * W;
-                const uint64_t *rb = tb.rbits + static_cast<uint64_t>(b) * W;
-                uint64_t *o = jb.out + r * W;
-#pragma unroll
-                for (int w = 0; w < WT; ++w)
-                    if (w < static_cast<int>(W)) o[w] = fb[w] & rb[w];
-                b = rd[b * C + cls[byte_of(xw, t)]];
-            }
-        }
-        if (a0 == lo) break;
+template <bool TAB_LDS, bool BITS_LDS>
+__device__ inline BuildTabs<TAB_LDS, BITS_LDS> stage_build(const Tabs &tb, uint8_t *smem, uint32_t skip) {
+    BuildTabs<TAB_LDS, BITS_LDS> t;
+    const uint32_t nth = blockDim.x;
+    uint8_t *p = smem + skip;
+    if constexpr (TAB_LDS) {
+        uint16_t *cls = reinterpret_cast<uint16_t *>(p);
+        uint16_t *fd = cls + 256;
+        uint16_t *rd = fd + tb.nf * tb.C;
+        for (uint32_t k = threadIdx.x; k < 256; k += nth) cls[k] = tb.classmap[k];
+        for (uint32_t k = threadIdx.x; k < tb.nf * tb.C; k += nth) fd[k] = tb.fdelta[k];
+        for (uint32_t k = threadIdx.x; k < tb.nr * tb.C; k += nth) rd[k] = tb.rdelta[k];
+        t.cls = cls;
+        t.fd = fd;
+        t.rd = rd;
+        p += (512 + (tb.nf + tb.nr) * tb.C * 2 + 15) & ~15u;
+    } else {
+        t.cls = tb.classmap;
+        t.fd = tb.fdelta;
+        t.rd = tb.rdelta;
     }
-    if (i == 0) {   // compose: C_0 = J_0 & J^_1
-        const uint64_t *fb = tb.fbits + static_cast<uint64_t>(tb.fstart) * W;
-        const uint64_t *rb = tb.rbits + static_cast<uint64_t>(b) * W;
-        for (uint32_t w = 0; w < W; ++w) jb.out[w] = fb[w] & rb[w];
+    if constexpr (BITS_LDS) {
+        uint64_t *fb = reinterpret_cast<uint64_t *>(p);
+        uint64_t *rb = fb + tb.nf * tb.W;
+        for (uint32_t k = threadIdx.x; k < tb.nf * tb.W; k += nth) fb[k] = tb.fbits[k];
+        for (uint32_t k = threadIdx.x; k < tb.nr * tb.W; k += nth) rb[k] = tb.rbits[k];
+        t.fb = fb;
+        t.rb = rb;
+    } else {
+        t.fb = tb.fbits;
+        t.rb = tb.rbits;
+    }
+    __syncthreads();
+    return t;
+}
+
+__device__ inline uint64_t shfl_u64(uint64_t v, int src) {
+    uint32_t lo = __shfl(static_cast<uint32_t>(v), src);
+    uint32_t hi = __shfl(static_cast<uint32_t>(v >> 32), src);
+    return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
+// Wavefront-local synchronization: LDS written by some lanes of a wavefront
+// is visible to the other lanes of the same wavefront after this point.
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Classes of the 64 window bytes, packed four per word.
+template <class BT>
+__device__ inline void window_classes(const BT &T, const uint32_t *xw, uint32_t *cw) {
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const uint32_t v = xw[k];
+        cw[k] = static_cast<uint32_t>(T.cls[v & 0xffu]) | (static_cast<uint32_t>(T.cls[(v >> 8) & 0xffu]) << 8) |
+                (static_cast<uint32_t>(T.cls[(v >> 16) & 0xffu]) << 16) |
+                (static_cast<uint32_t>(T.cls[v >> 24]) << 24);
     }
 }
 
-// --------------------------------------------------------------- tree count
+constexpr int kBuildThreads = 512;             // 8 wavefronts
+constexpr int kHalf = 32;                      // positions per staged half window
+constexpr int kStageRow = kHalf + 1;           // padded: lanes fall in distinct banks
+constexpr int kStageBytes = kBuildThreads * kStageRow * 4;
+
+// Fused builder & merger.  Each lane owns one chunk and writes its columns
+// P_i .. P_{i+1}-1 (the last chunk also the text-end column n): a forward DFA
+// run from J at P_i storing a checkpoint per 64-byte window, then window by
+// window from the right: the reverse DFA runs from the right edge while the
+// forward ids of the next window to the left are recomputed from its
+// checkpoint (two independent lookup chains per lane), and the (forward,
+// backward) id pair of every column goes to LDS.  Every 32 columns the
+// wavefront writes the staged columns of its 64 chunks, each chunk's columns
+// as one contiguous run of W-word columns starting on a 32-column boundary
+// (so on a 128-byte boundary for any W); lane e writes word e, 512
+// contiguous bytes per store instruction.  Wavefronts synchronize only with
+// themselves.
+template <bool TAB_LDS, bool BITS_LDS>
+__global__ __launch_bounds__(kBuildThreads) void k_build(Tabs tb, Job jb) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    uint32_t *stage = reinterpret_cast<uint32_t *>(smem);
+    const BuildTabs<TAB_LDS, BITS_LDS> T = stage_build<TAB_LDS, BITS_LDS>(tb, smem, kStageBytes);
+    const uint32_t C = tb.C, W = tb.W;
+    const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t wave_first = blockIdx.x * blockDim.x + wv * 64;
+    if (wave_first >= jb.c) return;                 // whole wavefront idle
+    const bool act = i < jb.c;
+    const uint64_t s = jb.s;
+    uint64_t lo = 0, hi = 0;
+    uint32_t nwin = 0;
+    if (act) {
+        lo = static_cast<uint64_t>(i) * s;
+        hi = (i + 1 == jb.c) ? jb.n : lo + s;
+        nwin = static_cast<uint32_t>((hi - lo + 63) / 64);
+    }
+    // windows of the wavefront's longest chunk (only the text's last chunk is shorter)
+    const uint32_t nwin_wave = (wave_first + 1 < jb.c) ? static_cast<uint32_t>(s / 64)
+                                                       : static_cast<uint32_t>((jb.n - static_cast<uint64_t>(jb.c - 1) * s + 63) / 64);
+    uint32_t xw[16], cw[16];
+
+    // forward sweep: checkpoints
+    uint32_t f = act ? jb.fid[i] : 0;
+    for (uint32_t w = 0; w < nwin; ++w) {
+        const uint64_t a0 = lo + 64ull * w;
+        const uint32_t len = static_cast<uint32_t>(hi - a0 < 64 ? hi - a0 : 64);
+        jb.ckpt[a0 >> 6] = static_cast<uint16_t>(f);
+        load_window(jb.text, a0, len, xw);
+        window_classes(T, xw, cw);
+#pragma unroll
+        for (int t = 0; t < 64; ++t)
+            if (t < static_cast<int>(len)) f = T.fd[f * C + byte_of(cw, t)];
+    }
+    if (i + 1 == jb.c) {   // the text-end column: J_c & F
+        for (uint32_t w = 0; w < W; ++w)
+            jb.out[jb.n * W + w] = T.fb[f * W + w] & T.rb[tb.rstart * W + w];
+    }
+
+    // backward sweep, two windows in flight; fwA[t] = forward id at column a0+t
+    uint32_t b = act ? jb.rid[i] : 0;
+    uint32_t *mine = stage + threadIdx.x * kStageRow;
+    const uint32_t *wave_rows = stage + wv * 64 * kStageRow;
+    uint32_t fwA[64], cwA[16];
+    uint32_t lenA = 0;
+    uint64_t a0A = 0;
+    if (nwin) {   // the last window of the chunk
+        a0A = lo + 64ull * (nwin - 1);
+        lenA = static_cast<uint32_t>(hi - a0A);
+        load_window(jb.text, a0A, lenA, xw);
+        window_classes(T, xw, cwA);
+        uint32_t g = jb.ckpt[a0A >> 6];
+#pragma unroll
+        for (int t = 0; t < 64; ++t) {
+            fwA[t] = g;
+            if (t < static_cast<int>(lenA)) g = T.fd[g * C + byte_of(cwA, t)];
+        }
+    }
+    for (int w = static_cast<int>(nwin_wave) - 1; w >= 0; --w) {
+        const bool on = w < static_cast<int>(nwin);
+        // window w-1 (full length) is prepared while window w is merged
+        const bool nxt = on && w > 0;
+        uint32_t cwB[16], fwB[64];
+        uint32_t g = 0;
+        if (nxt) {
+            load_window(jb.text, lo + 64ull * (w - 1), 64, xw);
+            window_classes(T, xw, cwB);
+            g = jb.ckpt[(lo >> 6) + w - 1];
+        }
+        if (on) jb.bckpt[a0A >> 6] = static_cast<uint16_t>(b);
+        const uint32_t len_now = on ? lenA : 0;
+#pragma unroll
+        for (int h = 1; h >= 0; --h) {
+            // columns a0+32h .. a0+32h+31 of window w, right to left
+#pragma unroll
+            for (int u = kHalf - 1; u >= 0; --u) {
+                const int t = h * kHalf + u;
+                if (on && t < static_cast<int>(lenA)) {
+                    b = T.rd[b * C + byte_of(cwA, t)];    // now the backward id at column a0+t
+                    mine[u] = fwA[t] | (b << 16);
+                }
+                const int tf = (1 - h) * kHalf + (kHalf - 1 - u);   // forward step of window w-1
+                if (nxt) {
+                    fwB[tf] = g;
+                    g = T.fd[g * C + byte_of(cwB, tf)];
+                }
+            }
+            wave_sync();
+            // write columns a0+32h .. of every chunk of the wavefront
+            for (int j = 0; j < 64; ++j) {
+                const uint32_t lj = __builtin_amdgcn_readlane(len_now, j);
+                const uint32_t np = lj > static_cast<uint32_t>(h * kHalf)
+                                        ? (lj - h * kHalf < static_cast<uint32_t>(kHalf) ? lj - h * kHalf : kHalf) : 0;
+                if (np == 0) continue;
+                const uint64_t aj = (static_cast<uint64_t>(__builtin_amdgcn_readlane(static_cast<uint32_t>(a0A >> 32), j)) << 32) |
+                                    __builtin_amdgcn_readlane(static_cast<uint32_t>(a0A), j);
+                uint64_t *region = jb.out + (aj + h * kHalf) * W;
+                const uint32_t *sj = wave_rows + j * kStageRow;
+                const uint32_t nwords = np * W;
+                for (uint32_t e = lane; e < nwords; e += 64) {
+                    const uint32_t p = static_cast<uint32_t>((static_cast<uint64_t>(e) * tb.wmagic) >> 32);
+                    const uint32_t ww = e - p * W;
+                    const uint32_t v = sj[p];
+                    region[e] = T.fb[(v & 0xffffu) * W + ww] & T.rb[(v >> 16) * W + ww];
+                }
+            }
+            wave_sync();
+        }
+        if (nxt) {
+#pragma unroll
+            for (int t = 0; t < 64; ++t) fwA[t] = fwB[t];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) cwA[k] = cwB[k];
+            lenA = 64;
+            a0A = lo + 64ull * (w - 1);
+        }
+    }
+}
+
+// ------------------------------------------------------ tree count, fast path
+
+// List the segments of the clean column (fi, bi) into seg[0..kVec); returns
+// the number of segments (values beyond kVec are not listed).
+template <class BT>
+__device__ inline uint32_t list_clean(const BT &T, uint32_t W, uint32_t fi, uint32_t bi, uint32_t seg[kVec]) {
+    uint32_t m = 0;
+    for (uint32_t w = 0; w < W; ++w) {
+        uint64_t v = T.fb[fi * W + w] & T.rb[bi * W + w];
+        while (v) {
+            const uint32_t sg = w * 64 + __builtin_ctzll(v);
+            v &= v - 1;
+#pragma unroll
+            for (int k = 0; k < kVec; ++k)
+                if (m == static_cast<uint32_t>(k)) seg[k] = sg;
+            ++m;
+        }
+    }
+    return m;
+}
+
+__device__ inline bool follows(const uint64_t *folseg, uint32_t W, uint32_t rho, uint32_t sigma) {
+    return (folseg[static_cast<uint64_t>(rho) * W + (sigma >> 6)] >> (sigma & 63)) & 1ull;
+}
+
+// Fast tree count.  Paths through a singleton clean column all pass through
+// its one segment, so a chunk with a singleton column r1 has the rank-1
+// transfer matrix T = v * pi * u^T:
+//   u[q]  paths from the segment of r1 to the q-th segment of the right edge
+//         column (vector DP forwards from r1, r1 the rightmost singleton);
+//   pi    product of the path counts between consecutive singleton columns
+//         (vector DP backwards from r1, collapsing at every singleton);
+//   v[k]  paths from the k-th segment of the left edge column to the leftmost
+//         singleton.
+// Columns are recomputed from the build's window checkpoints.  Chunks with no
+// singleton column or a column of more than kVec segments go to the general
+// kernel.
+template <bool TAB_LDS, bool BITS_LDS>
+__global__ __launch_bounds__(128) void k_count_fast(Tabs tb, Job jb) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    if (jb.scalars[0] == 0) return;    // rejected text: no tree
+    constexpr uint32_t kLanes = 128;
+    uint16_t *fws = reinterpret_cast<uint16_t *>(smem);        // [128][64] forward ids
+    uint16_t *bws = fws + kLanes * 64;                         // [128][64] backward ids
+    uint8_t *xbs = reinterpret_cast<uint8_t *>(bws + kLanes * 64);   // [128][64] bytes
+    const BuildTabs<TAB_LDS, BITS_LDS> T = stage_build<TAB_LDS, BITS_LDS>(tb, smem, kLanes * 64 * 5);
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= jb.c) return;
+    const uint32_t C = tb.C, W = tb.W;
+    const uint64_t *folseg = tb.folseg;
+    const uint64_t lo = static_cast<uint64_t>(i) * jb.s;
+    const uint64_t hi = (i + 1 == jb.c) ? jb.n : lo + jb.s;
+    const uint32_t nwin = static_cast<uint32_t>((hi - lo + 63) / 64);
+    uint16_t *myf = fws + threadIdx.x * 64;
+    uint16_t *myb = bws + threadIdx.x * 64;
+    uint8_t *myx = xbs + threadIdx.x * 64;
+    uint32_t xw[16];
+
+    uint64_t y[kVec];
+    uint32_t prev[kVec], cur[kVec];
+    uint32_t mp = 0;
+    uint64_t pi = 1;
+    bool found = false, over = false;
+    uint64_t r1 = 0;
+#pragma unroll
+    for (int k = 0; k < kVec; ++k) y[k] = 0, prev[k] = 0, cur[k] = 0;
+
+    // one backward step: y over column r+1 (prev, mp) -> column r (cur, m)
+    auto back = [&](uint32_t m) {
+        uint64_t z[kVec];
+#pragma unroll
+        for (int k = 0; k < kVec; ++k) {
+            z[k] = 0;
+            if (k < static_cast<int>(m)) {
+                if (mp == 1) {
+                    z[k] = y[0];
+                } else {
+#pragma unroll
+                    for (int j = 0; j < kVec; ++j)
+                        if (j < static_cast<int>(mp) && (m == 1 || follows(folseg, W, cur[k], prev[j]))) z[k] += y[j];
+                }
+            }
+        }
+        if (m == 1) {          // singleton: collapse into pi, restart from 1
+            pi *= z[0];
+            z[0] = 1;
+        }
+#pragma unroll
+        for (int k = 0; k < kVec; ++k) y[k] = z[k], prev[k] = cur[k];
+        mp = m;
+    };
+
+    uint32_t b = 0;
+    for (int w = static_cast<int>(nwin) - 1; w >= 0 && !over; --w) {
+        const uint64_t a0 = lo + 64ull * w;
+        const uint32_t len = static_cast<uint32_t>(hi - a0 < 64 ? hi - a0 : 64);
+        load_window(jb.text, a0, len, xw);
+        uint32_t g = jb.ckpt[a0 >> 6];
+#pragma unroll
+        for (int t = 0; t < 64; ++t) {
+            const uint32_t x = byte_of(xw, t);
+            if (t < static_cast<int>(len)) g = T.fd[g * C + T.cls[x]];
+            myf[t] = static_cast<uint16_t>(g);
+            myx[t] = static_cast<uint8_t>(x);
+        }
+        b = jb.bckpt[a0 >> 6];
+        for (int t = static_cast<int>(len) - 1; t >= 0; --t) {
+            const uint32_t m = list_clean(T, W, myf[t], b, cur);
+            if (m > static_cast<uint32_t>(kVec) || m == 0) {
+                over = true;
+                break;
+            }
+            if (found) {
+                back(m);
+            } else if (m == 1) {
+                found = true;
+                r1 = a0 + t + 1;
+                y[0] = 1;
+                prev[0] = cur[0];
+                mp = 1;
+            }
+            b = T.rd[b * C + T.cls[myx[t]]];
+        }
+    }
+    uint32_t mL = 0;
+    if (!over) {   // the left edge column P_i
+        const uint32_t m = list_clean(T, W, jb.fid[i], b, cur);
+        if (m > static_cast<uint32_t>(kVec) || m == 0) over = true;
+        else if (found) back(m);
+        else if (m == 1) {
+            found = true;
+            r1 = lo;
+            y[0] = 1;
+            prev[0] = cur[0];
+            mp = 1;
+        } else over = true;          // no singleton column in the chunk
+        mL = m;
+    }
+    if (over) {
+        jb.tbig_idx[i] = kOverflow;
+        jb.ovf[atomicAdd(&jb.flags[3], 1u)] = i;
+        return;
+    }
+    // pi counted the singleton at the left edge collapse: if the left edge
+    // column is a singleton its path count went into pi and v = [1]
+    uint64_t *uv = jb.uv + static_cast<uint64_t>(i) * 2 * kVec;
+#pragma unroll
+    for (int k = 0; k < kVec; ++k) uv[kVec + k] = y[k];
+
+    // forward from r1 to the right edge: x[k] = paths from r1's segment to
+    // the k-th segment of the current column
+    uint64_t x[kVec];
+    uint32_t pseg[kVec];
+#pragma unroll
+    for (int k = 0; k < kVec; ++k) x[k] = 0, pseg[k] = 0;
+    x[0] = 1;
+    uint32_t pm = 1;
+    const uint32_t w_start = static_cast<uint32_t>(r1 > lo ? (r1 - 1 - lo) / 64 : 0);
+    for (uint32_t w = w_start; w < nwin; ++w) {
+        const uint64_t a0 = lo + 64ull * w;
+        const uint32_t len = static_cast<uint32_t>(hi - a0 < 64 ? hi - a0 : 64);
+        load_window(jb.text, a0, len, xw);
+        const uint32_t g0 = jb.ckpt[a0 >> 6];
+        uint32_t g = g0, bb = jb.bckpt[a0 >> 6];
+#pragma unroll
+        for (int t = 63; t >= 0; --t) {
+            if (t < static_cast<int>(len)) {
+                myb[t] = static_cast<uint16_t>(bb);      // backward id at column a0+t+1
+                bb = T.rd[bb * C + T.cls[byte_of(xw, t)]];
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 64; ++t) {
+            if (t < static_cast<int>(len)) g = T.fd[g * C + T.cls[byte_of(xw, t)]];
+            myf[t] = static_cast<uint16_t>(g);            // forward id at column a0+t+1
+        }
+        if (w == w_start) {   // the segment of the singleton column r1
+            if (r1 == a0) list_clean(T, W, g0, bb, pseg);
+            else list_clean(T, W, myf[r1 - a0 - 1], myb[r1 - a0 - 1], pseg);
+        }
+        for (uint32_t t = 0; t < len; ++t) {
+            if (a0 + t + 1 <= r1) continue;
+            const uint32_t m = list_clean(T, W, myf[t], myb[t], cur);
+            uint64_t z[kVec];
+#pragma unroll
+            for (int k = 0; k < kVec; ++k) {
+                z[k] = 0;
+                if (k < static_cast<int>(m)) {
+                    if (pm == 1) {
+                        z[k] = x[0];
+                    } else {
+#pragma unroll
+                        for (int j = 0; j < kVec; ++j)
+                            if (j < static_cast<int>(pm) && (m == 1 || follows(folseg, W, pseg[j], cur[k]))) z[k] += x[j];
+                    }
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < kVec; ++k) x[k] = z[k], pseg[k] = cur[k];
+            pm = m;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kVec; ++k) uv[k] = x[k];
+    jb.pi[i] = pi;
+    jb.dims[2 * i] = static_cast<uint8_t>(mL);
+    jb.dims[2 * i + 1] = static_cast<uint8_t>(pm);
+    jb.tbig_idx[i] = kRank1;
+}
+
+// Count factors: factor[0] covers the text start, factor[i+1] the rank-1
+// chunk i (its pi times u_i^T . (full chunks) . v_j up to the next rank-1
+// chunk j, or the sum at the text end); entries of full chunks are 1.
+__global__ __launch_bounds__(256) void k_count_factor(Job jb) {
+    if (jb.scalars[0] == 0 || jb.flags[2] != 0) return;
+    const uint32_t c = jb.c;
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;   // t = 0: text start; t = i+1: chunk i
+    if (t > c) return;
+    uint64_t vec[kBigT];
+    uint32_t dim;
+    uint64_t f = 1;
+    if (t == 0) {
+        dim = jb.dims[0];
+        for (uint32_t k = 0; k < dim; ++k) vec[k] = 1;
+    } else {
+        const uint32_t i = t - 1;
+        if (jb.tbig_idx[i] != kRank1) {
+            jb.factor[t] = 1;
+            return;
+        }
+        f = jb.pi[i];
+        dim = jb.dims[2 * i + 1];
+        for (uint32_t k = 0; k < dim; ++k) vec[k] = jb.uv[static_cast<uint64_t>(i) * 2 * kVec + k];
+    }
+    uint32_t j = t;   // next chunk index
+    while (j < c && jb.tbig_idx[j] != kRank1) {
+        const uint64_t *M = jb.tbig + static_cast<uint64_t>(jb.tbig_idx[j]) * kBigT * kBigT;
+        const uint32_t rows = jb.dims[2 * j], cols = jb.dims[2 * j + 1];
+        uint64_t nv[kBigT];
+        for (uint32_t q = 0; q < cols; ++q) {
+            uint64_t acc = 0;
+            for (uint32_t k = 0; k < rows && k < dim; ++k) acc += vec[k] * M[k * kBigT + q];
+            nv[q] = acc;
+        }
+        for (uint32_t q = 0; q < cols; ++q) vec[q] = nv[q];
+        dim = cols;
+        ++j;
+    }
+    uint64_t d = 0;
+    if (j == c) {
+        for (uint32_t k = 0; k < dim; ++k) d += vec[k];
+    } else {
+        const uint64_t *v = jb.uv + static_cast<uint64_t>(j) * 2 * kVec + kVec;
+        for (uint32_t k = 0; k < dim; ++k) d += vec[k] * v[k];
+    }
+    jb.factor[t] = f * d;
+}
+
+// Product of the factors modulo 2^64: one block reduces, the last level
+// writes the count.
+__global__ __launch_bounds__(256) void k_prod_reduce(Job jb, const uint64_t *in, uint32_t N, uint64_t *out,
+                                                     int final_level) {
+    __shared__ uint64_t part[256];
+    const uint32_t t = threadIdx.x;
+    if (jb.scalars[0] == 0 || jb.flags[2] != 0) {
+        if (final_level && blockIdx.x == 0 && t == 0) {
+            jb.scalars[1] = 0;
+            jb.scalars[2] = jb.flags[2] ? 1ull : 0ull;
+        }
+        return;
+    }
+    uint64_t acc = 1;
+    for (uint32_t k = blockIdx.x * 256 + t; k < N; k += gridDim.x * 256) acc *= in[k];
+    part[t] = acc;
+    __syncthreads();
+    for (uint32_t h = 128; h; h >>= 1) {
+        if (t < h) part[t] *= part[t + h];
+        __syncthreads();
+    }
+    if (t == 0) {
+        if (final_level) {
+            jb.scalars[1] = part[0];
+            jb.scalars[2] = 0;
+        } else {
+            out[blockIdx.x] = part[0];
+        }
+    }
+}
 
 // Transfer matrix of chunk i: T[k][q] = number of paths in the clean SLPF from
 // the k-th segment of column P_i to the q-th segment of column P_{i+1}
@@ -510,14 +969,13 @@ __global__ __launch_bounds__(256) void k_build(Tabs tb, Job jb) {
 // consecutive clean columns iff sigma is a follower of rho (the label of rho
 // equals the byte read, as every segment of a clean column does).  One
 // wavefront per chunk; lane q keeps column q of the running matrix U in LDS.
-__global__ __launch_bounds__(64) void k_count_chunk(Tabs tb, Job jb) {
+__device__ inline void count_chunk_general(const Tabs &tb, const Job &jb, uint32_t i) {
     __shared__ uint64_t U[2][kBigT][kBigT];
     __shared__ uint32_t segs[2][kBigT];
     __shared__ uint64_t arcs[kBigT];
     __shared__ uint32_t nseg[2];
     __shared__ uint32_t fail;
-    const uint32_t i = blockIdx.x, q = threadIdx.x;
-    if (jb.scalars[0] == 0) return;
+    const uint32_t q = threadIdx.x;
     const uint32_t W = tb.W;
     const uint64_t lo = static_cast<uint64_t>(i) * jb.s;
     const uint64_t hi = (i + 1 == jb.c) ? jb.n : lo + jb.s;
@@ -587,95 +1045,24 @@ __global__ __launch_bounds__(64) void k_count_chunk(Tabs tb, Job jb) {
         jb.dims[2 * i] = static_cast<uint8_t>(mL);
         jb.dims[2 * i + 1] = static_cast<uint8_t>(mR);
     }
-    if (mL <= kSmallT && mR <= kSmallT) {
-        if (q == 0) jb.tbig_idx[i] = 0xffffffffu;
-        if (q < kSmallT)
-            for (uint32_t k = 0; k < kSmallT; ++k)
-                jb.tsmall[static_cast<uint64_t>(i) * kSmallT * kSmallT + k * kSmallT + q] =
-                    (k < mL && q < mR) ? U[cur][k][q] : 0ull;
-    } else {
-        __shared__ uint32_t slot;
-        if (q == 0) {
-            slot = atomicAdd(&jb.flags[1], 1u);
-            jb.tbig_idx[i] = slot;
-        }
-        __syncthreads();
-        if (slot >= jb.big_pool) {
-            if (q == 0) atomicOr(&jb.flags[2], 1u);
-            return;
-        }
-        for (uint32_t k = 0; k < kBigT; ++k)
-            jb.tbig[static_cast<uint64_t>(slot) * kBigT * kBigT + k * kBigT + q] =
-                (k < mL && q < mR) ? U[cur][k][q] : 0ull;
+    __shared__ uint32_t slot;
+    if (q == 0) slot = atomicAdd(&jb.flags[1], 1u);
+    __syncthreads();
+    if (slot >= jb.big_pool) {
+        if (q == 0) atomicOr(&jb.flags[2], 1u);
+        return;
     }
+    for (uint32_t k = 0; k < kBigT; ++k)
+        jb.tbig[static_cast<uint64_t>(slot) * kBigT * kBigT + k * kBigT + q] = (k < mL && q < mR) ? U[cur][k][q] : 0ull;
+    __syncthreads();
+    if (q == 0) jb.tbig_idx[i] = slot;
 }
 
-// Ordered product of transfer matrices.  Level 0 reads the per-chunk slots;
-// higher levels read the previous level's 64x64 outputs.  One wavefront per
-// group of `G` consecutive matrices; lane q computes column q.
-__global__ __launch_bounds__(64) void k_prod(Job jb, int level0, const uint64_t *in,
-                                             const uint8_t *in_dims, uint32_t N, uint32_t G,
-                                             uint64_t *out, uint8_t *out_dims, int final_level) {
-    __shared__ uint64_t P[kBigT][kBigT + 1];
-    __shared__ uint32_t drows, dcols;
-    const uint32_t g = blockIdx.x, q = threadIdx.x;
-    if (jb.scalars[0] == 0 || jb.flags[2] != 0) {
-        if (final_level && g == 0 && q == 0) {
-            jb.scalars[1] = 0;
-            jb.scalars[2] = jb.flags[2] ? 1ull : 0ull;
-        }
-        return;
-    }
-    auto elem = [&](uint32_t idx, uint32_t k, uint32_t col) -> uint64_t {
-        if (level0) {
-            uint32_t bi = jb.tbig_idx[idx];
-            if (bi == 0xffffffffu)
-                return (k < kSmallT && col < kSmallT)
-                           ? jb.tsmall[static_cast<uint64_t>(idx) * kSmallT * kSmallT + k * kSmallT + col]
-                           : 0ull;
-            return jb.tbig[static_cast<uint64_t>(bi) * kBigT * kBigT + k * kBigT + col];
-        }
-        return in[static_cast<uint64_t>(idx) * kBigT * kBigT + k * kBigT + col];
-    };
-    const uint32_t k0 = g * G, k1 = min(k0 + G, N);
-    if (q == 0) {
-        drows = in_dims[2 * k0];
-        dcols = in_dims[2 * k0 + 1];
-    }
-    __syncthreads();
-    for (uint32_t k = 0; k < kBigT; ++k) P[k][q] = (k < drows && q < dcols) ? elem(k0, k, q) : 0ull;
-    __syncthreads();
-    uint64_t col[kBigT];
-    for (uint32_t idx = k0 + 1; idx < k1; ++idx) {
-        const uint32_t br = in_dims[2 * idx], bc = in_dims[2 * idx + 1];
-        const uint32_t rows = drows;
-        for (uint32_t k = 0; k < kBigT; ++k) col[k] = 0;
-        if (q < bc) {
-            for (uint32_t l = 0; l < br; ++l) {
-                uint64_t e = elem(idx, l, q);
-                if (!e) continue;
-                for (uint32_t k = 0; k < rows; ++k) col[k] += P[k][l] * e;
-            }
-        }
+__global__ __launch_bounds__(64) void k_count_chunk(Tabs tb, Job jb) {
+    if (jb.scalars[0] == 0) return;
+    for (uint32_t item = blockIdx.x; item < jb.flags[3]; item += gridDim.x) {
+        count_chunk_general(tb, jb, jb.ovf[item]);
         __syncthreads();
-        for (uint32_t k = 0; k < kBigT; ++k) P[k][q] = col[k];
-        if (q == 0) dcols = bc;
-        __syncthreads();
-    }
-    if (final_level) {
-        if (q == 0) {
-            uint64_t tot = 0;
-            for (uint32_t k = 0; k < drows; ++k)
-                for (uint32_t l = 0; l < dcols; ++l) tot += P[k][l];
-            jb.scalars[1] = tot;
-            jb.scalars[2] = 0;
-        }
-        return;
-    }
-    for (uint32_t k = 0; k < kBigT; ++k) out[static_cast<uint64_t>(g) * kBigT * kBigT + k * kBigT + q] = P[k][q];
-    if (q == 0) {
-        out_dims[2 * g] = static_cast<uint8_t>(drows);
-        out_dims[2 * g + 1] = static_cast<uint8_t>(dcols);
     }
 }
 

@@ -17,8 +17,7 @@ namespace {
 using namespace slpf;
 
 constexpr size_t kLdsBudget = 96 * 1024;   // transition tables staged in LDS up to this size
-constexpr uint32_t kBigPool = 1024;         // 64x64 transfer-matrix slots (32 KiB each)
-constexpr uint32_t kProdGroup = 256;
+constexpr uint32_t kBigPool = 2048;         // 64x64 transfer-matrix slots (32 KiB each)
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -32,6 +31,7 @@ struct Workspace {
 struct slpf_parser {
     HostAutomaton A;
     int device = 0;
+    size_t lds_limit = 64 * 1024;     // dynamic LDS per workgroup on the device
     void *blob = nullptr;
     size_t blob_bytes = 0;
     Tabs tabs{};
@@ -107,6 +107,7 @@ slpf_status upload(slpf_parser *p) {
     t.fstart = A.fwd.start;
     t.rstart = A.rev.start;
     t.emax = std::max<uint32_t>(A.max_entries, 1);
+    t.wmagic = ((1ull << 32) + A.W - 1) / A.W;
     return SLPF_OK;
 }
 
@@ -117,8 +118,12 @@ void set_placement(slpf_parser *p) {
     if (!p->host_only) {
         int lim = 0;
         if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, p->device) == hipSuccess &&
-            lim > 0)
-            budget = std::min<size_t>(budget, static_cast<size_t>(lim));
+            lim > 0) {
+            p->lds_limit = static_cast<size_t>(lim);
+            budget = std::min<size_t>(budget, p->lds_limit);
+        }
+    } else {
+        p->lds_limit = 160 * 1024;
     }
     p->placement = p->lds_bytes <= budget ? 0 : 1;
 }
@@ -146,12 +151,6 @@ struct Layout {
 std::vector<uint32_t> join_levels(uint32_t c) {
     std::vector<uint32_t> lv{c};
     while (lv.back() > 64) lv.push_back((lv.back() + 63) / 64);
-    return lv;
-}
-
-std::vector<uint32_t> prod_levels(uint32_t c) {
-    std::vector<uint32_t> lv{c};
-    while (lv.back() > 1) lv.push_back((lv.back() + kProdGroup - 1) / kProdGroup);
     return lv;
 }
 
@@ -304,7 +303,6 @@ slpf_status slpf_parse(const slpf_parser *cp, const uint8_t *text, uint64_t n, c
     jb.c = c;
     const uint32_t E = tb.emax, W = tb.W;
     const std::vector<uint32_t> jl = join_levels(c);
-    const std::vector<uint32_t> pl = prod_levels(c);
 
     Layout L;
     int iR = L.add(size_t(E) * c * 2), iRh = L.add(size_t(E) * c * 2);
@@ -313,6 +311,7 @@ slpf_status slpf_parse(const slpf_parser *cp, const uint8_t *text, uint64_t n, c
     int ivf = L.add(size_t(c + 1) * 8), ivb = L.add(size_t(c + 1) * 8);
     int ifid = L.add(size_t(c) * 2), irid = L.add(size_t(c) * 2);
     int ickpt = L.add((n + 63) / 64 * 2);
+    int ibckpt = L.add((n + 63) / 64 * 2);
     int iflags = L.add(16);
     // join levels >= 1: maps [N][64], nx [N+1], vectors [N+1], both directions
     std::vector<int> jmf, jmb, jnxf, jnxb, jvf, jvb;
@@ -324,17 +323,17 @@ slpf_status slpf_parse(const slpf_parser *cp, const uint8_t *text, uint64_t n, c
         jvf.push_back(L.add(size_t(jl[l] + 1) * 8));
         jvb.push_back(L.add(size_t(jl[l] + 1) * 8));
     }
-    int idims = -1, itsmall = -1, itidx = -1, itbig = -1;
-    std::vector<int> pout, pdims;
+    int idims = -1, iuv = -1, ipi = -1, ifac = -1, itidx = -1, itbig = -1, iovf = -1, ired = -1;
+    const uint32_t red_blocks = std::min<uint32_t>((c + 1 + 255) / 256, 1024);
     if (count) {
         idims = L.add(size_t(c) * 2);
-        itsmall = L.add(size_t(c) * kSmallT * kSmallT * 8);
+        iuv = L.add(size_t(c) * 2 * kVec * 8);
+        ipi = L.add(size_t(c) * 8);
+        ifac = L.add(size_t(c + 1) * 8);
         itidx = L.add(size_t(c) * 4);
+        iovf = L.add(size_t(c) * 4);
         itbig = L.add(size_t(kBigPool) * kBigT * kBigT * 8);
-        for (size_t l = 1; l < pl.size(); ++l) {
-            pout.push_back(L.add(size_t(pl[l]) * kBigT * kBigT * 8));
-            pdims.push_back(L.add(size_t(pl[l]) * 2));
-        }
+        ired = L.add(size_t(red_blocks) * 8);
     }
 
     uint8_t *base;
@@ -369,27 +368,42 @@ slpf_status slpf_parse(const slpf_parser *cp, const uint8_t *text, uint64_t n, c
     jb.fid = reinterpret_cast<uint16_t *>(ptr(ifid));
     jb.rid = reinterpret_cast<uint16_t *>(ptr(irid));
     jb.ckpt = reinterpret_cast<uint16_t *>(ptr(ickpt));
+    jb.bckpt = reinterpret_cast<uint16_t *>(ptr(ibckpt));
     jb.flags = reinterpret_cast<uint32_t *>(ptr(iflags));
     jb.trace = nullptr;
     if (opts && opts->trace_dev && opts->trace_bytes >= 2ull * (c + 1) * W * 8) jb.trace = opts->trace_dev;
     if (count) {
         jb.dims = ptr(idims);
-        jb.tsmall = reinterpret_cast<uint64_t *>(ptr(itsmall));
+        jb.uv = reinterpret_cast<uint64_t *>(ptr(iuv));
+        jb.pi = reinterpret_cast<uint64_t *>(ptr(ipi));
+        jb.factor = reinterpret_cast<uint64_t *>(ptr(ifac));
         jb.tbig_idx = reinterpret_cast<uint32_t *>(ptr(itidx));
+        jb.ovf = reinterpret_cast<uint32_t *>(ptr(iovf));
         jb.tbig = reinterpret_cast<uint64_t *>(ptr(itbig));
         jb.big_pool = kBigPool;
     }
 
+    const bool timed = opts && opts->events && opts->num_events >= SLPF_NUM_PHASE_EVENTS;
+    if (opts && opts->events && opts->num_events && !timed) return SLPF_E_ARG;
+    if (timed)
+        for (int k = 0; k < SLPF_NUM_PHASE_EVENTS; ++k)
+            if (!opts->events[k]) return SLPF_E_ARG;
+    hipError_t ev_err = hipSuccess;
+    auto mark = [&](int k) {
+        if (timed && ev_err == hipSuccess) ev_err = hipEventRecord(static_cast<hipEvent_t>(opts->events[k]), stream);
+    };
     const bool lds = p->placement == 0 && !(flags & SLPF_PARSE_FORCE_L2);
     const size_t lds_bytes = lds ? p->lds_bytes : 0;
     const uint32_t blocks = (c + 255) / 256;
 
     hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, stream, jb);
 
+    mark(0);
     // reach
     if (lds) hipLaunchKernelGGL(k_reach<true>, dim3(blocks), dim3(256), lds_bytes, stream, tb, jb);
     else hipLaunchKernelGGL(k_reach<false>, dim3(blocks), dim3(256), 0, stream, tb, jb);
 
+    mark(1);
     // join: forward maps (Mf, nxf) and reversed backward maps (MbR, nxb)
     for (int dir = 0; dir < 2; ++dir) {
         std::vector<const uint64_t *> M{dir == 0 ? jb.Mf : jb.MbR};
@@ -414,47 +428,55 @@ slpf_status slpf_parse(const slpf_parser *cp, const uint8_t *text, uint64_t n, c
                                vec[l + 1], jl[l + 1], vec[l]);
         }
     }
+    mark(2);
     hipLaunchKernelGGL(k_starts, dim3(blocks), dim3(256), 0, stream, tb, jb);
+    mark(3);
 
-    // build & merge
-    const uint32_t wt = W <= 1 ? 1 : W <= 2 ? 2 : W <= 4 ? 4 : W <= 8 ? 8 : W <= 16 ? 16 : 32;
-#define SLPF_BUILD(WT_)                                                                                \
-    do {                                                                                               \
-        if (lds) hipLaunchKernelGGL((k_build<WT_, true>), dim3(blocks), dim3(256), lds_bytes, stream, tb, jb); \
-        else hipLaunchKernelGGL((k_build<WT_, false>), dim3(blocks), dim3(256), 0, stream, tb, jb);    \
-    } while (0)
-    switch (wt) {
-    case 1: SLPF_BUILD(1); break;
-    case 2: SLPF_BUILD(2); break;
-    case 4: SLPF_BUILD(4); break;
-    case 8: SLPF_BUILD(8); break;
-    case 16: SLPF_BUILD(16); break;
-    default: SLPF_BUILD(32); break;
-    }
-#undef SLPF_BUILD
-
+    // build & merge: transition tables and bit sets in LDS when they fit
+    const size_t tab_lds = (512 + (size_t(tb.nf) + tb.nr) * tb.C * 2 + 15) & ~size_t(15);
+    const size_t bits_lds = (size_t(tb.nf) + tb.nr) * W * 8;
+    const bool fit_tab = lds && kStageBytes + tab_lds <= p->lds_limit;
+    const bool fit_bits = fit_tab && kStageBytes + tab_lds + bits_lds <= p->lds_limit;
+    const uint32_t bblocks = (c + kBuildThreads - 1) / kBuildThreads;
+    if (fit_bits)
+        hipLaunchKernelGGL((k_build<true, true>), dim3(bblocks), dim3(kBuildThreads), kStageBytes + tab_lds + bits_lds,
+                           stream, tb, jb);
+    else if (fit_tab)
+        hipLaunchKernelGGL((k_build<true, false>), dim3(bblocks), dim3(kBuildThreads), kStageBytes + tab_lds, stream,
+                           tb, jb);
+    else
+        hipLaunchKernelGGL((k_build<false, false>), dim3(bblocks), dim3(kBuildThreads), kStageBytes, stream, tb, jb);
+    mark(4);
     // tree count
     if (count) {
-        hipLaunchKernelGGL(k_count_chunk, dim3(c), dim3(64), 0, stream, tb, jb);
-        const uint64_t *in = nullptr;
-        const uint8_t *indims = jb.dims;
-        for (size_t l = 1; l < pl.size(); ++l) {
-            const bool last = (l + 1 == pl.size());
-            uint64_t *o = reinterpret_cast<uint64_t *>(ptr(pout[l - 1]));
-            uint8_t *od = ptr(pdims[l - 1]);
-            hipLaunchKernelGGL(k_prod, dim3(pl[l]), dim3(64), 0, stream, jb, l == 1 ? 1 : 0, in, indims, pl[l - 1],
-                               kProdGroup, o, od, last ? 1 : 0);
-            in = o;
-            indims = od;
+        const size_t cnt_stage = 128 * 64 * 5;
+        const uint32_t cblocks = (c + 127) / 128;
+        const bool cfit_tab = lds && cnt_stage + tab_lds <= p->lds_limit;
+        const bool cfit_bits = cfit_tab && cnt_stage + tab_lds + bits_lds <= p->lds_limit;
+        if (cfit_bits)
+            hipLaunchKernelGGL((k_count_fast<true, true>), dim3(cblocks), dim3(128), cnt_stage + tab_lds + bits_lds,
+                               stream, tb, jb);
+        else if (cfit_tab)
+            hipLaunchKernelGGL((k_count_fast<true, false>), dim3(cblocks), dim3(128), cnt_stage + tab_lds, stream,
+                               tb, jb);
+        else
+            hipLaunchKernelGGL((k_count_fast<false, false>), dim3(cblocks), dim3(128), cnt_stage, stream, tb, jb);
+        hipLaunchKernelGGL(k_count_chunk, dim3(std::min<uint32_t>(c, 1024)), dim3(64), 0, stream, tb, jb);
+        hipLaunchKernelGGL(k_count_factor, dim3((c + 1 + 255) / 256), dim3(256), 0, stream, jb);
+        uint64_t *red = reinterpret_cast<uint64_t *>(ptr(ired));
+        if (red_blocks == 1) {
+            hipLaunchKernelGGL(k_prod_reduce, dim3(1), dim3(256), 0, stream, jb, jb.factor, c + 1, red, 1);
+        } else {
+            hipLaunchKernelGGL(k_prod_reduce, dim3(red_blocks), dim3(256), 0, stream, jb, jb.factor, c + 1, red, 0);
+            hipLaunchKernelGGL(k_prod_reduce, dim3(1), dim3(256), 0, stream, jb, static_cast<const uint64_t *>(red),
+                               red_blocks, red, 1);
         }
-        if (pl.size() == 1)   // a single chunk: its matrix is the product
-            hipLaunchKernelGGL(k_prod, dim3(1), dim3(64), 0, stream, jb, 1, static_cast<const uint64_t *>(nullptr),
-                               indims, 1u, kProdGroup, static_cast<uint64_t *>(nullptr),
-                               static_cast<uint8_t *>(nullptr), 1);
     } else {
         hipLaunchKernelGGL(k_set_scalars, dim3(1), dim3(1), 0, stream, jb, 0ull, 2ull);
     }
     hipLaunchKernelGGL(k_finish, dim3(1), dim3(1), 0, stream, jb);
+    mark(5);
+    if (ev_err != hipSuccess) return SLPF_E_ARG;
     return hip_ok(hipGetLastError());
 }
 

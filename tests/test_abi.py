@@ -105,7 +105,7 @@ def test_parse_with_host_only_parser_is_an_argument_error():
     p = S.Parser("(ab|a)*", host_only=True)
     L = S.lib()
     f = S.Forest(1, 1 << 20, 1)
-    o = S.ParseOpts(ctypes.sizeof(S.ParseOpts), 0, 0, 0, None, 0)
+    o = S.ParseOpts(ctypes.sizeof(S.ParseOpts), 0, 0, 0, None, 0, None, 0, 0)
     assert L.slpf_parse(p.handle, None, 0, ctypes.byref(o), ctypes.byref(f), None) == S.E_ARG
 
 

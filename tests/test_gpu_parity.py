@@ -151,3 +151,25 @@ def test_argument_errors():
     with pytest.raises(S.SlpfError) as e:       # misaligned text
         p.parse_into(big[1:], 40, cols, sc)
     assert e.value.status == S.E_ARG
+
+
+def test_tree_count_paths():
+    """Tree counts through every count path: rank-1 chunks (a singleton clean
+    column inside), chunks with no singleton column (e.g. (a|b|ab)+ on abab...),
+    columns above 16 segments, and the mixtures at chunk edges."""
+    cases = [
+        ("(a|b|ab)+", b"ab" * 1500, (64, 128, 192, 4096)),           # no singleton column at all
+        ("(a|b|ab)+", b"ab" * 31 + b"a", (64,)),                      # 2^31 trees
+        ("(a|b|ab)+", (b"ab" * 40 + b"b") * 30, (64, 256)),
+        ("(a|ab|b)*(c|bc)+(a|b)*", None, (64, 512, 8192)),
+    ]
+    tree3 = regen.random_re(3)
+    cases.append((regen.to_re(tree3), textgen.sample_text(tree3, 3, 60000).tobytes(), (64, 1024, 4160)))
+    motif = regen.motif_re()
+    cases.append((regen.to_re(motif), textgen.sample_text(motif, 1, 40000).tobytes(), (64, 320, 4096)))
+    for pat, text, ks in cases:
+        if text is None:
+            text = textgen.sample_text(regen.plain_small_re(), 9, 20000).tobytes()
+        o, p = Oracle(pat), S.Parser(pat)
+        for k in ks:
+            check(pat, text, chunk_bytes=k, o=o, p=p)
