@@ -62,6 +62,7 @@ struct Tabs {
     uint32_t nf, nr;            // table sizes including id 0
     uint32_t fstart, rstart;    // ids of I and F
     uint32_t emax;
+    uint32_t nseg;
     uint64_t wmagic;            // ceil(2^32 / W): e / W == (e * wmagic) >> 32 for e < 2^16
 };
 
@@ -699,188 +700,216 @@ __device__ inline bool follows(const uint64_t *folseg, uint32_t W, uint32_t rho,
     return (folseg[static_cast<uint64_t>(rho) * W + (sigma >> 6)] >> (sigma & 63)) & 1ull;
 }
 
+// Wavefront-uniform maximum and minimum.
+__device__ inline uint32_t wave_max_small(uint32_t v) {   // v <= 31
+    uint32_t r = 0;
+#pragma unroll
+    for (int bit = 4; bit >= 0; --bit) {
+        const uint32_t cand = r | (1u << bit);
+        if (__any(v >= cand)) r = cand;
+    }
+    return r;
+}
+__device__ inline uint32_t wave_min(uint32_t v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = min(v, static_cast<uint32_t>(__shfl_xor(static_cast<int>(v), off)));
+    return v;
+}
+
+constexpr int kCountThreads = 256;
+
 // Fast tree count.  Paths through a singleton clean column all pass through
-// its one segment, so a chunk with a singleton column r1 has the rank-1
-// transfer matrix T = v * pi * u^T:
-//   u[q]  paths from the segment of r1 to the q-th segment of the right edge
-//         column (vector DP forwards from r1, r1 the rightmost singleton);
+// its one segment, so a chunk whose columns P_i .. P_{i+1}-1 include a
+// singleton column has the rank-1 transfer matrix T = v * pi * u^T from
+// column P_i to column P_{i+1}:
+//   v[k]  paths from the k-th segment of column P_i to the leftmost singleton;
 //   pi    product of the path counts between consecutive singleton columns
-//         (vector DP backwards from r1, collapsing at every singleton);
-//   v[k]  paths from the k-th segment of the left edge column to the leftmost
-//         singleton.
-// Columns are recomputed from the build's window checkpoints.  Chunks with no
-// singleton column or a column of more than kVec segments go to the general
-// kernel.
-template <bool TAB_LDS, bool BITS_LDS>
-__global__ __launch_bounds__(128) void k_count_fast(Tabs tb, Job jb) {
+//         (a backward vector DP that collapses at every singleton);
+//   u[q]  paths from the rightmost singleton r1 to the q-th segment of
+//         column P_{i+1} (a forward vector DP from r1).
+// Columns are recomputed from the build's window checkpoints, the window's
+// ids held in registers and indexed by the wavefront-uniform loop counter.
+// Loop bounds of the vector steps are wavefront maxima, so a lane with an
+// ambiguous column costs only its own column sizes.  Chunks with no singleton
+// or with a column above kVec segments go to the general kernel.
+template <bool TAB_LDS, bool BITS_LDS, bool FOL_LDS>
+__global__ __launch_bounds__(kCountThreads) void k_count_fast(Tabs tb, Job jb) {
     extern __shared__ __align__(16) uint8_t smem[];
     if (jb.scalars[0] == 0) return;    // rejected text: no tree
-    constexpr uint32_t kLanes = 128;
-    uint16_t *fws = reinterpret_cast<uint16_t *>(smem);        // [128][64] forward ids
-    uint16_t *bws = fws + kLanes * 64;                         // [128][64] backward ids
-    uint8_t *xbs = reinterpret_cast<uint8_t *>(bws + kLanes * 64);   // [128][64] bytes
-    const BuildTabs<TAB_LDS, BITS_LDS> T = stage_build<TAB_LDS, BITS_LDS>(tb, smem, kLanes * 64 * 5);
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= jb.c) return;
     const uint32_t C = tb.C, W = tb.W;
-    const uint64_t *folseg = tb.folseg;
-    const uint64_t lo = static_cast<uint64_t>(i) * jb.s;
-    const uint64_t hi = (i + 1 == jb.c) ? jb.n : lo + jb.s;
-    const uint32_t nwin = static_cast<uint32_t>((hi - lo + 63) / 64);
-    uint16_t *myf = fws + threadIdx.x * 64;
-    uint16_t *myb = bws + threadIdx.x * 64;
-    uint8_t *myx = xbs + threadIdx.x * 64;
-    uint32_t xw[16];
-
-    uint64_t y[kVec];
+    const uint32_t fol_bytes = FOL_LDS ? ((tb.nseg * W * 8 + 15) & ~15u) : 0;
+    if constexpr (FOL_LDS) {
+        uint64_t *fl = reinterpret_cast<uint64_t *>(smem);
+        for (uint32_t k = threadIdx.x; k < tb.nseg * W; k += blockDim.x) fl[k] = tb.folseg[k];
+    }
+    const BuildTabs<TAB_LDS, BITS_LDS> T = stage_build<TAB_LDS, BITS_LDS>(tb, smem, fol_bytes);
+    const uint64_t *fol = FOL_LDS ? reinterpret_cast<const uint64_t *>(smem) : tb.folseg;
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t wave_first = blockIdx.x * blockDim.x + (threadIdx.x & ~63u);
+    if (wave_first >= jb.c) return;
+    const bool act = i < jb.c;
+    const uint64_t s = jb.s;
+    uint64_t lo = 0, hi = 0;
+    uint32_t nwin = 0;
+    if (act) {
+        lo = static_cast<uint64_t>(i) * s;
+        hi = (i + 1 == jb.c) ? jb.n : lo + s;
+        nwin = static_cast<uint32_t>((hi - lo + 63) / 64);
+    }
+    const uint32_t nwin_wave = (wave_first + 1 < jb.c) ? static_cast<uint32_t>(s / 64)
+                                                       : static_cast<uint32_t>((jb.n - static_cast<uint64_t>(jb.c - 1) * s + 63) / 64);
+    uint32_t xw[16], cw[16], fwv[64];
+    uint64_t y[kVec], z[kVec];
     uint32_t prev[kVec], cur[kVec];
-    uint32_t mp = 0;
-    uint64_t pi = 1;
-    bool found = false, over = false;
-    uint64_t r1 = 0;
 #pragma unroll
     for (int k = 0; k < kVec; ++k) y[k] = 0, prev[k] = 0, cur[k] = 0;
+    uint32_t mp = 0, seg_r1 = 0;
+    uint64_t pi = 1, r1 = 0;
+    bool found = false, over = !act;
 
-    // one backward step: y over column r+1 (prev, mp) -> column r (cur, m)
-    auto back = [&](uint32_t m) {
-        uint64_t z[kVec];
+    // one vector step between neighbouring clean columns, uniform loop bounds;
+    // fwd: x over the left column (prev) -> right column (cur); else the reverse
+    auto vstep = [&](bool need, uint32_t m, bool fwd, bool collapse) {
+        const uint32_t mw = wave_max_small(need ? m : 0), mpw = wave_max_small(need ? mp : 0);
+#pragma unroll
+        for (int k = 0; k < kVec; ++k) z[k] = 0;
 #pragma unroll
         for (int k = 0; k < kVec; ++k) {
-            z[k] = 0;
-            if (k < static_cast<int>(m)) {
-                if (mp == 1) {
-                    z[k] = y[0];
-                } else {
+            if (k < static_cast<int>(mw)) {
 #pragma unroll
-                    for (int j = 0; j < kVec; ++j)
-                        if (j < static_cast<int>(mp) && (m == 1 || follows(folseg, W, cur[k], prev[j]))) z[k] += y[j];
+                for (int j = 0; j < kVec; ++j) {
+                    if (j < static_cast<int>(mpw)) {
+                        if (need && k < static_cast<int>(m) && j < static_cast<int>(mp)) {
+                            const bool arc = (mp == 1) || (m == 1) ||
+                                             (fwd ? follows(fol, W, prev[j], cur[k]) : follows(fol, W, cur[k], prev[j]));
+                            if (arc) z[k] += y[j];
+                        }
+                    }
                 }
             }
         }
-        if (m == 1) {          // singleton: collapse into pi, restart from 1
-            pi *= z[0];
-            z[0] = 1;
-        }
+        if (need) {
+            if (collapse && m == 1) {
+                pi *= z[0];
+                z[0] = 1;
+            }
 #pragma unroll
-        for (int k = 0; k < kVec; ++k) y[k] = z[k], prev[k] = cur[k];
-        mp = m;
+            for (int k = 0; k < kVec; ++k) y[k] = z[k], prev[k] = cur[k];
+            mp = m;
+        }
     };
 
-    uint32_t b = 0;
-    for (int w = static_cast<int>(nwin) - 1; w >= 0 && !over; --w) {
-        const uint64_t a0 = lo + 64ull * w;
-        const uint32_t len = static_cast<uint32_t>(hi - a0 < 64 ? hi - a0 : 64);
-        load_window(jb.text, a0, len, xw);
-        uint32_t g = jb.ckpt[a0 >> 6];
+    // backward over the chunk's columns hi-1 .. lo
+    for (int w = static_cast<int>(nwin_wave) - 1; w >= 0; --w) {
+        const bool on = !over && w < static_cast<int>(nwin);
+        uint64_t a0 = 0;
+        uint32_t len = 0, b = 0;
+        if (on) {
+            a0 = lo + 64ull * w;
+            len = static_cast<uint32_t>(hi - a0 < 64 ? hi - a0 : 64);
+            load_window(jb.text, a0, len, xw);
+            window_classes(T, xw, cw);
+            uint32_t g = jb.ckpt[a0 >> 6];
 #pragma unroll
-        for (int t = 0; t < 64; ++t) {
-            const uint32_t x = byte_of(xw, t);
-            if (t < static_cast<int>(len)) g = T.fd[g * C + T.cls[x]];
-            myf[t] = static_cast<uint16_t>(g);
-            myx[t] = static_cast<uint8_t>(x);
+            for (int t = 0; t < 64; ++t) {
+                fwv[t] = g;
+                if (t < static_cast<int>(len)) g = T.fd[g * C + byte_of(cw, t)];
+            }
+            b = jb.bckpt[a0 >> 6];
         }
-        b = jb.bckpt[a0 >> 6];
-        for (int t = static_cast<int>(len) - 1; t >= 0; --t) {
-            const uint32_t m = list_clean(T, W, myf[t], b, cur);
-            if (m > static_cast<uint32_t>(kVec) || m == 0) {
-                over = true;
-                break;
+        for (int t = 63; t >= 0; --t) {
+            bool live = on && !over && t < static_cast<int>(len);
+            uint32_t m = 0;
+            if (live) {
+                b = T.rd[b * C + byte_of(cw, t)];
+                m = list_clean(T, W, fwv[t], b, cur);
+                if (m > static_cast<uint32_t>(kVec) || m == 0) {
+                    over = true;
+                    live = false;
+                }
             }
-            if (found) {
-                back(m);
-            } else if (m == 1) {
-                found = true;
-                r1 = a0 + t + 1;
-                y[0] = 1;
-                prev[0] = cur[0];
-                mp = 1;
+            if (live && !found) {
+                if (m == 1) {
+                    found = true;
+                    r1 = a0 + t;
+                    seg_r1 = cur[0];
+                    y[0] = 1;
+                    prev[0] = cur[0];
+                    mp = 1;
+                }
+                live = false;
             }
-            b = T.rd[b * C + T.cls[myx[t]]];
+            const bool need = live && !(m == 1 && mp == 1);
+            if (__any(need)) vstep(need, m, false, true);
+            if (live && !need) prev[0] = cur[0];      // singleton after singleton: one arc
         }
     }
-    uint32_t mL = 0;
-    if (!over) {   // the left edge column P_i
-        const uint32_t m = list_clean(T, W, jb.fid[i], b, cur);
-        if (m > static_cast<uint32_t>(kVec) || m == 0) over = true;
-        else if (found) back(m);
-        else if (m == 1) {
-            found = true;
-            r1 = lo;
-            y[0] = 1;
-            prev[0] = cur[0];
-            mp = 1;
-        } else over = true;          // no singleton column in the chunk
-        mL = m;
+    if (act && !over && !found) over = true;          // no singleton column in the chunk
+    const uint32_t mL = mp;
+    if (act && !over) {
+        uint64_t *uv = jb.uv + static_cast<uint64_t>(i) * 2 * kVec;
+#pragma unroll
+        for (int k = 0; k < kVec; ++k) uv[kVec + k] = y[k];
     }
-    if (over) {
+
+    // forward from r1 to column hi = P_{i+1}
+#pragma unroll
+    for (int k = 0; k < kVec; ++k) y[k] = 0, prev[k] = 0;
+    y[0] = 1;
+    prev[0] = seg_r1;
+    mp = 1;
+    const bool fw_on = act && !over;
+    const uint32_t w_first = wave_min(fw_on ? static_cast<uint32_t>((r1 - lo) / 64) : 0xffffffffu);
+    uint32_t bwv[64];
+    for (uint32_t w = w_first; w < nwin_wave; ++w) {
+        const bool on = fw_on && w < nwin;
+        uint64_t a0 = 0;
+        uint32_t len = 0, f_end = 0, b_end = 0;
+        if (on) {
+            a0 = lo + 64ull * w;
+            len = static_cast<uint32_t>(hi - a0 < 64 ? hi - a0 : 64);
+            load_window(jb.text, a0, len, xw);
+            window_classes(T, xw, cw);
+            uint32_t g = jb.ckpt[a0 >> 6];
+#pragma unroll
+            for (int t = 0; t < 64; ++t) {
+                fwv[t] = g;
+                if (t < static_cast<int>(len)) g = T.fd[g * C + byte_of(cw, t)];
+            }
+            f_end = g;
+            b_end = jb.bckpt[a0 >> 6];
+            uint32_t bb = b_end;
+#pragma unroll
+            for (int t = 63; t >= 0; --t) {
+                if (t < static_cast<int>(len)) bb = T.rd[bb * C + byte_of(cw, t)];
+                bwv[t] = bb;
+            }
+        }
+        for (int t = 1; t <= 64; ++t) {     // column a0 + t
+            const uint64_t col = a0 + t;
+            const bool live = on && t <= static_cast<int>(len) && col > r1;
+            uint32_t m = 0;
+            if (live) {
+                const uint32_t fi = t < 64 && t < static_cast<int>(len) ? fwv[t & 63] : f_end;
+                const uint32_t bi = t < 64 && t < static_cast<int>(len) ? bwv[t & 63] : b_end;
+                m = list_clean(T, W, fi, bi, cur);
+            }
+            const bool need = live;
+            if (__any(need)) vstep(need, m, true, false);
+        }
+    }
+    if (act && over) {
         jb.tbig_idx[i] = kOverflow;
         jb.ovf[atomicAdd(&jb.flags[3], 1u)] = i;
         return;
     }
-    // pi counted the singleton at the left edge collapse: if the left edge
-    // column is a singleton its path count went into pi and v = [1]
+    if (!act) return;
     uint64_t *uv = jb.uv + static_cast<uint64_t>(i) * 2 * kVec;
 #pragma unroll
-    for (int k = 0; k < kVec; ++k) uv[kVec + k] = y[k];
-
-    // forward from r1 to the right edge: x[k] = paths from r1's segment to
-    // the k-th segment of the current column
-    uint64_t x[kVec];
-    uint32_t pseg[kVec];
-#pragma unroll
-    for (int k = 0; k < kVec; ++k) x[k] = 0, pseg[k] = 0;
-    x[0] = 1;
-    uint32_t pm = 1;
-    const uint32_t w_start = static_cast<uint32_t>(r1 > lo ? (r1 - 1 - lo) / 64 : 0);
-    for (uint32_t w = w_start; w < nwin; ++w) {
-        const uint64_t a0 = lo + 64ull * w;
-        const uint32_t len = static_cast<uint32_t>(hi - a0 < 64 ? hi - a0 : 64);
-        load_window(jb.text, a0, len, xw);
-        const uint32_t g0 = jb.ckpt[a0 >> 6];
-        uint32_t g = g0, bb = jb.bckpt[a0 >> 6];
-#pragma unroll
-        for (int t = 63; t >= 0; --t) {
-            if (t < static_cast<int>(len)) {
-                myb[t] = static_cast<uint16_t>(bb);      // backward id at column a0+t+1
-                bb = T.rd[bb * C + T.cls[byte_of(xw, t)]];
-            }
-        }
-#pragma unroll
-        for (int t = 0; t < 64; ++t) {
-            if (t < static_cast<int>(len)) g = T.fd[g * C + T.cls[byte_of(xw, t)]];
-            myf[t] = static_cast<uint16_t>(g);            // forward id at column a0+t+1
-        }
-        if (w == w_start) {   // the segment of the singleton column r1
-            if (r1 == a0) list_clean(T, W, g0, bb, pseg);
-            else list_clean(T, W, myf[r1 - a0 - 1], myb[r1 - a0 - 1], pseg);
-        }
-        for (uint32_t t = 0; t < len; ++t) {
-            if (a0 + t + 1 <= r1) continue;
-            const uint32_t m = list_clean(T, W, myf[t], myb[t], cur);
-            uint64_t z[kVec];
-#pragma unroll
-            for (int k = 0; k < kVec; ++k) {
-                z[k] = 0;
-                if (k < static_cast<int>(m)) {
-                    if (pm == 1) {
-                        z[k] = x[0];
-                    } else {
-#pragma unroll
-                        for (int j = 0; j < kVec; ++j)
-                            if (j < static_cast<int>(pm) && (m == 1 || follows(folseg, W, pseg[j], cur[k]))) z[k] += x[j];
-                    }
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < kVec; ++k) x[k] = z[k], pseg[k] = cur[k];
-            pm = m;
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < kVec; ++k) uv[k] = x[k];
+    for (int k = 0; k < kVec; ++k) uv[k] = y[k];
     jb.pi[i] = pi;
     jb.dims[2 * i] = static_cast<uint8_t>(mL);
-    jb.dims[2 * i + 1] = static_cast<uint8_t>(pm);
+    jb.dims[2 * i + 1] = static_cast<uint8_t>(mp);
     jb.tbig_idx[i] = kRank1;
 }
 

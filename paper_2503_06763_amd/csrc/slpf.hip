@@ -108,6 +108,7 @@ slpf_status upload(slpf_parser *p) {
     t.rstart = A.rev.start;
     t.emax = std::max<uint32_t>(A.max_entries, 1);
     t.wmagic = ((1ull << 32) + A.W - 1) / A.W;
+    t.nseg = A.nseg;
     return SLPF_OK;
 }
 
@@ -128,12 +129,16 @@ void set_placement(slpf_parser *p) {
     p->placement = p->lds_bytes <= budget ? 0 : 1;
 }
 
+uint32_t A_nseg(const slpf_parser *p) { return p->A.nseg; }
+
 uint64_t chunk_bytes_for(uint64_t n, const slpf_parse_opts *o) {
     if (o && o->chunk_bytes) return o->chunk_bytes;
-    // aim at ~64K lane chunks (one per lane of ~4 waves on each of 256 CUs)
-    uint64_t s = (n + 65535) / 65536;
+    // 1 KiB lane chunks for large texts (a chunk-size sweep on MI355X: reach
+    // latency falls with more lanes while build & merge stays flat), down to
+    // 256 bytes so that small texts still fill several wavefronts
+    uint64_t s = (n + 262143) / 262144;
     s = (s + 63) / 64 * 64;
-    return std::min<uint64_t>(std::max<uint64_t>(s, 256), 1u << 20);
+    return std::min<uint64_t>(std::max<uint64_t>(s, 256), 1024);
 }
 
 struct Layout {
@@ -449,18 +454,19 @@ slpf_status slpf_parse(const slpf_parser *cp, const uint8_t *text, uint64_t n, c
     mark(4);
     // tree count
     if (count) {
-        const size_t cnt_stage = 128 * 64 * 5;
-        const uint32_t cblocks = (c + 127) / 128;
-        const bool cfit_tab = lds && cnt_stage + tab_lds <= p->lds_limit;
-        const bool cfit_bits = cfit_tab && cnt_stage + tab_lds + bits_lds <= p->lds_limit;
+        const size_t fol_lds = (size_t(A_nseg(p)) * W * 8 + 15) & ~size_t(15);
+        const uint32_t cblocks = (c + kCountThreads - 1) / kCountThreads;
+        const bool cfit_tab = lds && fol_lds + tab_lds <= p->lds_limit;
+        const bool cfit_bits = cfit_tab && fol_lds + tab_lds + bits_lds <= p->lds_limit;
         if (cfit_bits)
-            hipLaunchKernelGGL((k_count_fast<true, true>), dim3(cblocks), dim3(128), cnt_stage + tab_lds + bits_lds,
-                               stream, tb, jb);
+            hipLaunchKernelGGL((k_count_fast<true, true, true>), dim3(cblocks), dim3(kCountThreads),
+                               fol_lds + tab_lds + bits_lds, stream, tb, jb);
         else if (cfit_tab)
-            hipLaunchKernelGGL((k_count_fast<true, false>), dim3(cblocks), dim3(128), cnt_stage + tab_lds, stream,
-                               tb, jb);
+            hipLaunchKernelGGL((k_count_fast<true, false, true>), dim3(cblocks), dim3(kCountThreads),
+                               fol_lds + tab_lds, stream, tb, jb);
         else
-            hipLaunchKernelGGL((k_count_fast<false, false>), dim3(cblocks), dim3(128), cnt_stage, stream, tb, jb);
+            hipLaunchKernelGGL((k_count_fast<false, false, false>), dim3(cblocks), dim3(kCountThreads), 0, stream,
+                               tb, jb);
         hipLaunchKernelGGL(k_count_chunk, dim3(std::min<uint32_t>(c, 1024)), dim3(64), 0, stream, tb, jb);
         hipLaunchKernelGGL(k_count_factor, dim3((c + 1 + 255) / 256), dim3(256), 0, stream, jb);
         uint64_t *red = reinterpret_cast<uint64_t *>(ptr(ired));
