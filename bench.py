@@ -108,6 +108,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=32 << 20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-companion", action="store_true")
+    ap.add_argument("--copy-calib", type=int, default=0,
+                    help="after timing, copy this many bytes device-to-device (scale reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build runs on a single MI355X and has no multi-GPU path "
@@ -156,6 +158,13 @@ def main():
     }
     del _
     torch.cuda.empty_cache()
+    if args.copy_calib:
+        a = torch.empty(args.copy_calib, dtype=torch.uint8, device="cuda:0")
+        bb = torch.empty_like(a)
+        bb.copy_(a)
+        torch.cuda.synchronize()
+        del a, bb
+        torch.cuda.empty_cache()
     if not args.no_companion:
         pat2, clean = make_text(args.bytes, corrupt=False)
         ms2, phase2, scal2, _c = run_gpu(parser, clean, args.steps, args.warmup, args.chunk_bytes)

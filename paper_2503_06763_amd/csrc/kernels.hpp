@@ -95,6 +95,10 @@ struct Job {
 };
 
 constexpr int kDedupEvery = 32;
+
+// Window checkpoints are stored window-major (w * c + i), so the lanes of a
+// wavefront write 64 consecutive entries.
+__device__ inline uint64_t ck(const Job &jb, uint32_t i, uint32_t w) { return static_cast<uint64_t>(w) * jb.c + i; }
 constexpr int kGroup = 8;
 constexpr int kBigT = 64;
 constexpr int kVec = 16;                      // clean-column segments handled by the fast count
@@ -583,7 +587,7 @@ __global__ __launch_bounds__(kBuildThreads) void k_build(Tabs tb, Job jb) {
     for (uint32_t w = 0; w < nwin; ++w) {
         const uint64_t a0 = lo + 64ull * w;
         const uint32_t len = static_cast<uint32_t>(hi - a0 < 64 ? hi - a0 : 64);
-        jb.ckpt[a0 >> 6] = static_cast<uint16_t>(f);
+        jb.ckpt[ck(jb, i, w)] = static_cast<uint16_t>(f);
         load_window(jb.text, a0, len, xw);
         window_classes(T, xw, cw);
 #pragma unroll
@@ -607,7 +611,7 @@ __global__ __launch_bounds__(kBuildThreads) void k_build(Tabs tb, Job jb) {
         lenA = static_cast<uint32_t>(hi - a0A);
         load_window(jb.text, a0A, lenA, xw);
         window_classes(T, xw, cwA);
-        uint32_t g = jb.ckpt[a0A >> 6];
+        uint32_t g = jb.ckpt[ck(jb, i, nwin - 1)];
 #pragma unroll
         for (int t = 0; t < 64; ++t) {
             fwA[t] = g;
@@ -623,9 +627,9 @@ __global__ __launch_bounds__(kBuildThreads) void k_build(Tabs tb, Job jb) {
         if (nxt) {
             load_window(jb.text, lo + 64ull * (w - 1), 64, xw);
             window_classes(T, xw, cwB);
-            g = jb.ckpt[(lo >> 6) + w - 1];
+            g = jb.ckpt[ck(jb, i, w - 1)];
         }
-        if (on) jb.bckpt[a0A >> 6] = static_cast<uint16_t>(b);
+        if (on) jb.bckpt[ck(jb, i, w)] = static_cast<uint16_t>(b);
         const uint32_t len_now = on ? lenA : 0;
 #pragma unroll
         for (int h = 1; h >= 0; --h) {
@@ -809,13 +813,13 @@ __global__ __launch_bounds__(kCountThreads) void k_count_fast(Tabs tb, Job jb) {
             len = static_cast<uint32_t>(hi - a0 < 64 ? hi - a0 : 64);
             load_window(jb.text, a0, len, xw);
             window_classes(T, xw, cw);
-            uint32_t g = jb.ckpt[a0 >> 6];
+            uint32_t g = jb.ckpt[ck(jb, i, w)];
 #pragma unroll
             for (int t = 0; t < 64; ++t) {
                 fwv[t] = g;
                 if (t < static_cast<int>(len)) g = T.fd[g * C + byte_of(cw, t)];
             }
-            b = jb.bckpt[a0 >> 6];
+            b = jb.bckpt[ck(jb, i, w)];
         }
         for (int t = 63; t >= 0; --t) {
             bool live = on && !over && t < static_cast<int>(len);
@@ -870,14 +874,14 @@ __global__ __launch_bounds__(kCountThreads) void k_count_fast(Tabs tb, Job jb) {
             len = static_cast<uint32_t>(hi - a0 < 64 ? hi - a0 : 64);
             load_window(jb.text, a0, len, xw);
             window_classes(T, xw, cw);
-            uint32_t g = jb.ckpt[a0 >> 6];
+            uint32_t g = jb.ckpt[ck(jb, i, w)];
 #pragma unroll
             for (int t = 0; t < 64; ++t) {
                 fwv[t] = g;
                 if (t < static_cast<int>(len)) g = T.fd[g * C + byte_of(cw, t)];
             }
             f_end = g;
-            b_end = jb.bckpt[a0 >> 6];
+            b_end = jb.bckpt[ck(jb, i, w)];
             uint32_t bb = b_end;
 #pragma unroll
             for (int t = 63; t >= 0; --t) {

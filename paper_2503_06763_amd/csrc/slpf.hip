@@ -315,8 +315,9 @@ slpf_status slpf_parse(const slpf_parser *cp, const uint8_t *text, uint64_t n, c
     int inxf = L.add(c + 1), inxb = L.add(c + 1);
     int ivf = L.add(size_t(c + 1) * 8), ivb = L.add(size_t(c + 1) * 8);
     int ifid = L.add(size_t(c) * 2), irid = L.add(size_t(c) * 2);
-    int ickpt = L.add((n + 63) / 64 * 2);
-    int ibckpt = L.add((n + 63) / 64 * 2);
+    const size_t nck = size_t(c) * ((s + 63) / 64);   // window-major checkpoints
+    int ickpt = L.add(nck * 2);
+    int ibckpt = L.add(nck * 2);
     int iflags = L.add(16);
     // join levels >= 1: maps [N][64], nx [N+1], vectors [N+1], both directions
     std::vector<int> jmf, jmb, jnxf, jnxb, jvf, jvb;
