@@ -1,0 +1,55 @@
+"""Parity at the benchmark's full size and launch configuration.
+
+The single-RE large-text workload (random RE seed 23, 256 MiB text, with and
+without the 5 % corruption blocks) is parsed by the HIP path with the
+benchmark's automatic chunking.  The oracle's DFA-lookup serial parser runs
+over the whole text and returns sampled column windows (text start and end,
+lane-chunk edges, random interior positions), the accept flag and the tree
+count, which must equal the GPU's bit for bit.
+"""
+import numpy as np
+import pytest
+
+from gen import regen, textgen
+from oracle.oracle import Oracle
+
+S = pytest.importorskip("paper_2503_06763_amd")
+pytestmark = pytest.mark.gpu
+
+N = 1 << 28
+WIN = 96
+
+
+@pytest.fixture(scope="module")
+def workload():
+    tree = regen.random_re(23)
+    pat = regen.to_re(tree)
+    clean = textgen.sample_text(tree, 23, N)
+    bad = textgen.corrupt(clean, 24, frac=0.05, block=(64, 4096))
+    return pat, clean, bad
+
+
+@pytest.mark.parametrize("which", ["corrupted", "clean"])
+def test_full_size_sampled_windows(workload, which):
+    import torch
+    pat, clean, bad = workload
+    text = bad if which == "corrupted" else clean
+    n = text.size
+    p = S.Parser(pat)
+    t = torch.from_numpy(text).to("cuda:0")
+    cols, sc = p.parse(t)
+    torch.cuda.synchronize()
+    s = 1024
+    rng = np.random.default_rng(5)
+    starts = sorted({0, n + 1 - WIN, s - WIN // 2, 7 * s - 3, (n // s // 2) * s - 1,
+                     *[int(x) for x in rng.integers(0, n + 1 - WIN, size=6)]})
+    o = Oracle(pat)
+    win, acc, cnt = o.parse_dfa(text, starts, WIN)
+    sc = sc.cpu().numpy().view(np.uint64)
+    assert bool(sc[0]) == acc == (which == "clean")
+    assert int(sc[2]) == 0 and int(sc[1]) == cnt
+    for k, st in enumerate(starts):
+        g = cols[st:st + WIN].cpu().numpy().view(np.uint64)
+        assert np.array_equal(g, win[k]), "window at column %d" % st
+    del cols
+    torch.cuda.empty_cache()
