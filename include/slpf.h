@@ -169,8 +169,12 @@ typedef struct {
  * scalars_dev[1] = number of syntax trees modulo 2^64 (the number of
  *                  accepting NFA runs, one per LST, Sect. 2.3.4);
  * scalars_dev[2] = 0 if scalars_dev[1] is valid, 1 if the count was not
- *                  computed because a clean column held more than 64
- *                  segments, 2 if not requested (SLPF_PARSE_NO_COUNT).
+ *                  computed because the job's 2048 transfer-matrix slots
+ *                  ran out (clean columns never exceed 64 segments, the
+ *                  entry-list limit of slpf_compile), 2 if not requested (SLPF_PARSE_NO_COUNT), 3 on an
+ *                  internal error (a join set missing from the tables).
+ * columns_dev must be 8-byte aligned; with 128-byte alignment every store
+ * of the build covers whole cache lines.
  */
 typedef struct {
     uint64_t *columns_dev;     /* device, capacity_bytes >= slpf_forest_bytes(p, n) */
@@ -201,6 +205,32 @@ typedef struct {
  */
 slpf_status slpf_parse(const slpf_parser *p, const uint8_t *text_dev, uint64_t n,
                        const slpf_parse_opts *opts, const slpf_forest *forest, void *hip_stream);
+
+/* One text of a batch: its device bytes and its output buffers (as for
+ * slpf_parse; each text needs its own columns and scalars). */
+typedef struct {
+    const uint8_t *text_dev;
+    uint64_t n;
+    slpf_forest out;
+} slpf_text;
+
+/*
+ * Parse `count` texts with one parser in one job (the batched form of
+ * slpf_parse).  The lane chunks of all texts form one index space, so one
+ * launch of each phase covers every text and thousands of small texts fill
+ * the GPU; the join is a scan segmented at text boundaries.  Results are
+ * identical to parsing each text alone, with one exception: the tree
+ * count's 2048 transfer-matrix slots (used by lane chunks whose columns
+ * all hold several segments, or more than 16) are shared by the job, so a
+ * count can fail (status 1) in a batch and succeed alone.  Every item must satisfy the
+ * conditions of slpf_parse (alignment, capacity); the first violation is
+ * returned and nothing is launched.  opts->chunk_bytes applies to every
+ * text; the join trace is not available for batches.  The descriptors are
+ * copied from a pinned staging buffer on the stream; the host waits for the
+ * previous batch's copy on the same stream before reusing that buffer.
+ */
+slpf_status slpf_parse_batch(const slpf_parser *p, const slpf_text *items, size_t count,
+                             const slpf_parse_opts *opts, void *hip_stream);
 
 /* Number of lane chunks a parse of n bytes uses with the given options. */
 uint64_t slpf_num_chunks(const slpf_parser *p, uint64_t n, const slpf_parse_opts *opts);

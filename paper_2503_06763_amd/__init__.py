@@ -27,7 +27,8 @@ PARSE_NO_COUNT = 1
 PARSE_FORCE_L2 = 2
 
 EXPORTS = ["slpf_compile", "slpf_parser_destroy", "slpf_parser_info_get", "slpf_segment_text",
-           "slpf_table_dump", "slpf_forest_bytes", "slpf_parse", "slpf_num_chunks", "slpf_status_str"]
+           "slpf_table_dump", "slpf_forest_bytes", "slpf_parse", "slpf_parse_batch", "slpf_num_chunks",
+           "slpf_status_str"]
 
 
 class SlpfError(RuntimeError):
@@ -67,6 +68,10 @@ class Forest(ctypes.Structure):
                 ("scalars_dev", ctypes.c_void_p)]
 
 
+class Text(ctypes.Structure):
+    _fields_ = [("text_dev", ctypes.c_void_p), ("n", ctypes.c_uint64), ("out", Forest)]
+
+
 _lib = None
 
 
@@ -97,6 +102,8 @@ def lib(path: str = LIB_PATH):
     L.slpf_forest_bytes.restype = ctypes.c_uint64
     L.slpf_parse.argtypes = [vp, vp, ctypes.c_uint64, ctypes.POINTER(ParseOpts), ctypes.POINTER(Forest), vp]
     L.slpf_parse.restype = ctypes.c_int
+    L.slpf_parse_batch.argtypes = [vp, ctypes.POINTER(Text), sz, ctypes.POINTER(ParseOpts), vp]
+    L.slpf_parse_batch.restype = ctypes.c_int
     L.slpf_num_chunks.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ParseOpts)]
     L.slpf_num_chunks.restype = ctypes.c_uint64
     L.slpf_status_str.argtypes = [ctypes.c_int]
@@ -236,6 +243,57 @@ class Parser:
         flags = (0 if count else PARSE_NO_COUNT) | (PARSE_FORCE_L2 if force_l2 else 0)
         self.parse_into(text, n, cols, sc, chunk_bytes, flags, tr, stream, events)
         return (cols, sc, tr) if trace else (cols, sc)
+
+
+    def parse_batch_into(self, items, chunk_bytes: int = 0, flags: int = 0, stream=None, events=None):
+        """Raw slpf_parse_batch.  ``items``: list of (text tensor or None, n, columns tensor,
+        scalars tensor); asynchronous on ``stream``."""
+        import torch
+        if stream is None:
+            dev = next((t.device for t, _, _, _ in items if t is not None), torch.device("cuda", self.device))
+            stream = torch.cuda.current_stream(dev)
+        ev = None
+        if events is not None:
+            for e in events:
+                if not e.cuda_event:
+                    e.record(stream)
+            ev = (ctypes.c_void_p * len(events))(*[e.cuda_event for e in events])
+        o = ParseOpts(ctypes.sizeof(ParseOpts), chunk_bytes, flags, 0, None, 0,
+                      ctypes.cast(ev, ctypes.POINTER(ctypes.c_void_p)) if ev is not None else None,
+                      len(events) if events is not None else 0, 0)
+        arr = (Text * len(items))()
+        for k, (t, n, cols, sc) in enumerate(items):
+            arr[k].text_dev = t.data_ptr() if (t is not None and n) else None
+            arr[k].n = n
+            arr[k].out = Forest(cols.data_ptr(), cols.numel() * cols.element_size(), sc.data_ptr())
+        st = self._L.slpf_parse_batch(self._h, arr, len(items), ctypes.byref(o), ctypes.c_void_p(stream.cuda_stream))
+        _check(st, "slpf_parse_batch")
+
+    def parse_batch(self, texts, chunk_bytes: int = 0, count: bool = True, force_l2: bool = False,
+                    stream=None, events=None):
+        """Parse a list of uint8 device tensors in one job; returns a list of
+        (columns [n+1, W], scalars [3]) per text.  The columns of all texts are
+        views of one allocation, each starting on a 256-byte boundary."""
+        import torch
+        if not texts:
+            return []
+        dev = texts[0].device
+        W = self.W
+        offs, tot = [], 0
+        for t in texts:
+            offs.append(tot)
+            tot += ((t.numel() + 1) * W + 31) // 32 * 32
+        big = torch.empty(max(tot, 1), dtype=torch.int64, device=dev)
+        sc = torch.empty((len(texts), 3), dtype=torch.int64, device=dev)
+        out, items = [], []
+        for k, t in enumerate(texts):
+            n = t.numel()
+            cols = big[offs[k]:offs[k] + (n + 1) * W].view(n + 1, W)
+            out.append((cols, sc[k]))
+            items.append((t, n, cols, sc[k]))
+        flags = (0 if count else PARSE_NO_COUNT) | (PARSE_FORCE_L2 if force_l2 else 0)
+        self.parse_batch_into(items, chunk_bytes, flags, stream, events)
+        return out
 
 
 def status_str(st: int) -> str:

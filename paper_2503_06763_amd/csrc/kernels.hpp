@@ -67,28 +67,35 @@ struct Tabs {
 };
 
 struct Job {
-    const uint8_t *text;
-    uint64_t n;
+    // texts: a job parses one or many texts with one parser; the lane chunks of
+    // all texts form one index space, text t owning chunks tchunk0[t] ..
+    // tchunk0[t+1]-1.  With one text the descriptor is carried in d0.
+    uint32_t ntexts;
+    const uint64_t *tdesc;      // [T][4]: text ptr, n, columns ptr, scalars ptr
+    const uint32_t *tchunk0;    // [T+1]
+    uint64_t d0[4];
     uint64_t s;                 // lane chunk bytes
-    uint32_t c;                 // lane chunks
+    uint32_t c;                 // lane chunks of all texts
     uint16_t *R, *Rh;           // [emax][c] end ids of the reach runs
     uint64_t *Mf, *MbR;         // [c][emax] masks; MbR indexed by c-1-i
-    uint8_t *nxf, *nxb;         // |X_b| for b = 0..c (nxb reversed: nxb[k] = |X_{c-k}|)
-    uint64_t *vf, *vb;          // join vectors, vf[b] = J_b & X_b, vb[k] = J^_{c-k} & X_{c-k}
+    uint8_t *nxf, *nxb;         // entry-list sizes at the scan input of item k (forward: left edge of
+                                // chunk k; backward: right edge of chunk c-1-k)
+    uint8_t *rsf, *rsb;         // item k starts a text (forward: first chunk; backward: last chunk)
+    uint64_t *fin, *fout;       // forward join masks at the left / right edge of chunk i
+    uint64_t *bin, *bout;       // backward join masks (reversed item order: index c-1-i)
     uint16_t *fid, *rid;        // build start ids per chunk
     uint16_t *ckpt;             // forward id at the left edge of every 64-byte window
     uint16_t *bckpt;            // backward id at the right edge of every 64-byte window
-    uint64_t *out;              // SLPF columns
-    uint64_t *scalars;          // [0] accepted [1] count [2] count status
-    uint32_t *flags;            // [0] set not found, [1] big-slot counter, [2] count impossible,
+    uint32_t *flags;            // [0] set not found, [1] big-slot counter, [2] unused,
                                 // [3] chunks for the general count kernel
-    uint64_t *trace;            // optional J / J^ words
+    uint64_t *trace;            // optional J / J^ words (one text only)
     // tree count
     uint8_t *dims;              // [c][2]: edge column sizes
     uint64_t *uv;               // [c][2][kVec]: u (right edge) then v (left edge) of a rank-1 chunk
     uint64_t *pi;               // [c] scalar factor of a rank-1 chunk
-    uint64_t *factor;           // [c+1] per-edge factors of the count
-    uint32_t *tbig_idx;         // [c], kRank1, kOverflow or a pool slot of a full matrix
+    uint64_t *factor;           // [c + T] chunk factors, then one text-start factor per text
+    uint32_t *tbig_idx;         // [c], kRank1, a pool slot of a full matrix, or kOverflow (the
+                                // general kernel failed: a column beyond its limit, or no slot)
     uint32_t *ovf;              // chunks left to the general count kernel (count in flags[3])
     uint64_t *tbig;             // [pool][64*64]
     uint32_t big_pool;
@@ -99,6 +106,57 @@ constexpr int kDedupEvery = 32;
 // Window checkpoints are stored window-major (w * c + i), so the lanes of a
 // wavefront write 64 consecutive entries.
 __device__ inline uint64_t ck(const Job &jb, uint32_t i, uint32_t w) { return static_cast<uint64_t>(w) * jb.c + i; }
+// One text of a job and one lane chunk of it.
+struct TextRef {
+    const uint8_t *text;
+    uint64_t n;
+    uint64_t *out;
+    uint64_t *scalars;
+};
+
+__device__ inline TextRef text_ref(const Job &jb, uint32_t t) {
+    const uint64_t *d = jb.ntexts == 1 ? jb.d0 : jb.tdesc + 4ull * t;
+    return {reinterpret_cast<const uint8_t *>(d[0]), d[1], reinterpret_cast<uint64_t *>(d[2]),
+            reinterpret_cast<uint64_t *>(d[3])};
+}
+
+__device__ inline uint32_t first_chunk(const Job &jb, uint32_t t) {
+    return jb.ntexts == 1 ? (t == 0 ? 0 : jb.c) : jb.tchunk0[t];
+}
+
+// text owning chunk i: the largest t < T with tchunk0[t] <= i
+__device__ inline uint32_t text_of(const Job &jb, uint32_t i) {
+    if (jb.ntexts == 1) return 0;
+    uint32_t lo = 0, hi = jb.ntexts - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (jb.tchunk0[mid] <= i) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+struct ChunkCtx {
+    TextRef tr;
+    uint32_t t, li, ct;         // text, chunk index within the text, chunks of the text
+    uint64_t lo, hi;            // byte range within the text
+    bool first, last;
+};
+
+__device__ inline ChunkCtx chunk_ctx(const Job &jb, uint32_t i) {
+    ChunkCtx x;
+    x.t = text_of(jb, i);
+    x.tr = text_ref(jb, x.t);
+    const uint32_t c0 = first_chunk(jb, x.t);
+    x.ct = first_chunk(jb, x.t + 1) - c0;
+    x.li = i - c0;
+    x.lo = static_cast<uint64_t>(x.li) * jb.s;
+    x.first = x.li == 0;
+    x.last = x.li + 1 == x.ct;
+    x.hi = x.last ? x.tr.n : x.lo + jb.s;
+    return x;
+}
+
 constexpr int kGroup = 8;
 constexpr int kBigT = 64;
 constexpr int kVec = 16;                      // clean-column segments handled by the fast count
@@ -271,17 +329,18 @@ __global__ __launch_bounds__(256) void k_reach(Tabs tb, Job jb) {
     Lookup<LDS> lk = stage_tables<LDS>(tb, smem, true, true);
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= jb.c) return;
-    const uint64_t lo = static_cast<uint64_t>(i) * jb.s;
-    const uint64_t hi = (i + 1 == jb.c) ? jb.n : lo + jb.s;
-    const uint32_t la = boundary_list(tb, lk.cls, jb.text, jb.n, jb.s, jb.c, i);
-    const uint32_t lb = boundary_list(tb, lk.cls, jb.text, jb.n, jb.s, jb.c, i + 1);
+    const ChunkCtx cx = chunk_ctx(jb, i);
+    const uint8_t *text = cx.tr.text;
+    const uint64_t lo = cx.lo, hi = cx.hi;
+    const uint32_t la = boundary_list(tb, lk.cls, text, cx.tr.n, jb.s, cx.ct, cx.li);
+    const uint32_t lb = boundary_list(tb, lk.cls, text, cx.tr.n, jb.s, cx.ct, cx.li + 1);
     const uint32_t xa0 = tb.xoff[la], na = tb.xoff[la + 1] - xa0;
     const uint32_t xb0 = tb.xoff[lb], nb = tb.xoff[lb + 1] - xb0;
-    // entry-list sizes per edge, forward order and reversed (nxb[k] = |X_{c-k}|)
+    // scan items: forward item i maps X_i -> X_{i+1}; backward item c-1-i maps X_{i+1} -> X_i
     jb.nxf[i] = static_cast<uint8_t>(na);
+    jb.rsf[i] = cx.first ? 1 : 0;
     jb.nxb[jb.c - 1 - i] = static_cast<uint8_t>(nb);
-    if (i + 1 == jb.c) jb.nxf[jb.c] = static_cast<uint8_t>(nb);
-    if (i == 0) jb.nxb[jb.c] = static_cast<uint8_t>(na);
+    jb.rsb[jb.c - 1 - i] = cx.last ? 1 : 0;
 
     // forward runs from X_i
     for (uint32_t g0 = 0; __any(g0 < na); g0 += kGroup) {
@@ -292,7 +351,7 @@ __global__ __launch_bounds__(256) void k_reach(Tabs tb, Job jb) {
             st[k] = (g0 + k < na) ? tb.fsingle[tb.xlist[xa0 + g0 + k]] : 0;
             alias |= static_cast<uint32_t>(k) << (4 * k);
         }
-        run_group<true>(jb.text, lo, hi, lk.cls, lk.fd, tb.C, st, alias);
+        run_group<true>(text, lo, hi, lk.cls, lk.fd, tb.C, st, alias);
 #pragma unroll
         for (int k = 0; k < kGroup; ++k) {
             if (g0 + k < na) {
@@ -313,7 +372,7 @@ __global__ __launch_bounds__(256) void k_reach(Tabs tb, Job jb) {
             st[k] = (g0 + k < nb) ? tb.rsingle[tb.xlist[xb0 + g0 + k]] : 0;
             alias |= static_cast<uint32_t>(k) << (4 * k);
         }
-        run_group<false>(jb.text, lo, hi, lk.cls, lk.rd, tb.C, st, alias);
+        run_group<false>(text, lo, hi, lk.cls, lk.rd, tb.C, st, alias);
 #pragma unroll
         for (int k = 0; k < kGroup; ++k) {
             if (g0 + k < nb) {
@@ -351,68 +410,108 @@ __global__ __launch_bounds__(256) void k_reach(Tabs tb, Job jb) {
 
 // --------------------------------------------------------------------- join
 
-// Compose groups of 64 consecutive maps: out[g] = M[64g+63] o ... o M[64g].
-// One wavefront per group, lane = row (entry of the group's first list).
-__global__ __launch_bounds__(64) void k_compose(const uint64_t *M, uint32_t stride, uint32_t N,
-                                                const uint8_t *nx, uint64_t *out, uint8_t *out_nx) {
+// The join is a segmented scan over "items" (chunks, in text order for the
+// forward direction and reversed for the backward one).  Item k maps masks
+// over the entry list at its input edge to masks over the one at its output
+// edge; an item that starts a text ignores its input and starts from all of
+// its entry list (J_0 = I restricted, or J^ = F restricted).  Aggregates of 64
+// items are either a map (rows[m] = image of entry m) or a constant.
+struct ScanLevel {
+    const uint64_t *rows;       // [N][stride]
+    uint32_t stride;
+    uint32_t N;
+    const uint8_t *nx;          // [N+1] input entry-list size per item (level 0)
+    const uint8_t *rs;          // level 0: item starts a text
+    const uint8_t *isc;         // level >= 1: aggregate is constant
+    const uint64_t *cv;         // level >= 1: its constant
+    int level0;
+};
+
+__device__ inline uint64_t scan_apply(const ScanLevel &L, uint32_t k, uint64_t v) {
+    const uint64_t *rows = L.rows + static_cast<uint64_t>(k) * L.stride;
+    if (L.level0) return apply_map(rows, L.rs[k] ? low_mask(L.nx[k]) : v);
+    return L.isc[k] ? L.cv[k] : apply_map(rows, v);
+}
+
+__device__ inline bool scan_const(const ScanLevel &L, uint32_t k) { return L.level0 ? L.rs[k] != 0 : L.isc[k] != 0; }
+
+// Compose groups of 64 consecutive items; one wavefront per group, lane m
+// follows entry m of the group's input list.
+__global__ __launch_bounds__(64) void k_compose(ScanLevel L, uint64_t *out_rows, uint8_t *out_isc, uint64_t *out_cv) {
     const uint32_t g = blockIdx.x, m = threadIdx.x;
-    const uint32_t k0 = g * 64, k1 = min(k0 + 64, N);
-    const uint32_t rows = nx[k0];
+    const uint32_t k0 = g * 64, k1 = min(k0 + 64, L.N);
+    // entries beyond the input list of a level-0 group have no row
+    uint64_t v = (L.level0 && m >= L.nx[k0]) ? 0 : 1ull << m;
+    bool cst = false;
+    for (uint32_t k = k0; k < k1; ++k) {
+        cst = cst || scan_const(L, k);
+        v = scan_apply(L, k, v);
+    }
+    out_rows[static_cast<uint64_t>(g) * 64 + m] = v;
     if (m == 0) {
-        out_nx[g] = nx[k0];
-        if (k1 == N) out_nx[g + 1] = nx[N];
+        out_isc[g] = cst ? 1 : 0;
+        out_cv[g] = v;
     }
-    uint64_t v = 0;
-    if (m < rows) {
-        v = 1ull << m;
-        for (uint32_t k = k0; k < k1; ++k) v = apply_map(M + static_cast<uint64_t>(k) * stride, v);
-    }
-    out[static_cast<uint64_t>(g) * 64 + m] = v;
 }
 
-// Sequential scan over the top level: vec[0] = all entries of the first list.
-__global__ void k_scan_top(const uint64_t *M, uint32_t stride, uint32_t N, const uint8_t *nx,
-                           uint64_t *vec) {
+// Sequential scan over the top level (at most 64 items): vec[k] = mask entering item k.
+__global__ void k_scan_top(ScanLevel L, uint64_t *vec) {
     if (threadIdx.x || blockIdx.x) return;
-    uint64_t v = low_mask(nx[0]);
-    vec[0] = v;
-    for (uint32_t k = 0; k < N; ++k) {
-        v = apply_map(M + static_cast<uint64_t>(k) * stride, v);
-        vec[k + 1] = v;
+    uint64_t v = 0;
+    for (uint32_t k = 0; k < L.N; ++k) {
+        vec[k] = v;
+        v = scan_apply(L, k, v);
     }
+    vec[L.N] = v;
 }
 
-// Expand parent vectors down one level: one thread per parent group.
-__global__ __launch_bounds__(64) void k_expand(const uint64_t *M, uint32_t stride, uint32_t N,
-                                               const uint64_t *pvec, uint32_t NP, uint64_t *vec) {
+// Expand parent vectors one level down (levels >= 1): one thread per parent.
+__global__ __launch_bounds__(64) void k_expand(ScanLevel L, const uint64_t *pvec, uint32_t NP, uint64_t *vec) {
     const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= NP) return;
     uint64_t v = pvec[p];
-    const uint32_t k0 = p * 64, k1 = min(k0 + 64, N);
+    const uint32_t k0 = p * 64, k1 = min(k0 + 64, L.N);
     for (uint32_t k = k0; k < k1; ++k) {
         vec[k] = v;
-        v = apply_map(M + static_cast<uint64_t>(k) * stride, v);
+        v = scan_apply(L, k, v);
     }
-    if (k1 == N) vec[N] = v;
+}
+
+// Level 0: the masks at both edges of every item.  pvec == nullptr: the whole
+// level is scanned by one thread.
+__global__ __launch_bounds__(64) void k_expand0(ScanLevel L, const uint64_t *pvec, uint32_t NP, uint64_t *vin,
+                                                uint64_t *vout) {
+    const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= NP) return;
+    uint64_t v = pvec ? pvec[p] : 0;
+    const uint32_t k0 = pvec ? p * 64 : 0, k1 = pvec ? min(k0 + 64, L.N) : L.N;
+    for (uint32_t k = k0; k < k1; ++k) {
+        const uint64_t in = L.rs[k] ? low_mask(L.nx[k]) : v;
+        vin[k] = in;
+        v = apply_map(L.rows + static_cast<uint64_t>(k) * L.stride, in);
+        vout[k] = v;
+    }
 }
 
 // Join sets and build start ids.  Thread i handles chunk i: fid_i = id of
-// J at P_i, rid_i = id of J^ at P_{i+1}.
+// J at P_i, rid_i = id of J^ at P_{i+1}; the last chunk of a text writes its
+// accept flag.
 __global__ __launch_bounds__(256) void k_starts(Tabs tb, Job jb) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t c = jb.c, W = tb.W;
     if (i >= c) return;
+    const ChunkCtx cx = chunk_ctx(jb, i);
     uint64_t acc[kMaxWords];
-    // forward: J at P_i is the union of the ends of the runs of chunk i-1 selected by vf[i-1]
-    auto join_fwd = [&](uint32_t b) -> uint32_t {   // J at P_b, b >= 1
-        uint64_t sel = jb.vf[b - 1];
+    // J at the right edge of chunk k: union of the ends of its runs selected by fin[k]
+    auto join_fwd = [&](uint32_t k) -> uint32_t {
+        uint64_t sel = jb.fin[k];
         for (uint32_t w = 0; w < W; ++w) acc[w] = 0;
         uint32_t first = 0xffffffffu;
         bool same = true;
         while (sel) {
             int m = __builtin_ctzll(sel);
             sel &= sel - 1;
-            uint32_t id = jb.R[static_cast<uint64_t>(m) * c + (b - 1)];
+            uint32_t id = jb.R[static_cast<uint64_t>(m) * c + k];
             if (first == 0xffffffffu) first = id;
             same = same && (id == first);
             const uint64_t *bt = tb.fbits + static_cast<uint64_t>(id) * W;
@@ -422,16 +521,16 @@ __global__ __launch_bounds__(256) void k_starts(Tabs tb, Job jb) {
         if (same) return first;
         return lookup_set(tb.fhash, tb.fhmask, tb.fbits, W, acc, jb.flags);
     };
-    // backward: J^ at P_b (b <= c-1) from the runs of chunk b selected by g at P_{b+1}
-    auto join_bwd = [&](uint32_t b) -> uint32_t {
-        uint64_t sel = jb.vb[c - (b + 1)];
+    // J^ at the left edge of chunk k: union of its backward runs selected by the mask at its right edge
+    auto join_bwd = [&](uint32_t k) -> uint32_t {
+        uint64_t sel = jb.bin[c - 1 - k];      // reversed item c-1-k enters at chunk k's right edge
         for (uint32_t w = 0; w < W; ++w) acc[w] = 0;
         uint32_t first = 0xffffffffu;
         bool same = true;
         while (sel) {
             int m = __builtin_ctzll(sel);
             sel &= sel - 1;
-            uint32_t id = jb.Rh[static_cast<uint64_t>(m) * c + b];
+            uint32_t id = jb.Rh[static_cast<uint64_t>(m) * c + k];
             if (first == 0xffffffffu) first = id;
             same = same && (id == first);
             const uint64_t *bt = tb.rbits + static_cast<uint64_t>(id) * W;
@@ -441,30 +540,26 @@ __global__ __launch_bounds__(256) void k_starts(Tabs tb, Job jb) {
         if (same) return first;
         return lookup_set(tb.rhash, tb.rhmask, tb.rbits, W, acc, jb.flags);
     };
-    const uint32_t f = (i == 0) ? tb.fstart : join_fwd(i);
-    const uint32_t r = (i + 1 == c) ? tb.rstart : join_bwd(i + 1);
+    const uint32_t f = cx.first ? tb.fstart : join_fwd(i - 1);
+    const uint32_t r = cx.last ? tb.rstart : join_bwd(i + 1);
     jb.fid[i] = static_cast<uint16_t>(f);
     jb.rid[i] = static_cast<uint16_t>(r);
-    if (jb.trace) {
+    if (jb.trace) {   // one text: J and J^ at every chunk edge
         uint64_t *Jt = jb.trace, *Jh = jb.trace + static_cast<uint64_t>(c + 1) * W;
         const uint64_t *fb = tb.fbits + static_cast<uint64_t>(f) * W;
         for (uint32_t w = 0; w < W; ++w) Jt[static_cast<uint64_t>(i) * W + w] = fb[w];
         const uint64_t *rb = tb.rbits + static_cast<uint64_t>(r) * W;
         for (uint32_t w = 0; w < W; ++w) Jh[static_cast<uint64_t>(i + 1) * W + w] = rb[w];
         if (i + 1 == c) {
-            uint32_t fe = join_fwd(c);
-            const uint64_t *fe_b = tb.fbits + static_cast<uint64_t>(fe) * W;
-            for (uint32_t w = 0; w < W; ++w) Jt[static_cast<uint64_t>(c) * W + w] = fe_b[w];
+            const uint64_t *e = tb.fbits + static_cast<uint64_t>(join_fwd(c - 1)) * W;
+            for (uint32_t w = 0; w < W; ++w) Jt[static_cast<uint64_t>(c) * W + w] = e[w];
         }
         if (i == 0) {
-            uint32_t r0 = join_bwd(0);
-            const uint64_t *r0b = tb.rbits + static_cast<uint64_t>(r0) * W;
-            for (uint32_t w = 0; w < W; ++w) Jh[w] = r0b[w];
+            const uint64_t *e = tb.rbits + static_cast<uint64_t>(join_bwd(0)) * W;
+            for (uint32_t w = 0; w < W; ++w) Jh[w] = e[w];
         }
     }
-    if (i == 0) {
-        jb.scalars[0] = jb.vf[c] != 0 ? 1ull : 0ull;
-    }
+    if (cx.last) cx.tr.scalars[0] = jb.fout[i] != 0 ? 1ull : 0ull;
 }
 
 // -------------------------------------------------------------------- build
@@ -541,6 +636,20 @@ __device__ inline void window_classes(const BT &T, const uint32_t *xw, uint32_t 
     }
 }
 
+// Lane j's value of v.  The builtin returns int: each half goes through
+// uint32_t so that the low half is not sign-extended into the high one.
+__device__ inline uint64_t readlane_u64(uint64_t v, int j) {
+    const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(v)), j));
+    const uint32_t hi = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(static_cast<uint32_t>(v >> 32)), j));
+    return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
+__device__ inline uint32_t wave_max_u32(uint32_t v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = max(v, static_cast<uint32_t>(__shfl_xor(static_cast<int>(v), off)));
+    return v;
+}
+
 constexpr int kBuildThreads = 512;             // 8 wavefronts
 constexpr int kHalf = 32;                      // positions per staged half window
 constexpr int kStageRow = kHalf + 1;           // padded: lanes fall in distinct banks
@@ -569,17 +678,20 @@ __global__ __launch_bounds__(kBuildThreads) void k_build(Tabs tb, Job jb) {
     const uint32_t wave_first = blockIdx.x * blockDim.x + wv * 64;
     if (wave_first >= jb.c) return;                 // whole wavefront idle
     const bool act = i < jb.c;
-    const uint64_t s = jb.s;
+    ChunkCtx cx{};
     uint64_t lo = 0, hi = 0;
     uint32_t nwin = 0;
+    const uint8_t *text = nullptr;
+    uint64_t *out = nullptr;
     if (act) {
-        lo = static_cast<uint64_t>(i) * s;
-        hi = (i + 1 == jb.c) ? jb.n : lo + s;
+        cx = chunk_ctx(jb, i);
+        lo = cx.lo;
+        hi = cx.hi;
+        text = cx.tr.text;
+        out = cx.tr.out;
         nwin = static_cast<uint32_t>((hi - lo + 63) / 64);
     }
-    // windows of the wavefront's longest chunk (only the text's last chunk is shorter)
-    const uint32_t nwin_wave = (wave_first + 1 < jb.c) ? static_cast<uint32_t>(s / 64)
-                                                       : static_cast<uint32_t>((jb.n - static_cast<uint64_t>(jb.c - 1) * s + 63) / 64);
+    const uint32_t nwin_wave = wave_max_u32(nwin);
     uint32_t xw[16], cw[16];
 
     // forward sweep: checkpoints
@@ -588,15 +700,15 @@ __global__ __launch_bounds__(kBuildThreads) void k_build(Tabs tb, Job jb) {
         const uint64_t a0 = lo + 64ull * w;
         const uint32_t len = static_cast<uint32_t>(hi - a0 < 64 ? hi - a0 : 64);
         jb.ckpt[ck(jb, i, w)] = static_cast<uint16_t>(f);
-        load_window(jb.text, a0, len, xw);
+        load_window(text, a0, len, xw);
         window_classes(T, xw, cw);
 #pragma unroll
         for (int t = 0; t < 64; ++t)
             if (t < static_cast<int>(len)) f = T.fd[f * C + byte_of(cw, t)];
     }
-    if (i + 1 == jb.c) {   // the text-end column: J_c & F
+    if (act && cx.last) {   // the text-end column: J_c & F
         for (uint32_t w = 0; w < W; ++w)
-            jb.out[jb.n * W + w] = T.fb[f * W + w] & T.rb[tb.rstart * W + w];
+            out[cx.tr.n * W + w] = T.fb[f * W + w] & T.rb[tb.rstart * W + w];
     }
 
     // backward sweep, two windows in flight; fwA[t] = forward id at column a0+t
@@ -609,7 +721,7 @@ __global__ __launch_bounds__(kBuildThreads) void k_build(Tabs tb, Job jb) {
     if (nwin) {   // the last window of the chunk
         a0A = lo + 64ull * (nwin - 1);
         lenA = static_cast<uint32_t>(hi - a0A);
-        load_window(jb.text, a0A, lenA, xw);
+        load_window(text, a0A, lenA, xw);
         window_classes(T, xw, cwA);
         uint32_t g = jb.ckpt[ck(jb, i, nwin - 1)];
 #pragma unroll
@@ -625,7 +737,7 @@ __global__ __launch_bounds__(kBuildThreads) void k_build(Tabs tb, Job jb) {
         uint32_t cwB[16], fwB[64];
         uint32_t g = 0;
         if (nxt) {
-            load_window(jb.text, lo + 64ull * (w - 1), 64, xw);
+            load_window(text, lo + 64ull * (w - 1), 64, xw);
             window_classes(T, xw, cwB);
             g = jb.ckpt[ck(jb, i, w - 1)];
         }
@@ -650,13 +762,12 @@ __global__ __launch_bounds__(kBuildThreads) void k_build(Tabs tb, Job jb) {
             wave_sync();
             // write columns a0+32h .. of every chunk of the wavefront
             for (int j = 0; j < 64; ++j) {
-                const uint32_t lj = __builtin_amdgcn_readlane(len_now, j);
+                const uint32_t lj = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(len_now), j));
                 const uint32_t np = lj > static_cast<uint32_t>(h * kHalf)
                                         ? (lj - h * kHalf < static_cast<uint32_t>(kHalf) ? lj - h * kHalf : kHalf) : 0;
                 if (np == 0) continue;
-                const uint64_t aj = (static_cast<uint64_t>(__builtin_amdgcn_readlane(static_cast<uint32_t>(a0A >> 32), j)) << 32) |
-                                    __builtin_amdgcn_readlane(static_cast<uint32_t>(a0A), j);
-                uint64_t *region = jb.out + (aj + h * kHalf) * W;
+                uint64_t *region = reinterpret_cast<uint64_t *>(readlane_u64(reinterpret_cast<uint64_t>(out + a0A * W), j)) +
+                                   static_cast<uint64_t>(h * kHalf) * W;
                 const uint32_t *sj = wave_rows + j * kStageRow;
                 const uint32_t nwords = np * W;
                 for (uint32_t e = lane; e < nwords; e += 64) {
@@ -739,7 +850,7 @@ constexpr int kCountThreads = 256;
 template <bool TAB_LDS, bool BITS_LDS, bool FOL_LDS>
 __global__ __launch_bounds__(kCountThreads) void k_count_fast(Tabs tb, Job jb) {
     extern __shared__ __align__(16) uint8_t smem[];
-    if (jb.scalars[0] == 0) return;    // rejected text: no tree
+    if (jb.ntexts == 1 && text_ref(jb, 0).scalars[0] == 0) return;    // rejected text: no tree
     const uint32_t C = tb.C, W = tb.W;
     const uint32_t fol_bytes = FOL_LDS ? ((tb.nseg * W * 8 + 15) & ~15u) : 0;
     if constexpr (FOL_LDS) {
@@ -751,17 +862,21 @@ __global__ __launch_bounds__(kCountThreads) void k_count_fast(Tabs tb, Job jb) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t wave_first = blockIdx.x * blockDim.x + (threadIdx.x & ~63u);
     if (wave_first >= jb.c) return;
-    const bool act = i < jb.c;
-    const uint64_t s = jb.s;
+    ChunkCtx cx{};
+    bool act = i < jb.c;
+    if (act) {
+        cx = chunk_ctx(jb, i);
+        act = cx.tr.scalars[0] != 0;             // trees only in accepted texts
+    }
+    const uint8_t *text = cx.tr.text;
     uint64_t lo = 0, hi = 0;
     uint32_t nwin = 0;
     if (act) {
-        lo = static_cast<uint64_t>(i) * s;
-        hi = (i + 1 == jb.c) ? jb.n : lo + s;
+        lo = cx.lo;
+        hi = cx.hi;
         nwin = static_cast<uint32_t>((hi - lo + 63) / 64);
     }
-    const uint32_t nwin_wave = (wave_first + 1 < jb.c) ? static_cast<uint32_t>(s / 64)
-                                                       : static_cast<uint32_t>((jb.n - static_cast<uint64_t>(jb.c - 1) * s + 63) / 64);
+    const uint32_t nwin_wave = wave_max_u32(nwin);
     uint32_t xw[16], cw[16], fwv[64];
     uint64_t y[kVec], z[kVec];
     uint32_t prev[kVec], cur[kVec];
@@ -811,7 +926,7 @@ __global__ __launch_bounds__(kCountThreads) void k_count_fast(Tabs tb, Job jb) {
         if (on) {
             a0 = lo + 64ull * w;
             len = static_cast<uint32_t>(hi - a0 < 64 ? hi - a0 : 64);
-            load_window(jb.text, a0, len, xw);
+            load_window(text, a0, len, xw);
             window_classes(T, xw, cw);
             uint32_t g = jb.ckpt[ck(jb, i, w)];
 #pragma unroll
@@ -872,7 +987,7 @@ __global__ __launch_bounds__(kCountThreads) void k_count_fast(Tabs tb, Job jb) {
         if (on) {
             a0 = lo + 64ull * w;
             len = static_cast<uint32_t>(hi - a0 < 64 ? hi - a0 : 64);
-            load_window(jb.text, a0, len, xw);
+            load_window(text, a0, len, xw);
             window_classes(T, xw, cw);
             uint32_t g = jb.ckpt[ck(jb, i, w)];
 #pragma unroll
@@ -917,82 +1032,126 @@ __global__ __launch_bounds__(kCountThreads) void k_count_fast(Tabs tb, Job jb) {
     jb.tbig_idx[i] = kRank1;
 }
 
-// Count factors: factor[0] covers the text start, factor[i+1] the rank-1
-// chunk i (its pi times u_i^T . (full chunks) . v_j up to the next rank-1
-// chunk j, or the sum at the text end); entries of full chunks are 1.
+// Count factors.  factor[i] for a rank-1 chunk i: its pi times u_i^T (full
+// chunk matrices) v_j up to the next rank-1 chunk j of the same text, or the
+// sum at the text end; 1 for a full chunk.  factor[c + t] for text t: the
+// all-ones vector over its column 0 through its leading full chunks to the
+// first rank-1 chunk's v (or the sum).
 __global__ __launch_bounds__(256) void k_count_factor(Job jb) {
-    if (jb.scalars[0] == 0 || jb.flags[2] != 0) return;
     const uint32_t c = jb.c;
-    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;   // t = 0: text start; t = i+1: chunk i
-    if (t > c) return;
+    const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= c + jb.ntexts) return;
+    const uint32_t t = g < c ? text_of(jb, g) : g - c;
+    const TextRef tr = text_ref(jb, t);
+    if (tr.n == 0 || tr.scalars[0] == 0) {
+        jb.factor[g] = 1;
+        return;
+    }
+    const uint32_t c0 = first_chunk(jb, t), c1 = first_chunk(jb, t + 1);
     uint64_t vec[kBigT];
-    uint32_t dim;
+    uint32_t dim, j;
     uint64_t f = 1;
-    if (t == 0) {
-        dim = jb.dims[0];
-        for (uint32_t k = 0; k < dim; ++k) vec[k] = 1;
-    } else {
-        const uint32_t i = t - 1;
-        if (jb.tbig_idx[i] != kRank1) {
-            jb.factor[t] = 1;
+    if (g >= c) {
+        if (jb.tbig_idx[c0] == kOverflow) {   // the text's count failed
+            jb.factor[g] = 0;
             return;
         }
-        f = jb.pi[i];
-        dim = jb.dims[2 * i + 1];
-        for (uint32_t k = 0; k < dim; ++k) vec[k] = jb.uv[static_cast<uint64_t>(i) * 2 * kVec + k];
+        dim = jb.dims[2 * c0];
+        for (uint32_t k = 0; k < dim; ++k) vec[k] = 1;
+        j = c0;
+    } else {
+        if (jb.tbig_idx[g] != kRank1) {
+            jb.factor[g] = 1;
+            return;
+        }
+        f = jb.pi[g];
+        dim = jb.dims[2 * g + 1];
+        for (uint32_t k = 0; k < dim; ++k) vec[k] = jb.uv[static_cast<uint64_t>(g) * 2 * kVec + k];
+        j = g + 1;
     }
-    uint32_t j = t;   // next chunk index
-    while (j < c && jb.tbig_idx[j] != kRank1) {
+    while (j < c1 && jb.tbig_idx[j] != kRank1) {
+        if (jb.tbig_idx[j] == kOverflow) {   // the text's count failed
+            jb.factor[g] = 0;
+            return;
+        }
         const uint64_t *M = jb.tbig + static_cast<uint64_t>(jb.tbig_idx[j]) * kBigT * kBigT;
         const uint32_t rows = jb.dims[2 * j], cols = jb.dims[2 * j + 1];
         uint64_t nv[kBigT];
         for (uint32_t q = 0; q < cols; ++q) {
-            uint64_t acc = 0;
-            for (uint32_t k = 0; k < rows && k < dim; ++k) acc += vec[k] * M[k * kBigT + q];
-            nv[q] = acc;
+            uint64_t a = 0;
+            for (uint32_t k = 0; k < rows && k < dim; ++k) a += vec[k] * M[k * kBigT + q];
+            nv[q] = a;
         }
         for (uint32_t q = 0; q < cols; ++q) vec[q] = nv[q];
         dim = cols;
         ++j;
     }
     uint64_t d = 0;
-    if (j == c) {
+    if (j == c1) {
         for (uint32_t k = 0; k < dim; ++k) d += vec[k];
     } else {
         const uint64_t *v = jb.uv + static_cast<uint64_t>(j) * 2 * kVec + kVec;
         for (uint32_t k = 0; k < dim; ++k) d += vec[k] * v[k];
     }
-    jb.factor[t] = f * d;
+    jb.factor[g] = f * d;
 }
 
-// Product of the factors modulo 2^64: one block reduces, the last level
-// writes the count.
-__global__ __launch_bounds__(256) void k_prod_reduce(Job jb, const uint64_t *in, uint32_t N, uint64_t *out,
-                                                     int final_level) {
+// Per-text scalars: one block per text.  Empty text: column 0 = I & F and
+// one tree per initial-and-final segment.  Otherwise the count is the
+// product of the text's factors modulo 2^64 (0 for a rejected text); status
+// 2 when not requested, 1 when the general count failed on a chunk of the
+// text, 3 when a join set was not a table state.
+__global__ __launch_bounds__(256) void k_text_scalars(Tabs tb, Job jb, int count) {
     __shared__ uint64_t part[256];
-    const uint32_t t = threadIdx.x;
-    if (jb.scalars[0] == 0 || jb.flags[2] != 0) {
-        if (final_level && blockIdx.x == 0 && t == 0) {
-            jb.scalars[1] = 0;
-            jb.scalars[2] = jb.flags[2] ? 1ull : 0ull;
+    __shared__ uint32_t failed;
+    const uint32_t t = blockIdx.x, th = threadIdx.x;
+    const TextRef tr = text_ref(jb, t);
+    if (tr.n == 0) {
+        if (th == 0) {
+            const uint64_t *fb = tb.fbits + static_cast<uint64_t>(tb.fstart) * tb.W;
+            const uint64_t *rb = tb.rbits + static_cast<uint64_t>(tb.rstart) * tb.W;
+            uint64_t any = 0, pc = 0;
+            for (uint32_t w = 0; w < tb.W; ++w) {
+                const uint64_t v = fb[w] & rb[w];
+                tr.out[w] = v;
+                any |= v;
+                pc += __popcll(v);
+            }
+            tr.scalars[0] = any ? 1 : 0;
+            tr.scalars[1] = count ? pc : 0;
+            tr.scalars[2] = count ? 0 : 2;
         }
         return;
     }
-    uint64_t acc = 1;
-    for (uint32_t k = blockIdx.x * 256 + t; k < N; k += gridDim.x * 256) acc *= in[k];
-    part[t] = acc;
-    __syncthreads();
-    for (uint32_t h = 128; h; h >>= 1) {
-        if (t < h) part[t] *= part[t + h];
+    uint64_t st = 0, val = 0;
+    if (!count) {
+        st = 2;
+    } else if (tr.scalars[0] == 0) {
+        st = 0;
+    } else {
+        const uint32_t c0 = first_chunk(jb, t), c1 = first_chunk(jb, t + 1);
+        if (th == 0) failed = 0;
         __syncthreads();
-    }
-    if (t == 0) {
-        if (final_level) {
-            jb.scalars[1] = part[0];
-            jb.scalars[2] = 0;
-        } else {
-            out[blockIdx.x] = part[0];
+        uint64_t acc = 1;
+        bool bad = false;
+        for (uint32_t k = c0 + th; k < c1; k += blockDim.x) {
+            acc *= jb.factor[k];
+            bad = bad || jb.tbig_idx[k] == kOverflow;
         }
+        if (bad) atomicOr(&failed, 1u);
+        part[th] = acc;
+        __syncthreads();
+        for (uint32_t h = 128; h; h >>= 1) {
+            if (th < h) part[th] *= part[th + h];
+            __syncthreads();
+        }
+        if (failed) st = 1;
+        else val = part[0] * jb.factor[jb.c + t];
+    }
+    if (jb.flags[0]) st = 3;
+    if (th == 0) {
+        tr.scalars[1] = val;
+        tr.scalars[2] = st;
     }
 }
 
@@ -1010,15 +1169,16 @@ __device__ inline void count_chunk_general(const Tabs &tb, const Job &jb, uint32
     __shared__ uint32_t fail;
     const uint32_t q = threadIdx.x;
     const uint32_t W = tb.W;
-    const uint64_t lo = static_cast<uint64_t>(i) * jb.s;
-    const uint64_t hi = (i + 1 == jb.c) ? jb.n : lo + jb.s;
+    const ChunkCtx cx = chunk_ctx(jb, i);
+    const uint64_t lo = cx.lo, hi = cx.hi;
+    uint64_t *out = cx.tr.out;
     if (q == 0) fail = 0;
     __syncthreads();
     // list the segments of column r into segs[slot]; returns the count or > 64
     auto list_column = [&](uint64_t r, int slot) {
         if (q == 0) {
             uint32_t cnt = 0;
-            const uint64_t *col = jb.out + r * W;
+            const uint64_t *col = out + r * W;
             for (uint32_t w = 0; w < W && cnt <= kBigT; ++w) {
                 uint64_t v = col[w];
                 while (v) {
@@ -1035,20 +1195,14 @@ __device__ inline void count_chunk_general(const Tabs &tb, const Job &jb, uint32
     int cur = 0;
     list_column(hi, cur);
     const uint32_t mR = nseg[cur];
-    if (mR > kBigT) {
-        if (q == 0) atomicOr(&jb.flags[2], 1u);
-        return;
-    }
+    if (mR > kBigT) return;     // tbig_idx[i] stays kOverflow
     for (uint32_t k = 0; k < kBigT; ++k) U[cur][k][q] = (k == q && q < mR) ? 1ull : 0ull;
     __syncthreads();
     for (uint64_t r = hi; r-- > lo;) {
         const int nxt = cur ^ 1;
         list_column(r, nxt);
         const uint32_t m = nseg[nxt], mp = nseg[cur];
-        if (m > kBigT) {
-            if (q == 0) atomicOr(&jb.flags[2], 1u);
-            return;
-        }
+        if (m > kBigT) return;
         if (q < m) {   // arcs of the q-th segment of column r into column r+1
             const uint64_t *fs = tb.folseg + static_cast<uint64_t>(segs[nxt][q]) * W;
             uint64_t a = 0;
@@ -1081,10 +1235,7 @@ __device__ inline void count_chunk_general(const Tabs &tb, const Job &jb, uint32
     __shared__ uint32_t slot;
     if (q == 0) slot = atomicAdd(&jb.flags[1], 1u);
     __syncthreads();
-    if (slot >= jb.big_pool) {
-        if (q == 0) atomicOr(&jb.flags[2], 1u);
-        return;
-    }
+    if (slot >= jb.big_pool) return;
     for (uint32_t k = 0; k < kBigT; ++k)
         jb.tbig[static_cast<uint64_t>(slot) * kBigT * kBigT + k * kBigT + q] = (k < mL && q < mR) ? U[cur][k][q] : 0ull;
     __syncthreads();
@@ -1092,7 +1243,6 @@ __device__ inline void count_chunk_general(const Tabs &tb, const Job &jb, uint32
 }
 
 __global__ __launch_bounds__(64) void k_count_chunk(Tabs tb, Job jb) {
-    if (jb.scalars[0] == 0) return;
     for (uint32_t item = blockIdx.x; item < jb.flags[3]; item += gridDim.x) {
         count_chunk_general(tb, jb, jb.ovf[item]);
         __syncthreads();
@@ -1101,36 +1251,6 @@ __global__ __launch_bounds__(64) void k_count_chunk(Tabs tb, Job jb) {
 
 __global__ void k_init(Job jb) {
     if (blockIdx.x == 0 && threadIdx.x < 4) jb.flags[threadIdx.x] = 0;
-}
-
-__global__ void k_set_scalars(Job jb, uint64_t v1, uint64_t v2) {
-    if (threadIdx.x || blockIdx.x) return;
-    jb.scalars[1] = v1;
-    jb.scalars[2] = v2;
-}
-
-// An edge set that is not a state of the table means a broken table: report
-// it as count status 3 so that callers never take such a result as valid.
-__global__ void k_finish(Job jb) {
-    if (threadIdx.x || blockIdx.x) return;
-    if (jb.flags[0]) jb.scalars[2] = 3;
-}
-
-// Empty text: one column I & F; one tree per initial-and-final segment.
-__global__ void k_empty(Tabs tb, Job jb, int count) {
-    if (threadIdx.x || blockIdx.x) return;
-    const uint64_t *fb = tb.fbits + static_cast<uint64_t>(tb.fstart) * tb.W;
-    const uint64_t *rb = tb.rbits + static_cast<uint64_t>(tb.rstart) * tb.W;
-    uint64_t any = 0, pc = 0;
-    for (uint32_t w = 0; w < tb.W; ++w) {
-        uint64_t v = fb[w] & rb[w];
-        jb.out[w] = v;
-        any |= v;
-        pc += __popcll(v);
-    }
-    jb.scalars[0] = any ? 1 : 0;
-    jb.scalars[1] = count ? pc : 0;
-    jb.scalars[2] = count ? 0 : 2;
 }
 
 }  // namespace slpf

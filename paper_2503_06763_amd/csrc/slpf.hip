@@ -24,6 +24,9 @@ size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 struct Workspace {
     void *base = nullptr;
     size_t bytes = 0;
+    uint64_t *pinned = nullptr;       // host staging of batch descriptors
+    size_t pinned_words = 0;
+    hipEvent_t copied = nullptr;      // the last descriptor copy
 };
 
 }  // namespace
@@ -39,7 +42,7 @@ struct slpf_parser {
     size_t lds_bytes = 0;
     bool host_only = false;
     std::mutex mu;
-    std::map<void *, Workspace> ws;   // per stream
+    std::map<hipStream_t, Workspace> ws;   // per stream
 };
 
 namespace {
@@ -142,13 +145,12 @@ uint64_t chunk_bytes_for(uint64_t n, const slpf_parse_opts *o) {
 }
 
 struct Layout {
-    size_t off[40];
-    int k = 0;
+    std::vector<size_t> off;
     size_t total = 0;
-    size_t add(size_t bytes) {
-        off[k] = total;
+    int add(size_t bytes) {
+        off.push_back(total);
         total = align_up(total + std::max<size_t>(bytes, 8), 256);
-        return k++;
+        return static_cast<int>(off.size()) - 1;
     }
 };
 
@@ -216,8 +218,12 @@ void slpf_parser_destroy(slpf_parser *p) {
         return;
     }
     hipSetDevice(p->device);
-    for (auto &kv : p->ws)
+    for (auto &kv : p->ws) {
+        if (kv.second.copied) hipEventSynchronize(kv.second.copied);
         if (kv.second.base) hipFree(kv.second.base);
+        if (kv.second.pinned) hipHostFree(kv.second.pinned);
+        if (kv.second.copied) hipEventDestroy(kv.second.copied);
+    }
     if (p->blob) hipFree(p->blob);
     delete p;
 }
@@ -271,81 +277,85 @@ uint64_t slpf_forest_bytes(const slpf_parser *p, uint64_t n) {
     return (n + 1) * static_cast<uint64_t>(p->A.W) * 8;
 }
 
-uint64_t slpf_num_chunks(const slpf_parser *p, uint64_t n, const slpf_parse_opts *opts) {
+uint64_t slpf_num_chunks(const slpf_parser *p, uint64_t n, const slpf_parse_opts *opts) {  // one text
     if (!p || n == 0) return 0;
     uint64_t s = chunk_bytes_for(n, opts);
     return (n + s - 1) / s;
 }
 
-slpf_status slpf_parse(const slpf_parser *cp, const uint8_t *text, uint64_t n, const slpf_parse_opts *opts,
-                       const slpf_forest *forest, void *hip_stream) {
-    slpf_parser *p = const_cast<slpf_parser *>(cp);
-    if (!p || p->host_only || !forest || !forest->columns_dev || !forest->scalars_dev) return SLPF_E_ARG;
-    if (opts && opts->struct_size != sizeof(slpf_parse_opts)) return SLPF_E_ARG;
-    if (n && !text) return SLPF_E_ARG;
-    if (reinterpret_cast<uintptr_t>(text) % 16 != 0) return SLPF_E_ARG;
-    if (opts && opts->chunk_bytes && (opts->chunk_bytes % 64 != 0)) return SLPF_E_ARG;
-    if (forest->capacity_bytes < slpf_forest_bytes(p, n)) return SLPF_E_CAPACITY;
+}  // extern "C"
+
+namespace {
+
+// One job: T texts parsed with one parser; text t owns lane chunks
+// tchunk0[t] .. tchunk0[t+1]-1 of a common index space.
+slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf_parse_opts *opts,
+                    hipStream_t stream) {
     const uint32_t flags = opts ? opts->flags : 0;
     const bool count = !(flags & SLPF_PARSE_NO_COUNT);
-    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
     if (hipSetDevice(p->device) != hipSuccess) return SLPF_E_DEVICE;
     Tabs tb = p->tabs;
-    Job jb{};
-    jb.text = text;
-    jb.n = n;
-    jb.out = forest->columns_dev;
-    jb.scalars = forest->scalars_dev;
-    if (n == 0) {
-        hipLaunchKernelGGL(k_empty, dim3(1), dim3(1), 0, stream, tb, jb, count ? 1 : 0);
-        return hip_ok(hipGetLastError());
+    const uint32_t W = tb.W, E = tb.emax;
+    uint64_t total = 0;
+    for (size_t t = 0; t < T; ++t) total += items[t].n;
+    const uint64_t s = chunk_bytes_for(total, opts);
+    std::vector<uint32_t> tchunk0(T + 1, 0);
+    uint64_t c64 = 0;
+    for (size_t t = 0; t < T; ++t) {
+        tchunk0[t] = static_cast<uint32_t>(c64);
+        c64 += (items[t].n + s - 1) / s;
+        if (c64 > 0x7fffffffull) return SLPF_E_ARG;
     }
-    const uint64_t s = chunk_bytes_for(n, opts);
-    const uint64_t c64 = (n + s - 1) / s;
-    if (c64 > 0x7fffffffull) return SLPF_E_ARG;
+    tchunk0[T] = static_cast<uint32_t>(c64);
     const uint32_t c = static_cast<uint32_t>(c64);
+    const uint32_t nt = static_cast<uint32_t>(T);
+
+    Job jb{};
+    jb.ntexts = nt;
     jb.s = s;
     jb.c = c;
-    const uint32_t E = tb.emax, W = tb.W;
-    const std::vector<uint32_t> jl = join_levels(c);
+    if (T == 1) {
+        jb.d0[0] = reinterpret_cast<uint64_t>(items[0].text_dev);
+        jb.d0[1] = items[0].n;
+        jb.d0[2] = reinterpret_cast<uint64_t>(items[0].out.columns_dev);
+        jb.d0[3] = reinterpret_cast<uint64_t>(items[0].out.scalars_dev);
+    }
+    const std::vector<uint32_t> jl = join_levels(std::max<uint32_t>(c, 1));
+    const size_t nck = size_t(c) * ((s + 63) / 64);   // window-major checkpoints
 
     Layout L;
+    int itd = L.add(T > 1 ? T * 32 + (T + 1) * 4 + 64 : 8);
     int iR = L.add(size_t(E) * c * 2), iRh = L.add(size_t(E) * c * 2);
     int iMf = L.add(size_t(c) * E * 8), iMb = L.add(size_t(c) * E * 8);
-    int inxf = L.add(c + 1), inxb = L.add(c + 1);
-    int ivf = L.add(size_t(c + 1) * 8), ivb = L.add(size_t(c + 1) * 8);
+    int inxf = L.add(c + 1), inxb = L.add(c + 1), irsf = L.add(c + 1), irsb = L.add(c + 1);
+    int ifin = L.add(size_t(c + 1) * 8), ifout = L.add(size_t(c + 1) * 8);
+    int ibin = L.add(size_t(c + 1) * 8), ibout = L.add(size_t(c + 1) * 8);
     int ifid = L.add(size_t(c) * 2), irid = L.add(size_t(c) * 2);
-    const size_t nck = size_t(c) * ((s + 63) / 64);   // window-major checkpoints
-    int ickpt = L.add(nck * 2);
-    int ibckpt = L.add(nck * 2);
+    int ickpt = L.add(nck * 2), ibckpt = L.add(nck * 2);
     int iflags = L.add(16);
-    // join levels >= 1: maps [N][64], nx [N+1], vectors [N+1], both directions
-    std::vector<int> jmf, jmb, jnxf, jnxb, jvf, jvb;
-    for (size_t l = 1; l < jl.size(); ++l) {
-        jmf.push_back(L.add(size_t(jl[l]) * 64 * 8));
-        jmb.push_back(L.add(size_t(jl[l]) * 64 * 8));
-        jnxf.push_back(L.add(jl[l] + 1));
-        jnxb.push_back(L.add(jl[l] + 1));
-        jvf.push_back(L.add(size_t(jl[l] + 1) * 8));
-        jvb.push_back(L.add(size_t(jl[l] + 1) * 8));
-    }
-    int idims = -1, iuv = -1, ipi = -1, ifac = -1, itidx = -1, itbig = -1, iovf = -1, ired = -1;
-    const uint32_t red_blocks = std::min<uint32_t>((c + 1 + 255) / 256, 1024);
+    std::vector<int> jrows[2], jisc[2], jcv[2], jvec[2];
+    for (size_t l = 1; l < jl.size(); ++l)
+        for (int d = 0; d < 2; ++d) {
+            jrows[d].push_back(L.add(size_t(jl[l]) * 64 * 8));
+            jisc[d].push_back(L.add(jl[l] + 1));
+            jcv[d].push_back(L.add(size_t(jl[l] + 1) * 8));
+            jvec[d].push_back(L.add(size_t(jl[l] + 1) * 8));
+        }
+    int idims = -1, iuv = -1, ipi = -1, ifac = -1, itidx = -1, itbig = -1, iovf = -1;
     if (count) {
         idims = L.add(size_t(c) * 2);
         iuv = L.add(size_t(c) * 2 * kVec * 8);
         ipi = L.add(size_t(c) * 8);
-        ifac = L.add(size_t(c + 1) * 8);
+        ifac = L.add(size_t(c + T) * 8);
         itidx = L.add(size_t(c) * 4);
         iovf = L.add(size_t(c) * 4);
         itbig = L.add(size_t(kBigPool) * kBigT * kBigT * 8);
-        ired = L.add(size_t(red_blocks) * 8);
     }
 
     uint8_t *base;
     {
         std::lock_guard<std::mutex> g(p->mu);
-        Workspace &w = p->ws[hip_stream];
+        Workspace &w = p->ws[stream];
         if (w.bytes < L.total) {
             if (w.base) {
                 if (hipStreamSynchronize(stream) != hipSuccess) return SLPF_E_DEVICE;
@@ -361,23 +371,58 @@ slpf_status slpf_parse(const slpf_parser *cp, const uint8_t *text, uint64_t n, c
             w.bytes = want;
         }
         base = static_cast<uint8_t *>(w.base);
+        if (T > 1) {   // text descriptors: pinned staging, copied on the stream
+            if (w.copied && hipEventSynchronize(w.copied) != hipSuccess) return SLPF_E_DEVICE;
+            const size_t need = T * 4 + (T + 1 + 1) / 2 + 8;
+            if (w.pinned_words < need) {
+                if (w.pinned) hipHostFree(w.pinned);
+                w.pinned = nullptr;
+                if (hipHostMalloc(reinterpret_cast<void **>(&w.pinned), need * 8, hipHostMallocDefault) != hipSuccess) {
+                    w.pinned_words = 0;
+                    return SLPF_E_NOMEM;
+                }
+                w.pinned_words = need;
+            }
+            uint64_t *d = w.pinned;
+            for (size_t t = 0; t < T; ++t) {
+                d[4 * t] = reinterpret_cast<uint64_t>(items[t].text_dev);
+                d[4 * t + 1] = items[t].n;
+                d[4 * t + 2] = reinterpret_cast<uint64_t>(items[t].out.columns_dev);
+                d[4 * t + 3] = reinterpret_cast<uint64_t>(items[t].out.scalars_dev);
+            }
+            std::memcpy(d + 4 * T, tchunk0.data(), (T + 1) * 4);
+            if (hipMemcpyAsync(base + L.off[itd], d, T * 32 + (T + 1) * 4, hipMemcpyHostToDevice, stream) !=
+                hipSuccess)
+                return SLPF_E_DEVICE;
+            if (!w.copied && hipEventCreateWithFlags(&w.copied, hipEventDisableTiming) != hipSuccess)
+                return SLPF_E_DEVICE;
+            if (hipEventRecord(w.copied, stream) != hipSuccess) return SLPF_E_DEVICE;
+        }
     }
     auto ptr = [&](int k) { return base + L.off[k]; };
+    if (T > 1) {
+        jb.tdesc = reinterpret_cast<const uint64_t *>(ptr(itd));
+        jb.tchunk0 = reinterpret_cast<const uint32_t *>(ptr(itd) + T * 32);
+    }
     jb.R = reinterpret_cast<uint16_t *>(ptr(iR));
     jb.Rh = reinterpret_cast<uint16_t *>(ptr(iRh));
     jb.Mf = reinterpret_cast<uint64_t *>(ptr(iMf));
     jb.MbR = reinterpret_cast<uint64_t *>(ptr(iMb));
     jb.nxf = ptr(inxf);
     jb.nxb = ptr(inxb);
-    jb.vf = reinterpret_cast<uint64_t *>(ptr(ivf));
-    jb.vb = reinterpret_cast<uint64_t *>(ptr(ivb));
+    jb.rsf = ptr(irsf);
+    jb.rsb = ptr(irsb);
+    jb.fin = reinterpret_cast<uint64_t *>(ptr(ifin));
+    jb.fout = reinterpret_cast<uint64_t *>(ptr(ifout));
+    jb.bin = reinterpret_cast<uint64_t *>(ptr(ibin));
+    jb.bout = reinterpret_cast<uint64_t *>(ptr(ibout));
     jb.fid = reinterpret_cast<uint16_t *>(ptr(ifid));
     jb.rid = reinterpret_cast<uint16_t *>(ptr(irid));
     jb.ckpt = reinterpret_cast<uint16_t *>(ptr(ickpt));
     jb.bckpt = reinterpret_cast<uint16_t *>(ptr(ibckpt));
     jb.flags = reinterpret_cast<uint32_t *>(ptr(iflags));
     jb.trace = nullptr;
-    if (opts && opts->trace_dev && opts->trace_bytes >= 2ull * (c + 1) * W * 8) jb.trace = opts->trace_dev;
+    if (T == 1 && opts && opts->trace_dev && opts->trace_bytes >= 2ull * (c + 1) * W * 8) jb.trace = opts->trace_dev;
     if (count) {
         jb.dims = ptr(idims);
         jb.uv = reinterpret_cast<uint64_t *>(ptr(iuv));
@@ -403,58 +448,80 @@ slpf_status slpf_parse(const slpf_parser *cp, const uint8_t *text, uint64_t n, c
     const uint32_t blocks = (c + 255) / 256;
 
     hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, stream, jb);
-
     mark(0);
-    // reach
-    if (lds) hipLaunchKernelGGL(k_reach<true>, dim3(blocks), dim3(256), lds_bytes, stream, tb, jb);
-    else hipLaunchKernelGGL(k_reach<false>, dim3(blocks), dim3(256), 0, stream, tb, jb);
-
+    if (c) {
+        // reach
+        if (lds) hipLaunchKernelGGL(k_reach<true>, dim3(blocks), dim3(256), lds_bytes, stream, tb, jb);
+        else hipLaunchKernelGGL(k_reach<false>, dim3(blocks), dim3(256), 0, stream, tb, jb);
+    }
     mark(1);
-    // join: forward maps (Mf, nxf) and reversed backward maps (MbR, nxb)
-    for (int dir = 0; dir < 2; ++dir) {
-        std::vector<const uint64_t *> M{dir == 0 ? jb.Mf : jb.MbR};
-        std::vector<uint32_t> stride{E};
-        std::vector<const uint8_t *> nx{dir == 0 ? jb.nxf : jb.nxb};
-        std::vector<uint64_t *> vec{dir == 0 ? jb.vf : jb.vb};
-        for (size_t l = 1; l < jl.size(); ++l) {
-            uint64_t *outM = reinterpret_cast<uint64_t *>(ptr(dir == 0 ? jmf[l - 1] : jmb[l - 1]));
-            uint8_t *outnx = ptr(dir == 0 ? jnxf[l - 1] : jnxb[l - 1]);
-            hipLaunchKernelGGL(k_compose, dim3(jl[l]), dim3(64), 0, stream, M.back(), stride.back(), jl[l - 1],
-                               nx.back(), outM, outnx);
-            M.push_back(outM);
-            stride.push_back(64);
-            nx.push_back(outnx);
-            vec.push_back(reinterpret_cast<uint64_t *>(ptr(dir == 0 ? jvf[l - 1] : jvb[l - 1])));
-        }
-        const size_t top = jl.size() - 1;
-        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1), 0, stream, M[top], stride[top], jl[top], nx[top],
-                           vec[top]);
-        for (size_t l = top; l-- > 0;) {
-            hipLaunchKernelGGL(k_expand, dim3((jl[l + 1] + 63) / 64), dim3(64), 0, stream, M[l], stride[l], jl[l],
-                               vec[l + 1], jl[l + 1], vec[l]);
+    if (c) {
+        // join: segmented scans, forward (text order) and backward (reversed)
+        for (int d = 0; d < 2; ++d) {
+            std::vector<ScanLevel> lv;
+            ScanLevel l0{};
+            l0.rows = d == 0 ? jb.Mf : jb.MbR;
+            l0.stride = E;
+            l0.N = c;
+            l0.nx = d == 0 ? jb.nxf : jb.nxb;
+            l0.rs = d == 0 ? jb.rsf : jb.rsb;
+            l0.level0 = 1;
+            lv.push_back(l0);
+            std::vector<uint64_t *> vec{nullptr};
+            for (size_t l = 1; l < jl.size(); ++l) {
+                uint64_t *rows = reinterpret_cast<uint64_t *>(ptr(jrows[d][l - 1]));
+                uint8_t *isc = ptr(jisc[d][l - 1]);
+                uint64_t *cv = reinterpret_cast<uint64_t *>(ptr(jcv[d][l - 1]));
+                hipLaunchKernelGGL(k_compose, dim3(jl[l]), dim3(64), 0, stream, lv.back(), rows, isc, cv);
+                ScanLevel nl{};
+                nl.rows = rows;
+                nl.stride = 64;
+                nl.N = jl[l];
+                nl.isc = isc;
+                nl.cv = cv;
+                nl.level0 = 0;
+                lv.push_back(nl);
+                vec.push_back(reinterpret_cast<uint64_t *>(ptr(jvec[d][l - 1])));
+            }
+            uint64_t *vin = d == 0 ? jb.fin : jb.bin, *vout = d == 0 ? jb.fout : jb.bout;
+            const size_t top = lv.size() - 1;
+            if (top == 0) {
+                hipLaunchKernelGGL(k_expand0, dim3(1), dim3(64), 0, stream, lv[0], static_cast<const uint64_t *>(nullptr),
+                                   1u, vin, vout);
+            } else {
+                hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1), 0, stream, lv[top], vec[top]);
+                for (size_t l = top; l-- > 1;)
+                    hipLaunchKernelGGL(k_expand, dim3((jl[l + 1] + 63) / 64), dim3(64), 0, stream, lv[l],
+                                       static_cast<const uint64_t *>(vec[l + 1]), jl[l + 1], vec[l]);
+                hipLaunchKernelGGL(k_expand0, dim3((jl[1] + 63) / 64), dim3(64), 0, stream, lv[0],
+                                   static_cast<const uint64_t *>(vec[1]), jl[1], vin, vout);
+            }
         }
     }
     mark(2);
-    hipLaunchKernelGGL(k_starts, dim3(blocks), dim3(256), 0, stream, tb, jb);
+    if (c) hipLaunchKernelGGL(k_starts, dim3(blocks), dim3(256), 0, stream, tb, jb);
     mark(3);
 
     // build & merge: transition tables and bit sets in LDS when they fit
     const size_t tab_lds = (512 + (size_t(tb.nf) + tb.nr) * tb.C * 2 + 15) & ~size_t(15);
     const size_t bits_lds = (size_t(tb.nf) + tb.nr) * W * 8;
-    const bool fit_tab = lds && kStageBytes + tab_lds <= p->lds_limit;
-    const bool fit_bits = fit_tab && kStageBytes + tab_lds + bits_lds <= p->lds_limit;
-    const uint32_t bblocks = (c + kBuildThreads - 1) / kBuildThreads;
-    if (fit_bits)
-        hipLaunchKernelGGL((k_build<true, true>), dim3(bblocks), dim3(kBuildThreads), kStageBytes + tab_lds + bits_lds,
-                           stream, tb, jb);
-    else if (fit_tab)
-        hipLaunchKernelGGL((k_build<true, false>), dim3(bblocks), dim3(kBuildThreads), kStageBytes + tab_lds, stream,
-                           tb, jb);
-    else
-        hipLaunchKernelGGL((k_build<false, false>), dim3(bblocks), dim3(kBuildThreads), kStageBytes, stream, tb, jb);
+    if (c) {
+        const bool fit_tab = lds && kStageBytes + tab_lds <= p->lds_limit;
+        const bool fit_bits = fit_tab && kStageBytes + tab_lds + bits_lds <= p->lds_limit;
+        const uint32_t bblocks = (c + kBuildThreads - 1) / kBuildThreads;
+        if (fit_bits)
+            hipLaunchKernelGGL((k_build<true, true>), dim3(bblocks), dim3(kBuildThreads),
+                               kStageBytes + tab_lds + bits_lds, stream, tb, jb);
+        else if (fit_tab)
+            hipLaunchKernelGGL((k_build<true, false>), dim3(bblocks), dim3(kBuildThreads), kStageBytes + tab_lds,
+                               stream, tb, jb);
+        else
+            hipLaunchKernelGGL((k_build<false, false>), dim3(bblocks), dim3(kBuildThreads), kStageBytes, stream, tb,
+                               jb);
+    }
     mark(4);
     // tree count
-    if (count) {
+    if (count && c) {
         const size_t fol_lds = (size_t(A_nseg(p)) * W * 8 + 15) & ~size_t(15);
         const uint32_t cblocks = (c + kCountThreads - 1) / kCountThreads;
         const bool cfit_tab = lds && fol_lds + tab_lds <= p->lds_limit;
@@ -469,22 +536,51 @@ slpf_status slpf_parse(const slpf_parser *cp, const uint8_t *text, uint64_t n, c
             hipLaunchKernelGGL((k_count_fast<false, false, false>), dim3(cblocks), dim3(kCountThreads), 0, stream,
                                tb, jb);
         hipLaunchKernelGGL(k_count_chunk, dim3(std::min<uint32_t>(c, 1024)), dim3(64), 0, stream, tb, jb);
-        hipLaunchKernelGGL(k_count_factor, dim3((c + 1 + 255) / 256), dim3(256), 0, stream, jb);
-        uint64_t *red = reinterpret_cast<uint64_t *>(ptr(ired));
-        if (red_blocks == 1) {
-            hipLaunchKernelGGL(k_prod_reduce, dim3(1), dim3(256), 0, stream, jb, jb.factor, c + 1, red, 1);
-        } else {
-            hipLaunchKernelGGL(k_prod_reduce, dim3(red_blocks), dim3(256), 0, stream, jb, jb.factor, c + 1, red, 0);
-            hipLaunchKernelGGL(k_prod_reduce, dim3(1), dim3(256), 0, stream, jb, static_cast<const uint64_t *>(red),
-                               red_blocks, red, 1);
-        }
-    } else {
-        hipLaunchKernelGGL(k_set_scalars, dim3(1), dim3(1), 0, stream, jb, 0ull, 2ull);
+        hipLaunchKernelGGL(k_count_factor, dim3((c + nt + 255) / 256), dim3(256), 0, stream, jb);
     }
-    hipLaunchKernelGGL(k_finish, dim3(1), dim3(1), 0, stream, jb);
+    hipLaunchKernelGGL(k_text_scalars, dim3(nt), dim3(256), 0, stream, tb, jb, count ? 1 : 0);
     mark(5);
     if (ev_err != hipSuccess) return SLPF_E_ARG;
     return hip_ok(hipGetLastError());
+}
+
+slpf_status check_item(const slpf_parser *p, const uint8_t *text, uint64_t n, const slpf_forest *forest) {
+    if (!forest || !forest->columns_dev || !forest->scalars_dev) return SLPF_E_ARG;
+    if (n && !text) return SLPF_E_ARG;
+    if (reinterpret_cast<uintptr_t>(text) % 16 != 0) return SLPF_E_ARG;
+    if (forest->capacity_bytes < slpf_forest_bytes(p, n)) return SLPF_E_CAPACITY;
+    return SLPF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+slpf_status slpf_parse(const slpf_parser *cp, const uint8_t *text, uint64_t n, const slpf_parse_opts *opts,
+                       const slpf_forest *forest, void *hip_stream) {
+    slpf_parser *p = const_cast<slpf_parser *>(cp);
+    if (!p || p->host_only) return SLPF_E_ARG;
+    if (opts && opts->struct_size != sizeof(slpf_parse_opts)) return SLPF_E_ARG;
+    if (opts && opts->chunk_bytes && (opts->chunk_bytes % 64 != 0)) return SLPF_E_ARG;
+    slpf_status st = check_item(p, text, n, forest);
+    if (st != SLPF_OK) return st;
+    slpf_text item{text, n, *forest};
+    return run_job(p, &item, 1, opts, static_cast<hipStream_t>(hip_stream));
+}
+
+slpf_status slpf_parse_batch(const slpf_parser *cp, const slpf_text *items, size_t count, const slpf_parse_opts *opts,
+                             void *hip_stream) {
+    slpf_parser *p = const_cast<slpf_parser *>(cp);
+    if (!p || p->host_only || (!items && count)) return SLPF_E_ARG;
+    if (opts && opts->struct_size != sizeof(slpf_parse_opts)) return SLPF_E_ARG;
+    if (opts && opts->chunk_bytes && (opts->chunk_bytes % 64 != 0)) return SLPF_E_ARG;
+    if (count == 0) return SLPF_OK;
+    if (count > 0x7fffffffull) return SLPF_E_ARG;
+    for (size_t t = 0; t < count; ++t) {
+        slpf_status st = check_item(p, items[t].text_dev, items[t].n, &items[t].out);
+        if (st != SLPF_OK) return st;
+    }
+    return run_job(p, items, count, opts, static_cast<hipStream_t>(hip_stream));
 }
 
 }  // extern "C"

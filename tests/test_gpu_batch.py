@@ -1,0 +1,161 @@
+"""Batched parsing (slpf_parse_batch): one job over many texts gives, for
+every text, exactly the columns, accept flag, count and status of parsing
+that text alone, and of the oracle.
+
+Covers empty and one-byte texts between long ones, texts that are rejected
+next to accepted ones, a text whose count fails next to one whose count
+succeeds, enough lane chunks for a three-level join scan with text
+boundaries inside every scan group, and the argument checks.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from gen import regen, textgen
+from gpu_util import device, gpu_parse, to_device
+from oracle.oracle import Oracle
+
+S = pytest.importorskip("paper_2503_06763_amd")
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def run_batch(p, texts, chunk_bytes=0, count=True, force_l2=False):
+    import torch
+    dts = [to_device(t) for t in texts]
+    res = p.parse_batch(dts, chunk_bytes=chunk_bytes, count=count, force_l2=force_l2)
+    torch.cuda.synchronize()
+    out = []
+    for cols, sc in res:
+        s = sc.cpu().numpy().view(np.uint64)
+        out.append((cols.cpu().numpy().view(np.uint64), bool(s[0]), int(s[1]), int(s[2])))
+    return out
+
+
+def mixed_texts(tree, seed, k, max_len):
+    """Accepted samples and corrupted (mostly rejected) copies, log-uniform
+    lengths, with empty and one-byte texts mixed in."""
+    rng = np.random.default_rng(seed)
+    texts = []
+    for j in range(k):
+        r = rng.random()
+        if r < 0.08:
+            texts.append(b"")
+            continue
+        n = int(np.exp(rng.uniform(0, np.log(max_len))))
+        t = textgen.sample_text(tree, seed * 1000 + j, n).tobytes()
+        if r > 0.7:
+            t = textgen.corrupt(np.frombuffer(t, np.uint8), seed * 1000 + j, frac=0.05,
+                                block=(1, 64)).tobytes()
+        if r < 0.12:
+            t = t[:1]
+        texts.append(t)
+    return texts
+
+
+def check_batch(pat, texts, chunk_bytes=0, force_l2=False, oracle=True):
+    say("batch", pat[:50], "texts=%d" % len(texts), "bytes=%d" % sum(map(len, texts)),
+        "k=%d" % chunk_bytes, "l2=%d" % force_l2)
+    p = S.Parser(pat)
+    o = Oracle(pat) if oracle else None
+    got = run_batch(p, texts, chunk_bytes=chunk_bytes, force_l2=force_l2)
+    for j, t in enumerate(texts):
+        alone = gpu_parse(p, t, chunk_bytes=chunk_bytes, force_l2=force_l2)
+        b = got[j]
+        assert b[0].shape == alone[0].shape, j
+        bad = np.nonzero((b[0] != alone[0]).any(axis=1))[0]
+        assert bad.size == 0, "text %d (n=%d): column %d differs from the single parse" % (j, len(t), bad[0])
+        assert b[1:] == alone[1:], (j, b[1:], alone[1:])
+        if o is not None:
+            cols, acc, cnt = o.parse(t)
+            assert np.array_equal(b[0], cols), j
+            assert b[1] == acc, j
+            if b[3] == 0:
+                assert b[2] == cnt, j
+    return got
+
+
+def test_batch_plain_small_mixed():
+    device()
+    tree = regen.plain_small_re()
+    pat = regen.to_re(tree).decode()
+    texts = mixed_texts(tree, 3, 40, 20000)
+    for k in (0, 64, 256):
+        got = check_batch(pat, texts, chunk_bytes=k)
+    assert any(g[1] for g in got) and not all(g[1] for g in got)
+
+
+def test_batch_force_l2_and_random_res():
+    device()
+    for seed in (5, 11):
+        tree = regen.random_re(300 + seed, n_ops=12, max_depth=5, alphabet=b"abc")
+        pat = regen.to_re(tree).decode()
+        texts = mixed_texts(tree, seed, 24, 5000)
+        check_batch(pat, texts, chunk_bytes=128)
+        check_batch(pat, texts, chunk_bytes=128, force_l2=True)
+
+
+def test_batch_empty_and_tiny_only():
+    device()
+    pat = "(ab|a)*"
+    texts = [b"", b"a", b"", b"ab", b"b", b"aba", b"", b"z", b"abaaba"]
+    check_batch(pat, texts)
+    check_batch(pat, [b""])
+    check_batch(pat, [b"", b""])
+
+
+def test_batch_count_failure_is_per_text():
+    # every column of a^n holds 20 segments (no singleton), so each of its
+    # 2100 lane chunks needs a full transfer matrix and the 2048 slots run
+    # out: its count fails; the texts of b's (singleton columns) still count
+    device()
+    pat = "((" + "|".join(["a"] * 20) + ")|b)*"
+    texts = [b"b" * 300, b"a" * (64 * 2100), b"", b"b" * 5]
+    got = check_batch(pat, texts, chunk_bytes=64)
+    assert [g[3] for g in got] == [0, 1, 0, 0]
+    assert got[0][2] == 1 and got[3][2] == 1
+
+
+def test_batch_deep_join_scan():
+    # about 6000 lane chunks of 64 bytes: a three-level join scan whose
+    # groups of 64 items hold several text boundaries each
+    device()
+    tree = regen.plain_small_re()
+    pat = regen.to_re(tree).decode()
+    rng = np.random.default_rng(9)
+    texts = []
+    for j in range(700):
+        n = int(rng.integers(0, 1100))
+        t = textgen.sample_text(tree, 5000 + j, n).tobytes()[:n]
+        if j % 7 == 3 and len(t) > 10:
+            t = t[:len(t) // 2] + b"\x00" + t[len(t) // 2 + 1:]
+        texts.append(t)
+    p = S.Parser(pat)
+    assert sum(p.num_chunks(len(t), 64) for t in texts) > 4096
+    check_batch(pat, texts, chunk_bytes=64)
+
+
+def test_batch_argument_errors():
+    import torch
+    dev = device()
+    p = S.Parser("(ab|a)*")
+    t = to_device(b"abab" * 8)
+    cols = torch.empty((33, p.W), dtype=torch.int64, device=dev)
+    sc = torch.empty(3, dtype=torch.int64, device=dev)
+    small = torch.empty((3, p.W), dtype=torch.int64, device=dev)
+    with pytest.raises(S.SlpfError) as e:
+        p.parse_batch_into([(t, 32, cols, sc), (t, 32, small, sc)])
+    assert e.value.status == S.E_CAPACITY
+    with pytest.raises(S.SlpfError) as e:
+        p.parse_batch_into([(t, 32, cols, sc), (t[1:], 31, cols, sc)])
+    assert e.value.status == S.E_ARG
+    with pytest.raises(S.SlpfError) as e:
+        p.parse_batch_into([(t, 32, cols, sc)], chunk_bytes=100)
+    assert e.value.status == S.E_ARG
+    p.parse_batch_into([])
+    torch.cuda.synchronize()
