@@ -408,89 +408,181 @@ __global__ __launch_bounds__(256) void k_reach(Tabs tb, Job jb) {
     }
 }
 
+// Value of v in lane (lane - 1) of the wavefront (lane 0 gets its own value).
+__device__ inline uint64_t shfl_up_u64(uint64_t v, int delta) {
+    const uint32_t lo = static_cast<uint32_t>(__shfl_up(static_cast<int>(static_cast<uint32_t>(v)), delta));
+    const uint32_t hi = static_cast<uint32_t>(__shfl_up(static_cast<int>(static_cast<uint32_t>(v >> 32)), delta));
+    return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
 // --------------------------------------------------------------------- join
 
 // The join is a segmented scan over "items" (chunks, in text order for the
 // forward direction and reversed for the backward one).  Item k maps masks
 // over the entry list at its input edge to masks over the one at its output
-// edge; an item that starts a text ignores its input and starts from all of
-// its entry list (J_0 = I restricted, or J^ = F restricted).  Aggregates of 64
-// items are either a map (rows[m] = image of entry m) or a constant.
+// edge: f(v) = cst ? cv : OR of rows[m] over the bits m of v.  An item that
+// starts a text ignores its input and starts from all of its entry list (J_0 =
+// I restricted, or J^ = F restricted), so it is a constant map.  Level l+1
+// holds the compositions of groups of 64 items of level l, up to a level of
+// one item.  Every wavefront scans its group in LDS (Hillis-Steele, lanes =
+// items) and writes the prefix maps, so the expansion back down is one
+// independent map application per item.
 struct ScanLevel {
-    const uint64_t *rows;       // [N][stride]
-    uint32_t stride;
+    const uint64_t *rows;       // [N][E]
     uint32_t N;
-    const uint8_t *nx;          // [N+1] input entry-list size per item (level 0)
-    const uint8_t *rs;          // level 0: item starts a text
-    const uint8_t *isc;         // level >= 1: aggregate is constant
-    const uint64_t *cv;         // level >= 1: its constant
+    const uint8_t *nx;          // [N] input entry-list size per item
+    const uint8_t *cst;         // [N] level 0: item starts a text; above: constant map
+    const uint64_t *cv;         // [N] level >= 1: the constant
     int level0;
 };
 
-__device__ inline uint64_t scan_apply(const ScanLevel &L, uint32_t k, uint64_t v) {
-    const uint64_t *rows = L.rows + static_cast<uint64_t>(k) * L.stride;
-    if (L.level0) return apply_map(rows, L.rs[k] ? low_mask(L.nx[k]) : v);
-    return L.isc[k] ? L.cv[k] : apply_map(rows, v);
+// Both directions of the join run in the same launches: blockIdx.y selects
+// the forward (0) or the backward (1) scan.
+struct ScanPair {
+    ScanLevel L[2];
+};
+struct ScanOut {
+    uint64_t *rows[2];          // next level
+    uint8_t *nx[2];
+    uint8_t *cst[2];
+    uint64_t *cv[2];
+    uint64_t *prow[2];          // prefix maps of this level's items within their group: [N][E]
+    uint8_t *pcst[2];
+    uint64_t *pcv[2];
+};
+struct ScanPrefix {
+    const uint64_t *prow[2];
+    const uint8_t *pcst[2];
+    const uint64_t *pcv[2];
+    const uint64_t *pvec[2];    // vectors entering the groups (nullptr: the empty mask)
+    uint64_t *vin[2];           // mask entering every item
+    uint64_t *vout[2];          // level 0: mask leaving every item
+};
+
+__device__ inline uint64_t map_apply(const uint64_t *rows, bool cst, uint64_t cv, uint64_t v) {
+    if (cst) return cv;
+    uint64_t r = 0;
+    while (v) {
+        const int m = __builtin_ctzll(v);
+        v &= v - 1;
+        r |= rows[m];
+    }
+    return r;
 }
 
-__device__ inline bool scan_const(const ScanLevel &L, uint32_t k) { return L.level0 ? L.rs[k] != 0 : L.isc[k] != 0; }
-
-// Compose groups of 64 consecutive items; one wavefront per group, lane m
-// follows entry m of the group's input list.
-__global__ __launch_bounds__(64) void k_compose(ScanLevel L, uint64_t *out_rows, uint8_t *out_isc, uint64_t *out_cv) {
-    const uint32_t g = blockIdx.x, m = threadIdx.x;
-    const uint32_t k0 = g * 64, k1 = min(k0 + 64, L.N);
-    // entries beyond the input list of a level-0 group have no row
-    uint64_t v = (L.level0 && m >= L.nx[k0]) ? 0 : 1ull << m;
+// Scan of one group of up to 64 items per wavefront: dynamic LDS holds two
+// buffers of 64 x E rows.
+__global__ __launch_bounds__(64) void k_compose(ScanPair S, ScanOut O, uint32_t E) {
+    extern __shared__ uint64_t mrows[];
+    __shared__ uint64_t mcv[2][64];
+    __shared__ uint8_t mcst[2][64];
+    const uint32_t d = blockIdx.y;
+    const ScanLevel L = d ? S.L[1] : S.L[0];
+    const uint32_t g = blockIdx.x, k = threadIdx.x;
+    const uint32_t k0 = g * 64, n = min(k0 + 64, L.N) - k0;
+    // stage the group's rows (contiguous in memory), 16 loads in flight per lane
+    const uint64_t *src = L.rows + static_cast<uint64_t>(k0) * E;
+    const uint32_t tot = n * E;
+    for (uint32_t e0 = 0; e0 < tot; e0 += 64 * 16) {
+        uint64_t tmp[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const uint32_t e = e0 + u * 64 + k;
+            tmp[u] = e < tot ? src[e] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const uint32_t e = e0 + u * 64 + k;
+            if (e < tot) mrows[e] = tmp[u];
+        }
+    }
+    const uint32_t nx0 = L.nx[k0];              // input list of the group
     bool cst = false;
-    for (uint32_t k = k0; k < k1; ++k) {
-        cst = cst || scan_const(L, k);
-        v = scan_apply(L, k, v);
+    uint64_t cv = 0;
+    uint32_t nxin = 0;                          // input-list size of the lane's composite
+    if (k < n) {
+        nxin = L.nx[k0 + k];
+        cst = L.cst[k0 + k] != 0;
+        if (L.level0) {
+            if (cst) {   // a text start: its image of the whole entry list
+                const uint64_t *r = src + static_cast<uint64_t>(k) * E;
+                for (uint32_t m = 0; m < nxin; ++m) cv |= r[m];
+            }
+        } else {
+            cv = L.cv[k0 + k];
+        }
     }
-    out_rows[static_cast<uint64_t>(g) * 64 + m] = v;
-    if (m == 0) {
-        out_isc[g] = cst ? 1 : 0;
-        out_cv[g] = v;
+    mcst[0][k] = cst ? 1 : 0;
+    mcv[0][k] = cv;
+    __syncthreads();
+    // inclusive scan: lane k's map becomes (map_k after map_{k-dd}); after the
+    // last round it is the composite of items 0..k of the group
+    int cur = 0;
+    for (uint32_t dd = 1; dd < 64; dd <<= 1) {
+        const int nxt = cur ^ 1;
+        uint64_t *mine = mrows + (nxt * 64 + k) * E;
+        const uint64_t *self = mrows + (cur * 64 + k) * E;
+        bool hc = mcst[cur][k] != 0;
+        uint64_t hv = mcv[cur][k];
+        const uint32_t nxa = __shfl_up(static_cast<int>(nxin), dd);
+        if (k >= dd && k < n) {
+            const uint32_t a = k - dd;
+            const uint64_t *arow = mrows + (cur * 64 + a) * E;
+            if (!hc) {
+                if (mcst[cur][a]) {
+                    hv = map_apply(self, false, 0, mcv[cur][a]);
+                    hc = true;
+                } else {
+                    for (uint32_t m = 0; m < nxa; ++m) mine[m] = map_apply(self, false, 0, arow[m]);
+                }
+            }
+            nxin = nxa;
+        } else if (!hc) {
+            for (uint32_t m = 0; m < nxin; ++m) mine[m] = self[m];
+        }
+        mcst[nxt][k] = hc ? 1 : 0;
+        mcv[nxt][k] = hv;
+        __syncthreads();
+        cur = nxt;
+    }
+    // prefix maps of this level, coalesced from LDS
+    const uint64_t *fin = mrows + cur * 64 * E;
+    uint64_t *pdst = O.prow[d] + static_cast<uint64_t>(k0) * E;
+    for (uint32_t e = k; e < tot; e += 64) pdst[e] = fin[e];
+    if (k < n) {
+        O.pcst[d][k0 + k] = mcst[cur][k];
+        O.pcv[d][k0 + k] = mcv[cur][k];
+    }
+    // the group's composite is the next level's item g
+    if (k < nx0) O.rows[d][static_cast<uint64_t>(g) * E + k] = fin[(n - 1) * E + k];
+    if (k == 0) {
+        O.nx[d][g] = static_cast<uint8_t>(nx0);
+        O.cst[d][g] = mcst[cur][n - 1];
+        O.cv[d][g] = mcv[cur][n - 1];
     }
 }
 
-// Sequential scan over the top level (at most 64 items): vec[k] = mask entering item k.
-__global__ void k_scan_top(ScanLevel L, uint64_t *vec) {
-    if (threadIdx.x || blockIdx.x) return;
-    uint64_t v = 0;
-    for (uint32_t k = 0; k < L.N; ++k) {
-        vec[k] = v;
-        v = scan_apply(L, k, v);
-    }
-    vec[L.N] = v;
-}
-
-// Expand parent vectors one level down (levels >= 1): one thread per parent.
-__global__ __launch_bounds__(64) void k_expand(ScanLevel L, const uint64_t *pvec, uint32_t NP, uint64_t *vec) {
-    const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= NP) return;
-    uint64_t v = pvec[p];
-    const uint32_t k0 = p * 64, k1 = min(k0 + 64, L.N);
-    for (uint32_t k = k0; k < k1; ++k) {
-        vec[k] = v;
-        v = scan_apply(L, k, v);
-    }
-}
-
-// Level 0: the masks at both edges of every item.  pvec == nullptr: the whole
-// level is scanned by one thread.
-__global__ __launch_bounds__(64) void k_expand0(ScanLevel L, const uint64_t *pvec, uint32_t NP, uint64_t *vin,
-                                                uint64_t *vout) {
-    const uint32_t p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= NP) return;
-    uint64_t v = pvec ? pvec[p] : 0;
-    const uint32_t k0 = pvec ? p * 64 : 0, k1 = pvec ? min(k0 + 64, L.N) : L.N;
-    for (uint32_t k = k0; k < k1; ++k) {
-        const uint64_t in = L.rs[k] ? low_mask(L.nx[k]) : v;
-        vin[k] = in;
-        v = apply_map(L.rows + static_cast<uint64_t>(k) * L.stride, in);
-        vout[k] = v;
-    }
+// Expand one level: thread k (lanes = items of its group) applies its prefix
+// map to the vector entering its group.  Level 0 (L.level0) also writes the
+// mask leaving every item; a text start enters with its whole entry list.
+__global__ __launch_bounds__(256) void k_expand(ScanPair S, ScanPrefix P, uint32_t E) {
+    const uint32_t d = blockIdx.y;
+    const ScanLevel L = d ? S.L[1] : S.L[0];
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t g = k >> 6;
+    const bool act = k < L.N;
+    uint64_t vp = 0;
+    if (act && P.pvec[d]) vp = P.pvec[d][g];
+    uint64_t out = 0;
+    if (act)
+        out = map_apply(P.prow[d] + static_cast<uint64_t>(k) * E, P.pcst[d][k] != 0, P.pcv[d][k], vp);
+    const uint64_t prev = shfl_up_u64(out, 1);
+    if (!act) return;
+    uint64_t in = lane == 0 ? vp : prev;
+    if (L.level0 && L.cst[k]) in = low_mask(L.nx[k]);
+    P.vin[d][k] = in;
+    if (L.level0) P.vout[d][k] = out;
 }
 
 // Join sets and build start ids.  Thread i handles chunk i: fid_i = id of

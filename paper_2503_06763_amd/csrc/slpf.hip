@@ -154,10 +154,11 @@ struct Layout {
     }
 };
 
-// join level sizes: N_0 = c, N_{L+1} = ceil(N_L / 64) until <= 64
+// join level sizes: N_0 = c, N_{l+1} = ceil(N_l / 64) down to a level of one item
 std::vector<uint32_t> join_levels(uint32_t c) {
     std::vector<uint32_t> lv{c};
-    while (lv.back() > 64) lv.push_back((lv.back() + 63) / 64);
+    do lv.push_back((lv.back() + 63) / 64);
+    while (lv.back() > 1);
     return lv;
 }
 
@@ -333,13 +334,21 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
     int ifid = L.add(size_t(c) * 2), irid = L.add(size_t(c) * 2);
     int ickpt = L.add(nck * 2), ibckpt = L.add(nck * 2);
     int iflags = L.add(16);
-    std::vector<int> jrows[2], jisc[2], jcv[2], jvec[2];
-    for (size_t l = 1; l < jl.size(); ++l)
+    // join levels: items of level l >= 1 (rows, nx, cst, cv, entering vectors)
+    // and prefix maps of every level below the top
+    const size_t TL = jl.size() - 1;
+    std::vector<int> jrows[2], jnx[2], jisc[2], jcv[2], jvec[2], jprow[2], jpcst[2], jpcv[2];
+    for (size_t l = 0; l <= TL; ++l)
         for (int d = 0; d < 2; ++d) {
-            jrows[d].push_back(L.add(size_t(jl[l]) * 64 * 8));
-            jisc[d].push_back(L.add(jl[l] + 1));
-            jcv[d].push_back(L.add(size_t(jl[l] + 1) * 8));
-            jvec[d].push_back(L.add(size_t(jl[l] + 1) * 8));
+            const size_t N = jl[l];
+            jrows[d].push_back(l ? L.add(N * E * 8) : -1);
+            jnx[d].push_back(l ? L.add(N + 1) : -1);
+            jisc[d].push_back(l ? L.add(N + 1) : -1);
+            jcv[d].push_back(l ? L.add((N + 1) * 8) : -1);
+            jvec[d].push_back(l ? L.add((N + 1) * 8) : -1);
+            jprow[d].push_back(l < TL ? L.add(N * E * 8) : -1);
+            jpcst[d].push_back(l < TL ? L.add(N + 1) : -1);
+            jpcv[d].push_back(l < TL ? L.add((N + 1) * 8) : -1);
         }
     int idims = -1, iuv = -1, ipi = -1, ifac = -1, itidx = -1, itbig = -1, iovf = -1;
     if (count) {
@@ -456,46 +465,58 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
     }
     mark(1);
     if (c) {
-        // join: segmented scans, forward (text order) and backward (reversed)
-        for (int d = 0; d < 2; ++d) {
-            std::vector<ScanLevel> lv;
-            ScanLevel l0{};
-            l0.rows = d == 0 ? jb.Mf : jb.MbR;
-            l0.stride = E;
-            l0.N = c;
-            l0.nx = d == 0 ? jb.nxf : jb.nxb;
-            l0.rs = d == 0 ? jb.rsf : jb.rsb;
-            l0.level0 = 1;
-            lv.push_back(l0);
-            std::vector<uint64_t *> vec{nullptr};
-            for (size_t l = 1; l < jl.size(); ++l) {
-                uint64_t *rows = reinterpret_cast<uint64_t *>(ptr(jrows[d][l - 1]));
-                uint8_t *isc = ptr(jisc[d][l - 1]);
-                uint64_t *cv = reinterpret_cast<uint64_t *>(ptr(jcv[d][l - 1]));
-                hipLaunchKernelGGL(k_compose, dim3(jl[l]), dim3(64), 0, stream, lv.back(), rows, isc, cv);
-                ScanLevel nl{};
-                nl.rows = rows;
-                nl.stride = 64;
-                nl.N = jl[l];
-                nl.isc = isc;
-                nl.cv = cv;
-                nl.level0 = 0;
-                lv.push_back(nl);
-                vec.push_back(reinterpret_cast<uint64_t *>(ptr(jvec[d][l - 1])));
+        // join: segmented scans, forward (text order) and backward (reversed),
+        // both directions in each launch; up the levels composing groups of
+        // 64 items, then down applying the prefix maps
+        auto u64p = [&](int k) { return reinterpret_cast<uint64_t *>(ptr(k)); };
+        std::vector<ScanPair> lv(TL + 1);
+        for (size_t l = 0; l <= TL; ++l)
+            for (int d = 0; d < 2; ++d) {
+                ScanLevel &x = lv[l].L[d];
+                x.N = jl[l];
+                x.level0 = l == 0;
+                if (l == 0) {
+                    x.rows = d == 0 ? jb.Mf : jb.MbR;
+                    x.nx = d == 0 ? jb.nxf : jb.nxb;
+                    x.cst = d == 0 ? jb.rsf : jb.rsb;
+                    x.cv = nullptr;
+                } else {
+                    x.rows = u64p(jrows[d][l]);
+                    x.nx = ptr(jnx[d][l]);
+                    x.cst = ptr(jisc[d][l]);
+                    x.cv = u64p(jcv[d][l]);
+                }
             }
-            uint64_t *vin = d == 0 ? jb.fin : jb.bin, *vout = d == 0 ? jb.fout : jb.bout;
-            const size_t top = lv.size() - 1;
-            if (top == 0) {
-                hipLaunchKernelGGL(k_expand0, dim3(1), dim3(64), 0, stream, lv[0], static_cast<const uint64_t *>(nullptr),
-                                   1u, vin, vout);
-            } else {
-                hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1), 0, stream, lv[top], vec[top]);
-                for (size_t l = top; l-- > 1;)
-                    hipLaunchKernelGGL(k_expand, dim3((jl[l + 1] + 63) / 64), dim3(64), 0, stream, lv[l],
-                                       static_cast<const uint64_t *>(vec[l + 1]), jl[l + 1], vec[l]);
-                hipLaunchKernelGGL(k_expand0, dim3((jl[1] + 63) / 64), dim3(64), 0, stream, lv[0],
-                                   static_cast<const uint64_t *>(vec[1]), jl[1], vin, vout);
+        const size_t grp_lds = size_t(2) * 64 * E * 8;
+        for (size_t l = 0; l < TL; ++l) {
+            ScanOut o{};
+            for (int d = 0; d < 2; ++d) {
+                o.rows[d] = u64p(jrows[d][l + 1]);
+                o.nx[d] = ptr(jnx[d][l + 1]);
+                o.cst[d] = ptr(jisc[d][l + 1]);
+                o.cv[d] = u64p(jcv[d][l + 1]);
+                o.prow[d] = u64p(jprow[d][l]);
+                o.pcst[d] = ptr(jpcst[d][l]);
+                o.pcv[d] = u64p(jpcv[d][l]);
             }
+            hipLaunchKernelGGL(k_compose, dim3(jl[l + 1], 2), dim3(64), grp_lds, stream, lv[l], o, E);
+        }
+        for (size_t l = TL; l-- > 0;) {
+            ScanPrefix pf{};
+            for (int d = 0; d < 2; ++d) {
+                pf.prow[d] = u64p(jprow[d][l]);
+                pf.pcst[d] = ptr(jpcst[d][l]);
+                pf.pcv[d] = u64p(jpcv[d][l]);
+                pf.pvec[d] = l + 1 < TL ? u64p(jvec[d][l + 1]) : nullptr;
+                if (l == 0) {
+                    pf.vin[d] = d == 0 ? jb.fin : jb.bin;
+                    pf.vout[d] = d == 0 ? jb.fout : jb.bout;
+                } else {
+                    pf.vin[d] = u64p(jvec[d][l]);
+                    pf.vout[d] = nullptr;
+                }
+            }
+            hipLaunchKernelGGL(k_expand, dim3((jl[l] + 255) / 256, 2), dim3(256), 0, stream, lv[l], pf, E);
         }
     }
     mark(2);
