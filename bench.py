@@ -27,6 +27,7 @@ METRIC = "parsed GB/s per GPU + % HBM roofline, bit-exact SLPF; p50/p99 latency 
 HBM_PEAK_GBS = 8000.0
 RE_SEED, TEXT_SEED, CORRUPT_SEED = 23, 23, 24
 TEXT_BYTES = 1 << 28
+BATCH_RE_SEED, BATCH_LEN_SEED, BATCH_TEXT_SEED = 4000, 4001, 4002
 KERNEL_SOURCES = ["paper_2503_06763_amd/csrc/kernels.hpp", "paper_2503_06763_amd/csrc/slpf.hip"]
 
 
@@ -98,6 +99,167 @@ def cpu_baseline(pat, text_np, sample_bytes):
                       "with in-place intersection and tree count, single thread, %.1f s" % (len(x), dt)}
 
 
+def _aligned_offsets(sizes, align):
+    offs, tot = [], 0
+    for z in sizes:
+        offs.append(tot)
+        tot += (int(z) + align - 1) // align * align
+    return offs, max(tot, align)
+
+
+def oracle_pool_baseline(jobs, seconds_hint):
+    """The oracle over host cores: one text per task on a process pool; jobs
+    is a list of (pattern, bytes)."""
+    import concurrent.futures as cf
+    cores = min(16, os.cpu_count() or 1)
+    t0 = time.perf_counter()
+    with cf.ProcessPoolExecutor(max_workers=cores) as ex:
+        list(ex.map(_oracle_task, jobs, chunksize=1))
+    dt = time.perf_counter() - t0
+    nb = sum(len(x) for _, x in jobs)
+    return {"value": round(nb / dt / 1e9, 6), "unit": "GB/s", "cores": cores, "kind": "oracle",
+            "sample": "%d texts, %d bytes, serial oracle parser (Fig. serialparser) with tree count, one "
+                      "text per process on %d processes, %.1f s" % (len(jobs), nb, cores, dt)}
+
+
+_ORACLES = {}
+
+
+def _oracle_task(job):
+    from oracle.oracle import Oracle
+    pat, x = job
+    o = _ORACLES.get(pat)
+    if o is None:
+        o = _ORACLES[pat] = Oracle(pat)
+    o.parse(x)
+    return len(x)
+
+
+def run_batched(args):
+    """Many REs and texts: 16 REs, 4096 texts of log-uniform length; per-text
+    plain parses vs one batched job per RE (autotuned chunk size and table
+    placement, jobs spread over streams).  Both results are compared."""
+    import numpy as np
+    import torch
+    import paper_2503_06763_amd as S
+    from gen import regen, workloads as wl
+
+    def fits(re):
+        try:
+            S.Parser(re, host_only=True)
+            return True
+        except S.SlpfError:
+            return False
+    t0 = time.perf_counter()
+    res = wl.batched_res(fits, seed=BATCH_RE_SEED)
+    lengths = wl.loguniform_lengths(BATCH_LEN_SEED, args.texts)
+    texts = wl.texts_for(res, lengths, BATCH_TEXT_SEED)
+    gen_s = time.perf_counter() - t0
+    pats = [regen.to_re(t) for _, t in res]
+    parsers = [S.Parser(pt) for pt in pats]
+    dev = torch.device("cuda:0")
+    ns = [int(x.size) for _, x in texts]
+    Ws = [parsers[r].W for r, _ in texts]
+    toffs, ttot = _aligned_offsets(ns, 256)
+    tbuf = torch.empty(ttot, dtype=torch.uint8, device=dev)
+    host = np.zeros(ttot, np.uint8)
+    for (r, x), o in zip(texts, toffs):
+        host[o:o + x.size] = x
+    tbuf.copy_(torch.from_numpy(host))
+    del host
+    coffs, ctot = _aligned_offsets([(n + 1) * w for n, w in zip(ns, Ws)], 32)
+    outs = []
+    for _ in range(2):
+        cbig = torch.zeros(ctot, dtype=torch.int64, device=dev)
+        sc = torch.zeros((len(texts), 3), dtype=torch.int64, device=dev)
+        items = [(tbuf[o:o + n], n, cbig[c:c + (n + 1) * w], sc[k])
+                 for k, (o, n, c, w) in enumerate(zip(toffs, ns, coffs, Ws))]
+        outs.append((cbig, sc, items))
+    torch.cuda.synchronize()
+    total = sum(ns)
+    algo = sum(n + (n + 1) * 8 * w for n, w in zip(ns, Ws))
+    print("batched workload: %d REs, %d texts, %d bytes (algorithmic %d), gen %.1fs" % (
+        len(res), len(texts), total, algo, gen_s), file=sys.stderr, flush=True)
+
+    # plain: one slpf_parse per text, in workload order, one stream
+    _, _, items_p = outs[0]
+
+    def plain_pass():
+        for (r, _), it in zip(texts, items_p):
+            parsers[r].parse_into(it[0], it[1], it[2], it[3])
+    plain_pass()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plain_pass()
+    torch.cuda.synchronize()
+    plain_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+
+    # batched: one job per RE, autotuned, over several streams
+    _, _, items_b = outs[1]
+    groups = [[k for k, (r, _) in enumerate(texts) if r == q] for q in range(len(res))]
+    tuned, arrays = [], []
+    for q, g in enumerate(groups):
+        its = [items_b[k] for k in g]
+        if not its:
+            tuned.append(None)
+            arrays.append(None)
+            continue
+        tuned.append(parsers[q].tune(its))
+        arrays.append(parsers[q]._text_array(its))
+    streams = [torch.cuda.Stream(device=dev) for _ in range(args.streams)]
+    torch.cuda.synchronize()
+
+    def batched_pass():
+        for q, arr in enumerate(arrays):
+            if arr is None:
+                continue
+            st = streams[q % len(streams)]
+            parsers[q].parse_batch_prepared(arr, len(groups[q]), tuned[q][0], tuned[q][1], st)
+    batched_pass()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        batched_pass()
+    torch.cuda.synchronize()
+    batch_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    same = bool(torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1]))
+    sc = outs[1][1].cpu().numpy().view(np.uint64)
+    print("plain %.3f ms, batched %.3f ms, identical %s" % (plain_ms, batch_ms, same), file=sys.stderr,
+          flush=True)
+    gbs = total / (batch_ms * 1e-3) / 1e9
+    out = {
+        "metric": METRIC, "value": round(gbs, 3), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": 1, "ms_per_step": round(batch_ms, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "batched: %d seeded random REs (depth 4-8; alphabets of 4, 26 and 128 "
+                               "symbols) and the motif RE, %d texts of log-uniform length 1 KiB-4 MiB "
+                               "sampled from their REs, one job per RE, jobs over %d streams" % (
+                                   len(res) - 1, len(texts), len(streams)),
+                   "texts": len(texts), "text_bytes": total, "algorithmic_bytes": algo,
+                   "tuned": {res[q][0]: {"chunk_bytes": t[0], "placement": "l2" if t[1] & S.PARSE_FORCE_L2
+                                         else "lds", "ms": round(t[2], 3)}
+                             for q, t in enumerate(tuned) if t},
+                   "accepted": int(sc[:, 0].sum()), "count_ok": int((sc[:, 2] == 0).sum())},
+        "plain_per_text": {"value": round(total / (plain_ms * 1e-3) / 1e9, 3), "ms_per_step": round(plain_ms, 4)},
+        "speedup_vs_plain": round(plain_ms / batch_ms, 3),
+        "identical_to_plain": same,
+        "roofline": {"bound": "hbm", "achieved": round(algo / (batch_ms * 1e-3) / 1e9, 2), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(algo / (batch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "traffic": None, "kernel": "whole job (all kernels of all jobs)",
+                     "algorithmic_bytes": algo},
+    }
+    if not args.no_cpu_baseline:
+        jobs, acc = [], 0
+        for r, x in texts:
+            if acc + x.size > args.cpu_sample:
+                continue
+            jobs.append((pats[r], x.tobytes()))
+            acc += x.size
+        out["cpu_baseline"] = oracle_pool_baseline(jobs, 0)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -108,6 +270,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=32 << 20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-companion", action="store_true")
+    ap.add_argument("--workload", choices=["single", "batched"], default="single")
+    ap.add_argument("--texts", type=int, default=4096, help="batched: number of texts")
+    ap.add_argument("--streams", type=int, default=4, help="batched: streams the per-RE jobs are spread over")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="after timing, copy this many bytes device-to-device (scale reference for HBM counters)")
     args = ap.parse_args()
@@ -119,6 +284,10 @@ def main():
     import paper_2503_06763_amd as S
     S.lib()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.workload == "batched":
+        if args.steps == 10:
+            args.steps = 3
+        return run_batched(args)
 
     t0 = time.perf_counter()
     pat, text = make_text(args.bytes, corrupt=True)

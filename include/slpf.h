@@ -232,6 +232,19 @@ typedef struct {
 slpf_status slpf_parse_batch(const slpf_parser *p, const slpf_text *items, size_t count,
                              const slpf_parse_opts *opts, void *hip_stream);
 
+/*
+ * Autotuner: time one batched parse of `items` (after one untimed run) for
+ * every lane-chunk size in {256, 512, 1024, 2048, 4096} bytes and, when the
+ * tables fit in LDS, both table placements (LDS and L2), and return the
+ * fastest in best->chunk_bytes and best->flags (`flags` plus
+ * SLPF_PARSE_FORCE_L2 when that placement won); *best_ms (may be NULL)
+ * receives its time.  best->struct_size must be set; its other fields are
+ * overwritten.  The items' outputs hold a complete parse on return (every
+ * candidate computes the same result).  Synchronizes the stream.
+ */
+slpf_status slpf_tune(const slpf_parser *p, const slpf_text *items, size_t count, uint32_t flags,
+                      slpf_parse_opts *best, float *best_ms, void *hip_stream);
+
 /* Number of lane chunks a parse of n bytes uses with the given options. */
 uint64_t slpf_num_chunks(const slpf_parser *p, uint64_t n, const slpf_parse_opts *opts);
 

@@ -27,8 +27,8 @@ PARSE_NO_COUNT = 1
 PARSE_FORCE_L2 = 2
 
 EXPORTS = ["slpf_compile", "slpf_parser_destroy", "slpf_parser_info_get", "slpf_segment_text",
-           "slpf_table_dump", "slpf_forest_bytes", "slpf_parse", "slpf_parse_batch", "slpf_num_chunks",
-           "slpf_status_str"]
+           "slpf_table_dump", "slpf_forest_bytes", "slpf_parse", "slpf_parse_batch", "slpf_tune",
+           "slpf_num_chunks", "slpf_status_str"]
 
 
 class SlpfError(RuntimeError):
@@ -104,6 +104,9 @@ def lib(path: str = LIB_PATH):
     L.slpf_parse.restype = ctypes.c_int
     L.slpf_parse_batch.argtypes = [vp, ctypes.POINTER(Text), sz, ctypes.POINTER(ParseOpts), vp]
     L.slpf_parse_batch.restype = ctypes.c_int
+    L.slpf_tune.argtypes = [vp, ctypes.POINTER(Text), sz, ctypes.c_uint32, ctypes.POINTER(ParseOpts),
+                            ctypes.POINTER(ctypes.c_float), vp]
+    L.slpf_tune.restype = ctypes.c_int
     L.slpf_num_chunks.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ParseOpts)]
     L.slpf_num_chunks.restype = ctypes.c_uint64
     L.slpf_status_str.argtypes = [ctypes.c_int]
@@ -261,12 +264,37 @@ class Parser:
         o = ParseOpts(ctypes.sizeof(ParseOpts), chunk_bytes, flags, 0, None, 0,
                       ctypes.cast(ev, ctypes.POINTER(ctypes.c_void_p)) if ev is not None else None,
                       len(events) if events is not None else 0, 0)
+        arr = self._text_array(items)
+        st = self._L.slpf_parse_batch(self._h, arr, len(items), ctypes.byref(o), ctypes.c_void_p(stream.cuda_stream))
+        _check(st, "slpf_parse_batch")
+
+    def _text_array(self, items):
         arr = (Text * len(items))()
         for k, (t, n, cols, sc) in enumerate(items):
             arr[k].text_dev = t.data_ptr() if (t is not None and n) else None
             arr[k].n = n
             arr[k].out = Forest(cols.data_ptr(), cols.numel() * cols.element_size(), sc.data_ptr())
-        st = self._L.slpf_parse_batch(self._h, arr, len(items), ctypes.byref(o), ctypes.c_void_p(stream.cuda_stream))
+        return arr
+
+    def tune(self, items, count: bool = True, stream=None):
+        """slpf_tune over ``items`` (as for parse_batch_into); returns
+        (chunk_bytes, flags, ms).  The items' outputs hold a complete parse."""
+        import torch
+        if stream is None:
+            dev = next((t.device for t, _, _, _ in items if t is not None), torch.device("cuda", self.device))
+            stream = torch.cuda.current_stream(dev)
+        o = ParseOpts(ctypes.sizeof(ParseOpts), 0, 0, 0, None, 0, None, 0, 0)
+        ms = ctypes.c_float(0)
+        arr = self._text_array(items)
+        st = self._L.slpf_tune(self._h, arr, len(items), 0 if count else PARSE_NO_COUNT, ctypes.byref(o),
+                               ctypes.byref(ms), ctypes.c_void_p(stream.cuda_stream))
+        _check(st, "slpf_tune")
+        return int(o.chunk_bytes), int(o.flags), float(ms.value)
+
+    def parse_batch_prepared(self, arr, count: int, chunk_bytes: int, flags: int, stream):
+        """slpf_parse_batch on an array made by _text_array (no per-call marshalling)."""
+        o = ParseOpts(ctypes.sizeof(ParseOpts), chunk_bytes, flags, 0, None, 0, None, 0, 0)
+        st = self._L.slpf_parse_batch(self._h, arr, count, ctypes.byref(o), ctypes.c_void_p(stream.cuda_stream))
         _check(st, "slpf_parse_batch")
 
     def parse_batch(self, texts, chunk_bytes: int = 0, count: bool = True, force_l2: bool = False,

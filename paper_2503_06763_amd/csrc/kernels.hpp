@@ -57,6 +57,8 @@ struct Tabs {
     const uint32_t *fhash;
     const uint32_t *rhash;
     const uint64_t *folseg;     // nseg x W
+    const uint16_t *fsole;      // per forward state: its only segment, or kNoSole
+    const uint16_t *rsole;      // per backward state
     uint32_t fhmask, rhmask;
     uint32_t C, W, NL;          // classes, words, C + 1
     uint32_t nf, nr;            // table sizes including id 0
@@ -923,7 +925,28 @@ __device__ inline uint32_t wave_min(uint32_t v) {
     return v;
 }
 
-constexpr int kCountThreads = 256;
+constexpr int kCountThreads = 512;
+constexpr int kQuarter = 16;                                // columns staged per row fill
+constexpr int kCountRow = kQuarter + 1;                     // padded per-lane row of 16 columns
+constexpr int kCountSegWords = kVec;                        // two lists of kVec u16 segment ids
+constexpr int kCountLaneBytes = (kCountRow + kCountSegWords) * 4;
+constexpr int kCountLdsBytes = kCountThreads * kCountLaneBytes;
+
+// LDS offsets of the count kernel's staged tables after the per-lane areas:
+// class map and transition tables, then the sole-segment tables, then (FULL)
+// the state bit sets and the follower sets.
+struct CountLds {
+    uint32_t tab, sole, bits, fol, end;
+};
+__host__ __device__ inline CountLds count_lds(uint32_t nf, uint32_t nr, uint32_t C, uint32_t W, uint32_t nseg) {
+    CountLds o;
+    o.tab = kCountLdsBytes;
+    o.sole = o.tab + ((512 + (nf + nr) * C * 2 + 15) & ~15u);
+    o.bits = o.sole + (((nf + nr) * 2 + 15) & ~15u);
+    o.fol = o.bits + (nf + nr) * W * 8;
+    o.end = o.fol + nseg * W * 8;
+    return o;
+}
 
 // Fast tree count.  Paths through a singleton clean column all pass through
 // its one segment, so a chunk whose columns P_i .. P_{i+1}-1 include a
@@ -934,23 +957,57 @@ constexpr int kCountThreads = 256;
 //         (a backward vector DP that collapses at every singleton);
 //   u[q]  paths from the rightmost singleton r1 to the q-th segment of
 //         column P_{i+1} (a forward vector DP from r1).
-// Columns are recomputed from the build's window checkpoints, the window's
-// ids held in registers and indexed by the wavefront-uniform loop counter.
-// Loop bounds of the vector steps are wavefront maxima, so a lane with an
-// ambiguous column costs only its own column sizes.  Chunks with no singleton
-// or with a column above kVec segments go to the general kernel.
-template <bool TAB_LDS, bool BITS_LDS, bool FOL_LDS>
+// A clean column of an accepted text is non-empty and inside both of its
+// state sets, so it is the only segment of either state when that state's set
+// has one (the sole-segment tables); only columns where both sets hold
+// several segments are listed from the bit sets.  Between a singleton and any
+// column every arc exists (each segment of a clean column has a neighbour in
+// the next and in the previous one), so the follower relation is read only
+// between two ambiguous columns.  Per 64-byte window the forward ids come
+// from the build's checkpoint and the backward ids from its backward
+// checkpoint; each half window's (forward, backward) id pairs go to the
+// lane's LDS row, which the DP then walks.  Segment lists of the current and
+// the previous column live in the lane's LDS too, so the vector state in
+// registers is only the path counts.  Chunks with no singleton or with a
+// column above kVec segments go to the general kernel.
+template <bool TAB_LDS, bool FULL>
 __global__ __launch_bounds__(kCountThreads) void k_count_fast(Tabs tb, Job jb) {
     extern __shared__ __align__(16) uint8_t smem[];
     if (jb.ntexts == 1 && text_ref(jb, 0).scalars[0] == 0) return;    // rejected text: no tree
     const uint32_t C = tb.C, W = tb.W;
-    const uint32_t fol_bytes = FOL_LDS ? ((tb.nseg * W * 8 + 15) & ~15u) : 0;
-    if constexpr (FOL_LDS) {
-        uint64_t *fl = reinterpret_cast<uint64_t *>(smem);
-        for (uint32_t k = threadIdx.x; k < tb.nseg * W; k += blockDim.x) fl[k] = tb.folseg[k];
+    uint32_t *row = reinterpret_cast<uint32_t *>(smem) + threadIdx.x * kCountRow;
+    uint16_t *segl = reinterpret_cast<uint16_t *>(smem + kCountThreads * kCountRow * 4) + threadIdx.x * 2 * kVec;
+    // transition tables and sole-segment tables (and with FULL the bit sets
+    // and follower sets) staged in LDS
+    const uint16_t *cls, *fd, *rd, *fso, *rso;
+    const uint64_t *fbits = tb.fbits, *rbits = tb.rbits, *fol = tb.folseg;
+    if constexpr (TAB_LDS) {
+        const CountLds o = count_lds(tb.nf, tb.nr, C, W, tb.nseg);
+        uint16_t *c16 = reinterpret_cast<uint16_t *>(smem + o.tab);
+        uint16_t *f16 = c16 + 256, *r16 = f16 + tb.nf * C;
+        uint16_t *fs16 = reinterpret_cast<uint16_t *>(smem + o.sole);
+        uint16_t *rs16 = fs16 + tb.nf;
+        for (uint32_t k = threadIdx.x; k < 256; k += blockDim.x) c16[k] = tb.classmap[k];
+        for (uint32_t k = threadIdx.x; k < tb.nf * C; k += blockDim.x) f16[k] = tb.fdelta[k];
+        for (uint32_t k = threadIdx.x; k < tb.nr * C; k += blockDim.x) r16[k] = tb.rdelta[k];
+        for (uint32_t k = threadIdx.x; k < tb.nf; k += blockDim.x) fs16[k] = tb.fsole[k];
+        for (uint32_t k = threadIdx.x; k < tb.nr; k += blockDim.x) rs16[k] = tb.rsole[k];
+        if constexpr (FULL) {
+            uint64_t *fb64 = reinterpret_cast<uint64_t *>(smem + o.bits), *rb64 = fb64 + tb.nf * W;
+            uint64_t *fl64 = reinterpret_cast<uint64_t *>(smem + o.fol);
+            for (uint32_t k = threadIdx.x; k < tb.nf * W; k += blockDim.x) fb64[k] = tb.fbits[k];
+            for (uint32_t k = threadIdx.x; k < tb.nr * W; k += blockDim.x) rb64[k] = tb.rbits[k];
+            for (uint32_t k = threadIdx.x; k < tb.nseg * W; k += blockDim.x) fl64[k] = tb.folseg[k];
+            fbits = fb64, rbits = rb64, fol = fl64;
+        }
+        __syncthreads();
+        cls = c16, fd = f16, rd = r16, fso = fs16, rso = rs16;
+    } else {
+        cls = tb.classmap, fd = tb.fdelta, rd = tb.rdelta, fso = tb.fsole, rso = tb.rsole;
     }
-    const BuildTabs<TAB_LDS, BITS_LDS> T = stage_build<TAB_LDS, BITS_LDS>(tb, smem, fol_bytes);
-    const uint64_t *fol = FOL_LDS ? reinterpret_cast<const uint64_t *>(smem) : tb.folseg;
+    struct ClsTab {
+        const uint16_t *cls;
+    } ct{cls};
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t wave_first = blockIdx.x * blockDim.x + (threadIdx.x & ~63u);
     if (wave_first >= jb.c) return;
@@ -969,45 +1026,118 @@ __global__ __launch_bounds__(kCountThreads) void k_count_fast(Tabs tb, Job jb) {
         nwin = static_cast<uint32_t>((hi - lo + 63) / 64);
     }
     const uint32_t nwin_wave = wave_max_u32(nwin);
-    uint32_t xw[16], cw[16], fwv[64];
-    uint64_t y[kVec], z[kVec];
-    uint32_t prev[kVec], cur[kVec];
+    uint32_t xw[16], cw[16], fwp[32];            // window bytes, classes, forward ids (two per word)
+    uint64_t y[kVec];                            // path counts over the previous column's segments
 #pragma unroll
-    for (int k = 0; k < kVec; ++k) y[k] = 0, prev[k] = 0, cur[k] = 0;
-    uint32_t mp = 0, seg_r1 = 0;
+    for (int k = 0; k < kVec; ++k) y[k] = 0;
+    uint32_t mp = 0, cb = 0;                     // previous column size; list buffer of the next column
     uint64_t pi = 1, r1 = 0;
     bool found = false, over = !act;
 
-    // one vector step between neighbouring clean columns, uniform loop bounds;
-    // fwd: x over the left column (prev) -> right column (cur); else the reverse
-    auto vstep = [&](bool need, uint32_t m, bool fwd, bool collapse) {
-        const uint32_t mw = wave_max_small(need ? m : 0), mpw = wave_max_small(need ? mp : 0);
-#pragma unroll
-        for (int k = 0; k < kVec; ++k) z[k] = 0;
-#pragma unroll
-        for (int k = 0; k < kVec; ++k) {
-            if (k < static_cast<int>(mw)) {
-#pragma unroll
-                for (int j = 0; j < kVec; ++j) {
-                    if (j < static_cast<int>(mpw)) {
-                        if (need && k < static_cast<int>(m) && j < static_cast<int>(mp)) {
-                            const bool arc = (mp == 1) || (m == 1) ||
-                                             (fwd ? follows(fol, W, prev[j], cur[k]) : follows(fol, W, cur[k], prev[j]));
-                            if (arc) z[k] += y[j];
-                        }
+    // a staged column: (f | b << 16) for the state ids, or (s << 16) when the
+    // clean column is the single segment s (f = 0, the empty set, never
+    // labels a column of an accepted text)
+    auto entry = [&](uint32_t f, uint32_t b) -> uint32_t {
+        uint32_t s = fso[f];
+        if (s == kNoSole) s = rso[b];
+        return s != kNoSole ? (s << 16) : (f | (b << 16));
+    };
+    // number of segments of a staged column; an ambiguous column's segments go
+    // to list cb (only ambiguous columns need their list: a step from a
+    // singleton reaches every segment of the next column)
+    auto column = [&](bool live, uint32_t e) -> uint32_t {
+        const bool multi = live && (e & 0xffffu) != 0;
+        uint32_t m = live ? 1u : 0u;
+        if (__any(multi)) {
+            if (multi) {
+                uint16_t *lst = segl + cb * kVec;
+                const uint32_t f = e & 0xffffu, b = e >> 16;
+                m = 0;
+                for (uint32_t w = 0; w < W; ++w) {
+                    uint64_t v = fbits[f * W + w] & rbits[b * W + w];
+                    while (v) {
+                        if (m < static_cast<uint32_t>(kVec)) lst[m] = static_cast<uint16_t>(w * 64 + __builtin_ctzll(v));
+                        v &= v - 1;
+                        ++m;
                     }
                 }
             }
         }
-        if (need) {
-            if (collapse && m == 1) {
-                pi *= z[0];
-                z[0] = 1;
-            }
+        return m;
+    };
+    // one DP step onto the column in list cb (m segments) from the previous
+    // column (mp segments, list cb^1 when mp > 1); fwd: the previous column is
+    // the left one; collapse: multiply pi at singletons (backward pass).  Each
+    // case other than singleton-to-singleton sits behind a wavefront-uniform
+    // test, so a wavefront skips the cases none of its lanes needs.
+    auto step = [&](bool live, uint32_t m, bool fwd, bool collapse) {
+        const bool gen = live && m > 1 && mp > 1;
+        if (__any(gen)) {   // ambiguous to ambiguous: follower checks, uniform bounds over those lanes
+            const uint32_t mw = wave_max_small(gen ? m : 0), mpw = wave_max_small(gen ? mp : 0);
+            const uint16_t *lc = segl + cb * kVec, *lp = segl + (cb ^ 1u) * kVec;
+            uint64_t z[kVec];
 #pragma unroll
-            for (int k = 0; k < kVec; ++k) y[k] = z[k], prev[k] = cur[k];
+            for (int k = 0; k < kVec; ++k) z[k] = 0;
+#pragma unroll 1
+            for (uint32_t k = 0; k < mw; ++k) {
+                const bool on_k = gen && k < m;
+                const uint32_t sk = on_k ? lc[k] : 0u;
+                uint64_t acc = 0;
+#pragma unroll
+                for (int j = 0; j < kVec; ++j) {
+                    if (j < static_cast<int>(mpw) && on_k && j < static_cast<int>(mp)) {
+                        const uint32_t sj = lp[j];
+                        const bool arc = fwd ? follows(fol, W, sj, sk) : follows(fol, W, sk, sj);
+                        if (arc) acc += y[j];
+                    }
+                }
+#pragma unroll
+                for (int kk = 0; kk < kVec; ++kk)
+                    if (static_cast<uint32_t>(kk) == k) z[kk] = acc;
+            }
+            if (gen) {
+#pragma unroll
+                for (int k = 0; k < kVec; ++k) y[k] = z[k];
+            }
+        }
+        const bool sum = live && m == 1 && mp > 1;     // every segment of the previous column reaches the singleton
+        if (__any(sum)) {
+            if (sum) {
+                uint64_t t = 0;
+#pragma unroll
+                for (int j = 0; j < kVec; ++j) t += j < static_cast<int>(mp) ? y[j] : 0ull;
+                y[0] = t;
+            }
+        }
+        const bool bcast = live && m > 1 && mp == 1;   // the singleton reaches every segment of this column
+        if (__any(bcast)) {
+            if (bcast) {
+                const uint64_t y0 = y[0];
+#pragma unroll
+                for (int k = 0; k < kVec; ++k) y[k] = k < static_cast<int>(m) ? y0 : 0ull;
+            }
+        }
+        if (collapse && live && m == 1) {
+            pi *= y[0];
+            y[0] = 1;
+        }
+        if (live) {
+            if (m > 1) cb ^= 1u;         // this column's list becomes the previous one
             mp = m;
         }
+    };
+    // forward ids of window w (columns a0 .. a0+63) into fwp; returns the id after the window
+    auto forward_ids = [&](uint32_t w, uint32_t len) -> uint32_t {
+        uint32_t g = jb.ckpt[ck(jb, i, w)];
+#pragma unroll
+        for (int t = 0; t < 64; t += 2) {
+            uint32_t lo16 = g;
+            if (t < static_cast<int>(len)) g = fd[g * C + byte_of(cw, t)];
+            uint32_t hi16 = g;
+            if (t + 1 < static_cast<int>(len)) g = fd[g * C + byte_of(cw, t + 1)];
+            fwp[t >> 1] = lo16 | (hi16 << 16);
+        }
+        return g;
     };
 
     // backward over the chunk's columns hi-1 .. lo
@@ -1019,40 +1149,48 @@ __global__ __launch_bounds__(kCountThreads) void k_count_fast(Tabs tb, Job jb) {
             a0 = lo + 64ull * w;
             len = static_cast<uint32_t>(hi - a0 < 64 ? hi - a0 : 64);
             load_window(text, a0, len, xw);
-            window_classes(T, xw, cw);
-            uint32_t g = jb.ckpt[ck(jb, i, w)];
-#pragma unroll
-            for (int t = 0; t < 64; ++t) {
-                fwv[t] = g;
-                if (t < static_cast<int>(len)) g = T.fd[g * C + byte_of(cw, t)];
-            }
+            window_classes(ct, xw, cw);
+            forward_ids(w, len);
             b = jb.bckpt[ck(jb, i, w)];
         }
-        for (int t = 63; t >= 0; --t) {
-            bool live = on && !over && t < static_cast<int>(len);
-            uint32_t m = 0;
-            if (live) {
-                b = T.rd[b * C + byte_of(cw, t)];
-                m = list_clean(T, W, fwv[t], b, cur);
-                if (m > static_cast<uint32_t>(kVec) || m == 0) {
+#pragma unroll 1
+        for (int q = 3; q >= 0; --q) {
+            // backward ids of the quarter, with the forward ids, into the lane's row
+            // (q selects between static register indices: no indexed registers)
+            if (on) {
+#pragma unroll
+                for (int u = kQuarter - 1; u >= 0; --u) {
+                    const int t = q * kQuarter + u;
+                    const uint32_t cwd = q == 3 ? cw[12 + (u >> 2)] : q == 2 ? cw[8 + (u >> 2)]
+                                       : q == 1 ? cw[4 + (u >> 2)] : cw[u >> 2];
+                    const uint32_t fpr = q == 3 ? fwp[24 + (u >> 1)] : q == 2 ? fwp[16 + (u >> 1)]
+                                       : q == 1 ? fwp[8 + (u >> 1)] : fwp[u >> 1];
+                    if (t < static_cast<int>(len)) {
+                        b = rd[b * C + ((cwd >> ((u & 3) * 8)) & 0xffu)];
+                        row[u] = entry((fpr >> ((u & 1) * 16)) & 0xffffu, b);
+                    }
+                }
+            }
+#pragma unroll 1
+            for (int u = kQuarter - 1; u >= 0; --u) {
+                const int t = q * kQuarter + u;
+                bool live = on && !over && t < static_cast<int>(len);
+                uint32_t m = column(live, live ? row[u] : 0u);
+                if (live && (m > static_cast<uint32_t>(kVec) || m == 0)) {
                     over = true;
                     live = false;
                 }
-            }
-            if (live && !found) {
-                if (m == 1) {
-                    found = true;
-                    r1 = a0 + t;
-                    seg_r1 = cur[0];
-                    y[0] = 1;
-                    prev[0] = cur[0];
-                    mp = 1;
+                if (live && !found) {
+                    if (m == 1) {
+                        found = true;
+                        r1 = a0 + t;
+                        y[0] = 1;
+                        mp = 1;
+                    }
+                    live = false;
                 }
-                live = false;
+                step(live, m, false, true);
             }
-            const bool need = live && !(m == 1 && mp == 1);
-            if (__any(need)) vstep(need, m, false, true);
-            if (live && !need) prev[0] = cur[0];      // singleton after singleton: one arc
         }
     }
     if (act && !over && !found) over = true;          // no singleton column in the chunk
@@ -1060,18 +1198,16 @@ __global__ __launch_bounds__(kCountThreads) void k_count_fast(Tabs tb, Job jb) {
     if (act && !over) {
         uint64_t *uv = jb.uv + static_cast<uint64_t>(i) * 2 * kVec;
 #pragma unroll
-        for (int k = 0; k < kVec; ++k) uv[kVec + k] = y[k];
+        for (int k = 0; k < kVec; ++k) uv[kVec + k] = k < static_cast<int>(mL) ? y[k] : 0ull;
     }
 
     // forward from r1 to column hi = P_{i+1}
 #pragma unroll
-    for (int k = 0; k < kVec; ++k) y[k] = 0, prev[k] = 0;
+    for (int k = 0; k < kVec; ++k) y[k] = 0;
     y[0] = 1;
-    prev[0] = seg_r1;
     mp = 1;
     const bool fw_on = act && !over;
     const uint32_t w_first = wave_min(fw_on ? static_cast<uint32_t>((r1 - lo) / 64) : 0xffffffffu);
-    uint32_t bwv[64];
     for (uint32_t w = w_first; w < nwin_wave; ++w) {
         const bool on = fw_on && w < nwin;
         uint64_t a0 = 0;
@@ -1080,33 +1216,50 @@ __global__ __launch_bounds__(kCountThreads) void k_count_fast(Tabs tb, Job jb) {
             a0 = lo + 64ull * w;
             len = static_cast<uint32_t>(hi - a0 < 64 ? hi - a0 : 64);
             load_window(text, a0, len, xw);
-            window_classes(T, xw, cw);
-            uint32_t g = jb.ckpt[ck(jb, i, w)];
-#pragma unroll
-            for (int t = 0; t < 64; ++t) {
-                fwv[t] = g;
-                if (t < static_cast<int>(len)) g = T.fd[g * C + byte_of(cw, t)];
-            }
-            f_end = g;
+            window_classes(ct, xw, cw);
+            f_end = forward_ids(w, len);
             b_end = jb.bckpt[ck(jb, i, w)];
-            uint32_t bb = b_end;
-#pragma unroll
-            for (int t = 63; t >= 0; --t) {
-                if (t < static_cast<int>(len)) bb = T.rd[bb * C + byte_of(cw, t)];
-                bwv[t] = bb;
-            }
         }
-        for (int t = 1; t <= 64; ++t) {     // column a0 + t
-            const uint64_t col = a0 + t;
-            const bool live = on && t <= static_cast<int>(len) && col > r1;
-            uint32_t m = 0;
-            if (live) {
-                const uint32_t fi = t < 64 && t < static_cast<int>(len) ? fwv[t & 63] : f_end;
-                const uint32_t bi = t < 64 && t < static_cast<int>(len) ? bwv[t & 63] : b_end;
-                m = list_clean(T, W, fi, bi, cur);
+#pragma unroll 1
+        for (int q = 0; q < 4; ++q) {
+            // (forward, backward) ids of the columns a0+16q+1 .. a0+16q+16 below
+            // a0+len into row[0..16); the column a0+len is (f_end, b_end).  The
+            // backward ids run from the window's right edge, first over the
+            // bytes above the quarter.  q selects between static indices.
+            if (on) {
+                uint32_t b = b_end;
+#pragma unroll
+                for (int t = 63; t >= kQuarter + 1; --t)
+                    if (t > q * kQuarter + kQuarter && t < static_cast<int>(len)) b = rd[b * C + byte_of(cw, t)];
+#pragma unroll
+                for (int u = kQuarter - 1; u >= 0; --u) {
+                    const int t = q * kQuarter + u + 1;           // column a0+t, byte t
+                    const int t1 = u + 1, t2 = kQuarter + u + 1, t3 = 2 * kQuarter + u + 1;
+                    const int t4 = u < kQuarter - 1 ? 3 * kQuarter + u + 1 : 3 * kQuarter;   // static, q = 3
+                    const uint32_t by = q == 3 ? byte_of(cw, t4) : q == 2 ? byte_of(cw, t3)
+                                      : q == 1 ? byte_of(cw, t2) : byte_of(cw, t1);
+                    const uint32_t fpr = q == 3 ? fwp[t4 >> 1] : q == 2 ? fwp[t3 >> 1] : q == 1 ? fwp[t2 >> 1]
+                                       : fwp[t1 >> 1];
+                    if (t < static_cast<int>(len)) {
+                        b = rd[b * C + by];                       // backward id at column a0+t
+                        row[u] = entry((fpr >> ((t & 1) * 16)) & 0xffffu, b);
+                    }
+                }
             }
-            const bool need = live;
-            if (__any(need)) vstep(need, m, true, false);
+#pragma unroll 1
+            for (int u = 0; u < kQuarter; ++u) {   // column a0 + 16q + u + 1
+                const int t = q * kQuarter + u + 1;
+                const uint64_t col = a0 + t;
+                bool live = on && !over && t <= static_cast<int>(len) && col > r1;
+                uint32_t e = 0;
+                if (live) e = t == static_cast<int>(len) ? entry(f_end, b_end) : row[u];
+                uint32_t m = column(live, e);
+                if (live && (m > static_cast<uint32_t>(kVec) || m == 0)) {
+                    over = true;
+                    live = false;
+                }
+                step(live, m, true, false);
+            }
         }
     }
     if (act && over) {
@@ -1117,7 +1270,7 @@ __global__ __launch_bounds__(kCountThreads) void k_count_fast(Tabs tb, Job jb) {
     if (!act) return;
     uint64_t *uv = jb.uv + static_cast<uint64_t>(i) * 2 * kVec;
 #pragma unroll
-    for (int k = 0; k < kVec; ++k) uv[k] = y[k];
+    for (int k = 0; k < kVec; ++k) uv[k] = k < static_cast<int>(mp) ? y[k] : 0ull;
     jb.pi[i] = pi;
     jb.dims[2 * i] = static_cast<uint8_t>(mL);
     jb.dims[2 * i + 1] = static_cast<uint8_t>(mp);

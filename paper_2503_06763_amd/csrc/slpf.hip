@@ -50,8 +50,24 @@ namespace {
 slpf_status hip_ok(hipError_t e) { return e == hipSuccess ? SLPF_OK : SLPF_E_DEVICE; }
 
 // Device-side copy of the tables in one allocation.
+// Per state: its only segment when the state's set has exactly one, else kNoSole.
+std::vector<uint16_t> sole_segments(const HostTable &t, uint32_t W) {
+    std::vector<uint16_t> out(t.nstates, kNoSole);
+    for (uint32_t s = 0; s < t.nstates; ++s) {
+        int cnt = 0, seg = 0;
+        for (uint32_t w = 0; w < W; ++w) {
+            const uint64_t v = t.bits[size_t(s) * W + w];
+            cnt += __builtin_popcountll(v);
+            if (v) seg = int(w * 64 + __builtin_ctzll(v));
+        }
+        if (cnt == 1) out[s] = static_cast<uint16_t>(seg);
+    }
+    return out;
+}
+
 slpf_status upload(slpf_parser *p) {
     const HostAutomaton &A = p->A;
+    const std::vector<uint16_t> fsole = sole_segments(A.fwd, A.W), rsole = sole_segments(A.rev, A.W);
     struct Part {
         const void *src;
         size_t bytes;
@@ -70,6 +86,8 @@ slpf_status upload(slpf_parser *p) {
         {A.fwd.hash.data(), A.fwd.hash.size() * 4, 0},
         {A.rev.hash.data(), A.rev.hash.size() * 4, 0},
         {A.folseg.data(), A.folseg.size() * 8, 0},
+        {fsole.data(), fsole.size() * 2, 0},
+        {rsole.data(), rsole.size() * 2, 0},
     };
     size_t total = 0;
     for (auto &pt : parts) {
@@ -100,6 +118,8 @@ slpf_status upload(slpf_parser *p) {
     t.fhash = reinterpret_cast<const uint32_t *>(at(9));
     t.rhash = reinterpret_cast<const uint32_t *>(at(10));
     t.folseg = reinterpret_cast<const uint64_t *>(at(11));
+    t.fsole = reinterpret_cast<const uint16_t *>(at(12));
+    t.rsole = reinterpret_cast<const uint16_t *>(at(13));
     t.fhmask = static_cast<uint32_t>(A.fwd.hash.size() - 1);
     t.rhmask = static_cast<uint32_t>(A.rev.hash.size() - 1);
     t.C = A.C;
@@ -131,8 +151,6 @@ void set_placement(slpf_parser *p) {
     }
     p->placement = p->lds_bytes <= budget ? 0 : 1;
 }
-
-uint32_t A_nseg(const slpf_parser *p) { return p->A.nseg; }
 
 uint64_t chunk_bytes_for(uint64_t n, const slpf_parse_opts *o) {
     if (o && o->chunk_bytes) return o->chunk_bytes;
@@ -543,19 +561,19 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
     mark(4);
     // tree count
     if (count && c) {
-        const size_t fol_lds = (size_t(A_nseg(p)) * W * 8 + 15) & ~size_t(15);
+        // the count kernel keeps per-lane rows and segment lists in LDS and
+        // stages the tables there too when they fit (all of them, or the
+        // transition and sole-segment tables only)
+        const CountLds co = count_lds(tb.nf, tb.nr, tb.C, W, tb.nseg);
         const uint32_t cblocks = (c + kCountThreads - 1) / kCountThreads;
-        const bool cfit_tab = lds && fol_lds + tab_lds <= p->lds_limit;
-        const bool cfit_bits = cfit_tab && fol_lds + tab_lds + bits_lds <= p->lds_limit;
-        if (cfit_bits)
-            hipLaunchKernelGGL((k_count_fast<true, true, true>), dim3(cblocks), dim3(kCountThreads),
-                               fol_lds + tab_lds + bits_lds, stream, tb, jb);
-        else if (cfit_tab)
-            hipLaunchKernelGGL((k_count_fast<true, false, true>), dim3(cblocks), dim3(kCountThreads),
-                               fol_lds + tab_lds, stream, tb, jb);
+        if (lds && co.end <= p->lds_limit)
+            hipLaunchKernelGGL((k_count_fast<true, true>), dim3(cblocks), dim3(kCountThreads), co.end, stream, tb, jb);
+        else if (lds && co.bits <= p->lds_limit)
+            hipLaunchKernelGGL((k_count_fast<true, false>), dim3(cblocks), dim3(kCountThreads), co.bits, stream, tb,
+                               jb);
         else
-            hipLaunchKernelGGL((k_count_fast<false, false, false>), dim3(cblocks), dim3(kCountThreads), 0, stream,
-                               tb, jb);
+            hipLaunchKernelGGL((k_count_fast<false, false>), dim3(cblocks), dim3(kCountThreads), kCountLdsBytes,
+                               stream, tb, jb);
         hipLaunchKernelGGL(k_count_chunk, dim3(std::min<uint32_t>(c, 1024)), dim3(64), 0, stream, tb, jb);
         hipLaunchKernelGGL(k_count_factor, dim3((c + nt + 255) / 256), dim3(256), 0, stream, jb);
     }
@@ -602,6 +620,55 @@ slpf_status slpf_parse_batch(const slpf_parser *cp, const slpf_text *items, size
         if (st != SLPF_OK) return st;
     }
     return run_job(p, items, count, opts, static_cast<hipStream_t>(hip_stream));
+}
+
+slpf_status slpf_tune(const slpf_parser *cp, const slpf_text *items, size_t count, uint32_t flags,
+                      slpf_parse_opts *best, float *best_ms, void *hip_stream) {
+    slpf_parser *p = const_cast<slpf_parser *>(cp);
+    if (!p || p->host_only || !best || best->struct_size != sizeof(slpf_parse_opts) || !items || !count)
+        return SLPF_E_ARG;
+    flags &= ~static_cast<uint32_t>(SLPF_PARSE_FORCE_L2);
+    hipStream_t stream = static_cast<hipStream_t>(hip_stream);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) hipEventDestroy(e0);
+        return SLPF_E_DEVICE;
+    }
+    slpf_status st = SLPF_OK;
+    float best_t = -1.0f;
+    uint32_t best_chunk = 0, best_flags = flags;
+    const uint32_t chunks[] = {256, 512, 1024, 2048, 4096};
+    const int nplace = p->placement == 0 ? 2 : 1;    // LDS tables and, if they fit, L2 as well
+    for (uint32_t k : chunks) {
+        for (int pl = 0; pl < nplace && st == SLPF_OK; ++pl) {
+            slpf_parse_opts o{};
+            o.struct_size = sizeof(o);
+            o.chunk_bytes = k;
+            o.flags = flags | (pl ? SLPF_PARSE_FORCE_L2 : 0u);
+            // one untimed run (workspace growth, caches), one timed run
+            st = slpf_parse_batch(p, items, count, &o, stream);
+            if (st != SLPF_OK) break;
+            if (hipEventRecord(e0, stream) != hipSuccess) st = SLPF_E_DEVICE;
+            if (st == SLPF_OK) st = slpf_parse_batch(p, items, count, &o, stream);
+            if (st == SLPF_OK && hipEventRecord(e1, stream) != hipSuccess) st = SLPF_E_DEVICE;
+            if (st == SLPF_OK && hipEventSynchronize(e1) != hipSuccess) st = SLPF_E_DEVICE;
+            float ms = 0;
+            if (st == SLPF_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = SLPF_E_DEVICE;
+            if (st == SLPF_OK && (best_t < 0 || ms < best_t)) {
+                best_t = ms;
+                best_chunk = k;
+                best_flags = o.flags;
+            }
+        }
+        if (st != SLPF_OK) break;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (st != SLPF_OK) return st;
+    best->chunk_bytes = best_chunk;
+    best->flags = best_flags;
+    if (best_ms) *best_ms = best_t;
+    return SLPF_OK;
 }
 
 }  // extern "C"

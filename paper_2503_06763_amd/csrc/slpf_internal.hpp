@@ -14,6 +14,7 @@ namespace slpf {
 constexpr int kMaxEntries = 64;     // entries of one speculative entry list (u64 masks)
 constexpr int kMaxWords = 32;       // words per SLPF column handled by the kernels
 constexpr uint32_t kHashEmpty = 0xffffffffu;
+constexpr uint16_t kNoSole = 0xffffu;  // state set with zero or several segments
 
 // Hash of a W-word segment set, identical on host and device.
 __host__ __device__ inline uint32_t hash_words(const uint64_t *w, int W) {

@@ -159,3 +159,61 @@ def test_batch_argument_errors():
     assert e.value.status == S.E_ARG
     p.parse_batch_into([])
     torch.cuda.synchronize()
+
+
+def _fits(re):
+    try:
+        S.Parser(re, host_only=True)
+        return True
+    except S.SlpfError:
+        return False
+
+
+def test_batched_re_family_vs_oracle():
+    # the batched workload's 16 REs (4, 26 and 128-symbol alphabets and the
+    # motif RE), 64 texts of log-uniform length 256 B - 64 KiB, one job per RE
+    import torch
+    from gen import workloads as wl
+    device()
+    res = wl.batched_res(_fits)
+    assert len(res) == 16
+    texts = wl.texts_for(res, wl.loguniform_lengths(7, 64, lo=256, hi=64 << 10), 8)
+    for q, (name, tree) in enumerate(res):
+        mine = [x.tobytes() for r, x in texts if r == q]
+        if not mine:
+            continue
+        pat = regen.to_re(tree)
+        say("family", name, len(mine), "texts")
+        p, o = S.Parser(pat), Oracle(pat)
+        got = run_batch(p, mine)
+        for t, g in zip(mine, got):
+            cols, acc, cnt = o.parse(t)
+            assert acc and g[1], name                    # sampled from the language
+            assert np.array_equal(g[0], cols), name
+            assert g[3] == 0 and g[2] == cnt, (name, g[2:], cnt)
+    torch.cuda.synchronize()
+
+
+def test_tune_picks_a_candidate_and_keeps_results_exact():
+    import torch
+    dev = device()
+    tree = regen.plain_small_re()
+    pat = regen.to_re(tree).decode()
+    texts = mixed_texts(tree, 21, 12, 30000)
+    p, o = S.Parser(pat), Oracle(pat)
+    dts = [to_device(t) for t in texts]
+    cols = [torch.zeros((len(t) + 1, p.W), dtype=torch.int64, device=dev) for t in texts]
+    sc = torch.zeros((len(texts), 3), dtype=torch.int64, device=dev)
+    items = [(d, len(t), c, sc[k]) for k, (d, t, c) in enumerate(zip(dts, texts, cols))]
+    chunk, flags, ms = p.tune(items)
+    say("tuned", chunk, flags, ms)
+    assert chunk in (256, 512, 1024, 2048, 4096) and ms > 0
+    assert flags & ~S.PARSE_FORCE_L2 == 0
+    torch.cuda.synchronize()
+    s = sc.cpu().numpy().view(np.uint64)
+    for k, t in enumerate(texts):
+        c, acc, cnt = o.parse(t)
+        assert np.array_equal(cols[k].cpu().numpy().view(np.uint64), c), k
+        assert bool(s[k, 0]) == acc
+        if s[k, 2] == 0:
+            assert int(s[k, 1]) == cnt
