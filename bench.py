@@ -28,6 +28,8 @@ HBM_PEAK_GBS = 8000.0
 RE_SEED, TEXT_SEED, CORRUPT_SEED = 23, 23, 24
 TEXT_BYTES = 1 << 28
 BATCH_RE_SEED, BATCH_LEN_SEED, BATCH_TEXT_SEED = 4000, 4001, 4002
+SERVE_RE_SEED, SERVE_LEN_SEED, SERVE_TEXT_SEED, SERVE_ARRIVAL_SEED = 5000, 5001, 5002, 5003
+SERVE_RATES = [0.25, 0.5, 0.75, 0.9, 1.1]
 KERNEL_SOURCES = ["paper_2503_06763_amd/csrc/kernels.hpp", "paper_2503_06763_amd/csrc/slpf.hip"]
 
 
@@ -260,6 +262,129 @@ def run_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def run_served(args):
+    """Served: 64 resident REs, Poisson arrivals at 5 rates relative to the
+    plain per-request capacity, lognormal text lengths; the request server
+    (continuous batching, admission by projected SLPF bytes within the memory
+    budget) against the plain per-request path (one request per job, one job
+    in flight).  p50/p99 latency from arrival to finished, and aggregate GB/s."""
+    import numpy as np
+    import torch
+    import paper_2503_06763_amd as S
+    from gen import regen, workloads as wl
+
+    def fits(re):
+        try:
+            S.Parser(re, host_only=True)
+            return True
+        except S.SlpfError:
+            return False
+    t0 = time.perf_counter()
+    res = wl.served_res(fits, seed=SERVE_RE_SEED)
+    lengths = wl.lognormal_lengths(SERVE_LEN_SEED, args.pool)
+    pool = wl.texts_for(res, lengths, SERVE_TEXT_SEED)
+    gen_s = time.perf_counter() - t0
+    pats = [regen.to_re(t) for _, t in res]
+    parsers = [S.Parser(pt) for pt in pats]
+    dev = torch.device("cuda:0")
+    ns = [int(x.size) for _, x in pool]
+    offs, tot = _aligned_offsets(ns, 256)
+    host = np.zeros(tot, np.uint8)
+    for (r, x), o in zip(pool, offs):
+        host[o:o + x.size] = x
+    tbuf = torch.from_numpy(host).to(dev)
+    del host
+    views = [tbuf[o:o + n] for o, n in zip(offs, ns)]
+    torch.cuda.synchronize()
+    print("served workload: %d REs, pool of %d texts (%d bytes), gen %.1fs" % (
+        len(res), len(pool), sum(ns), gen_s), file=sys.stderr, flush=True)
+
+    servers = {"plain": S.Server(slots=1, max_batch_texts=1, memory_budget=args.budget),
+               "served": S.Server(slots=args.slots, max_batch_texts=args.max_batch, memory_budget=args.budget)}
+
+    def run(mode, arrivals):
+        """Drive one server through the arrival schedule; returns latencies (s), the span and bytes."""
+        srv = servers[mode]
+        nreq = len(arrivals)
+        lat = np.zeros(nreq)
+        nb = 0
+        k = 0
+        fin = 0
+        start = time.perf_counter()
+        while fin < nreq:
+            now = time.perf_counter() - start
+            while k < nreq and arrivals[k] <= now:
+                j = k % len(pool)
+                srv.submit(parsers[pool[j][0]], views[j], ns[j], k)
+                nb += ns[j]
+                k += 1
+            for tag in srv.poll():
+                lat[tag] = time.perf_counter() - start - arrivals[tag]
+                srv.release(tag)
+                fin += 1
+        span = time.perf_counter() - start
+        return lat, span, nb
+
+    # warm both servers (work buffers of every parser on every slot stream),
+    # then the capacities: the whole pool submitted at once
+    run("served", np.zeros(len(pool)))
+    run("plain", np.zeros(len(pool)))
+    cap = {}
+    for mode in ("plain", "served"):
+        lat, span, nb = run(mode, np.zeros(len(pool)))
+        cap[mode] = {"requests_per_s": round(len(pool) / span, 2), "gbs": round(nb / span / 1e9, 3),
+                     "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                     "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3)}
+    mu = cap["plain"]["requests_per_s"]
+    print("capacity: plain %s | served %s" % (cap["plain"], cap["served"]), file=sys.stderr, flush=True)
+    rows = []
+    for f in SERVE_RATES:
+        lam = f * mu
+        arr = wl.poisson_arrivals(SERVE_ARRIVAL_SEED + int(f * 100), args.requests, lam)
+        row = {"rate_vs_plain_capacity": f, "requests_per_s": round(lam, 2)}
+        for mode in ("served", "plain"):
+            lat, span, nb = run(mode, arr)
+            row[mode] = {"p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                         "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+                         "gbs": round(nb / span / 1e9, 3), "span_s": round(span, 3)}
+        print("rate %.2f x mu: served p50 %.2f p99 %.2f ms %.2f GB/s | plain p50 %.2f p99 %.2f ms %.2f GB/s" % (
+            f, row["served"]["p50_ms"], row["served"]["p99_ms"], row["served"]["gbs"], row["plain"]["p50_ms"],
+            row["plain"]["p99_ms"], row["plain"]["gbs"]), file=sys.stderr, flush=True)
+        rows.append(row)
+    for srv in servers.values():
+        srv.close()
+    top = rows[-1]
+    out = {
+        "metric": METRIC, "value": cap["served"]["gbs"], "unit": "GB/s", "n_gpus": 1, "steps": len(rows),
+        "warmup": 1, "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "served: %d resident REs (random REs of depth 4-8 over 4, 26 and 128 symbols, "
+                               "and the motif RE), Poisson arrivals at %s x the plain per-request capacity, "
+                               "%d requests per rate over a pool of %d texts with lognormal lengths (median "
+                               "64 KiB, sigma 1.5, cap 64 MiB), admission by projected SLPF bytes within %d "
+                               "bytes, %d slots, up to %d requests per job" % (
+                                   len(res), SERVE_RATES, args.requests, len(pool), args.budget, args.slots,
+                                   args.max_batch),
+                   "plain_capacity_requests_per_s": round(mu, 2)},
+        "capacity": cap,
+        "speedup_vs_plain": round(cap["served"]["gbs"] / cap["plain"]["gbs"], 3),
+        "latency_at_1.1x_plain_capacity": {"served": {"p50_ms": top["served"]["p50_ms"],
+                                                      "p99_ms": top["served"]["p99_ms"]},
+                                           "plain": {"p50_ms": top["plain"]["p50_ms"],
+                                                     "p99_ms": top["plain"]["p99_ms"]}},
+        "rates": rows,
+    }
+    if not args.no_cpu_baseline:
+        jobs, acc = [], 0
+        for r, x in pool:
+            if acc + x.size > args.cpu_sample:
+                continue
+            jobs.append((pats[r], x.tobytes()))
+            acc += x.size
+        out["cpu_baseline"] = oracle_pool_baseline(jobs, 0)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -270,7 +395,12 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=32 << 20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-companion", action="store_true")
-    ap.add_argument("--workload", choices=["single", "batched"], default="single")
+    ap.add_argument("--workload", choices=["single", "batched", "served"], default="single")
+    ap.add_argument("--requests", type=int, default=4000, help="served: requests per arrival rate")
+    ap.add_argument("--pool", type=int, default=1024, help="served: distinct texts the requests cycle over")
+    ap.add_argument("--budget", type=int, default=64 << 30, help="served: SLPF bytes admitted at once")
+    ap.add_argument("--slots", type=int, default=4, help="served: jobs in flight")
+    ap.add_argument("--max-batch", type=int, default=256, help="served: requests per job at most")
     ap.add_argument("--texts", type=int, default=4096, help="batched: number of texts")
     ap.add_argument("--streams", type=int, default=4, help="batched: streams the per-RE jobs are spread over")
     ap.add_argument("--copy-calib", type=int, default=0,
@@ -288,6 +418,8 @@ def main():
         if args.steps == 10:
             args.steps = 3
         return run_batched(args)
+    if args.workload == "served":
+        return run_served(args)
 
     t0 = time.perf_counter()
     pat, text = make_text(args.bytes, corrupt=True)

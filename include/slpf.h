@@ -233,6 +233,13 @@ slpf_status slpf_parse_batch(const slpf_parser *p, const slpf_text *items, size_
                              const slpf_parse_opts *opts, void *hip_stream);
 
 /*
+ * Free the work buffers the parser keeps for parses on hip_stream (after
+ * synchronizing that stream); call before destroying a stream the parser was
+ * used on.  Later parses on the stream allocate them again.
+ */
+slpf_status slpf_parser_trim(const slpf_parser *p, void *hip_stream);
+
+/*
  * Autotuner: time one batched parse of `items` (after one untimed run) for
  * every lane-chunk size in {256, 512, 1024, 2048, 4096} bytes and, when the
  * tables fit in LDS, both table placements (LDS and L2), and return the
@@ -244,6 +251,59 @@ slpf_status slpf_parse_batch(const slpf_parser *p, const slpf_text *items, size_
  */
 slpf_status slpf_tune(const slpf_parser *p, const slpf_text *items, size_t count, uint32_t flags,
                       slpf_parse_opts *best, float *best_ms, void *hip_stream);
+
+/* ---------------------------------------------------------------- server
+ *
+ * Continuous batching of parse requests on one GPU (for serving): parsers
+ * stay resident, requests queue in FIFO order, and a request is admitted
+ * when a job slot is free and the SLPF it will produce (slpf_forest_bytes,
+ * plus the scalars) fits in the server's device arena of memory_budget
+ * bytes.  The requests admitted into a slot run as one job (per parser, one
+ * slpf_parse_batch) on that slot's stream; slots run concurrently.  Results
+ * are identical to slpf_parse of each text alone (see slpf_parse_batch for
+ * the one exception).  A server is driven from one host thread.
+ */
+typedef struct slpf_server slpf_server;
+
+typedef struct {
+    uint32_t struct_size;        /* sizeof(slpf_server_opts) */
+    uint32_t slots;              /* jobs in flight at once (each on its own stream) */
+    uint32_t max_batch_texts;    /* requests admitted into one job at most */
+    uint32_t parse_flags;        /* SLPF_PARSE_* for every job */
+    uint64_t memory_budget;      /* bytes of the output arena (allocated at create) */
+    int32_t device;
+    uint32_t reserved;
+} slpf_server_opts;
+
+typedef struct {
+    uint64_t queued, in_flight, busy_slots, finished_unreleased;
+    uint64_t admitted_bytes, arena_bytes;
+} slpf_server_state;
+
+slpf_status slpf_server_create(const slpf_server_opts *opts, slpf_server **out);
+/* Waits for the jobs in flight, then frees the arena, the streams and the
+ * work buffers the parsers kept for those streams.  Parsers used by the
+ * server must outlive it. */
+void slpf_server_destroy(slpf_server *s);
+/* Queue a request: text_dev (16-byte aligned, n bytes) stays owned by the
+ * caller and must stay valid until the request is reported done; its bytes
+ * must already be in place (the server's streams do not wait for work on
+ * other streams).  tag
+ * identifies the request in slpf_server_poll/result/release and must be
+ * unique among requests not yet released.  SLPF_E_CAPACITY if its output
+ * alone exceeds the budget. */
+slpf_status slpf_server_submit(slpf_server *s, const slpf_parser *p, const uint8_t *text_dev, uint64_t n,
+                               uint64_t tag);
+/* Retire finished jobs, admit and launch queued requests into free slots,
+ * and report up to cap finished tags (the rest are reported by later
+ * calls).  Does not block on the GPU. */
+slpf_status slpf_server_poll(slpf_server *s, uint64_t *done_tags, size_t cap, size_t *n_done);
+/* Output of a finished request (device pointers into the arena, valid until
+ * slpf_server_release). */
+slpf_status slpf_server_result(const slpf_server *s, uint64_t tag, slpf_forest *out);
+/* Return a finished request's arena space. */
+slpf_status slpf_server_release(slpf_server *s, uint64_t tag);
+slpf_status slpf_server_stats(const slpf_server *s, slpf_server_state *state);
 
 /* Number of lane chunks a parse of n bytes uses with the given options. */
 uint64_t slpf_num_chunks(const slpf_parser *p, uint64_t n, const slpf_parse_opts *opts);

@@ -27,8 +27,10 @@ PARSE_NO_COUNT = 1
 PARSE_FORCE_L2 = 2
 
 EXPORTS = ["slpf_compile", "slpf_parser_destroy", "slpf_parser_info_get", "slpf_segment_text",
-           "slpf_table_dump", "slpf_forest_bytes", "slpf_parse", "slpf_parse_batch", "slpf_tune",
-           "slpf_num_chunks", "slpf_status_str"]
+           "slpf_table_dump", "slpf_forest_bytes", "slpf_parse", "slpf_parse_batch", "slpf_tune", "slpf_parser_trim",
+           "slpf_num_chunks", "slpf_status_str", "slpf_server_create", "slpf_server_destroy",
+           "slpf_server_submit", "slpf_server_poll", "slpf_server_result", "slpf_server_release",
+           "slpf_server_stats"]
 
 
 class SlpfError(RuntimeError):
@@ -66,6 +68,17 @@ PHASES = ["reach", "join", "starts", "build", "count"]
 class Forest(ctypes.Structure):
     _fields_ = [("columns_dev", ctypes.c_void_p), ("capacity_bytes", ctypes.c_uint64),
                 ("scalars_dev", ctypes.c_void_p)]
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("slots", ctypes.c_uint32),
+                ("max_batch_texts", ctypes.c_uint32), ("parse_flags", ctypes.c_uint32),
+                ("memory_budget", ctypes.c_uint64), ("device", ctypes.c_int32), ("reserved", ctypes.c_uint32)]
+
+
+class ServerState(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_uint64) for k in ("queued", "in_flight", "busy_slots", "finished_unreleased",
+                                               "admitted_bytes", "arena_bytes")]
 
 
 class Text(ctypes.Structure):
@@ -107,6 +120,22 @@ def lib(path: str = LIB_PATH):
     L.slpf_tune.argtypes = [vp, ctypes.POINTER(Text), sz, ctypes.c_uint32, ctypes.POINTER(ParseOpts),
                             ctypes.POINTER(ctypes.c_float), vp]
     L.slpf_tune.restype = ctypes.c_int
+    L.slpf_parser_trim.argtypes = [vp, vp]
+    L.slpf_parser_trim.restype = ctypes.c_int
+    L.slpf_server_create.argtypes = [ctypes.POINTER(ServerOpts), ctypes.POINTER(vp)]
+    L.slpf_server_create.restype = ctypes.c_int
+    L.slpf_server_destroy.argtypes = [vp]
+    L.slpf_server_destroy.restype = None
+    L.slpf_server_submit.argtypes = [vp, vp, vp, ctypes.c_uint64, ctypes.c_uint64]
+    L.slpf_server_submit.restype = ctypes.c_int
+    L.slpf_server_poll.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64), sz, ctypes.POINTER(sz)]
+    L.slpf_server_poll.restype = ctypes.c_int
+    L.slpf_server_result.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(Forest)]
+    L.slpf_server_result.restype = ctypes.c_int
+    L.slpf_server_release.argtypes = [vp, ctypes.c_uint64]
+    L.slpf_server_release.restype = ctypes.c_int
+    L.slpf_server_stats.argtypes = [vp, ctypes.POINTER(ServerState)]
+    L.slpf_server_stats.restype = ctypes.c_int
     L.slpf_num_chunks.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ParseOpts)]
     L.slpf_num_chunks.restype = ctypes.c_uint64
     L.slpf_status_str.argtypes = [ctypes.c_int]
@@ -322,6 +351,91 @@ class Parser:
         flags = (0 if count else PARSE_NO_COUNT) | (PARSE_FORCE_L2 if force_l2 else 0)
         self.parse_batch_into(items, chunk_bytes, flags, stream, events)
         return out
+
+
+class Server:
+    """slpf_server: continuous batching of parse requests (FIFO admission by
+    projected SLPF bytes within ``memory_budget``, ``slots`` jobs in flight)."""
+
+    def __init__(self, slots: int = 4, max_batch_texts: int = 256, memory_budget: int = 1 << 30,
+                 count: bool = True, device: int = 0):
+        L = lib()
+        o = ServerOpts(ctypes.sizeof(ServerOpts), slots, max_batch_texts, 0 if count else PARSE_NO_COUNT,
+                       memory_budget, device, 0)
+        h = ctypes.c_void_p()
+        _check(L.slpf_server_create(ctypes.byref(o), ctypes.byref(h)), "slpf_server_create")
+        self._L, self._h = L, h
+        self._buf = (ctypes.c_uint64 * 4096)()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.slpf_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, parser: Parser, text, n: int, tag: int):
+        """Queue a request; ``text`` is a device tensor whose bytes are in place."""
+        st = self._L.slpf_server_submit(self._h, parser.handle, text.data_ptr() if n else None, n, tag)
+        _check(st, "slpf_server_submit")
+
+    def poll(self):
+        """Advance the server; returns the list of tags finished since the last call."""
+        out = []
+        while True:
+            nd = ctypes.c_size_t(0)
+            _check(self._L.slpf_server_poll(self._h, self._buf, len(self._buf), ctypes.byref(nd)),
+                   "slpf_server_poll")
+            out.extend(self._buf[:nd.value])
+            if nd.value < len(self._buf):
+                return out
+
+    def result(self, tag: int):
+        """(columns_ptr, capacity_bytes, scalars_ptr) of a finished request."""
+        f = Forest()
+        _check(self._L.slpf_server_result(self._h, tag, ctypes.byref(f)), "slpf_server_result")
+        return f.columns_dev, f.capacity_bytes, f.scalars_dev
+
+    def result_tensors(self, tag: int, n: int, W: int, device="cuda:0"):
+        """Host copies (columns uint64 [n+1, W], scalars uint64 [3]) of a finished request."""
+        import numpy as np
+        import torch
+        cp, cap, sp = self.result(tag)
+        cols = np.empty((n + 1) * W, np.uint64)
+        sc = np.empty(3, np.uint64)
+        torch.cuda.synchronize()
+        _hip_copy_to_host(cols.ctypes.data, cp, cols.nbytes)
+        _hip_copy_to_host(sc.ctypes.data, sp, sc.nbytes)
+        return cols.reshape(n + 1, W), sc
+
+    def release(self, tag: int):
+        _check(self._L.slpf_server_release(self._h, tag), "slpf_server_release")
+
+    def stats(self):
+        s = ServerState()
+        _check(self._L.slpf_server_stats(self._h, ctypes.byref(s)), "slpf_server_stats")
+        return {k: getattr(s, k) for k, _ in ServerState._fields_}
+
+
+_hip = None
+
+
+def _hip_copy_to_host(dst, src, nbytes):
+    """Synchronous device-to-host copy through the HIP runtime torch loaded."""
+    global _hip
+    if _hip is None:
+        import torch  # noqa: F401  (loads the HIP runtime; the soname resolves to that copy)
+        _hip = ctypes.CDLL("libamdhip64.so.7")
+        _hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+        _hip.hipMemcpy.restype = ctypes.c_int
+    if nbytes:
+        st = _hip.hipMemcpy(ctypes.c_void_p(dst), ctypes.c_void_p(src), nbytes, 2)   # device to host
+        if st != 0:
+            raise SlpfError(E_DEVICE, "hipMemcpy")
 
 
 def status_str(st: int) -> str:

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libslpf.so")
 BUILD_DIR = os.path.join(HERE, "_build")
-SOURCES = ["slpf.hip", "compiler.cpp"]
+SOURCES = ["slpf.hip", "compiler.cpp", "server.hip"]
 HEADERS = ["kernels.hpp", "slpf_internal.hpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

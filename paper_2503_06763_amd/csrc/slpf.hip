@@ -376,7 +376,7 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
         ifac = L.add(size_t(c + T) * 8);
         itidx = L.add(size_t(c) * 4);
         iovf = L.add(size_t(c) * 4);
-        itbig = L.add(size_t(kBigPool) * kBigT * kBigT * 8);
+        itbig = L.add(size_t(std::min<uint32_t>(kBigPool, std::max<uint32_t>(c, 1))) * kBigT * kBigT * 8);
     }
 
     uint8_t *base;
@@ -458,7 +458,7 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
         jb.tbig_idx = reinterpret_cast<uint32_t *>(ptr(itidx));
         jb.ovf = reinterpret_cast<uint32_t *>(ptr(iovf));
         jb.tbig = reinterpret_cast<uint64_t *>(ptr(itbig));
-        jb.big_pool = kBigPool;
+        jb.big_pool = std::min<uint32_t>(kBigPool, std::max<uint32_t>(c, 1));   // at most one slot per chunk
     }
 
     const bool timed = opts && opts->events && opts->num_events >= SLPF_NUM_PHASE_EVENTS;
@@ -620,6 +620,22 @@ slpf_status slpf_parse_batch(const slpf_parser *cp, const slpf_text *items, size
         if (st != SLPF_OK) return st;
     }
     return run_job(p, items, count, opts, static_cast<hipStream_t>(hip_stream));
+}
+
+slpf_status slpf_parser_trim(const slpf_parser *cp, void *hip_stream) {
+    slpf_parser *p = const_cast<slpf_parser *>(cp);
+    if (!p) return SLPF_E_ARG;
+    std::lock_guard<std::mutex> g(p->mu);
+    auto it = p->ws.find(static_cast<hipStream_t>(hip_stream));
+    if (it == p->ws.end()) return SLPF_OK;
+    Workspace &w = it->second;
+    if (hipSetDevice(p->device) != hipSuccess) return SLPF_E_DEVICE;
+    if (hipStreamSynchronize(it->first) != hipSuccess) return SLPF_E_DEVICE;
+    if (w.copied) (void)hipEventDestroy(w.copied);
+    if (w.base) (void)hipFree(w.base);
+    if (w.pinned) (void)hipHostFree(w.pinned);
+    p->ws.erase(it);
+    return SLPF_OK;
 }
 
 slpf_status slpf_tune(const slpf_parser *cp, const slpf_text *items, size_t count, uint32_t flags,

@@ -1,0 +1,111 @@
+"""The request server (slpf_server_*): continuous batching with admission by
+projected SLPF bytes.  Every result must be identical alone and in the mix:
+each request's columns, accept flag, count and status equal those of
+slpf_parse on that text alone (and of the oracle), whatever the arrival
+order, the batch it landed in and the requests it overlapped with.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from gen import regen, workloads as wl
+from gpu_util import device, gpu_parse, to_device
+from oracle.oracle import Oracle
+
+S = pytest.importorskip("paper_2503_06763_amd")
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _fits(re):
+    try:
+        S.Parser(re, host_only=True)
+        return True
+    except S.SlpfError:
+        return False
+
+
+def _workload(n_res, n_req, seed, median=2048, cap=1 << 16):
+    res = wl.served_res(_fits)[:n_res]
+    lengths = wl.lognormal_lengths(seed, n_req, median=median, sigma=1.5, cap=cap)
+    texts = wl.texts_for(res, lengths, seed + 1)
+    return res, texts
+
+
+def test_server_alone_vs_mix():
+    import torch
+    device()
+    res, texts = _workload(8, 160, 31)
+    pats = [regen.to_re(t) for _, t in res]
+    parsers = [S.Parser(p) for p in pats]
+    # empty and one-byte requests in the mix
+    texts[5] = (texts[5][0], texts[5][1][:0])
+    texts[9] = (texts[9][0], texts[9][1][:1])
+    dts = [to_device(x.tobytes()) for _, x in texts]
+    torch.cuda.synchronize()
+    # a small arena: requests wait for space; 3 slots overlap
+    srv = S.Server(slots=3, max_batch_texts=12, memory_budget=6 << 20)
+    rng = np.random.default_rng(5)
+    order = rng.permutation(len(texts))
+    pending, done = list(order), {}
+    max_admitted = 0
+    while len(done) < len(texts):
+        # arrivals in small random bursts while earlier requests run
+        for _ in range(int(rng.integers(0, 6))):
+            if pending:
+                k = int(pending.pop(0))
+                r, x = texts[k]
+                srv.submit(parsers[r], dts[k], x.size, k)
+        for tag in srv.poll():
+            r, x = texts[tag]
+            done[tag] = srv.result_tensors(tag, x.size, parsers[r].W)
+            srv.release(tag)
+        st = srv.stats()
+        max_admitted = max(max_admitted, st["admitted_bytes"])
+        assert st["admitted_bytes"] <= st["arena_bytes"]
+    say("server: %d requests, peak admitted %d of %d bytes" % (len(done), max_admitted, 6 << 20))
+    assert srv.stats()["admitted_bytes"] == 0
+    srv.close()
+    oracles = {}
+    for k, (r, x) in enumerate(texts):
+        cols, sc = done[k]
+        alone = gpu_parse(parsers[r], dts[k])
+        assert np.array_equal(cols, alone[0]), k
+        assert (bool(sc[0]), int(sc[1]), int(sc[2])) == alone[1:], k
+        if x.size <= 4096:
+            o = oracles.setdefault(r, Oracle(pats[r]))
+            c2, acc, cnt = o.parse(x.tobytes())
+            assert np.array_equal(cols, c2) and bool(sc[0]) == acc, k
+            if sc[2] == 0:
+                assert int(sc[1]) == cnt, k
+
+
+def test_server_capacity_and_arguments():
+    import torch
+    device()
+    p = S.Parser("(ab|a)*")
+    srv = S.Server(slots=1, max_batch_texts=4, memory_budget=1 << 16)
+    big = to_device(b"ab" * 4096)                   # its SLPF needs more than the budget
+    with pytest.raises(S.SlpfError) as e:
+        srv.submit(p, big, 8192, 1)
+    assert e.value.status == S.E_CAPACITY
+    small = to_device(b"abaaba")
+    torch.cuda.synchronize()
+    srv.submit(p, small, 6, 7)
+    got = []
+    while not got:
+        got = srv.poll()
+    assert got == [7]
+    cols, sc = srv.result_tensors(7, 6, p.W)
+    assert bool(sc[0]) and int(sc[1]) == 1
+    with pytest.raises(S.SlpfError):
+        srv.result(8)                               # unknown tag
+    srv.release(7)
+    with pytest.raises(S.SlpfError):
+        srv.release(7)                              # already released
+    srv.close()
