@@ -30,6 +30,7 @@ TEXT_BYTES = 1 << 28
 BATCH_RE_SEED, BATCH_LEN_SEED, BATCH_TEXT_SEED = 4000, 4001, 4002
 SERVE_RE_SEED, SERVE_LEN_SEED, SERVE_TEXT_SEED, SERVE_ARRIVAL_SEED = 5000, 5001, 5002, 5003
 SERVE_RATES = [0.25, 0.5, 0.75, 0.9, 1.1]
+RECORD_SEED, RECORD_BYTES = 31, 1 << 30
 KERNEL_SOURCES = ["paper_2503_06763_amd/csrc/kernels.hpp", "paper_2503_06763_amd/csrc/slpf.hip"]
 
 
@@ -395,7 +396,7 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=32 << 20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-companion", action="store_true")
-    ap.add_argument("--workload", choices=["single", "batched", "served"], default="single")
+    ap.add_argument("--workload", choices=["single", "record", "batched", "served"], default="single")
     ap.add_argument("--requests", type=int, default=4000, help="served: requests per arrival rate")
     ap.add_argument("--pool", type=int, default=1024, help="served: distinct texts the requests cycle over")
     ap.add_argument("--budget", type=int, default=64 << 30, help="served: SLPF bytes admitted at once")
@@ -422,7 +423,16 @@ def main():
         return run_served(args)
 
     t0 = time.perf_counter()
-    pat, text = make_text(args.bytes, corrupt=True)
+    if args.workload == "record":
+        from gen import regen, textgen
+        if args.bytes == TEXT_BYTES:
+            args.bytes = RECORD_BYTES
+        pat, text = regen.to_re(regen.record_re()), textgen.record_text(RECORD_SEED, args.bytes)
+        args.no_companion = True
+        if args.cpu_sample == 32 << 20:
+            args.cpu_sample = 8 << 20
+    else:
+        pat, text = make_text(args.bytes, corrupt=True)
     gen_s = time.perf_counter() - t0
     t0 = time.perf_counter()
     parser = S.Parser(pat)
@@ -438,15 +448,20 @@ def main():
     khash = kernel_hash()
     roof = {"bound": "hbm", "achieved": round(algo / (build_ms * 1e-3) / 1e9, 2), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(algo / (build_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-            "traffic": traffic_from_profiles("single_re_large", khash), "kernel": "k_build",
+            "traffic": traffic_from_profiles("single_re_large" if args.workload == "single" else "record_re",
+                                             khash), "kernel": "k_build",
             "algorithmic_bytes": algo}
     out = {
         "metric": METRIC, "value": round(n / (ms * 1e-3) / 1e9, 3), "unit": "GB/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
-        "config": {"workload": "single-RE large text: seeded random RE (depth 7, 40 operators, 26 letters, "
-                               "seed %d), %d-byte text sampled from its language with 5%% random-byte "
-                               "corruption blocks" % (RE_SEED, n),
+        "config": {"workload": ("single-RE large text: seeded random RE (depth 7, 40 operators, 26 letters, "
+                                "seed %d), %d-byte text sampled from its language with 5%% random-byte "
+                                "corruption blocks" % (RE_SEED, n)) if args.workload == "single" else
+                               ("record RE with L2-resident tables: CSV-like traffic records (timestamp digits, "
+                                "':' '-' ',' separators, 3-8 numeric fields, optional quoted field, newline) under "
+                                "one star over 123 byte classes, %d-byte text of records (seed %d), field "
+                                "lengths 1-12" % (n, RECORD_SEED)),
                    "text_bytes": n, "words_per_column": W, "segments": parser.nseg,
                    "fwd_states": parser.info.fwd_states, "rev_states": parser.info.rev_states,
                    "table_placement": "lds" if parser.info.placement == 0 else "l2",
