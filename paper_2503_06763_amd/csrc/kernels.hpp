@@ -116,10 +116,19 @@ struct TextRef {
     uint64_t *scalars;
 };
 
+// Text and output buffers are global memory.  The pointers are made in the
+// global address space and then converted, so the compiler emits global (not
+// flat) loads and stores: flat accesses share a wait counter with LDS, and
+// every LDS wait would then wait for the text loads and column stores too.
+template <class T>
+__device__ inline T *global_ptr(uint64_t a) {
+    using G = __attribute__((address_space(1))) T;
+    return (T *)((G *)a);
+}
+
 __device__ inline TextRef text_ref(const Job &jb, uint32_t t) {
     const uint64_t *d = jb.ntexts == 1 ? jb.d0 : jb.tdesc + 4ull * t;
-    return {reinterpret_cast<const uint8_t *>(d[0]), d[1], reinterpret_cast<uint64_t *>(d[2]),
-            reinterpret_cast<uint64_t *>(d[3])};
+    return {global_ptr<const uint8_t>(d[0]), d[1], global_ptr<uint64_t>(d[2]), global_ptr<uint64_t>(d[3])};
 }
 
 __device__ inline uint32_t first_chunk(const Job &jb, uint32_t t) {
@@ -289,10 +298,38 @@ __device__ inline void run_group(const uint8_t *text, uint64_t lo, uint64_t hi, 
                 }
             }
         }
-        uint32_t top = 0;
+        // compact the live runs to the front so that the wavefront bound below
+        // counts live runs, not the highest live slot; entries whose run died
+        // point to slot 15 (no slot: final state 0)
+        uint32_t live = 0;
 #pragma unroll
-        for (int j = 0; j < kGroup; ++j)
-            if (st[j]) top = j + 1;
+        for (int j = 0; j < kGroup; ++j) live |= (st[j] != 0 ? 1u : 0u) << j;
+        uint32_t nidx = 0;                       // new slot of slot j in nibble j (15: dead)
+#pragma unroll
+        for (int j = 0; j < kGroup; ++j) {
+            const uint32_t ix = ((live >> j) & 1u) ? static_cast<uint32_t>(__builtin_popcount(live & ((1u << j) - 1u)))
+                                                   : 15u;
+            nidx |= ix << (4 * j);
+        }
+        uint32_t ns[kGroup];
+#pragma unroll
+        for (int t = 0; t < kGroup; ++t) {
+            ns[t] = 0;
+#pragma unroll
+            for (int j = t; j < kGroup; ++j)
+                if (((nidx >> (4 * j)) & 15u) == static_cast<uint32_t>(t)) ns[t] = st[j];
+        }
+        uint32_t na = 0;
+#pragma unroll
+        for (int k = 0; k < kGroup; ++k) {
+            const uint32_t a = (alias >> (4 * k)) & 15u;
+            const uint32_t m = a < kGroup ? (nidx >> (4 * a)) & 15u : 15u;
+            na |= m << (4 * k);
+        }
+        alias = na;
+#pragma unroll
+        for (int t = 0; t < kGroup; ++t) st[t] = ns[t];
+        const uint32_t top = static_cast<uint32_t>(__builtin_popcount(live));
         nl = 0;
 #pragma unroll
         for (int j = kGroup; j >= 1; --j)
@@ -311,15 +348,20 @@ __device__ inline void run_group(const uint8_t *text, uint64_t lo, uint64_t hi, 
         for (uint64_t p = hi; p-- > lo + body;) step(text[p]);
     const uint64_t nblk = body >> 4;
     const uint4 *vp = reinterpret_cast<const uint4 *>(text + lo);
+    // 16-byte blocks in processing order; the next block is loaded while the
+    // current one is consumed, so the wave does not wait on HBM per block
+    auto blk = [&](uint64_t k) { return vp[FWD ? k : nblk - 1 - k]; };
+    uint4 v = nblk ? blk(0) : uint4{0, 0, 0, 0};
     for (uint64_t k = 0; k < nblk; ++k) {
+        const uint4 nv = k + 1 < nblk ? blk(k + 1) : v;
         if ((k & 3) == 3 && !settle()) return;
-        const uint4 v = vp[FWD ? k : nblk - 1 - k];
         const uint32_t wd[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
         for (int t = 0; t < 16; ++t) {
             const int tt = FWD ? t : 15 - t;
             step((wd[tt >> 2] >> ((tt & 3) * 8)) & 0xffu);
         }
+        v = nv;
     }
     if (FWD)
         for (uint64_t p = lo + body; p < hi; ++p) step(text[p]);
@@ -745,8 +787,9 @@ __device__ inline uint32_t wave_max_u32(uint32_t v) {
 }
 
 constexpr int kBuildThreads = 512;             // 8 wavefronts
-constexpr int kHalf = 32;                      // positions per staged half window
-constexpr int kStageRow = kHalf + 1;           // padded: lanes fall in distinct banks
+constexpr int kStageCols = 32;                 // columns per staged part of a window
+constexpr int kParts = 64 / kStageCols;
+constexpr int kStageRow = kStageCols + 1;      // padded: lanes fall in distinct banks
 constexpr int kStageBytes = kBuildThreads * kStageRow * 4;
 
 // Fused builder & merger.  Each lane owns one chunk and writes its columns
@@ -838,30 +881,30 @@ __global__ __launch_bounds__(kBuildThreads) void k_build(Tabs tb, Job jb) {
         if (on) jb.bckpt[ck(jb, i, w)] = static_cast<uint16_t>(b);
         const uint32_t len_now = on ? lenA : 0;
 #pragma unroll
-        for (int h = 1; h >= 0; --h) {
-            // columns a0+32h .. a0+32h+31 of window w, right to left
+        for (int h = kParts - 1; h >= 0; --h) {
+            // columns a0+S*h .. a0+S*h+S-1 of window w (S = kStageCols), right to left
 #pragma unroll
-            for (int u = kHalf - 1; u >= 0; --u) {
-                const int t = h * kHalf + u;
+            for (int u = kStageCols - 1; u >= 0; --u) {
+                const int t = h * kStageCols + u;
                 if (on && t < static_cast<int>(lenA)) {
                     b = T.rd[b * C + byte_of(cwA, t)];    // now the backward id at column a0+t
                     mine[u] = fwA[t] | (b << 16);
                 }
-                const int tf = (1 - h) * kHalf + (kHalf - 1 - u);   // forward step of window w-1
+                const int tf = (kParts - 1 - h) * kStageCols + (kStageCols - 1 - u);   // forward step of window w-1
                 if (nxt) {
                     fwB[tf] = g;
                     g = T.fd[g * C + byte_of(cwB, tf)];
                 }
             }
             wave_sync();
-            // write columns a0+32h .. of every chunk of the wavefront
+            // write columns a0+S*h .. of every chunk of the wavefront
             for (int j = 0; j < 64; ++j) {
                 const uint32_t lj = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(len_now), j));
-                const uint32_t np = lj > static_cast<uint32_t>(h * kHalf)
-                                        ? (lj - h * kHalf < static_cast<uint32_t>(kHalf) ? lj - h * kHalf : kHalf) : 0;
+                const uint32_t np = lj > static_cast<uint32_t>(h * kStageCols)
+                                        ? (lj - h * kStageCols < static_cast<uint32_t>(kStageCols) ? lj - h * kStageCols : kStageCols) : 0;
                 if (np == 0) continue;
-                uint64_t *region = reinterpret_cast<uint64_t *>(readlane_u64(reinterpret_cast<uint64_t>(out + a0A * W), j)) +
-                                   static_cast<uint64_t>(h * kHalf) * W;
+                uint64_t *region = global_ptr<uint64_t>(readlane_u64(reinterpret_cast<uint64_t>(out + a0A * W), j)) +
+                                   static_cast<uint64_t>(h * kStageCols) * W;
                 const uint32_t *sj = wave_rows + j * kStageRow;
                 const uint32_t nwords = np * W;
                 for (uint32_t e = lane; e < nwords; e += 64) {
