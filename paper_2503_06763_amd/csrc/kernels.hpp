@@ -59,6 +59,11 @@ struct Tabs {
     const uint64_t *folseg;     // nseg x W
     const uint16_t *fsole;      // per forward state: its only segment, or kNoSole
     const uint16_t *rsole;      // per backward state
+    // offset form of the transition tables (present when off16): an entry is
+    // the byte offset of the next state's row, the class map gives byte
+    // offsets of the classes, so a step is one add and one lookup
+    const uint16_t *fdo, *rdo, *cls2;
+    uint32_t off16;
     uint32_t fhmask, rhmask;
     uint32_t C, W, NL;          // classes, words, C + 1
     uint32_t nf, nr;            // table sizes including id 0
@@ -279,7 +284,7 @@ __device__ inline void load_window(const uint8_t *text, uint64_t a0, uint32_t le
 // loads.  Runs that reach the same state are merged (equal states have equal
 // futures); `alias` maps entry k of the group to the slot holding its run.
 // Slots dead in every lane of the wavefront are skipped.
-template <bool FWD>
+template <bool FWD, bool OFF>
 __device__ inline void run_group(const uint8_t *text, uint64_t lo, uint64_t hi, const uint16_t *cls,
                                  const uint16_t *delta, uint32_t C, uint32_t st[kGroup],
                                  uint32_t &alias) {
@@ -338,9 +343,16 @@ __device__ inline void run_group(const uint8_t *text, uint64_t lo, uint64_t hi, 
     };
     auto step = [&](uint32_t byte) {
         const uint32_t cl = cls[byte];
+        if constexpr (OFF) {   // st and cl are byte offsets into the table
+            const uint8_t *db = reinterpret_cast<const uint8_t *>(delta);
 #pragma unroll
-        for (int j = 0; j < kGroup; ++j)
-            if (j < static_cast<int>(nl)) st[j] = delta[st[j] * C + cl];
+            for (int j = 0; j < kGroup; ++j)
+                if (j < static_cast<int>(nl)) st[j] = *reinterpret_cast<const uint16_t *>(db + st[j] + cl);
+        } else {
+#pragma unroll
+            for (int j = 0; j < kGroup; ++j)
+                if (j < static_cast<int>(nl)) st[j] = delta[st[j] * C + cl];
+        }
     };
     const uint64_t body = (hi - lo) & ~15ull;
     if (!settle()) return;
@@ -367,17 +379,27 @@ __device__ inline void run_group(const uint8_t *text, uint64_t lo, uint64_t hi, 
         for (uint64_t p = lo + body; p < hi; ++p) step(text[p]);
 }
 
-template <bool LDS>
+// OFF: the runs step through the offset form of the tables; states are byte
+// offsets (id * 2C) until the end ids are stored.
+template <bool LDS, bool OFF>
 __global__ __launch_bounds__(256) void k_reach(Tabs tb, Job jb) {
     extern __shared__ __align__(16) uint8_t smem[];
-    Lookup<LDS> lk = stage_tables<LDS>(tb, smem, true, true);
+    Tabs ts = tb;
+    if constexpr (OFF) {
+        ts.classmap = tb.cls2;
+        ts.fdelta = tb.fdo;
+        ts.rdelta = tb.rdo;
+    }
+    Lookup<LDS> lk = stage_tables<LDS>(ts, smem, true, true);
+    const uint32_t c2 = OFF ? 2 * tb.C : 1;     // state id -> offset factor
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= jb.c) return;
     const ChunkCtx cx = chunk_ctx(jb, i);
     const uint8_t *text = cx.tr.text;
     const uint64_t lo = cx.lo, hi = cx.hi;
-    const uint32_t la = boundary_list(tb, lk.cls, text, cx.tr.n, jb.s, cx.ct, cx.li);
-    const uint32_t lb = boundary_list(tb, lk.cls, text, cx.tr.n, jb.s, cx.ct, cx.li + 1);
+    const uint16_t *bcls = OFF ? tb.classmap : lk.cls;
+    const uint32_t la = boundary_list(tb, bcls, text, cx.tr.n, jb.s, cx.ct, cx.li);
+    const uint32_t lb = boundary_list(tb, bcls, text, cx.tr.n, jb.s, cx.ct, cx.li + 1);
     const uint32_t xa0 = tb.xoff[la], na = tb.xoff[la + 1] - xa0;
     const uint32_t xb0 = tb.xoff[lb], nb = tb.xoff[lb + 1] - xb0;
     // scan items: forward item i maps X_i -> X_{i+1}; backward item c-1-i maps X_{i+1} -> X_i
@@ -392,10 +414,10 @@ __global__ __launch_bounds__(256) void k_reach(Tabs tb, Job jb) {
         uint32_t alias = 0;
 #pragma unroll
         for (int k = 0; k < kGroup; ++k) {
-            st[k] = (g0 + k < na) ? tb.fsingle[tb.xlist[xa0 + g0 + k]] : 0;
+            st[k] = (g0 + k < na) ? tb.fsingle[tb.xlist[xa0 + g0 + k]] * c2 : 0;
             alias |= static_cast<uint32_t>(k) << (4 * k);
         }
-        run_group<true>(text, lo, hi, lk.cls, lk.fd, tb.C, st, alias);
+        run_group<true, OFF>(text, lo, hi, lk.cls, lk.fd, tb.C, st, alias);
 #pragma unroll
         for (int k = 0; k < kGroup; ++k) {
             if (g0 + k < na) {
@@ -403,7 +425,7 @@ __global__ __launch_bounds__(256) void k_reach(Tabs tb, Job jb) {
 #pragma unroll
                 for (int q = 0; q < kGroup; ++q)
                     if (sl == static_cast<uint32_t>(q)) v = st[q];
-                jb.R[static_cast<uint64_t>(g0 + k) * jb.c + i] = static_cast<uint16_t>(v);
+                jb.R[static_cast<uint64_t>(g0 + k) * jb.c + i] = static_cast<uint16_t>(OFF ? v / c2 : v);
             }
         }
     }
@@ -413,10 +435,10 @@ __global__ __launch_bounds__(256) void k_reach(Tabs tb, Job jb) {
         uint32_t alias = 0;
 #pragma unroll
         for (int k = 0; k < kGroup; ++k) {
-            st[k] = (g0 + k < nb) ? tb.rsingle[tb.xlist[xb0 + g0 + k]] : 0;
+            st[k] = (g0 + k < nb) ? tb.rsingle[tb.xlist[xb0 + g0 + k]] * c2 : 0;
             alias |= static_cast<uint32_t>(k) << (4 * k);
         }
-        run_group<false>(text, lo, hi, lk.cls, lk.rd, tb.C, st, alias);
+        run_group<false, OFF>(text, lo, hi, lk.cls, lk.rd, tb.C, st, alias);
 #pragma unroll
         for (int k = 0; k < kGroup; ++k) {
             if (g0 + k < nb) {
@@ -424,7 +446,7 @@ __global__ __launch_bounds__(256) void k_reach(Tabs tb, Job jb) {
 #pragma unroll
                 for (int q = 0; q < kGroup; ++q)
                     if (sl == static_cast<uint32_t>(q)) v = st[q];
-                jb.Rh[static_cast<uint64_t>(g0 + k) * jb.c + i] = static_cast<uint16_t>(v);
+                jb.Rh[static_cast<uint64_t>(g0 + k) * jb.c + i] = static_cast<uint16_t>(OFF ? v / c2 : v);
             }
         }
     }

@@ -68,6 +68,18 @@ std::vector<uint16_t> sole_segments(const HostTable &t, uint32_t W) {
 slpf_status upload(slpf_parser *p) {
     const HostAutomaton &A = p->A;
     const std::vector<uint16_t> fsole = sole_segments(A.fwd, A.W), rsole = sole_segments(A.rev, A.W);
+    // offset form of the transition tables when byte offsets fit in u16
+    const uint32_t c2 = 2 * A.C;
+    const bool off16 = size_t(A.fwd.nstates) * c2 <= 65535 && size_t(A.rev.nstates) * c2 <= 65535;
+    std::vector<uint16_t> fdo, rdo, cls2;
+    if (off16) {
+        fdo.resize(A.fwd.delta.size());
+        rdo.resize(A.rev.delta.size());
+        cls2.resize(256);
+        for (size_t k = 0; k < fdo.size(); ++k) fdo[k] = static_cast<uint16_t>(A.fwd.delta[k] * c2);
+        for (size_t k = 0; k < rdo.size(); ++k) rdo[k] = static_cast<uint16_t>(A.rev.delta[k] * c2);
+        for (size_t k = 0; k < 256; ++k) cls2[k] = static_cast<uint16_t>(A.classmap[k] * 2);
+    }
     struct Part {
         const void *src;
         size_t bytes;
@@ -88,6 +100,9 @@ slpf_status upload(slpf_parser *p) {
         {A.folseg.data(), A.folseg.size() * 8, 0},
         {fsole.data(), fsole.size() * 2, 0},
         {rsole.data(), rsole.size() * 2, 0},
+        {fdo.data(), fdo.size() * 2, 0},
+        {rdo.data(), rdo.size() * 2, 0},
+        {cls2.data(), cls2.size() * 2, 0},
     };
     size_t total = 0;
     for (auto &pt : parts) {
@@ -120,6 +135,10 @@ slpf_status upload(slpf_parser *p) {
     t.folseg = reinterpret_cast<const uint64_t *>(at(11));
     t.fsole = reinterpret_cast<const uint16_t *>(at(12));
     t.rsole = reinterpret_cast<const uint16_t *>(at(13));
+    t.off16 = off16 ? 1u : 0u;
+    t.fdo = off16 ? reinterpret_cast<const uint16_t *>(at(14)) : nullptr;
+    t.rdo = off16 ? reinterpret_cast<const uint16_t *>(at(15)) : nullptr;
+    t.cls2 = off16 ? reinterpret_cast<const uint16_t *>(at(16)) : nullptr;
     t.fhmask = static_cast<uint32_t>(A.fwd.hash.size() - 1);
     t.rhmask = static_cast<uint32_t>(A.rev.hash.size() - 1);
     t.C = A.C;
@@ -478,8 +497,12 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
     mark(0);
     if (c) {
         // reach
-        if (lds) hipLaunchKernelGGL(k_reach<true>, dim3(blocks), dim3(256), lds_bytes, stream, tb, jb);
-        else hipLaunchKernelGGL(k_reach<false>, dim3(blocks), dim3(256), 0, stream, tb, jb);
+        if (lds && tb.off16)
+            hipLaunchKernelGGL((k_reach<true, true>), dim3(blocks), dim3(256), lds_bytes, stream, tb, jb);
+        else if (lds)
+            hipLaunchKernelGGL((k_reach<true, false>), dim3(blocks), dim3(256), lds_bytes, stream, tb, jb);
+        else
+            hipLaunchKernelGGL((k_reach<false, false>), dim3(blocks), dim3(256), 0, stream, tb, jb);
     }
     mark(1);
     if (c) {
