@@ -933,7 +933,8 @@ __global__ __launch_bounds__(kBuildThreads) void k_build(Tabs tb, Job jb) {
                     const uint32_t p = static_cast<uint32_t>((static_cast<uint64_t>(e) * tb.wmagic) >> 32);
                     const uint32_t ww = e - p * W;
                     const uint32_t v = sj[p];
-                    region[e] = T.fb[(v & 0xffffu) * W + ww] & T.rb[(v >> 16) * W + ww];
+                    // streaming store: the SLPF is not read back by this kernel
+                    __builtin_nontemporal_store(T.fb[(v & 0xffffu) * W + ww] & T.rb[(v >> 16) * W + ww], region + e);
                 }
             }
             wave_sync();
@@ -1411,8 +1412,10 @@ __global__ __launch_bounds__(256) void k_count_factor(Job jb) {
 // product of the text's factors modulo 2^64 (0 for a rejected text); status
 // 2 when not requested, 1 when the general count failed on a chunk of the
 // text, 3 when a join set was not a table state.
-__global__ __launch_bounds__(256) void k_text_scalars(Tabs tb, Job jb, int count) {
-    __shared__ uint64_t part[256];
+constexpr int kScalarThreads = 1024;
+
+__global__ __launch_bounds__(kScalarThreads) void k_text_scalars(Tabs tb, Job jb, int count) {
+    __shared__ uint64_t part[kScalarThreads];
     __shared__ uint32_t failed;
     const uint32_t t = blockIdx.x, th = threadIdx.x;
     const TextRef tr = text_ref(jb, t);
@@ -1442,16 +1445,26 @@ __global__ __launch_bounds__(256) void k_text_scalars(Tabs tb, Job jb, int count
         const uint32_t c0 = first_chunk(jb, t), c1 = first_chunk(jb, t + 1);
         if (th == 0) failed = 0;
         __syncthreads();
-        uint64_t acc = 1;
+        // eight independent products per thread keep eight loads in flight
+        uint64_t acc[8] = {1, 1, 1, 1, 1, 1, 1, 1};
         bool bad = false;
-        for (uint32_t k = c0 + th; k < c1; k += blockDim.x) {
-            acc *= jb.factor[k];
+        const uint32_t stride = blockDim.x;
+        uint32_t k = c0 + th;
+        for (; k + 7 * stride < c1; k += 8 * stride) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                acc[u] *= jb.factor[k + u * stride];
+                bad = bad || jb.tbig_idx[k + u * stride] == kOverflow;
+            }
+        }
+        for (; k < c1; k += stride) {
+            acc[0] *= jb.factor[k];
             bad = bad || jb.tbig_idx[k] == kOverflow;
         }
         if (bad) atomicOr(&failed, 1u);
-        part[th] = acc;
+        part[th] = acc[0] * acc[1] * acc[2] * acc[3] * acc[4] * acc[5] * acc[6] * acc[7];
         __syncthreads();
-        for (uint32_t h = 128; h; h >>= 1) {
+        for (uint32_t h = kScalarThreads / 2; h; h >>= 1) {
             if (th < h) part[th] *= part[th + h];
             __syncthreads();
         }

@@ -600,7 +600,7 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
         hipLaunchKernelGGL(k_count_chunk, dim3(std::min<uint32_t>(c, 1024)), dim3(64), 0, stream, tb, jb);
         hipLaunchKernelGGL(k_count_factor, dim3((c + nt + 255) / 256), dim3(256), 0, stream, jb);
     }
-    hipLaunchKernelGGL(k_text_scalars, dim3(nt), dim3(256), 0, stream, tb, jb, count ? 1 : 0);
+    hipLaunchKernelGGL(k_text_scalars, dim3(nt), dim3(kScalarThreads), 0, stream, tb, jb, count ? 1 : 0);
     mark(5);
     if (ev_err != hipSuccess) return SLPF_E_ARG;
     return hip_ok(hipGetLastError());
