@@ -90,6 +90,23 @@ def run_gpu(parser, text_np, steps, warmup, chunk_bytes):
     return ms, phase, (int(s[0]), int(s[1]), int(s[2])), cols
 
 
+def run_recognize(parser, text_np, steps, warmup, chunk_bytes):
+    """Recogniser mode (forward reach and forward join only) on the same text."""
+    import numpy as np
+    import torch
+    dev = torch.device("cuda:0")
+    text = torch.from_numpy(text_np).to(dev)
+    for _ in range(warmup):
+        sc = parser.recognize(text, chunk_bytes)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sc = parser.recognize(text, chunk_bytes)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    return ms, int(sc.cpu().numpy().view(np.uint64)[0])
+
+
 def cpu_baseline(pat, text_np, sample_bytes):
     from oracle.oracle import Oracle
     o = Oracle(pat)
@@ -473,6 +490,11 @@ def main():
         "roofline": roof,
     }
     del _
+    torch.cuda.empty_cache()
+    rms, racc = run_recognize(parser, text, args.steps, args.warmup, args.chunk_bytes)
+    out["recognizer"] = {"value": round(n / (rms * 1e-3) / 1e9, 3), "unit": "GB/s", "ms_per_step": round(rms, 4),
+                         "accepted": racc, "what": "forward reach and forward join only (accept flag, no SLPF)"}
+    print("recognizer: %.3f ms/step accepted %d" % (rms, racc), file=sys.stderr, flush=True)
     torch.cuda.empty_cache()
     if args.copy_calib:
         a = torch.empty(args.copy_calib, dtype=torch.uint8, device="cuda:0")

@@ -140,7 +140,10 @@ uint64_t slpf_forest_bytes(const slpf_parser *p, uint64_t n);
 
 enum {
     SLPF_PARSE_NO_COUNT = 1u << 0,      /* skip the tree count (scalars[1] = 0, [2] = 2) */
-    SLPF_PARSE_FORCE_L2 = 1u << 1       /* read transition tables through L2 even if LDS fits */
+    SLPF_PARSE_FORCE_L2 = 1u << 1,      /* read transition tables through L2 even if LDS fits */
+    SLPF_PARSE_RECOGNIZE = 1u << 2      /* recogniser only (Sect. 3.2: the forward reacher and joiner
+                                           decide membership): scalars[0] = accept, [1] = 0, [2] = 2;
+                                           no column is written (columns_dev may be NULL) */
 };
 
 typedef struct {

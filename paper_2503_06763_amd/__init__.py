@@ -25,6 +25,7 @@ COMPILE_HOST_ONLY = 1
 
 PARSE_NO_COUNT = 1
 PARSE_FORCE_L2 = 2
+PARSE_RECOGNIZE = 4
 
 EXPORTS = ["slpf_compile", "slpf_parser_destroy", "slpf_parser_info_get", "slpf_segment_text",
            "slpf_table_dump", "slpf_forest_bytes", "slpf_parse", "slpf_parse_batch", "slpf_tune", "slpf_parser_trim",
@@ -254,7 +255,8 @@ class Parser:
                       trace.numel() * trace.element_size() if trace is not None else 0,
                       ctypes.cast(ev, ctypes.POINTER(ctypes.c_void_p)) if ev is not None else None,
                       len(events) if events is not None else 0, 0)
-        f = Forest(columns.data_ptr(), columns.numel() * columns.element_size(), scalars.data_ptr())
+        f = Forest(columns.data_ptr() if columns is not None else None,
+                   columns.numel() * columns.element_size() if columns is not None else 0, scalars.data_ptr())
         st = self._L.slpf_parse(self._h, text.data_ptr() if n else None, n, ctypes.byref(o), ctypes.byref(f),
                                 ctypes.c_void_p(stream.cuda_stream))
         _check(st, "slpf_parse")
@@ -276,6 +278,15 @@ class Parser:
         self.parse_into(text, n, cols, sc, chunk_bytes, flags, tr, stream, events)
         return (cols, sc, tr) if trace else (cols, sc)
 
+
+    def recognize(self, text, chunk_bytes: int = 0, force_l2: bool = False, stream=None, events=None):
+        """Recogniser mode (forward reach and join only): returns the scalars
+        tensor [3] on the device (accept, 0, 2); no SLPF is written."""
+        import torch
+        sc = torch.empty(3, dtype=torch.int64, device=text.device)
+        flags = PARSE_RECOGNIZE | (PARSE_FORCE_L2 if force_l2 else 0)
+        self.parse_into(text, text.numel(), None, sc, chunk_bytes, flags, None, stream, events)
+        return sc
 
     def parse_batch_into(self, items, chunk_bytes: int = 0, flags: int = 0, stream=None, events=None):
         """Raw slpf_parse_batch.  ``items``: list of (text tensor or None, n, columns tensor,
@@ -302,7 +313,8 @@ class Parser:
         for k, (t, n, cols, sc) in enumerate(items):
             arr[k].text_dev = t.data_ptr() if (t is not None and n) else None
             arr[k].n = n
-            arr[k].out = Forest(cols.data_ptr(), cols.numel() * cols.element_size(), sc.data_ptr())
+            arr[k].out = Forest(cols.data_ptr() if cols is not None else None,
+                                cols.numel() * cols.element_size() if cols is not None else 0, sc.data_ptr())
         return arr
 
     def tune(self, items, count: bool = True, stream=None):

@@ -106,6 +106,7 @@ struct Job {
     uint32_t *ovf;              // chunks left to the general count kernel (count in flags[3])
     uint64_t *tbig;             // [pool][64*64]
     uint32_t big_pool;
+    uint32_t fwd_only;          // recogniser: forward runs and forward join only
 };
 
 constexpr int kDedupEvery = 32;
@@ -429,8 +430,8 @@ __global__ __launch_bounds__(256) void k_reach(Tabs tb, Job jb) {
             }
         }
     }
-    // backward runs from X_{i+1}
-    for (uint32_t g0 = 0; __any(g0 < nb); g0 += kGroup) {
+    // backward runs from X_{i+1} (not for the recogniser)
+    for (uint32_t g0 = 0; !jb.fwd_only && __any(g0 < nb); g0 += kGroup) {
         uint32_t st[kGroup];
         uint32_t alias = 0;
 #pragma unroll
@@ -462,7 +463,7 @@ __global__ __launch_bounds__(256) void k_reach(Tabs tb, Job jb) {
         }
         jb.Mf[static_cast<uint64_t>(i) * tb.emax + m] = row;
     }
-    for (uint32_t m = 0; m < nb; ++m) {
+    for (uint32_t m = 0; m < (jb.fwd_only ? 0u : nb); ++m) {
         uint32_t id = jb.Rh[static_cast<uint64_t>(m) * jb.c + i];
         const uint64_t *bits = tb.rbits + static_cast<uint64_t>(id) * W;
         uint64_t row = 0;
@@ -1407,7 +1408,8 @@ __global__ __launch_bounds__(256) void k_count_factor(Job jb) {
     jb.factor[g] = f * d;
 }
 
-// Per-text scalars: one block per text.  Empty text: column 0 = I & F and
+// Per-text scalars: one block per text (count: 0 not requested, 1 requested,
+// 2 recogniser).  Empty text: column 0 = I & F and
 // one tree per initial-and-final segment.  Otherwise the count is the
 // product of the text's factors modulo 2^64 (0 for a rejected text); status
 // 2 when not requested, 1 when the general count failed on a chunk of the
@@ -1419,6 +1421,22 @@ __global__ __launch_bounds__(kScalarThreads) void k_text_scalars(Tabs tb, Job jb
     __shared__ uint32_t failed;
     const uint32_t t = blockIdx.x, th = threadIdx.x;
     const TextRef tr = text_ref(jb, t);
+    if (count == 2) {   // recogniser: accept from the forward join alone
+        if (th == 0) {
+            uint64_t any = 0;
+            if (tr.n == 0) {
+                const uint64_t *fb = tb.fbits + static_cast<uint64_t>(tb.fstart) * tb.W;
+                const uint64_t *rb = tb.rbits + static_cast<uint64_t>(tb.rstart) * tb.W;
+                for (uint32_t w = 0; w < tb.W; ++w) any |= fb[w] & rb[w];
+            } else {
+                any = jb.fout[first_chunk(jb, t + 1) - 1];
+            }
+            tr.scalars[0] = any ? 1 : 0;
+            tr.scalars[1] = 0;
+            tr.scalars[2] = jb.flags[0] ? 3 : 2;
+        }
+        return;
+    }
     if (tr.n == 0) {
         if (th == 0) {
             const uint64_t *fb = tb.fbits + static_cast<uint64_t>(tb.fstart) * tb.W;

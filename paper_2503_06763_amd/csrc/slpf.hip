@@ -330,7 +330,8 @@ namespace {
 slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf_parse_opts *opts,
                     hipStream_t stream) {
     const uint32_t flags = opts ? opts->flags : 0;
-    const bool count = !(flags & SLPF_PARSE_NO_COUNT);
+    const bool recog = (flags & SLPF_PARSE_RECOGNIZE) != 0;
+    const bool count = !(flags & SLPF_PARSE_NO_COUNT) && !recog;
     if (hipSetDevice(p->device) != hipSuccess) return SLPF_E_DEVICE;
     Tabs tb = p->tabs;
     const uint32_t W = tb.W, E = tb.emax;
@@ -350,6 +351,7 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
 
     Job jb{};
     jb.ntexts = nt;
+    jb.fwd_only = recog ? 1u : 0u;
     jb.s = s;
     jb.c = c;
     if (T == 1) {
@@ -529,6 +531,7 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
                 }
             }
         const size_t grp_lds = size_t(2) * 64 * E * 8;
+        const uint32_t ndir = recog ? 1u : 2u;    // the recogniser joins forward only
         for (size_t l = 0; l < TL; ++l) {
             ScanOut o{};
             for (int d = 0; d < 2; ++d) {
@@ -540,7 +543,7 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
                 o.pcst[d] = ptr(jpcst[d][l]);
                 o.pcv[d] = u64p(jpcv[d][l]);
             }
-            hipLaunchKernelGGL(k_compose, dim3(jl[l + 1], 2), dim3(64), grp_lds, stream, lv[l], o, E);
+            hipLaunchKernelGGL(k_compose, dim3(jl[l + 1], ndir), dim3(64), grp_lds, stream, lv[l], o, E);
         }
         for (size_t l = TL; l-- > 0;) {
             ScanPrefix pf{};
@@ -557,17 +560,17 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
                     pf.vout[d] = nullptr;
                 }
             }
-            hipLaunchKernelGGL(k_expand, dim3((jl[l] + 255) / 256, 2), dim3(256), 0, stream, lv[l], pf, E);
+            hipLaunchKernelGGL(k_expand, dim3((jl[l] + 255) / 256, ndir), dim3(256), 0, stream, lv[l], pf, E);
         }
     }
     mark(2);
-    if (c) hipLaunchKernelGGL(k_starts, dim3(blocks), dim3(256), 0, stream, tb, jb);
+    if (c && !recog) hipLaunchKernelGGL(k_starts, dim3(blocks), dim3(256), 0, stream, tb, jb);
     mark(3);
 
     // build & merge: transition tables and bit sets in LDS when they fit
     const size_t tab_lds = (512 + (size_t(tb.nf) + tb.nr) * tb.C * 2 + 15) & ~size_t(15);
     const size_t bits_lds = (size_t(tb.nf) + tb.nr) * W * 8;
-    if (c) {
+    if (c && !recog) {
         const bool fit_tab = lds && kStageBytes + tab_lds <= p->lds_limit;
         const bool fit_bits = fit_tab && kStageBytes + tab_lds + bits_lds <= p->lds_limit;
         const uint32_t bblocks = (c + kBuildThreads - 1) / kBuildThreads;
@@ -600,16 +603,19 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
         hipLaunchKernelGGL(k_count_chunk, dim3(std::min<uint32_t>(c, 1024)), dim3(64), 0, stream, tb, jb);
         hipLaunchKernelGGL(k_count_factor, dim3((c + nt + 255) / 256), dim3(256), 0, stream, jb);
     }
-    hipLaunchKernelGGL(k_text_scalars, dim3(nt), dim3(kScalarThreads), 0, stream, tb, jb, count ? 1 : 0);
+    hipLaunchKernelGGL(k_text_scalars, dim3(nt), dim3(kScalarThreads), 0, stream, tb, jb, recog ? 2 : count ? 1 : 0);
     mark(5);
     if (ev_err != hipSuccess) return SLPF_E_ARG;
     return hip_ok(hipGetLastError());
 }
 
-slpf_status check_item(const slpf_parser *p, const uint8_t *text, uint64_t n, const slpf_forest *forest) {
-    if (!forest || !forest->columns_dev || !forest->scalars_dev) return SLPF_E_ARG;
+slpf_status check_item(const slpf_parser *p, const uint8_t *text, uint64_t n, const slpf_forest *forest,
+                       bool recog) {
+    if (!forest || !forest->scalars_dev) return SLPF_E_ARG;
     if (n && !text) return SLPF_E_ARG;
     if (reinterpret_cast<uintptr_t>(text) % 16 != 0) return SLPF_E_ARG;
+    if (recog) return SLPF_OK;   // no column is written
+    if (!forest->columns_dev) return SLPF_E_ARG;
     if (forest->capacity_bytes < slpf_forest_bytes(p, n)) return SLPF_E_CAPACITY;
     return SLPF_OK;
 }
@@ -624,7 +630,8 @@ slpf_status slpf_parse(const slpf_parser *cp, const uint8_t *text, uint64_t n, c
     if (!p || p->host_only) return SLPF_E_ARG;
     if (opts && opts->struct_size != sizeof(slpf_parse_opts)) return SLPF_E_ARG;
     if (opts && opts->chunk_bytes && (opts->chunk_bytes % 64 != 0)) return SLPF_E_ARG;
-    slpf_status st = check_item(p, text, n, forest);
+    const bool recog = opts && (opts->flags & SLPF_PARSE_RECOGNIZE);
+    slpf_status st = check_item(p, text, n, forest, recog);
     if (st != SLPF_OK) return st;
     slpf_text item{text, n, *forest};
     return run_job(p, &item, 1, opts, static_cast<hipStream_t>(hip_stream));
@@ -639,7 +646,8 @@ slpf_status slpf_parse_batch(const slpf_parser *cp, const slpf_text *items, size
     if (count == 0) return SLPF_OK;
     if (count > 0x7fffffffull) return SLPF_E_ARG;
     for (size_t t = 0; t < count; ++t) {
-        slpf_status st = check_item(p, items[t].text_dev, items[t].n, &items[t].out);
+        slpf_status st = check_item(p, items[t].text_dev, items[t].n, &items[t].out,
+                                    opts && (opts->flags & SLPF_PARSE_RECOGNIZE));
         if (st != SLPF_OK) return st;
     }
     return run_job(p, items, count, opts, static_cast<hipStream_t>(hip_stream));

@@ -173,3 +173,39 @@ def test_tree_count_paths():
         o, p = Oracle(pat), S.Parser(pat)
         for k in ks:
             check(pat, text, chunk_bytes=k, o=o, p=p)
+
+
+def test_recognizer_mode():
+    # forward reach and forward join only: the accept flag of every text equals
+    # the oracle's, alone and in a batch; no column is written
+    import torch
+    from gpu_util import device
+    device()
+    cases = [("(ab|a)*", [b"", b"a", b"abaaba", b"b", b"abb", b"z"]),
+             (regen.to_re(regen.plain_small_re()).decode(), None)]
+    tree = regen.plain_small_re()
+    base = textgen.sample_text(tree, 3, 20000).tobytes()
+    cases[1] = (cases[1][0], [base, base[:-1], base[:1000], base[:5000] + b"a" + base[5001:], b"c", b"abc"])
+    for seed in (3, 7):
+        rt = regen.random_re(400 + seed, n_ops=14, max_depth=5, alphabet=b"abcd")
+        x = textgen.sample_text(rt, seed, 9000)
+        cases.append((regen.to_re(rt).decode(), [x.tobytes(), textgen.corrupt(x, seed, 0.01, (1, 8)).tobytes()]))
+    for pat, texts in cases:
+        o, p = Oracle(pat), S.Parser(pat)
+        want = [o.parse(t)[1] for t in texts]
+        for k in (0, 64, 512):
+            got = []
+            for t in texts:
+                sc = p.recognize(to_device(t), chunk_bytes=k)
+                torch.cuda.synchronize()
+                s = sc.cpu().numpy().view(np.uint64)
+                got.append(bool(s[0]))
+                assert int(s[1]) == 0 and int(s[2]) == 2
+            assert got == want, (pat[:40], k, got, want)
+        # batched recogniser
+        dts = [to_device(t) for t in texts]
+        sc = torch.zeros((len(texts), 3), dtype=torch.int64, device="cuda:0")
+        p.parse_batch_into([(d, len(t), None, sc[j]) for j, (d, t) in enumerate(zip(dts, texts))],
+                           flags=S.PARSE_RECOGNIZE)
+        torch.cuda.synchronize()
+        assert [bool(v) for v in sc[:, 0].cpu().tolist()] == want
