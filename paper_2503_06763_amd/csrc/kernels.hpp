@@ -821,12 +821,12 @@ constexpr int kStageBytes = kBuildThreads * kStageRow * 4;
 // window from the right: the reverse DFA runs from the right edge while the
 // forward ids of the next window to the left are recomputed from its
 // checkpoint (two independent lookup chains per lane), and the (forward,
-// backward) id pair of every column goes to LDS.  Every 32 columns the
-// wavefront writes the staged columns of its 64 chunks, each chunk's columns
-// as one contiguous run of W-word columns starting on a 32-column boundary
-// (so on a 128-byte boundary for any W); lane e writes word e, 512
-// contiguous bytes per store instruction.  Wavefronts synchronize only with
-// themselves.
+// backward) id pair of every column goes to LDS.  Every kStageCols (32)
+// columns the wavefront writes the staged columns of its 64 chunks, each
+// chunk's columns as one contiguous run of W-word columns starting on a
+// 32-column boundary (so on a 128-byte boundary for any W); lane e writes word
+// e, 512 contiguous bytes per store instruction, as streaming (nontemporal)
+// stores.  Wavefronts synchronize only with themselves.
 template <bool TAB_LDS, bool BITS_LDS>
 __global__ __launch_bounds__(kBuildThreads) void k_build(Tabs tb, Job jb) {
     extern __shared__ __align__(16) uint8_t smem[];
