@@ -39,6 +39,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "slpf_internal.hpp"
 
@@ -176,7 +177,7 @@ __device__ inline ChunkCtx chunk_ctx(const Job &jb, uint32_t i) {
 
 constexpr int kGroup = 8;
 constexpr int kBigT = 64;
-constexpr int kVec = 16;                      // clean-column segments handled by the fast count
+constexpr int kVec = 12;                      // clean-column segments handled by the fast count
 constexpr uint32_t kRank1 = 0xffffffffu;       // chunk matrix held as v * pi * u^T
 constexpr uint32_t kOverflow = 0xfffffffeu;    // chunk left to the general count kernel
 
@@ -992,11 +993,11 @@ __device__ inline uint32_t wave_min(uint32_t v) {
     return v;
 }
 
-constexpr int kCountThreads = 512;
+constexpr int kCountThreads = 256;
 constexpr int kQuarter = 16;                                // columns staged per row fill
 constexpr int kCountRow = kQuarter + 1;                     // padded per-lane row of 16 columns
-constexpr int kCountSegWords = kVec;                        // two lists of kVec u16 segment ids
-constexpr int kCountLaneBytes = (kCountRow + kCountSegWords) * 4;
+constexpr int kCountY = 2 * kVec + 1;                       // two count vectors (u64), padded
+constexpr int kCountLaneBytes = kCountY * 8 + kCountRow * 4;
 constexpr int kCountLdsBytes = kCountThreads * kCountLaneBytes;
 
 // LDS offsets of the count kernel's staged tables after the per-lane areas:
@@ -1026,24 +1027,24 @@ __host__ __device__ inline CountLds count_lds(uint32_t nf, uint32_t nr, uint32_t
 //         column P_{i+1} (a forward vector DP from r1).
 // A clean column of an accepted text is non-empty and inside both of its
 // state sets, so it is the only segment of either state when that state's set
-// has one (the sole-segment tables); only columns where both sets hold
-// several segments are listed from the bit sets.  Between a singleton and any
-// column every arc exists (each segment of a clean column has a neighbour in
-// the next and in the previous one), so the follower relation is read only
-// between two ambiguous columns.  Per 64-byte window the forward ids come
-// from the build's checkpoint and the backward ids from its backward
-// checkpoint; each half window's (forward, backward) id pairs go to the
-// lane's LDS row, which the DP then walks.  Segment lists of the current and
-// the previous column live in the lane's LDS too, so the vector state in
-// registers is only the path counts.  Chunks with no singleton or with a
-// column above kVec segments go to the general kernel.
+// has one (the sole-segment tables).  Between a singleton and any column
+// every arc exists (each segment of a clean column has a neighbour in the next
+// and in the previous one), so arcs are looked at only between two ambiguous
+// columns, and there only the arcs themselves: a column is its bit set
+// bitsF[f] & bitsR[b], the arcs of a segment into the other column are its
+// follower row ANDed with that set, and count vectors are indexed by rank in
+// the column (kept in the lane's LDS, so a rank is an address).  Per 64-byte
+// window the forward ids come from the build's checkpoint and the backward ids
+// from its backward checkpoint; each quarter window's (forward, backward) ids
+// go to the lane's LDS row, which the DP then walks.  Chunks with no singleton
+// or with a column above kVec segments go to the general kernel.
 template <bool TAB_LDS, bool FULL>
 __global__ __launch_bounds__(kCountThreads) void k_count_fast(Tabs tb, Job jb) {
     extern __shared__ __align__(16) uint8_t smem[];
     if (jb.ntexts == 1 && text_ref(jb, 0).scalars[0] == 0) return;    // rejected text: no tree
     const uint32_t C = tb.C, W = tb.W;
-    uint32_t *row = reinterpret_cast<uint32_t *>(smem) + threadIdx.x * kCountRow;
-    uint16_t *segl = reinterpret_cast<uint16_t *>(smem + kCountThreads * kCountRow * 4) + threadIdx.x * 2 * kVec;
+    uint64_t *yb = reinterpret_cast<uint64_t *>(smem) + threadIdx.x * kCountY;   // yb[0..kVec), yb[kVec..2kVec)
+    uint32_t *row = reinterpret_cast<uint32_t *>(smem + kCountThreads * kCountY * 8) + threadIdx.x * kCountRow;
     // transition tables and sole-segment tables (and with FULL the bit sets
     // and follower sets) staged in LDS
     const uint16_t *cls, *fd, *rd, *fso, *rso;
@@ -1093,7 +1094,386 @@ __global__ __launch_bounds__(kCountThreads) void k_count_fast(Tabs tb, Job jb) {
         nwin = static_cast<uint32_t>((hi - lo + 63) / 64);
     }
     const uint32_t nwin_wave = wave_max_u32(nwin);
-    uint32_t xw[16], cw[16], fwp[32];            // window bytes, classes, forward ids (two per word)
+    uint32_t xw[16], cw[16], qs[4];              // window bytes, classes, forward id at each quarter start
+    uint32_t mp = 0, yc = 0;                     // previous column's size; its vector is yb + yc*kVec
+    uint32_t fp = 0, bp = 0;                     // previous column's state ids when it was ambiguous
+    uint64_t pi = 1, r1 = 0;
+    bool found = false, over = !act;
+
+    // a staged column: (f | b << 16) for the state ids, or (s << 16) when the
+    // clean column is the single segment s (f = 0, the empty set, never
+    // labels a column of an accepted text)
+    auto entry = [&](uint32_t f, uint32_t b) -> uint32_t {
+        uint32_t s = fso[f];
+        if (s == kNoSole) s = rso[b];
+        return s != kNoSole ? (s << 16) : (f | (b << 16));
+    };
+    auto word = [&](uint32_t f, uint32_t b, uint32_t w) -> uint64_t { return fbits[f * W + w] & rbits[b * W + w]; };
+    // number of segments of a staged column
+    auto column = [&](bool live, uint32_t e) -> uint32_t {
+        const bool multi = live && (e & 0xffffu) != 0;
+        uint32_t m = live ? 1u : 0u;
+        if (__any(multi)) {
+            if (multi) {
+                m = 0;
+                for (uint32_t w = 0; w < W; ++w) m += __popcll(word(e & 0xffffu, e >> 16, w));
+            }
+        }
+        return m;
+    };
+    // one DP step onto the column e (m segments) from the previous column (mp
+    // segments); fwd: the previous column is the left one; collapse: multiply
+    // pi at singletons (backward pass).  Each case other than singleton to
+    // singleton sits behind a wavefront-uniform test.
+    auto step = [&](bool live, uint32_t m, uint32_t e, bool fwd, bool collapse) {
+        uint64_t *yprev = yb + yc * kVec, *ycur = yb + (yc ^ 1u) * kVec;
+        const uint32_t f = e & 0xffffu, b = e >> 16;
+        const bool gen = live && m > 1 && mp > 1;
+        if (__any(gen)) {
+            if (gen && !fwd) {
+                // backward: y[k] over the current (left) column gathers the counts of
+                // the followers of its k-th segment in the previous (right) column
+                uint32_t k = 0;
+                for (uint32_t w = 0; w < W; ++w) {
+                    uint64_t cv = word(f, b, w);
+                    while (cv) {
+                        const uint32_t sk = w * 64 + __builtin_ctzll(cv);
+                        cv &= cv - 1;
+                        uint64_t acc = 0;
+                        uint32_t pre = 0;
+                        for (uint32_t v = 0; v < W; ++v) {
+                            const uint64_t pv = word(fp, bp, v);
+                            uint64_t a = fol[static_cast<uint64_t>(sk) * W + v] & pv;
+                            while (a) {
+                                const uint32_t s = __builtin_ctzll(a);
+                                a &= a - 1;
+                                acc += yprev[pre + __popcll(pv & low_mask(s))];
+                            }
+                            pre += __popcll(pv);
+                        }
+                        ycur[k++] = acc;
+                    }
+                }
+            } else if (gen) {
+                // forward: each segment of the previous (left) column adds its count
+                // to its followers in the current (right) column
+                for (uint32_t k = 0; k < m; ++k) ycur[k] = 0;
+                uint32_t j = 0;
+                for (uint32_t v = 0; v < W; ++v) {
+                    uint64_t pv = word(fp, bp, v);
+                    while (pv) {
+                        const uint32_t sj = v * 64 + __builtin_ctzll(pv);
+                        pv &= pv - 1;
+                        const uint64_t val = yprev[j++];
+                        uint32_t pre = 0;
+                        for (uint32_t w = 0; w < W; ++w) {
+                            const uint64_t cwv = word(f, b, w);
+                            uint64_t a = fol[static_cast<uint64_t>(sj) * W + w] & cwv;
+                            while (a) {
+                                const uint32_t s = __builtin_ctzll(a);
+                                a &= a - 1;
+                                ycur[pre + __popcll(cwv & low_mask(s))] += val;
+                            }
+                            pre += __popcll(cwv);
+                        }
+                    }
+                }
+            }
+        }
+        const bool sum = live && m == 1 && mp > 1;     // every segment of the previous column reaches the singleton
+        if (__any(sum)) {
+            if (sum) {
+                uint64_t t = 0;
+                for (uint32_t j = 0; j < mp; ++j) t += yprev[j];
+                yprev[0] = t;
+            }
+        }
+        const bool bcast = live && m > 1 && mp == 1;   // the singleton reaches every segment of this column
+        if (__any(bcast)) {
+            if (bcast) {
+                const uint64_t y0 = yprev[0];
+                for (uint32_t k = 0; k < m; ++k) ycur[k] = y0;
+            }
+        }
+        if (collapse && live && m == 1 && mp > 1) {
+            pi *= yprev[0];
+            yprev[0] = 1;
+        }
+        if (live) {
+            if (m > 1) {
+                yc ^= 1u;          // the current column's vector becomes the previous one
+                fp = f;
+                bp = b;
+            }
+            mp = m;
+        }
+    };
+    // forward ids at the quarter starts of window w (columns a0, a0+16, a0+32,
+    // a0+48) into qs; returns the id after the window
+    auto quarter_starts = [&](uint32_t w, uint32_t len) -> uint32_t {
+        uint32_t g = jb.ckpt[ck(jb, i, w)];
+#pragma unroll
+        for (int t = 0; t < 64; ++t) {
+            if ((t & (kQuarter - 1)) == 0) qs[t / kQuarter] = g;
+            if (t < static_cast<int>(len)) g = fd[g * C + byte_of(cw, t)];
+        }
+        return g;
+    };
+
+    // backward over the chunk's columns hi-1 .. lo
+    for (int w = static_cast<int>(nwin_wave) - 1; w >= 0; --w) {
+        const bool on = !over && w < static_cast<int>(nwin);
+        uint64_t a0 = 0;
+        uint32_t len = 0, b = 0;
+        if (on) {
+            a0 = lo + 64ull * w;
+            len = static_cast<uint32_t>(hi - a0 < 64 ? hi - a0 : 64);
+            load_window(text, a0, len, xw);
+            window_classes(ct, xw, cw);
+            quarter_starts(w, len);
+            b = jb.bckpt[ck(jb, i, w)];
+        }
+#pragma unroll 1
+        for (int q = 3; q >= 0; --q) {
+            if (on) {
+                // one static copy per quarter: register arrays indexed by constants only
+                // (an index that depends on q would put them in scratch memory)
+                auto stage_bwd = [&](auto qc) {
+                    constexpr int Q = decltype(qc)::value;
+                    uint32_t fq[kQuarter];               // forward ids at columns a0+16Q .. a0+16Q+15
+                    uint32_t g = qs[Q];
+#pragma unroll
+                    for (int u = 0; u < kQuarter; ++u) {
+                        fq[u] = g;
+                        if (Q * kQuarter + u < static_cast<int>(len)) g = fd[g * C + byte_of(cw, Q * kQuarter + u)];
+                    }
+#pragma unroll
+                    for (int u = kQuarter - 1; u >= 0; --u) {
+                        const int t = Q * kQuarter + u;
+                        if (t < static_cast<int>(len)) {
+                            b = rd[b * C + byte_of(cw, t)];
+                            row[u] = entry(fq[u], b);
+                        }
+                    }
+                };
+                if (q == 3) stage_bwd(std::integral_constant<int, 3>{});
+                else if (q == 2) stage_bwd(std::integral_constant<int, 2>{});
+                else if (q == 1) stage_bwd(std::integral_constant<int, 1>{});
+                else stage_bwd(std::integral_constant<int, 0>{});
+            }
+#pragma unroll 1
+            for (int u = kQuarter - 1; u >= 0; --u) {
+                const int t = q * kQuarter + u;
+                bool live = on && !over && t < static_cast<int>(len);
+                const uint32_t e = live ? row[u] : 0u;
+                uint32_t m = column(live, e);
+                if (live && (m > static_cast<uint32_t>(kVec) || m == 0)) {
+                    over = true;
+                    live = false;
+                }
+                if (live && !found) {
+                    if (m == 1) {
+                        found = true;
+                        r1 = a0 + t;
+                        yb[yc * kVec] = 1;
+                        mp = 1;
+                    }
+                    live = false;
+                }
+                step(live, m, e, false, true);
+            }
+        }
+    }
+    if (act && !over && !found) over = true;          // no singleton column in the chunk
+    const uint32_t mL = mp;
+    if (act && !over) {
+        uint64_t *uv = jb.uv + static_cast<uint64_t>(i) * 2 * kVec;
+        const uint64_t *yv = yb + yc * kVec;
+        for (int k = 0; k < kVec; ++k) uv[kVec + k] = k < static_cast<int>(mL) ? yv[k] : 0ull;
+    }
+
+    // forward from r1 to column hi = P_{i+1}
+    yc = 0;
+    yb[0] = 1;
+    mp = 1;
+    const bool fw_on = act && !over;
+    const uint32_t w_first = wave_min(fw_on ? static_cast<uint32_t>((r1 - lo) / 64) : 0xffffffffu);
+    for (uint32_t w = w_first; w < nwin_wave; ++w) {
+        const bool on = fw_on && w < nwin;
+        uint64_t a0 = 0;
+        uint32_t len = 0, f_end = 0, b_end = 0;
+        if (on) {
+            a0 = lo + 64ull * w;
+            len = static_cast<uint32_t>(hi - a0 < 64 ? hi - a0 : 64);
+            load_window(text, a0, len, xw);
+            window_classes(ct, xw, cw);
+            f_end = quarter_starts(w, len);
+            b_end = jb.bckpt[ck(jb, i, w)];
+        }
+#pragma unroll 1
+        for (int q = 0; q < 4; ++q) {
+            // (forward, backward) ids of the columns a0+16q+1 .. a0+16q+16 below
+            // a0+len into row[0..16); the column a0+len is (f_end, b_end).  The
+            // backward ids run from the window's right edge, first over the
+            // bytes above the quarter.  One static copy per quarter.
+            if (on) {
+                auto stage_fwd = [&](auto qc) {
+                    constexpr int Q = decltype(qc)::value;
+                    uint32_t fq[kQuarter];               // forward ids at columns a0+16Q+1 .. a0+16Q+16
+                    uint32_t g = qs[Q];
+#pragma unroll
+                    for (int u = 0; u < kQuarter; ++u) {
+                        if (Q * kQuarter + u < static_cast<int>(len)) g = fd[g * C + byte_of(cw, Q * kQuarter + u)];
+                        fq[u] = g;
+                    }
+                    uint32_t b = b_end;
+#pragma unroll
+                    for (int t = 63; t >= Q * kQuarter + 1; --t) {
+                        if (t < static_cast<int>(len)) {
+                            b = rd[b * C + byte_of(cw, t)];       // backward id at column a0+t
+                            if (t <= Q * kQuarter + kQuarter) row[t - Q * kQuarter - 1] = entry(fq[t - Q * kQuarter - 1], b);
+                        }
+                    }
+                };
+                if (q == 3) stage_fwd(std::integral_constant<int, 3>{});
+                else if (q == 2) stage_fwd(std::integral_constant<int, 2>{});
+                else if (q == 1) stage_fwd(std::integral_constant<int, 1>{});
+                else stage_fwd(std::integral_constant<int, 0>{});
+            }
+#pragma unroll 1
+            for (int u = 0; u < kQuarter; ++u) {   // column a0 + 16q + u + 1
+                const int t = q * kQuarter + u + 1;
+                const uint64_t col = a0 + t;
+                bool live = on && !over && t <= static_cast<int>(len) && col > r1;
+                uint32_t e = 0;
+                if (live) e = t == static_cast<int>(len) ? entry(f_end, b_end) : row[u];
+                uint32_t m = column(live, e);
+                if (live && (m > static_cast<uint32_t>(kVec) || m == 0)) {
+                    over = true;
+                    live = false;
+                }
+                step(live, m, e, true, false);
+            }
+        }
+    }
+    if (act && over) {
+        jb.tbig_idx[i] = kOverflow;
+        jb.ovf[atomicAdd(&jb.flags[3], 1u)] = i;
+        return;
+    }
+    if (!act) return;
+    uint64_t *uv = jb.uv + static_cast<uint64_t>(i) * 2 * kVec;
+    const uint64_t *yv = yb + yc * kVec;
+    for (int k = 0; k < kVec; ++k) uv[k] = k < static_cast<int>(mp) ? yv[k] : 0ull;
+    jb.pi[i] = pi;
+    jb.dims[2 * i] = static_cast<uint8_t>(mL);
+    jb.dims[2 * i + 1] = static_cast<uint8_t>(mp);
+    jb.tbig_idx[i] = kRank1;
+}
+
+// ---- tree count for wide columns (W > 2): segment lists in LDS
+
+constexpr int kListThreads = 512;
+constexpr int kListRow = kQuarter + 1;                     // padded per-lane row of 16 columns
+constexpr int kListSegWords = kVec;                        // two lists of kVec u16 segment ids
+constexpr int kListLaneBytes = (kListRow + kListSegWords) * 4;
+constexpr int kListLdsBytes = kListThreads * kListLaneBytes;
+
+// LDS offsets of the count kernel's staged tables after the per-lane areas:
+// class map and transition tables, then the sole-segment tables, then (FULL)
+// the state bit sets and the follower sets.
+struct ListLds {
+    uint32_t tab, sole, bits, fol, end;
+};
+__host__ __device__ inline ListLds list_lds(uint32_t nf, uint32_t nr, uint32_t C, uint32_t W, uint32_t nseg) {
+    ListLds o;
+    o.tab = kListLdsBytes;
+    o.sole = o.tab + ((512 + (nf + nr) * C * 2 + 15) & ~15u);
+    o.bits = o.sole + (((nf + nr) * 2 + 15) & ~15u);
+    o.fol = o.bits + (nf + nr) * W * 8;
+    o.end = o.fol + nseg * W * 8;
+    return o;
+}
+
+// Fast tree count.  Paths through a singleton clean column all pass through
+// its one segment, so a chunk whose columns P_i .. P_{i+1}-1 include a
+// singleton column has the rank-1 transfer matrix T = v * pi * u^T from
+// column P_i to column P_{i+1}:
+//   v[k]  paths from the k-th segment of column P_i to the leftmost singleton;
+//   pi    product of the path counts between consecutive singleton columns
+//         (a backward vector DP that collapses at every singleton);
+//   u[q]  paths from the rightmost singleton r1 to the q-th segment of
+//         column P_{i+1} (a forward vector DP from r1).
+// A clean column of an accepted text is non-empty and inside both of its
+// state sets, so it is the only segment of either state when that state's set
+// has one (the sole-segment tables); only columns where both sets hold
+// several segments are listed from the bit sets.  Between a singleton and any
+// column every arc exists (each segment of a clean column has a neighbour in
+// the next and in the previous one), so the follower relation is read only
+// between two ambiguous columns.  Per 64-byte window the forward ids come
+// from the build's checkpoint and the backward ids from its backward
+// checkpoint; each half window's (forward, backward) id pairs go to the
+// lane's LDS row, which the DP then walks.  Segment lists of the current and
+// the previous column live in the lane's LDS too, so the vector state in
+// registers is only the path counts.  Chunks with no singleton or with a
+// column above kVec segments go to the general kernel.
+template <bool TAB_LDS, bool FULL>
+__global__ __launch_bounds__(kListThreads) void k_count_list(Tabs tb, Job jb) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    if (jb.ntexts == 1 && text_ref(jb, 0).scalars[0] == 0) return;    // rejected text: no tree
+    const uint32_t C = tb.C, W = tb.W;
+    uint32_t *row = reinterpret_cast<uint32_t *>(smem) + threadIdx.x * kListRow;
+    uint16_t *segl = reinterpret_cast<uint16_t *>(smem + kListThreads * kListRow * 4) + threadIdx.x * 2 * kVec;
+    // transition tables and sole-segment tables (and with FULL the bit sets
+    // and follower sets) staged in LDS
+    const uint16_t *cls, *fd, *rd, *fso, *rso;
+    const uint64_t *fbits = tb.fbits, *rbits = tb.rbits, *fol = tb.folseg;
+    if constexpr (TAB_LDS) {
+        const ListLds o = list_lds(tb.nf, tb.nr, C, W, tb.nseg);
+        uint16_t *c16 = reinterpret_cast<uint16_t *>(smem + o.tab);
+        uint16_t *f16 = c16 + 256, *r16 = f16 + tb.nf * C;
+        uint16_t *fs16 = reinterpret_cast<uint16_t *>(smem + o.sole);
+        uint16_t *rs16 = fs16 + tb.nf;
+        for (uint32_t k = threadIdx.x; k < 256; k += blockDim.x) c16[k] = tb.classmap[k];
+        for (uint32_t k = threadIdx.x; k < tb.nf * C; k += blockDim.x) f16[k] = tb.fdelta[k];
+        for (uint32_t k = threadIdx.x; k < tb.nr * C; k += blockDim.x) r16[k] = tb.rdelta[k];
+        for (uint32_t k = threadIdx.x; k < tb.nf; k += blockDim.x) fs16[k] = tb.fsole[k];
+        for (uint32_t k = threadIdx.x; k < tb.nr; k += blockDim.x) rs16[k] = tb.rsole[k];
+        if constexpr (FULL) {
+            uint64_t *fb64 = reinterpret_cast<uint64_t *>(smem + o.bits), *rb64 = fb64 + tb.nf * W;
+            uint64_t *fl64 = reinterpret_cast<uint64_t *>(smem + o.fol);
+            for (uint32_t k = threadIdx.x; k < tb.nf * W; k += blockDim.x) fb64[k] = tb.fbits[k];
+            for (uint32_t k = threadIdx.x; k < tb.nr * W; k += blockDim.x) rb64[k] = tb.rbits[k];
+            for (uint32_t k = threadIdx.x; k < tb.nseg * W; k += blockDim.x) fl64[k] = tb.folseg[k];
+            fbits = fb64, rbits = rb64, fol = fl64;
+        }
+        __syncthreads();
+        cls = c16, fd = f16, rd = r16, fso = fs16, rso = rs16;
+    } else {
+        cls = tb.classmap, fd = tb.fdelta, rd = tb.rdelta, fso = tb.fsole, rso = tb.rsole;
+    }
+    struct ClsTab {
+        const uint16_t *cls;
+    } ct{cls};
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t wave_first = blockIdx.x * blockDim.x + (threadIdx.x & ~63u);
+    if (wave_first >= jb.c) return;
+    ChunkCtx cx{};
+    bool act = i < jb.c;
+    if (act) {
+        cx = chunk_ctx(jb, i);
+        act = cx.tr.scalars[0] != 0;             // trees only in accepted texts
+    }
+    const uint8_t *text = cx.tr.text;
+    uint64_t lo = 0, hi = 0;
+    uint32_t nwin = 0;
+    if (act) {
+        lo = cx.lo;
+        hi = cx.hi;
+        nwin = static_cast<uint32_t>((hi - lo + 63) / 64);
+    }
+    const uint32_t nwin_wave = wave_max_u32(nwin);
+    uint32_t xw[16], cw[16], qs[4];              // window bytes, classes, forward id at each quarter start
     uint64_t y[kVec];                            // path counts over the previous column's segments
 #pragma unroll
     for (int k = 0; k < kVec; ++k) y[k] = 0;
@@ -1193,16 +1573,14 @@ __global__ __launch_bounds__(kCountThreads) void k_count_fast(Tabs tb, Job jb) {
             mp = m;
         }
     };
-    // forward ids of window w (columns a0 .. a0+63) into fwp; returns the id after the window
-    auto forward_ids = [&](uint32_t w, uint32_t len) -> uint32_t {
+    // forward ids at the quarter starts of window w (columns a0, a0+16, a0+32,
+    // a0+48) into qs; returns the id after the window
+    auto quarter_starts = [&](uint32_t w, uint32_t len) -> uint32_t {
         uint32_t g = jb.ckpt[ck(jb, i, w)];
 #pragma unroll
-        for (int t = 0; t < 64; t += 2) {
-            uint32_t lo16 = g;
+        for (int t = 0; t < 64; ++t) {
+            if ((t & (kQuarter - 1)) == 0) qs[t / kQuarter] = g;
             if (t < static_cast<int>(len)) g = fd[g * C + byte_of(cw, t)];
-            uint32_t hi16 = g;
-            if (t + 1 < static_cast<int>(len)) g = fd[g * C + byte_of(cw, t + 1)];
-            fwp[t >> 1] = lo16 | (hi16 << 16);
         }
         return g;
     };
@@ -1217,7 +1595,7 @@ __global__ __launch_bounds__(kCountThreads) void k_count_fast(Tabs tb, Job jb) {
             len = static_cast<uint32_t>(hi - a0 < 64 ? hi - a0 : 64);
             load_window(text, a0, len, xw);
             window_classes(ct, xw, cw);
-            forward_ids(w, len);
+            quarter_starts(w, len);
             b = jb.bckpt[ck(jb, i, w)];
         }
 #pragma unroll 1
@@ -1225,18 +1603,29 @@ __global__ __launch_bounds__(kCountThreads) void k_count_fast(Tabs tb, Job jb) {
             // backward ids of the quarter, with the forward ids, into the lane's row
             // (q selects between static register indices: no indexed registers)
             if (on) {
+                // one static copy per quarter: register arrays indexed by constants only
+                auto stage_bwd = [&](auto qc) {
+                    constexpr int Q = decltype(qc)::value;
+                    uint32_t fq[kQuarter];               // forward ids at columns a0+16Q .. a0+16Q+15
+                    uint32_t g = qs[Q];
 #pragma unroll
-                for (int u = kQuarter - 1; u >= 0; --u) {
-                    const int t = q * kQuarter + u;
-                    const uint32_t cwd = q == 3 ? cw[12 + (u >> 2)] : q == 2 ? cw[8 + (u >> 2)]
-                                       : q == 1 ? cw[4 + (u >> 2)] : cw[u >> 2];
-                    const uint32_t fpr = q == 3 ? fwp[24 + (u >> 1)] : q == 2 ? fwp[16 + (u >> 1)]
-                                       : q == 1 ? fwp[8 + (u >> 1)] : fwp[u >> 1];
-                    if (t < static_cast<int>(len)) {
-                        b = rd[b * C + ((cwd >> ((u & 3) * 8)) & 0xffu)];
-                        row[u] = entry((fpr >> ((u & 1) * 16)) & 0xffffu, b);
+                    for (int u = 0; u < kQuarter; ++u) {
+                        fq[u] = g;
+                        if (Q * kQuarter + u < static_cast<int>(len)) g = fd[g * C + byte_of(cw, Q * kQuarter + u)];
                     }
-                }
+#pragma unroll
+                    for (int u = kQuarter - 1; u >= 0; --u) {
+                        const int t = Q * kQuarter + u;
+                        if (t < static_cast<int>(len)) {
+                            b = rd[b * C + byte_of(cw, t)];
+                            row[u] = entry(fq[u], b);
+                        }
+                    }
+                };
+                if (q == 3) stage_bwd(std::integral_constant<int, 3>{});
+                else if (q == 2) stage_bwd(std::integral_constant<int, 2>{});
+                else if (q == 1) stage_bwd(std::integral_constant<int, 1>{});
+                else stage_bwd(std::integral_constant<int, 0>{});
             }
 #pragma unroll 1
             for (int u = kQuarter - 1; u >= 0; --u) {
@@ -1284,34 +1673,37 @@ __global__ __launch_bounds__(kCountThreads) void k_count_fast(Tabs tb, Job jb) {
             len = static_cast<uint32_t>(hi - a0 < 64 ? hi - a0 : 64);
             load_window(text, a0, len, xw);
             window_classes(ct, xw, cw);
-            f_end = forward_ids(w, len);
+            f_end = quarter_starts(w, len);
             b_end = jb.bckpt[ck(jb, i, w)];
         }
 #pragma unroll 1
         for (int q = 0; q < 4; ++q) {
             // (forward, backward) ids of the columns a0+16q+1 .. a0+16q+16 below
-            // a0+len into row[0..16); the column a0+len is (f_end, b_end).  The
-            // backward ids run from the window's right edge, first over the
-            // bytes above the quarter.  q selects between static indices.
+            // a0+len into row[0..16); the column a0+len is (f_end, b_end).  One
+            // static copy per quarter.
             if (on) {
-                uint32_t b = b_end;
+                auto stage_fwd = [&](auto qc) {
+                    constexpr int Q = decltype(qc)::value;
+                    uint32_t fq[kQuarter];               // forward ids at columns a0+16Q+1 .. a0+16Q+16
+                    uint32_t g = qs[Q];
 #pragma unroll
-                for (int t = 63; t >= kQuarter + 1; --t)
-                    if (t > q * kQuarter + kQuarter && t < static_cast<int>(len)) b = rd[b * C + byte_of(cw, t)];
-#pragma unroll
-                for (int u = kQuarter - 1; u >= 0; --u) {
-                    const int t = q * kQuarter + u + 1;           // column a0+t, byte t
-                    const int t1 = u + 1, t2 = kQuarter + u + 1, t3 = 2 * kQuarter + u + 1;
-                    const int t4 = u < kQuarter - 1 ? 3 * kQuarter + u + 1 : 3 * kQuarter;   // static, q = 3
-                    const uint32_t by = q == 3 ? byte_of(cw, t4) : q == 2 ? byte_of(cw, t3)
-                                      : q == 1 ? byte_of(cw, t2) : byte_of(cw, t1);
-                    const uint32_t fpr = q == 3 ? fwp[t4 >> 1] : q == 2 ? fwp[t3 >> 1] : q == 1 ? fwp[t2 >> 1]
-                                       : fwp[t1 >> 1];
-                    if (t < static_cast<int>(len)) {
-                        b = rd[b * C + by];                       // backward id at column a0+t
-                        row[u] = entry((fpr >> ((t & 1) * 16)) & 0xffffu, b);
+                    for (int u = 0; u < kQuarter; ++u) {
+                        if (Q * kQuarter + u < static_cast<int>(len)) g = fd[g * C + byte_of(cw, Q * kQuarter + u)];
+                        fq[u] = g;
                     }
-                }
+                    uint32_t b = b_end;
+#pragma unroll
+                    for (int t = 63; t >= Q * kQuarter + 1; --t) {
+                        if (t < static_cast<int>(len)) {
+                            b = rd[b * C + byte_of(cw, t)];       // backward id at column a0+t
+                            if (t <= Q * kQuarter + kQuarter) row[t - Q * kQuarter - 1] = entry(fq[t - Q * kQuarter - 1], b);
+                        }
+                    }
+                };
+                if (q == 3) stage_fwd(std::integral_constant<int, 3>{});
+                else if (q == 2) stage_fwd(std::integral_constant<int, 2>{});
+                else if (q == 1) stage_fwd(std::integral_constant<int, 1>{});
+                else stage_fwd(std::integral_constant<int, 0>{});
             }
 #pragma unroll 1
             for (int u = 0; u < kQuarter; ++u) {   // column a0 + 16q + u + 1

@@ -587,19 +587,35 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
     mark(4);
     // tree count
     if (count && c) {
-        // the count kernel keeps per-lane rows and segment lists in LDS and
-        // stages the tables there too when they fit (all of them, or the
-        // transition and sole-segment tables only)
-        const CountLds co = count_lds(tb.nf, tb.nr, tb.C, W, tb.nseg);
-        const uint32_t cblocks = (c + kCountThreads - 1) / kCountThreads;
-        if (lds && co.end <= p->lds_limit)
-            hipLaunchKernelGGL((k_count_fast<true, true>), dim3(cblocks), dim3(kCountThreads), co.end, stream, tb, jb);
-        else if (lds && co.bits <= p->lds_limit)
-            hipLaunchKernelGGL((k_count_fast<true, false>), dim3(cblocks), dim3(kCountThreads), co.bits, stream, tb,
-                               jb);
-        else
-            hipLaunchKernelGGL((k_count_fast<false, false>), dim3(cblocks), dim3(kCountThreads), kCountLdsBytes,
-                               stream, tb, jb);
+        // the count kernels keep per-lane rows and count vectors in LDS and stage
+        // the tables there too when they fit (all of them, or the transition and
+        // sole-segment tables only).  Narrow columns (W <= 2): the sparse-arc
+        // kernel; wider ones: the segment-list kernel (more lanes per CU)
+        if (W <= 2) {
+            const CountLds co = count_lds(tb.nf, tb.nr, tb.C, W, tb.nseg);
+            const uint32_t cblocks = (c + kCountThreads - 1) / kCountThreads;
+            if (lds && co.end <= p->lds_limit)
+                hipLaunchKernelGGL((k_count_fast<true, true>), dim3(cblocks), dim3(kCountThreads), co.end, stream,
+                                   tb, jb);
+            else if (lds && co.bits <= p->lds_limit)
+                hipLaunchKernelGGL((k_count_fast<true, false>), dim3(cblocks), dim3(kCountThreads), co.bits, stream,
+                                   tb, jb);
+            else
+                hipLaunchKernelGGL((k_count_fast<false, false>), dim3(cblocks), dim3(kCountThreads), kCountLdsBytes,
+                                   stream, tb, jb);
+        } else {
+            const ListLds co = list_lds(tb.nf, tb.nr, tb.C, W, tb.nseg);
+            const uint32_t cblocks = (c + kListThreads - 1) / kListThreads;
+            if (lds && co.end <= p->lds_limit)
+                hipLaunchKernelGGL((k_count_list<true, true>), dim3(cblocks), dim3(kListThreads), co.end, stream, tb,
+                                   jb);
+            else if (lds && co.bits <= p->lds_limit)
+                hipLaunchKernelGGL((k_count_list<true, false>), dim3(cblocks), dim3(kListThreads), co.bits, stream,
+                                   tb, jb);
+            else
+                hipLaunchKernelGGL((k_count_list<false, false>), dim3(cblocks), dim3(kListThreads), kListLdsBytes,
+                                   stream, tb, jb);
+        }
         hipLaunchKernelGGL(k_count_chunk, dim3(std::min<uint32_t>(c, 1024)), dim3(64), 0, stream, tb, jb);
         hipLaunchKernelGGL(k_count_factor, dim3((c + nt + 255) / 256), dim3(256), 0, stream, jb);
     }
