@@ -172,10 +172,13 @@ typedef struct {
  * scalars_dev[1] = number of syntax trees modulo 2^64 (the number of
  *                  accepting NFA runs, one per LST, Sect. 2.3.4);
  * scalars_dev[2] = 0 if scalars_dev[1] is valid, 1 if the count was not
- *                  computed because the job's 2048 transfer-matrix slots
- *                  ran out (clean columns never exceed 64 segments, the
- *                  entry-list limit of slpf_compile), 2 if not requested (SLPF_PARSE_NO_COUNT), 3 on an
+ *                  computed because a clean column held more than 64
+ *                  segments (it cannot: 64 is the entry-list limit of
+ *                  slpf_compile, and every clean column lies in an entry
+ *                  list), 2 if not requested (SLPF_PARSE_NO_COUNT), 3 on an
  *                  internal error (a join set missing from the tables).
+ *                  The count is exact for every accepted text and does not
+ *                  depend on the lane-chunk size or on batching.
  * columns_dev must be 8-byte aligned; with 128-byte alignment every store
  * of the build covers whole cache lines.
  */
@@ -222,10 +225,7 @@ typedef struct {
  * slpf_parse).  The lane chunks of all texts form one index space, so one
  * launch of each phase covers every text and thousands of small texts fill
  * the GPU; the join is a scan segmented at text boundaries.  Results are
- * identical to parsing each text alone, with one exception: the tree
- * count's 2048 transfer-matrix slots (used by lane chunks whose columns
- * all hold several segments, or more than 16) are shared by the job, so a
- * count can fail (status 1) in a batch and succeed alone.  Every item must satisfy the
+ * identical to parsing each text alone.  Every item must satisfy the
  * conditions of slpf_parse (alignment, capacity); the first violation is
  * returned and nothing is launched.  opts->chunk_bytes applies to every
  * text; the join trace is not available for batches.  The descriptors are

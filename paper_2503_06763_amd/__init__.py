@@ -367,7 +367,12 @@ class Parser:
 
 class Server:
     """slpf_server: continuous batching of parse requests (FIFO admission by
-    projected SLPF bytes within ``memory_budget``, ``slots`` jobs in flight)."""
+    projected SLPF bytes within ``memory_budget``, ``slots`` jobs in flight).
+
+    The server keeps a reference to every parser submitted to it until it is
+    closed (destroying the server releases the parsers' buffers for its
+    streams, so they must outlive it), and to each request's text tensor until
+    ``poll`` reports the request finished (the GPU reads it until then)."""
 
     def __init__(self, slots: int = 4, max_batch_texts: int = 256, memory_budget: int = 1 << 30,
                  count: bool = True, device: int = 0):
@@ -378,11 +383,15 @@ class Server:
         _check(L.slpf_server_create(ctypes.byref(o), ctypes.byref(h)), "slpf_server_create")
         self._L, self._h = L, h
         self._buf = (ctypes.c_uint64 * 4096)()
+        self._parsers = {}      # handle -> Parser, for the server's lifetime
+        self._texts = {}        # tag -> text tensor, until the request finishes
 
     def close(self):
         if getattr(self, "_h", None):
             self._L.slpf_server_destroy(self._h)
             self._h = None
+            self._parsers.clear()
+            self._texts.clear()
 
     def __del__(self):
         try:
@@ -394,6 +403,8 @@ class Server:
         """Queue a request; ``text`` is a device tensor whose bytes are in place."""
         st = self._L.slpf_server_submit(self._h, parser.handle, text.data_ptr() if n else None, n, tag)
         _check(st, "slpf_server_submit")
+        self._parsers[parser.handle.value] = parser
+        self._texts[tag] = text
 
     def poll(self):
         """Advance the server; returns the list of tags finished since the last call."""
@@ -404,6 +415,8 @@ class Server:
                    "slpf_server_poll")
             out.extend(self._buf[:nd.value])
             if nd.value < len(self._buf):
+                for tag in out:
+                    self._texts.pop(tag, None)
                 return out
 
     def result(self, tag: int):

@@ -30,10 +30,14 @@
 //            bytes, then window by window backwards: recompute the window's
 //            forward ids from its checkpoint, run the reverse DFA and write
 //            the clean column bitsF[fwd] & bitsR[bwd] of every position.
-//   k_count_chunk / k_prod
-//            the number of syntax trees: per chunk a transfer matrix of path
-//            counts between its clean edge columns, then their ordered
-//            product modulo 2^64.
+//   k_count_fast / k_count_list / k_count_general / k_count_factor /
+//   k_count_chain / k_text_scalars
+//            the number of syntax trees modulo 2^64: the product of the
+//            chunks' path-count matrices between their clean edge columns,
+//            each factored through an anchor column (a singleton: rank 1;
+//            else the smallest column, rank <= kGenR), so that the product
+//            falls apart into per-chunk numbers and short chains of small
+//            anchor-to-anchor matrices.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -94,7 +98,7 @@ struct Job {
     uint16_t *fid, *rid;        // build start ids per chunk
     uint16_t *ckpt;             // forward id at the left edge of every 64-byte window
     uint16_t *bckpt;            // backward id at the right edge of every 64-byte window
-    uint32_t *flags;            // [0] set not found, [1] big-slot counter, [2] unused,
+    uint32_t *flags;            // [0] set not found, [1] chain starts, [2] unused,
                                 // [3] chunks for the general count kernel
     uint64_t *trace;            // optional J / J^ words (one text only)
     // tree count
@@ -102,11 +106,12 @@ struct Job {
     uint64_t *uv;               // [c][2][kVec]: u (right edge) then v (left edge) of a rank-1 chunk
     uint64_t *pi;               // [c] scalar factor of a rank-1 chunk
     uint64_t *factor;           // [c + T] chunk factors, then one text-start factor per text
-    uint32_t *tbig_idx;         // [c], kRank1, a pool slot of a full matrix, or kOverflow (the
-                                // general kernel failed: a column beyond its limit, or no slot)
+    uint32_t *kind;             // [c]: kRank1, kPending (left to the general kernel), kGeneral,
+                                // kSkip, or kOverflow (a column beyond kGenSeg: the count fails)
     uint32_t *ovf;              // chunks left to the general count kernel (count in flags[3])
-    uint64_t *tbig;             // [pool][64*64]
-    uint32_t big_pool;
+    uint32_t *chains;           // general chunks that start a chain (count in flags[1])
+    uint64_t *gmat;             // [c][kGenR][kGenR]: anchor-to-anchor matrix of a general chunk
+    uint64_t *gin;              // [c][kGenR]: row vector into a chain's first anchor
     uint32_t fwd_only;          // recogniser: forward runs and forward join only
 };
 
@@ -176,10 +181,16 @@ __device__ inline ChunkCtx chunk_ctx(const Job &jb, uint32_t i) {
 }
 
 constexpr int kGroup = 8;
-constexpr int kBigT = 64;
 constexpr int kVec = 12;                      // clean-column segments handled by the fast count
 constexpr uint32_t kRank1 = 0xffffffffu;       // chunk matrix held as v * pi * u^T
-constexpr uint32_t kOverflow = 0xfffffffeu;    // chunk left to the general count kernel
+constexpr uint32_t kOverflow = 0xfffffffeu;    // general chunk beyond the kernel's limits
+constexpr uint32_t kPending = 0xfffffffdu;     // chunk left to the general count kernel
+constexpr uint32_t kGeneral = 0xfffffffcu;     // chunk matrix held as A * B through an anchor column
+constexpr uint32_t kSkip = 0xfffffffbu;        // general chunk with no anchor: walked through
+constexpr int kGenR = 8;                       // largest anchor column of a general chunk
+constexpr int kGenSeg = 64;                    // largest clean column on a general chunk's walks
+
+__device__ inline bool kind_failed(uint32_t k) { return k != kRank1 && k != kGeneral && k != kSkip; }
 
 __device__ inline uint32_t boundary_list(const Tabs &tb, const uint16_t *cls, const uint8_t *text,
                                          uint64_t n, uint64_t s, uint32_t c, uint32_t b) {
@@ -1357,7 +1368,7 @@ __global__ __launch_bounds__(kCountThreads) void k_count_fast(Tabs tb, Job jb) {
         }
     }
     if (act && over) {
-        jb.tbig_idx[i] = kOverflow;
+        jb.kind[i] = kPending;
         jb.ovf[atomicAdd(&jb.flags[3], 1u)] = i;
         return;
     }
@@ -1368,7 +1379,7 @@ __global__ __launch_bounds__(kCountThreads) void k_count_fast(Tabs tb, Job jb) {
     jb.pi[i] = pi;
     jb.dims[2 * i] = static_cast<uint8_t>(mL);
     jb.dims[2 * i + 1] = static_cast<uint8_t>(mp);
-    jb.tbig_idx[i] = kRank1;
+    jb.kind[i] = kRank1;
 }
 
 // ---- tree count for wide columns (W > 2): segment lists in LDS
@@ -1722,7 +1733,7 @@ __global__ __launch_bounds__(kListThreads) void k_count_list(Tabs tb, Job jb) {
         }
     }
     if (act && over) {
-        jb.tbig_idx[i] = kOverflow;
+        jb.kind[i] = kPending;
         jb.ovf[atomicAdd(&jb.flags[3], 1u)] = i;
         return;
     }
@@ -1733,14 +1744,38 @@ __global__ __launch_bounds__(kListThreads) void k_count_list(Tabs tb, Job jb) {
     jb.pi[i] = pi;
     jb.dims[2 * i] = static_cast<uint8_t>(mL);
     jb.dims[2 * i + 1] = static_cast<uint8_t>(mp);
-    jb.tbig_idx[i] = kRank1;
+    jb.kind[i] = kRank1;
 }
 
-// Count factors.  factor[i] for a rank-1 chunk i: its pi times u_i^T (full
-// chunk matrices) v_j up to the next rank-1 chunk j of the same text, or the
-// sum at the text end; 1 for a full chunk.  factor[c + t] for text t: the
-// all-ones vector over its column 0 through its leading full chunks to the
-// first rank-1 chunk's v (or the sum).
+__device__ inline uint64_t shfl_xor_u64(uint64_t v, int m) {
+    const uint32_t lo = static_cast<uint32_t>(__shfl_xor(static_cast<int>(static_cast<uint32_t>(v)), m));
+    const uint32_t hi = static_cast<uint32_t>(__shfl_xor(static_cast<int>(static_cast<uint32_t>(v >> 32)), m));
+    return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
+__device__ inline uint64_t wave_min_u64(uint64_t v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const uint64_t o = shfl_xor_u64(v, off);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+
+__device__ inline uint64_t wave_sum_u64(uint64_t v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += shfl_xor_u64(v, off);
+    return v;
+}
+
+// Count factors.  The count of a text is the all-ones row over its column 0
+// times the chunk matrices times the all-ones column over column n.  A rank-1
+// chunk g contributes factor[g] = pi_g times u_g^T carried to the next anchor:
+// u_g . v_{g+1} when the next chunk is rank-1, the sum of u_g at the text end.
+// factor[c + t] for text t is the all-ones row carried to the first anchor:
+// the sum of v over the first chunk when it is rank-1.  When the next chunk
+// (or the first chunk) is general, the chain kernel writes these factors.
+// General chunks contribute 1.
 __global__ __launch_bounds__(256) void k_count_factor(Job jb) {
     const uint32_t c = jb.c;
     const uint32_t g = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1752,52 +1787,93 @@ __global__ __launch_bounds__(256) void k_count_factor(Job jb) {
         return;
     }
     const uint32_t c0 = first_chunk(jb, t), c1 = first_chunk(jb, t + 1);
-    uint64_t vec[kBigT];
-    uint32_t dim, j;
-    uint64_t f = 1;
     if (g >= c) {
-        if (jb.tbig_idx[c0] == kOverflow) {   // the text's count failed
-            jb.factor[g] = 0;
-            return;
-        }
-        dim = jb.dims[2 * c0];
-        for (uint32_t k = 0; k < dim; ++k) vec[k] = 1;
-        j = c0;
-    } else {
-        if (jb.tbig_idx[g] != kRank1) {
-            jb.factor[g] = 1;
-            return;
-        }
-        f = jb.pi[g];
-        dim = jb.dims[2 * g + 1];
-        for (uint32_t k = 0; k < dim; ++k) vec[k] = jb.uv[static_cast<uint64_t>(g) * 2 * kVec + k];
-        j = g + 1;
+        if (jb.kind[c0] != kRank1) return;                 // the chain kernel's
+        const uint32_t dim = jb.dims[2 * c0];
+        const uint64_t *v = jb.uv + static_cast<uint64_t>(c0) * 2 * kVec + kVec;
+        uint64_t d = 0;
+        for (uint32_t k = 0; k < dim; ++k) d += v[k];
+        jb.factor[g] = d;
+        return;
     }
-    while (j < c1 && jb.tbig_idx[j] != kRank1) {
-        if (jb.tbig_idx[j] == kOverflow) {   // the text's count failed
-            jb.factor[g] = 0;
-            return;
-        }
-        const uint64_t *M = jb.tbig + static_cast<uint64_t>(jb.tbig_idx[j]) * kBigT * kBigT;
-        const uint32_t rows = jb.dims[2 * j], cols = jb.dims[2 * j + 1];
-        uint64_t nv[kBigT];
-        for (uint32_t q = 0; q < cols; ++q) {
-            uint64_t a = 0;
-            for (uint32_t k = 0; k < rows && k < dim; ++k) a += vec[k] * M[k * kBigT + q];
-            nv[q] = a;
-        }
-        for (uint32_t q = 0; q < cols; ++q) vec[q] = nv[q];
-        dim = cols;
-        ++j;
+    if (jb.kind[g] != kRank1) {
+        jb.factor[g] = 1;
+        return;
     }
+    const uint64_t *u = jb.uv + static_cast<uint64_t>(g) * 2 * kVec;
+    const uint32_t dim = jb.dims[2 * g + 1];
     uint64_t d = 0;
-    if (j == c1) {
-        for (uint32_t k = 0; k < dim; ++k) d += vec[k];
+    if (g + 1 == c1) {
+        for (uint32_t k = 0; k < dim; ++k) d += u[k];
+    } else if (jb.kind[g + 1] == kRank1) {
+        const uint64_t *v = jb.uv + static_cast<uint64_t>(g + 1) * 2 * kVec + kVec;
+        for (uint32_t k = 0; k < dim; ++k) d += u[k] * v[k];
     } else {
-        const uint64_t *v = jb.uv + static_cast<uint64_t>(j) * 2 * kVec + kVec;
-        for (uint32_t k = 0; k < dim; ++k) d += vec[k] * v[k];
+        return;                                            // the chain kernel's
     }
-    jb.factor[g] = f * d;
+    jb.factor[g] = jb.pi[g] * d;
+}
+
+// Chains through general chunks: one wavefront per run of general chunks (a
+// text's first chunks, or the chunks after a rank-1 chunk, up to the next
+// rank-1 chunk or the text end).  The row vector gin[j0] of its first chunk
+// j0 is multiplied by the anchor-to-anchor matrices of the run's anchored
+// chunks in order; the last matrix has one column, so the product is a
+// number (and when the run has no anchor, gin[j0] is that number already):
+// the factor of the rank-1 chunk before j0 (times its pi), or the
+// text-start factor.  Lane 8k+b holds entry (k, b) of the current matrix
+// and entry k of the row vector; entry b of the product is the sum over the
+// lanes b, b+8, ..., b+56.
+__global__ __launch_bounds__(64) void k_count_chain(Job jb) {
+    const uint32_t L = threadIdx.x, k = L >> 3;
+    for (uint32_t item = blockIdx.x; item < jb.flags[1]; item += gridDim.x) {
+        const uint32_t j0 = jb.chains[item];
+        const uint32_t t = text_of(jb, j0);
+        const uint32_t c0 = first_chunk(jb, t), c1 = first_chunk(jb, t + 1);
+        uint64_t vk = jb.gin[static_cast<uint64_t>(j0) * kGenR + k];
+        bool bad = false;
+        uint32_t j = j0;
+        while (j < c1) {
+            // four matrices in flight
+            uint32_t kd[4];
+            uint64_t gm[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                kd[u] = j + u < c1 ? jb.kind[j + u] : kRank1;
+                gm[u] = j + u < c1 ? jb.gmat[static_cast<uint64_t>(j + u) * kGenR * kGenR + L] : 0ull;
+            }
+            bool stop = false;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (stop) break;
+                if (kd[u] == kRank1) {       // the next anchor is a rank-1 chunk's (or the text ended)
+                    stop = true;
+                    break;
+                }
+                if (kd[u] == kSkip) {        // no anchor: walked through by the matrices around it
+                    ++j;
+                    continue;
+                }
+                if (kd[u] != kGeneral) {
+                    bad = true;
+                    stop = true;
+                    break;
+                }
+                uint64_t p = vk * gm[u];
+                p += shfl_xor_u64(p, 8);
+                p += shfl_xor_u64(p, 16);
+                p += shfl_xor_u64(p, 32);
+                vk = shfl_u64(p, static_cast<int>(k));   // entry k of the new row vector
+                ++j;
+            }
+            if (stop) break;
+        }
+        if (L == 0) {
+            const uint64_t d = bad ? 0ull : vk;           // entry 0 of the final row (one column)
+            if (j0 == c0) jb.factor[jb.c + t] = d;
+            else jb.factor[j0 - 1] = jb.pi[j0 - 1] * d;
+        }
+    }
 }
 
 // Per-text scalars: one block per text (count: 0 not requested, 1 requested,
@@ -1864,12 +1940,12 @@ __global__ __launch_bounds__(kScalarThreads) void k_text_scalars(Tabs tb, Job jb
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 acc[u] *= jb.factor[k + u * stride];
-                bad = bad || jb.tbig_idx[k + u * stride] == kOverflow;
+                bad = bad || kind_failed(jb.kind[k + u * stride]);
             }
         }
         for (; k < c1; k += stride) {
             acc[0] *= jb.factor[k];
-            bad = bad || jb.tbig_idx[k] == kOverflow;
+            bad = bad || kind_failed(jb.kind[k]);
         }
         if (bad) atomicOr(&failed, 1u);
         part[th] = acc[0] * acc[1] * acc[2] * acc[3] * acc[4] * acc[5] * acc[6] * acc[7];
@@ -1888,96 +1964,264 @@ __global__ __launch_bounds__(kScalarThreads) void k_text_scalars(Tabs tb, Job jb
     }
 }
 
-// Transfer matrix of chunk i: T[k][q] = number of paths in the clean SLPF from
-// the k-th segment of column P_i to the q-th segment of column P_{i+1}
-// (segments ranked by id).  A path crosses an arc rho -> sigma between
-// consecutive clean columns iff sigma is a follower of rho (the label of rho
-// equals the byte read, as every segment of a clean column does).  One
-// wavefront per chunk; lane q keeps column q of the running matrix U in LDS.
-__device__ inline void count_chunk_general(const Tabs &tb, const Job &jb, uint32_t i) {
-    __shared__ uint64_t U[2][kBigT][kBigT];
-    __shared__ uint32_t segs[2][kBigT];
-    __shared__ uint64_t arcs[kBigT];
-    __shared__ uint32_t nseg[2];
-    __shared__ uint32_t fail;
-    const uint32_t q = threadIdx.x;
-    const uint32_t W = tb.W;
-    const ChunkCtx cx = chunk_ctx(jb, i);
-    const uint64_t lo = cx.lo, hi = cx.hi;
-    uint64_t *out = cx.tr.out;
-    if (q == 0) fail = 0;
-    __syncthreads();
-    // list the segments of column r into segs[slot]; returns the count or > 64
-    auto list_column = [&](uint64_t r, int slot) {
-        if (q == 0) {
+// ---- tree count, general chunks: a chunk with no singleton column, or with
+// a column above kVec segments.  Its matrix M = T(lo -> hi) (paths between
+// the segments of its edge columns) is factored through an anchor column a,
+// the leftmost column of [lo, hi] with the fewest segments, when that column
+// has r <= kGenR segments: M = A B with A = T(lo -> a), B = T(a -> hi).  The
+// kernel stores the anchor-to-anchor matrix G = T(a -> a'), with a' the next
+// anchor of the run (unit vectors), or the next rank-1 chunk's left edge
+// weighed by its v, or the text end weighed by ones; r x r' zero-padded to
+// kGenR x kGenR.  A chunk whose smallest column is larger has no anchor and
+// is walked through by its neighbours' products, so the count never depends
+// on where the lane chunks fall.  The first chunk of a run stores the row
+// vector w^T T(lo -> first anchor) with w the previous chunk's u or the
+// all-ones row.  Each product is one backward walk over the clean columns:
+// count vectors y_c[k] (paths from the k-th segment of column c to the start
+// vectors) go from column c+1 to c along the arcs rho -> sigma with sigma a
+// follower of rho.  One wavefront per chunk; lane k holds segment k of the
+// current column; the columns are staged kGenBlock at a time in LDS with
+// their segment lists.
+
+constexpr int kGenBlock = 32;                  // columns staged per block
+
+// LDS of the general kernel (one wavefront): staged column words and prefix
+// counts (row 0 is the column above the block), segment lists, two count
+// vector buffers, and the follower table when it fits.
+struct GenLds {
+    uint32_t colw, pre, segl, mcnt, y, fol, end;
+};
+
+__host__ __device__ inline GenLds gen_lds(uint32_t W, uint32_t nseg, bool fol_lds) {
+    GenLds o{};
+    uint32_t at = 0;
+    o.colw = at;
+    at += (kGenBlock + 1) * W * 8;
+    o.y = at;
+    at += 2 * kGenSeg * kGenR * 8;
+    o.pre = at;
+    at += (kGenBlock + 1) * W * 2;
+    o.segl = at;
+    at += kGenBlock * kGenSeg * 2;
+    o.mcnt = at;
+    at += (kGenBlock + 1) * 4 + 4;
+    at = (at + 15u) & ~15u;
+    o.fol = at;
+    if (fol_lds) at += nseg * W * 8;
+    o.end = at;
+    return o;
+}
+
+struct GenCtx {
+    const uint64_t *out;     // the text's clean columns
+    const uint64_t *fol;     // follower table (LDS or global)
+    uint64_t *colw, *y;
+    uint16_t *pre, *segl;
+    uint32_t *mcnt;
+    uint32_t W;
+};
+
+// Leftmost column of [lo, hi] with the fewest segments, as
+// (segments << 40) | (column - lo).
+__device__ inline uint64_t gen_anchor(const GenCtx &g, uint64_t lo, uint64_t hi) {
+    uint64_t best = ~0ull;
+    for (uint64_t col = lo + threadIdx.x; col <= hi; col += 64) {
+        const uint64_t *cw = g.out + col * g.W;
+        uint32_t m = 0;
+        for (uint32_t w = 0; w < g.W; ++w) m += __popcll(cw[w]);
+        const uint64_t key = (static_cast<uint64_t>(m) << 40) | (col - lo);
+        best = key < best ? key : best;
+    }
+    return wave_min_u64(best);
+}
+
+// Backward walk from column `from` down to column `to` (to <= from).  V <=
+// kGenR count vectors start at column `from`: start(k, v) for its k-th
+// segment.  On return lane k < m_to holds y_to[k][v] in acc[v] (zero for v
+// past the start vectors).  Returns false when a column of the walk has more
+// than kGenSeg segments.
+template <class Start>
+__device__ inline bool gen_walk(const GenCtx &g, uint64_t from, uint64_t to, Start start, uint64_t acc[kGenR],
+                                uint32_t *m_to) {
+    const uint32_t lane = threadIdx.x, W = g.W;
+    uint32_t yc = 0;
+    bool first = true;
+    uint32_t m = 0;
+    for (uint64_t top = from;; top -= kGenBlock) {
+        const uint32_t rows = static_cast<uint32_t>(top - to + 1 < kGenBlock ? top - to + 1 : kGenBlock);
+        // row 0: the column above the block (the previous block's last row)
+        if (!first) {
+            for (uint32_t w = lane; w < W; w += 64) {
+                g.colw[w] = g.colw[kGenBlock * W + w];
+                g.pre[w] = g.pre[kGenBlock * W + w];
+            }
+            if (lane == 0) g.mcnt[0] = g.mcnt[kGenBlock];
+        }
+        __syncthreads();
+        // rows 1..rows: columns top, top-1, ...; lane l lists its column
+        bool big = false;
+        if (lane < rows) {
+            const uint32_t row = lane + 1;
+            const uint64_t *cw = g.out + (top - lane) * W;
             uint32_t cnt = 0;
-            const uint64_t *col = out + r * W;
-            for (uint32_t w = 0; w < W && cnt <= kBigT; ++w) {
-                uint64_t v = col[w];
+            for (uint32_t w = 0; w < W; ++w) {
+                uint64_t v = cw[w];
+                g.colw[row * W + w] = v;
+                g.pre[row * W + w] = static_cast<uint16_t>(cnt);
                 while (v) {
-                    int bpos = __builtin_ctzll(v);
+                    const uint32_t b = static_cast<uint32_t>(__builtin_ctzll(v));
                     v &= v - 1;
-                    if (cnt < kBigT) segs[slot][cnt] = w * 64 + bpos;
+                    if (cnt < kGenSeg) g.segl[lane * kGenSeg + cnt] = static_cast<uint16_t>(w * 64 + b);
                     ++cnt;
                 }
             }
-            nseg[slot] = cnt;
+            g.mcnt[row] = cnt;
+            big = cnt > kGenSeg;
         }
+        if (__any(big)) return false;
         __syncthreads();
-    };
-    int cur = 0;
-    list_column(hi, cur);
-    const uint32_t mR = nseg[cur];
-    if (mR > kBigT) return;     // tbig_idx[i] stays kOverflow
-    for (uint32_t k = 0; k < kBigT; ++k) U[cur][k][q] = (k == q && q < mR) ? 1ull : 0ull;
-    __syncthreads();
-    for (uint64_t r = hi; r-- > lo;) {
-        const int nxt = cur ^ 1;
-        list_column(r, nxt);
-        const uint32_t m = nseg[nxt], mp = nseg[cur];
-        if (m > kBigT) return;
-        if (q < m) {   // arcs of the q-th segment of column r into column r+1
-            const uint64_t *fs = tb.folseg + static_cast<uint64_t>(segs[nxt][q]) * W;
-            uint64_t a = 0;
-            for (uint32_t j = 0; j < mp; ++j) {
-                uint32_t sg = segs[cur][j];
-                a |= ((fs[sg >> 6] >> (sg & 63)) & 1ull) << j;
-            }
-            arcs[q] = a;
-        }
-        __syncthreads();
-        if (q < mR) {
-            for (uint32_t k = 0; k < m; ++k) {
-                uint64_t sum = 0, a = arcs[k];
-                while (a) {
-                    int j = __builtin_ctzll(a);
-                    a &= a - 1;
-                    sum += U[cur][j][q];
+        for (uint32_t r = 1; r <= rows; ++r) {
+            m = g.mcnt[r];
+            uint64_t a[kGenR];
+#pragma unroll
+            for (int v = 0; v < kGenR; ++v) a[v] = 0;
+            if (first && r == 1) {
+                if (lane < m) {
+#pragma unroll
+                    for (int v = 0; v < kGenR; ++v) a[v] = start(lane, v);
                 }
-                U[nxt][k][q] = sum;
+            } else if (lane < m) {
+                const uint64_t *yprev = g.y + yc * kGenSeg * kGenR;
+                const uint32_t s = g.segl[(r - 1) * kGenSeg + lane];
+                const uint64_t *nx = g.colw + (r - 1) * W;
+                const uint16_t *np = g.pre + (r - 1) * W;
+                for (uint32_t w = 0; w < W; ++w) {
+                    const uint64_t cwd = nx[w];
+                    uint64_t f = g.fol[s * W + w] & cwd;
+                    while (f) {
+                        const uint32_t b = static_cast<uint32_t>(__builtin_ctzll(f));
+                        f &= f - 1;
+                        const uint32_t rk = np[w] + static_cast<uint32_t>(__popcll(cwd & low_mask(b)));
+                        const uint64_t *yr = yprev + rk * kGenR;
+#pragma unroll
+                        for (int v = 0; v < kGenR; ++v) a[v] += yr[v];
+                    }
+                }
             }
+            yc ^= 1u;
+            if (lane < m) {
+                uint64_t *ycur = g.y + yc * kGenSeg * kGenR + lane * kGenR;
+#pragma unroll
+                for (int v = 0; v < kGenR; ++v) ycur[v] = a[v];
+            }
+#pragma unroll
+            for (int v = 0; v < kGenR; ++v) acc[v] = a[v];
+            __syncthreads();
         }
-        __syncthreads();
-        cur = nxt;
+        first = false;
+        if (top - rows + 1 == to) break;
     }
-    const uint32_t mL = nseg[cur];
-    if (q == 0) {
-        jb.dims[2 * i] = static_cast<uint8_t>(mL);
-        jb.dims[2 * i + 1] = static_cast<uint8_t>(mR);
-    }
-    __shared__ uint32_t slot;
-    if (q == 0) slot = atomicAdd(&jb.flags[1], 1u);
-    __syncthreads();
-    if (slot >= jb.big_pool) return;
-    for (uint32_t k = 0; k < kBigT; ++k)
-        jb.tbig[static_cast<uint64_t>(slot) * kBigT * kBigT + k * kBigT + q] = (k < mL && q < mR) ? U[cur][k][q] : 0ull;
-    __syncthreads();
-    if (q == 0) jb.tbig_idx[i] = slot;
+    *m_to = m;
+    return true;
 }
 
-__global__ __launch_bounds__(64) void k_count_chunk(Tabs tb, Job jb) {
+// The first anchor at or after chunk jj of a run (the chunks after a rank-1
+// chunk or the text start that are not rank-1): the leftmost smallest column
+// of the first chunk whose smallest column has at most kGenR segments; else
+// the left edge of the run's closing rank-1 chunk, whose v weighs it; else
+// the text end, weighed by ones.
+struct GenTarget {
+    uint64_t col;
+    uint32_t how;            // 0: unit vectors over r segments, 1: v of chunk h, 2: ones
+    uint32_t h;
+};
+
+__device__ inline GenTarget gen_next(const GenCtx &g, const Job &jb, const ChunkCtx &cx, uint32_t c0, uint32_t jj) {
+    for (;; ++jj) {
+        const uint32_t li = jj - c0;
+        if (li == cx.ct) return {cx.tr.n, 2u, 0u};
+        const uint64_t lo = static_cast<uint64_t>(li) * jb.s;
+        if (jb.kind[jj] == kRank1) return {lo, 1u, jj};
+        const uint64_t hi = li + 1 == cx.ct ? cx.tr.n : lo + jb.s;
+        const uint64_t key = gen_anchor(g, lo, hi);
+        if ((key >> 40) <= static_cast<uint64_t>(kGenR)) return {lo + (key & ((1ull << 40) - 1)), 0u, 0u};
+    }
+}
+
+template <bool FOL_LDS>
+__global__ __launch_bounds__(64) void k_count_general(Tabs tb, Job jb) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    const uint32_t W = tb.W, lane = threadIdx.x;
+    const GenLds o = gen_lds(W, tb.nseg, FOL_LDS);
+    GenCtx g;
+    g.colw = reinterpret_cast<uint64_t *>(smem + o.colw);
+    g.y = reinterpret_cast<uint64_t *>(smem + o.y);
+    g.pre = reinterpret_cast<uint16_t *>(smem + o.pre);
+    g.segl = reinterpret_cast<uint16_t *>(smem + o.segl);
+    g.mcnt = reinterpret_cast<uint32_t *>(smem + o.mcnt);
+    g.W = W;
+    if constexpr (FOL_LDS) {
+        uint64_t *f = reinterpret_cast<uint64_t *>(smem + o.fol);
+        for (uint32_t k = lane; k < tb.nseg * W; k += 64) f[k] = tb.folseg[k];
+        g.fol = f;
+    } else {
+        g.fol = tb.folseg;
+    }
+    __syncthreads();
     for (uint32_t item = blockIdx.x; item < jb.flags[3]; item += gridDim.x) {
-        count_chunk_general(tb, jb, jb.ovf[item]);
+        const uint32_t j = jb.ovf[item];
+        const ChunkCtx cx = chunk_ctx(jb, j);
+        const uint32_t c0 = j - cx.li;
+        g.out = cx.tr.out;
+        const bool starts = cx.first || jb.kind[j - 1] == kRank1;
+        const uint64_t key = gen_anchor(g, cx.lo, cx.hi);
+        const bool anchored = (key >> 40) <= static_cast<uint64_t>(kGenR);
+        const uint64_t a = cx.lo + (key & ((1ull << 40) - 1));
+        bool ok = true;
+        uint64_t acc[kGenR];
+        uint32_t mt = 0;
+        auto walk_to = [&](const GenTarget &tg, uint64_t to) -> bool {
+            const uint64_t *vh = jb.uv + static_cast<uint64_t>(tg.h) * 2 * kVec + kVec;
+            auto start = [&](uint32_t k, int v) -> uint64_t {
+                if (tg.how == 0) return k == static_cast<uint32_t>(v) ? 1ull : 0ull;
+                if (v != 0) return 0ull;
+                return tg.how == 1 ? vh[k] : 1ull;
+            };
+            return gen_walk(g, tg.col, to, start, acc, &mt);
+        };
+        // the row into the run: w^T T(lo -> first anchor), w the previous
+        // chunk's u or ones (a number when the run has no anchor)
+        if (starts) {
+            const GenTarget tg = anchored ? GenTarget{a, 0u, 0u} : gen_next(g, jb, cx, c0, j + 1);
+            ok = walk_to(tg, cx.lo);
+            if (ok) {
+                const uint64_t wk = lane >= mt ? 0ull
+                                    : cx.first ? 1ull
+                                               : jb.uv[static_cast<uint64_t>(j - 1) * 2 * kVec + lane];
+                uint64_t row[kGenR];
+#pragma unroll
+                for (int v = 0; v < kGenR; ++v) row[v] = wave_sum_u64(wk * acc[v]);
+                if (lane == 0) {
+#pragma unroll
+                    for (int v = 0; v < kGenR; ++v) jb.gin[static_cast<uint64_t>(j) * kGenR + v] = row[v];
+                }
+            }
+        }
+        // anchor-to-anchor matrix G = T(a -> next anchor), weighed at the far end
+        if (ok && anchored) {
+            const GenTarget tg = gen_next(g, jb, cx, c0, j + 1);
+            ok = walk_to(tg, a);
+            if (ok && lane < static_cast<uint32_t>(kGenR)) {
+                // lane k < r holds row k; rows r..kGenR-1 are zero
+                uint64_t *gm = jb.gmat + static_cast<uint64_t>(j) * kGenR * kGenR;
+#pragma unroll
+                for (int v = 0; v < kGenR; ++v) gm[lane * kGenR + v] = lane < mt ? acc[v] : 0ull;
+            }
+        }
+        if (lane == 0) {
+            jb.kind[j] = !ok ? kOverflow : anchored ? kGeneral : kSkip;
+            if (starts) jb.chains[atomicAdd(&jb.flags[1], 1u)] = j;
+        }
         __syncthreads();
     }
 }

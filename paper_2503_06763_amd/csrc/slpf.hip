@@ -17,7 +17,6 @@ namespace {
 using namespace slpf;
 
 constexpr size_t kLdsBudget = 96 * 1024;   // transition tables staged in LDS up to this size
-constexpr uint32_t kBigPool = 2048;         // 64x64 transfer-matrix slots (32 KiB each)
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -170,6 +169,8 @@ void set_placement(slpf_parser *p) {
     }
     p->placement = p->lds_bytes <= budget ? 0 : 1;
 }
+
+constexpr uint32_t kGenFolLds = 40 * 1024;   // LDS of the general count kernel with its follower table
 
 uint64_t chunk_bytes_for(uint64_t n, const slpf_parse_opts *o) {
     if (o && o->chunk_bytes) return o->chunk_bytes;
@@ -389,15 +390,17 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
             jpcst[d].push_back(l < TL ? L.add(N + 1) : -1);
             jpcv[d].push_back(l < TL ? L.add((N + 1) * 8) : -1);
         }
-    int idims = -1, iuv = -1, ipi = -1, ifac = -1, itidx = -1, itbig = -1, iovf = -1;
+    int idims = -1, iuv = -1, ipi = -1, ifac = -1, ikind = -1, iovf = -1, ichain = -1, igmat = -1, igin = -1;
     if (count) {
         idims = L.add(size_t(c) * 2);
         iuv = L.add(size_t(c) * 2 * kVec * 8);
         ipi = L.add(size_t(c) * 8);
         ifac = L.add(size_t(c + T) * 8);
-        itidx = L.add(size_t(c) * 4);
+        ikind = L.add(size_t(c) * 4);
         iovf = L.add(size_t(c) * 4);
-        itbig = L.add(size_t(std::min<uint32_t>(kBigPool, std::max<uint32_t>(c, 1))) * kBigT * kBigT * 8);
+        ichain = L.add(size_t(c) * 4);
+        igmat = L.add(size_t(c) * kGenR * kGenR * 8);
+        igin = L.add(size_t(c) * kGenR * 8);
     }
 
     uint8_t *base;
@@ -476,10 +479,11 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
         jb.uv = reinterpret_cast<uint64_t *>(ptr(iuv));
         jb.pi = reinterpret_cast<uint64_t *>(ptr(ipi));
         jb.factor = reinterpret_cast<uint64_t *>(ptr(ifac));
-        jb.tbig_idx = reinterpret_cast<uint32_t *>(ptr(itidx));
+        jb.kind = reinterpret_cast<uint32_t *>(ptr(ikind));
         jb.ovf = reinterpret_cast<uint32_t *>(ptr(iovf));
-        jb.tbig = reinterpret_cast<uint64_t *>(ptr(itbig));
-        jb.big_pool = std::min<uint32_t>(kBigPool, std::max<uint32_t>(c, 1));   // at most one slot per chunk
+        jb.chains = reinterpret_cast<uint32_t *>(ptr(ichain));
+        jb.gmat = reinterpret_cast<uint64_t *>(ptr(igmat));
+        jb.gin = reinterpret_cast<uint64_t *>(ptr(igin));
     }
 
     const bool timed = opts && opts->events && opts->num_events >= SLPF_NUM_PHASE_EVENTS;
@@ -616,8 +620,18 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
                 hipLaunchKernelGGL((k_count_list<false, false>), dim3(cblocks), dim3(kListThreads), kListLdsBytes,
                                    stream, tb, jb);
         }
-        hipLaunchKernelGGL(k_count_chunk, dim3(std::min<uint32_t>(c, 1024)), dim3(64), 0, stream, tb, jb);
+        // general chunks (their number is known on the device only): one
+        // wavefront each over a grid that loops, the follower table in LDS
+        // when it is small
+        const GenLds go = gen_lds(W, tb.nseg, true);
+        const uint32_t gblocks = std::min<uint32_t>(c, 2048);
+        if (lds && go.end <= kGenFolLds)
+            hipLaunchKernelGGL(k_count_general<true>, dim3(gblocks), dim3(64), go.end, stream, tb, jb);
+        else
+            hipLaunchKernelGGL(k_count_general<false>, dim3(gblocks), dim3(64), gen_lds(W, tb.nseg, false).end,
+                               stream, tb, jb);
         hipLaunchKernelGGL(k_count_factor, dim3((c + nt + 255) / 256), dim3(256), 0, stream, jb);
+        hipLaunchKernelGGL(k_count_chain, dim3(std::min<uint32_t>(c, 1024)), dim3(64), 0, stream, jb);
     }
     hipLaunchKernelGGL(k_text_scalars, dim3(nt), dim3(kScalarThreads), 0, stream, tb, jb, recog ? 2 : count ? 1 : 0);
     mark(5);

@@ -3,8 +3,8 @@ every text, exactly the columns, accept flag, count and status of parsing
 that text alone, and of the oracle.
 
 Covers empty and one-byte texts between long ones, texts that are rejected
-next to accepted ones, a text whose count fails next to one whose count
-succeeds, enough lane chunks for a three-level join scan with text
+next to accepted ones, a text counted through general chunks with no anchor
+next to texts counted through rank-1 chunks, enough lane chunks for a three-level join scan with text
 boundaries inside every scan group, and the argument checks.
 """
 import sys
@@ -109,16 +109,18 @@ def test_batch_empty_and_tiny_only():
     check_batch(pat, [b"", b""])
 
 
-def test_batch_count_failure_is_per_text():
-    # every column of a^n holds 20 segments (no singleton), so each of its
-    # 2100 lane chunks needs a full transfer matrix and the 2048 slots run
-    # out: its count fails; the texts of b's (singleton columns) still count
+def test_batch_count_without_anchor():
+    # every column of a^n holds 20 segments: none of its 2100 lane chunks has
+    # a singleton or a small column, so its count is one walk over the text;
+    # the texts of b's (singleton columns) count through rank-1 chunks.
+    # Every count is computed (20^n is 0 modulo 2^64 once n >= 32)
     device()
     pat = "((" + "|".join(["a"] * 20) + ")|b)*"
-    texts = [b"b" * 300, b"a" * (64 * 2100), b"", b"b" * 5]
+    texts = [b"b" * 300, b"a" * (64 * 2100), b"", b"b" * 5, b"a" * 21]
     got = check_batch(pat, texts, chunk_bytes=64)
-    assert [g[3] for g in got] == [0, 1, 0, 0]
+    assert [g[3] for g in got] == [0, 0, 0, 0, 0]
     assert got[0][2] == 1 and got[3][2] == 1
+    assert got[1][2] == 0 and got[4][2] == pow(20, 21, 1 << 64)
 
 
 def test_batch_deep_join_scan():

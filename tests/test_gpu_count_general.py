@@ -1,0 +1,117 @@
+"""Tree count through general lane chunks (no singleton column, or a column
+above the fast kernels' limit): chunks anchored at a small column (rank
+above 1), chunks with no small column (walked through), and runs of them
+between rank-1 chunks.  The count must equal the oracle's and a closed form
+where there is one, and must not depend on the chunk size or on batching.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from gpu_util import device, gpu_parse, to_device
+from oracle.oracle import Oracle
+
+S = pytest.importorskip("paper_2503_06763_amd")
+pytestmark = pytest.mark.gpu
+
+M64 = (1 << 64) - 1
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def fib_mod(n):
+    """F(n) modulo 2^64 with F(1) = F(2) = 1."""
+    a, b = 0, 1
+    for _ in range(n):
+        a, b = b, (a + b) & M64
+    return a
+
+
+def test_rank2_columns_closed_form():
+    # (a|aa)* over a^n: every inner column holds two or three segments, so
+    # every chunk is general with an anchor of rank 2 or 3; the number of
+    # trees is the number of compositions of n into 1s and 2s, F(n+1)
+    device()
+    p = S.Parser("(a|aa)*")
+    for n in (1, 2, 63, 64, 65, 1000, 4097, 20000):
+        text = b"a" * n
+        for k in (64, 256, 0):
+            cols, acc, cnt, st = gpu_parse(p, text, chunk_bytes=k)
+            assert acc and st == 0, (n, k, st)
+            assert cnt == fib_mod(n + 1), (n, k, cnt)
+    say("rank-2 chains ok")
+
+
+def _blocks(rng, alphabet_blocks, total):
+    out = []
+    size = 0
+    while size < total:
+        letter, lo, hi = alphabet_blocks[int(rng.integers(len(alphabet_blocks)))]
+        k = int(rng.integers(lo, hi + 1))
+        out.append(letter * k)
+        size += k
+    return b"".join(out)[:total]
+
+
+MIXED_RE = "((a|a|a|a|a|a|a|a|a|a)|b|(c|cc)|(d|dd|ddd))*"
+
+
+def test_mixed_runs_vs_oracle_and_chunking():
+    # b-blocks give singleton columns (rank-1 chunks), c- and d-blocks small
+    # ambiguous columns (anchored general chunks), a-blocks ten segments per
+    # column (chunks with no anchor); block lengths around the chunk sizes
+    device()
+    p, o = S.Parser(MIXED_RE), Oracle(MIXED_RE)
+    rng = np.random.default_rng(17)
+    blocks = [(b"a", 1, 300), (b"b", 1, 200), (b"c", 1, 400), (b"d", 1, 150), (b"a", 200, 900)]
+    texts = [_blocks(rng, blocks, int(rng.integers(1, 12000))) for _ in range(10)]
+    texts += [b"a" * 5000, b"b" * 3 + b"a" * 3000 + b"b", b"c" * 3000 + b"a" * 700 + b"d" * 900]
+    for t in texts:
+        _, acc, want = o.parse(t)
+        assert acc
+        got = set()
+        for k in (64, 128, 512, 0):
+            cols, a2, cnt, st = gpu_parse(p, t, chunk_bytes=k)
+            assert a2 and st == 0, (len(t), k, st)
+            assert cnt == want, (len(t), k, cnt, want)
+            got.add(cnt)
+        assert len(got) == 1
+    say("mixed runs ok:", len(texts), "texts")
+
+
+def test_general_chunks_batched_equal_alone():
+    import torch
+    device()
+    p, o = S.Parser(MIXED_RE), Oracle(MIXED_RE)
+    rng = np.random.default_rng(23)
+    blocks = [(b"a", 1, 400), (b"b", 1, 100), (b"c", 1, 300), (b"d", 50, 600)]
+    texts = [_blocks(rng, blocks, int(rng.integers(0, 6000))) for _ in range(40)]
+    dts = [to_device(t) for t in texts]
+    for k in (64, 0):
+        res = p.parse_batch(dts, chunk_bytes=k)
+        torch.cuda.synchronize()
+        for t, (cols, sc) in zip(texts, res):
+            s = sc.cpu().numpy().view(np.uint64)
+            alone = gpu_parse(p, t, chunk_bytes=k)
+            assert np.array_equal(cols.cpu().numpy().view(np.uint64), alone[0])
+            assert (bool(s[0]), int(s[1]), int(s[2])) == alone[1:]
+            assert int(s[2]) == 0 and int(s[1]) == o.parse(t)[2]
+    say("batched general chunks ok")
+
+
+def test_no_anchor_anywhere():
+    # every column of a^n holds ten segments: no chunk has an anchor, and the
+    # count is one walk over the whole text; 10^n mod 2^64 (zero once 2^n
+    # divides it)
+    device()
+    p = S.Parser("(a|a|a|a|a|a|a|a|a|a)*")
+    for n in (1, 5, 19, 64, 700, 3000):
+        for k in (64, 0):
+            _, acc, cnt, st = gpu_parse(p, b"a" * n, chunk_bytes=k)
+            assert acc and st == 0
+            assert cnt == pow(10, n, 1 << 64), (n, k)
+    say("no-anchor walks ok")
