@@ -112,6 +112,7 @@ struct Job {
     uint32_t *chains;           // general chunks that start a chain (count in flags[1])
     uint64_t *gmat;             // [c][kGenR][kGenR]: anchor-to-anchor matrix of a general chunk
     uint64_t *gin;              // [c][kGenR]: row vector into a chain's first anchor
+    uint32_t *pend;             // [c]: the chunk after a stretch of general chunks (piece products)
     uint32_t fwd_only;          // recogniser: forward runs and forward join only
 };
 
@@ -189,6 +190,7 @@ constexpr uint32_t kGeneral = 0xfffffffcu;     // chunk matrix held as A * B thr
 constexpr uint32_t kSkip = 0xfffffffbu;        // general chunk with no anchor: walked through
 constexpr int kGenR = 8;                       // largest anchor column of a general chunk
 constexpr int kGenSeg = 64;                    // largest clean column on a general chunk's walks
+static_assert(kGenR * kGenR == 64, "the chain kernels hold one anchor matrix per wavefront, an entry a lane");
 
 __device__ inline bool kind_failed(uint32_t k) { return k != kRank1 && k != kGeneral && k != kSkip; }
 
@@ -1814,16 +1816,77 @@ __global__ __launch_bounds__(256) void k_count_factor(Job jb) {
     jb.factor[g] = jb.pi[g] * d;
 }
 
+// Products of the anchor-to-anchor matrices over pieces of 64 chunks: one
+// wavefront per piece multiplies, in order, the matrices of each stretch of
+// general chunks of one text inside the piece (a run cut at the piece's
+// edges), a chunk without an anchor counting as the identity.  The product
+// replaces the matrix of the stretch's first chunk, and pend[first] is the
+// chunk after the stretch.  Lane 8k+b holds entry (k, b); entry (k, b) of
+// P G is the sum over m of P(k, m) G(m, b), P(k, m) taken from lane 8k+m.
+__global__ __launch_bounds__(64) void k_count_piece(Job jb) {
+    const uint32_t L = threadIdx.x, k = L >> 3, b = L & 7;
+    const uint32_t p0 = blockIdx.x * 64;
+    if (p0 >= jb.c) return;
+    const uint32_t np = jb.c - p0 < 64 ? jb.c - p0 : 64;
+    // lane l: kind of chunk p0+l (rank-1 for chunks of rejected texts) and
+    // its text
+    uint32_t kd = kRank1, tl = 0;
+    if (L < np) {
+        tl = text_of(jb, p0 + L);
+        if (text_ref(jb, tl).scalars[0] != 0) kd = jb.kind[p0 + L];
+    }
+    if (!__any(kd != kRank1)) return;
+    const uint64_t ident = k == b ? 1ull : 0ull;
+    uint64_t P = ident;
+    int st = -1;
+    uint32_t ts = 0;
+    uint64_t gc[kGenR], gn[kGenR];
+#pragma unroll
+    for (int m = 0; m < kGenR; ++m) gc[m] = jb.gmat[static_cast<uint64_t>(p0) * kGenR * kGenR + m * kGenR + b];
+    for (uint32_t l = 0; l < np; ++l) {
+        // the next chunk's column b in flight while this one is applied
+        const uint32_t ln = l + 1 < np ? l + 1 : l;
+#pragma unroll
+        for (int m = 0; m < kGenR; ++m) gn[m] = jb.gmat[static_cast<uint64_t>(p0 + ln) * kGenR * kGenR + m * kGenR + b];
+        const uint32_t kl = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(kd), static_cast<int>(l)));
+        const uint32_t tcur = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(tl), static_cast<int>(l)));
+        const bool gen = kl != kRank1;
+        if (st >= 0 && (!gen || tcur != ts)) {
+            jb.gmat[static_cast<uint64_t>(p0 + st) * kGenR * kGenR + L] = P;
+            if (L == 0) jb.pend[p0 + st] = p0 + l;
+            st = -1;
+        }
+        if (gen) {
+            if (st < 0) {
+                st = static_cast<int>(l);
+                ts = tcur;
+                P = ident;
+            }
+            if (kl == kGeneral) {
+                uint64_t q = 0;
+#pragma unroll
+                for (int m = 0; m < kGenR; ++m) q += shfl_u64(P, static_cast<int>(k * kGenR + m)) * gc[m];
+                P = q;
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < kGenR; ++m) gc[m] = gn[m];
+    }
+    if (st >= 0) {
+        jb.gmat[static_cast<uint64_t>(p0 + st) * kGenR * kGenR + L] = P;
+        if (L == 0) jb.pend[p0 + st] = p0 + np;
+    }
+}
+
 // Chains through general chunks: one wavefront per run of general chunks (a
 // text's first chunks, or the chunks after a rank-1 chunk, up to the next
 // rank-1 chunk or the text end).  The row vector gin[j0] of its first chunk
-// j0 is multiplied by the anchor-to-anchor matrices of the run's anchored
-// chunks in order; the last matrix has one column, so the product is a
-// number (and when the run has no anchor, gin[j0] is that number already):
-// the factor of the rank-1 chunk before j0 (times its pi), or the
-// text-start factor.  Lane 8k+b holds entry (k, b) of the current matrix
-// and entry k of the row vector; entry b of the product is the sum over the
-// lanes b, b+8, ..., b+56.
+// j0 is multiplied by the run's piece products in order; the last anchor
+// matrix has one column, so the product is a number (and when the run has no
+// anchor, gin[j0] is that number already): the factor of the rank-1 chunk
+// before j0 (times its pi), or the text-start factor.  Lane 8k+b holds entry
+// (k, b) of the current matrix and entry k of the row vector; entry b of
+// the product is the sum over the lanes b, b+8, ..., b+56.
 __global__ __launch_bounds__(64) void k_count_chain(Job jb) {
     const uint32_t L = threadIdx.x, k = L >> 3;
     for (uint32_t item = blockIdx.x; item < jb.flags[1]; item += gridDim.x) {
@@ -1831,47 +1894,22 @@ __global__ __launch_bounds__(64) void k_count_chain(Job jb) {
         const uint32_t t = text_of(jb, j0);
         const uint32_t c0 = first_chunk(jb, t), c1 = first_chunk(jb, t + 1);
         uint64_t vk = jb.gin[static_cast<uint64_t>(j0) * kGenR + k];
-        bool bad = false;
         uint32_t j = j0;
-        while (j < c1) {
-            // four matrices in flight
-            uint32_t kd[4];
-            uint64_t gm[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                kd[u] = j + u < c1 ? jb.kind[j + u] : kRank1;
-                gm[u] = j + u < c1 ? jb.gmat[static_cast<uint64_t>(j + u) * kGenR * kGenR + L] : 0ull;
-            }
-            bool stop = false;
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                if (stop) break;
-                if (kd[u] == kRank1) {       // the next anchor is a rank-1 chunk's (or the text ended)
-                    stop = true;
-                    break;
-                }
-                if (kd[u] == kSkip) {        // no anchor: walked through by the matrices around it
-                    ++j;
-                    continue;
-                }
-                if (kd[u] != kGeneral) {
-                    bad = true;
-                    stop = true;
-                    break;
-                }
-                uint64_t p = vk * gm[u];
-                p += shfl_xor_u64(p, 8);
-                p += shfl_xor_u64(p, 16);
-                p += shfl_xor_u64(p, 32);
-                vk = shfl_u64(p, static_cast<int>(k));   // entry k of the new row vector
-                ++j;
-            }
-            if (stop) break;
+        while (true) {
+            const uint64_t gm = jb.gmat[static_cast<uint64_t>(j) * kGenR * kGenR + L];
+            const uint32_t e = jb.pend[j];
+            uint64_t p = vk * gm;
+            p += shfl_xor_u64(p, 8);
+            p += shfl_xor_u64(p, 16);
+            p += shfl_xor_u64(p, 32);
+            vk = shfl_u64(p, static_cast<int>(k));   // entry k of the new row vector
+            // the run goes on into the next piece
+            if (e < c1 && e % 64 == 0 && jb.kind[e] != kRank1) j = e;
+            else break;
         }
         if (L == 0) {
-            const uint64_t d = bad ? 0ull : vk;           // entry 0 of the final row (one column)
-            if (j0 == c0) jb.factor[jb.c + t] = d;
-            else jb.factor[j0 - 1] = jb.pi[j0 - 1] * d;
+            if (j0 == c0) jb.factor[jb.c + t] = vk;   // entry 0 of the final row (one column)
+            else jb.factor[j0 - 1] = jb.pi[j0 - 1] * vk;
         }
     }
 }
@@ -1984,6 +2022,7 @@ __global__ __launch_bounds__(kScalarThreads) void k_text_scalars(Tabs tb, Job jb
 // their segment lists.
 
 constexpr int kGenBlock = 32;                  // columns staged per block
+constexpr int kGenYRows = kGenSeg;             // count vector rows
 
 // LDS of the general kernel (one wavefront): staged column words and prefix
 // counts (row 0 is the column above the block), segment lists, two count
@@ -1998,7 +2037,7 @@ __host__ __device__ inline GenLds gen_lds(uint32_t W, uint32_t nseg, bool fol_ld
     o.colw = at;
     at += (kGenBlock + 1) * W * 8;
     o.y = at;
-    at += 2 * kGenSeg * kGenR * 8;
+    at += 2 * kGenYRows * kGenR * 8;
     o.pre = at;
     at += (kGenBlock + 1) * W * 2;
     o.segl = at;
@@ -2035,12 +2074,12 @@ __device__ inline uint64_t gen_anchor(const GenCtx &g, uint64_t lo, uint64_t hi)
     return wave_min_u64(best);
 }
 
-// Backward walk from column `from` down to column `to` (to <= from).  V <=
+// Backward walk from column `from` down to column `to` (to <= from).  VB <=
 // kGenR count vectors start at column `from`: start(k, v) for its k-th
 // segment.  On return lane k < m_to holds y_to[k][v] in acc[v] (zero for v
-// past the start vectors).  Returns false when a column of the walk has more
-// than kGenSeg segments.
-template <class Start>
+// >= VB).  Returns false when a column of the walk has more than kGenSeg
+// segments.
+template <int VB, class Start>
 __device__ inline bool gen_walk(const GenCtx &g, uint64_t from, uint64_t to, Start start, uint64_t acc[kGenR],
                                 uint32_t *m_to) {
     const uint32_t lane = threadIdx.x, W = g.W;
@@ -2088,10 +2127,10 @@ __device__ inline bool gen_walk(const GenCtx &g, uint64_t from, uint64_t to, Sta
             if (first && r == 1) {
                 if (lane < m) {
 #pragma unroll
-                    for (int v = 0; v < kGenR; ++v) a[v] = start(lane, v);
+                    for (int v = 0; v < VB; ++v) a[v] = start(lane, v);
                 }
             } else if (lane < m) {
-                const uint64_t *yprev = g.y + yc * kGenSeg * kGenR;
+                const uint64_t *yprev = g.y + yc * kGenYRows * kGenR;
                 const uint32_t s = g.segl[(r - 1) * kGenSeg + lane];
                 const uint64_t *nx = g.colw + (r - 1) * W;
                 const uint16_t *np = g.pre + (r - 1) * W;
@@ -2104,15 +2143,15 @@ __device__ inline bool gen_walk(const GenCtx &g, uint64_t from, uint64_t to, Sta
                         const uint32_t rk = np[w] + static_cast<uint32_t>(__popcll(cwd & low_mask(b)));
                         const uint64_t *yr = yprev + rk * kGenR;
 #pragma unroll
-                        for (int v = 0; v < kGenR; ++v) a[v] += yr[v];
+                        for (int v = 0; v < VB; ++v) a[v] += yr[v];
                     }
                 }
             }
             yc ^= 1u;
             if (lane < m) {
-                uint64_t *ycur = g.y + yc * kGenSeg * kGenR + lane * kGenR;
+                uint64_t *ycur = g.y + yc * kGenYRows * kGenR + lane * kGenR;
 #pragma unroll
-                for (int v = 0; v < kGenR; ++v) ycur[v] = a[v];
+                for (int v = 0; v < VB; ++v) ycur[v] = a[v];
             }
 #pragma unroll
             for (int v = 0; v < kGenR; ++v) acc[v] = a[v];
@@ -2134,17 +2173,19 @@ struct GenTarget {
     uint64_t col;
     uint32_t how;            // 0: unit vectors over r segments, 1: v of chunk h, 2: ones
     uint32_t h;
+    uint32_t r;              // start vectors
 };
 
 __device__ inline GenTarget gen_next(const GenCtx &g, const Job &jb, const ChunkCtx &cx, uint32_t c0, uint32_t jj) {
     for (;; ++jj) {
         const uint32_t li = jj - c0;
-        if (li == cx.ct) return {cx.tr.n, 2u, 0u};
+        if (li == cx.ct) return {cx.tr.n, 2u, 0u, 1u};
         const uint64_t lo = static_cast<uint64_t>(li) * jb.s;
-        if (jb.kind[jj] == kRank1) return {lo, 1u, jj};
+        if (jb.kind[jj] == kRank1) return {lo, 1u, jj, 1u};
         const uint64_t hi = li + 1 == cx.ct ? cx.tr.n : lo + jb.s;
         const uint64_t key = gen_anchor(g, lo, hi);
-        if ((key >> 40) <= static_cast<uint64_t>(kGenR)) return {lo + (key & ((1ull << 40) - 1)), 0u, 0u};
+        const uint32_t r = static_cast<uint32_t>(key >> 40);
+        if (r <= static_cast<uint32_t>(kGenR)) return {lo + (key & ((1ull << 40) - 1)), 0u, 0u, r};
     }
 }
 
@@ -2187,12 +2228,16 @@ __global__ __launch_bounds__(64) void k_count_general(Tabs tb, Job jb) {
                 if (v != 0) return 0ull;
                 return tg.how == 1 ? vh[k] : 1ull;
             };
-            return gen_walk(g, tg.col, to, start, acc, &mt);
+            if (tg.r <= 1) return gen_walk<1>(g, tg.col, to, start, acc, &mt);
+            if (tg.r <= 2) return gen_walk<2>(g, tg.col, to, start, acc, &mt);
+            if (tg.r <= 4) return gen_walk<4>(g, tg.col, to, start, acc, &mt);
+            return gen_walk<kGenR>(g, tg.col, to, start, acc, &mt);
         };
         // the row into the run: w^T T(lo -> first anchor), w the previous
         // chunk's u or ones (a number when the run has no anchor)
         if (starts) {
-            const GenTarget tg = anchored ? GenTarget{a, 0u, 0u} : gen_next(g, jb, cx, c0, j + 1);
+            const GenTarget tg = anchored ? GenTarget{a, 0u, 0u, static_cast<uint32_t>(key >> 40)}
+                                          : gen_next(g, jb, cx, c0, j + 1);
             ok = walk_to(tg, cx.lo);
             if (ok) {
                 const uint64_t wk = lane >= mt ? 0ull

@@ -390,7 +390,7 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
             jpcst[d].push_back(l < TL ? L.add(N + 1) : -1);
             jpcv[d].push_back(l < TL ? L.add((N + 1) * 8) : -1);
         }
-    int idims = -1, iuv = -1, ipi = -1, ifac = -1, ikind = -1, iovf = -1, ichain = -1, igmat = -1, igin = -1;
+    int idims = -1, iuv = -1, ipi = -1, ifac = -1, ikind = -1, iovf = -1, ichain = -1, igmat = -1, igin = -1, ipend = -1;
     if (count) {
         idims = L.add(size_t(c) * 2);
         iuv = L.add(size_t(c) * 2 * kVec * 8);
@@ -401,6 +401,7 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
         ichain = L.add(size_t(c) * 4);
         igmat = L.add(size_t(c) * kGenR * kGenR * 8);
         igin = L.add(size_t(c) * kGenR * 8);
+        ipend = L.add(size_t(c) * 4);
     }
 
     uint8_t *base;
@@ -484,6 +485,7 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
         jb.chains = reinterpret_cast<uint32_t *>(ptr(ichain));
         jb.gmat = reinterpret_cast<uint64_t *>(ptr(igmat));
         jb.gin = reinterpret_cast<uint64_t *>(ptr(igin));
+        jb.pend = reinterpret_cast<uint32_t *>(ptr(ipend));
     }
 
     const bool timed = opts && opts->events && opts->num_events >= SLPF_NUM_PHASE_EVENTS;
@@ -630,6 +632,7 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
         else
             hipLaunchKernelGGL(k_count_general<false>, dim3(gblocks), dim3(64), gen_lds(W, tb.nseg, false).end,
                                stream, tb, jb);
+        hipLaunchKernelGGL(k_count_piece, dim3((c + 63) / 64), dim3(64), 0, stream, jb);
         hipLaunchKernelGGL(k_count_factor, dim3((c + nt + 255) / 256), dim3(256), 0, stream, jb);
         hipLaunchKernelGGL(k_count_chain, dim3(std::min<uint32_t>(c, 1024)), dim3(64), 0, stream, jb);
     }
