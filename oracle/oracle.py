@@ -227,6 +227,45 @@ class Oracle:
         """The multi-entry DFA: powerset from every singleton {q_j} (forward)."""
         return self.powerset([frozenset([j]) for j in range(self.nseg)], 0, alphabet)
 
+    # -- compact SLPF (App. SLPF optimization, SLPF encoding), plain Python
+    def candidates(self, prev, nxt):
+        """The segments that can sit in a column between byte ``prev`` (None
+        at the text start) and byte ``nxt`` (None at the text end), ascending:
+        end-letter ``nxt`` (final segments at the end) and a follower of some
+        segment labelled ``prev`` (initial segments at the start).  Every
+        segment of a clean column follows a segment of the previous column
+        through that column's label, and has the next byte as end-letter."""
+        if prev is None:
+            pool = self.I
+        else:
+            pool = frozenset().union(*([self.folseg[r] for r in range(self.nseg) if self.labels[r] == prev] or
+                                       [frozenset()]))
+        keep = self.F if nxt is None else frozenset(s for s in range(self.nseg) if self.labels[s] == nxt)
+        return sorted(pool & keep)
+
+    def compact(self, text, cols=None):
+        """Column r as one word: bit k set iff the k-th candidate of
+        (x_r, x_{r+1}) is in the clean column.  Raises ValueError if a clean
+        segment is not a candidate or a candidate index reaches 64."""
+        x = _bytes(text)
+        n = len(x)
+        if cols is None:
+            cols = self.parse(x)[0]
+        out = np.zeros(n + 1, np.uint64)
+        ranks = {}
+        for r in range(n + 1):
+            key = (x[r - 1] if r > 0 else None, x[r] if r < n else None)
+            if key not in ranks:
+                ranks[key] = {s: k for k, s in enumerate(self.candidates(*key))}
+            rk = ranks[key]
+            word = 0
+            for s in self.to_set(cols[r]):
+                if s not in rk or rk[s] >= 64:
+                    raise ValueError("column %d: segment %d outside its candidate list" % (r, s))
+                word |= 1 << rk[s]
+            out[r] = np.uint64(word)
+        return out
+
     # -- the parallel algorithm's quantities (Sect. 3.2), plain Python
     def run_fwd(self, s, y):
         for a in y:

@@ -116,6 +116,44 @@ def test_e2_ex6_parallel(e2):
     assert cols == tr["C"] and acc and cnt == ex["trees"]
 
 
+def test_e2_compact_encoding(e2):
+    # hand-derived candidate lists and compact words of Ex. 6 (App. SLPF
+    # optimization); the order inside a list is the segment order of Tab.
+    # segments, which the canonical order keeps for e2's lists
+    g, o, pid = e2
+    byte = {"start": None, "end": None, "a": ord("a"), "b": ord("b")}
+    for key, want in g["candidates"].items():
+        p, q = key.split(",")
+        got = o.candidates(byte[p], byte[q])
+        assert got == [pid[k] for k in want], key
+    ex = g["ex6"]
+    assert o.compact(ex["text"].encode()).tolist() == g["compact_ex6"]
+
+
+def _decode_compact(o, x, words):
+    out = []
+    for r, w in enumerate(words.tolist()):
+        cand = o.candidates(x[r - 1] if r > 0 else None, x[r] if r < len(x) else None)
+        out.append(frozenset(cand[k] for k in range(64) if (w >> k) & 1))
+    return out
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_compact_is_lossless_and_columns_lie_in_candidates(seed):
+    # every clean column lies inside its candidate list (the invariant the
+    # encoding rests on) and decoding the words gives the columns back
+    tree = regen.random_re(900 + seed, n_ops=10, max_depth=5, alphabet=b"abc")
+    o = Oracle(regen.to_re(tree))
+    rng = np.random.default_rng(seed)
+    from gen import textgen
+    for j in range(4):
+        t = textgen.sample_text(tree, seed * 10 + j, int(rng.integers(0, 300))).tobytes()
+        cols, acc, _ = o.parse(t)
+        words = o.compact(t, cols)
+        assert _decode_compact(o, t, words) == [o.to_set(c) for c in cols]
+        assert all(w != 0 for w in words.tolist()) == acc
+
+
 # ------------------------------------------------------------ e3, e1, e4
 
 def test_e3_nfa_and_slpf():
