@@ -64,7 +64,8 @@ def make_text(n, corrupt):
     return regen.to_re(tree), text
 
 
-def run_gpu(parser, text_np, steps, warmup, chunk_bytes):
+def run_gpu(parser, text_np, steps, warmup, chunk_bytes, compact=False):
+    """Timed parses; ``compact``: the compact SLPF (one word per column)."""
     import numpy as np
     import torch
     import paper_2503_06763_amd as S
@@ -72,15 +73,16 @@ def run_gpu(parser, text_np, steps, warmup, chunk_bytes):
     n = text_np.size
     text = torch.from_numpy(text_np).to(dev)
     W = parser.W
-    cols = torch.empty((n + 1, W), dtype=torch.int64, device=dev)
+    cols = torch.empty((n + 1,) if compact else (n + 1, W), dtype=torch.int64, device=dev)
     sc = torch.empty(3, dtype=torch.int64, device=dev)
+    flags = S.PARSE_COMPACT if compact else 0
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(S.NUM_PHASE_EVENTS)] for _ in range(steps)]
     for _ in range(warmup):
-        parser.parse_into(text, n, cols, sc, chunk_bytes)
+        parser.parse_into(text, n, cols, sc, chunk_bytes, flags)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(steps):
-        parser.parse_into(text, n, cols, sc, chunk_bytes, events=evs[k])
+        parser.parse_into(text, n, cols, sc, chunk_bytes, flags, events=evs[k])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms = (t1 - t0) * 1e3 / steps
@@ -489,7 +491,21 @@ def main():
         "slpf_gbs": round(algo / (ms * 1e-3) / 1e9, 2),
         "roofline": roof,
     }
-    del _
+    # compact SLPF of the same text: one word per column over its candidate
+    # list; checked against the plain layout through slpf_decode_compact
+    cms, cphase, cscal, ccols = run_gpu(parser, text, args.steps, args.warmup, args.chunk_bytes, compact=True)
+    dec = parser.decode_compact(torch.from_numpy(text).to("cuda:0"), ccols)
+    same = bool(torch.equal(dec, _)) and cscal == scal
+    del dec, ccols, _
+    calgo = n + (n + 1) * 8
+    out["compact"] = {"value": round(n / (cms * 1e-3) / 1e9, 3), "unit": "GB/s", "ms_per_step": round(cms, 4),
+                      "phases_ms": {k: round(v, 4) for k, v in cphase.items()},
+                      "algorithmic_bytes": calgo,
+                      "build_achieved_gbs": round(calgo / (cphase["build"] * 1e-3) / 1e9, 2),
+                      "build_frac_of_hbm_peak": round(calgo / (cphase["build"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                      "decodes_to_plain": same,
+                      "what": "SLPF_PARSE_COMPACT: each column as one word over its candidate list"}
+    print("compact: %.3f ms/step phases %s decodes_to_plain %s" % (cms, cphase, same), file=sys.stderr, flush=True)
     torch.cuda.empty_cache()
     rms, racc = run_recognize(parser, text, args.steps, args.warmup, args.chunk_bytes)
     out["recognizer"] = {"value": round(n / (rms * 1e-3) / 1e9, 3), "unit": "GB/s", "ms_per_step": round(rms, 4),
@@ -516,6 +532,14 @@ def main():
             "build_frac_of_hbm_peak": round(algo2 / (phase2["build"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
         print("companion: %.3f ms/step phases %s scalars %s" % (ms2, phase2, scal2), file=sys.stderr,
               flush=True)
+        torch.cuda.empty_cache()
+        cms2, cphase2, cscal2, _c = run_gpu(parser, clean, args.steps, args.warmup, args.chunk_bytes, compact=True)
+        del _c
+        out["companion_clean_text"]["compact"] = {
+            "value": round(n2 / (cms2 * 1e-3) / 1e9, 3), "ms_per_step": round(cms2, 4),
+            "phases_ms": {k: round(v, 4) for k, v in cphase2.items()},
+            "same_scalars": cscal2 == scal2}
+        print("companion compact: %.3f ms/step phases %s" % (cms2, cphase2), file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pat, text, args.cpu_sample)

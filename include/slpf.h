@@ -136,14 +136,40 @@ slpf_status slpf_table_dump(const slpf_parser *p, int dir, uint64_t *sets, uint3
 /* Bytes of the SLPF of an n-byte text: (n + 1) * W * 8. */
 uint64_t slpf_forest_bytes(const slpf_parser *p, uint64_t n);
 
+/*
+ * Compact SLPF (App. SLPF optimization, SLPF encoding).  Every segment of
+ * the clean column C_r follows a segment labelled x_r and has the end-letter
+ * x_{r+1}, so C_r lies in the candidate list X(x_r, x_{r+1}): the segments
+ * with end-letter class of x_{r+1} (final segments at r = n) that follow a
+ * segment labelled with the class of x_r (initial segments at r = 0),
+ * ascending by segment id.  slpf_compile bounds every such list to 64
+ * segments, so the compact column r is one uint64_t whose bit k is set iff
+ * the k-th segment of X(x_r, x_{r+1}) is in C_r: (n + 1) * 8 bytes for the
+ * whole SLPF instead of (n + 1) * W * 8, with no overflow case.
+ */
+uint64_t slpf_compact_bytes(uint64_t n);
+
+/*
+ * Expand a compact SLPF (compact_dev, n + 1 words, from a parse of text_dev
+ * with SLPF_PARSE_COMPACT) into the W-word columns of slpf_forest
+ * (columns_dev, slpf_forest_bytes(p, n) bytes).  Device pointers; the text
+ * gives each column's candidate list.  Stream-ordered on hip_stream.
+ * SLPF_E_ARG on a NULL pointer (text_dev may be NULL when n = 0).
+ */
+slpf_status slpf_decode_compact(const slpf_parser *p, const uint8_t *text_dev, uint64_t n,
+                                const uint64_t *compact_dev, uint64_t *columns_dev, void *hip_stream);
+
 /* -------------------------------------------------------------------- parse */
 
 enum {
     SLPF_PARSE_NO_COUNT = 1u << 0,      /* skip the tree count (scalars[1] = 0, [2] = 2) */
     SLPF_PARSE_FORCE_L2 = 1u << 1,      /* read transition tables through L2 even if LDS fits */
-    SLPF_PARSE_RECOGNIZE = 1u << 2      /* recogniser only (Sect. 3.2: the forward reacher and joiner
+    SLPF_PARSE_RECOGNIZE = 1u << 2,     /* recogniser only (Sect. 3.2: the forward reacher and joiner
                                            decide membership): scalars[0] = accept, [1] = 0, [2] = 2;
                                            no column is written (columns_dev may be NULL) */
+    SLPF_PARSE_COMPACT = 1u << 3        /* write the compact SLPF (App. SLPF optimization, SLPF
+                                           encoding): column r as ONE word; see slpf_decode_compact.
+                                           capacity_bytes >= slpf_compact_bytes(n) */
 };
 
 typedef struct {

@@ -26,12 +26,13 @@ COMPILE_HOST_ONLY = 1
 PARSE_NO_COUNT = 1
 PARSE_FORCE_L2 = 2
 PARSE_RECOGNIZE = 4
+PARSE_COMPACT = 8
 
 EXPORTS = ["slpf_compile", "slpf_parser_destroy", "slpf_parser_info_get", "slpf_segment_text",
            "slpf_table_dump", "slpf_forest_bytes", "slpf_parse", "slpf_parse_batch", "slpf_tune", "slpf_parser_trim",
            "slpf_num_chunks", "slpf_status_str", "slpf_server_create", "slpf_server_destroy",
            "slpf_server_submit", "slpf_server_poll", "slpf_server_result", "slpf_server_release",
-           "slpf_server_stats"]
+           "slpf_server_stats", "slpf_compact_bytes", "slpf_decode_compact"]
 
 
 class SlpfError(RuntimeError):
@@ -137,6 +138,10 @@ def lib(path: str = LIB_PATH):
     L.slpf_server_release.restype = ctypes.c_int
     L.slpf_server_stats.argtypes = [vp, ctypes.POINTER(ServerState)]
     L.slpf_server_stats.restype = ctypes.c_int
+    L.slpf_compact_bytes.argtypes = [ctypes.c_uint64]
+    L.slpf_compact_bytes.restype = ctypes.c_uint64
+    L.slpf_decode_compact.argtypes = [vp, vp, ctypes.c_uint64, vp, vp, vp]
+    L.slpf_decode_compact.restype = ctypes.c_int
     L.slpf_num_chunks.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ParseOpts)]
     L.slpf_num_chunks.restype = ctypes.c_uint64
     L.slpf_status_str.argtypes = [ctypes.c_int]
@@ -278,6 +283,30 @@ class Parser:
         self.parse_into(text, n, cols, sc, chunk_bytes, flags, tr, stream, events)
         return (cols, sc, tr) if trace else (cols, sc)
 
+    def parse_compact(self, text, chunk_bytes: int = 0, count: bool = True, force_l2: bool = False,
+                      stream=None, events=None):
+        """Parse into the compact SLPF: returns (columns [n+1] int64 view of one uint64 word
+        per column over its candidate list, scalars [3]) on the device."""
+        import torch
+        n = text.numel()
+        cols = torch.empty(n + 1, dtype=torch.int64, device=text.device)
+        sc = torch.empty(3, dtype=torch.int64, device=text.device)
+        flags = PARSE_COMPACT | (0 if count else PARSE_NO_COUNT) | (PARSE_FORCE_L2 if force_l2 else 0)
+        self.parse_into(text, n, cols, sc, chunk_bytes, flags, None, stream, events)
+        return cols, sc
+
+    def decode_compact(self, text, compact, stream=None):
+        """W-word columns [n+1, W] (int64 view) of a compact SLPF of ``text`` (device tensors)."""
+        import torch
+        n = text.numel()
+        out = torch.empty((n + 1, self.W), dtype=torch.int64, device=compact.device)
+        if stream is None:
+            stream = torch.cuda.current_stream(compact.device)
+        st = self._L.slpf_decode_compact(self._h, text.data_ptr() if n else None, n, compact.data_ptr(),
+                                         out.data_ptr(), ctypes.c_void_p(stream.cuda_stream))
+        _check(st, "slpf_decode_compact")
+        return out
+
 
     def recognize(self, text, chunk_bytes: int = 0, force_l2: bool = False, stream=None, events=None):
         """Recogniser mode (forward reach and join only): returns the scalars
@@ -375,10 +404,11 @@ class Server:
     ``poll`` reports the request finished (the GPU reads it until then)."""
 
     def __init__(self, slots: int = 4, max_batch_texts: int = 256, memory_budget: int = 1 << 30,
-                 count: bool = True, device: int = 0):
+                 count: bool = True, device: int = 0, compact: bool = False):
         L = lib()
-        o = ServerOpts(ctypes.sizeof(ServerOpts), slots, max_batch_texts, 0 if count else PARSE_NO_COUNT,
-                       memory_budget, device, 0)
+        flags = (0 if count else PARSE_NO_COUNT) | (PARSE_COMPACT if compact else 0)
+        o = ServerOpts(ctypes.sizeof(ServerOpts), slots, max_batch_texts, flags, memory_budget, device, 0)
+        self.compact = compact
         h = ctypes.c_void_p()
         _check(L.slpf_server_create(ctypes.byref(o), ctypes.byref(h)), "slpf_server_create")
         self._L, self._h = L, h
@@ -426,16 +456,19 @@ class Server:
         return f.columns_dev, f.capacity_bytes, f.scalars_dev
 
     def result_tensors(self, tag: int, n: int, W: int, device="cuda:0"):
-        """Host copies (columns uint64 [n+1, W], scalars uint64 [3]) of a finished request."""
+        """Host copies (columns uint64 [n+1, W], or [n+1] compact words, and
+        scalars uint64 [3]) of a finished request."""
         import numpy as np
         import torch
         cp, cap, sp = self.result(tag)
+        if self.compact:
+            W = 1
         cols = np.empty((n + 1) * W, np.uint64)
         sc = np.empty(3, np.uint64)
         torch.cuda.synchronize()
         _hip_copy_to_host(cols.ctypes.data, cp, cols.nbytes)
         _hip_copy_to_host(sc.ctypes.data, sp, sc.nbytes)
-        return cols.reshape(n + 1, W), sc
+        return (cols if self.compact else cols.reshape(n + 1, W)), sc
 
     def release(self, tag: int):
         _check(self._L.slpf_server_release(self._h, tag), "slpf_server_release")

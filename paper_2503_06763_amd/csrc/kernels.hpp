@@ -68,6 +68,7 @@ struct Tabs {
     // the byte offset of the next state's row, the class map gives byte
     // offsets of the classes, so a step is one add and one lookup
     const uint16_t *fdo, *rdo, *cls2;
+    const uint8_t *rankx;       // NL x nseg: rank of a segment in X[p, its end-letter class]
     uint32_t off16;
     uint32_t fhmask, rhmask;
     uint32_t C, W, NL;          // classes, words, C + 1
@@ -114,6 +115,8 @@ struct Job {
     uint64_t *gin;              // [c][kGenR]: row vector into a chain's first anchor
     uint32_t *pend;             // [c]: the chunk after a stretch of general chunks (piece products)
     uint32_t fwd_only;          // recogniser: forward runs and forward join only
+    uint32_t compact;           // columns as one word over the candidate list X[x_r, x_r+1]
+    uint32_t rank_lds;          // compact build: LDS byte offset of the rank table, 0 = read it from L2
 };
 
 constexpr int kDedupEvery = 32;
@@ -825,7 +828,6 @@ __device__ inline uint32_t wave_max_u32(uint32_t v) {
 
 constexpr int kBuildThreads = 512;             // 8 wavefronts
 constexpr int kStageCols = 32;                 // columns per staged part of a window
-constexpr int kParts = 64 / kStageCols;
 constexpr int kStageRow = kStageCols + 1;      // padded: lanes fall in distinct banks
 constexpr int kStageBytes = kBuildThreads * kStageRow * 4;
 
@@ -841,12 +843,30 @@ constexpr int kStageBytes = kBuildThreads * kStageRow * 4;
 // 32-column boundary (so on a 128-byte boundary for any W); lane e writes word
 // e, 512 contiguous bytes per store instruction, as streaming (nontemporal)
 // stores.  Wavefronts synchronize only with themselves.
-template <bool TAB_LDS, bool BITS_LDS>
+//
+// COMPACT writes the compact SLPF instead: column r as one word whose bit k
+// says that the k-th segment of the candidate list X[class(x_r),
+// class(x_{r+1})] is in the clean column (the clean column lies in that list,
+// which holds at most 64 segments).  Parts are 16 columns (one 128-byte line
+// per chunk), and the stage row holds each column's previous-byte class
+// after its id pairs.
+template <bool TAB_LDS, bool BITS_LDS, bool COMPACT>
 __global__ __launch_bounds__(kBuildThreads) void k_build(Tabs tb, Job jb) {
+    constexpr int SC = COMPACT ? 16 : kStageCols;     // columns per part
+    constexpr int PARTS = 64 / SC;
+    static_assert(!COMPACT || 2 * SC <= kStageRow, "a compact stage row holds ids and classes");
     extern __shared__ __align__(16) uint8_t smem[];
     uint32_t *stage = reinterpret_cast<uint32_t *>(smem);
     const BuildTabs<TAB_LDS, BITS_LDS> T = stage_build<TAB_LDS, BITS_LDS>(tb, smem, kStageBytes);
     const uint32_t C = tb.C, W = tb.W;
+    // compact: the rank table in LDS when the launch reserved room for it
+    const uint8_t *rkl = smem + jb.rank_lds;
+    if (COMPACT && jb.rank_lds) {
+        uint8_t *dst = smem + jb.rank_lds;
+        for (uint32_t k = threadIdx.x; k < tb.NL * tb.nseg; k += blockDim.x) dst[k] = tb.rankx[k];
+        __syncthreads();
+    }
+    auto rank_of = [&](uint32_t idx) -> uint32_t { return jb.rank_lds ? rkl[idx] : tb.rankx[idx]; };
     const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t wave_first = blockIdx.x * blockDim.x + wv * 64;
@@ -881,8 +901,22 @@ __global__ __launch_bounds__(kBuildThreads) void k_build(Tabs tb, Job jb) {
             if (t < static_cast<int>(len)) f = T.fd[f * C + byte_of(cw, t)];
     }
     if (act && cx.last) {   // the text-end column: J_c & F
-        for (uint32_t w = 0; w < W; ++w)
-            out[cx.tr.n * W + w] = T.fb[f * W + w] & T.rb[tb.rstart * W + w];
+        if constexpr (COMPACT) {
+            const uint32_t pc = T.cls[text[cx.tr.n - 1]];
+            uint64_t m = 0;
+            for (uint32_t w = 0; w < W; ++w) {
+                uint64_t v = T.fb[f * W + w] & T.rb[tb.rstart * W + w];
+                while (v) {
+                    const uint32_t sg = w * 64 + static_cast<uint32_t>(__builtin_ctzll(v));
+                    v &= v - 1;
+                    m |= 1ull << tb.rankx[pc * tb.nseg + sg];
+                }
+            }
+            out[cx.tr.n] = m;
+        } else {
+            for (uint32_t w = 0; w < W; ++w)
+                out[cx.tr.n * W + w] = T.fb[f * W + w] & T.rb[tb.rstart * W + w];
+        }
     }
 
     // backward sweep, two windows in flight; fwA[t] = forward id at column a0+t
@@ -892,6 +926,8 @@ __global__ __launch_bounds__(kBuildThreads) void k_build(Tabs tb, Job jb) {
     uint32_t fwA[64], cwA[16];
     uint32_t lenA = 0;
     uint64_t a0A = 0;
+    // class of the byte before the chunk (the text start: the sentinel C)
+    const uint32_t pfirst = COMPACT && act && lo > 0 ? T.cls[text[lo - 1]] : C;
     if (nwin) {   // the last window of the chunk
         a0A = lo + 64ull * (nwin - 1);
         lenA = static_cast<uint32_t>(hi - a0A);
@@ -917,39 +953,73 @@ __global__ __launch_bounds__(kBuildThreads) void k_build(Tabs tb, Job jb) {
         }
         if (on) jb.bckpt[ck(jb, i, w)] = static_cast<uint16_t>(b);
         const uint32_t len_now = on ? lenA : 0;
+        // class of the byte before window w: the last byte of window w-1
+        const uint32_t pA0 = nxt ? byte_of(cwB, 63) : pfirst;
 #pragma unroll
-        for (int h = kParts - 1; h >= 0; --h) {
-            // columns a0+S*h .. a0+S*h+S-1 of window w (S = kStageCols), right to left
+        for (int h = PARTS - 1; h >= 0; --h) {
+            // columns a0+S*h .. a0+S*h+S-1 of window w (S = SC), right to left
 #pragma unroll
-            for (int u = kStageCols - 1; u >= 0; --u) {
-                const int t = h * kStageCols + u;
+            for (int u = SC - 1; u >= 0; --u) {
+                const int t = h * SC + u;
                 if (on && t < static_cast<int>(lenA)) {
                     b = T.rd[b * C + byte_of(cwA, t)];    // now the backward id at column a0+t
                     mine[u] = fwA[t] | (b << 16);
+                    if constexpr (COMPACT) mine[SC + u] = t > 0 ? byte_of(cwA, t - 1) : pA0;
                 }
-                const int tf = (kParts - 1 - h) * kStageCols + (kStageCols - 1 - u);   // forward step of window w-1
+                const int tf = (PARTS - 1 - h) * SC + (SC - 1 - u);   // forward step of window w-1
                 if (nxt) {
                     fwB[tf] = g;
                     g = T.fd[g * C + byte_of(cwB, tf)];
                 }
             }
             wave_sync();
-            // write columns a0+S*h .. of every chunk of the wavefront
-            for (int j = 0; j < 64; ++j) {
-                const uint32_t lj = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(len_now), j));
-                const uint32_t np = lj > static_cast<uint32_t>(h * kStageCols)
-                                        ? (lj - h * kStageCols < static_cast<uint32_t>(kStageCols) ? lj - h * kStageCols : kStageCols) : 0;
-                if (np == 0) continue;
-                uint64_t *region = global_ptr<uint64_t>(readlane_u64(reinterpret_cast<uint64_t>(out + a0A * W), j)) +
-                                   static_cast<uint64_t>(h * kStageCols) * W;
-                const uint32_t *sj = wave_rows + j * kStageRow;
-                const uint32_t nwords = np * W;
-                for (uint32_t e = lane; e < nwords; e += 64) {
-                    const uint32_t p = static_cast<uint32_t>((static_cast<uint64_t>(e) * tb.wmagic) >> 32);
-                    const uint32_t ww = e - p * W;
-                    const uint32_t v = sj[p];
-                    // streaming store: the SLPF is not read back by this kernel
-                    __builtin_nontemporal_store(T.fb[(v & 0xffffu) * W + ww] & T.rb[(v >> 16) * W + ww], region + e);
+            if constexpr (COMPACT) {
+                // 16 words per chunk: lanes 16g..16g+15 write chunk 4q+g
+                const uint32_t e = lane & 15;
+                const uint64_t base = reinterpret_cast<uint64_t>(out + a0A) + static_cast<uint64_t>(h * SC) * 8;
+#pragma unroll 1
+                for (int q = 0; q < 16; ++q) {
+                    const int j = q * 4 + static_cast<int>(lane >> 4);
+                    const uint32_t lj = static_cast<uint32_t>(__shfl(static_cast<int>(len_now), j));
+                    const uint64_t rj = shfl_u64(base, j);
+                    const uint32_t np = lj > static_cast<uint32_t>(h * SC)
+                                            ? (lj - h * SC < static_cast<uint32_t>(SC) ? lj - h * SC : SC) : 0;
+                    if (e < np) {
+                        const uint32_t *sj = wave_rows + j * kStageRow;
+                        const uint32_t v = sj[e], pc = sj[SC + e];
+                        const uint32_t fi = v & 0xffffu, bi = v >> 16;
+                        uint64_t m = 0;
+                        if (fi != 0 && bi != 0) {   // id 0 is the empty set (dead run)
+                            for (uint32_t ww = 0; ww < W; ++ww) {
+                                uint64_t x = T.fb[fi * W + ww] & T.rb[bi * W + ww];
+                                while (x) {
+                                    const uint32_t sg = ww * 64 + static_cast<uint32_t>(__builtin_ctzll(x));
+                                    x &= x - 1;
+                                    m |= 1ull << rank_of(pc * tb.nseg + sg);
+                                }
+                            }
+                        }
+                        __builtin_nontemporal_store(m, global_ptr<uint64_t>(rj) + e);
+                    }
+                }
+            } else {
+                // write columns a0+S*h .. of every chunk of the wavefront
+                for (int j = 0; j < 64; ++j) {
+                    const uint32_t lj = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(len_now), j));
+                    const uint32_t np = lj > static_cast<uint32_t>(h * SC)
+                                            ? (lj - h * SC < static_cast<uint32_t>(SC) ? lj - h * SC : SC) : 0;
+                    if (np == 0) continue;
+                    uint64_t *region = global_ptr<uint64_t>(readlane_u64(reinterpret_cast<uint64_t>(out + a0A * W), j)) +
+                                       static_cast<uint64_t>(h * SC) * W;
+                    const uint32_t *sj = wave_rows + j * kStageRow;
+                    const uint32_t nwords = np * W;
+                    for (uint32_t e = lane; e < nwords; e += 64) {
+                        const uint32_t p = static_cast<uint32_t>((static_cast<uint64_t>(e) * tb.wmagic) >> 32);
+                        const uint32_t ww = e - p * W;
+                        const uint32_t v = sj[p];
+                        // streaming store: the SLPF is not read back by this kernel
+                        __builtin_nontemporal_store(T.fb[(v & 0xffffu) * W + ww] & T.rb[(v >> 16) * W + ww], region + e);
+                    }
                 }
             }
             wave_sync();
@@ -1947,13 +2017,16 @@ __global__ __launch_bounds__(kScalarThreads) void k_text_scalars(Tabs tb, Job jb
         if (th == 0) {
             const uint64_t *fb = tb.fbits + static_cast<uint64_t>(tb.fstart) * tb.W;
             const uint64_t *rb = tb.rbits + static_cast<uint64_t>(tb.rstart) * tb.W;
-            uint64_t any = 0, pc = 0;
+            uint64_t any = 0, pc = 0, cm = 0;
             for (uint32_t w = 0; w < tb.W; ++w) {
                 const uint64_t v = fb[w] & rb[w];
-                tr.out[w] = v;
+                if (!jb.compact) tr.out[w] = v;
                 any |= v;
                 pc += __popcll(v);
+                for (uint64_t x = v; x; x &= x - 1)   // compact: ranks in X[start, end]
+                    cm |= 1ull << tb.rankx[tb.C * tb.nseg + w * 64 + static_cast<uint32_t>(__builtin_ctzll(x))];
             }
+            if (jb.compact) tr.out[0] = cm;
             tr.scalars[0] = any ? 1 : 0;
             tr.scalars[1] = count ? pc : 0;
             tr.scalars[2] = count ? 0 : 2;
@@ -2058,16 +2131,30 @@ struct GenCtx {
     uint16_t *pre, *segl;
     uint32_t *mcnt;
     uint32_t W;
+    // compact columns: one word over the candidate list X[class(x_r), class(x_r+1)]
+    bool compact;
+    const uint8_t *text;
+    uint64_t n;
+    const uint16_t *cls, *xlist;
+    const uint32_t *xoff;
+    uint32_t C, NL;
 };
+
+// Segment count of column col.
+__device__ inline uint32_t gen_colsize(const GenCtx &g, uint64_t col) {
+    if (g.compact) return static_cast<uint32_t>(__popcll(g.out[col]));
+    const uint64_t *cw = g.out + col * g.W;
+    uint32_t m = 0;
+    for (uint32_t w = 0; w < g.W; ++w) m += __popcll(cw[w]);
+    return m;
+}
 
 // Leftmost column of [lo, hi] with the fewest segments, as
 // (segments << 40) | (column - lo).
 __device__ inline uint64_t gen_anchor(const GenCtx &g, uint64_t lo, uint64_t hi) {
     uint64_t best = ~0ull;
     for (uint64_t col = lo + threadIdx.x; col <= hi; col += 64) {
-        const uint64_t *cw = g.out + col * g.W;
-        uint32_t m = 0;
-        for (uint32_t w = 0; w < g.W; ++w) m += __popcll(cw[w]);
+        const uint32_t m = gen_colsize(g, col);
         const uint64_t key = (static_cast<uint64_t>(m) << 40) | (col - lo);
         best = key < best ? key : best;
     }
@@ -2101,11 +2188,24 @@ __device__ inline bool gen_walk(const GenCtx &g, uint64_t from, uint64_t to, Sta
         bool big = false;
         if (lane < rows) {
             const uint32_t row = lane + 1;
-            const uint64_t *cw = g.out + (top - lane) * W;
+            const uint64_t col = top - lane;
+            uint64_t *rw = g.colw + row * W;
+            if (g.compact) {   // the column's words from its candidate list
+                for (uint32_t w = 0; w < W; ++w) rw[w] = 0;
+                const uint32_t p = col > 0 ? g.cls[g.text[col - 1]] : g.C;
+                const uint32_t q = col < g.n ? g.cls[g.text[col]] : g.C;
+                const uint16_t *xl = g.xlist + g.xoff[p * g.NL + q];
+                for (uint64_t m = g.out[col]; m; m &= m - 1) {
+                    const uint32_t sg = xl[__builtin_ctzll(m)];
+                    rw[sg >> 6] |= 1ull << (sg & 63);
+                }
+            } else {
+                const uint64_t *cw = g.out + col * W;
+                for (uint32_t w = 0; w < W; ++w) rw[w] = cw[w];
+            }
             uint32_t cnt = 0;
             for (uint32_t w = 0; w < W; ++w) {
-                uint64_t v = cw[w];
-                g.colw[row * W + w] = v;
+                uint64_t v = rw[w];
                 g.pre[row * W + w] = static_cast<uint16_t>(cnt);
                 while (v) {
                     const uint32_t b = static_cast<uint32_t>(__builtin_ctzll(v));
@@ -2201,6 +2301,12 @@ __global__ __launch_bounds__(64) void k_count_general(Tabs tb, Job jb) {
     g.segl = reinterpret_cast<uint16_t *>(smem + o.segl);
     g.mcnt = reinterpret_cast<uint32_t *>(smem + o.mcnt);
     g.W = W;
+    g.compact = jb.compact != 0;
+    g.cls = tb.classmap;
+    g.xlist = tb.xlist;
+    g.xoff = tb.xoff;
+    g.C = tb.C;
+    g.NL = tb.NL;
     if constexpr (FOL_LDS) {
         uint64_t *f = reinterpret_cast<uint64_t *>(smem + o.fol);
         for (uint32_t k = lane; k < tb.nseg * W; k += 64) f[k] = tb.folseg[k];
@@ -2214,6 +2320,8 @@ __global__ __launch_bounds__(64) void k_count_general(Tabs tb, Job jb) {
         const ChunkCtx cx = chunk_ctx(jb, j);
         const uint32_t c0 = j - cx.li;
         g.out = cx.tr.out;
+        g.text = cx.tr.text;
+        g.n = cx.tr.n;
         const bool starts = cx.first || jb.kind[j - 1] == kRank1;
         const uint64_t key = gen_anchor(g, cx.lo, cx.hi);
         const bool anchored = (key >> 40) <= static_cast<uint64_t>(kGenR);
@@ -2268,6 +2376,27 @@ __global__ __launch_bounds__(64) void k_count_general(Tabs tb, Job jb) {
             if (starts) jb.chains[atomicAdd(&jb.flags[1], 1u)] = j;
         }
         __syncthreads();
+    }
+}
+
+// Compact SLPF to W-word columns: one thread per column r, whose bit k names
+// the k-th segment of X[class(x_r), class(x_r+1)] (the sentinel C before the
+// text and after it).
+__global__ __launch_bounds__(256) void k_decode_compact(Tabs tb, const uint8_t *text, uint64_t n,
+                                                        const uint64_t *cmp, uint64_t *out) {
+    const uint64_t r = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r > n) return;
+    const uint32_t p = r > 0 ? tb.classmap[text[r - 1]] : tb.C;
+    const uint32_t q = r < n ? tb.classmap[text[r]] : tb.C;
+    const uint16_t *xl = tb.xlist + tb.xoff[p * tb.NL + q];
+    const uint64_t m = cmp[r];
+    for (uint32_t w = 0; w < tb.W; ++w) {
+        uint64_t v = 0;
+        for (uint64_t x = m; x; x &= x - 1) {
+            const uint32_t sg = xl[__builtin_ctzll(x)];
+            if ((sg >> 6) == w) v |= 1ull << (sg & 63);
+        }
+        out[r * tb.W + w] = v;
     }
 }
 

@@ -192,7 +192,7 @@ slpf_status slpf_server_submit(slpf_server *s, const slpf_parser *p, const uint8
     r.text = text_dev;
     r.n = n;
     r.tag = tag;
-    r.forest = slpf_forest_bytes(p, n);
+    r.forest = (s->o.parse_flags & SLPF_PARSE_COMPACT) ? slpf_compact_bytes(n) : slpf_forest_bytes(p, n);
     if (r.forest == 0) return SLPF_E_ARG;
     r.bytes = round_up(r.forest) + kAlign;        // columns, then the three scalars
     if (r.bytes > s->arena_bytes) return SLPF_E_CAPACITY;

@@ -79,6 +79,13 @@ slpf_status upload(slpf_parser *p) {
         for (size_t k = 0; k < rdo.size(); ++k) rdo[k] = static_cast<uint16_t>(A.rev.delta[k] * c2);
         for (size_t k = 0; k < 256; ++k) cls2[k] = static_cast<uint16_t>(A.classmap[k] * 2);
     }
+    // rank of segment s in the candidate list X[p, end-letter class of s],
+    // per previous class p (the compact SLPF's bit index)
+    const uint32_t NL = A.C + 1;
+    std::vector<uint8_t> rankx(size_t(NL) * std::max<uint32_t>(A.nseg, 1), 0xff);
+    for (uint32_t pq = 0; pq < NL * NL; ++pq)
+        for (uint32_t k = A.xoff[pq]; k < A.xoff[pq + 1]; ++k)
+            rankx[size_t(pq / NL) * A.nseg + A.xlist[k]] = static_cast<uint8_t>(k - A.xoff[pq]);
     struct Part {
         const void *src;
         size_t bytes;
@@ -102,6 +109,7 @@ slpf_status upload(slpf_parser *p) {
         {fdo.data(), fdo.size() * 2, 0},
         {rdo.data(), rdo.size() * 2, 0},
         {cls2.data(), cls2.size() * 2, 0},
+        {rankx.data(), rankx.size(), 0},
     };
     size_t total = 0;
     for (auto &pt : parts) {
@@ -138,6 +146,7 @@ slpf_status upload(slpf_parser *p) {
     t.fdo = off16 ? reinterpret_cast<const uint16_t *>(at(14)) : nullptr;
     t.rdo = off16 ? reinterpret_cast<const uint16_t *>(at(15)) : nullptr;
     t.cls2 = off16 ? reinterpret_cast<const uint16_t *>(at(16)) : nullptr;
+    t.rankx = at(17);
     t.fhmask = static_cast<uint32_t>(A.fwd.hash.size() - 1);
     t.rhmask = static_cast<uint32_t>(A.rev.hash.size() - 1);
     t.C = A.C;
@@ -316,6 +325,21 @@ uint64_t slpf_forest_bytes(const slpf_parser *p, uint64_t n) {
     return (n + 1) * static_cast<uint64_t>(p->A.W) * 8;
 }
 
+uint64_t slpf_compact_bytes(uint64_t n) { return (n + 1) * 8; }
+
+slpf_status slpf_decode_compact(const slpf_parser *cp, const uint8_t *text_dev, uint64_t n,
+                                const uint64_t *compact_dev, uint64_t *columns_dev, void *hip_stream) {
+    const slpf_parser *p = cp;
+    if (!p || p->host_only || !compact_dev || !columns_dev || (n && !text_dev)) return SLPF_E_ARG;
+    if (hipSetDevice(p->device) != hipSuccess) return SLPF_E_DEVICE;
+    const uint64_t cols = n + 1;
+    const uint64_t blocks = (cols + 255) / 256;
+    if (blocks > 0x7fffffffull) return SLPF_E_ARG;
+    hipLaunchKernelGGL(k_decode_compact, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0,
+                       static_cast<hipStream_t>(hip_stream), p->tabs, text_dev, n, compact_dev, columns_dev);
+    return hipGetLastError() == hipSuccess ? SLPF_OK : SLPF_E_DEVICE;
+}
+
 uint64_t slpf_num_chunks(const slpf_parser *p, uint64_t n, const slpf_parse_opts *opts) {  // one text
     if (!p || n == 0) return 0;
     uint64_t s = chunk_bytes_for(n, opts);
@@ -353,6 +377,7 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
     Job jb{};
     jb.ntexts = nt;
     jb.fwd_only = recog ? 1u : 0u;
+    jb.compact = (flags & SLPF_PARSE_COMPACT) ? 1u : 0u;
     jb.s = s;
     jb.c = c;
     if (T == 1) {
@@ -580,15 +605,26 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
         const bool fit_tab = lds && kStageBytes + tab_lds <= p->lds_limit;
         const bool fit_bits = fit_tab && kStageBytes + tab_lds + bits_lds <= p->lds_limit;
         const uint32_t bblocks = (c + kBuildThreads - 1) / kBuildThreads;
-        if (fit_bits)
-            hipLaunchKernelGGL((k_build<true, true>), dim3(bblocks), dim3(kBuildThreads),
-                               kStageBytes + tab_lds + bits_lds, stream, tb, jb);
-        else if (fit_tab)
-            hipLaunchKernelGGL((k_build<true, false>), dim3(bblocks), dim3(kBuildThreads), kStageBytes + tab_lds,
-                               stream, tb, jb);
-        else
-            hipLaunchKernelGGL((k_build<false, false>), dim3(bblocks), dim3(kBuildThreads), kStageBytes, stream, tb,
-                               jb);
+        // compact: the rank table goes after the tables when LDS has room
+        const size_t tabs_end = kStageBytes + (fit_tab ? tab_lds : 0) + (fit_bits ? bits_lds : 0);
+        const size_t rank_bytes = (size_t(tb.NL) * tb.nseg + 15) & ~size_t(15);
+        jb.rank_lds = jb.compact && lds && tabs_end + rank_bytes <= p->lds_limit ? static_cast<uint32_t>(tabs_end)
+                                                                                : 0u;
+        const size_t bld_lds = tabs_end + (jb.rank_lds ? rank_bytes : 0);
+        auto launch = [&](auto compact) {
+            constexpr bool CM = decltype(compact)::value;
+            if (fit_bits)
+                hipLaunchKernelGGL((k_build<true, true, CM>), dim3(bblocks), dim3(kBuildThreads), bld_lds, stream,
+                                   tb, jb);
+            else if (fit_tab)
+                hipLaunchKernelGGL((k_build<true, false, CM>), dim3(bblocks), dim3(kBuildThreads), bld_lds, stream,
+                                   tb, jb);
+            else
+                hipLaunchKernelGGL((k_build<false, false, CM>), dim3(bblocks), dim3(kBuildThreads), bld_lds, stream,
+                                   tb, jb);
+        };
+        if (jb.compact) launch(std::true_type{});
+        else launch(std::false_type{});
     }
     mark(4);
     // tree count
@@ -643,13 +679,14 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
 }
 
 slpf_status check_item(const slpf_parser *p, const uint8_t *text, uint64_t n, const slpf_forest *forest,
-                       bool recog) {
+                       uint32_t flags) {
     if (!forest || !forest->scalars_dev) return SLPF_E_ARG;
     if (n && !text) return SLPF_E_ARG;
     if (reinterpret_cast<uintptr_t>(text) % 16 != 0) return SLPF_E_ARG;
-    if (recog) return SLPF_OK;   // no column is written
+    if (flags & SLPF_PARSE_RECOGNIZE) return SLPF_OK;   // no column is written
     if (!forest->columns_dev) return SLPF_E_ARG;
-    if (forest->capacity_bytes < slpf_forest_bytes(p, n)) return SLPF_E_CAPACITY;
+    const uint64_t need = (flags & SLPF_PARSE_COMPACT) ? slpf_compact_bytes(n) : slpf_forest_bytes(p, n);
+    if (forest->capacity_bytes < need) return SLPF_E_CAPACITY;
     return SLPF_OK;
 }
 
@@ -663,8 +700,7 @@ slpf_status slpf_parse(const slpf_parser *cp, const uint8_t *text, uint64_t n, c
     if (!p || p->host_only) return SLPF_E_ARG;
     if (opts && opts->struct_size != sizeof(slpf_parse_opts)) return SLPF_E_ARG;
     if (opts && opts->chunk_bytes && (opts->chunk_bytes % 64 != 0)) return SLPF_E_ARG;
-    const bool recog = opts && (opts->flags & SLPF_PARSE_RECOGNIZE);
-    slpf_status st = check_item(p, text, n, forest, recog);
+    slpf_status st = check_item(p, text, n, forest, opts ? opts->flags : 0u);
     if (st != SLPF_OK) return st;
     slpf_text item{text, n, *forest};
     return run_job(p, &item, 1, opts, static_cast<hipStream_t>(hip_stream));
@@ -679,8 +715,7 @@ slpf_status slpf_parse_batch(const slpf_parser *cp, const slpf_text *items, size
     if (count == 0) return SLPF_OK;
     if (count > 0x7fffffffull) return SLPF_E_ARG;
     for (size_t t = 0; t < count; ++t) {
-        slpf_status st = check_item(p, items[t].text_dev, items[t].n, &items[t].out,
-                                    opts && (opts->flags & SLPF_PARSE_RECOGNIZE));
+        slpf_status st = check_item(p, items[t].text_dev, items[t].n, &items[t].out, opts ? opts->flags : 0u);
         if (st != SLPF_OK) return st;
     }
     return run_job(p, items, count, opts, static_cast<hipStream_t>(hip_stream));

@@ -5,7 +5,8 @@ without the 5 % corruption blocks) is parsed by the HIP path with the
 benchmark's automatic chunking.  The oracle's DFA-lookup serial parser runs
 over the whole text and returns sampled column windows (text start and end,
 lane-chunk edges, random interior positions), the accept flag and the tree
-count, which must equal the GPU's bit for bit.
+count, which must equal the GPU's bit for bit; the same windows of the
+compact SLPF (SLPF_PARSE_COMPACT) must equal the oracle's index words.
 """
 import numpy as np
 import pytest
@@ -52,4 +53,23 @@ def test_full_size_sampled_windows(workload, which):
         g = cols[st:st + WIN].cpu().numpy().view(np.uint64)
         assert np.array_equal(g, win[k]), "window at column %d" % st
     del cols
+    torch.cuda.empty_cache()
+    # the compact SLPF of the same parse: each sampled column as the index
+    # word over its candidate list (the oracle's candidates)
+    cmp, sc2 = p.parse_compact(t)
+    torch.cuda.synchronize()
+    assert np.array_equal(sc2.cpu().numpy().view(np.uint64), sc)
+    cand = {}
+    for k, st in enumerate(starts):
+        g = cmp[st:st + WIN].cpu().numpy().view(np.uint64)
+        for u in range(WIN):
+            r = st + u
+            key = (int(text[r - 1]) if r > 0 else None, int(text[r]) if r < n else None)
+            if key not in cand:
+                cand[key] = {s_: j for j, s_ in enumerate(o.candidates(*key))}
+            want = 0
+            for s_ in o.to_set(win[k][u]):
+                want |= 1 << cand[key][s_]
+            assert int(g[u]) == want, "compact column %d" % r
+    del cmp
     torch.cuda.empty_cache()

@@ -109,3 +109,30 @@ def test_server_capacity_and_arguments():
     with pytest.raises(S.SlpfError):
         srv.release(7)                              # already released
     srv.close()
+
+
+def test_server_compact_alone_vs_mix():
+    # the server with SLPF_PARSE_COMPACT: admission by compact bytes, every
+    # result equal to the compact parse of its text alone
+    import torch
+    device()
+    res, texts = _workload(4, 40, 41, median=4096)
+    parsers = [S.Parser(regen.to_re(t)) for _, t in res]
+    dts = [to_device(x.tobytes()) for _, x in texts]
+    torch.cuda.synchronize()
+    srv = S.Server(slots=2, max_batch_texts=8, memory_budget=1 << 20, compact=True)
+    for k, (r, x) in enumerate(texts):
+        srv.submit(parsers[r], dts[k], x.size, k)
+    done = {}
+    while len(done) < len(texts):
+        for tag in srv.poll():
+            r, x = texts[tag]
+            done[tag] = srv.result_tensors(tag, x.size, parsers[r].W)
+            srv.release(tag)
+    srv.close()
+    for k, (r, x) in enumerate(texts):
+        cmp, sc = parsers[r].parse_compact(dts[k])
+        torch.cuda.synchronize()
+        cols, s2 = done[k]
+        assert np.array_equal(cols, cmp.cpu().numpy().view(np.uint64)), k
+        assert np.array_equal(s2, sc.cpu().numpy().view(np.uint64)), k
