@@ -69,6 +69,7 @@ struct Tabs {
     // offsets of the classes, so a step is one add and one lookup
     const uint16_t *fdo, *rdo, *cls2;
     const uint8_t *rankx;       // NL x nseg: rank of a segment in X[p, its end-letter class]
+    const uint32_t *fnz, *rnz;  // per state: bit w set iff word w of its set is non-zero
     uint32_t off16;
     uint32_t fhmask, rhmask;
     uint32_t C, W, NL;          // classes, words, C + 1
@@ -748,6 +749,7 @@ template <bool TAB_LDS, bool BITS_LDS>
 struct BuildTabs {
     const uint16_t *cls, *fd, *rd;
     const uint64_t *fb, *rb;
+    const uint32_t *fnz, *rnz;
 };
 
 template <bool TAB_LDS, bool BITS_LDS>
@@ -776,11 +778,18 @@ __device__ inline BuildTabs<TAB_LDS, BITS_LDS> stage_build(const Tabs &tb, uint8
         uint64_t *rb = fb + tb.nf * tb.W;
         for (uint32_t k = threadIdx.x; k < tb.nf * tb.W; k += nth) fb[k] = tb.fbits[k];
         for (uint32_t k = threadIdx.x; k < tb.nr * tb.W; k += nth) rb[k] = tb.rbits[k];
+        uint32_t *fz = reinterpret_cast<uint32_t *>(rb + tb.nr * tb.W), *rz = fz + tb.nf;
+        for (uint32_t k = threadIdx.x; k < tb.nf; k += nth) fz[k] = tb.fnz[k];
+        for (uint32_t k = threadIdx.x; k < tb.nr; k += nth) rz[k] = tb.rnz[k];
         t.fb = fb;
         t.rb = rb;
+        t.fnz = fz;
+        t.rnz = rz;
     } else {
         t.fb = tb.fbits;
         t.rb = tb.rbits;
+        t.fnz = tb.fnz;
+        t.rnz = tb.rnz;
     }
     __syncthreads();
     return t;
@@ -989,14 +998,14 @@ __global__ __launch_bounds__(kBuildThreads) void k_build(Tabs tb, Job jb) {
                         const uint32_t v = sj[e], pc = sj[SC + e];
                         const uint32_t fi = v & 0xffffu, bi = v >> 16;
                         uint64_t m = 0;
-                        if (fi != 0 && bi != 0) {   // id 0 is the empty set (dead run)
-                            for (uint32_t ww = 0; ww < W; ++ww) {
-                                uint64_t x = T.fb[fi * W + ww] & T.rb[bi * W + ww];
-                                while (x) {
-                                    const uint32_t sg = ww * 64 + static_cast<uint32_t>(__builtin_ctzll(x));
-                                    x &= x - 1;
-                                    m |= 1ull << rank_of(pc * tb.nseg + sg);
-                                }
+                        // only the words where both sets are non-zero (id 0 is
+                        // the empty set: a dead run)
+                        const uint32_t nz0 = fi != 0 && bi != 0 ? T.fnz[fi] & T.rnz[bi] : 0u;
+                        for (uint32_t nz = nz0; nz; nz &= nz - 1) {
+                            const uint32_t ww = static_cast<uint32_t>(__builtin_ctz(nz));
+                            for (uint64_t y = T.fb[fi * W + ww] & T.rb[bi * W + ww]; y; y &= y - 1) {
+                                const uint32_t sg = ww * 64 + static_cast<uint32_t>(__builtin_ctzll(y));
+                                m |= 1ull << rank_of(pc * tb.nseg + sg);
                             }
                         }
                         __builtin_nontemporal_store(m, global_ptr<uint64_t>(rj) + e);

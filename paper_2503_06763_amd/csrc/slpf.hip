@@ -86,6 +86,15 @@ slpf_status upload(slpf_parser *p) {
     for (uint32_t pq = 0; pq < NL * NL; ++pq)
         for (uint32_t k = A.xoff[pq]; k < A.xoff[pq + 1]; ++k)
             rankx[size_t(pq / NL) * A.nseg + A.xlist[k]] = static_cast<uint8_t>(k - A.xoff[pq]);
+    // per state, the non-zero words of its set (W <= 32)
+    auto nonzero_words = [&](const HostTable &t) {
+        std::vector<uint32_t> nz(t.nstates, 0);
+        for (uint32_t q = 0; q < t.nstates; ++q)
+            for (uint32_t w = 0; w < A.W; ++w)
+                if (t.bits[size_t(q) * A.W + w]) nz[q] |= 1u << w;
+        return nz;
+    };
+    const std::vector<uint32_t> fnz = nonzero_words(A.fwd), rnz = nonzero_words(A.rev);
     struct Part {
         const void *src;
         size_t bytes;
@@ -110,6 +119,8 @@ slpf_status upload(slpf_parser *p) {
         {rdo.data(), rdo.size() * 2, 0},
         {cls2.data(), cls2.size() * 2, 0},
         {rankx.data(), rankx.size(), 0},
+        {fnz.data(), fnz.size() * 4, 0},
+        {rnz.data(), rnz.size() * 4, 0},
     };
     size_t total = 0;
     for (auto &pt : parts) {
@@ -147,6 +158,8 @@ slpf_status upload(slpf_parser *p) {
     t.rdo = off16 ? reinterpret_cast<const uint16_t *>(at(15)) : nullptr;
     t.cls2 = off16 ? reinterpret_cast<const uint16_t *>(at(16)) : nullptr;
     t.rankx = at(17);
+    t.fnz = reinterpret_cast<const uint32_t *>(at(18));
+    t.rnz = reinterpret_cast<const uint32_t *>(at(19));
     t.fhmask = static_cast<uint32_t>(A.fwd.hash.size() - 1);
     t.rhmask = static_cast<uint32_t>(A.rev.hash.size() - 1);
     t.C = A.C;
@@ -180,6 +193,7 @@ void set_placement(slpf_parser *p) {
 }
 
 constexpr uint32_t kGenFolLds = 40 * 1024;   // LDS of the general count kernel with its follower table
+constexpr size_t kLdsPerCu = 160 * 1024;     // LDS of one compute unit (gfx950)
 
 uint64_t chunk_bytes_for(uint64_t n, const slpf_parse_opts *o) {
     if (o && o->chunk_bytes) return o->chunk_bytes;
@@ -600,16 +614,18 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
 
     // build & merge: transition tables and bit sets in LDS when they fit
     const size_t tab_lds = (512 + (size_t(tb.nf) + tb.nr) * tb.C * 2 + 15) & ~size_t(15);
-    const size_t bits_lds = (size_t(tb.nf) + tb.nr) * W * 8;
+    const size_t bits_lds = ((size_t(tb.nf) + tb.nr) * (W * 8 + 4) + 15) & ~size_t(15);   // sets, non-zero words
     if (c && !recog) {
         const bool fit_tab = lds && kStageBytes + tab_lds <= p->lds_limit;
         const bool fit_bits = fit_tab && kStageBytes + tab_lds + bits_lds <= p->lds_limit;
         const uint32_t bblocks = (c + kBuildThreads - 1) / kBuildThreads;
-        // compact: the rank table goes after the tables when LDS has room
+        // compact: the rank table goes after the tables when LDS has room and
+        // it does not cost a resident block per CU
         const size_t tabs_end = kStageBytes + (fit_tab ? tab_lds : 0) + (fit_bits ? bits_lds : 0);
         const size_t rank_bytes = (size_t(tb.NL) * tb.nseg + 15) & ~size_t(15);
-        jb.rank_lds = jb.compact && lds && tabs_end + rank_bytes <= p->lds_limit ? static_cast<uint32_t>(tabs_end)
-                                                                                : 0u;
+        const bool rank_fits = tabs_end + rank_bytes <= p->lds_limit &&
+                               kLdsPerCu / (tabs_end + rank_bytes) == kLdsPerCu / tabs_end;
+        jb.rank_lds = jb.compact && lds && rank_fits ? static_cast<uint32_t>(tabs_end) : 0u;
         const size_t bld_lds = tabs_end + (jb.rank_lds ? rank_bytes : 0);
         auto launch = [&](auto compact) {
             constexpr bool CM = decltype(compact)::value;
