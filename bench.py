@@ -64,7 +64,7 @@ def make_text(n, corrupt):
     return regen.to_re(tree), text
 
 
-def run_gpu(parser, text_np, steps, warmup, chunk_bytes, compact=False):
+def run_gpu(parser, text_np, steps, warmup, chunk_bytes, compact=False, flags=0):
     """Timed parses; ``compact``: the compact SLPF (one word per column)."""
     import numpy as np
     import torch
@@ -75,7 +75,7 @@ def run_gpu(parser, text_np, steps, warmup, chunk_bytes, compact=False):
     W = parser.W
     cols = torch.empty((n + 1,) if compact else (n + 1, W), dtype=torch.int64, device=dev)
     sc = torch.empty(3, dtype=torch.int64, device=dev)
-    flags = S.PARSE_COMPACT if compact else 0
+    flags |= S.PARSE_COMPACT if compact else 0
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(S.NUM_PHASE_EVENTS)] for _ in range(steps)]
     for _ in range(warmup):
         parser.parse_into(text, n, cols, sc, chunk_bytes, flags)
@@ -507,6 +507,23 @@ def main():
                       "what": "SLPF_PARSE_COMPACT: each column as one word over its candidate list"}
     print("compact: %.3f ms/step phases %s decodes_to_plain %s" % (cms, cphase, same), file=sys.stderr, flush=True)
     torch.cuda.empty_cache()
+    # speculation ablation: runs started from every segment whose end-letter
+    # is the chunk's first byte, without the previous-byte filter
+    if parser.info.max_entries_next_byte <= 64:
+        nms, nphase, nscal, _n = run_gpu(parser, text, args.steps, args.warmup, args.chunk_bytes,
+                                         flags=S.PARSE_NEXT_BYTE_ENTRIES)
+        del _n
+        out["speculation_ablation"] = {
+            "reduced_entries": {"max_entries": parser.info.max_entries, "reach_ms": round(phase["reach"], 4),
+                                "ms_per_step": round(ms, 4)},
+            "next_byte_entries": {"max_entries": parser.info.max_entries_next_byte,
+                                  "reach_ms": round(nphase["reach"], 4), "ms_per_step": round(nms, 4),
+                                  "same_scalars": nscal == scal},
+            "what": "lane-chunk runs from the reduced entry list X(previous byte, next byte) vs from every "
+                    "segment whose end-letter is the next byte"}
+        print("next-byte entries: %.3f ms/step reach %.3f ms (reduced: reach %.3f ms)" % (
+            nms, nphase["reach"], phase["reach"]), file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
     rms, racc = run_recognize(parser, text, args.steps, args.warmup, args.chunk_bytes)
     out["recognizer"] = {"value": round(n / (rms * 1e-3) / 1e9, 3), "unit": "GB/s", "ms_per_step": round(rms, 4),
                          "accepted": racc, "what": "forward reach and forward join only (accept flag, no SLPF)"}

@@ -105,7 +105,8 @@ typedef struct {
     uint32_t num_classes;        /* byte classes, class 0 = bytes outside the RE */
     uint32_t max_entries;        /* longest speculative entry list (<= 64) */
     uint32_t placement;          /* 0 = transition tables staged in LDS, 1 = read through L2 */
-    uint32_t reserved;
+    uint32_t max_entries_next_byte;  /* longest entry list without the previous-byte filter
+                                        (SLPF_PARSE_NEXT_BYTE_ENTRIES needs <= 64) */
     uint64_t table_bytes;        /* device bytes of all tables */
 } slpf_parser_info;
 
@@ -167,9 +168,15 @@ enum {
     SLPF_PARSE_RECOGNIZE = 1u << 2,     /* recogniser only (Sect. 3.2: the forward reacher and joiner
                                            decide membership): scalars[0] = accept, [1] = 0, [2] = 2;
                                            no column is written (columns_dev may be NULL) */
-    SLPF_PARSE_COMPACT = 1u << 3        /* write the compact SLPF (App. SLPF optimization, SLPF
+    SLPF_PARSE_COMPACT = 1u << 3,       /* write the compact SLPF (App. SLPF optimization, SLPF
                                            encoding): column r as ONE word; see slpf_decode_compact.
                                            capacity_bytes >= slpf_compact_bytes(n) */
+    SLPF_PARSE_NEXT_BYTE_ENTRIES = 1u << 4  /* speculation ablation: each lane chunk's runs start
+                                           from every segment whose end-letter is the chunk's first
+                                           byte (the ME-DFA entries of Sect. 3.1 for that letter),
+                                           without the filter by the previous byte.  Same results;
+                                           SLPF_E_TOO_LARGE when such a list exceeds 64 segments
+                                           (slpf_parser_info.max_entries_next_byte) */
 };
 
 typedef struct {

@@ -27,6 +27,7 @@ PARSE_NO_COUNT = 1
 PARSE_FORCE_L2 = 2
 PARSE_RECOGNIZE = 4
 PARSE_COMPACT = 8
+PARSE_NEXT_BYTE_ENTRIES = 16
 
 EXPORTS = ["slpf_compile", "slpf_parser_destroy", "slpf_parser_info_get", "slpf_segment_text",
            "slpf_table_dump", "slpf_forest_bytes", "slpf_parse", "slpf_parse_batch", "slpf_tune", "slpf_parser_trim",
@@ -53,7 +54,7 @@ class ParserInfo(ctypes.Structure):
     _fields_ = [(k, ctypes.c_uint32) for k in (
         "num_segments", "words_per_column", "num_initial", "num_final", "fwd_states", "rev_states",
         "dfa_states", "medfa_states", "rdfa_states", "rmedfa_states", "num_classes", "max_entries",
-        "placement", "reserved")] + [("table_bytes", ctypes.c_uint64)]
+        "placement", "max_entries_next_byte")] + [("table_bytes", ctypes.c_uint64)]
 
 
 class ParseOpts(ctypes.Structure):
@@ -170,6 +171,7 @@ class Info:
     num_classes: int
     max_entries: int
     placement: int
+    max_entries_next_byte: int
     table_bytes: int
 
 
@@ -267,7 +269,7 @@ class Parser:
         _check(st, "slpf_parse")
 
     def parse(self, text, chunk_bytes: int = 0, count: bool = True, force_l2: bool = False,
-              trace: bool = False, stream=None, events=None):
+              trace: bool = False, stream=None, events=None, flags: int = 0):
         """Parse a uint8 device tensor; returns (columns [n+1, W] int64 view of uint64 words,
         scalars [3]) on the device, plus the join trace if asked."""
         import torch
@@ -279,7 +281,7 @@ class Parser:
         if trace:
             c = self.num_chunks(n, chunk_bytes)
             tr = torch.zeros((2, c + 1, self.W), dtype=torch.int64, device=dev)
-        flags = (0 if count else PARSE_NO_COUNT) | (PARSE_FORCE_L2 if force_l2 else 0)
+        flags |= (0 if count else PARSE_NO_COUNT) | (PARSE_FORCE_L2 if force_l2 else 0)
         self.parse_into(text, n, cols, sc, chunk_bytes, flags, tr, stream, events)
         return (cols, sc, tr) if trace else (cols, sc)
 

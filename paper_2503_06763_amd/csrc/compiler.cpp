@@ -613,6 +613,26 @@ int compile_re(const uint8_t *re, size_t len, const CompileLimits &lim, HostAuto
     }
     A.xoff[static_cast<size_t>(NL) * NL] = static_cast<uint32_t>(A.xlist.size());
     if (A.max_entries > static_cast<uint32_t>(kMaxEntries)) return SLPF_E_TOO_LARGE;
+    // the same lists without the previous-byte filter (initial segments at
+    // the text start): the speculation ablation; usable when they fit a mask
+    A.xoff_nb.assign(static_cast<size_t>(NL) * NL + 1, 0);
+    A.xlist_nb.clear();
+    A.max_entries_nb = 0;
+    for (uint32_t p = 0; p < NL; ++p) {
+        for (uint32_t q = 0; q < NL; ++q) {
+            A.xoff_nb[p * NL + q] = static_cast<uint32_t>(A.xlist_nb.size());
+            if (p == 0 || q == 0) continue;
+            uint32_t cnt = 0;
+            for (uint32_t s = 0; s < L; ++s) {
+                bool label_ok = (q == C) ? F.get(s) : (lclass[s] == static_cast<int>(q));
+                if (!label_ok || (p == C && !I.get(s))) continue;
+                A.xlist_nb.push_back(static_cast<uint16_t>(s));
+                ++cnt;
+            }
+            A.max_entries_nb = std::max(A.max_entries_nb, cnt);
+        }
+    }
+    A.xoff_nb[static_cast<size_t>(NL) * NL] = static_cast<uint32_t>(A.xlist_nb.size());
     return SLPF_OK;
 }
 

@@ -70,6 +70,9 @@ struct Tabs {
     const uint16_t *fdo, *rdo, *cls2;
     const uint8_t *rankx;       // NL x nseg: rank of a segment in X[p, its end-letter class]
     const uint32_t *fnz, *rnz;  // per state: bit w set iff word w of its set is non-zero
+    const uint32_t *xoff_nb;    // entry lists filtered by the next byte only (ablation)
+    const uint16_t *xlist_nb;
+    uint32_t emax_nb;
     uint32_t off16;
     uint32_t fhmask, rhmask;
     uint32_t C, W, NL;          // classes, words, C + 1

@@ -121,6 +121,8 @@ slpf_status upload(slpf_parser *p) {
         {rankx.data(), rankx.size(), 0},
         {fnz.data(), fnz.size() * 4, 0},
         {rnz.data(), rnz.size() * 4, 0},
+        {A.xoff_nb.data(), A.xoff_nb.size() * 4, 0},
+        {A.xlist_nb.data(), std::max<size_t>(A.xlist_nb.size(), 1) * 2, 0},
     };
     size_t total = 0;
     for (auto &pt : parts) {
@@ -160,6 +162,9 @@ slpf_status upload(slpf_parser *p) {
     t.rankx = at(17);
     t.fnz = reinterpret_cast<const uint32_t *>(at(18));
     t.rnz = reinterpret_cast<const uint32_t *>(at(19));
+    t.xoff_nb = reinterpret_cast<const uint32_t *>(at(20));
+    t.xlist_nb = reinterpret_cast<const uint16_t *>(at(21));
+    t.emax_nb = std::max<uint32_t>(A.max_entries_nb, 1);
     t.fhmask = static_cast<uint32_t>(A.fwd.hash.size() - 1);
     t.rhmask = static_cast<uint32_t>(A.rev.hash.size() - 1);
     t.C = A.C;
@@ -306,6 +311,7 @@ slpf_status slpf_parser_info_get(const slpf_parser *p, slpf_parser_info *info) {
     info->rmedfa_states = A.rev.medfa_states;
     info->num_classes = A.C;
     info->max_entries = A.max_entries;
+    info->max_entries_next_byte = A.max_entries_nb;
     info->placement = p->placement;
     info->table_bytes = p->blob_bytes;
     return SLPF_OK;
@@ -373,7 +379,15 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
     const bool count = !(flags & SLPF_PARSE_NO_COUNT) && !recog;
     if (hipSetDevice(p->device) != hipSuccess) return SLPF_E_DEVICE;
     Tabs tb = p->tabs;
-    const uint32_t W = tb.W, E = tb.emax;
+    // speculation entry lists: reduced (default) or filtered by the next byte only
+    Tabs ts = tb;
+    if (flags & SLPF_PARSE_NEXT_BYTE_ENTRIES) {
+        if (tb.emax_nb > static_cast<uint32_t>(kMaxEntries)) return SLPF_E_TOO_LARGE;
+        ts.xoff = tb.xoff_nb;
+        ts.xlist = tb.xlist_nb;
+        ts.emax = tb.emax_nb;
+    }
+    const uint32_t W = tb.W, E = ts.emax;
     uint64_t total = 0;
     for (size_t t = 0; t < T; ++t) total += items[t].n;
     const uint64_t s = chunk_bytes_for(total, opts);
@@ -545,11 +559,11 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
     if (c) {
         // reach
         if (lds && tb.off16)
-            hipLaunchKernelGGL((k_reach<true, true>), dim3(blocks), dim3(256), lds_bytes, stream, tb, jb);
+            hipLaunchKernelGGL((k_reach<true, true>), dim3(blocks), dim3(256), lds_bytes, stream, ts, jb);
         else if (lds)
-            hipLaunchKernelGGL((k_reach<true, false>), dim3(blocks), dim3(256), lds_bytes, stream, tb, jb);
+            hipLaunchKernelGGL((k_reach<true, false>), dim3(blocks), dim3(256), lds_bytes, stream, ts, jb);
         else
-            hipLaunchKernelGGL((k_reach<false, false>), dim3(blocks), dim3(256), 0, stream, tb, jb);
+            hipLaunchKernelGGL((k_reach<false, false>), dim3(blocks), dim3(256), 0, stream, ts, jb);
     }
     mark(1);
     if (c) {
@@ -609,7 +623,7 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
         }
     }
     mark(2);
-    if (c && !recog) hipLaunchKernelGGL(k_starts, dim3(blocks), dim3(256), 0, stream, tb, jb);
+    if (c && !recog) hipLaunchKernelGGL(k_starts, dim3(blocks), dim3(256), 0, stream, ts, jb);
     mark(3);
 
     // build & merge: transition tables and bit sets in LDS when they fit

@@ -46,6 +46,11 @@ struct HostAutomaton {
     std::vector<uint32_t> xoff;           // (C+1)^2 + 1 offsets of the entry lists
     std::vector<uint16_t> xlist;          // segment ids
     uint32_t max_entries = 0;
+    // entry lists filtered by the next byte only (every ME-DFA entry whose
+    // end-letter is the next byte): the speculation ablation
+    std::vector<uint32_t> xoff_nb;
+    std::vector<uint16_t> xlist_nb;
+    uint32_t max_entries_nb = 0;
     uint32_t ninit = 0, nfinal = 0;
     HostTable fwd, rev;
 };

@@ -20,11 +20,11 @@ def to_device(text: bytes):
     return t[:a.size]
 
 
-def gpu_parse(parser, text, chunk_bytes=0, count=True, force_l2=False, trace=False):
+def gpu_parse(parser, text, chunk_bytes=0, count=True, force_l2=False, trace=False, flags=0):
     """(columns uint64 [n+1, W], accepted, count, count_status[, trace uint64 [2, c+1, W]])."""
     import torch
     t = to_device(text) if not hasattr(text, "device") else text
-    res = parser.parse(t, chunk_bytes=chunk_bytes, count=count, force_l2=force_l2, trace=trace)
+    res = parser.parse(t, chunk_bytes=chunk_bytes, count=count, force_l2=force_l2, trace=trace, flags=flags)
     torch.cuda.synchronize()
     cols = res[0].cpu().numpy().view(np.uint64)
     sc = res[1].cpu().numpy().view(np.uint64)

@@ -209,3 +209,36 @@ def test_recognizer_mode():
                            flags=S.PARSE_RECOGNIZE)
         torch.cuda.synchronize()
         assert [bool(v) for v in sc[:, 0].cpu().tolist()] == want
+
+
+def test_next_byte_entries_give_the_same_slpf():
+    # speculation from every segment whose end-letter is the chunk's first
+    # byte (no previous-byte filter): more runs, the same join results, so
+    # the same SLPF, accept flag and count as the reduced entry lists and the
+    # oracle; recogniser mode too
+    import torch
+    from gpu_util import device, gpu_parse
+    device()
+    cases = []
+    for seed in (1, 4, 9):
+        rt = regen.random_re(500 + seed, n_ops=14, max_depth=5, alphabet=b"abcd")
+        x = textgen.sample_text(rt, seed, 12000)
+        cases.append((regen.to_re(rt).decode(), [x.tobytes(), textgen.corrupt(x, seed, 0.01, (1, 8)).tobytes(),
+                                                 x.tobytes()[:100], b""]))
+    tree = regen.plain_small_re()
+    cases.append((regen.to_re(tree).decode(), [textgen.sample_text(tree, 5, 30000).tobytes()]))
+    for pat, texts in cases:
+        o, p = Oracle(pat), S.Parser(pat)
+        assert p.info.max_entries_next_byte >= p.info.max_entries
+        if p.info.max_entries_next_byte > 64:
+            continue
+        for t in texts:
+            cols, acc, cnt = o.parse(t)
+            for k in (64, 0):
+                g = gpu_parse(p, t, chunk_bytes=k, flags=S.PARSE_NEXT_BYTE_ENTRIES)
+                assert np.array_equal(g[0], cols), (pat[:40], len(t), k)
+                assert g[1] == acc and g[3] == 0 and g[2] == cnt
+                sc = torch.zeros(3, dtype=torch.int64, device="cuda:0")
+                p.parse_into(to_device(t), len(t), None, sc, k, S.PARSE_RECOGNIZE | S.PARSE_NEXT_BYTE_ENTRIES)
+                torch.cuda.synchronize()
+                assert bool(sc.cpu().numpy()[0]) == acc
