@@ -266,6 +266,43 @@ class Oracle:
             out[r] = np.uint64(word)
         return out
 
+    # -- match extraction (Sect. 4, Other functions of the tool: getMatches)
+    def group_events(self, g):
+        """Per segment, its symbols "g(" / ")g" in order (from the segment text)."""
+        o, c = "%d(" % g, ")%d" % g
+        return [[t for t in txt.split(" ") if t in (o, c)] for txt in self.segments]
+
+    def matches(self, text, g, cols=None):
+        """Sorted (start, end) pairs: some tree has "g(" at position start and
+        its matching ")g" at position end.  From each segment of C_r whose
+        last g-symbol is an open, follow arcs (followers present in the next
+        column) through segments without g-symbols; a segment whose first
+        g-symbol is a close ends a match.  "g( .. )g" inside one segment is
+        the empty match (r, r)."""
+        x = _bytes(text)
+        n = len(x)
+        if cols is None:
+            cols = self.parse(x)[0]
+        ev = self.group_events(g)
+        opens = {s for s, e in enumerate(ev) if e and e[-1].endswith("(")}
+        closes = {s for s, e in enumerate(ev) if e and e[0].startswith(")")}
+        empty = {s for s, e in enumerate(ev) if any(e[k].endswith("(") and e[k + 1].startswith(")")
+                                                     for k in range(len(e) - 1))}
+        C = [self.to_set(c) for c in cols]
+        out = []
+        for r in range(n + 1):
+            if C[r] & empty:
+                out.append((r, r))
+            f = C[r] & opens
+            c = r
+            while f and c < n:
+                c += 1
+                nf = frozenset().union(*[self.folseg[s] for s in f]) & C[c]
+                if nf & closes:
+                    out.append((r, c))
+                f = nf - closes
+        return sorted(out)
+
     # -- the parallel algorithm's quantities (Sect. 3.2), plain Python
     def run_fwd(self, s, y):
         for a in y:

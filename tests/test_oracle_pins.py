@@ -154,6 +154,54 @@ def test_compact_is_lossless_and_columns_lie_in_candidates(seed):
         assert all(w != 0 for w in words.tolist()) == acc
 
 
+def _brute_matches(re_, text, g):
+    """Group spans over every LST (brute force): "g(" at position p and its
+    matching ")g" at position q, positions counted in terminals."""
+    o, c = "%d(" % g, ")%d" % g
+    out = set()
+    for t in lst_brute.lsts(re_, text):
+        p, stack = 0, []
+        for tok in t:
+            if tok == o:
+                stack.append(p)
+            elif tok == c:
+                out.add((stack.pop(), p))
+            elif lst_brute.is_end_letter(tok):
+                p += 1
+    return sorted(out)
+
+
+MATCH_CASES = [
+    ("(ab|a)*", [b"", b"a", b"ab", b"abaaba", b"aab"]),
+    ("(a|b|ab)+", [b"abab", b"a", b"bab"]),
+    ("(a|ab|aba)+", [b"aba", b"abaab"]),
+    ("(a|())b", [b"b", b"ab"]),
+    ("((a|b)*c)+", [b"abcbc", b"c", b"cc"]),
+    ("(a?b)*(ab?)*", [b"abab", b"aab", b"ba"]),
+    ("x(y|yz)*(z|zy)*", [b"xyzzy", b"xyzyz"]),
+]
+
+
+@pytest.mark.parametrize("re_,texts", MATCH_CASES)
+def test_match_extraction_equals_brute_force(re_, texts):
+    # every group's match set equals the spans over all enumerated trees
+    o = Oracle(re_)
+    groups = sorted({int(t[:-1]) for seg in o.segments for t in seg.split(" ") if t.endswith("(")})
+    for text in texts:
+        for g in groups:
+            assert o.matches(text, g) == _brute_matches(re_.encode(), text, g), (re_, text, g)
+
+
+def test_match_extraction_rejected_and_e2_example():
+    o = Oracle("(ab|a)*")
+    assert o.matches(b"abb", 1) == [] and o.matches(b"b", 2) == []
+    # Ex. 6, "abaaba" = (ab)(a)(ab)(a): the union group 2 spans each factor,
+    # the concatenation 3 the two "ab", the star 1 the whole text
+    assert o.matches(b"abaaba", 2) == [(0, 2), (2, 3), (3, 5), (5, 6)]
+    assert o.matches(b"abaaba", 3) == [(0, 2), (3, 5)]
+    assert o.matches(b"abaaba", 1) == [(0, 6)]
+
+
 # ------------------------------------------------------------ e3, e1, e4
 
 def test_e3_nfa_and_slpf():
