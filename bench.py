@@ -109,6 +109,30 @@ def run_recognize(parser, text_np, steps, warmup, chunk_bytes):
     return ms, int(sc.cpu().numpy().view(np.uint64)[0])
 
 
+def time_matches(parser, text_np, cols):
+    """Match extraction on the parsed text: the group with the most matches on
+    a 64 KiB prefix (a record field), then its matches over the whole text."""
+    import torch
+    import numpy as np
+    n = text_np.size
+    pre = torch.from_numpy(text_np[:1 << 16].copy()).to("cuda:0")
+    pcols, _ = parser.parse(pre)
+    groups = sorted({int(t[:-1]) for i in range(parser.nseg) for t in parser.segment_text(i).split(" ")
+                     if t.endswith("(")})
+    best = max(groups, key=lambda g: (len(parser.matches(pcols, g)), -g))
+    del pcols
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    m = parser.matches(cols, best, capacity=n // 2)
+    ms = (time.perf_counter() - t0) * 1e3
+    lens = (m[:, 1] - m[:, 0]).astype(np.int64) if len(m) else np.zeros(0, np.int64)
+    print("matches: group %d, %d matches in %.1f ms" % (best, len(m), ms), file=sys.stderr, flush=True)
+    return {"group": best, "matches": int(len(m)), "ms": round(ms, 2),
+            "mean_match_bytes": round(float(lens.mean()), 2) if len(m) else 0.0,
+            "text_gbs": round(n / (ms * 1e-3) / 1e9, 3),
+            "what": "slpf_get_matches over the whole parsed text (group spans; call time incl. its work buffers)"}
+
+
 def cpu_baseline(pat, text_np, sample_bytes):
     from oracle.oracle import Oracle
     o = Oracle(pat)
@@ -496,7 +520,10 @@ def main():
     cms, cphase, cscal, ccols = run_gpu(parser, text, args.steps, args.warmup, args.chunk_bytes, compact=True)
     dec = parser.decode_compact(torch.from_numpy(text).to("cuda:0"), ccols)
     same = bool(torch.equal(dec, _)) and cscal == scal
-    del dec, ccols, _
+    del dec, ccols
+    if args.workload == "record":
+        out["matches"] = time_matches(parser, text, _)
+    del _
     calgo = n + (n + 1) * 8
     out["compact"] = {"value": round(n / (cms * 1e-3) / 1e9, 3), "unit": "GB/s", "ms_per_step": round(cms, 4),
                       "phases_ms": {k: round(v, 4) for k, v in cphase.items()},

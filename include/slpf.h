@@ -160,6 +160,27 @@ uint64_t slpf_compact_bytes(uint64_t n);
 slpf_status slpf_decode_compact(const slpf_parser *p, const uint8_t *text_dev, uint64_t n,
                                 const uint64_t *compact_dev, uint64_t *columns_dev, void *hip_stream);
 
+/*
+ * Match extraction (Sect. 4, Other functions of the tool: getMatches).  The
+ * matches of group `group` -- the operator node with that number in the
+ * preorder numbering of the RE, as printed by slpf_segment_text ("g(" and
+ * ")g") -- in the clean SLPF columns_dev of an n-byte text (the W-word
+ * layout of slpf_parse, device memory): every pair (start, end) of text
+ * positions, 0 <= start <= end <= n, such that some syntax tree of the text
+ * has "g(" at position start and its matching ")g" at position end, i.e. the
+ * group's substring is text[start, end).  A rejected text has none.
+ *
+ * pairs_dev: device, room for `capacity` pairs of uint64_t (start, end),
+ *   written sorted by (start, end).
+ * *num_matches (host): the number of matches.  SLPF_E_CAPACITY when it
+ *   exceeds capacity (the first `capacity` pairs are written).
+ * SLPF_E_ARG: NULL pointer, group 0 or past the last node number, n >= 2^31 - 1.
+ * Work buffers are allocated for the call; the call synchronizes hip_stream.
+ * The cost is proportional to the summed lengths of the matches.
+ */
+slpf_status slpf_get_matches(const slpf_parser *p, const uint64_t *columns_dev, uint64_t n, uint32_t group,
+                             uint64_t *pairs_dev, uint64_t capacity, uint64_t *num_matches, void *hip_stream);
+
 /* -------------------------------------------------------------------- parse */
 
 enum {

@@ -33,7 +33,7 @@ EXPORTS = ["slpf_compile", "slpf_parser_destroy", "slpf_parser_info_get", "slpf_
            "slpf_table_dump", "slpf_forest_bytes", "slpf_parse", "slpf_parse_batch", "slpf_tune", "slpf_parser_trim",
            "slpf_num_chunks", "slpf_status_str", "slpf_server_create", "slpf_server_destroy",
            "slpf_server_submit", "slpf_server_poll", "slpf_server_result", "slpf_server_release",
-           "slpf_server_stats", "slpf_compact_bytes", "slpf_decode_compact"]
+           "slpf_server_stats", "slpf_compact_bytes", "slpf_decode_compact", "slpf_get_matches"]
 
 
 class SlpfError(RuntimeError):
@@ -143,6 +143,9 @@ def lib(path: str = LIB_PATH):
     L.slpf_compact_bytes.restype = ctypes.c_uint64
     L.slpf_decode_compact.argtypes = [vp, vp, ctypes.c_uint64, vp, vp, vp]
     L.slpf_decode_compact.restype = ctypes.c_int
+    L.slpf_get_matches.argtypes = [vp, vp, ctypes.c_uint64, ctypes.c_uint32, vp, ctypes.c_uint64,
+                                   ctypes.POINTER(ctypes.c_uint64), vp]
+    L.slpf_get_matches.restype = ctypes.c_int
     L.slpf_num_chunks.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ParseOpts)]
     L.slpf_num_chunks.restype = ctypes.c_uint64
     L.slpf_status_str.argtypes = [ctypes.c_int]
@@ -296,6 +299,26 @@ class Parser:
         flags = PARSE_COMPACT | (0 if count else PARSE_NO_COUNT) | (PARSE_FORCE_L2 if force_l2 else 0)
         self.parse_into(text, n, cols, sc, chunk_bytes, flags, None, stream, events)
         return cols, sc
+
+    def matches(self, columns, group: int, capacity: int = 1 << 16, stream=None):
+        """Matches of group ``group`` (its number in slpf_segment_text) in the
+        plain SLPF ``columns`` [n+1, W] of a parsed text: a host uint64 array
+        [k, 2] of (start, end) pairs sorted by (start, end)."""
+        import numpy as np
+        import torch
+        n = columns.shape[0] - 1
+        if stream is None:
+            stream = torch.cuda.current_stream(columns.device)
+        while True:
+            out = torch.empty((max(capacity, 1), 2), dtype=torch.int64, device=columns.device)
+            cnt = ctypes.c_uint64(0)
+            st = self._L.slpf_get_matches(self._h, columns.data_ptr(), n, group, out.data_ptr(), capacity,
+                                          ctypes.byref(cnt), ctypes.c_void_p(stream.cuda_stream))
+            if st == E_CAPACITY:
+                capacity = int(cnt.value)
+                continue
+            _check(st, "slpf_get_matches")
+            return out[:cnt.value].cpu().numpy().view(np.uint64)
 
     def decode_compact(self, text, compact, stream=None):
         """W-word columns [n+1, W] (int64 view) of a compact SLPF of ``text`` (device tensors)."""

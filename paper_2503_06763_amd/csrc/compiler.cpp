@@ -458,6 +458,30 @@ int compile_re(const uint8_t *re, size_t len, const CompileLimits &lim, HostAuto
         const Bits &f = folT.at(e);
         std::copy(f.w.begin(), f.w.end(), A.folseg.begin() + static_cast<size_t>(q) * W);
     }
+    // group masks for match extraction
+    int maxnum = 0;
+    for (auto &v : nodes) maxnum = std::max(maxnum, v.num);
+    A.ngroups = static_cast<uint32_t>(maxnum + 1);
+    A.gmask.assign(static_cast<size_t>(A.ngroups) * 3 * W, 0);
+    for (uint32_t q = 0; q < L; ++q) {
+        std::vector<int> first(A.ngroups, -1), last(A.ngroups, -1);   // first / last g-symbol kind
+        std::vector<char> open_then_close(A.ngroups, 0);
+        for (int sy : segs[q]) {
+            const Sym &y = syms[sy];
+            if (y.kind != SOpen && y.kind != SClose) continue;
+            const int g = nodes[y.node].num;
+            if (first[g] < 0) first[g] = y.kind;
+            if (y.kind == SClose && last[g] == SOpen) open_then_close[g] = 1;
+            last[g] = y.kind;
+        }
+        for (uint32_t g = 1; g < A.ngroups; ++g) {
+            uint64_t *m = A.gmask.data() + static_cast<size_t>(g) * 3 * W;
+            const uint64_t bit = uint64_t(1) << (q & 63);
+            if (last[g] == SOpen) m[q >> 6] |= bit;
+            if (first[g] == SClose) m[W + (q >> 6)] |= bit;
+            if (open_then_close[g]) m[2 * W + (q >> 6)] |= bit;
+        }
+    }
     A.I = I.w;
     A.F = F.w;
     A.ninit = A.nfinal = 0;

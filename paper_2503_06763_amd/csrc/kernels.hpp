@@ -73,6 +73,8 @@ struct Tabs {
     const uint32_t *xoff_nb;    // entry lists filtered by the next byte only (ablation)
     const uint16_t *xlist_nb;
     uint32_t emax_nb;
+    const uint64_t *gmask;      // match extraction: ngroups x 3 x W segment masks
+    uint32_t ngroups;
     uint32_t off16;
     uint32_t fhmask, rhmask;
     uint32_t C, W, NL;          // classes, words, C + 1

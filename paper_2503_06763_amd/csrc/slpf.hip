@@ -1,7 +1,9 @@
 // C ABI of the SLPF library: compile (host) and parse (device launches).
 #include <hip/hip_runtime.h>
+#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
+#include <climits>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -123,6 +125,7 @@ slpf_status upload(slpf_parser *p) {
         {rnz.data(), rnz.size() * 4, 0},
         {A.xoff_nb.data(), A.xoff_nb.size() * 4, 0},
         {A.xlist_nb.data(), std::max<size_t>(A.xlist_nb.size(), 1) * 2, 0},
+        {A.gmask.data(), A.gmask.size() * 8, 0},
     };
     size_t total = 0;
     for (auto &pt : parts) {
@@ -165,6 +168,8 @@ slpf_status upload(slpf_parser *p) {
     t.xoff_nb = reinterpret_cast<const uint32_t *>(at(20));
     t.xlist_nb = reinterpret_cast<const uint16_t *>(at(21));
     t.emax_nb = std::max<uint32_t>(A.max_entries_nb, 1);
+    t.gmask = reinterpret_cast<const uint64_t *>(at(22));
+    t.ngroups = A.ngroups;
     t.fhmask = static_cast<uint32_t>(A.fwd.hash.size() - 1);
     t.rhmask = static_cast<uint32_t>(A.rev.hash.size() - 1);
     t.C = A.C;
@@ -817,3 +822,162 @@ slpf_status slpf_tune(const slpf_parser *cp, const slpf_text *items, size_t coun
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------ match extraction
+// Match extraction over a clean SLPF (Sect. 4, "Other functions of the tool",
+// Match extraction: getMatches).
+//
+// A match of group g (the operator node numbered g) is a pair (start, end)
+// of text positions such that some syntax tree has "g(" at position start
+// and its matching ")g" at position end.  In the clean SLPF every local
+// path extends to a whole tree (each segment lies on one), so the matches
+// starting at column r are found by a walk: from the segments of C_r whose
+// last g-symbol is "g(", follow the arcs (followers present in the next
+// column) through segments without g-symbols, and every column e where a
+// segment whose first g-symbol is ")g" is reached gives (r, e).  A segment
+// holding "g( .. )g" gives the empty match (r, r).  Group g cannot open
+// inside itself, so no other g-symbol can appear on such a path.
+//
+// Pass 1 flags the start columns, a device select lists them in order; one
+// wavefront per start column walks and counts its matches; an exclusive
+// scan gives each start its output offset; the second walk writes the pairs,
+// so they come out sorted by (start, end).
+namespace slpf {
+namespace {
+
+__global__ __launch_bounds__(256) void k_match_flags(Tabs tb, const uint64_t *cols, uint64_t n, uint32_t g,
+                                                     uint8_t *flags) {
+    const uint64_t r = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r > n) return;
+    const uint32_t W = tb.W;
+    const uint64_t *m = tb.gmask + static_cast<uint64_t>(g) * 3 * W;
+    uint64_t any = 0;
+    for (uint32_t w = 0; w < W; ++w) any |= cols[r * W + w] & (m[w] | m[2 * W + w]);
+    flags[r] = any != 0 ? 1 : 0;
+}
+
+// One wavefront per start column; lane w holds word w of the walk's frontier.
+template <bool WRITE>
+__global__ __launch_bounds__(64) void k_match_walk(Tabs tb, const uint64_t *cols, uint64_t n, uint32_t g,
+                                                   const uint64_t *starts, const int *nstarts, uint64_t *counts,
+                                                   const uint64_t *offs, uint64_t *pairs, uint64_t cap) {
+    const uint32_t lane = threadIdx.x, W = tb.W;
+    const bool on = lane < W;
+    const uint64_t *m = tb.gmask + static_cast<uint64_t>(g) * 3 * W;
+    const uint64_t op = on ? m[lane] : 0ull, cl = on ? m[W + lane] : 0ull, oc = on ? m[2 * W + lane] : 0ull;
+    const int ns = *nstarts;
+    for (int item = blockIdx.x; item < ns; item += gridDim.x) {
+        const uint64_t r = starts[item];
+        uint64_t pos = WRITE ? offs[item] : 0ull;
+        auto emit = [&](uint64_t e) {
+            if (WRITE && lane == 0 && pos < cap) {
+                pairs[2 * pos] = r;
+                pairs[2 * pos + 1] = e;
+            }
+            ++pos;
+        };
+        const uint64_t c0 = on ? cols[r * W + lane] : 0ull;
+        if (__any((c0 & oc) != 0)) emit(r);                  // "g( .. )g" inside a segment
+        uint64_t f = c0 & op;                                // g is open after these segments
+        uint64_t c = r;
+        while (c < n && __any(f != 0)) {
+            ++c;
+            uint64_t nf = 0;
+            for (uint32_t w = 0; w < W; ++w) {
+                for (uint64_t fw = readlane_u64(f, static_cast<int>(w)); fw; fw &= fw - 1) {
+                    const uint64_t sg = w * 64ull + static_cast<uint64_t>(__builtin_ctzll(fw));
+                    if (on) nf |= tb.folseg[sg * W + lane];
+                }
+            }
+            if (on) nf &= cols[c * W + lane];
+            if (__any((nf & cl) != 0)) emit(c);
+            f = nf & ~cl;
+        }
+        if (!WRITE && lane == 0) counts[item] = pos;
+    }
+}
+
+__global__ void k_match_fill(uint64_t *a, uint64_t n) {
+    const uint64_t k = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k < n) a[k] = 0;
+}
+
+__global__ void k_match_total(const uint64_t *offs, const uint64_t *counts, const int *ns, uint64_t *total) {
+    const int k = *ns;
+    *total = k > 0 ? offs[k - 1] + counts[k - 1] : 0ull;
+}
+
+}  // namespace
+}  // namespace slpf
+
+extern "C" slpf_status slpf_get_matches(const slpf_parser *p, const uint64_t *columns_dev, uint64_t n, uint32_t group,
+                                        uint64_t *pairs_dev, uint64_t capacity, uint64_t *num_matches,
+                                        void *hip_stream) {
+    using namespace slpf;
+    if (!p || p->host_only || !columns_dev || !num_matches || (capacity && !pairs_dev)) return SLPF_E_ARG;
+    const Tabs tb = p->tabs;
+    const int device = p->device;
+    if (group == 0 || group >= tb.ngroups) return SLPF_E_ARG;
+    if (n >= static_cast<uint64_t>(INT_MAX)) return SLPF_E_ARG;
+    if (hipSetDevice(device) != hipSuccess) return SLPF_E_DEVICE;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    const uint64_t N = n + 1;
+    const int NI = static_cast<int>(N);
+    // work buffers: flags, starts, their number, counts, offsets, total
+    size_t sel_bytes = 0, scan_bytes = 0;
+    hipcub::CountingInputIterator<uint64_t> idx(0);
+    if (hipcub::DeviceSelect::Flagged(nullptr, sel_bytes, idx, static_cast<uint8_t *>(nullptr),
+                                      static_cast<uint64_t *>(nullptr), static_cast<int *>(nullptr), NI, st) !=
+            hipSuccess ||
+        hipcub::DeviceScan::ExclusiveSum(nullptr, scan_bytes, static_cast<uint64_t *>(nullptr),
+                                         static_cast<uint64_t *>(nullptr), NI, st) != hipSuccess)
+        return SLPF_E_DEVICE;
+    const size_t tmp_bytes = sel_bytes > scan_bytes ? sel_bytes : scan_bytes;
+    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t o_flags = 0, o_starts = o_flags + al(N), o_counts = o_starts + al(N * 8), o_offs = o_counts + al(N * 8),
+                 o_ns = o_offs + al(N * 8), o_total = o_ns + 256, o_tmp = o_total + 256, bytes = o_tmp + al(tmp_bytes);
+    uint8_t *buf = nullptr;
+    if (hipMalloc(reinterpret_cast<void **>(&buf), bytes) != hipSuccess) return SLPF_E_NOMEM;
+    uint8_t *flags = buf + o_flags;
+    uint64_t *starts = reinterpret_cast<uint64_t *>(buf + o_starts);
+    uint64_t *counts = reinterpret_cast<uint64_t *>(buf + o_counts);
+    uint64_t *offs = reinterpret_cast<uint64_t *>(buf + o_offs);
+    int *ns = reinterpret_cast<int *>(buf + o_ns);
+    uint64_t *total = reinterpret_cast<uint64_t *>(buf + o_total);
+    void *tmp = buf + o_tmp;
+    slpf_status status = SLPF_OK;
+    uint64_t h_total = 0;
+    const uint32_t blocks = static_cast<uint32_t>((N + 255) / 256);
+    const uint32_t walkers = static_cast<uint32_t>(N < 4096 ? N : 4096);
+    do {
+        hipLaunchKernelGGL(k_match_flags, dim3(blocks), dim3(256), 0, st, tb, columns_dev, n, group, flags);
+        hipLaunchKernelGGL(k_match_fill, dim3(blocks), dim3(256), 0, st, counts, N);
+        size_t tb1 = tmp_bytes;
+        if (hipcub::DeviceSelect::Flagged(tmp, tb1, idx, flags, starts, ns, NI, st) != hipSuccess) {
+            status = SLPF_E_DEVICE;
+            break;
+        }
+        hipLaunchKernelGGL(k_match_walk<false>, dim3(walkers), dim3(64), 0, st, tb, columns_dev, n, group, starts, ns,
+                           counts, nullptr, nullptr, 0ull);
+        size_t tb2 = tmp_bytes;
+        if (hipcub::DeviceScan::ExclusiveSum(tmp, tb2, counts, offs, NI, st) != hipSuccess) {
+            status = SLPF_E_DEVICE;
+            break;
+        }
+        hipLaunchKernelGGL(k_match_total, dim3(1), dim3(1), 0, st, offs, counts, ns, total);
+        if (hipMemcpyAsync(&h_total, total, 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess) {
+            status = SLPF_E_DEVICE;
+            break;
+        }
+        if (h_total && capacity)
+            hipLaunchKernelGGL(k_match_walk<true>, dim3(walkers), dim3(64), 0, st, tb, columns_dev, n, group, starts,
+                               ns, counts, offs, pairs_dev, capacity);
+        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) status = SLPF_E_DEVICE;
+    } while (false);
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(buf);
+    if (status != SLPF_OK) return status;
+    *num_matches = h_total;
+    return h_total > capacity ? SLPF_E_CAPACITY : SLPF_OK;
+}

@@ -53,6 +53,12 @@ struct HostAutomaton {
     uint32_t max_entries_nb = 0;
     uint32_t ninit = 0, nfinal = 0;
     HostTable fwd, rev;
+    // match extraction: per node number g (1 .. ngroups-1) three W-word
+    // segment masks: the segment leaves g open (its last g-symbol is "g("),
+    // it closes an open g (its first g-symbol is ")g"), it holds "g( .. )g"
+    // (an empty match); all zero for leaves
+    uint32_t ngroups = 0;
+    std::vector<uint64_t> gmask;          // ngroups x 3 x W
 };
 
 struct CompileLimits {
