@@ -115,12 +115,20 @@ def time_matches(parser, text_np, cols):
     import torch
     import numpy as np
     n = text_np.size
-    pre = torch.from_numpy(text_np[:1 << 16].copy()).to("cuda:0")
-    pcols, _ = parser.parse(pre)
+    # a prefix of whole records (cut after its last newline), so that it is
+    # accepted; the group with the most matches there is a field (the star's
+    # group has one match spanning the text, walked in one wavefront)
+    head = text_np[:1 << 16]
+    cut = int(np.nonzero(head == 10)[0][-1]) + 1
+    pre = torch.from_numpy(head[:cut].copy()).to("cuda:0")
+    pcols, psc = parser.parse(pre)
     groups = sorted({int(t[:-1]) for i in range(parser.nseg) for t in parser.segment_text(i).split(" ")
                      if t.endswith("(")})
-    best = max(groups, key=lambda g: (len(parser.matches(pcols, g)), -g))
+    counts = {g: len(parser.matches(pcols, g)) for g in groups}
+    best = max(groups, key=lambda g: (counts[g], -g))
     del pcols
+    if counts[best] <= 1:
+        return {"skipped": "no field group with matches on the prefix"}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     m = parser.matches(cols, best, capacity=n // 2)
