@@ -17,7 +17,8 @@
  *  - Host pointers are only read during the call.
  *  - Calls taking a hip_stream (a hipStream_t, NULL = the default stream)
  *    are asynchronous and stream-ordered: results are valid once the stream
- *    reaches the point of the call.
+ *    reaches the point of the call (slpf_get_matches and slpf_tune return
+ *    after synchronizing the stream).
  *  - A compiled parser is immutable and may be used concurrently from
  *    several host threads and streams.
  *
@@ -48,7 +49,7 @@ typedef enum {
     SLPF_E_TOO_LARGE = -4,  /* automaton beyond the limits (segments, states, entry lists) */
     SLPF_E_NOMEM = -5,      /* host or device allocation failed */
     SLPF_E_DEVICE = -6,     /* a HIP call failed */
-    SLPF_E_CAPACITY = -7,   /* output buffer smaller than slpf_forest_bytes() */
+    SLPF_E_CAPACITY = -7,   /* output too small: slpf_forest_bytes(), slpf_compact_bytes(), match pairs */
     SLPF_E_INTERNAL = -8
 } slpf_status;
 
@@ -221,7 +222,8 @@ typedef struct {
 /*
  * Output of a parse.  columns_dev: the SLPF, column r (0 <= r <= n) at
  * words [r*W, (r+1)*W), bit j of the column set iff segment j is in the
- * clean column C_r (Sect. 2.3.4; Boolean vectors as in Sect. 2.4).
+ * clean column C_r (Sect. 2.3.4; Boolean vectors as in Sect. 2.4); with
+ * SLPF_PARSE_COMPACT, word r is the compact column (see slpf_compact_bytes).
  * scalars_dev[0] = 1 if the text is in the language else 0;
  * scalars_dev[1] = number of syntax trees modulo 2^64 (the number of
  *                  accepting NFA runs, one per LST, Sect. 2.3.4);
@@ -237,7 +239,8 @@ typedef struct {
  * of the build covers whole cache lines.
  */
 typedef struct {
-    uint64_t *columns_dev;     /* device, capacity_bytes >= slpf_forest_bytes(p, n) */
+    uint64_t *columns_dev;     /* device, capacity_bytes >= slpf_forest_bytes(p, n), or
+                                  slpf_compact_bytes(n) with SLPF_PARSE_COMPACT */
     uint64_t capacity_bytes;
     uint64_t *scalars_dev;     /* device, 3 words */
 } slpf_forest;
