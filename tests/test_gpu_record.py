@@ -83,3 +83,41 @@ def test_record_large_sampled_windows(record):
         assert np.array_equal(g, w[k]), "window at column %d" % st
     del cols
     torch.cuda.empty_cache()
+
+
+def test_record_full_size_sampled_records(record):
+    # the record workload at its full size (1 GiB, the benchmark's automatic
+    # chunking).  The RE is a star of records, so a run of whole records is a
+    # text of the language and its trees are the full text's trees cut at the
+    # record boundaries: the oracle's columns of the run, except its first and
+    # last column (the star's opening and closing there), must equal the GPU's
+    # columns at the same positions; the whole text has exactly one tree
+    import torch
+    device()
+    pat, p, o = record
+    text = textgen.record_text(31, 1 << 30)
+    n = text.size
+    t = torch.from_numpy(text).to("cuda:0")
+    cols, sc = p.parse(t)
+    torch.cuda.synchronize()
+    scn = sc.cpu().numpy().view(np.uint64)
+    assert bool(scn[0]) and int(scn[1]) == 1 and int(scn[2]) == 0
+    rng = np.random.default_rng(11)
+    cuts = [0] + [int(x) for x in rng.integers(0, n - (1 << 12), size=8)] + [n - (1 << 12)]
+    for a0 in cuts:
+        # three whole records from the first record start at or after a0
+        if a0 == 0:
+            a = 0
+        else:
+            a = a0 + int(np.nonzero(text[a0:a0 + 4096] == 10)[0][0]) + 1
+        ends = np.nonzero(text[a:a + 4096] == 10)[0]
+        b = a + int(ends[min(2, ends.size - 1)]) + 1
+        sub = text[a:b].tobytes()
+        oc, acc, cnt = o.parse(sub)
+        assert acc and cnt == 1
+        g = cols[a:b + 1].cpu().numpy().view(np.uint64)
+        lo = 0 if a == 0 else 1                          # column 0 is the same at the text start
+        hi = b - a + 1 if b == n else b - a              # and column n at the text end
+        assert np.array_equal(g[lo:hi], oc[lo:hi]), "records %d..%d" % (a, b)
+    del cols, t
+    torch.cuda.empty_cache()
