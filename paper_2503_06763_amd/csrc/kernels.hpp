@@ -1193,6 +1193,8 @@ __global__ __launch_bounds__(kCountThreads) void k_count_fast(Tabs tb, Job jb) {
     const uint32_t nwin_wave = wave_max_u32(nwin);
     uint32_t xw[16], cw[16], qs[4];              // window bytes, classes, forward id at each quarter start
     uint32_t mp = 0, yc = 0;                     // previous column's size; its vector is yb + yc*kVec
+    bool lz = false;                             // that vector is all ylz (a singleton's count, not written)
+    uint64_t ylz = 0;
     uint32_t fp = 0, bp = 0;                     // previous column's state ids when it was ambiguous
     uint64_t pi = 1, r1 = 0;
     bool found = false, over = !act;
@@ -1227,6 +1229,10 @@ __global__ __launch_bounds__(kCountThreads) void k_count_fast(Tabs tb, Job jb) {
         const uint32_t f = e & 0xffffu, b = e >> 16;
         const bool gen = live && m > 1 && mp > 1;
         if (__any(gen)) {
+            if (gen && lz) {   // write out the broadcast count before the arcs read it
+                for (uint32_t j = 0; j < mp; ++j) yprev[j] = ylz;
+                lz = false;
+            }
             if (gen && !fwd) {
                 // backward: y[k] over the current (left) column gathers the counts of
                 // the followers of its k-th segment in the previous (right) column
@@ -1281,16 +1287,20 @@ __global__ __launch_bounds__(kCountThreads) void k_count_fast(Tabs tb, Job jb) {
         if (__any(sum)) {
             if (sum) {
                 uint64_t t = 0;
-                for (uint32_t j = 0; j < mp; ++j) t += yprev[j];
+                if (lz) {
+                    t = ylz * mp;
+                } else {
+                    for (uint32_t j = 0; j < mp; ++j) t += yprev[j];
+                }
                 yprev[0] = t;
+                lz = false;
             }
         }
-        const bool bcast = live && m > 1 && mp == 1;   // the singleton reaches every segment of this column
-        if (__any(bcast)) {
-            if (bcast) {
-                const uint64_t y0 = yprev[0];
-                for (uint32_t k = 0; k < m; ++k) ycur[k] = y0;
-            }
+        // the singleton reaches every segment of this column: the vector is
+        // its count everywhere, kept as one number until arcs need it
+        if (live && m > 1 && mp == 1) {
+            lz = true;
+            ylz = yprev[0];
         }
         if (collapse && live && m == 1 && mp > 1) {
             pi *= yprev[0];
@@ -1374,6 +1384,7 @@ __global__ __launch_bounds__(kCountThreads) void k_count_fast(Tabs tb, Job jb) {
                         r1 = a0 + t;
                         yb[yc * kVec] = 1;
                         mp = 1;
+                        lz = false;
                     }
                     live = false;
                 }
@@ -1386,13 +1397,14 @@ __global__ __launch_bounds__(kCountThreads) void k_count_fast(Tabs tb, Job jb) {
     if (act && !over) {
         uint64_t *uv = jb.uv + static_cast<uint64_t>(i) * 2 * kVec;
         const uint64_t *yv = yb + yc * kVec;
-        for (int k = 0; k < kVec; ++k) uv[kVec + k] = k < static_cast<int>(mL) ? yv[k] : 0ull;
+        for (int k = 0; k < kVec; ++k) uv[kVec + k] = k < static_cast<int>(mL) ? (lz ? ylz : yv[k]) : 0ull;
     }
 
     // forward from r1 to column hi = P_{i+1}
     yc = 0;
     yb[0] = 1;
     mp = 1;
+    lz = false;
     const bool fw_on = act && !over;
     const uint32_t w_first = wave_min(fw_on ? static_cast<uint32_t>((r1 - lo) / 64) : 0xffffffffu);
     for (uint32_t w = w_first; w < nwin_wave; ++w) {
@@ -1461,7 +1473,7 @@ __global__ __launch_bounds__(kCountThreads) void k_count_fast(Tabs tb, Job jb) {
     if (!act) return;
     uint64_t *uv = jb.uv + static_cast<uint64_t>(i) * 2 * kVec;
     const uint64_t *yv = yb + yc * kVec;
-    for (int k = 0; k < kVec; ++k) uv[k] = k < static_cast<int>(mp) ? yv[k] : 0ull;
+    for (int k = 0; k < kVec; ++k) uv[k] = k < static_cast<int>(mp) ? (lz ? ylz : yv[k]) : 0ull;
     jb.pi[i] = pi;
     jb.dims[2 * i] = static_cast<uint8_t>(mL);
     jb.dims[2 * i + 1] = static_cast<uint8_t>(mp);
