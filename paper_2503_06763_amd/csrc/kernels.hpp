@@ -308,7 +308,7 @@ __device__ inline void load_window(const uint8_t *text, uint64_t a0, uint32_t le
 // loads.  Runs that reach the same state are merged (equal states have equal
 // futures); `alias` maps entry k of the group to the slot holding its run.
 // Slots dead in every lane of the wavefront are skipped.
-template <bool FWD, bool OFF>
+template <bool FWD, bool OFF, bool GRP>
 __device__ inline void run_group(const uint8_t *text, uint64_t lo, uint64_t hi, const uint16_t *cls,
                                  const uint16_t *delta, uint32_t C, uint32_t st[kGroup],
                                  uint32_t &alias) {
@@ -385,19 +385,51 @@ __device__ inline void run_group(const uint8_t *text, uint64_t lo, uint64_t hi, 
     const uint64_t nblk = body >> 4;
     const uint4 *vp = reinterpret_cast<const uint4 *>(text + lo);
     // 16-byte blocks in processing order; the next block is loaded while the
-    // current one is consumed, so the wave does not wait on HBM per block
+    // current ones are consumed, so the wave does not wait on HBM per block.
+    // GRP: four blocks (64 bytes) a lane per load round, so that a lane uses
+    // half a cache line at once and lines are not fetched again after
+    // eviction (with tables in L2 the registers go to the lookups instead)
     auto blk = [&](uint64_t k) { return vp[FWD ? k : nblk - 1 - k]; };
-    uint4 v = nblk ? blk(0) : uint4{0, 0, 0, 0};
-    for (uint64_t k = 0; k < nblk; ++k) {
-        const uint4 nv = k + 1 < nblk ? blk(k + 1) : v;
-        if ((k & 3) == 3 && !settle()) return;
+    auto run16 = [&](const uint4 &v) {
         const uint32_t wd[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
         for (int t = 0; t < 16; ++t) {
             const int tt = FWD ? t : 15 - t;
             step((wd[tt >> 2] >> ((tt & 3) * 8)) & 0xffu);
         }
-        v = nv;
+    };
+    if constexpr (GRP) {
+        const uint64_t ngrp = nblk >> 2;
+        uint4 cur[4], nxt[4];
+        if (ngrp) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) cur[j] = blk(j);
+        }
+        for (uint64_t g = 0; g < ngrp; ++g) {
+            if (g + 1 < ngrp) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) nxt[j] = blk(4 * (g + 1) + j);
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (j == 3 && !settle()) return;
+                run16(cur[j]);
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) cur[j] = nxt[j];
+        }
+        for (uint64_t k = 4 * ngrp; k < nblk; ++k) {
+            if ((k & 3) == 3 && !settle()) return;
+            run16(blk(k));
+        }
+    } else {
+        uint4 v = nblk ? blk(0) : uint4{0, 0, 0, 0};
+        for (uint64_t k = 0; k < nblk; ++k) {
+            const uint4 nv = k + 1 < nblk ? blk(k + 1) : v;
+            if ((k & 3) == 3 && !settle()) return;
+            run16(v);
+            v = nv;
+        }
     }
     if (FWD)
         for (uint64_t p = lo + body; p < hi; ++p) step(text[p]);
@@ -441,7 +473,7 @@ __global__ __launch_bounds__(256) void k_reach(Tabs tb, Job jb) {
             st[k] = (g0 + k < na) ? tb.fsingle[tb.xlist[xa0 + g0 + k]] * c2 : 0;
             alias |= static_cast<uint32_t>(k) << (4 * k);
         }
-        run_group<true, OFF>(text, lo, hi, lk.cls, lk.fd, tb.C, st, alias);
+        run_group<true, OFF, LDS>(text, lo, hi, lk.cls, lk.fd, tb.C, st, alias);
 #pragma unroll
         for (int k = 0; k < kGroup; ++k) {
             if (g0 + k < na) {
@@ -462,7 +494,7 @@ __global__ __launch_bounds__(256) void k_reach(Tabs tb, Job jb) {
             st[k] = (g0 + k < nb) ? tb.rsingle[tb.xlist[xb0 + g0 + k]] * c2 : 0;
             alias |= static_cast<uint32_t>(k) << (4 * k);
         }
-        run_group<false, OFF>(text, lo, hi, lk.cls, lk.rd, tb.C, st, alias);
+        run_group<false, OFF, LDS>(text, lo, hi, lk.cls, lk.rd, tb.C, st, alias);
 #pragma unroll
         for (int k = 0; k < kGroup; ++k) {
             if (g0 + k < nb) {
