@@ -190,7 +190,7 @@ __device__ inline ChunkCtx chunk_ctx(const Job &jb, uint32_t i) {
     return x;
 }
 
-constexpr int kGroup = 8;
+constexpr int kGroup = 12;                    // runs in lockstep (slot nibbles in a u64)
 constexpr int kVec = 12;                      // clean-column segments handled by the fast count
 constexpr uint32_t kRank1 = 0xffffffffu;       // chunk matrix held as v * pi * u^T
 constexpr uint32_t kOverflow = 0xfffffffeu;    // general chunk beyond the kernel's limits
@@ -311,7 +311,7 @@ __device__ inline void load_window(const uint8_t *text, uint64_t a0, uint32_t le
 template <bool FWD, bool OFF, bool GRP>
 __device__ inline void run_group(const uint8_t *text, uint64_t lo, uint64_t hi, const uint16_t *cls,
                                  const uint16_t *delta, uint32_t C, uint32_t st[kGroup],
-                                 uint32_t &alias) {
+                                 uint64_t &alias) {
     uint32_t nl = kGroup;
     auto settle = [&]() -> bool {
 #pragma unroll
@@ -322,7 +322,7 @@ __device__ inline void run_group(const uint8_t *text, uint64_t lo, uint64_t hi, 
 #pragma unroll
                     for (int k = 0; k < kGroup; ++k)
                         if (((alias >> (4 * k)) & 15u) == static_cast<uint32_t>(j))
-                            alias = (alias & ~(15u << (4 * k))) | (static_cast<uint32_t>(i) << (4 * k));
+                            alias = (alias & ~(15ull << (4 * k))) | (static_cast<uint64_t>(i) << (4 * k));
                     st[j] = 0;
                 }
             }
@@ -333,12 +333,12 @@ __device__ inline void run_group(const uint8_t *text, uint64_t lo, uint64_t hi, 
         uint32_t live = 0;
 #pragma unroll
         for (int j = 0; j < kGroup; ++j) live |= (st[j] != 0 ? 1u : 0u) << j;
-        uint32_t nidx = 0;                       // new slot of slot j in nibble j (15: dead)
+        uint64_t nidx = 0;                       // new slot of slot j in nibble j (15: dead)
 #pragma unroll
         for (int j = 0; j < kGroup; ++j) {
             const uint32_t ix = ((live >> j) & 1u) ? static_cast<uint32_t>(__builtin_popcount(live & ((1u << j) - 1u)))
                                                    : 15u;
-            nidx |= ix << (4 * j);
+            nidx |= static_cast<uint64_t>(ix) << (4 * j);
         }
         uint32_t ns[kGroup];
 #pragma unroll
@@ -348,12 +348,12 @@ __device__ inline void run_group(const uint8_t *text, uint64_t lo, uint64_t hi, 
             for (int j = t; j < kGroup; ++j)
                 if (((nidx >> (4 * j)) & 15u) == static_cast<uint32_t>(t)) ns[t] = st[j];
         }
-        uint32_t na = 0;
+        uint64_t na = 0;
 #pragma unroll
         for (int k = 0; k < kGroup; ++k) {
             const uint32_t a = (alias >> (4 * k)) & 15u;
             const uint32_t m = a < kGroup ? (nidx >> (4 * a)) & 15u : 15u;
-            na |= m << (4 * k);
+            na |= static_cast<uint64_t>(m) << (4 * k);
         }
         alias = na;
 #pragma unroll
@@ -467,11 +467,11 @@ __global__ __launch_bounds__(256) void k_reach(Tabs tb, Job jb) {
     // forward runs from X_i
     for (uint32_t g0 = 0; __any(g0 < na); g0 += kGroup) {
         uint32_t st[kGroup];
-        uint32_t alias = 0;
+        uint64_t alias = 0;
 #pragma unroll
         for (int k = 0; k < kGroup; ++k) {
             st[k] = (g0 + k < na) ? tb.fsingle[tb.xlist[xa0 + g0 + k]] * c2 : 0;
-            alias |= static_cast<uint32_t>(k) << (4 * k);
+            alias |= static_cast<uint64_t>(k) << (4 * k);
         }
         run_group<true, OFF, LDS>(text, lo, hi, lk.cls, lk.fd, tb.C, st, alias);
 #pragma unroll
@@ -488,11 +488,11 @@ __global__ __launch_bounds__(256) void k_reach(Tabs tb, Job jb) {
     // backward runs from X_{i+1} (not for the recogniser)
     for (uint32_t g0 = 0; !jb.fwd_only && __any(g0 < nb); g0 += kGroup) {
         uint32_t st[kGroup];
-        uint32_t alias = 0;
+        uint64_t alias = 0;
 #pragma unroll
         for (int k = 0; k < kGroup; ++k) {
             st[k] = (g0 + k < nb) ? tb.rsingle[tb.xlist[xb0 + g0 + k]] * c2 : 0;
-            alias |= static_cast<uint32_t>(k) << (4 * k);
+            alias |= static_cast<uint64_t>(k) << (4 * k);
         }
         run_group<false, OFF, LDS>(text, lo, hi, lk.cls, lk.rd, tb.C, st, alias);
 #pragma unroll
