@@ -1618,7 +1618,7 @@ __global__ __launch_bounds__(kListThreads) void k_count_list(Tabs tb, Job jb) {
     uint64_t y[kVec];                            // path counts over the previous column's segments
 #pragma unroll
     for (int k = 0; k < kVec; ++k) y[k] = 0;
-    uint32_t mp = 0, cb = 0;                     // previous column size; list buffer of the next column
+    uint32_t mp = 0, ep = 0;                     // previous column's size, and its entry when ambiguous
     uint64_t pi = 1, r1 = 0;
     bool found = false, over = !act;
 
@@ -1630,39 +1630,48 @@ __global__ __launch_bounds__(kListThreads) void k_count_list(Tabs tb, Job jb) {
         if (s == kNoSole) s = rso[b];
         return s != kNoSole ? (s << 16) : (f | (b << 16));
     };
-    // number of segments of a staged column; an ambiguous column's segments go
-    // to list cb (only ambiguous columns need their list: a step from a
-    // singleton reaches every segment of the next column)
+    // number of segments of a staged column
     auto column = [&](bool live, uint32_t e) -> uint32_t {
         const bool multi = live && (e & 0xffffu) != 0;
         uint32_t m = live ? 1u : 0u;
         if (__any(multi)) {
             if (multi) {
-                uint16_t *lst = segl + cb * kVec;
                 const uint32_t f = e & 0xffffu, b = e >> 16;
                 m = 0;
-                for (uint32_t w = 0; w < W; ++w) {
-                    uint64_t v = fbits[f * W + w] & rbits[b * W + w];
-                    while (v) {
-                        if (m < static_cast<uint32_t>(kVec)) lst[m] = static_cast<uint16_t>(w * 64 + __builtin_ctzll(v));
-                        v &= v - 1;
-                        ++m;
-                    }
-                }
+                for (uint32_t w = 0; w < W; ++w) m += static_cast<uint32_t>(__popcll(fbits[f * W + w] & rbits[b * W + w]));
             }
         }
         return m;
     };
-    // one DP step onto the column in list cb (m segments) from the previous
-    // column (mp segments, list cb^1 when mp > 1); fwd: the previous column is
-    // the left one; collapse: multiply pi at singletons (backward pass).  Each
-    // case other than singleton-to-singleton sits behind a wavefront-uniform
-    // test, so a wavefront skips the cases none of its lanes needs.
-    auto step = [&](bool live, uint32_t m, bool fwd, bool collapse) {
+    // the segments of an ambiguous column (entry e) into lst[0..kVec)
+    auto list_into = [&](uint32_t e, uint16_t *lst) {
+        const uint32_t f = e & 0xffffu, b = e >> 16;
+        uint32_t m = 0;
+        for (uint32_t w = 0; w < W; ++w) {
+            uint64_t v = fbits[f * W + w] & rbits[b * W + w];
+            while (v) {
+                if (m < static_cast<uint32_t>(kVec)) lst[m] = static_cast<uint16_t>(w * 64 + __builtin_ctzll(v));
+                v &= v - 1;
+                ++m;
+            }
+        }
+    };
+    // one DP step onto the column e (m segments) from the previous column
+    // (mp segments, entry ep when mp > 1); fwd: the previous column is the
+    // left one; collapse: multiply pi at singletons (backward pass).  The
+    // segment lists are made only for a step between two ambiguous columns (a
+    // step from or to a singleton needs no arcs).  Each case other than
+    // singleton-to-singleton sits behind a wavefront-uniform test, so a
+    // wavefront skips the cases none of its lanes needs.
+    auto step = [&](bool live, uint32_t m, uint32_t e, bool fwd, bool collapse) {
         const bool gen = live && m > 1 && mp > 1;
         if (__any(gen)) {   // ambiguous to ambiguous: follower checks, uniform bounds over those lanes
             const uint32_t mw = wave_max_small(gen ? m : 0), mpw = wave_max_small(gen ? mp : 0);
-            const uint16_t *lc = segl + cb * kVec, *lp = segl + (cb ^ 1u) * kVec;
+            uint16_t *lc = segl, *lp = segl + kVec;
+            if (gen) {
+                list_into(e, lc);
+                list_into(ep, lp);
+            }
             uint64_t z[kVec];
 #pragma unroll
             for (int k = 0; k < kVec; ++k) z[k] = 0;
@@ -1710,7 +1719,7 @@ __global__ __launch_bounds__(kListThreads) void k_count_list(Tabs tb, Job jb) {
             y[0] = 1;
         }
         if (live) {
-            if (m > 1) cb ^= 1u;         // this column's list becomes the previous one
+            if (m > 1) ep = e;
             mp = m;
         }
     };
@@ -1772,7 +1781,8 @@ __global__ __launch_bounds__(kListThreads) void k_count_list(Tabs tb, Job jb) {
             for (int u = kQuarter - 1; u >= 0; --u) {
                 const int t = q * kQuarter + u;
                 bool live = on && !over && t < static_cast<int>(len);
-                uint32_t m = column(live, live ? row[u] : 0u);
+                const uint32_t e = live ? row[u] : 0u;
+                uint32_t m = column(live, e);
                 if (live && (m > static_cast<uint32_t>(kVec) || m == 0)) {
                     over = true;
                     live = false;
@@ -1786,7 +1796,7 @@ __global__ __launch_bounds__(kListThreads) void k_count_list(Tabs tb, Job jb) {
                     }
                     live = false;
                 }
-                step(live, m, false, true);
+                step(live, m, e, false, true);
             }
         }
     }
@@ -1858,7 +1868,7 @@ __global__ __launch_bounds__(kListThreads) void k_count_list(Tabs tb, Job jb) {
                     over = true;
                     live = false;
                 }
-                step(live, m, true, false);
+                step(live, m, e, true, false);
             }
         }
     }
