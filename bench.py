@@ -459,7 +459,7 @@ def main():
                     help="after timing, copy this many bytes device-to-device (scale reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build runs on a single MI355X and has no multi-GPU path "
+        print("bench.py measures one GPU: the parser runs on a single MI355X and has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
