@@ -75,6 +75,7 @@ struct Tabs {
     uint32_t emax_nb;
     const uint64_t *gmask;      // match extraction: ngroups x 3 x W segment masks
     uint32_t ngroups;
+    uint32_t col_single;        // every (forward, reverse) state pair shares at most one segment
     uint32_t off16;
     uint32_t fhmask, rhmask;
     uint32_t C, W, NL;          // classes, words, C + 1
@@ -197,6 +198,7 @@ constexpr uint32_t kOverflow = 0xfffffffeu;    // general chunk beyond the kerne
 constexpr uint32_t kPending = 0xfffffffdu;     // chunk left to the general count kernel
 constexpr uint32_t kGeneral = 0xfffffffcu;     // chunk matrix held as A * B through an anchor column
 constexpr uint32_t kSkip = 0xfffffffbu;        // general chunk with no anchor: walked through
+constexpr uint32_t kUncounted = 0u;            // chunk not counted yet
 constexpr int kGenR = 8;                       // largest anchor column of a general chunk
 constexpr int kGenSeg = 64;                    // largest clean column on a general chunk's walks
 static_assert(kGenR * kGenR == 64, "the chain kernels hold one anchor matrix per wavefront, an entry a lane");
@@ -1145,6 +1147,28 @@ __host__ __device__ inline CountLds count_lds(uint32_t nf, uint32_t nr, uint32_t
     return o;
 }
 
+// When every pair of a forward and a reverse state shares at most one
+// segment (col_single), every clean column is a singleton and every chunk of
+// an accepted text has one path between its edges: the rank-1 factor
+// v = u = (1), pi = 1, stored here without reading the text or the columns.
+// Empty chunks are left to the narrow count kernel (kUncounted).
+constexpr int kSingleThreads = 256;
+__global__ __launch_bounds__(kSingleThreads) void k_count_single(Job jb) {
+    const uint32_t i = blockIdx.x * kSingleThreads + threadIdx.x;
+    if (i >= jb.c) return;
+    const ChunkCtx cx = chunk_ctx(jb, i);
+    if (cx.tr.scalars[0] != 0 && cx.hi > cx.lo) {
+        uint64_t *uv = jb.uv + static_cast<uint64_t>(i) * 2 * kVec;
+        for (int k = 0; k < 2 * kVec; ++k) uv[k] = (k == 0 || k == kVec) ? 1ull : 0ull;
+        jb.pi[i] = 1;
+        jb.dims[2 * i] = 1;
+        jb.dims[2 * i + 1] = 1;
+        jb.kind[i] = kRank1;
+    } else {
+        jb.kind[i] = kUncounted;
+    }
+}
+
 // Fast tree count.  Paths through a singleton clean column all pass through
 // its one segment, so a chunk whose columns P_i .. P_{i+1}-1 include a
 // singleton column has the rank-1 transfer matrix T = v * pi * u^T from
@@ -1212,7 +1236,8 @@ __global__ __launch_bounds__(kCountThreads) void k_count_fast(Tabs tb, Job jb) {
     bool act = i < jb.c;
     if (act) {
         cx = chunk_ctx(jb, i);
-        act = cx.tr.scalars[0] != 0;             // trees only in accepted texts
+        // trees only in accepted texts; with col_single the chunks already counted
+        act = cx.tr.scalars[0] != 0 && !(tb.col_single && jb.kind[i] == kRank1);
     }
     const uint8_t *text = cx.tr.text;
     uint64_t lo = 0, hi = 0;

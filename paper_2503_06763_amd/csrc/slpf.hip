@@ -170,6 +170,20 @@ slpf_status upload(slpf_parser *p) {
     t.emax_nb = std::max<uint32_t>(A.max_entries_nb, 1);
     t.gmask = reinterpret_cast<const uint64_t *>(at(22));
     t.ngroups = A.ngroups;
+    // col_single: no clean column can hold two segments, since a column is
+    // the intersection of a forward and a reverse state set
+    t.col_single = 1;
+    for (uint32_t f = 0; f < A.fwd.nstates && t.col_single; ++f)
+        for (uint32_t b = 0; b < A.rev.nstates; ++b) {
+            uint32_t m = 0;
+            for (uint32_t w = 0; w < A.W; ++w)
+                m += static_cast<uint32_t>(__builtin_popcountll(A.fwd.bits[size_t(f) * A.W + w] &
+                                                                A.rev.bits[size_t(b) * A.W + w]));
+            if (m > 1) {
+                t.col_single = 0;
+                break;
+            }
+        }
     t.fhmask = static_cast<uint32_t>(A.fwd.hash.size() - 1);
     t.rhmask = static_cast<uint32_t>(A.rev.hash.size() - 1);
     t.C = A.C;
@@ -671,6 +685,10 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
         if (W <= 2) {
             const CountLds co = count_lds(tb.nf, tb.nr, tb.C, W, tb.nseg);
             const uint32_t cblocks = (c + kCountThreads - 1) / kCountThreads;
+            // an RE whose clean columns are all singletons: one path per chunk
+            if (tb.col_single)
+                hipLaunchKernelGGL(k_count_single, dim3((c + kSingleThreads - 1) / kSingleThreads),
+                                   dim3(kSingleThreads), 0, stream, jb);
             if (lds && co.end <= p->lds_limit)
                 hipLaunchKernelGGL((k_count_fast<true, true>), dim3(cblocks), dim3(kCountThreads), co.end, stream,
                                    tb, jb);

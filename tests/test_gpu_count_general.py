@@ -115,3 +115,53 @@ def test_no_anchor_anywhere():
             assert acc and st == 0
             assert cnt == pow(10, n, 1 << 64), (n, k)
     say("no-anchor walks ok")
+
+
+def _column_unambiguous(o):
+    """Every reachable forward state set meets every reachable reverse state
+    set in at most one segment (from the oracle's own automata)."""
+    alpha = sorted(set(o.labels))
+
+    def closure(start, step):
+        seen, todo = {start}, [start]
+        while todo:
+            s = todo.pop()
+            for a in alpha:
+                t = step(s, a)
+                if t and t not in seen:
+                    seen.add(t)
+                    todo.append(t)
+        return seen
+    fs, bs = closure(o.I, o.step_fwd), closure(o.F, o.step_bwd)
+    return max(len(f & b) for f in fs for b in bs) <= 1
+
+
+def test_column_unambiguous_res_one_tree():
+    # REs whose clean columns are always singletons: one tree per accepted
+    # text, counted without re-running the automata; empty texts, rejected
+    # texts, chunk sizes and batching
+    import torch
+    device()
+    rng = np.random.default_rng(31)
+    for pat, alpha in (("(ab|cd)*e", b"abcde"), ("(a|b)*c(d|e)+", b"abcde"), ("x(yz)*", b"xyz")):
+        p, o = S.Parser(pat), Oracle(pat)
+        assert _column_unambiguous(o), pat
+        texts = [b"", b"e", b"ab" * 700 + b"e", b"cd" * 3000 + b"ab" + b"e", b"abab" + b"x" + b"e", b"x", b"xyz" * 900,
+                 b"ab" * 40 + b"c" + b"d" * 2000, b"c" + b"e" * 5000]
+        texts += [bytes(rng.choice(list(alpha), int(rng.integers(1, 3000)))) for _ in range(4)]
+        for t in texts:
+            _, acc, want = o.parse(t)
+            assert want == (1 if acc else 0)
+            for k in (64, 256, 0):
+                _, a2, cnt, st = gpu_parse(p, t, chunk_bytes=k)
+                assert (a2, cnt, st) == (acc, want, 0), (pat, len(t), k, a2, cnt, st)
+        dts = [to_device(t) for t in texts]
+        for k in (64, 0):
+            res = p.parse_batch(dts, chunk_bytes=k)
+            torch.cuda.synchronize()
+            for t, (cols, sc) in zip(texts, res):
+                s = sc.cpu().numpy().view(np.uint64)
+                alone = gpu_parse(p, t, chunk_bytes=k)
+                assert np.array_equal(cols.cpu().numpy().view(np.uint64), alone[0])
+                assert (bool(s[0]), int(s[1]), int(s[2])) == alone[1:]
+    say("column-unambiguous REs ok")
