@@ -75,7 +75,7 @@ struct Tabs {
     uint32_t emax_nb;
     const uint64_t *gmask;      // match extraction: ngroups x 3 x W segment masks
     uint32_t ngroups;
-    uint32_t col_single;        // every (forward, reverse) state pair shares at most one segment
+    uint32_t col_single;        // reachable forward and reverse states share at most one segment
     uint32_t off16;
     uint32_t fhmask, rhmask;
     uint32_t C, W, NL;          // classes, words, C + 1
@@ -1147,11 +1147,12 @@ __host__ __device__ inline CountLds count_lds(uint32_t nf, uint32_t nr, uint32_t
     return o;
 }
 
-// When every pair of a forward and a reverse state shares at most one
-// segment (col_single), every clean column is a singleton and every chunk of
+// When every forward state reachable from I and every reverse state reachable
+// from F share at most one segment (col_single), every clean column is a
+// singleton and every chunk of
 // an accepted text has one path between its edges: the rank-1 factor
 // v = u = (1), pi = 1, stored here without reading the text or the columns.
-// Empty chunks are left to the narrow count kernel (kUncounted).
+// Empty chunks are left to the count kernels (kUncounted).
 constexpr int kSingleThreads = 256;
 __global__ __launch_bounds__(kSingleThreads) void k_count_single(Job jb) {
     const uint32_t i = blockIdx.x * kSingleThreads + threadIdx.x;
@@ -1628,7 +1629,8 @@ __global__ __launch_bounds__(kListThreads) void k_count_list(Tabs tb, Job jb) {
     bool act = i < jb.c;
     if (act) {
         cx = chunk_ctx(jb, i);
-        act = cx.tr.scalars[0] != 0;             // trees only in accepted texts
+        // trees only in accepted texts; with col_single the chunks already counted
+        act = cx.tr.scalars[0] != 0 && !(tb.col_single && jb.kind[i] == kRank1);
     }
     const uint8_t *text = cx.tr.text;
     uint64_t lo = 0, hi = 0;

@@ -170,15 +170,33 @@ slpf_status upload(slpf_parser *p) {
     t.emax_nb = std::max<uint32_t>(A.max_entries_nb, 1);
     t.gmask = reinterpret_cast<const uint64_t *>(at(22));
     t.ngroups = A.ngroups;
-    // col_single: no clean column can hold two segments, since a column is
-    // the intersection of a forward and a reverse state set
+    // col_single: no clean column can hold two segments.  A clean column of an
+    // accepted text is the intersection of the forward set of its prefix and
+    // the reverse set of its suffix, i.e. of a state reachable from I in the
+    // forward table and one reachable from F in the reverse table (the
+    // multi-entry states never label a column), so only those pairs count.
+    auto reachable = [&](const HostTable &T) {
+        std::vector<uint32_t> out{T.start};
+        std::vector<uint8_t> seen(T.nstates, 0);
+        seen[T.start] = 1;
+        for (size_t k = 0; k < out.size(); ++k)
+            for (uint32_t c = 0; c < A.C; ++c) {
+                const uint32_t nx = T.delta[size_t(out[k]) * A.C + c];
+                if (!seen[nx]) {
+                    seen[nx] = 1;
+                    out.push_back(nx);
+                }
+            }
+        return out;
+    };
+    const std::vector<uint32_t> rf = reachable(A.fwd), rr = reachable(A.rev);
     t.col_single = 1;
-    for (uint32_t f = 0; f < A.fwd.nstates && t.col_single; ++f)
-        for (uint32_t b = 0; b < A.rev.nstates; ++b) {
+    for (size_t x = 0; x < rf.size() && t.col_single; ++x)
+        for (const uint32_t bs : rr) {
             uint32_t m = 0;
             for (uint32_t w = 0; w < A.W; ++w)
-                m += static_cast<uint32_t>(__builtin_popcountll(A.fwd.bits[size_t(f) * A.W + w] &
-                                                                A.rev.bits[size_t(b) * A.W + w]));
+                m += static_cast<uint32_t>(__builtin_popcountll(A.fwd.bits[size_t(rf[x]) * A.W + w] &
+                                                                A.rev.bits[size_t(bs) * A.W + w]));
             if (m > 1) {
                 t.col_single = 0;
                 break;
@@ -701,6 +719,9 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
         } else {
             const ListLds co = list_lds(tb.nf, tb.nr, tb.C, W, tb.nseg);
             const uint32_t cblocks = (c + kListThreads - 1) / kListThreads;
+            if (tb.col_single)
+                hipLaunchKernelGGL(k_count_single, dim3((c + kSingleThreads - 1) / kSingleThreads),
+                                   dim3(kSingleThreads), 0, stream, jb);
             if (lds && co.end <= p->lds_limit)
                 hipLaunchKernelGGL((k_count_list<true, true>), dim3(cblocks), dim3(kListThreads), co.end, stream, tb,
                                    jb);
