@@ -9,6 +9,7 @@ import sys
 import numpy as np
 import pytest
 
+from automata_props import column_unambiguous
 from gpu_util import device, gpu_parse, to_device
 from oracle.oracle import Oracle
 
@@ -117,25 +118,6 @@ def test_no_anchor_anywhere():
     say("no-anchor walks ok")
 
 
-def _column_unambiguous(o):
-    """Every reachable forward state set meets every reachable reverse state
-    set in at most one segment (from the oracle's own automata)."""
-    alpha = sorted(set(o.labels))
-
-    def closure(start, step):
-        seen, todo = {start}, [start]
-        while todo:
-            s = todo.pop()
-            for a in alpha:
-                t = step(s, a)
-                if t and t not in seen:
-                    seen.add(t)
-                    todo.append(t)
-        return seen
-    fs, bs = closure(o.I, o.step_fwd), closure(o.F, o.step_bwd)
-    return max(len(f & b) for f in fs for b in bs) <= 1
-
-
 def test_column_unambiguous_res_one_tree():
     # REs whose clean columns are always singletons: one tree per accepted
     # text, counted without re-running the automata; empty texts, rejected
@@ -145,7 +127,7 @@ def test_column_unambiguous_res_one_tree():
     rng = np.random.default_rng(31)
     for pat, alpha in (("(ab|cd)*e", b"abcde"), ("(a|b)*c(d|e)+", b"abcde"), ("x(yz)*", b"xyz")):
         p, o = S.Parser(pat), Oracle(pat)
-        assert _column_unambiguous(o), pat
+        assert column_unambiguous(o), pat
         texts = [b"", b"e", b"ab" * 700 + b"e", b"cd" * 3000 + b"ab" + b"e", b"abab" + b"x" + b"e", b"x", b"xyz" * 900,
                  b"ab" * 40 + b"c" + b"d" * 2000, b"c" + b"e" * 5000]
         texts += [bytes(rng.choice(list(alpha), int(rng.integers(1, 3000)))) for _ in range(4)]

@@ -15,6 +15,7 @@ import pytest
 import yaml
 
 import lst_brute
+from automata_props import column_unambiguous
 from gen import regen
 from oracle.oracle import Oracle, OracleError, STATUS_INF_AMBIG, STATUS_SYNTAX
 
@@ -324,6 +325,36 @@ def test_unambiguous_counts_are_zero_or_one():
         for x in _strings("ab", 8):
             _, acc, cnt = o.columns(x)
             assert cnt == int(acc)
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_column_unambiguous_res_have_one_tree(seed):
+    # the fact behind the count's shortcut for such REs: when no reachable
+    # forward and reverse state sets share two segments, the brute-force
+    # enumerator finds at most one tree for every text, and the clean columns
+    # are single segments
+    rng = np.random.default_rng(5000 + seed)
+    tree = _tiny_random_re(rng)
+    pat = regen.to_re(tree)
+    o = Oracle(pat)
+    if not column_unambiguous(o):
+        pytest.skip("RE not column-unambiguous")
+    for x in _strings("abc", 5):
+        bcols, bcnt = lst_brute.clean_columns(pat, x)
+        assert bcnt <= 1, (pat, x)
+        assert all(len(c) <= 1 for c in bcols), (pat, x)
+
+
+def test_column_unambiguity_is_not_vacuous():
+    # the property holds for some of the random REs above and fails for
+    # ambiguous ones
+    hits = sum(column_unambiguous(Oracle(regen.to_re(_tiny_random_re(np.random.default_rng(5000 + s)))))
+               for s in range(40))
+    assert 5 <= hits < 40
+    for pat in ["(a|ab|b)*", "(a|aa)*", "(a|b|ab)+"]:
+        assert not column_unambiguous(Oracle(pat))
+    for pat in ["(ab|cd)*e", "x(yz)*", "(ab|a)*"]:
+        assert column_unambiguous(Oracle(pat))
 
 
 # ------------------------------------------------------------ invariants
