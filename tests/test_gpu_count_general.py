@@ -125,12 +125,13 @@ def test_column_unambiguous_res_one_tree():
     import torch
     device()
     rng = np.random.default_rng(31)
-    for pat, alpha in (("(ab|cd)*e", b"abcde"), ("(a|b)*c(d|e)+", b"abcde"), ("x(yz)*", b"xyz")):
+    for pat, alpha in (("(ab|cd)*e", b"abcde"), ("(a|b)*c(d|e)+", b"abcde"), ("x(yz)*", b"xyz"), ("(ab|a)*", b"ab")):
         p, o = S.Parser(pat), Oracle(pat)
         assert column_unambiguous(o), pat
         texts = [b"", b"e", b"ab" * 700 + b"e", b"cd" * 3000 + b"ab" + b"e", b"abab" + b"x" + b"e", b"x", b"xyz" * 900,
                  b"ab" * 40 + b"c" + b"d" * 2000, b"c" + b"e" * 5000]
         texts += [bytes(rng.choice(list(alpha), int(rng.integers(1, 3000)))) for _ in range(4)]
+        texts += [b"a" * 5000, b"ab" * 1500 + b"a" * 64]
         for t in texts:
             _, acc, want = o.parse(t)
             assert want == (1 if acc else 0)
