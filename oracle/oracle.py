@@ -76,6 +76,7 @@ class OracleError(Exception):
 
 
 STATUS_SYNTAX, STATUS_INF_AMBIG, STATUS_TOO_LARGE = -2, -3, -4
+P61 = (1 << 61) - 1          # the second modulus of the tree count
 
 
 def _bytes(x):
@@ -161,17 +162,27 @@ class Oracle:
         return self.to_set(o)
 
     # -- serial parsers
-    def parse(self, text):
-        """Serial NFA parser (Fig. serialparser): (cols[(n+1), W] uint64, accepted, count)."""
+    def parse_full(self, text):
+        """Serial NFA parser (Fig. serialparser): (cols[(n+1), W] uint64,
+        accepted, tree count mod 2^64, tree count mod 2^61 - 1)."""
         x = _bytes(text)
         n = len(x)
         cols = np.zeros((n + 1, self.W), np.uint64)
-        sc = np.zeros(2, np.uint64)
+        sc = np.zeros(3, np.uint64)
         self._L.oracle_parse(self._h, x, n, _u64(cols), _u64(sc))
-        return cols, bool(sc[0]), int(sc[1])
+        return cols, bool(sc[0]), int(sc[1]), int(sc[2])
+
+    def parse(self, text):
+        """Serial NFA parser (Fig. serialparser): (cols[(n+1), W] uint64, accepted, count mod 2^64)."""
+        return self.parse_full(text)[:3]
 
     def parse_dfa(self, text, win_starts=(), win_len: int = 0):
-        """DFA-lookup serial parser; returns (window columns [nwin, win_len, W], accepted, count)."""
+        """DFA-lookup serial parser; returns (window columns [nwin, win_len, W], accepted, count mod 2^64)."""
+        return self.parse_dfa_full(text, win_starts, win_len)[:3]
+
+    def parse_dfa_full(self, text, win_starts=(), win_len: int = 0):
+        """DFA-lookup serial parser; returns (window columns [nwin, win_len, W],
+        accepted, count mod 2^64, count mod 2^61 - 1)."""
         x = _bytes(text) if not isinstance(text, np.ndarray) else text
         if isinstance(x, np.ndarray):
             n = x.size
@@ -181,12 +192,12 @@ class Oracle:
             xp = x
         ws = np.ascontiguousarray(np.asarray(win_starts, dtype=np.uint64))
         out = np.zeros((len(ws), max(win_len, 0), self.W), np.uint64)
-        sc = np.zeros(2, np.uint64)
+        sc = np.zeros(3, np.uint64)
         st = self._L.oracle_parse_dfa(self._h, xp, n, len(ws), _u64(ws) if len(ws) else None,
                                       win_len, _u64(out) if out.size else None, _u64(sc))
         if st != 0:
             raise MemoryError("oracle_parse_dfa failed")
-        return out, bool(sc[0]), int(sc[1])
+        return out, bool(sc[0]), int(sc[1]), int(sc[2])
 
     def columns(self, text):
         cols, acc, cnt = self.parse(text)

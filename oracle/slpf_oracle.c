@@ -26,7 +26,9 @@
  *      remark closing Sect. 2.4);
  *   6. the number of syntax trees = number of accepting NFA runs, i.e. of
  *      paths through the clean SLPF (each accepting run is one LST, Sect.
- *      2.3.4), counted modulo 2^64;
+ *      2.3.4), counted modulo 2^64 and, as a second check that does not
+ *      vanish on counts that are multiples of 2^64, modulo the prime
+ *      2^61 - 1;
  *   7. a second serial parser driven by the powerset DFA of the same NFA and
  *      its reverse (Sect. 3.1), built lazily, for long texts; the paper names
  *      this DFA-lookup parser as an alternative serial reference (Sect. 4.1).
@@ -509,32 +511,50 @@ void oracle_step_bwd(const oracle_t *o, const uint64_t *in, int a, uint64_t *out
 
 /* --------------------------------------- count of trees (accepting runs) */
 
+/* The second modulus of the tree count: the Mersenne prime 2^61 - 1. */
+#define P61 ((((uint64_t)1) << 61) - 1)
+
+static uint64_t addp(uint64_t a, uint64_t b) {   /* a, b < P61 */
+    uint64_t s = a + b;
+    return s >= P61 ? s - P61 : s;
+}
+
 /* cnt_0[sigma] = 1 on C_0; cnt_r[sigma] = sum of cnt_{r-1}[rho] over the arcs
- * rho -> sigma labelled x_r inside the clean SLPF; result = sum over C_n. */
-static uint64_t count_paths(const oracle_t *o, const unsigned char *x, uint64_t n,
-                            const uint64_t *cols) {
+ * rho -> sigma labelled x_r inside the clean SLPF; result = sum over C_n.
+ * The sums are kept modulo 2^64 (cnt) and modulo 2^61 - 1 (cntp). */
+static void count_paths(const oracle_t *o, const unsigned char *x, uint64_t n,
+                        const uint64_t *cols, uint64_t *out64, uint64_t *outp) {
     int W = o->W, L = o->nseg;
     uint64_t *cur = (uint64_t *)calloc(L, 8), *nxt = (uint64_t *)calloc(L, 8);
-    for (int s = 0; s < L; s++) if (GET_BIT(cols, s)) cur[s] = 1;
+    uint64_t *curp = (uint64_t *)calloc(L, 8), *nxtp = (uint64_t *)calloc(L, 8);
+    for (int s = 0; s < L; s++) if (GET_BIT(cols, s)) { cur[s] = 1; curp[s] = 1; }
     for (uint64_t r = 1; r <= n; r++) {
         const uint64_t *c = cols + r * W;
         memset(nxt, 0, 8 * (size_t)L);
+        memset(nxtp, 0, 8 * (size_t)L);
         for (int rho = 0; rho < L; rho++) {
-            if (!cur[rho] || o->seg_label[rho] != x[r - 1]) continue;
+            if (!GET_BIT(cols + (r - 1) * W, rho) || o->seg_label[rho] != x[r - 1]) continue;
             const uint64_t *f = o->folseg + (size_t)rho * W;
             for (int sg = 0; sg < L; sg++)
-                if (GET_BIT(f, sg) && GET_BIT(c, sg)) nxt[sg] += cur[rho];
+                if (GET_BIT(f, sg) && GET_BIT(c, sg)) {
+                    nxt[sg] += cur[rho];
+                    nxtp[sg] = addp(nxtp[sg], curp[rho]);
+                }
         }
         uint64_t *t = cur; cur = nxt; nxt = t;
+        t = curp; curp = nxtp; nxtp = t;
     }
-    uint64_t total = 0;
-    for (int s = 0; s < L; s++) if (GET_BIT(cols + n * W, s)) total += cur[s];
-    free(cur); free(nxt);
-    return total;
+    uint64_t total = 0, totalp = 0;
+    for (int s = 0; s < L; s++)
+        if (GET_BIT(cols + n * W, s)) { total += cur[s]; totalp = addp(totalp, curp[s]); }
+    free(cur); free(nxt); free(curp); free(nxtp);
+    *out64 = total;
+    *outp = totalp;
 }
 
 /* The serial NFA parser of Fig. serialparser.  cols: (n+1) x W words.
- * scalars: [0] accepted, [1] number of trees mod 2^64. */
+ * scalars: [0] accepted, [1] number of trees mod 2^64, [2] number of trees
+ * mod 2^61 - 1. */
 int oracle_parse(const oracle_t *o, const unsigned char *x, uint64_t n,
                  uint64_t *cols, uint64_t *scalars) {
     int W = o->W;
@@ -552,7 +572,8 @@ int oracle_parse(const oracle_t *o, const unsigned char *x, uint64_t n,
     uint64_t acc = 0;
     for (int w = 0; w < W; w++) acc |= cols[n * W + w];
     scalars[0] = acc != 0;
-    scalars[1] = acc ? count_paths(o, x, n, cols) : 0;
+    scalars[1] = scalars[2] = 0;
+    if (acc) count_paths(o, x, n, cols, &scalars[1], &scalars[2]);
     free(tmp); free(nb);
     return 0;
 }
@@ -639,7 +660,8 @@ static int lazy_step(oracle_t *o, lazy_dfa *d, int id, int a, uint64_t *scratch)
  * are written (nwin windows of win_len columns starting at win_start[i]);
  * scalars as in oracle_parse.  The tree count uses the backward form of the
  * same path count: cntB_n = 1 on C_n, cntB_r[rho] = sum of cntB_{r+1}[sigma]
- * over arcs rho -> sigma inside the clean SLPF, result = sum over C_0. */
+ * over arcs rho -> sigma inside the clean SLPF, result = sum over C_0, kept
+ * modulo 2^64 and modulo 2^61 - 1. */
 int oracle_parse_dfa(oracle_t *o, const unsigned char *x, uint64_t n,
                      int nwin, const uint64_t *win_start, uint64_t win_len,
                      uint64_t *win_cols, uint64_t *scalars) {
@@ -651,10 +673,11 @@ int oracle_parse_dfa(oracle_t *o, const unsigned char *x, uint64_t n,
     fid[0] = lazy_find(fd, o->I);
     for (uint64_t r = 1; r <= n; r++) fid[r] = lazy_step(o, fd, fid[r - 1], x[r - 1], scratch);
     uint64_t *cnt = (uint64_t *)calloc(L, 8), *cnt2 = (uint64_t *)calloc(L, 8);
+    uint64_t *cntp = (uint64_t *)calloc(L, 8), *cnt2p = (uint64_t *)calloc(L, 8);
     uint64_t *col = (uint64_t *)malloc(8 * W), *ncol = (uint64_t *)malloc(8 * W);
     int bid = lazy_find(bd, o->F);
     int accepted = 0;
-    uint64_t total = 0;
+    uint64_t total = 0, totalp = 0;
     for (uint64_t r = n + 1; r-- > 0;) {
         if (r < n) bid = lazy_step(o, bd, bid, x[r], scratch);
         const uint64_t *fs = fd->sets + (size_t)fid[r] * W;
@@ -667,10 +690,10 @@ int oracle_parse_dfa(oracle_t *o, const unsigned char *x, uint64_t n,
                 memcpy(win_cols + ((size_t)i * win_len + (r - win_start[i])) * W, col, 8 * W);
         if (!accepted) continue;
         if (r == n) {
-            for (int s = 0; s < L; s++) cnt[s] = GET_BIT(col, s) ? 1 : 0;
+            for (int s = 0; s < L; s++) cnt[s] = cntp[s] = GET_BIT(col, s) ? 1 : 0;
         } else {
             for (int rho = 0; rho < L; rho++) {
-                cnt2[rho] = 0;
+                cnt2[rho] = cnt2p[rho] = 0;
                 if (!GET_BIT(col, rho) || o->seg_label[rho] != x[r]) continue;
                 const uint64_t *f = o->folseg + (size_t)rho * W;
                 for (int w = 0; w < W; w++) {
@@ -679,18 +702,22 @@ int oracle_parse_dfa(oracle_t *o, const unsigned char *x, uint64_t n,
                         int b = __builtin_ctzll(m);
                         m &= m - 1;
                         cnt2[rho] += cnt[w * 64 + b];
+                        cnt2p[rho] = addp(cnt2p[rho], cntp[w * 64 + b]);
                     }
                 }
             }
             uint64_t *t = cnt; cnt = cnt2; cnt2 = t;
+            t = cntp; cntp = cnt2p; cnt2p = t;
         }
         memcpy(ncol, col, 8 * W);
         if (r == 0)
-            for (int s = 0; s < L; s++) if (GET_BIT(col, s)) total += cnt[s];
+            for (int s = 0; s < L; s++)
+                if (GET_BIT(col, s)) { total += cnt[s]; totalp = addp(totalp, cntp[s]); }
     }
     scalars[0] = accepted;
     scalars[1] = accepted ? total : 0;
-    free(fid); free(cnt); free(cnt2); free(col); free(ncol); free(scratch);
+    scalars[2] = accepted ? totalp : 0;
+    free(fid); free(cnt); free(cnt2); free(cntp); free(cnt2p); free(col); free(ncol); free(scratch);
     return 0;
 }
 

@@ -17,7 +17,7 @@ import yaml
 import lst_brute
 from automata_props import column_unambiguous
 from gen import regen
-from oracle.oracle import Oracle, OracleError, STATUS_INF_AMBIG, STATUS_SYNTAX
+from oracle.oracle import P61, Oracle, OracleError, STATUS_INF_AMBIG, STATUS_SYNTAX
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -286,6 +286,7 @@ def test_oracle_equals_brute_force(seed):
         bcols, bcnt = lst_brute.clean_columns(pat, x)
         assert [set(o.segments[i] for i in c) for c in cols] == bcols, (pat, x)
         assert cnt == bcnt, (pat, x)
+        assert o.parse_full(x)[3] == bcnt % P61, (pat, x)
         assert acc == (bcnt > 0) == (py.fullmatch(x.decode()) is not None), (pat, x)
 
 
@@ -309,14 +310,40 @@ def test_count_is_two_to_the_ab_occurrences(pat):
     for _ in range(60):
         n = int(rng.integers(1, 40))
         x = bytes(rng.choice([97, 98], size=n).tolist())
-        _, acc, cnt = o.columns(x)
+        _, acc, cnt, cntp = o.parse_full(x)
         assert acc and cnt == (2 ** x.count(b"ab")) % (1 << 64)
-    x = b"ab" * 70                      # 2^70 wraps to 0 modulo 2^64
-    _, acc, cnt = o.columns(x)
-    assert acc and cnt == 0
+        assert cntp == pow(2, x.count(b"ab"), P61)
+    x = b"ab" * 70                      # 2^70 wraps to 0 modulo 2^64, to 2^9 modulo 2^61 - 1
+    _, acc, cnt, cntp = o.parse_full(x)
+    assert acc and cnt == 0 and cntp == 512
     x = b"ab" * 63 + b"a"
-    _, acc, cnt = o.columns(x)
-    assert acc and cnt == 2 ** 63
+    _, acc, cnt, cntp = o.parse_full(x)
+    assert acc and cnt == 2 ** 63 and cntp == 4
+
+
+def _fib(n):
+    a, b = 0, 1
+    for _ in range(n):
+        a, b = b, a + b
+    return a
+
+
+def test_count_closed_forms_both_moduli():
+    # (a|aa)* over a^n: the compositions of n into parts 1 and 2, F(n+1);
+    # ten equal alternatives under a star over a^n: 10^n.  Exact integers
+    # reduced modulo 2^64 and modulo 2^61 - 1 (sums past both moduli)
+    o = Oracle("(a|aa)*")
+    for n in (0, 1, 2, 3, 10, 92, 93, 94, 150, 300):
+        _, acc, cnt, cntp = o.parse_full(b"a" * n)
+        want = _fib(n + 1)
+        assert acc and cnt == want % (1 << 64) and cntp == want % P61, n
+    o = Oracle("(a|a|a|a|a|a|a|a|a|a)*")
+    for n in (0, 1, 5, 19, 20, 64, 100):
+        _, acc, cnt, cntp = o.parse_full(b"a" * n)
+        assert acc and cnt == pow(10, n, 1 << 64) and cntp == pow(10, n, P61), n
+    # rejected text: both counts zero
+    _, acc, cnt, cntp = o.parse_full(b"ab")
+    assert not acc and cnt == 0 and cntp == 0
 
 
 def test_unambiguous_counts_are_zero_or_one():
@@ -392,11 +419,11 @@ def test_dfa_parser_equals_nfa_parser(seed):
     x = textgen.sample_text(tree, seed, 2000).tobytes()
     if seed % 2:
         x = x[:len(x) // 2] + b"c" + x[len(x) // 2:]
-    cols, acc, cnt = o.parse(x)
+    cols, acc, cnt, cntp = o.parse_full(x)
     n = len(x)
     starts = [0, n // 3, max(n - 50, 0)]
-    win, acc2, cnt2 = o.parse_dfa(x, starts, 50)
-    assert acc == acc2 and cnt == cnt2
+    win, acc2, cnt2, cntp2 = o.parse_dfa_full(x, starts, 50)
+    assert acc == acc2 and cnt == cnt2 and cntp == cntp2
     for i, s in enumerate(starts):
         m = min(50, n + 1 - s)
         assert np.array_equal(win[i, :m], cols[s:s + m])
