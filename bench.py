@@ -74,7 +74,7 @@ def run_gpu(parser, text_np, steps, warmup, chunk_bytes, compact=False, flags=0)
     text = torch.from_numpy(text_np).to(dev)
     W = parser.W
     cols = torch.empty((n + 1,) if compact else (n + 1, W), dtype=torch.int64, device=dev)
-    sc = torch.empty(3, dtype=torch.int64, device=dev)
+    sc = torch.empty(4, dtype=torch.int64, device=dev)
     flags |= S.PARSE_COMPACT if compact else 0
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(S.NUM_PHASE_EVENTS)] for _ in range(steps)]
     for _ in range(warmup):
@@ -225,7 +225,7 @@ def run_batched(args):
     outs = []
     for _ in range(2):
         cbig = torch.zeros(ctot, dtype=torch.int64, device=dev)
-        sc = torch.zeros((len(texts), 3), dtype=torch.int64, device=dev)
+        sc = torch.zeros((len(texts), 4), dtype=torch.int64, device=dev)
         items = [(tbuf[o:o + n], n, cbig[c:c + (n + 1) * w], sc[k])
                  for k, (o, n, c, w) in enumerate(zip(toffs, ns, coffs, Ws))]
         outs.append((cbig, sc, items))

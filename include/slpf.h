@@ -108,6 +108,10 @@ typedef struct {
     uint32_t placement;          /* 0 = transition tables staged in LDS, 1 = read through L2 */
     uint32_t max_entries_next_byte;  /* longest entry list without the previous-byte filter
                                         (SLPF_PARSE_NEXT_BYTE_ENTRIES needs <= 64) */
+    uint32_t column_unambiguous; /* 1 when no forward state reachable from I and reverse state
+                                    reachable from F share two segments: every clean column of an
+                                    accepted text is then one segment and the text has one tree */
+    uint32_t reserved;
     uint64_t table_bytes;        /* device bytes of all tables */
 } slpf_parser_info;
 
@@ -185,10 +189,11 @@ slpf_status slpf_get_matches(const slpf_parser *p, const uint64_t *columns_dev, 
 /* -------------------------------------------------------------------- parse */
 
 enum {
-    SLPF_PARSE_NO_COUNT = 1u << 0,      /* skip the tree count (scalars[1] = 0, [2] = 2) */
+    SLPF_PARSE_NO_COUNT = 1u << 0,      /* skip the tree count (scalars[1] = [3] = 0, [2] = 2) */
     SLPF_PARSE_FORCE_L2 = 1u << 1,      /* read transition tables through L2 even if LDS fits */
     SLPF_PARSE_RECOGNIZE = 1u << 2,     /* recogniser only (Sect. 3.2: the forward reacher and joiner
-                                           decide membership): scalars[0] = accept, [1] = 0, [2] = 2;
+                                           decide membership): scalars[0] = accept, [1] = [3] = 0,
+                                           [2] = 2;
                                            no column is written (columns_dev may be NULL) */
     SLPF_PARSE_COMPACT = 1u << 3,       /* write the compact SLPF (App. SLPF optimization, SLPF
                                            encoding): column r as ONE word; see slpf_decode_compact.
@@ -227,14 +232,17 @@ typedef struct {
  * scalars_dev[0] = 1 if the text is in the language else 0;
  * scalars_dev[1] = number of syntax trees modulo 2^64 (the number of
  *                  accepting NFA runs, one per LST, Sect. 2.3.4);
- * scalars_dev[2] = 0 if scalars_dev[1] is valid, 1 if the count was not
- *                  computed because a clean column held more than 64
- *                  segments (it cannot: 64 is the entry-list limit of
- *                  slpf_compile, and every clean column lies in an entry
- *                  list), 2 if not requested (SLPF_PARSE_NO_COUNT), 3 on an
- *                  internal error (a join set missing from the tables).
- *                  The count is exact for every accepted text and does not
- *                  depend on the lane-chunk size or on batching.
+ * scalars_dev[2] = 0 if scalars_dev[1] and [3] are valid, 1 if the count
+ *                  was not computed (a run of ambiguous columns with a column
+ *                  of more than 1024 segments, or a run longer than 512
+ *                  columns cut into pieces where a column after its first
+ *                  piece holds more than 128 segments), 2 if not requested
+ *                  (SLPF_PARSE_NO_COUNT), 3 on an internal error (a join set
+ *                  missing from the tables);
+ * scalars_dev[3] = number of syntax trees modulo the prime 2^61 - 1 (a
+ *                  second check that does not vanish when the count is a
+ *                  multiple of 2^64).
+ * The count is the same for every lane-chunk size and with batching.
  * columns_dev must be 8-byte aligned; with 128-byte alignment every store
  * of the build covers whole cache lines.
  */
@@ -242,7 +250,7 @@ typedef struct {
     uint64_t *columns_dev;     /* device, capacity_bytes >= slpf_forest_bytes(p, n), or
                                   slpf_compact_bytes(n) with SLPF_PARSE_COMPACT */
     uint64_t capacity_bytes;
-    uint64_t *scalars_dev;     /* device, 3 words */
+    uint64_t *scalars_dev;     /* device, 4 words */
 } slpf_forest;
 
 /*

@@ -55,7 +55,7 @@ def _load():
         L.oracle_parse.argtypes = [vp, ctypes.c_char_p, ctypes.c_uint64, u64p, u64p]
         L.oracle_parse.restype = ctypes.c_int
         L.oracle_parse_dfa.argtypes = [vp, ctypes.c_char_p, ctypes.c_uint64, ctypes.c_int, u64p,
-                                       ctypes.c_uint64, u64p, u64p]
+                                       ctypes.c_uint64, u64p, u64p, ctypes.c_int]
         L.oracle_parse_dfa.restype = ctypes.c_int
         L.oracle_powerset.argtypes = [vp, ctypes.c_int, u64p, ctypes.c_int, i32p, ctypes.c_int,
                                       ctypes.c_int, u64p, i32p]
@@ -180,9 +180,10 @@ class Oracle:
         """DFA-lookup serial parser; returns (window columns [nwin, win_len, W], accepted, count mod 2^64)."""
         return self.parse_dfa_full(text, win_starts, win_len)[:3]
 
-    def parse_dfa_full(self, text, win_starts=(), win_len: int = 0):
+    def parse_dfa_full(self, text, win_starts=(), win_len: int = 0, count: bool = True):
         """DFA-lookup serial parser; returns (window columns [nwin, win_len, W],
-        accepted, count mod 2^64, count mod 2^61 - 1)."""
+        accepted, count mod 2^64, count mod 2^61 - 1).  count=False skips the
+        tree count (both counts 0): the windows and the accept flag only."""
         x = _bytes(text) if not isinstance(text, np.ndarray) else text
         if isinstance(x, np.ndarray):
             n = x.size
@@ -194,7 +195,7 @@ class Oracle:
         out = np.zeros((len(ws), max(win_len, 0), self.W), np.uint64)
         sc = np.zeros(3, np.uint64)
         st = self._L.oracle_parse_dfa(self._h, xp, n, len(ws), _u64(ws) if len(ws) else None,
-                                      win_len, _u64(out) if out.size else None, _u64(sc))
+                                      win_len, _u64(out) if out.size else None, _u64(sc), 1 if count else 0)
         if st != 0:
             raise MemoryError("oracle_parse_dfa failed")
         return out, bool(sc[0]), int(sc[1]), int(sc[2])

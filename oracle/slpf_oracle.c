@@ -661,10 +661,11 @@ static int lazy_step(oracle_t *o, lazy_dfa *d, int id, int a, uint64_t *scratch)
  * scalars as in oracle_parse.  The tree count uses the backward form of the
  * same path count: cntB_n = 1 on C_n, cntB_r[rho] = sum of cntB_{r+1}[sigma]
  * over arcs rho -> sigma inside the clean SLPF, result = sum over C_0, kept
- * modulo 2^64 and modulo 2^61 - 1. */
+ * modulo 2^64 and modulo 2^61 - 1.  With want_count = 0 the count is skipped
+ * (scalars[1] = scalars[2] = 0): only the windows and the accept flag. */
 int oracle_parse_dfa(oracle_t *o, const unsigned char *x, uint64_t n,
                      int nwin, const uint64_t *win_start, uint64_t win_len,
-                     uint64_t *win_cols, uint64_t *scalars) {
+                     uint64_t *win_cols, uint64_t *scalars, int want_count) {
     int W = o->W, L = o->nseg;
     lazy_dfa *fd = lazy_get(o, 0), *bd = lazy_get(o, 1);
     uint64_t *scratch = (uint64_t *)malloc(8 * W);
@@ -688,7 +689,7 @@ int oracle_parse_dfa(oracle_t *o, const unsigned char *x, uint64_t n,
         for (int i = 0; i < nwin; i++)
             if (r >= win_start[i] && r < win_start[i] + win_len)
                 memcpy(win_cols + ((size_t)i * win_len + (r - win_start[i])) * W, col, 8 * W);
-        if (!accepted) continue;
+        if (!accepted || !want_count) continue;
         if (r == n) {
             for (int s = 0; s < L; s++) cnt[s] = cntp[s] = GET_BIT(col, s) ? 1 : 0;
         } else {
@@ -715,8 +716,8 @@ int oracle_parse_dfa(oracle_t *o, const unsigned char *x, uint64_t n,
                 if (GET_BIT(col, s)) { total += cnt[s]; totalp = addp(totalp, cntp[s]); }
     }
     scalars[0] = accepted;
-    scalars[1] = accepted ? total : 0;
-    scalars[2] = accepted ? totalp : 0;
+    scalars[1] = accepted && want_count ? total : 0;
+    scalars[2] = accepted && want_count ? totalp : 0;
     free(fid); free(cnt); free(cnt2); free(cntp); free(cnt2p); free(col); free(ncol); free(scratch);
     return 0;
 }

@@ -54,7 +54,7 @@ class ParserInfo(ctypes.Structure):
     _fields_ = [(k, ctypes.c_uint32) for k in (
         "num_segments", "words_per_column", "num_initial", "num_final", "fwd_states", "rev_states",
         "dfa_states", "medfa_states", "rdfa_states", "rmedfa_states", "num_classes", "max_entries",
-        "placement", "max_entries_next_byte")] + [("table_bytes", ctypes.c_uint64)]
+        "placement", "max_entries_next_byte", "column_unambiguous", "reserved")] + [("table_bytes", ctypes.c_uint64)]
 
 
 class ParseOpts(ctypes.Structure):
@@ -65,6 +65,8 @@ class ParseOpts(ctypes.Structure):
                 ("reserved2", ctypes.c_uint32)]
 
 NUM_PHASE_EVENTS = 6
+# scalars of a parse: accepted, trees mod 2^64, count status, trees mod 2^61 - 1
+NUM_SCALARS = 4
 PHASES = ["reach", "join", "starts", "build", "count"]
 
 
@@ -175,6 +177,8 @@ class Info:
     max_entries: int
     placement: int
     max_entries_next_byte: int
+    column_unambiguous: int
+    reserved: int
     table_bytes: int
 
 
@@ -274,12 +278,12 @@ class Parser:
     def parse(self, text, chunk_bytes: int = 0, count: bool = True, force_l2: bool = False,
               trace: bool = False, stream=None, events=None, flags: int = 0):
         """Parse a uint8 device tensor; returns (columns [n+1, W] int64 view of uint64 words,
-        scalars [3]) on the device, plus the join trace if asked."""
+        scalars [4]) on the device, plus the join trace if asked."""
         import torch
         n = text.numel()
         dev = text.device
         cols = torch.empty((n + 1, self.W), dtype=torch.int64, device=dev)
-        sc = torch.empty(3, dtype=torch.int64, device=dev)
+        sc = torch.empty(NUM_SCALARS, dtype=torch.int64, device=dev)
         tr = None
         if trace:
             c = self.num_chunks(n, chunk_bytes)
@@ -291,11 +295,11 @@ class Parser:
     def parse_compact(self, text, chunk_bytes: int = 0, count: bool = True, force_l2: bool = False,
                       stream=None, events=None):
         """Parse into the compact SLPF: returns (columns [n+1] int64 view of one uint64 word
-        per column over its candidate list, scalars [3]) on the device."""
+        per column over its candidate list, scalars [4]) on the device."""
         import torch
         n = text.numel()
         cols = torch.empty(n + 1, dtype=torch.int64, device=text.device)
-        sc = torch.empty(3, dtype=torch.int64, device=text.device)
+        sc = torch.empty(NUM_SCALARS, dtype=torch.int64, device=text.device)
         flags = PARSE_COMPACT | (0 if count else PARSE_NO_COUNT) | (PARSE_FORCE_L2 if force_l2 else 0)
         self.parse_into(text, n, cols, sc, chunk_bytes, flags, None, stream, events)
         return cols, sc
@@ -335,9 +339,9 @@ class Parser:
 
     def recognize(self, text, chunk_bytes: int = 0, force_l2: bool = False, stream=None, events=None):
         """Recogniser mode (forward reach and join only): returns the scalars
-        tensor [3] on the device (accept, 0, 2); no SLPF is written."""
+        tensor [4] on the device (accept, 0, 2, 0); no SLPF is written."""
         import torch
-        sc = torch.empty(3, dtype=torch.int64, device=text.device)
+        sc = torch.empty(NUM_SCALARS, dtype=torch.int64, device=text.device)
         flags = PARSE_RECOGNIZE | (PARSE_FORCE_L2 if force_l2 else 0)
         self.parse_into(text, text.numel(), None, sc, chunk_bytes, flags, None, stream, events)
         return sc
@@ -395,7 +399,7 @@ class Parser:
     def parse_batch(self, texts, chunk_bytes: int = 0, count: bool = True, force_l2: bool = False,
                     stream=None, events=None):
         """Parse a list of uint8 device tensors in one job; returns a list of
-        (columns [n+1, W], scalars [3]) per text.  The columns of all texts are
+        (columns [n+1, W], scalars [4]) per text.  The columns of all texts are
         views of one allocation, each starting on a 256-byte boundary."""
         import torch
         if not texts:
@@ -407,7 +411,7 @@ class Parser:
             offs.append(tot)
             tot += ((t.numel() + 1) * W + 31) // 32 * 32
         big = torch.empty(max(tot, 1), dtype=torch.int64, device=dev)
-        sc = torch.empty((len(texts), 3), dtype=torch.int64, device=dev)
+        sc = torch.empty((len(texts), NUM_SCALARS), dtype=torch.int64, device=dev)
         out, items = [], []
         for k, t in enumerate(texts):
             n = t.numel()
@@ -482,14 +486,14 @@ class Server:
 
     def result_tensors(self, tag: int, n: int, W: int, device="cuda:0"):
         """Host copies (columns uint64 [n+1, W], or [n+1] compact words, and
-        scalars uint64 [3]) of a finished request."""
+        scalars uint64 [4]) of a finished request."""
         import numpy as np
         import torch
         cp, cap, sp = self.result(tag)
         if self.compact:
             W = 1
         cols = np.empty((n + 1) * W, np.uint64)
-        sc = np.empty(3, np.uint64)
+        sc = np.empty(NUM_SCALARS, np.uint64)
         torch.cuda.synchronize()
         _hip_copy_to_host(cols.ctypes.data, cp, cols.nbytes)
         _hip_copy_to_host(sc.ctypes.data, sp, sc.nbytes)

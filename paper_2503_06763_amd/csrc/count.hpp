@@ -1,0 +1,694 @@
+// Tree count of the SLPF parser: the number of syntax trees of every
+// accepted text modulo 2^64 and modulo the prime 2^61 - 1.
+//
+// A syntax tree is one accepting run of the parser NFA (Sect. 2.3.4), i.e.
+// one path through the clean SLPF that starts in column 0, ends in column n
+// and steps from a segment rho of column r-1 to a follower sigma of rho in
+// column r.  Every such path passes through the one segment of each singleton
+// column, and every segment of a clean column lies on some path, so all arcs
+// exist between a singleton column and its neighbours.  The count is
+// therefore the product, over the maximal runs of ambiguous columns (two or
+// more segments), of the number of paths that enter the run's first column
+// anywhere and leave its last column anywhere; the text start and end act as
+// singletons.
+//
+//   k_build          multiplies in the one-column runs inside a lane chunk
+//                    (such a run has as many paths as the column has
+//                    segments) and marks every other column of a run
+//                    (RunMarks);
+//   k_count_runs     one thread per lane chunk finds the marked runs that
+//                    start in it; a short run whose columns hold at most kTV
+//                    segments is counted by a vector walk in registers, the
+//                    chunk's other short runs go to k_count_defer, long runs
+//                    (more than Job::lshort columns) to the piece kernels;
+//   k_count_defer    one wavefront per deferred chunk walks its short runs
+//                    with the count vector in LDS, a segment a lane;
+//   k_count_pieces   a long run is cut at anchor columns, the leftmost
+//                    smallest column of each cell of Job::cell columns when
+//                    it holds at most kPieceR segments; one wavefront per
+//                    piece computes the path counts between its two anchors
+//                    (a matrix of at most kPieceR x kPieceR);
+//   k_count_chain    one wavefront per long run multiplies its pieces;
+//   k_text_scalars   one block per text multiplies the chunk products and the
+//                    long-run products.
+// Products and sums are taken modulo 2^64 and modulo 2^61 - 1 side by side.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace slpf {
+
+// ------------------------------------------------------ modular arithmetic
+
+__device__ inline uint64_t addp(uint64_t a, uint64_t b) {   // a, b < 2^61 - 1
+    const uint64_t s = a + b;
+    return s >= kP61 ? s - kP61 : s;
+}
+
+// a * b modulo 2^61 - 1 (a, b < 2^61): with 2^61 = 1, the 122-bit product
+// hi * 2^64 + lo folds to (lo mod 2^61) + (lo >> 61) + 8 hi.
+__device__ inline uint64_t mulp(uint64_t a, uint64_t b) {
+    const uint64_t lo = a * b, hi = __umul64hi(a, b);
+    uint64_t r = (lo & kP61) + ((lo >> 61) | (hi << 3));
+    r = (r & kP61) + (r >> 61);
+    return r >= kP61 ? r - kP61 : r;
+}
+
+struct Cnt {                 // a count modulo 2^64 and modulo 2^61 - 1
+    uint64_t a, p;
+};
+__device__ inline Cnt cmul(Cnt x, Cnt y) { return {x.a * y.a, mulp(x.p, y.p)}; }
+__device__ inline Cnt cadd(Cnt x, Cnt y) { return {x.a + y.a, addp(x.p, y.p)}; }
+
+// Sum over the wavefront of both moduli.
+__device__ inline Cnt wave_sum_cnt(Cnt x) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        x.a += shfl_xor_u64(x.a, off);
+        x.p = addp(x.p, shfl_xor_u64(x.p, off));
+    }
+    return x;
+}
+
+// Multiply text t's product of long-run counts by x; several wavefronts may
+// do it at once (both products are commutative).
+__device__ inline void tprod_mul(const Job &jb, uint32_t t, Cnt x) {
+    unsigned long long *pa = reinterpret_cast<unsigned long long *>(jb.tprod + 2ull * t);
+    unsigned long long *pp = pa + 1;
+    unsigned long long old = *pa, seen;
+    do {
+        seen = old;
+        old = atomicCAS(pa, seen, seen * x.a);
+    } while (old != seen);
+    old = *pp;
+    do {
+        seen = old;
+        old = atomicCAS(pp, seen, static_cast<unsigned long long>(mulp(seen, x.p)));
+    } while (old != seen);
+}
+
+// ------------------------------------------------------------ marked runs
+
+struct TextCols {
+    const uint64_t *out;     // the text's clean columns (W words each, or one compact word)
+    const uint8_t *text;
+    uint64_t n;
+    uint32_t t, c0;          // text index, its first lane chunk
+};
+
+__device__ inline TextCols text_cols(const Job &jb, uint32_t t) {
+    const TextRef tr = text_ref(jb, t);
+    return {tr.out, tr.text, tr.n, t, first_chunk(jb, t)};
+}
+
+// Marks of the 64-column window that holds column r < n (bit r % 64).
+__device__ inline uint64_t mark_word(const Job &jb, const TextCols &tc, uint64_t r) {
+    const uint64_t li = r / jb.s;
+    const uint32_t w = static_cast<uint32_t>((r - li * jb.s) >> 6);
+    return jb.amask[ck(jb, tc.c0 + static_cast<uint32_t>(li), w)];
+}
+
+__device__ inline bool marked(const Job &jb, const TextCols &tc, uint64_t r) {
+    if (r == tc.n) return (jb.aend[tc.t] & 1ull) != 0;
+    return ((mark_word(jb, tc, r) >> (r & 63)) & 1ull) != 0;
+}
+
+// Last column of the marked run that starts at r0.
+__device__ inline uint64_t run_end(const Job &jb, const TextCols &tc, uint64_t r0) {
+    uint64_t e = r0;
+    while (true) {
+        const uint64_t nx = e + 1;
+        if (nx > tc.n) break;
+        if (nx == tc.n) {
+            if (jb.aend[tc.t] & 1ull) e = nx;
+            break;
+        }
+        const uint32_t sh = static_cast<uint32_t>(nx & 63);
+        const uint64_t v = mark_word(jb, tc, nx) >> sh;
+        const uint32_t ones = ~v == 0 ? 64u : static_cast<uint32_t>(__builtin_ctzll(~v));
+        if (ones == 0) break;
+        e = nx + ones - 1;
+        // the run ends inside this word, unless it reaches column n - 1: the
+        // text-end column n has its mark outside the windows
+        if (sh + ones < 64 && e + 1 < tc.n) break;
+    }
+    return e;
+}
+
+// Calls f(r0) for the first column of every marked run that starts in lane
+// chunk i (columns lo .. hi-1, and n for the last chunk), in column order.
+template <class F>
+__device__ inline void for_run_starts(const Job &jb, const TextCols &tc, uint32_t i, const ChunkCtx &cx, F f) {
+    const uint32_t nwin = static_cast<uint32_t>((cx.hi - cx.lo + 63) / 64);
+    uint64_t carry = cx.li > 0 && marked(jb, tc, cx.lo - 1) ? 1ull : 0ull;
+    for (uint32_t w = 0; w < nwin; ++w) {
+        const uint64_t v = jb.amask[ck(jb, i, w)];
+        uint64_t st = v & ~((v << 1) | carry);
+        carry = v >> 63;
+        while (st) {
+            const uint32_t b = static_cast<uint32_t>(__builtin_ctzll(st));
+            st &= st - 1;
+            f(cx.lo + 64ull * w + b);
+        }
+    }
+    if (cx.last && (jb.aend[tc.t] & 1ull) && !marked(jb, tc, tc.n - 1)) f(tc.n);
+}
+
+// Calls f(k, segment) for the segments of column r in ascending order;
+// returns their number.  Compact columns: bit k of the word names the k-th
+// segment of the candidate list X[class(x_r), class(x_{r+1})].
+template <class F>
+__device__ inline uint32_t for_segments(const Tabs &tb, const Job &jb, const TextCols &tc, uint64_t r, F f) {
+    uint32_t k = 0;
+    if (jb.compact) {
+        const uint32_t p = r > 0 ? tb.classmap[tc.text[r - 1]] : tb.C;
+        const uint32_t q = r < tc.n ? tb.classmap[tc.text[r]] : tb.C;
+        const uint16_t *xl = tb.xlist + tb.xoff[p * tb.NL + q];
+        for (uint64_t m = tc.out[r]; m; m &= m - 1) f(k++, static_cast<uint32_t>(xl[__builtin_ctzll(m)]));
+    } else {
+        const uint64_t *cw = tc.out + r * tb.W;
+        for (uint32_t w = 0; w < tb.W; ++w)
+            for (uint64_t v = cw[w]; v; v &= v - 1) f(k++, w * 64 + static_cast<uint32_t>(__builtin_ctzll(v)));
+    }
+    return k;
+}
+
+__device__ inline uint32_t column_size(const Tabs &tb, const Job &jb, const TextCols &tc, uint64_t r) {
+    if (jb.compact) return static_cast<uint32_t>(__popcll(tc.out[r]));
+    const uint64_t *cw = tc.out + r * tb.W;
+    uint32_t m = 0;
+    for (uint32_t w = 0; w < tb.W; ++w) m += static_cast<uint32_t>(__popcll(cw[w]));
+    return m;
+}
+
+__device__ inline bool follows(const Tabs &tb, uint32_t rho, uint32_t sigma) {
+    return (tb.folseg[static_cast<uint64_t>(rho) * tb.W + (sigma >> 6)] >> (sigma & 63)) & 1ull;
+}
+
+// ------------------------------------------------------- short runs, lanes
+
+constexpr int kTV = 8;               // largest column of a run counted in registers
+
+// Paths through columns r0 .. r1 entering anywhere and leaving anywhere
+// (one lane); false when a column holds more than kTV segments.
+__device__ inline bool run_paths_lane(const Tabs &tb, const Job &jb, const TextCols &tc, uint64_t r0, uint64_t r1,
+                                      Cnt &out) {
+    uint32_t sp[kTV], sn[kTV];
+    uint64_t ya[kTV], yp[kTV];
+    const uint32_t mp0 = for_segments(tb, jb, tc, r0, [&](uint32_t k, uint32_t sg) {
+#pragma unroll
+        for (int j = 0; j < kTV; ++j)
+            if (static_cast<uint32_t>(j) == k) sp[j] = sg;
+    });
+    if (mp0 > static_cast<uint32_t>(kTV)) return false;
+    uint32_t mp = mp0;
+#pragma unroll
+    for (int j = 0; j < kTV; ++j) {
+        ya[j] = static_cast<uint32_t>(j) < mp ? 1ull : 0ull;
+        yp[j] = ya[j];
+    }
+    for (uint64_t r = r0 + 1; r <= r1; ++r) {
+        const uint32_t m = for_segments(tb, jb, tc, r, [&](uint32_t k, uint32_t sg) {
+#pragma unroll
+            for (int j = 0; j < kTV; ++j)
+                if (static_cast<uint32_t>(j) == k) sn[j] = sg;
+        });
+        if (m > static_cast<uint32_t>(kTV)) return false;
+        uint64_t za[kTV], zp[kTV];
+#pragma unroll
+        for (int k = 0; k < kTV; ++k) {
+            za[k] = 0;
+            zp[k] = 0;
+            if (static_cast<uint32_t>(k) < m) {
+#pragma unroll
+                for (int j = 0; j < kTV; ++j) {
+                    if (static_cast<uint32_t>(j) < mp && follows(tb, sp[j], sn[k])) {
+                        za[k] += ya[j];
+                        zp[k] = addp(zp[k], yp[j]);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kTV; ++k) {
+            ya[k] = za[k];
+            yp[k] = zp[k];
+            sp[k] = sn[k];
+        }
+        mp = m;
+    }
+    Cnt s{0, 0};
+#pragma unroll
+    for (int j = 0; j < kTV; ++j)
+        if (static_cast<uint32_t>(j) < mp) s = cadd(s, Cnt{ya[j], yp[j]});
+    out = s;
+    return true;
+}
+
+// A long run r0 .. r1 of text t: its record and one piece per anchor cell.
+// Cells are [k G, (k+1) G) with G = Job::cell; the cells whose start lies
+// strictly inside the run may hold an anchor, and piece j (j >= 1) starts at
+// the anchor of the j-th of them.
+__device__ inline void emit_long(const Job &jb, uint32_t t, uint64_t r0, uint64_t r1) {
+    const uint64_t G = jb.cell;
+    const uint64_t kf = r0 / G + 1, kl = (r1 - 1) / G;
+    const uint32_t nb = kl >= kf ? static_cast<uint32_t>(kl - kf + 1) : 0u;
+    const uint32_t npc = nb + 1;
+    const uint32_t ri = atomicAdd(&jb.ccnt[1], 1u);
+    if (ri >= jb.cap_runs) {
+        jb.tfail[t] = 1;
+        return;
+    }
+    const uint32_t pb = atomicAdd(&jb.ccnt[2], npc);
+    const uint32_t mb = npc > 1 ? atomicAdd(&jb.ccnt[3], npc) : 0u;
+    uint64_t *rr = jb.runs + 8ull * ri;
+    if (pb + static_cast<uint64_t>(npc) > jb.cap_pieces ||
+        (npc > 1 && mb + static_cast<uint64_t>(npc) > jb.cap_mats)) {
+        jb.tfail[t] = 1;
+        rr[4] = 0;                                   // no pieces: the chain kernel skips it
+        return;
+    }
+    rr[0] = t;
+    rr[1] = r0;
+    rr[2] = r1;
+    rr[3] = pb;
+    rr[4] = npc;
+    rr[5] = mb;
+    for (uint32_t j = 0; j < npc; ++j) jb.piece[pb + j] = static_cast<uint64_t>(ri) | (static_cast<uint64_t>(j) << 32);
+}
+
+constexpr int kRunThreads = 256;
+
+__global__ __launch_bounds__(kRunThreads) void k_count_runs(Tabs tb, Job jb) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= jb.c) return;
+    const ChunkCtx cx = chunk_ctx(jb, i);
+    if (cx.tr.scalars[0] == 0) return;                    // rejected: no tree
+    const TextCols tc = text_cols(jb, cx.t);
+    Cnt acc{1, 1};
+    bool defer = false;
+    for_run_starts(jb, tc, i, cx, [&](uint64_t r0) {
+        const uint64_t r1 = run_end(jb, tc, r0);
+        if (r1 - r0 + 1 > jb.lshort) {
+            emit_long(jb, cx.t, r0, r1);
+            return;
+        }
+        if (defer) return;
+        Cnt x;
+        if (run_paths_lane(tb, jb, tc, r0, r1, x)) acc = cmul(acc, x);
+        else defer = true;
+    });
+    if (defer) {
+        jb.dchunk[atomicAdd(&jb.ccnt[0], 1u)] = i;       // at most one entry per chunk
+    } else {
+        const Cnt f{jb.cfac[2ull * i], jb.cfac[2ull * i + 1]};
+        const Cnt g = cmul(f, acc);
+        jb.cfac[2ull * i] = g.a;
+        jb.cfac[2ull * i + 1] = g.p;
+    }
+}
+
+// ----------------------------------------------------- wavefront walks
+
+constexpr uint32_t kWalkLdsWords = 4096;   // count vectors: 2 buffers x segments x VB x 2 moduli
+
+template <int VB>
+struct WalkCap {
+    static constexpr uint32_t segs = kWalkLdsWords / (4 * VB);   // VB = 1: 1024, VB = 8: 128
+};
+
+struct WalkLds {
+    uint64_t colw[2][kMaxWords];
+    uint32_t pre[2][kMaxWords];
+    uint32_t m[2];
+    uint16_t seg[2][1024];
+    uint64_t y[kWalkLdsWords];
+};
+
+// One wavefront walks columns a .. e of a text: VB count vectors start on
+// column a (VB = 1: all ones; else unit vector v on the v-th segment of
+// column a, v < m(a)), and each step to column r gives segment sigma the sum
+// of the previous column's counts over the segments that sigma follows.  On
+// return the vectors over column e are in y[buf] (segment k, vector v,
+// modulus d at (k * VB + v) * 2 + d) with buf and m(e) returned; false when
+// a column holds more segments than the LDS holds.
+template <int VB>
+__device__ inline bool wave_walk(const Tabs &tb, const Job &jb, const TextCols &tc, uint64_t a, uint64_t e,
+                                 WalkLds &L, uint32_t &buf, uint32_t &m_end) {
+    constexpr uint32_t cap = WalkCap<VB>::segs;
+    const uint32_t lane = threadIdx.x, W = tb.W;
+    uint32_t cur = 0;
+    for (uint64_t r = a;; ++r) {
+        // the column's words
+        if (jb.compact) {
+            const uint32_t p = r > 0 ? tb.classmap[tc.text[r - 1]] : tb.C;
+            const uint32_t q = r < tc.n ? tb.classmap[tc.text[r]] : tb.C;
+            const uint16_t *xl = tb.xlist + tb.xoff[p * tb.NL + q];
+            const uint64_t cm = tc.out[r];
+            for (uint32_t w = lane; w < W; w += 64) {
+                uint64_t v = 0;
+                for (uint64_t x = cm; x; x &= x - 1) {
+                    const uint32_t sg = xl[__builtin_ctzll(x)];
+                    if ((sg >> 6) == w) v |= 1ull << (sg & 63);
+                }
+                L.colw[cur][w] = v;
+            }
+        } else {
+            for (uint32_t w = lane; w < W; w += 64) L.colw[cur][w] = tc.out[r * W + w];
+        }
+        wave_sync();
+        // segments before each word, and the segment list
+        uint32_t mt = 0;
+        for (uint32_t w = 0; w < W; ++w) {
+            if (lane == w) L.pre[cur][w] = mt;
+            mt += static_cast<uint32_t>(__popcll(L.colw[cur][w]));
+        }
+        if (mt > cap) return false;
+        for (uint32_t w = lane; w < W; w += 64) {
+            uint32_t k = L.pre[cur][w];
+            for (uint64_t v = L.colw[cur][w]; v; v &= v - 1) L.seg[cur][k++] = static_cast<uint16_t>(w * 64 + __builtin_ctzll(v));
+        }
+        wave_sync();
+        uint64_t *yc = L.y + cur * (kWalkLdsWords / 2);
+        const uint64_t *yq = L.y + (cur ^ 1u) * (kWalkLdsWords / 2);
+        const uint32_t prv = cur ^ 1u;
+        for (uint32_t k = lane; k < mt; k += 64) {
+            uint64_t za[VB], zp[VB];
+            if (r == a) {
+#pragma unroll
+                for (int v = 0; v < VB; ++v) {
+                    za[v] = VB == 1 ? 1ull : (k == static_cast<uint32_t>(v) ? 1ull : 0ull);
+                    zp[v] = za[v];
+                }
+            } else {
+#pragma unroll
+                for (int v = 0; v < VB; ++v) za[v] = zp[v] = 0;
+                const uint32_t sg = L.seg[cur][k];
+                for (uint32_t w = 0; w < W; ++w) {
+                    const uint64_t pw = L.colw[prv][w];
+                    uint64_t x = tb.predseg[static_cast<uint64_t>(sg) * W + w] & pw;
+                    while (x) {
+                        const uint32_t b = static_cast<uint32_t>(__builtin_ctzll(x));
+                        x &= x - 1;
+                        const uint32_t rk = L.pre[prv][w] + static_cast<uint32_t>(__popcll(pw & low_mask(b)));
+#pragma unroll
+                        for (int v = 0; v < VB; ++v) {
+                            za[v] += yq[(rk * VB + v) * 2];
+                            zp[v] = addp(zp[v], yq[(rk * VB + v) * 2 + 1]);
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int v = 0; v < VB; ++v) {
+                yc[(k * VB + v) * 2] = za[v];
+                yc[(k * VB + v) * 2 + 1] = zp[v];
+            }
+        }
+        wave_sync();
+        if (r == e) {
+            buf = cur;
+            m_end = mt;
+            return true;
+        }
+        cur ^= 1u;
+    }
+}
+
+// Sum of vector v over the segments of the last column of a walk.
+template <int VB>
+__device__ inline Cnt walk_sum(const WalkLds &L, uint32_t buf, uint32_t m, int v) {
+    const uint64_t *y = L.y + buf * (kWalkLdsWords / 2);
+    Cnt s{0, 0};
+    for (uint32_t k = threadIdx.x; k < m; k += 64) s = cadd(s, Cnt{y[(k * VB + v) * 2], y[(k * VB + v) * 2 + 1]});
+    return wave_sum_cnt(s);
+}
+
+// Deferred chunks: their short runs, one wavefront per chunk.
+__global__ __launch_bounds__(64) void k_count_defer(Tabs tb, Job jb) {
+    __shared__ WalkLds L;
+    for (uint32_t item = blockIdx.x; item < jb.ccnt[0]; item += gridDim.x) {
+        const uint32_t i = jb.dchunk[item];
+        const ChunkCtx cx = chunk_ctx(jb, i);
+        const TextCols tc = text_cols(jb, cx.t);
+        Cnt acc{1, 1};
+        bool ok = true;
+        for_run_starts(jb, tc, i, cx, [&](uint64_t r0) {
+            const uint64_t r1 = run_end(jb, tc, r0);
+            if (r1 - r0 + 1 > jb.lshort || !ok) return;    // long runs: the piece kernels'
+            uint32_t buf = 0, m = 0;
+            if (!wave_walk<1>(tb, jb, tc, r0, r1, L, buf, m)) {
+                ok = false;
+                return;
+            }
+            acc = cmul(acc, walk_sum<1>(L, buf, m, 0));
+        });
+        if (threadIdx.x == 0) {
+            const Cnt g = cmul(Cnt{jb.cfac[2ull * i], jb.cfac[2ull * i + 1]}, acc);
+            jb.cfac[2ull * i] = g.a;
+            jb.cfac[2ull * i + 1] = g.p;
+            if (!ok) jb.tfail[cx.t] = 1;
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------ long runs
+
+// Anchor of cell k of the run r0 .. r1: the leftmost column of the cell
+// (inside the run) with the fewest segments, if it holds at most kPieceR;
+// returns (size << 40) | column, or ~0 for none.
+__device__ inline uint64_t cell_anchor(const Tabs &tb, const Job &jb, const TextCols &tc, uint64_t r1, uint64_t k) {
+    const uint64_t c0 = k * jb.cell, c1 = min(c0 + jb.cell, r1);   // c0 > r0 for the cells asked
+    uint64_t best = ~0ull;
+    for (uint64_t r = c0 + threadIdx.x; r < c1; r += 64) {
+        const uint64_t key = (static_cast<uint64_t>(column_size(tb, jb, tc, r)) << 40) | r;
+        best = key < best ? key : best;
+    }
+    best = wave_min_u64(best);
+    return (best >> 40) <= static_cast<uint64_t>(kPieceR) ? best : ~0ull;
+}
+
+constexpr uint32_t kVoidPiece = 0xffffffffu;
+
+// One wavefront per piece: the path counts from its first column (all ones
+// for piece 0, else the unit vectors of its start anchor) to the next anchor
+// of the run (one row per start vector and one column per anchor segment),
+// or summed over the run's last column.  A one-piece run multiplies its
+// count into the text's product directly.
+__global__ __launch_bounds__(64) void k_count_pieces(Tabs tb, Job jb) {
+    __shared__ WalkLds L;
+    const uint32_t lane = threadIdx.x;
+    const uint32_t np = min(jb.ccnt[2], jb.cap_pieces);
+    for (uint32_t item = blockIdx.x; item < np; item += gridDim.x) {
+        const uint64_t pc = jb.piece[item];
+        const uint32_t ri = static_cast<uint32_t>(pc), j = static_cast<uint32_t>(pc >> 32);
+        const uint64_t *rr = jb.runs + 8ull * ri;
+        const uint32_t t = static_cast<uint32_t>(rr[0]);
+        const uint64_t r0 = rr[1], r1 = rr[2];
+        const uint32_t npc = static_cast<uint32_t>(rr[4]), mb = static_cast<uint32_t>(rr[5]);
+        const TextCols tc = text_cols(jb, t);
+        const uint64_t kf = r0 / jb.cell + 1;
+        uint64_t a = r0;
+        uint32_t ra = 1;
+        if (j > 0) {
+            const uint64_t an = cell_anchor(tb, jb, tc, r1, kf + j - 1);
+            if (an == ~0ull) {                            // no anchor: walked through by an earlier piece
+                if (lane == 0) jb.pmat[item] = kVoidPiece;
+                continue;
+            }
+            a = an & ((1ull << 40) - 1);
+            ra = static_cast<uint32_t>(an >> 40);
+        }
+        // the next anchor, or the run's end
+        uint64_t e = r1;
+        uint32_t re = 0;
+        for (uint64_t k = kf + j; k * jb.cell < r1; ++k) {
+            const uint64_t an = cell_anchor(tb, jb, tc, r1, k);
+            if (an != ~0ull) {
+                e = an & ((1ull << 40) - 1);
+                re = static_cast<uint32_t>(an >> 40);
+                break;
+            }
+        }
+        uint32_t buf = 0, m = 0;
+        bool ok;
+        Cnt res[kPieceR];
+        if (j == 0) ok = wave_walk<1>(tb, jb, tc, a, e, L, buf, m);
+        else ok = wave_walk<kPieceR>(tb, jb, tc, a, e, L, buf, m);
+        if (!ok) {
+            if (lane == 0) {
+                jb.tfail[t] = 1;
+                jb.pmat[item] = kVoidPiece;
+            }
+            __syncthreads();
+            continue;
+        }
+        const int vb = j == 0 ? 1 : kPieceR;
+        if (re == 0) {   // the run's end: sums over its last column
+            for (int v = 0; v < kPieceR; ++v) {
+                if (v >= static_cast<int>(ra)) break;
+                res[v] = vb == 1 ? walk_sum<1>(L, buf, m, v) : walk_sum<kPieceR>(L, buf, m, v);
+            }
+        }
+        if (npc == 1) {                                   // a single piece: the run's count
+            if (lane == 0) tprod_mul(jb, t, res[0]);
+        } else {
+            // matrix rows = start vectors (ra), columns = end segments (re, or 1 when summed)
+            uint64_t *M = jb.mats + (static_cast<uint64_t>(mb) + j) * kPieceR * kPieceR * 2;
+            const uint64_t *y = L.y + buf * (kWalkLdsWords / 2);
+            if (lane < static_cast<uint32_t>(kPieceR * kPieceR)) {
+                const uint32_t v = lane / kPieceR, k = lane % kPieceR;
+                uint64_t xa = 0, xp = 0;
+                if (v < ra) {
+                    if (re == 0) {
+                        if (k == 0) {
+                            // res[v] is wavefront-uniform
+                            for (uint32_t q = 0; q < static_cast<uint32_t>(kPieceR); ++q)
+                                if (q == v) {
+                                    xa = res[q].a;
+                                    xp = res[q].p;
+                                }
+                        }
+                    } else if (k < re) {
+                        xa = y[(k * vb + v) * 2];
+                        xp = y[(k * vb + v) * 2 + 1];
+                    }
+                }
+                M[(v * kPieceR + k) * 2] = xa;
+                M[(v * kPieceR + k) * 2 + 1] = xp;
+            }
+            if (lane == 0) jb.pmat[item] = ra | ((re == 0 ? 1u : re) << 8);
+        }
+        __syncthreads();
+    }
+}
+
+// One wavefront per long run of several pieces: the row vector of piece 0
+// times the matrices of the pieces that start at an anchor; the last one
+// sums over the run's end, leaving the run's count.
+__global__ __launch_bounds__(64) void k_count_chain(Job jb) {
+    const uint32_t lane = threadIdx.x;
+    const uint32_t nr = min(jb.ccnt[1], jb.cap_runs);
+    for (uint32_t ri = blockIdx.x; ri < nr; ri += gridDim.x) {
+        const uint64_t *rr = jb.runs + 8ull * ri;
+        const uint32_t npc = static_cast<uint32_t>(rr[4]);
+        if (npc < 2) continue;
+        const uint32_t t = static_cast<uint32_t>(rr[0]);
+        const uint32_t pb = static_cast<uint32_t>(rr[3]), mb = static_cast<uint32_t>(rr[5]);
+        // lane k < kPieceR holds entry k of the row vector
+        Cnt vk{0, 0};
+        uint32_t dim = 0;
+        bool ok = true;
+        for (uint32_t j = 0; j < npc; ++j) {
+            const uint32_t info = jb.pmat[pb + j];
+            if (info == kVoidPiece) {
+                if (j == 0) ok = false;
+                continue;
+            }
+            const uint32_t rows = info & 0xffu, cols = info >> 8;
+            const uint64_t *M = jb.mats + (static_cast<uint64_t>(mb) + j) * kPieceR * kPieceR * 2;
+            if (j == 0) {
+                vk = lane < cols ? Cnt{M[lane * 2], M[lane * 2 + 1]} : Cnt{0, 0};
+            } else {
+                if (rows != dim) ok = false;
+                Cnt s{0, 0};
+                for (uint32_t r = 0; r < rows; ++r) {
+                    const Cnt vr{readlane_u64(vk.a, static_cast<int>(r)), readlane_u64(vk.p, static_cast<int>(r))};
+                    if (lane < cols) s = cadd(s, cmul(vr, Cnt{M[(r * kPieceR + lane) * 2], M[(r * kPieceR + lane) * 2 + 1]}));
+                }
+                vk = lane < cols ? s : Cnt{0, 0};
+            }
+            dim = cols;
+        }
+        if (lane == 0) {
+            if (!ok || dim != 1) jb.tfail[t] = 1;
+            else tprod_mul(jb, t, vk);
+        }
+    }
+}
+
+// Per-text scalars: one block per text (count: 0 not requested, 1 requested,
+// 2 recogniser).  Empty text: column 0 = I & F and one tree per
+// initial-and-final segment.  Otherwise the count is the product of the
+// text's chunk products and long-run products (0 for a rejected text).
+// scalars[2]: 0 counted, 1 a run could not be counted, 2 not requested, 3 a
+// join set was not a table state.
+constexpr int kScalarThreads = 1024;
+
+__global__ __launch_bounds__(kScalarThreads) void k_text_scalars(Tabs tb, Job jb, int count) {
+    __shared__ uint64_t pa[kScalarThreads], pq[kScalarThreads];
+    const uint32_t t = blockIdx.x, th = threadIdx.x;
+    const TextRef tr = text_ref(jb, t);
+    if (count == 2) {   // recogniser: accept from the forward join alone
+        if (th == 0) {
+            uint64_t any = 0;
+            if (tr.n == 0) {
+                const uint64_t *fb = tb.fbits + static_cast<uint64_t>(tb.fstart) * tb.W;
+                const uint64_t *rb = tb.rbits + static_cast<uint64_t>(tb.rstart) * tb.W;
+                for (uint32_t w = 0; w < tb.W; ++w) any |= fb[w] & rb[w];
+            } else {
+                any = jb.fout[first_chunk(jb, t + 1) - 1];
+            }
+            tr.scalars[0] = any ? 1 : 0;
+            tr.scalars[1] = 0;
+            tr.scalars[2] = jb.flags[0] ? 3 : 2;
+            tr.scalars[3] = 0;
+        }
+        return;
+    }
+    if (tr.n == 0) {
+        if (th == 0) {
+            const uint64_t *fb = tb.fbits + static_cast<uint64_t>(tb.fstart) * tb.W;
+            const uint64_t *rb = tb.rbits + static_cast<uint64_t>(tb.rstart) * tb.W;
+            uint64_t any = 0, pc = 0, cm = 0;
+            for (uint32_t w = 0; w < tb.W; ++w) {
+                const uint64_t v = fb[w] & rb[w];
+                if (!jb.compact) tr.out[w] = v;
+                any |= v;
+                pc += __popcll(v);
+                for (uint64_t x = v; x; x &= x - 1)   // compact: ranks in X[start, end]
+                    cm |= 1ull << tb.rankx[tb.C * tb.nseg + w * 64 + static_cast<uint32_t>(__builtin_ctzll(x))];
+            }
+            if (jb.compact) tr.out[0] = cm;
+            tr.scalars[0] = any ? 1 : 0;
+            tr.scalars[1] = count ? pc : 0;
+            tr.scalars[2] = count ? 0 : 2;
+            tr.scalars[3] = count ? pc : 0;
+        }
+        return;
+    }
+    uint64_t st = 0, va = 0, vp = 0;
+    if (!count) {
+        st = 2;
+    } else if (tr.scalars[0] != 0) {
+        const uint32_t c0 = first_chunk(jb, t), c1 = first_chunk(jb, t + 1);
+        Cnt acc{1, 1};
+        for (uint32_t k = c0 + th; k < c1; k += blockDim.x) acc = cmul(acc, Cnt{jb.cfac[2ull * k], jb.cfac[2ull * k + 1]});
+        pa[th] = acc.a;
+        pq[th] = acc.p;
+        __syncthreads();
+        for (uint32_t h = kScalarThreads / 2; h; h >>= 1) {
+            if (th < h) {
+                pa[th] *= pa[th + h];
+                pq[th] = mulp(pq[th], pq[th + h]);
+            }
+            __syncthreads();
+        }
+        va = pa[0];
+        vp = pq[0];
+        if (!tb.col_single) {
+            va *= jb.tprod[2ull * t];
+            vp = mulp(vp, jb.tprod[2ull * t + 1]);
+            if (jb.tfail[t]) st = 1;
+        }
+    }
+    if (jb.flags[0]) st = 3;
+    if (th == 0) {
+        tr.scalars[1] = va;
+        tr.scalars[2] = st;
+        tr.scalars[3] = vp;
+    }
+}
+
+}  // namespace slpf

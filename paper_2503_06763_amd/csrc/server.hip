@@ -194,7 +194,7 @@ slpf_status slpf_server_submit(slpf_server *s, const slpf_parser *p, const uint8
     r.tag = tag;
     r.forest = (s->o.parse_flags & SLPF_PARSE_COMPACT) ? slpf_compact_bytes(n) : slpf_forest_bytes(p, n);
     if (r.forest == 0) return SLPF_E_ARG;
-    r.bytes = round_up(r.forest) + kAlign;        // columns, then the three scalars
+    r.bytes = round_up(r.forest) + kAlign;        // columns, then the four scalars
     if (r.bytes > s->arena_bytes) return SLPF_E_CAPACITY;
     s->queue.push_back(r);
     return SLPF_OK;

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "../../include/slpf.h"
+#include "count.hpp"
 #include "kernels.hpp"
 #include "slpf_internal.hpp"
 
@@ -19,6 +20,7 @@ namespace {
 using namespace slpf;
 
 constexpr size_t kLdsBudget = 96 * 1024;   // transition tables staged in LDS up to this size
+constexpr size_t kMaxPairTable = 4u << 20;  // largest table of clean-column sizes (bytes)
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -42,6 +44,7 @@ struct slpf_parser {
     uint32_t placement = 0;
     size_t lds_bytes = 0;
     bool host_only = false;
+    bool col_single = false;          // every clean column of an accepted text is one segment
     std::mutex mu;
     std::map<hipStream_t, Workspace> ws;   // per stream
 };
@@ -64,6 +67,38 @@ std::vector<uint16_t> sole_segments(const HostTable &t, uint32_t W) {
         if (cnt == 1) out[s] = static_cast<uint16_t>(seg);
     }
     return out;
+}
+
+// No clean column can hold two segments.  A clean column of an accepted
+// text is the intersection of the forward set of its prefix and the reverse
+// set of its suffix, i.e. of a state reachable from I in the forward table
+// and one reachable from F in the reverse table (the multi-entry states never
+// label a column), so only those pairs count.
+bool column_unambiguous(const HostAutomaton &A) {
+    auto reachable = [&](const HostTable &T) {
+        std::vector<uint32_t> out{T.start};
+        std::vector<uint8_t> seen(T.nstates, 0);
+        seen[T.start] = 1;
+        for (size_t k = 0; k < out.size(); ++k)
+            for (uint32_t c = 0; c < A.C; ++c) {
+                const uint32_t nx = T.delta[size_t(out[k]) * A.C + c];
+                if (!seen[nx]) {
+                    seen[nx] = 1;
+                    out.push_back(nx);
+                }
+            }
+        return out;
+    };
+    const std::vector<uint32_t> rf = reachable(A.fwd), rr = reachable(A.rev);
+    for (const uint32_t fs : rf)
+        for (const uint32_t bs : rr) {
+            uint32_t m = 0;
+            for (uint32_t w = 0; w < A.W; ++w)
+                m += static_cast<uint32_t>(__builtin_popcountll(A.fwd.bits[size_t(fs) * A.W + w] &
+                                                                A.rev.bits[size_t(bs) * A.W + w]));
+            if (m > 1) return false;
+        }
+    return true;
 }
 
 slpf_status upload(slpf_parser *p) {
@@ -97,6 +132,27 @@ slpf_status upload(slpf_parser *p) {
         return nz;
     };
     const std::vector<uint32_t> fnz = nonzero_words(A.fwd), rnz = nonzero_words(A.rev);
+    // tree count: sizes of the clean columns over pairs of a forward state
+    // reachable from I (ids 1 .. dfa_states: the powerset from I is built
+    // first) and a reverse state reachable from F; every (forward, backward)
+    // id pair of an accepted text's column is such a pair.  Kept when small.
+    uint32_t kfd = A.fwd.dfa_states + 1, krd = A.rev.dfa_states + 1;
+    if (size_t(kfd) * krd > kMaxPairTable) kfd = krd = 0;
+    std::vector<uint8_t> pairm(std::max<size_t>(size_t(kfd) * krd, 1), 0);
+    for (uint32_t f = 0; f < kfd; ++f)
+        for (uint32_t b = 0; b < krd; ++b) {
+            uint32_t m = 0;
+            for (uint32_t w = 0; w < A.W; ++w)
+                m += static_cast<uint32_t>(
+                    __builtin_popcountll(A.fwd.bits[size_t(f) * A.W + w] & A.rev.bits[size_t(b) * A.W + w]));
+            pairm[size_t(f) * krd + b] = static_cast<uint8_t>(std::min<uint32_t>(m, 255));
+        }
+    // the segments each segment follows (transpose of FolSeg)
+    std::vector<uint64_t> pred(size_t(A.nseg) * A.W, 0);
+    for (uint32_t r = 0; r < A.nseg; ++r)
+        for (uint32_t sg = 0; sg < A.nseg; ++sg)
+            if ((A.folseg[size_t(r) * A.W + (sg >> 6)] >> (sg & 63)) & 1ull)
+                pred[size_t(sg) * A.W + (r >> 6)] |= 1ull << (r & 63);
     struct Part {
         const void *src;
         size_t bytes;
@@ -126,6 +182,8 @@ slpf_status upload(slpf_parser *p) {
         {A.xoff_nb.data(), A.xoff_nb.size() * 4, 0},
         {A.xlist_nb.data(), std::max<size_t>(A.xlist_nb.size(), 1) * 2, 0},
         {A.gmask.data(), A.gmask.size() * 8, 0},
+        {pairm.data(), pairm.size(), 0},
+        {pred.data(), pred.size() * 8, 0},
     };
     size_t total = 0;
     for (auto &pt : parts) {
@@ -170,38 +228,11 @@ slpf_status upload(slpf_parser *p) {
     t.emax_nb = std::max<uint32_t>(A.max_entries_nb, 1);
     t.gmask = reinterpret_cast<const uint64_t *>(at(22));
     t.ngroups = A.ngroups;
-    // col_single: no clean column can hold two segments.  A clean column of an
-    // accepted text is the intersection of the forward set of its prefix and
-    // the reverse set of its suffix, i.e. of a state reachable from I in the
-    // forward table and one reachable from F in the reverse table (the
-    // multi-entry states never label a column), so only those pairs count.
-    auto reachable = [&](const HostTable &T) {
-        std::vector<uint32_t> out{T.start};
-        std::vector<uint8_t> seen(T.nstates, 0);
-        seen[T.start] = 1;
-        for (size_t k = 0; k < out.size(); ++k)
-            for (uint32_t c = 0; c < A.C; ++c) {
-                const uint32_t nx = T.delta[size_t(out[k]) * A.C + c];
-                if (!seen[nx]) {
-                    seen[nx] = 1;
-                    out.push_back(nx);
-                }
-            }
-        return out;
-    };
-    const std::vector<uint32_t> rf = reachable(A.fwd), rr = reachable(A.rev);
-    t.col_single = 1;
-    for (size_t x = 0; x < rf.size() && t.col_single; ++x)
-        for (const uint32_t bs : rr) {
-            uint32_t m = 0;
-            for (uint32_t w = 0; w < A.W; ++w)
-                m += static_cast<uint32_t>(__builtin_popcountll(A.fwd.bits[size_t(rf[x]) * A.W + w] &
-                                                                A.rev.bits[size_t(bs) * A.W + w]));
-            if (m > 1) {
-                t.col_single = 0;
-                break;
-            }
-        }
+    t.pairm = at(23);
+    t.kfd = kfd;
+    t.krd = krd;
+    t.predseg = reinterpret_cast<const uint64_t *>(at(24));
+    t.col_single = p->col_single ? 1u : 0u;
     t.fhmask = static_cast<uint32_t>(A.fwd.hash.size() - 1);
     t.rhmask = static_cast<uint32_t>(A.rev.hash.size() - 1);
     t.C = A.C;
@@ -234,7 +265,6 @@ void set_placement(slpf_parser *p) {
     p->placement = p->lds_bytes <= budget ? 0 : 1;
 }
 
-constexpr uint32_t kGenFolLds = 40 * 1024;   // LDS of the general count kernel with its follower table
 constexpr size_t kLdsPerCu = 160 * 1024;     // LDS of one compute unit (gfx950)
 
 uint64_t chunk_bytes_for(uint64_t n, const slpf_parse_opts *o) {
@@ -305,7 +335,10 @@ slpf_status slpf_compile(const char *re, size_t re_len, const slpf_compile_opts 
         st = SLPF_E_INTERNAL;
     }
     p->host_only = opts && (opts->flags & SLPF_COMPILE_HOST_ONLY);
-    if (st == SLPF_OK) set_placement(p);
+    if (st == SLPF_OK) {
+        set_placement(p);
+        p->col_single = column_unambiguous(p->A);
+    }
     if (st == SLPF_OK && !p->host_only) st = upload(p);
     if (st != SLPF_OK) {
         slpf_parser_destroy(p);
@@ -350,6 +383,7 @@ slpf_status slpf_parser_info_get(const slpf_parser *p, slpf_parser_info *info) {
     info->max_entries = A.max_entries;
     info->max_entries_next_byte = A.max_entries_nb;
     info->placement = p->placement;
+    info->column_unambiguous = p->col_single ? 1u : 0u;
     info->table_bytes = p->blob_bytes;
     return SLPF_OK;
 }
@@ -480,18 +514,33 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
             jpcst[d].push_back(l < TL ? L.add(N + 1) : -1);
             jpcv[d].push_back(l < TL ? L.add((N + 1) * 8) : -1);
         }
-    int idims = -1, iuv = -1, ipi = -1, ifac = -1, ikind = -1, iovf = -1, ichain = -1, igmat = -1, igin = -1, ipend = -1;
+    // tree count: run marks per 64-column window (as the checkpoints), chunk
+    // and text products, and the lists of the run kernels.  Long runs (more
+    // than lshort columns) are at most total / lshort; runs with a cell
+    // boundary inside are at most total / cell, and so are the anchors, which
+    // bounds the piece matrices.
+    const uint64_t cols_total = total + T;
+    uint64_t cell = 2048;
+    while (cell < cols_total / 32768) cell <<= 1;
+    const uint32_t lshort = 512;
+    const uint64_t cap_runs = cols_total / lshort + T + 1;
+    const uint64_t cap_mats = 2 * (cols_total / cell) + 2;
+    const uint64_t cap_pieces = cap_runs + cols_total / cell + 1;
+    if (count && (cap_runs > 0xffffffffull || cap_pieces > 0xffffffffull)) return SLPF_E_ARG;
+    int iam = -1, iaend = -1, icfac = -1, itprod = -1, itfail = -1, iccnt = -1, idch = -1, iruns = -1, ipiece = -1,
+        imats = -1, ipmat = -1;
     if (count) {
-        idims = L.add(size_t(c) * 2);
-        iuv = L.add(size_t(c) * 2 * kVec * 8);
-        ipi = L.add(size_t(c) * 8);
-        ifac = L.add(size_t(c + T) * 8);
-        ikind = L.add(size_t(c) * 4);
-        iovf = L.add(size_t(c) * 4);
-        ichain = L.add(size_t(c) * 4);
-        igmat = L.add(size_t(c) * kGenR * kGenR * 8);
-        igin = L.add(size_t(c) * kGenR * 8);
-        ipend = L.add(size_t(c) * 4);
+        iam = L.add(nck * 8);
+        iaend = L.add(size_t(T) * 8);
+        icfac = L.add(size_t(c) * 16);
+        itprod = L.add(size_t(T) * 16);
+        itfail = L.add(size_t(T) * 4);
+        iccnt = L.add(16);
+        idch = L.add(size_t(c) * 4);
+        iruns = L.add(cap_runs * 64);
+        ipiece = L.add(cap_pieces * 8);
+        imats = L.add(cap_mats * kPieceR * kPieceR * 16);
+        ipmat = L.add(cap_pieces * 4);
     }
 
     uint8_t *base;
@@ -565,17 +614,24 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
     jb.flags = reinterpret_cast<uint32_t *>(ptr(iflags));
     jb.trace = nullptr;
     if (T == 1 && opts && opts->trace_dev && opts->trace_bytes >= 2ull * (c + 1) * W * 8) jb.trace = opts->trace_dev;
+    jb.count_on = count ? 1u : 0u;
     if (count) {
-        jb.dims = ptr(idims);
-        jb.uv = reinterpret_cast<uint64_t *>(ptr(iuv));
-        jb.pi = reinterpret_cast<uint64_t *>(ptr(ipi));
-        jb.factor = reinterpret_cast<uint64_t *>(ptr(ifac));
-        jb.kind = reinterpret_cast<uint32_t *>(ptr(ikind));
-        jb.ovf = reinterpret_cast<uint32_t *>(ptr(iovf));
-        jb.chains = reinterpret_cast<uint32_t *>(ptr(ichain));
-        jb.gmat = reinterpret_cast<uint64_t *>(ptr(igmat));
-        jb.gin = reinterpret_cast<uint64_t *>(ptr(igin));
-        jb.pend = reinterpret_cast<uint32_t *>(ptr(ipend));
+        jb.amask = reinterpret_cast<uint64_t *>(ptr(iam));
+        jb.aend = reinterpret_cast<uint64_t *>(ptr(iaend));
+        jb.cfac = reinterpret_cast<uint64_t *>(ptr(icfac));
+        jb.tprod = reinterpret_cast<uint64_t *>(ptr(itprod));
+        jb.tfail = reinterpret_cast<uint32_t *>(ptr(itfail));
+        jb.ccnt = reinterpret_cast<uint32_t *>(ptr(iccnt));
+        jb.dchunk = reinterpret_cast<uint32_t *>(ptr(idch));
+        jb.runs = reinterpret_cast<uint64_t *>(ptr(iruns));
+        jb.piece = reinterpret_cast<uint64_t *>(ptr(ipiece));
+        jb.mats = reinterpret_cast<uint64_t *>(ptr(imats));
+        jb.pmat = reinterpret_cast<uint32_t *>(ptr(ipmat));
+        jb.cap_runs = static_cast<uint32_t>(cap_runs);
+        jb.cap_pieces = static_cast<uint32_t>(cap_pieces);
+        jb.cap_mats = static_cast<uint32_t>(std::min<uint64_t>(cap_mats, 0xffffffffull));
+        jb.lshort = lshort;
+        jb.cell = cell;
     }
 
     const bool timed = opts && opts->events && opts->num_events >= SLPF_NUM_PHASE_EVENTS;
@@ -677,7 +733,13 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
         const bool rank_fits = tabs_end + rank_bytes <= p->lds_limit &&
                                kLdsPerCu / (tabs_end + rank_bytes) == kLdsPerCu / tabs_end;
         jb.rank_lds = jb.compact && lds && rank_fits ? static_cast<uint32_t>(tabs_end) : 0u;
-        const size_t bld_lds = tabs_end + (jb.rank_lds ? rank_bytes : 0);
+        size_t bld_lds = tabs_end + (jb.rank_lds ? rank_bytes : 0);
+        // tree count: the pair table after them, on the same terms
+        const size_t pair_bytes = (size_t(tb.kfd) * tb.krd + 15) & ~size_t(15);
+        const bool pair_fits = pair_bytes && bld_lds + pair_bytes <= p->lds_limit &&
+                               kLdsPerCu / (bld_lds + pair_bytes) == kLdsPerCu / bld_lds;
+        jb.pair_lds = count && !tb.col_single && lds && pair_fits ? static_cast<uint32_t>(bld_lds) : 0u;
+        if (jb.pair_lds) bld_lds += pair_bytes;
         auto launch = [&](auto compact) {
             constexpr bool CM = decltype(compact)::value;
             if (fit_bits)
@@ -694,56 +756,15 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
         else launch(std::false_type{});
     }
     mark(4);
-    // tree count
-    if (count && c) {
-        // the count kernels keep per-lane rows and count vectors in LDS and stage
-        // the tables there too when they fit (all of them, or the transition and
-        // sole-segment tables only).  Narrow columns (W <= 2): the sparse-arc
-        // kernel; wider ones: the segment-list kernel (more lanes per CU)
-        if (W <= 2) {
-            const CountLds co = count_lds(tb.nf, tb.nr, tb.C, W, tb.nseg);
-            const uint32_t cblocks = (c + kCountThreads - 1) / kCountThreads;
-            // an RE whose clean columns are all singletons: one path per chunk
-            if (tb.col_single)
-                hipLaunchKernelGGL(k_count_single, dim3((c + kSingleThreads - 1) / kSingleThreads),
-                                   dim3(kSingleThreads), 0, stream, jb);
-            if (lds && co.end <= p->lds_limit)
-                hipLaunchKernelGGL((k_count_fast<true, true>), dim3(cblocks), dim3(kCountThreads), co.end, stream,
-                                   tb, jb);
-            else if (lds && co.bits <= p->lds_limit)
-                hipLaunchKernelGGL((k_count_fast<true, false>), dim3(cblocks), dim3(kCountThreads), co.bits, stream,
-                                   tb, jb);
-            else
-                hipLaunchKernelGGL((k_count_fast<false, false>), dim3(cblocks), dim3(kCountThreads), kCountLdsBytes,
-                                   stream, tb, jb);
-        } else {
-            const ListLds co = list_lds(tb.nf, tb.nr, tb.C, W, tb.nseg);
-            const uint32_t cblocks = (c + kListThreads - 1) / kListThreads;
-            if (tb.col_single)
-                hipLaunchKernelGGL(k_count_single, dim3((c + kSingleThreads - 1) / kSingleThreads),
-                                   dim3(kSingleThreads), 0, stream, jb);
-            if (lds && co.end <= p->lds_limit)
-                hipLaunchKernelGGL((k_count_list<true, true>), dim3(cblocks), dim3(kListThreads), co.end, stream, tb,
-                                   jb);
-            else if (lds && co.bits <= p->lds_limit)
-                hipLaunchKernelGGL((k_count_list<true, false>), dim3(cblocks), dim3(kListThreads), co.bits, stream,
-                                   tb, jb);
-            else
-                hipLaunchKernelGGL((k_count_list<false, false>), dim3(cblocks), dim3(kListThreads), kListLdsBytes,
-                                   stream, tb, jb);
-        }
-        // general chunks (their number is known on the device only): one
-        // wavefront each over a grid that loops, the follower table in LDS
-        // when it is small
-        const GenLds go = gen_lds(W, tb.nseg, true);
-        const uint32_t gblocks = std::min<uint32_t>(c, 2048);
-        if (lds && go.end <= kGenFolLds)
-            hipLaunchKernelGGL(k_count_general<true>, dim3(gblocks), dim3(64), go.end, stream, tb, jb);
-        else
-            hipLaunchKernelGGL(k_count_general<false>, dim3(gblocks), dim3(64), gen_lds(W, tb.nseg, false).end,
-                               stream, tb, jb);
-        hipLaunchKernelGGL(k_count_piece, dim3((c + 63) / 64), dim3(64), 0, stream, jb);
-        hipLaunchKernelGGL(k_count_factor, dim3((c + nt + 255) / 256), dim3(256), 0, stream, jb);
+    // tree count: the marked runs (k_build marked them and multiplied in the
+    // one-column runs).  The deferred chunks, pieces and long runs are known on
+    // the device only: their kernels loop over grids of a fixed size.
+    if (count && c && !tb.col_single) {
+        hipLaunchKernelGGL(k_count_runs, dim3((c + kRunThreads - 1) / kRunThreads), dim3(kRunThreads), 0, stream, tb,
+                           jb);
+        const uint32_t wgrid = std::min<uint32_t>(c, 2048);
+        hipLaunchKernelGGL(k_count_defer, dim3(wgrid), dim3(64), 0, stream, tb, jb);
+        hipLaunchKernelGGL(k_count_pieces, dim3(wgrid), dim3(64), 0, stream, tb, jb);
         hipLaunchKernelGGL(k_count_chain, dim3(std::min<uint32_t>(c, 1024)), dim3(64), 0, stream, jb);
     }
     hipLaunchKernelGGL(k_text_scalars, dim3(nt), dim3(kScalarThreads), 0, stream, tb, jb, recog ? 2 : count ? 1 : 0);

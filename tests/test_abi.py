@@ -115,3 +115,27 @@ def test_forest_bytes_and_chunks():
     assert p.num_chunks(65536, 8192) == 8
     assert p.num_chunks(65537, 8192) == 9
     assert p.num_chunks(0, 8192) == 0
+
+
+def test_column_unambiguous_flag_matches_oracle():
+    # the library skips the count walk for REs whose clean columns are always
+    # single segments; its flag must equal the property read off the
+    # oracle's own automata, for random tiny REs and for known ambiguous ones
+    import importlib
+    ap = importlib.import_module("automata_props")
+    rng = np.random.default_rng(77)
+    pats = ["(a|ab|b)*", "(a|b|ab)+", "(a|aa)*", "(ab|a)*", "(ab|cd)*e", "x(yz)*"]
+    while len(pats) < 46:
+        try:
+            tree = regen.random_re(int(rng.integers(1 << 30)), n_ops=int(rng.integers(3, 9)),
+                                   max_depth=int(rng.integers(3, 5)), alphabet=b"abc")
+        except RuntimeError:       # no RE of that shape for the seed
+            continue
+        pats.append(regen.to_re(tree).decode())
+    seen = set()
+    for pat in pats:
+        p = S.Parser(pat, host_only=True)
+        want = ap.column_unambiguous(Oracle(pat))
+        assert p.info.column_unambiguous == int(want), pat
+        seen.add(want)
+    assert seen == {True, False}

@@ -14,7 +14,7 @@ import pytest
 
 from gen import regen, textgen
 from gpu_util import device, gpu_parse, to_device
-from oracle.oracle import Oracle
+from oracle.oracle import P61, Oracle
 
 S = pytest.importorskip("paper_2503_06763_amd")
 pytestmark = pytest.mark.gpu
@@ -33,7 +33,7 @@ def run_batch(p, texts, chunk_bytes=0, count=True, force_l2=False):
     out = []
     for cols, sc in res:
         s = sc.cpu().numpy().view(np.uint64)
-        out.append((cols.cpu().numpy().view(np.uint64), bool(s[0]), int(s[1]), int(s[2])))
+        out.append((cols.cpu().numpy().view(np.uint64), bool(s[0]), int(s[1]), int(s[2]), int(s[3])))
     return out
 
 
@@ -70,13 +70,12 @@ def check_batch(pat, texts, chunk_bytes=0, force_l2=False, oracle=True):
         assert b[0].shape == alone[0].shape, j
         bad = np.nonzero((b[0] != alone[0]).any(axis=1))[0]
         assert bad.size == 0, "text %d (n=%d): column %d differs from the single parse" % (j, len(t), bad[0])
-        assert b[1:] == alone[1:], (j, b[1:], alone[1:])
+        assert b[1:] == alone[1:] + (alone.countp,), (j, b[1:], alone[1:], alone.countp)
         if o is not None:
-            cols, acc, cnt = o.parse(t)
+            cols, acc, cnt, cntp = o.parse_full(t)
             assert np.array_equal(b[0], cols), j
             assert b[1] == acc, j
-            if b[3] == 0:
-                assert b[2] == cnt, j
+            assert b[3] == 0 and b[2] == cnt and b[4] == cntp, (j, b[2:], cnt, cntp)
     return got
 
 
@@ -121,6 +120,7 @@ def test_batch_count_without_anchor():
     assert [g[3] for g in got] == [0, 0, 0, 0, 0]
     assert got[0][2] == 1 and got[3][2] == 1
     assert got[1][2] == 0 and got[4][2] == pow(20, 21, 1 << 64)
+    assert got[1][4] == pow(20, 64 * 2100, P61) and got[4][4] == pow(20, 21, P61)
 
 
 def test_batch_deep_join_scan():
@@ -148,7 +148,7 @@ def test_batch_argument_errors():
     p = S.Parser("(ab|a)*")
     t = to_device(b"abab" * 8)
     cols = torch.empty((33, p.W), dtype=torch.int64, device=dev)
-    sc = torch.empty(3, dtype=torch.int64, device=dev)
+    sc = torch.empty(4, dtype=torch.int64, device=dev)
     small = torch.empty((3, p.W), dtype=torch.int64, device=dev)
     with pytest.raises(S.SlpfError) as e:
         p.parse_batch_into([(t, 32, cols, sc), (t, 32, small, sc)])
@@ -189,10 +189,10 @@ def test_batched_re_family_vs_oracle():
         p, o = S.Parser(pat), Oracle(pat)
         got = run_batch(p, mine)
         for t, g in zip(mine, got):
-            cols, acc, cnt = o.parse(t)
+            cols, acc, cnt, cntp = o.parse_full(t)
             assert acc and g[1], name                    # sampled from the language
             assert np.array_equal(g[0], cols), name
-            assert g[3] == 0 and g[2] == cnt, (name, g[2:], cnt)
+            assert g[3] == 0 and g[2] == cnt and g[4] == cntp, (name, g[2:], cnt, cntp)
     torch.cuda.synchronize()
 
 
@@ -205,7 +205,7 @@ def test_tune_picks_a_candidate_and_keeps_results_exact():
     p, o = S.Parser(pat), Oracle(pat)
     dts = [to_device(t) for t in texts]
     cols = [torch.zeros((len(t) + 1, p.W), dtype=torch.int64, device=dev) for t in texts]
-    sc = torch.zeros((len(texts), 3), dtype=torch.int64, device=dev)
+    sc = torch.zeros((len(texts), 4), dtype=torch.int64, device=dev)
     items = [(d, len(t), c, sc[k]) for k, (d, t, c) in enumerate(zip(dts, texts, cols))]
     chunk, flags, ms = p.tune(items)
     say("tuned", chunk, flags, ms)
@@ -214,8 +214,7 @@ def test_tune_picks_a_candidate_and_keeps_results_exact():
     torch.cuda.synchronize()
     s = sc.cpu().numpy().view(np.uint64)
     for k, t in enumerate(texts):
-        c, acc, cnt = o.parse(t)
+        c, acc, cnt, cntp = o.parse_full(t)
         assert np.array_equal(cols[k].cpu().numpy().view(np.uint64), c), k
         assert bool(s[k, 0]) == acc
-        if s[k, 2] == 0:
-            assert int(s[k, 1]) == cnt
+        assert int(s[k, 2]) == 0 and int(s[k, 1]) == cnt and int(s[k, 3]) == cntp, k

@@ -31,21 +31,21 @@ def gpu_compact(p, text, chunk_bytes=0, count=True, force_l2=False):
     torch.cuda.synchronize()
     s = sc.cpu().numpy().view(np.uint64)
     return (cmp.cpu().numpy().view(np.uint64), dec.cpu().numpy().view(np.uint64),
-            bool(s[0]), int(s[1]), int(s[2]))
+            bool(s[0]), int(s[1]), int(s[2]), int(s[3]))
 
 
 def check(pat, texts, chunks=(0, 64, 256), force_l2=False):
     p, o = S.Parser(pat), Oracle(pat)
     for t in texts:
-        cols, acc, cnt = o.parse(t)
+        cols, acc, cnt, cntp = o.parse_full(t)
         want = o.compact(t, cols)
         for k in chunks:
-            cmp, dec, a2, c2, st = gpu_compact(p, t, chunk_bytes=k, force_l2=force_l2)
+            cmp, dec, a2, c2, st, c2p = gpu_compact(p, t, chunk_bytes=k, force_l2=force_l2)
             bad = np.nonzero(cmp != want)[0]
             assert bad.size == 0, "n=%d k=%d: word %d is %x, oracle %x" % (len(t), k, bad[0], cmp[bad[0]],
                                                                           want[bad[0]])
             assert np.array_equal(dec, cols), (len(t), k)
-            assert a2 == acc and st == 0 and c2 == cnt, (len(t), k, a2, c2, st, cnt)
+            assert a2 == acc and st == 0 and c2 == cnt and c2p == cntp, (len(t), k, a2, c2, st, cnt, c2p, cntp)
     return p
 
 
@@ -106,16 +106,16 @@ def test_compact_batch_equals_alone():
     texts = _texts(tree, 11, 30, 30000)
     dts = [to_device(t) for t in texts]
     cols = [torch.empty(len(t) + 1, dtype=torch.int64, device=dev) for t in texts]
-    sc = torch.empty((len(texts), 3), dtype=torch.int64, device=dev)
+    sc = torch.empty((len(texts), 4), dtype=torch.int64, device=dev)
     items = [(d, len(t), c, sc[k]) for k, (d, t, c) in enumerate(zip(dts, texts, cols))]
     for k in (0, 64):
         p.parse_batch_into(items, chunk_bytes=k, flags=S.PARSE_COMPACT)
         torch.cuda.synchronize()
         s = sc.cpu().numpy().view(np.uint64)
         for j, t in enumerate(texts):
-            cmp, dec, a2, c2, st = gpu_compact(p, t, chunk_bytes=k)
+            cmp, dec, a2, c2, st, c2p = gpu_compact(p, t, chunk_bytes=k)
             assert np.array_equal(cols[j].cpu().numpy().view(np.uint64), cmp), (k, j)
-            assert (bool(s[j, 0]), int(s[j, 1]), int(s[j, 2])) == (a2, c2, st)
+            assert (bool(s[j, 0]), int(s[j, 1]), int(s[j, 2]), int(s[j, 3])) == (a2, c2, st, c2p)
             want = o.compact(t)
             assert np.array_equal(cmp, want), (k, j)
 
@@ -125,7 +125,7 @@ def test_compact_capacity_and_arguments():
     dev = device()
     p = S.Parser("(ab|a)*")
     t = to_device(b"abab" * 8)
-    sc = torch.empty(3, dtype=torch.int64, device=dev)
+    sc = torch.empty(4, dtype=torch.int64, device=dev)
     ok = torch.empty(33, dtype=torch.int64, device=dev)
     small = torch.empty(32, dtype=torch.int64, device=dev)
     with pytest.raises(S.SlpfError) as e:

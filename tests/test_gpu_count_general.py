@@ -11,7 +11,7 @@ import pytest
 
 from automata_props import column_unambiguous
 from gpu_util import device, gpu_parse, to_device
-from oracle.oracle import Oracle
+from oracle.oracle import P61, Oracle
 
 S = pytest.importorskip("paper_2503_06763_amd")
 pytestmark = pytest.mark.gpu
@@ -24,11 +24,11 @@ def say(*a):
     sys.stdout.flush()
 
 
-def fib_mod(n):
-    """F(n) modulo 2^64 with F(1) = F(2) = 1."""
+def fib_mod(n, m=1 << 64):
+    """F(n) modulo m with F(1) = F(2) = 1."""
     a, b = 0, 1
     for _ in range(n):
-        a, b = b, (a + b) & M64
+        a, b = b, (a + b) % m
     return a
 
 
@@ -41,9 +41,11 @@ def test_rank2_columns_closed_form():
     for n in (1, 2, 63, 64, 65, 1000, 4097, 20000):
         text = b"a" * n
         for k in (64, 256, 0):
-            cols, acc, cnt, st = gpu_parse(p, text, chunk_bytes=k)
+            g = gpu_parse(p, text, chunk_bytes=k)
+            cols, acc, cnt, st = g
             assert acc and st == 0, (n, k, st)
             assert cnt == fib_mod(n + 1), (n, k, cnt)
+            assert g.countp == fib_mod(n + 1, P61), (n, k, g.countp)
     say("rank-2 chains ok")
 
 
@@ -72,14 +74,15 @@ def test_mixed_runs_vs_oracle_and_chunking():
     texts = [_blocks(rng, blocks, int(rng.integers(1, 12000))) for _ in range(10)]
     texts += [b"a" * 5000, b"b" * 3 + b"a" * 3000 + b"b", b"c" * 3000 + b"a" * 700 + b"d" * 900]
     for t in texts:
-        _, acc, want = o.parse(t)
+        _, acc, want, wantp = o.parse_full(t)
         assert acc
         got = set()
         for k in (64, 128, 512, 0):
-            cols, a2, cnt, st = gpu_parse(p, t, chunk_bytes=k)
+            g = gpu_parse(p, t, chunk_bytes=k)
+            cols, a2, cnt, st = g
             assert a2 and st == 0, (len(t), k, st)
-            assert cnt == want, (len(t), k, cnt, want)
-            got.add(cnt)
+            assert cnt == want and g.countp == wantp, (len(t), k, cnt, want, g.countp, wantp)
+            got.add((cnt, g.countp))
         assert len(got) == 1
     say("mixed runs ok:", len(texts), "texts")
 
@@ -99,8 +102,8 @@ def test_general_chunks_batched_equal_alone():
             s = sc.cpu().numpy().view(np.uint64)
             alone = gpu_parse(p, t, chunk_bytes=k)
             assert np.array_equal(cols.cpu().numpy().view(np.uint64), alone[0])
-            assert (bool(s[0]), int(s[1]), int(s[2])) == alone[1:]
-            assert int(s[2]) == 0 and int(s[1]) == o.parse(t)[2]
+            assert (bool(s[0]), int(s[1]), int(s[2]), int(s[3])) == alone[1:] + (alone.countp,)
+            assert int(s[2]) == 0 and (int(s[1]), int(s[3])) == tuple(o.parse_full(t)[2:])
     say("batched general chunks ok")
 
 
@@ -112,9 +115,10 @@ def test_no_anchor_anywhere():
     p = S.Parser("(a|a|a|a|a|a|a|a|a|a)*")
     for n in (1, 5, 19, 64, 700, 3000):
         for k in (64, 0):
-            _, acc, cnt, st = gpu_parse(p, b"a" * n, chunk_bytes=k)
+            g = gpu_parse(p, b"a" * n, chunk_bytes=k)
+            _, acc, cnt, st = g
             assert acc and st == 0
-            assert cnt == pow(10, n, 1 << 64), (n, k)
+            assert cnt == pow(10, n, 1 << 64) and g.countp == pow(10, n, P61), (n, k)
     say("no-anchor walks ok")
 
 
@@ -128,6 +132,7 @@ def test_column_unambiguous_res_one_tree():
     for pat, alpha in (("(ab|cd)*e", b"abcde"), ("(a|b)*c(d|e)+", b"abcde"), ("x(yz)*", b"xyz"), ("(ab|a)*", b"ab")):
         p, o = S.Parser(pat), Oracle(pat)
         assert column_unambiguous(o), pat
+        assert p.info.column_unambiguous == 1, pat   # the library skips the count walk for it
         texts = [b"", b"e", b"ab" * 700 + b"e", b"cd" * 3000 + b"ab" + b"e", b"abab" + b"x" + b"e", b"x", b"xyz" * 900,
                  b"ab" * 40 + b"c" + b"d" * 2000, b"c" + b"e" * 5000]
         texts += [bytes(rng.choice(list(alpha), int(rng.integers(1, 3000)))) for _ in range(4)]
@@ -136,8 +141,9 @@ def test_column_unambiguous_res_one_tree():
             _, acc, want = o.parse(t)
             assert want == (1 if acc else 0)
             for k in (64, 256, 0):
-                _, a2, cnt, st = gpu_parse(p, t, chunk_bytes=k)
-                assert (a2, cnt, st) == (acc, want, 0), (pat, len(t), k, a2, cnt, st)
+                g = gpu_parse(p, t, chunk_bytes=k)
+                _, a2, cnt, st = g
+                assert (a2, cnt, st, g.countp) == (acc, want, 0, want), (pat, len(t), k, a2, cnt, st)
         dts = [to_device(t) for t in texts]
         for k in (64, 0):
             res = p.parse_batch(dts, chunk_bytes=k)
@@ -146,5 +152,28 @@ def test_column_unambiguous_res_one_tree():
                 s = sc.cpu().numpy().view(np.uint64)
                 alone = gpu_parse(p, t, chunk_bytes=k)
                 assert np.array_equal(cols.cpu().numpy().view(np.uint64), alone[0])
-                assert (bool(s[0]), int(s[1]), int(s[2])) == alone[1:]
+                assert (bool(s[0]), int(s[1]), int(s[2]), int(s[3])) == alone[1:] + (alone.countp,)
     say("column-unambiguous REs ok")
+
+
+def test_runs_reaching_the_text_end():
+    # ambiguous runs that end on the text-end column n (its mark lies outside
+    # the 64-column windows), for every text length modulo 64 and run lengths
+    # across window and lane-chunk edges; both count moduli against the oracle
+    device()
+    rng = np.random.default_rng(41)
+    for pat in ("(a|ab|b)*b?", "((c+)+(d|dd)?)*"):
+        p, o = S.Parser(pat), Oracle(pat)
+        alpha = b"ab" if pat.startswith("(a") else b"cd"
+        texts = []
+        for n in list(range(1, 70)) + [127, 128, 129, 255, 256, 257, 1000, 1024, 1087]:
+            t = bytes(rng.choice(list(alpha), n))
+            texts.append(t)
+            texts.append(t[:max(n - 40, 0)] + alpha[:1] * min(n, 40))   # a long run at the end
+        for t in texts:
+            _, acc, cnt, cntp = o.parse_full(t)
+            for k in (64, 128, 0):
+                g = gpu_parse(p, t, chunk_bytes=k)
+                assert (g[1], g[2], g[3], g.countp) == (acc, cnt if acc else 0, 0, cntp if acc else 0), \
+                    (pat, len(t), k, g[1:], g.countp, acc, cnt, cntp)
+    say("runs at the text end ok")

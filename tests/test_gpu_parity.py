@@ -1,7 +1,7 @@
 """Parity of the HIP path (through the C ABI) with the serial CPU oracle.
 
 Bit-exact on every column word, the accept flag and the tree count modulo
-2^64, over the paper's worked examples, the plain-small workload, random REs
+2^64 and modulo 2^61 - 1, over the paper's worked examples, the plain-small workload, random REs
 and texts (accepted and rejected), every lane-chunk size from one window to
 the whole text, both table placements, and the edge cases (empty text, one
 byte, ragged last chunk, bytes outside the alphabet).
@@ -29,13 +29,14 @@ def check(pat, text, chunk_bytes=0, force_l2=False, o=None, p=None):
     p = p or S.Parser(pat)
     say("case", pat[:60] if isinstance(pat, str) else pat[:60], "n=%d" % len(text), "k=%d" % chunk_bytes,
         "l2=%d" % force_l2)
-    cols, acc, cnt = o.parse(text)
-    gcols, gacc, gcnt, gst = gpu_parse(p, text, chunk_bytes=chunk_bytes, force_l2=force_l2)
+    cols, acc, cnt, cntp = o.parse_full(text)
+    g = gpu_parse(p, text, chunk_bytes=chunk_bytes, force_l2=force_l2)
+    gcols, gacc, gcnt, gst = g
     assert gcols.shape == cols.shape
     bad = np.nonzero((gcols != cols).any(axis=1))[0]
     assert bad.size == 0, "first differing column %d of %d" % (bad[0], len(text) + 1)
     assert gacc == acc
-    assert gst == 0 and gcnt == cnt
+    assert gst == 0 and gcnt == cnt and g.countp == cntp, (gst, gcnt, cnt, g.countp, cntp)
     return o, p
 
 
@@ -140,7 +141,7 @@ def test_argument_errors():
     p = S.Parser("(ab|a)*")
     t = to_device(b"abab" * 10)
     cols = torch.empty((41, p.W), dtype=torch.int64, device=t.device)
-    sc = torch.empty(3, dtype=torch.int64, device=t.device)
+    sc = torch.empty(4, dtype=torch.int64, device=t.device)
     with pytest.raises(S.SlpfError) as e:       # capacity
         p.parse_into(t, 40, cols[:10], sc)
     assert e.value.status == S.E_CAPACITY
@@ -204,7 +205,7 @@ def test_recognizer_mode():
             assert got == want, (pat[:40], k, got, want)
         # batched recogniser
         dts = [to_device(t) for t in texts]
-        sc = torch.zeros((len(texts), 3), dtype=torch.int64, device="cuda:0")
+        sc = torch.zeros((len(texts), 4), dtype=torch.int64, device="cuda:0")
         p.parse_batch_into([(d, len(t), None, sc[j]) for j, (d, t) in enumerate(zip(dts, texts))],
                            flags=S.PARSE_RECOGNIZE)
         torch.cuda.synchronize()
@@ -238,7 +239,7 @@ def test_next_byte_entries_give_the_same_slpf():
                 g = gpu_parse(p, t, chunk_bytes=k, flags=S.PARSE_NEXT_BYTE_ENTRIES)
                 assert np.array_equal(g[0], cols), (pat[:40], len(t), k)
                 assert g[1] == acc and g[3] == 0 and g[2] == cnt
-                sc = torch.zeros(3, dtype=torch.int64, device="cuda:0")
+                sc = torch.zeros(4, dtype=torch.int64, device="cuda:0")
                 p.parse_into(to_device(t), len(t), None, sc, k, S.PARSE_RECOGNIZE | S.PARSE_NEXT_BYTE_ENTRIES)
                 torch.cuda.synchronize()
                 assert bool(sc.cpu().numpy()[0]) == acc

@@ -76,13 +76,12 @@ def test_server_alone_vs_mix():
         cols, sc = done[k]
         alone = gpu_parse(parsers[r], dts[k])
         assert np.array_equal(cols, alone[0]), k
-        assert (bool(sc[0]), int(sc[1]), int(sc[2])) == alone[1:], k
+        assert (bool(sc[0]), int(sc[1]), int(sc[2]), int(sc[3])) == alone[1:] + (alone.countp,), k
         if x.size <= 4096:
             o = oracles.setdefault(r, Oracle(pats[r]))
-            c2, acc, cnt = o.parse(x.tobytes())
+            c2, acc, cnt, cntp = o.parse_full(x.tobytes())
             assert np.array_equal(cols, c2) and bool(sc[0]) == acc, k
-            if sc[2] == 0:
-                assert int(sc[1]) == cnt, k
+            assert int(sc[2]) == 0 and int(sc[1]) == cnt and int(sc[3]) == cntp, k
 
 
 def test_server_capacity_and_arguments():
