@@ -89,7 +89,7 @@ def run_gpu(parser, text_np, steps, warmup, chunk_bytes, compact=False, flags=0)
     phase = {name: sum(e[i].elapsed_time(e[i + 1]) for e in evs) / steps
              for i, name in enumerate(S.PHASES)}
     s = sc.cpu().numpy().view(np.uint64)
-    return ms, phase, (int(s[0]), int(s[1]), int(s[2])), cols
+    return ms, phase, (int(s[0]), int(s[1]), int(s[2]), int(s[3])), cols
 
 
 def run_recognize(parser, text_np, steps, warmup, chunk_bytes):
@@ -517,7 +517,8 @@ def main():
                    "fwd_states": parser.info.fwd_states, "rev_states": parser.info.rev_states,
                    "table_placement": "lds" if parser.info.placement == 0 else "l2",
                    "lane_chunks": parser.num_chunks(n, args.chunk_bytes), "chunk_bytes": args.chunk_bytes or "auto",
-                   "accepted": scal[0], "trees_mod_2_64": scal[1], "count_status": scal[2],
+                   "accepted": scal[0], "trees_mod_2_64": scal[1], "trees_mod_2_61_1": scal[3],
+                   "count_status": scal[2],
                    "compile_ms": round(compile_ms, 2)},
         "phases_ms": {k: round(v, 4) for k, v in phase.items()},
         "slpf_gbs": round(algo / (ms * 1e-3) / 1e9, 2),
@@ -579,7 +580,8 @@ def main():
         algo2 = n2 + (n2 + 1) * 8 * W
         out["companion_clean_text"] = {
             "value": round(n2 / (ms2 * 1e-3) / 1e9, 3), "ms_per_step": round(ms2, 4),
-            "accepted": scal2[0], "trees_mod_2_64": scal2[1], "count_status": scal2[2],
+            "accepted": scal2[0], "trees_mod_2_64": scal2[1], "trees_mod_2_61_1": scal2[3],
+            "count_status": scal2[2],
             "phases_ms": {k: round(v, 4) for k, v in phase2.items()},
             "build_frac_of_hbm_peak": round(algo2 / (phase2["build"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
         print("companion: %.3f ms/step phases %s scalars %s" % (ms2, phase2, scal2), file=sys.stderr,

@@ -16,12 +16,13 @@
 //                    (such a run has as many paths as the column has
 //                    segments) and marks every other column of a run
 //                    (RunMarks);
-//   k_count_runs     one thread per lane chunk finds the marked runs that
-//                    start in it; a short run whose columns hold at most kTV
-//                    segments is counted by a vector walk in registers, the
-//                    chunk's other short runs go to k_count_defer, long runs
-//                    (more than Job::lshort columns) to the piece kernels;
-//   k_count_defer    one wavefront per deferred chunk walks its short runs
+//   k_count_runs     one thread per 64-column window finds the marked runs
+//                    that start in it; a short run whose columns hold at
+//                    most kTV segments is counted by a vector walk in
+//                    registers, the window's other short runs go to
+//                    k_count_defer, long runs (more than Job::lshort
+//                    columns) to the piece kernels;
+//   k_count_defer    one wavefront per deferred window walks its short runs
 //                    with the count vector in LDS, a segment a lane;
 //   k_count_pieces   a long run is cut at anchor columns, the leftmost
 //                    smallest column of each cell of Job::cell columns when
@@ -45,15 +46,6 @@ __device__ inline uint64_t addp(uint64_t a, uint64_t b) {   // a, b < 2^61 - 1
     return s >= kP61 ? s - kP61 : s;
 }
 
-// a * b modulo 2^61 - 1 (a, b < 2^61): with 2^61 = 1, the 122-bit product
-// hi * 2^64 + lo folds to (lo mod 2^61) + (lo >> 61) + 8 hi.
-__device__ inline uint64_t mulp(uint64_t a, uint64_t b) {
-    const uint64_t lo = a * b, hi = __umul64hi(a, b);
-    uint64_t r = (lo & kP61) + ((lo >> 61) | (hi << 3));
-    r = (r & kP61) + (r >> 61);
-    return r >= kP61 ? r - kP61 : r;
-}
-
 struct Cnt {                 // a count modulo 2^64 and modulo 2^61 - 1
     uint64_t a, p;
 };
@@ -70,10 +62,10 @@ __device__ inline Cnt wave_sum_cnt(Cnt x) {
     return x;
 }
 
-// Multiply text t's product of long-run counts by x; several wavefronts may
-// do it at once (both products are commutative).
-__device__ inline void tprod_mul(const Job &jb, uint32_t t, Cnt x) {
-    unsigned long long *pa = reinterpret_cast<unsigned long long *>(jb.tprod + 2ull * t);
+// Multiply the count pair at p (mod 2^64, mod 2^61 - 1) by x; several
+// threads may do it at once (both products are commutative).
+__device__ inline void cmul_at(uint64_t *p, Cnt x) {
+    unsigned long long *pa = reinterpret_cast<unsigned long long *>(p);
     unsigned long long *pp = pa + 1;
     unsigned long long old = *pa, seen;
     do {
@@ -86,6 +78,8 @@ __device__ inline void tprod_mul(const Job &jb, uint32_t t, Cnt x) {
         old = atomicCAS(pp, seen, static_cast<unsigned long long>(mulp(seen, x.p)));
     } while (old != seen);
 }
+
+__device__ inline void tprod_mul(const Job &jb, uint32_t t, Cnt x) { cmul_at(jb.tprod + 2ull * t, x); }
 
 // ------------------------------------------------------------ marked runs
 
@@ -103,9 +97,10 @@ __device__ inline TextCols text_cols(const Job &jb, uint32_t t) {
 
 // Marks of the 64-column window that holds column r < n (bit r % 64).
 __device__ inline uint64_t mark_word(const Job &jb, const TextCols &tc, uint64_t r) {
-    const uint64_t li = r / jb.s;
-    const uint32_t w = static_cast<uint32_t>((r - li * jb.s) >> 6);
-    return jb.amask[ck(jb, tc.c0 + static_cast<uint32_t>(li), w)];
+    // in windows: the lane chunk of r and the window inside it (s is a multiple of 64)
+    const uint32_t rw = static_cast<uint32_t>(r >> 6), sw = static_cast<uint32_t>(jb.s >> 6);
+    const uint32_t li = rw / sw;
+    return jb.amask[ck(jb, tc.c0 + li, rw - li * sw)];
 }
 
 __device__ inline bool marked(const Job &jb, const TextCols &tc, uint64_t r) {
@@ -135,23 +130,24 @@ __device__ inline uint64_t run_end(const Job &jb, const TextCols &tc, uint64_t r
     return e;
 }
 
-// Calls f(r0) for the first column of every marked run that starts in lane
-// chunk i (columns lo .. hi-1, and n for the last chunk), in column order.
+// Calls f(r0) for the first column of every marked run that starts in
+// window w of lane chunk i (its columns lo + 64 w .., and n after the last
+// window of a text), in column order.
 template <class F>
-__device__ inline void for_run_starts(const Job &jb, const TextCols &tc, uint32_t i, const ChunkCtx &cx, F f) {
+__device__ inline void for_window_run_starts(const Job &jb, const TextCols &tc, uint32_t i, uint32_t w,
+                                             const ChunkCtx &cx, F f) {
     const uint32_t nwin = static_cast<uint32_t>((cx.hi - cx.lo + 63) / 64);
-    uint64_t carry = cx.li > 0 && marked(jb, tc, cx.lo - 1) ? 1ull : 0ull;
-    for (uint32_t w = 0; w < nwin; ++w) {
-        const uint64_t v = jb.amask[ck(jb, i, w)];
-        uint64_t st = v & ~((v << 1) | carry);
-        carry = v >> 63;
-        while (st) {
-            const uint32_t b = static_cast<uint32_t>(__builtin_ctzll(st));
-            st &= st - 1;
-            f(cx.lo + 64ull * w + b);
-        }
+    uint64_t carry;
+    if (w > 0) carry = jb.amask[ck(jb, i, w - 1)] >> 63;
+    else carry = cx.li > 0 && marked(jb, tc, cx.lo - 1) ? 1ull : 0ull;
+    const uint64_t v = jb.amask[ck(jb, i, w)];
+    uint64_t st = v & ~((v << 1) | carry);
+    while (st) {
+        const uint32_t b = static_cast<uint32_t>(__builtin_ctzll(st));
+        st &= st - 1;
+        f(cx.lo + 64ull * w + b);
     }
-    if (cx.last && (jb.aend[tc.t] & 1ull) && !marked(jb, tc, tc.n - 1)) f(tc.n);
+    if (cx.last && w + 1 == nwin && (jb.aend[tc.t] & 1ull) && !marked(jb, tc, tc.n - 1)) f(tc.n);
 }
 
 // Calls f(k, segment) for the segments of column r in ascending order;
@@ -279,15 +275,20 @@ __device__ inline void emit_long(const Job &jb, uint32_t t, uint64_t r0, uint64_
 
 constexpr int kRunThreads = 256;
 
+// One thread per 64-column window, window-major as the marks (g = w c + i):
+// the lanes of a wavefront read consecutive mark words.
 __global__ __launch_bounds__(kRunThreads) void k_count_runs(Tabs tb, Job jb) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= jb.c) return;
+    const uint32_t sw = static_cast<uint32_t>(jb.s >> 6);
+    const uint64_t gg = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (gg >= static_cast<uint64_t>(jb.c) * sw) return;
+    const uint32_t g = static_cast<uint32_t>(gg);
+    const uint32_t w = g / jb.c, i = g - w * jb.c;
     const ChunkCtx cx = chunk_ctx(jb, i);
-    if (cx.tr.scalars[0] == 0) return;                    // rejected: no tree
+    if (cx.tr.scalars[0] == 0 || 64ull * w >= cx.hi - cx.lo) return;    // rejected, or past the chunk
     const TextCols tc = text_cols(jb, cx.t);
     Cnt acc{1, 1};
     bool defer = false;
-    for_run_starts(jb, tc, i, cx, [&](uint64_t r0) {
+    for_window_run_starts(jb, tc, i, w, cx, [&](uint64_t r0) {
         const uint64_t r1 = run_end(jb, tc, r0);
         if (r1 - r0 + 1 > jb.lshort) {
             emit_long(jb, cx.t, r0, r1);
@@ -298,14 +299,8 @@ __global__ __launch_bounds__(kRunThreads) void k_count_runs(Tabs tb, Job jb) {
         if (run_paths_lane(tb, jb, tc, r0, r1, x)) acc = cmul(acc, x);
         else defer = true;
     });
-    if (defer) {
-        jb.dchunk[atomicAdd(&jb.ccnt[0], 1u)] = i;       // at most one entry per chunk
-    } else {
-        const Cnt f{jb.cfac[2ull * i], jb.cfac[2ull * i + 1]};
-        const Cnt g = cmul(f, acc);
-        jb.cfac[2ull * i] = g.a;
-        jb.cfac[2ull * i + 1] = g.p;
-    }
+    if (defer) jb.dchunk[atomicAdd(&jb.ccnt[0], 1u)] = g;      // one entry per window
+    else if (acc.a != 1 || acc.p != 1) cmul_at(jb.cfac + 2ull * i, acc);
 }
 
 // ----------------------------------------------------- wavefront walks
@@ -424,16 +419,17 @@ __device__ inline Cnt walk_sum(const WalkLds &L, uint32_t buf, uint32_t m, int v
     return wave_sum_cnt(s);
 }
 
-// Deferred chunks: their short runs, one wavefront per chunk.
+// Deferred windows: their short runs, one wavefront per window.
 __global__ __launch_bounds__(64) void k_count_defer(Tabs tb, Job jb) {
     __shared__ WalkLds L;
     for (uint32_t item = blockIdx.x; item < jb.ccnt[0]; item += gridDim.x) {
-        const uint32_t i = jb.dchunk[item];
+        const uint32_t g = jb.dchunk[item];
+        const uint32_t w = g / jb.c, i = g - w * jb.c;
         const ChunkCtx cx = chunk_ctx(jb, i);
         const TextCols tc = text_cols(jb, cx.t);
         Cnt acc{1, 1};
         bool ok = true;
-        for_run_starts(jb, tc, i, cx, [&](uint64_t r0) {
+        for_window_run_starts(jb, tc, i, w, cx, [&](uint64_t r0) {
             const uint64_t r1 = run_end(jb, tc, r0);
             if (r1 - r0 + 1 > jb.lshort || !ok) return;    // long runs: the piece kernels'
             uint32_t buf = 0, m = 0;
@@ -444,9 +440,7 @@ __global__ __launch_bounds__(64) void k_count_defer(Tabs tb, Job jb) {
             acc = cmul(acc, walk_sum<1>(L, buf, m, 0));
         });
         if (threadIdx.x == 0) {
-            const Cnt g = cmul(Cnt{jb.cfac[2ull * i], jb.cfac[2ull * i + 1]}, acc);
-            jb.cfac[2ull * i] = g.a;
-            jb.cfac[2ull * i + 1] = g.p;
+            cmul_at(jb.cfac + 2ull * i, acc);
             if (!ok) jb.tfail[cx.t] = 1;
         }
         __syncthreads();
@@ -663,10 +657,21 @@ __global__ __launch_bounds__(kScalarThreads) void k_text_scalars(Tabs tb, Job jb
         st = 2;
     } else if (tr.scalars[0] != 0) {
         const uint32_t c0 = first_chunk(jb, t), c1 = first_chunk(jb, t + 1);
-        Cnt acc{1, 1};
-        for (uint32_t k = c0 + th; k < c1; k += blockDim.x) acc = cmul(acc, Cnt{jb.cfac[2ull * k], jb.cfac[2ull * k + 1]});
-        pa[th] = acc.a;
-        pq[th] = acc.p;
+        // four independent products per thread keep four multiplications in flight
+        Cnt acc[4] = {{1, 1}, {1, 1}, {1, 1}, {1, 1}};
+        const uint32_t st4 = 4 * blockDim.x;
+        uint32_t k = c0 + th;
+        for (; k + 3 * blockDim.x < c1; k += st4) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint64_t q = k + u * blockDim.x;
+                acc[u] = cmul(acc[u], Cnt{jb.cfac[2 * q], jb.cfac[2 * q + 1]});
+            }
+        }
+        for (; k < c1; k += blockDim.x) acc[0] = cmul(acc[0], Cnt{jb.cfac[2ull * k], jb.cfac[2ull * k + 1]});
+        const Cnt a01 = cmul(acc[0], acc[1]), a23 = cmul(acc[2], acc[3]), all = cmul(a01, a23);
+        pa[th] = all.a;
+        pq[th] = all.p;
         __syncthreads();
         for (uint32_t h = kScalarThreads / 2; h; h >>= 1) {
             if (th < h) {

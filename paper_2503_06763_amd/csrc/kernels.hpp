@@ -83,6 +83,10 @@ struct Tabs {
     // follows (the transpose of folseg), nseg x W
     const uint8_t *pairm;
     uint32_t kfd, krd;
+    // arcs2[(f * krd + b) * C + c] = number of arcs between two adjacent clean
+    // columns: the left one of forward state f, the right one of reverse state
+    // b, the byte between them of class c (0xffff: unknown); null when large
+    const uint16_t *arcs2;
     const uint64_t *predseg;
     uint32_t off16;
     uint32_t fhmask, rhmask;
@@ -128,8 +132,8 @@ struct Job {
     uint64_t *cfac;             // [c][2] product per chunk, modulo 2^64 and 2^61 - 1
     uint64_t *tprod;            // [T][2] product of the long runs of each text
     uint32_t *tfail;            // [T] a run of the text could not be counted
-    uint32_t *ccnt;             // [0] deferred chunks, [1] long runs, [2] pieces, [3] matrix slots
-    uint32_t *dchunk;           // chunks whose short runs the wave kernel counts
+    uint32_t *ccnt;             // [0] deferred windows, [1] long runs, [2] pieces, [3] matrix slots
+    uint32_t *dchunk;           // windows (w c + i) whose short runs the wave kernel counts
     uint64_t *runs;             // [cap_runs][4]: text, first column, last column, (piece base | pieces << 32)
     uint64_t *piece;            // [cap_pieces]: run index | piece number << 32
     uint64_t *mats;             // [cap_mats][kPieceR][kPieceR][2] piece matrices
@@ -882,7 +886,17 @@ __device__ inline uint32_t wave_max_u32(uint32_t v) {
 
 constexpr uint64_t kP61 = (1ull << 61) - 1;    // the second modulus of the tree count
 
-// x * m modulo 2^61 - 1 for x < 2^61 and m < 2^8.
+// a * b modulo 2^61 - 1 (a, b < 2^61): with 2^61 = 1, the 122-bit product
+// hi * 2^64 + lo folds to (lo mod 2^61) + (lo >> 61) + 8 hi.
+__device__ inline uint64_t mulp(uint64_t a, uint64_t b) {
+    const uint64_t lo = a * b, hi = __umul64hi(a, b);
+    uint64_t r = (lo & kP61) + ((lo >> 61) | (hi << 3));
+    r = (r & kP61) + (r >> 61);
+    return r >= kP61 ? r - kP61 : r;
+}
+
+// x * m modulo 2^61 - 1 for x < 2^61 and m < 2^16 (the high word of the
+// product is below 2^13, so one fold and one subtraction suffice).
 __device__ inline uint64_t mulp_small(uint64_t x, uint32_t m) {
     const uint64_t lo = x * m, hi = __umul64hi(x, static_cast<uint64_t>(m));
     const uint64_t r = (lo & kP61) + ((lo >> 61) | (hi << 3));
@@ -898,36 +912,78 @@ __device__ inline uint64_t mulp_small(uint64_t x, uint32_t m) {
 // the chunk is multiplied in here; the columns of every other run (longer,
 // touching a chunk edge inside the text, or of unknown size) are marked,
 // one bit per column, for the run kernels.
+// A run of two columns is multiplied in too: its paths are the arcs between
+// them, a function of the left column's forward state, the right column's
+// reverse state and the byte between them (table arcs2).
 //   st 0: the column to the right is a singleton or the text end;
 //   st 1: it is an ambiguous column of size pm not marked yet, whose own
 //         right neighbour is a singleton;
-//   st 2: it is marked, or lies beyond the chunk.
+//   st 2: it and its right neighbour are ambiguous, not marked, with pa
+//         paths between them, and a singleton further right;
+//   st 3: it is marked, or lies beyond the chunk.
 struct RunMarks {
-    uint32_t st = 2, pm = 0, endmark = 0;
-    uint64_t a64 = 1, ap = 1;          // product of the one-column runs, mod 2^64 and 2^61 - 1
+    uint32_t st = 3, pm = 0, pa = 0, endmark = 0;
+    uint32_t e2 = 0;                   // one-column runs of two segments (a factor 2 each)
+    uint64_t a64 = 1, ap = 1;          // product of the other short runs, mod 2^64 and 2^61 - 1
     uint64_t wcur = 0, wright = 0;     // marks of the current window and of the window to its right
-    // column t of the current window has the size code m: 1 a singleton,
-    // 2..254 its size, other values unknown; right_is_end: the column to its
-    // right is the text end n (which has no bit in the windows)
-    __device__ inline void step(uint32_t t, uint32_t m, bool right_is_end) {
+    __device__ __forceinline__ void mul(uint32_t m) {
+        a64 *= m;
+        ap = mulp_small(ap, m);
+    }
+    // a singleton column: it closes a pending run of one or two columns
+    __device__ __forceinline__ void single() {
+        if (st == 1) {
+            if (pm == 2) ++e2;
+            else mul(pm);
+        } else if (st == 2) {
+            mul(pa);
+        }
+        st = 0;
+    }
+    // mark column t + d (d = 1, 2) of the current window; end: it is the text-end column
+    __device__ __forceinline__ void mark_right(uint32_t t, uint32_t d, bool end) {
+        if (end) endmark = 1;
+        else if (t + d >= 64) wright |= 1ull << (t + d - 64);
+        else wcur |= 1ull << (t + d);
+    }
+    // column t of the current window (text column col) has the size code m
+    // (1 a singleton, 2..254 its size, other values unknown) and forward
+    // state ft; the column to its right has reverse state bright (for the
+    // arcs table, with the class of the byte text[col] between them); endk:
+    // column t + k is the text end n (which has no bit in the windows)
+    template <class Cls>
+    __device__ __forceinline__ void step(const Tabs &tb, uint32_t t, uint32_t m, uint32_t ft, uint32_t bright,
+                                         const uint8_t *text, uint64_t col, const Cls *cls, bool end1, bool end2) {
+        const bool known = m - 2u <= 252u;
         if (m == 1) {
-            if (st == 1) {
-                a64 *= pm;
-                ap = mulp_small(ap, pm);
-            }
-            st = 0;
-        } else if (st == 0 && m >= 2 && m <= 254) {
+            single();
+            return;
+        }
+        if (st == 0 && known) {
             st = 1;
             pm = m;
-        } else {
-            if (st == 1) {
-                if (right_is_end) endmark = 1;
-                else if (t == 63) wright |= 1ull;
-                else wcur |= 2ull << t;
-            }
-            wcur |= 1ull << t;
-            st = 2;
+            return;
         }
+        if (st == 1 && known) {   // the byte between this column and the next is text[col]
+            const uint32_t a = tb.arcs2 && ft < tb.kfd && bright < tb.krd
+                                   ? tb.arcs2[(static_cast<uint64_t>(ft) * tb.krd + bright) * tb.C + cls[text[col]]]
+                                   : 0xffffu;
+            if (a != 0xffffu) {
+                st = 2;
+                pa = a;
+                return;
+            }
+        }
+        // the column is marked, and so are the pending ones to its right
+        if (st == 1 || st == 2) mark_right(t, 1, end1);
+        if (st == 2) mark_right(t, 2, end2);
+        wcur |= 1ull << t;
+        st = 3;
+    }
+    // fold the factors 2 into the products (2^61 = 1 modulo 2^61 - 1)
+    __device__ inline void finish() {
+        a64 = e2 < 64 ? a64 << e2 : 0ull;
+        ap = mulp(ap, 1ull << (e2 % 61));
     }
 };
 
@@ -985,6 +1041,7 @@ __global__ __launch_bounds__(kBuildThreads) void k_build(Tabs tb, Job jb) {
         const uint32_t k = fi * tb.krd + bi;
         return jb.pair_lds ? static_cast<uint32_t>(pml[k]) : static_cast<uint32_t>(tb.pairm[k]);
     };
+
     const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t wave_first = blockIdx.x * blockDim.x + wv * 64;
@@ -1047,13 +1104,15 @@ __global__ __launch_bounds__(kBuildThreads) void k_build(Tabs tb, Job jb) {
                 rm.pm = m;
             } else if (m != 1) {
                 rm.endmark = 1;
-                rm.st = 2;
+                rm.st = 3;
             }
         }
     }
 
     // backward sweep, two windows in flight; fwA[t] = forward id at column a0+t
     uint32_t b = act ? jb.rid[i] : 0;
+    uint32_t bright = b;               // tree count: backward id of the column right of the current part
+    uint32_t amb = 0;                  // tree count: the current part's columns that are not singletons
     uint32_t *mine = stage + threadIdx.x * kStageRow;
     const uint32_t *wave_rows = stage + wv * 64 * kStageRow;
     uint32_t fwA[64], cwA[16];
@@ -1102,7 +1161,7 @@ __global__ __launch_bounds__(kBuildThreads) void k_build(Tabs tb, Job jb) {
                     b = T.rd[b * C + byte_of(cwA, t)];    // now the backward id at column a0+t
                     mine[u] = fwA[t] | (b << 16);
                     if constexpr (COMPACT) mine[SC + u] = t > 0 ? byte_of(cwA, t - 1) : pA0;
-                    if (cnt) rm.step(static_cast<uint32_t>(t), pair_size(fwA[t], b), a0A + t + 1 == cx.tr.n);
+                    if (cnt) amb |= (pair_size(fwA[t], b) != 1 ? 1u : 0u) << u;   // not a singleton
                 }
                 const int tf = (PARTS - 1 - h) * SC + (SC - 1 - u);   // forward step of window w-1
                 if (nxt) {
@@ -1110,6 +1169,29 @@ __global__ __launch_bounds__(kBuildThreads) void k_build(Tabs tb, Job jb) {
                     g = T.fd[g * C + byte_of(cwB, tf)];
                 }
             }
+            if (cnt && on && static_cast<int>(lenA) > h * SC) {
+                // tree count: the part's ambiguous columns right to left, from
+                // their staged id pairs; a gap between two of them is a run of
+                // singletons, which closes a pending run
+                const int top = min(SC - 1, static_cast<int>(lenA) - 1 - h * SC);
+                int prev = top + 1;
+#pragma unroll 1
+                for (uint32_t am = amb; am;) {
+                    const int u = 31 - __builtin_clz(am);
+                    am &= ~(1u << u);
+                    if (u + 1 < prev) rm.single();
+                    const uint32_t t = static_cast<uint32_t>(h * SC + u), v = mine[u];
+                    const uint32_t fi = v & 0xffffu, bi = v >> 16;
+                    const uint32_t br = u + 1 <= top ? mine[u + 1] >> 16 : bright;   // the column to the right
+                    const uint64_t col = a0A + t;
+                    rm.step(tb, t, pair_size(fi, bi), fi, br, text, col, T.cls, col + 1 == cx.tr.n,
+                            col + 2 == cx.tr.n);
+                    prev = u;
+                }
+                if (prev > 0) rm.single();
+                bright = mine[0] >> 16;
+            }
+            amb = 0;
             wave_sync();
             if constexpr (COMPACT) {
                 // 16 words per chunk: lanes 16g..16g+15 write chunk 4q+g
@@ -1182,16 +1264,17 @@ __global__ __launch_bounds__(kBuildThreads) void k_build(Tabs tb, Job jb) {
         if (cnt) {
             // the column left of the chunk: the text start acts as a singleton;
             // inside the text it is another chunk's, so a pending column is marked
-            if (rm.st == 1) {
+            if (rm.st == 1 || rm.st == 2) {
                 if (cx.first) {
-                    rm.a64 *= rm.pm;
-                    rm.ap = mulp_small(rm.ap, rm.pm);
-                } else {
+                    rm.mul(rm.st == 1 ? rm.pm : rm.pa);
+                } else {   // the pending columns lo (and lo + 1, possibly the text end)
                     rm.wcur |= 1ull;
+                    if (rm.st == 2) rm.mark_right(0, 1, lo + 1 == cx.tr.n);
                 }
             }
             jb.amask[ck(jb, i, 0)] = rm.wcur;
             if (cx.last) jb.aend[cx.t] = rm.endmark;
+            rm.finish();
         }
         jb.cfac[2ull * i] = rm.a64;
         jb.cfac[2ull * i + 1] = rm.ap;

@@ -21,6 +21,7 @@ using namespace slpf;
 
 constexpr size_t kLdsBudget = 96 * 1024;   // transition tables staged in LDS up to this size
 constexpr size_t kMaxPairTable = 4u << 20;  // largest table of clean-column sizes (bytes)
+constexpr size_t kMaxArcsTable = 2u << 20;  // largest table of arcs between two columns (entries)
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -147,6 +148,35 @@ slpf_status upload(slpf_parser *p) {
                     __builtin_popcountll(A.fwd.bits[size_t(f) * A.W + w] & A.rev.bits[size_t(b) * A.W + w]));
             pairm[size_t(f) * krd + b] = static_cast<uint8_t>(std::min<uint32_t>(m, 255));
         }
+    // arcs between two adjacent clean columns of an accepted text, over the
+    // forward state f of the left column, the reverse state b of the right
+    // one and the class c of the byte between them: left = bits_f(f) &
+    // bits_r(rev(b, c)), right = bits_f(fwd(f, c)) & bits_r(b)
+    const size_t n_arcs = size_t(kfd) * krd * A.C;
+    const bool with_arcs = n_arcs && n_arcs <= kMaxArcsTable;
+    std::vector<uint16_t> arcs(with_arcs ? n_arcs : 1, 0xffffu);
+    if (with_arcs) {
+        std::vector<uint32_t> lft, rgt;
+        for (uint32_t f = 0; f < kfd; ++f)
+            for (uint32_t b = 0; b < krd; ++b)
+                for (uint32_t c = 1; c < A.C; ++c) {
+                    const uint32_t fr = A.fwd.delta[size_t(f) * A.C + c], bl = A.rev.delta[size_t(b) * A.C + c];
+                    lft.clear();
+                    rgt.clear();
+                    for (uint32_t w = 0; w < A.W; ++w) {
+                        for (uint64_t v = A.fwd.bits[size_t(f) * A.W + w] & A.rev.bits[size_t(bl) * A.W + w]; v;
+                             v &= v - 1)
+                            lft.push_back(w * 64 + static_cast<uint32_t>(__builtin_ctzll(v)));
+                        for (uint64_t v = A.fwd.bits[size_t(fr) * A.W + w] & A.rev.bits[size_t(b) * A.W + w]; v;
+                             v &= v - 1)
+                            rgt.push_back(w * 64 + static_cast<uint32_t>(__builtin_ctzll(v)));
+                    }
+                    uint32_t na = 0;
+                    for (const uint32_t r : lft)
+                        for (const uint32_t q : rgt) na += (A.folseg[size_t(r) * A.W + (q >> 6)] >> (q & 63)) & 1u;
+                    arcs[(size_t(f) * krd + b) * A.C + c] = static_cast<uint16_t>(std::min<uint32_t>(na, 0xffffu));
+                }
+    }
     // the segments each segment follows (transpose of FolSeg)
     std::vector<uint64_t> pred(size_t(A.nseg) * A.W, 0);
     for (uint32_t r = 0; r < A.nseg; ++r)
@@ -184,6 +214,7 @@ slpf_status upload(slpf_parser *p) {
         {A.gmask.data(), A.gmask.size() * 8, 0},
         {pairm.data(), pairm.size(), 0},
         {pred.data(), pred.size() * 8, 0},
+        {arcs.data(), arcs.size() * 2, 0},
     };
     size_t total = 0;
     for (auto &pt : parts) {
@@ -232,6 +263,7 @@ slpf_status upload(slpf_parser *p) {
     t.kfd = kfd;
     t.krd = krd;
     t.predseg = reinterpret_cast<const uint64_t *>(at(24));
+    t.arcs2 = with_arcs ? reinterpret_cast<const uint16_t *>(at(25)) : nullptr;
     t.col_single = p->col_single ? 1u : 0u;
     t.fhmask = static_cast<uint32_t>(A.fwd.hash.size() - 1);
     t.rhmask = static_cast<uint32_t>(A.rev.hash.size() - 1);
@@ -526,7 +558,7 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
     const uint64_t cap_runs = cols_total / lshort + T + 1;
     const uint64_t cap_mats = 2 * (cols_total / cell) + 2;
     const uint64_t cap_pieces = cap_runs + cols_total / cell + 1;
-    if (count && (cap_runs > 0xffffffffull || cap_pieces > 0xffffffffull)) return SLPF_E_ARG;
+    if (count && (cap_runs > 0xffffffffull || cap_pieces > 0xffffffffull || nck > 0xffffffffull)) return SLPF_E_ARG;
     int iam = -1, iaend = -1, icfac = -1, itprod = -1, itfail = -1, iccnt = -1, idch = -1, iruns = -1, ipiece = -1,
         imats = -1, ipmat = -1;
     if (count) {
@@ -536,7 +568,7 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
         itprod = L.add(size_t(T) * 16);
         itfail = L.add(size_t(T) * 4);
         iccnt = L.add(16);
-        idch = L.add(size_t(c) * 4);
+        idch = L.add(nck * 4);
         iruns = L.add(cap_runs * 64);
         ipiece = L.add(cap_pieces * 8);
         imats = L.add(cap_mats * kPieceR * kPieceR * 16);
@@ -760,8 +792,9 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
     // one-column runs).  The deferred chunks, pieces and long runs are known on
     // the device only: their kernels loop over grids of a fixed size.
     if (count && c && !tb.col_single) {
-        hipLaunchKernelGGL(k_count_runs, dim3((c + kRunThreads - 1) / kRunThreads), dim3(kRunThreads), 0, stream, tb,
-                           jb);
+        const uint64_t nwins = uint64_t(c) * (s / 64);
+        hipLaunchKernelGGL(k_count_runs, dim3(static_cast<uint32_t>((nwins + kRunThreads - 1) / kRunThreads)),
+                           dim3(kRunThreads), 0, stream, tb, jb);
         const uint32_t wgrid = std::min<uint32_t>(c, 2048);
         hipLaunchKernelGGL(k_count_defer, dim3(wgrid), dim3(64), 0, stream, tb, jb);
         hipLaunchKernelGGL(k_count_pieces, dim3(wgrid), dim3(64), 0, stream, tb, jb);
