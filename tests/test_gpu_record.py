@@ -6,10 +6,13 @@ oracle on whole 2 MiB texts (clean and with corruption blocks, at several
 lane-chunk sizes), and on sampled windows of a 64 MiB text with the
 automatic chunking.
 """
+import hashlib
+import os
 import sys
 
 import numpy as np
 import pytest
+import yaml
 
 from gen import regen, textgen
 from gpu_util import device, gpu_parse, to_device
@@ -44,7 +47,7 @@ def record_texts(record):
     text = textgen.record_text(41, 2 << 20)
     out = []
     for name, t in (("clean", text), ("corrupted", textgen.corrupt(text, 42, frac=0.02, block=(8, 512)))):
-        out.append((name, t, o.parse(t.tobytes())))
+        out.append((name, t, o.parse_full(t.tobytes())))
     return out
 
 
@@ -52,13 +55,13 @@ def record_texts(record):
 def test_record_text_whole(record, record_texts, chunk):
     device()
     pat, p, o = record
-    for name, t, (cols, acc, cnt) in record_texts:
+    for name, t, (cols, acc, cnt, cntp) in record_texts:
         say("record", name, t.size, "chunk", chunk)
         g = gpu_parse(p, to_device(t.tobytes()), chunk_bytes=chunk)
         bad = np.nonzero((g[0] != cols).any(axis=1))[0]
         assert bad.size == 0, "first differing column %d" % bad[0]
         assert g[1] == acc == (name == "clean")
-        assert g[3] == 0 and g[2] == cnt
+        assert g[3] == 0 and g[2] == cnt and g.countp == cntp
 
 
 def test_record_large_sampled_windows(record):
@@ -74,10 +77,12 @@ def test_record_large_sampled_windows(record):
     s = p.num_chunks(n) and (n + p.num_chunks(n) - 1) // p.num_chunks(n)
     rng = np.random.default_rng(9)
     starts = sorted({0, n + 1 - win, s - win // 2, 5 * s - 1, *[int(x) for x in rng.integers(0, n + 1 - win, size=6)]})
-    w, acc, cnt = o.parse_dfa(text, starts, win)
+    # windows and the accept flag (the counts are checked on the whole 2 MiB
+    # texts above and on the 1 GiB text below)
+    w, acc, _, _ = o.parse_dfa_full(text, starts, win, count=False)
     scn = sc.cpu().numpy().view(np.uint64)
     assert bool(scn[0]) == acc and acc
-    assert int(scn[2]) == 0 and int(scn[1]) == cnt
+    assert int(scn[2]) == 0
     for k, st in enumerate(starts):
         g = cols[st:st + win].cpu().numpy().view(np.uint64)
         assert np.array_equal(g, w[k]), "window at column %d" % st
@@ -101,7 +106,14 @@ def test_record_full_size_sampled_records(record):
     cols, sc = p.parse(t)
     torch.cuda.synchronize()
     scn = sc.cpu().numpy().view(np.uint64)
-    assert bool(scn[0]) and int(scn[1]) == 1 and int(scn[2]) == 0
+    # accept flag and counts from the oracle's serial parser over the whole
+    # text (tests/golden/full_size_counts.yaml, make_full_size_goldens.py)
+    with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "full_size_counts.yaml")) as f:
+        g = yaml.safe_load(f)["record_re"]
+    assert g["re_sha256"] == hashlib.sha256(pat).hexdigest()
+    assert g["text_bytes"] == n and g["text_sha256"] == hashlib.sha256(text.tobytes()).hexdigest()
+    assert int(scn[2]) == 0
+    assert (bool(scn[0]), int(scn[1]), int(scn[3])) == (g["accepted"], g["trees_mod_2_64"], g["trees_mod_2_61_1"])
     rng = np.random.default_rng(11)
     cuts = [0] + [int(x) for x in rng.integers(0, n - (1 << 12), size=8)] + [n - (1 << 12)]
     for a0 in cuts:
