@@ -257,19 +257,19 @@ __device__ inline void emit_long(const Job &jb, uint32_t t, uint64_t r0, uint64_
     }
     const uint32_t pb = atomicAdd(&jb.ccnt[2], npc);
     const uint32_t mb = npc > 1 ? atomicAdd(&jb.ccnt[3], npc) : 0u;
-    uint64_t *rr = jb.runs + 8ull * ri;
+    RunRec &rr = jb.runs[ri];
     if (pb + static_cast<uint64_t>(npc) > jb.cap_pieces ||
         (npc > 1 && mb + static_cast<uint64_t>(npc) > jb.cap_mats)) {
         jb.tfail[t] = 1;
-        rr[4] = 0;                                   // no pieces: the chain kernel skips it
+        rr.npc = 0;                                  // no pieces: the chain kernel skips it
         return;
     }
-    rr[0] = t;
-    rr[1] = r0;
-    rr[2] = r1;
-    rr[3] = pb;
-    rr[4] = npc;
-    rr[5] = mb;
+    rr.t = t;
+    rr.r0 = r0;
+    rr.r1 = r1;
+    rr.pb = pb;
+    rr.npc = npc;
+    rr.mb = mb;
     for (uint32_t j = 0; j < npc; ++j) jb.piece[pb + j] = static_cast<uint64_t>(ri) | (static_cast<uint64_t>(j) << 32);
 }
 
@@ -477,10 +477,10 @@ __global__ __launch_bounds__(64) void k_count_pieces(Tabs tb, Job jb) {
     for (uint32_t item = blockIdx.x; item < np; item += gridDim.x) {
         const uint64_t pc = jb.piece[item];
         const uint32_t ri = static_cast<uint32_t>(pc), j = static_cast<uint32_t>(pc >> 32);
-        const uint64_t *rr = jb.runs + 8ull * ri;
-        const uint32_t t = static_cast<uint32_t>(rr[0]);
-        const uint64_t r0 = rr[1], r1 = rr[2];
-        const uint32_t npc = static_cast<uint32_t>(rr[4]), mb = static_cast<uint32_t>(rr[5]);
+        const RunRec &rr = jb.runs[ri];
+        const uint32_t t = rr.t;
+        const uint64_t r0 = rr.r0, r1 = rr.r1;
+        const uint32_t npc = rr.npc, mb = rr.mb;
         const TextCols tc = text_cols(jb, t);
         const uint64_t kf = r0 / jb.cell + 1;
         uint64_t a = r0;
@@ -565,11 +565,10 @@ __global__ __launch_bounds__(64) void k_count_chain(Job jb) {
     const uint32_t lane = threadIdx.x;
     const uint32_t nr = min(jb.ccnt[1], jb.cap_runs);
     for (uint32_t ri = blockIdx.x; ri < nr; ri += gridDim.x) {
-        const uint64_t *rr = jb.runs + 8ull * ri;
-        const uint32_t npc = static_cast<uint32_t>(rr[4]);
+        const RunRec &rr = jb.runs[ri];
+        const uint32_t npc = rr.npc;
         if (npc < 2) continue;
-        const uint32_t t = static_cast<uint32_t>(rr[0]);
-        const uint32_t pb = static_cast<uint32_t>(rr[3]), mb = static_cast<uint32_t>(rr[5]);
+        const uint32_t t = rr.t, pb = rr.pb, mb = rr.mb;
         // lane k < kPieceR holds entry k of the row vector
         Cnt vk{0, 0};
         uint32_t dim = 0;

@@ -98,6 +98,13 @@ struct Tabs {
     uint64_t wmagic;            // ceil(2^32 / W): e / W == (e * wmagic) >> 32 for e < 2^16
 };
 
+// A long run of marked columns r0 .. r1 of text t, cut into npc pieces
+// (piece items pb .., matrix slots mb .. when npc > 1).
+struct RunRec {
+    uint64_t r0, r1;
+    uint32_t t, pb, npc, mb;
+};
+
 struct Job {
     // texts: a job parses one or many texts with one parser; the lane chunks of
     // all texts form one index space, text t owning chunks tchunk0[t] ..
@@ -134,7 +141,7 @@ struct Job {
     uint32_t *tfail;            // [T] a run of the text could not be counted
     uint32_t *ccnt;             // [0] deferred windows, [1] long runs, [2] pieces, [3] matrix slots
     uint32_t *dchunk;           // windows (w c + i) whose short runs the wave kernel counts
-    uint64_t *runs;             // [cap_runs][4]: text, first column, last column, (piece base | pieces << 32)
+    RunRec *runs;               // [cap_runs] long runs
     uint64_t *piece;            // [cap_pieces]: run index | piece number << 32
     uint64_t *mats;             // [cap_mats][kPieceR][kPieceR][2] piece matrices
     uint32_t *pmat;             // [cap_pieces]: rows | cols << 8 of the piece's matrix, or void

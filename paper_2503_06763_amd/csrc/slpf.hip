@@ -553,7 +553,7 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
     // bounds the piece matrices.
     const uint64_t cols_total = total + T;
     uint64_t cell = 2048;
-    while (cell < cols_total / 32768) cell <<= 1;
+    while (cell < cols_total / 4096) cell <<= 1;
     const uint32_t lshort = 512;
     const uint64_t cap_runs = cols_total / lshort + T + 1;
     const uint64_t cap_mats = 2 * (cols_total / cell) + 2;
@@ -569,7 +569,7 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
         itfail = L.add(size_t(T) * 4);
         iccnt = L.add(16);
         idch = L.add(nck * 4);
-        iruns = L.add(cap_runs * 64);
+        iruns = L.add(cap_runs * sizeof(RunRec));
         ipiece = L.add(cap_pieces * 8);
         imats = L.add(cap_mats * kPieceR * kPieceR * 16);
         ipmat = L.add(cap_pieces * 4);
@@ -655,7 +655,7 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
         jb.tfail = reinterpret_cast<uint32_t *>(ptr(itfail));
         jb.ccnt = reinterpret_cast<uint32_t *>(ptr(iccnt));
         jb.dchunk = reinterpret_cast<uint32_t *>(ptr(idch));
-        jb.runs = reinterpret_cast<uint64_t *>(ptr(iruns));
+        jb.runs = reinterpret_cast<RunRec *>(ptr(iruns));
         jb.piece = reinterpret_cast<uint64_t *>(ptr(ipiece));
         jb.mats = reinterpret_cast<uint64_t *>(ptr(imats));
         jb.pmat = reinterpret_cast<uint32_t *>(ptr(ipmat));
