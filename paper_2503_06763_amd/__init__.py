@@ -33,7 +33,8 @@ EXPORTS = ["slpf_compile", "slpf_parser_destroy", "slpf_parser_info_get", "slpf_
            "slpf_table_dump", "slpf_forest_bytes", "slpf_parse", "slpf_parse_batch", "slpf_tune", "slpf_parser_trim",
            "slpf_num_chunks", "slpf_status_str", "slpf_server_create", "slpf_server_destroy",
            "slpf_server_submit", "slpf_server_poll", "slpf_server_result", "slpf_server_release",
-           "slpf_server_stats", "slpf_compact_bytes", "slpf_decode_compact", "slpf_get_matches"]
+           "slpf_server_stats", "slpf_compact_bytes", "slpf_decode_compact", "slpf_get_matches",
+           "slpf_parse_noalloc"]
 
 
 class SlpfError(RuntimeError):
@@ -120,6 +121,8 @@ def lib(path: str = LIB_PATH):
     L.slpf_forest_bytes.restype = ctypes.c_uint64
     L.slpf_parse.argtypes = [vp, vp, ctypes.c_uint64, ctypes.POINTER(ParseOpts), ctypes.POINTER(Forest), vp]
     L.slpf_parse.restype = ctypes.c_int
+    L.slpf_parse_noalloc.argtypes = [vp, vp, ctypes.c_uint64, ctypes.POINTER(ParseOpts), ctypes.POINTER(Forest), vp]
+    L.slpf_parse_noalloc.restype = ctypes.c_int
     L.slpf_parse_batch.argtypes = [vp, ctypes.POINTER(Text), sz, ctypes.POINTER(ParseOpts), vp]
     L.slpf_parse_batch.restype = ctypes.c_int
     L.slpf_tune.argtypes = [vp, ctypes.POINTER(Text), sz, ctypes.c_uint32, ctypes.POINTER(ParseOpts),
@@ -274,6 +277,20 @@ class Parser:
         st = self._L.slpf_parse(self._h, text.data_ptr() if n else None, n, ctypes.byref(o), ctypes.byref(f),
                                 ctypes.c_void_p(stream.cuda_stream))
         _check(st, "slpf_parse")
+
+    def parse_noalloc_into(self, text, n: int, columns, scalars, chunk_bytes: int = 0, flags: int = 0,
+                           stream=None):
+        """Raw slpf_parse_noalloc (work buffers in the library's device array, no
+        allocation) on torch device tensors; asynchronous on ``stream``."""
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(scalars.device)
+        o = ParseOpts(ctypes.sizeof(ParseOpts), chunk_bytes, flags, 0, None, 0, None, 0, 0)
+        f = Forest(columns.data_ptr() if columns is not None else None,
+                   columns.numel() * columns.element_size() if columns is not None else 0, scalars.data_ptr())
+        st = self._L.slpf_parse_noalloc(self._h, text.data_ptr() if n else None, n, ctypes.byref(o),
+                                        ctypes.byref(f), ctypes.c_void_p(stream.cuda_stream))
+        _check(st, "slpf_parse_noalloc")
 
     def parse(self, text, chunk_bytes: int = 0, count: bool = True, force_l2: bool = False,
               trace: bool = False, stream=None, events=None, flags: int = 0):

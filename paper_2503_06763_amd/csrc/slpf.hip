@@ -475,8 +475,10 @@ namespace {
 
 // One job: T texts parsed with one parser; text t owns lane chunks
 // tchunk0[t] .. tchunk0[t+1]-1 of a common index space.
+// ext_ws / ext_bytes: a caller-held workspace (device memory) used instead of
+// the parser's per-stream one, for one text only; nothing is allocated then.
 slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf_parse_opts *opts,
-                    hipStream_t stream) {
+                    hipStream_t stream, uint8_t *ext_ws = nullptr, size_t ext_bytes = 0) {
     const uint32_t flags = opts ? opts->flags : 0;
     const bool recog = (flags & SLPF_PARSE_RECOGNIZE) != 0;
     const bool count = !(flags & SLPF_PARSE_NO_COUNT) && !recog;
@@ -576,7 +578,11 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
     }
 
     uint8_t *base;
-    {
+    if (ext_ws) {
+        if (T != 1) return SLPF_E_ARG;
+        if (L.total > ext_bytes) return SLPF_E_CAPACITY;
+        base = ext_ws;
+    } else {
         std::lock_guard<std::mutex> g(p->mu);
         Workspace &w = p->ws[stream];
         if (w.bytes < L.total) {
@@ -832,6 +838,57 @@ slpf_status slpf_parse(const slpf_parser *cp, const uint8_t *text, uint64_t n, c
     if (st != SLPF_OK) return st;
     slpf_text item{text, n, *forest};
     return run_job(p, &item, 1, opts, static_cast<hipStream_t>(hip_stream));
+}
+
+}  // extern "C"
+
+// ------------------------------------------------- parse without allocation
+// The workspace of slpf_parse_noalloc: a file-scope device array, one copy
+// per GPU, held until the process ends.  In host code `scratch` only names
+// the symbol; its device address on each GPU comes from hipGetSymbolAddress
+// (taken once per device, with that device current) and only that address
+// is passed to kernels.
+namespace {
+
+constexpr size_t kNoAllocScratchBytes = 64u << 20;
+constexpr int kMaxDevices = 64;
+
+__device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+
+std::mutex g_scratch_mu;
+uint8_t *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device` (the device must be current).
+slpf_status scratch_on(int device, uint8_t **out) {
+    if (device < 0 || device >= kMaxDevices) return SLPF_E_ARG;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return SLPF_E_DEVICE;
+        g_scratch_ptr[device] = static_cast<uint8_t *>(ptr);
+    }
+    *out = g_scratch_ptr[device];
+    return SLPF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+slpf_status slpf_parse_noalloc(const slpf_parser *cp, const uint8_t *text, uint64_t n, const slpf_parse_opts *opts,
+                               const slpf_forest *forest, void *hip_stream) {
+    slpf_parser *p = const_cast<slpf_parser *>(cp);
+    if (!p || p->host_only) return SLPF_E_ARG;
+    if (opts && opts->struct_size != sizeof(slpf_parse_opts)) return SLPF_E_ARG;
+    if (opts && opts->chunk_bytes && (opts->chunk_bytes % 64 != 0)) return SLPF_E_ARG;
+    slpf_status st = check_item(p, text, n, forest, opts ? opts->flags : 0u);
+    if (st != SLPF_OK) return st;
+    if (hipSetDevice(p->device) != hipSuccess) return SLPF_E_DEVICE;
+    uint8_t *ws = nullptr;
+    st = scratch_on(p->device, &ws);
+    if (st != SLPF_OK) return st;
+    slpf_text item{text, n, *forest};
+    return run_job(p, &item, 1, opts, static_cast<hipStream_t>(hip_stream), ws, kNoAllocScratchBytes);
 }
 
 slpf_status slpf_parse_batch(const slpf_parser *cp, const slpf_text *items, size_t count, const slpf_parse_opts *opts,
