@@ -1,9 +1,8 @@
 """Seeded synthetic workloads of many REs and texts (batched and served runs).
 
-Only RE trees, texts and arrival schedules: nothing here parses.  The RE
-strings are accepted by both the library and the oracle; whether an RE fits
-the library's limits is checked by the caller (``fits``), which redraws with
-the next seed.
+Only RE trees, texts and arrival schedules: nothing here parses.  An RE is
+redrawn with the next seed only when the generator finds no tree of the drawn
+shape; nothing is filtered by what a parser accepts.
 """
 from __future__ import annotations
 
@@ -22,10 +21,10 @@ def _depth_ops(rng):
     return depth, n_ops
 
 
-def re_family(seed: int, count: int, fits=None, alphabets=None):
+def re_family(seed: int, count: int, alphabets=None):
     """``count`` seeded random REs (cfg2 generator, depth U[4,8]) cycling over
     ``alphabets`` (default: 4 letters, 26 letters, 128 byte values in the
-    proportions 5:6:4), each redrawn with the next seed until ``fits(re)``."""
+    proportions 5:6:4)."""
     if alphabets is None:
         alphabets = [ALPHA_DNA] * 5 + [ALPHA_26] * 6 + [ALPHA_128] * 4
     out = []
@@ -40,21 +39,21 @@ def re_family(seed: int, count: int, fits=None, alphabets=None):
             except RuntimeError:
                 tree = None
             s += 1
-            if tree is not None and (fits is None or fits(regen.to_re(tree))):
+            if tree is not None:
                 break
         out.append(("rand%d_a%d_d%d" % (i, len(alpha), depth), tree))
     return out
 
 
-def batched_res(fits=None, seed: int = 4000):
+def batched_res(seed: int = 4000):
     """16 REs: 15 random ones (5 over ACGT, 6 over 26 letters, 4 over 128
     byte values) and the union-heavy 4-letter motif RE."""
-    return re_family(seed, 15, fits) + [("motif", regen.motif_re())]
+    return re_family(seed, 15) + [("motif", regen.motif_re())]
 
 
-def served_res(fits=None, seed: int = 5000):
+def served_res(seed: int = 5000):
     """64 REs from the same generator with other seeds (every 16th the motif RE)."""
-    res = re_family(seed, 60, fits)
+    res = re_family(seed, 60)
     for k in range(4):
         res.insert(16 * k + 15, ("motif%d" % k, regen.motif_re()))
     return res

@@ -104,10 +104,11 @@ typedef struct {
     uint32_t rdfa_states;        /* reverse DFA from F */
     uint32_t rmedfa_states;      /* reverse ME-DFA from the singletons */
     uint32_t num_classes;        /* byte classes, class 0 = bytes outside the RE */
-    uint32_t max_entries;        /* longest speculative entry list (<= 64) */
+    uint32_t max_entries;        /* longest speculative entry list (join masks take
+                                    ceil(max_entries / 64) words) */
     uint32_t placement;          /* 0 = transition tables staged in LDS, 1 = read through L2 */
     uint32_t max_entries_next_byte;  /* longest entry list without the previous-byte filter
-                                        (SLPF_PARSE_NEXT_BYTE_ENTRIES needs <= 64) */
+                                        (the lists of SLPF_PARSE_NEXT_BYTE_ENTRIES) */
     uint32_t column_unambiguous; /* 1 when no forward state reachable from I and reverse state
                                     reachable from F share two segments: every clean column of an
                                     accepted text is then one segment and the text has one tree */
@@ -148,10 +149,12 @@ uint64_t slpf_forest_bytes(const slpf_parser *p, uint64_t n);
  * x_{r+1}, so C_r lies in the candidate list X(x_r, x_{r+1}): the segments
  * with end-letter class of x_{r+1} (final segments at r = n) that follow a
  * segment labelled with the class of x_r (initial segments at r = 0),
- * ascending by segment id.  slpf_compile bounds every such list to 64
- * segments, so the compact column r is one uint64_t whose bit k is set iff
- * the k-th segment of X(x_r, x_{r+1}) is in C_r: (n + 1) * 8 bytes for the
- * whole SLPF instead of (n + 1) * W * 8, with no overflow case.
+ * ascending by segment id.  When every such list holds at most 64 segments
+ * (slpf_parser_info.max_entries <= 64), the compact column r is one
+ * uint64_t whose bit k is set iff the k-th segment of X(x_r, x_{r+1}) is in
+ * C_r: (n + 1) * 8 bytes for the whole SLPF instead of (n + 1) * W * 8.
+ * Parsers with longer lists have no compact form: SLPF_PARSE_COMPACT and
+ * slpf_decode_compact return SLPF_E_TOO_LARGE for them.
  */
 uint64_t slpf_compact_bytes(uint64_t n);
 
@@ -201,9 +204,7 @@ enum {
     SLPF_PARSE_NEXT_BYTE_ENTRIES = 1u << 4  /* speculation ablation: each lane chunk's runs start
                                            from every segment whose end-letter is the chunk's first
                                            byte (the ME-DFA entries of Sect. 3.1 for that letter),
-                                           without the filter by the previous byte.  Same results;
-                                           SLPF_E_TOO_LARGE when such a list exceeds 64 segments
-                                           (slpf_parser_info.max_entries_next_byte) */
+                                           without the filter by the previous byte.  Same results */
 };
 
 typedef struct {
@@ -390,7 +391,11 @@ slpf_status slpf_server_submit(slpf_server *s, const slpf_parser *p, const uint8
  * calls).  Does not block on the GPU. */
 slpf_status slpf_server_poll(slpf_server *s, uint64_t *done_tags, size_t cap, size_t *n_done);
 /* Output of a finished request (device pointers into the arena, valid until
- * slpf_server_release). */
+ * slpf_server_release).  Returns the request's parse status: a request whose
+ * job could not be launched (slpf_parse_batch failed for its parser, e.g. a
+ * parser compiled with SLPF_COMPILE_HOST_ONLY) is still reported finished by
+ * slpf_server_poll, and this call then returns that error; the requests of
+ * the other parsers in the same slot are not affected. */
 slpf_status slpf_server_result(const slpf_server *s, uint64_t tag, slpf_forest *out);
 /* Return a finished request's arena space. */
 slpf_status slpf_server_release(slpf_server *s, uint64_t tag);

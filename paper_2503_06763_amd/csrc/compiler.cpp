@@ -636,7 +636,6 @@ int compile_re(const uint8_t *re, size_t len, const CompileLimits &lim, HostAuto
         }
     }
     A.xoff[static_cast<size_t>(NL) * NL] = static_cast<uint32_t>(A.xlist.size());
-    if (A.max_entries > static_cast<uint32_t>(kMaxEntries)) return SLPF_E_TOO_LARGE;
     // the same lists without the previous-byte filter (initial segments at
     // the text start): the speculation ablation; usable when they fit a mask
     A.xoff_nb.assign(static_cast<size_t>(NL) * NL + 1, 0);

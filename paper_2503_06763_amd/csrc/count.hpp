@@ -621,7 +621,8 @@ __global__ __launch_bounds__(kScalarThreads) void k_text_scalars(Tabs tb, Job jb
                 const uint64_t *rb = tb.rbits + static_cast<uint64_t>(tb.rstart) * tb.W;
                 for (uint32_t w = 0; w < tb.W; ++w) any |= fb[w] & rb[w];
             } else {
-                any = jb.fout[first_chunk(jb, t + 1) - 1];
+                const uint64_t last = first_chunk(jb, t + 1) - 1;
+                for (uint32_t e = 0; e < jb.ew; ++e) any |= jb.fout[last * jb.ew + e];
             }
             tr.scalars[0] = any ? 1 : 0;
             tr.scalars[1] = 0;

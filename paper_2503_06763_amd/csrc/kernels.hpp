@@ -116,12 +116,13 @@ struct Job {
     uint64_t s;                 // lane chunk bytes
     uint32_t c;                 // lane chunks of all texts
     uint16_t *R, *Rh;           // [emax][c] end ids of the reach runs
-    uint64_t *Mf, *MbR;         // [c][emax] masks; MbR indexed by c-1-i
-    uint8_t *nxf, *nxb;         // entry-list sizes at the scan input of item k (forward: left edge of
+    uint64_t *Mf, *MbR;         // [c][emax][ew] masks; MbR indexed by c-1-i
+    uint32_t ew;                // words of an entry-list mask (ceil(emax / 64))
+    uint16_t *nxf, *nxb;        // entry-list sizes at the scan input of item k (forward: left edge of
                                 // chunk k; backward: right edge of chunk c-1-k)
     uint8_t *rsf, *rsb;         // item k starts a text (forward: first chunk; backward: last chunk)
-    uint64_t *fin, *fout;       // forward join masks at the left / right edge of chunk i
-    uint64_t *bin, *bout;       // backward join masks (reversed item order: index c-1-i)
+    uint64_t *fin, *fout;       // [c][ew] forward join masks at the left / right edge of chunk i
+    uint64_t *bin, *bout;       // [c][ew] backward join masks (reversed item order: index c-1-i)
     uint16_t *fid, *rid;        // build start ids per chunk
     uint16_t *ckpt;             // forward id at the left edge of every 64-byte window
     uint16_t *bckpt;            // backward id at the right edge of every 64-byte window
@@ -478,9 +479,9 @@ __global__ __launch_bounds__(256) void k_reach(Tabs tb, Job jb) {
     const uint32_t xa0 = tb.xoff[la], na = tb.xoff[la + 1] - xa0;
     const uint32_t xb0 = tb.xoff[lb], nb = tb.xoff[lb + 1] - xb0;
     // scan items: forward item i maps X_i -> X_{i+1}; backward item c-1-i maps X_{i+1} -> X_i
-    jb.nxf[i] = static_cast<uint8_t>(na);
+    jb.nxf[i] = static_cast<uint16_t>(na);
     jb.rsf[i] = cx.first ? 1 : 0;
-    jb.nxb[jb.c - 1 - i] = static_cast<uint8_t>(nb);
+    jb.nxb[jb.c - 1 - i] = static_cast<uint16_t>(nb);
     jb.rsb[jb.c - 1 - i] = cx.last ? 1 : 0;
 
     // forward runs from X_i
@@ -525,28 +526,44 @@ __global__ __launch_bounds__(256) void k_reach(Tabs tb, Job jb) {
             }
         }
     }
-    // maps between entry lists: forward X_i -> X_{i+1}, backward X_{i+1} -> X_i
-    const uint32_t W = tb.W;
+    // maps between entry lists: forward X_i -> X_{i+1}, backward X_{i+1} -> X_i;
+    // row m (ew words) has bit p set when the run from entry m ends in a set
+    // holding the p-th segment of the far list
+    const uint32_t W = tb.W, EW = jb.ew;
     for (uint32_t m = 0; m < na; ++m) {
         uint32_t id = jb.R[static_cast<uint64_t>(m) * jb.c + i];
         const uint64_t *bits = tb.fbits + static_cast<uint64_t>(id) * W;
-        uint64_t row = 0;
-        for (uint32_t p = 0; p < nb; ++p) {
-            uint32_t sg = tb.xlist[xb0 + p];
-            row |= ((bits[sg >> 6] >> (sg & 63)) & 1ull) << p;
+        uint64_t *dst = jb.Mf + (static_cast<uint64_t>(i) * tb.emax + m) * EW;
+        for (uint32_t w = 0; w < EW; ++w) {
+            uint64_t row = 0;
+            for (uint32_t p = 64 * w; p < nb && p < 64 * w + 64; ++p) {
+                uint32_t sg = tb.xlist[xb0 + p];
+                row |= ((bits[sg >> 6] >> (sg & 63)) & 1ull) << (p & 63);
+            }
+            dst[w] = row;
         }
-        jb.Mf[static_cast<uint64_t>(i) * tb.emax + m] = row;
     }
     for (uint32_t m = 0; m < (jb.fwd_only ? 0u : nb); ++m) {
         uint32_t id = jb.Rh[static_cast<uint64_t>(m) * jb.c + i];
         const uint64_t *bits = tb.rbits + static_cast<uint64_t>(id) * W;
-        uint64_t row = 0;
-        for (uint32_t p = 0; p < na; ++p) {
-            uint32_t sg = tb.xlist[xa0 + p];
-            row |= ((bits[sg >> 6] >> (sg & 63)) & 1ull) << p;
+        uint64_t *dst = jb.MbR + (static_cast<uint64_t>(jb.c - 1 - i) * tb.emax + m) * EW;
+        for (uint32_t w = 0; w < EW; ++w) {
+            uint64_t row = 0;
+            for (uint32_t p = 64 * w; p < na && p < 64 * w + 64; ++p) {
+                uint32_t sg = tb.xlist[xa0 + p];
+                row |= ((bits[sg >> 6] >> (sg & 63)) & 1ull) << (p & 63);
+            }
+            dst[w] = row;
         }
-        jb.MbR[static_cast<uint64_t>(jb.c - 1 - i) * tb.emax + m] = row;
     }
+}
+
+// Wavefront-local synchronization: LDS written by some lanes of a wavefront
+// is visible to the other lanes of the same wavefront after this point.
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // Value of v in lane (lane - 1) of the wavefront (lane 0 gets its own value).
@@ -571,7 +588,7 @@ __device__ inline uint64_t shfl_up_u64(uint64_t v, int delta) {
 struct ScanLevel {
     const uint64_t *rows;       // [N][E]
     uint32_t N;
-    const uint8_t *nx;          // [N] input entry-list size per item
+    const uint16_t *nx;         // [N] input entry-list size per item
     const uint8_t *cst;         // [N] level 0: item starts a text; above: constant map
     const uint64_t *cv;         // [N] level >= 1: the constant
     int level0;
@@ -584,7 +601,7 @@ struct ScanPair {
 };
 struct ScanOut {
     uint64_t *rows[2];          // next level
-    uint8_t *nx[2];
+    uint16_t *nx[2];
     uint8_t *cst[2];
     uint64_t *cv[2];
     uint64_t *prow[2];          // prefix maps of this level's items within their group: [N][E]
@@ -697,7 +714,7 @@ __global__ __launch_bounds__(64) void k_compose(ScanPair S, ScanOut O, uint32_t 
     // the group's composite is the next level's item g
     if (k < nx0) O.rows[d][static_cast<uint64_t>(g) * E + k] = fin[(n - 1) * E + k];
     if (k == 0) {
-        O.nx[d][g] = static_cast<uint8_t>(nx0);
+        O.nx[d][g] = static_cast<uint16_t>(nx0);
         O.cst[d][g] = mcst[cur][n - 1];
         O.cv[d][g] = mcv[cur][n - 1];
     }
@@ -726,6 +743,133 @@ __global__ __launch_bounds__(256) void k_expand(ScanPair S, ScanPrefix P, uint32
     if (L.level0) P.vout[d][k] = out;
 }
 
+// ---- join with entry lists of more than 64 segments (masks of EW words)
+//
+// The same segmented scan of maps between entry lists, with every row and
+// vector held as EW words.  One wavefront composes its group of 64 items in
+// order (lanes over the rows of the running prefix map, which go straight to
+// the prefix array), and the expansion stages each item's output in LDS as
+// the next item's input.
+
+// bits [64 w, 64 w + 64) of the mask of the first nx entries
+__device__ inline uint64_t low_mask_word(uint32_t nx, uint32_t w) {
+    if (nx >= 64 * w + 64) return ~0ull;
+    if (nx <= 64 * w) return 0ull;
+    return low_mask(nx - 64 * w);
+}
+
+// Dynamic LDS: two buffers of EW words (the running prefix when constant).
+__global__ __launch_bounds__(64) void k_compose_wide(ScanPair S, ScanOut O, uint32_t E, uint32_t EW) {
+    extern __shared__ uint64_t cvs[];
+    const uint32_t d = blockIdx.y;
+    const ScanLevel L = d ? S.L[1] : S.L[0];
+    const uint32_t g = blockIdx.x, lane = threadIdx.x;
+    const uint32_t k0 = g * 64, n = min(k0 + 64, L.N) - k0;
+    const uint32_t nx0 = L.nx[k0];
+    const uint64_t RS = static_cast<uint64_t>(E) * EW;         // words per map
+    bool pc = false;                                            // the running prefix is constant
+    uint32_t cb = 0;                                            // its value is in cvs[cb * EW ..]
+    for (uint32_t k = 0; k < n; ++k) {
+        const uint64_t it = k0 + k;
+        const uint64_t *rk = L.rows + it * RS;
+        uint64_t *pk = O.prow[d] + it * RS;
+        if (L.cst[it]) {
+            // a constant map: at level 0 a text start, the image of its whole entry list
+            for (uint32_t w = lane; w < EW; w += 64) {
+                uint64_t v = 0;
+                if (L.level0) {
+                    for (uint32_t m = 0; m < L.nx[it]; ++m) v |= rk[static_cast<uint64_t>(m) * EW + w];
+                } else {
+                    v = L.cv[it * EW + w];
+                }
+                cvs[(cb ^ 1u) * EW + w] = v;
+            }
+            cb ^= 1u;
+            pc = true;
+        } else if (k == 0) {
+            for (uint32_t m = lane; m < nx0; m += 64)
+                for (uint32_t w = 0; w < EW; ++w) pk[static_cast<uint64_t>(m) * EW + w] = rk[static_cast<uint64_t>(m) * EW + w];
+        } else if (pc) {
+            // item k after a constant prefix: the constant's image
+            const uint64_t *cv = cvs + cb * EW;
+            for (uint32_t w = lane; w < EW; w += 64) {
+                uint64_t v = 0;
+                for (uint32_t e = 0; e < EW; ++e)
+                    for (uint64_t x = cv[e]; x; x &= x - 1)
+                        v |= rk[(64ull * e + __builtin_ctzll(x)) * EW + w];
+                cvs[(cb ^ 1u) * EW + w] = v;
+            }
+            cb ^= 1u;
+        } else {
+            // row m of the new prefix: item k applied to row m of the previous prefix
+            const uint64_t *pp = O.prow[d] + (it - 1) * RS;
+            for (uint32_t m = lane; m < nx0; m += 64) {
+                const uint64_t *prv = pp + static_cast<uint64_t>(m) * EW;
+                for (uint32_t w = 0; w < EW; ++w) {
+                    uint64_t v = 0;
+                    for (uint32_t e = 0; e < EW; ++e)
+                        for (uint64_t x = prv[e]; x; x &= x - 1)
+                            v |= rk[(64ull * e + __builtin_ctzll(x)) * EW + w];
+                    pk[static_cast<uint64_t>(m) * EW + w] = v;
+                }
+            }
+        }
+        wave_sync();
+        if (lane == 0) O.pcst[d][it] = pc ? 1 : 0;
+        for (uint32_t w = lane; w < EW; w += 64) O.pcv[d][it * EW + w] = pc ? cvs[cb * EW + w] : 0ull;
+    }
+    // the group's composite is the next level's item g
+    const uint64_t last = k0 + n - 1;
+    if (pc) {
+        for (uint32_t w = lane; w < EW; w += 64) O.cv[d][static_cast<uint64_t>(g) * EW + w] = cvs[cb * EW + w];
+    } else {
+        const uint64_t *pl = O.prow[d] + last * RS;
+        for (uint32_t m = lane; m < nx0; m += 64)
+            for (uint32_t w = 0; w < EW; ++w)
+                O.rows[d][static_cast<uint64_t>(g) * RS + static_cast<uint64_t>(m) * EW + w] =
+                    pl[static_cast<uint64_t>(m) * EW + w];
+        for (uint32_t w = lane; w < EW; w += 64) O.cv[d][static_cast<uint64_t>(g) * EW + w] = 0ull;
+    }
+    if (lane == 0) {
+        O.nx[d][g] = static_cast<uint16_t>(nx0);
+        O.cst[d][g] = pc ? 1 : 0;
+    }
+}
+
+// Dynamic LDS: blockDim x EW words (each item's output).
+__global__ __launch_bounds__(256) void k_expand_wide(ScanPair S, ScanPrefix P, uint32_t E, uint32_t EW) {
+    extern __shared__ uint64_t outs[];
+    const uint32_t d = blockIdx.y;
+    const ScanLevel L = d ? S.L[1] : S.L[0];
+    const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t lane = threadIdx.x & 63, g = k >> 6;
+    const bool act = k < L.N;
+    const uint64_t *vp = act && P.pvec[d] ? P.pvec[d] + static_cast<uint64_t>(g) * EW : nullptr;
+    const uint64_t RS = static_cast<uint64_t>(E) * EW;
+    const bool cst = act && P.pcst[d][k] != 0;
+    for (uint32_t w = 0; w < EW; ++w) {
+        uint64_t o = 0;
+        if (act) {
+            if (cst) {
+                o = P.pcv[d][static_cast<uint64_t>(k) * EW + w];
+            } else if (vp) {
+                const uint64_t *rows = P.prow[d] + k * RS;
+                for (uint32_t e = 0; e < EW; ++e)
+                    for (uint64_t x = vp[e]; x; x &= x - 1) o |= rows[(64ull * e + __builtin_ctzll(x)) * EW + w];
+            }
+            if (L.level0) P.vout[d][static_cast<uint64_t>(k) * EW + w] = o;
+        }
+        outs[threadIdx.x * EW + w] = o;
+    }
+    __syncthreads();
+    if (!act) return;
+    for (uint32_t w = 0; w < EW; ++w) {
+        uint64_t in = lane == 0 ? (vp ? vp[w] : 0ull) : outs[(threadIdx.x - 1) * EW + w];
+        if (L.level0 && L.cst[k]) in = low_mask_word(L.nx[k], w);
+        P.vin[d][static_cast<uint64_t>(k) * EW + w] = in;
+    }
+}
+
 // Join sets and build start ids.  Thread i handles chunk i: fid_i = id of
 // J at P_i, rid_i = id of J^ at P_{i+1}; the last chunk of a text writes its
 // accept flag.
@@ -735,20 +879,23 @@ __global__ __launch_bounds__(256) void k_starts(Tabs tb, Job jb) {
     if (i >= c) return;
     const ChunkCtx cx = chunk_ctx(jb, i);
     uint64_t acc[kMaxWords];
+    const uint32_t EW = jb.ew;
     // J at the right edge of chunk k: union of the ends of its runs selected by fin[k]
     auto join_fwd = [&](uint32_t k) -> uint32_t {
-        uint64_t sel = jb.fin[k];
         for (uint32_t w = 0; w < W; ++w) acc[w] = 0;
         uint32_t first = 0xffffffffu;
         bool same = true;
-        while (sel) {
-            int m = __builtin_ctzll(sel);
-            sel &= sel - 1;
-            uint32_t id = jb.R[static_cast<uint64_t>(m) * c + k];
-            if (first == 0xffffffffu) first = id;
-            same = same && (id == first);
-            const uint64_t *bt = tb.fbits + static_cast<uint64_t>(id) * W;
-            for (uint32_t w = 0; w < W; ++w) acc[w] |= bt[w];
+        for (uint32_t e = 0; e < EW; ++e) {
+            uint64_t sel = jb.fin[static_cast<uint64_t>(k) * EW + e];
+            while (sel) {
+                const uint32_t m = 64 * e + static_cast<uint32_t>(__builtin_ctzll(sel));
+                sel &= sel - 1;
+                uint32_t id = jb.R[static_cast<uint64_t>(m) * c + k];
+                if (first == 0xffffffffu) first = id;
+                same = same && (id == first);
+                const uint64_t *bt = tb.fbits + static_cast<uint64_t>(id) * W;
+                for (uint32_t w = 0; w < W; ++w) acc[w] |= bt[w];
+            }
         }
         if (first == 0xffffffffu) return 0;
         if (same) return first;
@@ -756,18 +903,21 @@ __global__ __launch_bounds__(256) void k_starts(Tabs tb, Job jb) {
     };
     // J^ at the left edge of chunk k: union of its backward runs selected by the mask at its right edge
     auto join_bwd = [&](uint32_t k) -> uint32_t {
-        uint64_t sel = jb.bin[c - 1 - k];      // reversed item c-1-k enters at chunk k's right edge
         for (uint32_t w = 0; w < W; ++w) acc[w] = 0;
         uint32_t first = 0xffffffffu;
         bool same = true;
-        while (sel) {
-            int m = __builtin_ctzll(sel);
-            sel &= sel - 1;
-            uint32_t id = jb.Rh[static_cast<uint64_t>(m) * c + k];
-            if (first == 0xffffffffu) first = id;
-            same = same && (id == first);
-            const uint64_t *bt = tb.rbits + static_cast<uint64_t>(id) * W;
-            for (uint32_t w = 0; w < W; ++w) acc[w] |= bt[w];
+        for (uint32_t e = 0; e < EW; ++e) {
+            // reversed item c-1-k enters at chunk k's right edge
+            uint64_t sel = jb.bin[static_cast<uint64_t>(c - 1 - k) * EW + e];
+            while (sel) {
+                const uint32_t m = 64 * e + static_cast<uint32_t>(__builtin_ctzll(sel));
+                sel &= sel - 1;
+                uint32_t id = jb.Rh[static_cast<uint64_t>(m) * c + k];
+                if (first == 0xffffffffu) first = id;
+                same = same && (id == first);
+                const uint64_t *bt = tb.rbits + static_cast<uint64_t>(id) * W;
+                for (uint32_t w = 0; w < W; ++w) acc[w] |= bt[w];
+            }
         }
         if (first == 0xffffffffu) return 0;
         if (same) return first;
@@ -792,7 +942,11 @@ __global__ __launch_bounds__(256) void k_starts(Tabs tb, Job jb) {
             for (uint32_t w = 0; w < W; ++w) Jh[w] = e[w];
         }
     }
-    if (cx.last) cx.tr.scalars[0] = jb.fout[i] != 0 ? 1ull : 0ull;
+    if (cx.last) {
+        uint64_t any = 0;
+        for (uint32_t e = 0; e < EW; ++e) any |= jb.fout[static_cast<uint64_t>(i) * EW + e];
+        cx.tr.scalars[0] = any != 0 ? 1ull : 0ull;
+    }
 }
 
 // -------------------------------------------------------------------- build
@@ -857,13 +1011,6 @@ __device__ inline uint64_t shfl_u64(uint64_t v, int src) {
     return (static_cast<uint64_t>(hi) << 32) | lo;
 }
 
-// Wavefront-local synchronization: LDS written by some lanes of a wavefront
-// is visible to the other lanes of the same wavefront after this point.
-__device__ inline void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // Classes of the 64 window bytes, packed four per word.
 template <class BT>

@@ -34,6 +34,7 @@ struct Request {
     uint64_t n;
     uint64_t tag;
     uint64_t off = 0, bytes = 0, forest = 0;   // arena range; SLPF bytes inside it
+    slpf_status st = SLPF_OK;                  // why the request could not be parsed
 };
 
 struct Slot {
@@ -92,7 +93,9 @@ void arena_free(slpf_server *s, uint64_t off, uint64_t bytes) {
 }
 
 // Admit requests from the queue head into a free slot and launch them as one
-// job; *launched is false when the head does not fit in the arena.
+// job; *launched is false when the head does not fit in the arena, or when
+// no admitted request could be launched (those are reported finished with
+// their error status).
 slpf_status launch(slpf_server *s, Slot &sl, bool *launched) {
     *launched = false;
     std::vector<Request> batch;
@@ -110,8 +113,10 @@ slpf_status launch(slpf_server *s, Slot &sl, bool *launched) {
     slpf_parse_opts po{};
     po.struct_size = sizeof(po);
     po.flags = s->o.parse_flags;
-    slpf_status st = SLPF_OK;
+    // a parser whose job cannot be launched fails its own requests only; they
+    // are reported finished with that status (no GPU work reads their range)
     std::vector<slpf_text> items;
+    std::vector<Request> ran, failed;
     for (const slpf_parser *p : order) {
         if (std::find(s->used.begin(), s->used.end(), p) == s->used.end()) s->used.push_back(p);
         items.clear();
@@ -125,15 +130,29 @@ slpf_status launch(slpf_server *s, Slot &sl, bool *launched) {
             t.out.scalars_dev = reinterpret_cast<uint64_t *>(s->arena + r.off + round_up(r.forest));
             items.push_back(t);
         }
-        st = slpf_parse_batch(p, items.data(), items.size(), &po, sl.stream);
-        if (st != SLPF_OK) break;
+        const slpf_status st = slpf_parse_batch(p, items.data(), items.size(), &po, sl.stream);
+        for (Request r : batch) {
+            if (r.p != p) continue;
+            r.st = st;
+            (st == SLPF_OK ? ran : failed).push_back(r);
+        }
     }
-    if (st == SLPF_OK && hipEventRecord(sl.done, sl.stream) != hipSuccess) st = SLPF_E_DEVICE;
-    if (st != SLPF_OK) {   // nothing of this batch is reported; give its space back
-        for (const Request &r : batch) arena_free(s, r.off, r.bytes);
-        return st;
+    for (const Request &r : failed) {
+        s->finished[r.tag] = r;
+        s->done.push_back(r.tag);
     }
-    sl.reqs = std::move(batch);
+    if (ran.empty()) return SLPF_OK;
+    if (hipEventRecord(sl.done, sl.stream) != hipSuccess) {
+        // the launched jobs cannot be tracked: wait for them here
+        const slpf_status st = hipStreamSynchronize(sl.stream) == hipSuccess ? SLPF_OK : SLPF_E_DEVICE;
+        for (Request r : ran) {
+            if (st != SLPF_OK) r.st = st;
+            s->finished[r.tag] = r;
+            s->done.push_back(r.tag);
+        }
+        return SLPF_OK;
+    }
+    sl.reqs = std::move(ran);
     sl.busy = true;
     *launched = true;
     return SLPF_OK;
@@ -223,7 +242,7 @@ slpf_status slpf_server_poll(slpf_server *s, uint64_t *done_tags, size_t cap, si
         bool launched = false;
         slpf_status st = launch(s, sl, &launched);
         if (st != SLPF_OK) return st;
-        if (!launched) break;    // the queue head does not fit yet
+        if (!launched) break;    // the queue head does not fit yet (or the admitted requests all failed)
     }
     while (*n_done < cap && !s->done.empty()) {
         done_tags[(*n_done)++] = s->done.front();
@@ -240,7 +259,7 @@ slpf_status slpf_server_result(const slpf_server *s, uint64_t tag, slpf_forest *
     out->columns_dev = reinterpret_cast<uint64_t *>(s->arena + r.off);
     out->capacity_bytes = r.forest;
     out->scalars_dev = reinterpret_cast<uint64_t *>(s->arena + r.off + round_up(r.forest));
-    return SLPF_OK;
+    return r.st;
 }
 
 slpf_status slpf_server_release(slpf_server *s, uint64_t tag) {

@@ -454,6 +454,7 @@ slpf_status slpf_decode_compact(const slpf_parser *cp, const uint8_t *text_dev, 
                                 const uint64_t *compact_dev, uint64_t *columns_dev, void *hip_stream) {
     const slpf_parser *p = cp;
     if (!p || p->host_only || !compact_dev || !columns_dev || (n && !text_dev)) return SLPF_E_ARG;
+    if (p->A.max_entries > static_cast<uint32_t>(kMaxEntries)) return SLPF_E_TOO_LARGE;   // no compact form
     if (hipSetDevice(p->device) != hipSuccess) return SLPF_E_DEVICE;
     const uint64_t cols = n + 1;
     const uint64_t blocks = (cols + 255) / 256;
@@ -486,13 +487,13 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
     Tabs tb = p->tabs;
     // speculation entry lists: reduced (default) or filtered by the next byte only
     Tabs ts = tb;
+    if ((flags & SLPF_PARSE_COMPACT) && tb.emax > static_cast<uint32_t>(kMaxEntries)) return SLPF_E_TOO_LARGE;
     if (flags & SLPF_PARSE_NEXT_BYTE_ENTRIES) {
-        if (tb.emax_nb > static_cast<uint32_t>(kMaxEntries)) return SLPF_E_TOO_LARGE;
         ts.xoff = tb.xoff_nb;
         ts.xlist = tb.xlist_nb;
         ts.emax = tb.emax_nb;
     }
-    const uint32_t W = tb.W, E = ts.emax;
+    const uint32_t W = tb.W, E = ts.emax, EW = (E + 63) / 64;
     uint64_t total = 0;
     for (size_t t = 0; t < T; ++t) total += items[t].n;
     const uint64_t s = chunk_bytes_for(total, opts);
@@ -525,10 +526,10 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
     Layout L;
     int itd = L.add(T > 1 ? T * 32 + (T + 1) * 4 + 64 : 8);
     int iR = L.add(size_t(E) * c * 2), iRh = L.add(size_t(E) * c * 2);
-    int iMf = L.add(size_t(c) * E * 8), iMb = L.add(size_t(c) * E * 8);
-    int inxf = L.add(c + 1), inxb = L.add(c + 1), irsf = L.add(c + 1), irsb = L.add(c + 1);
-    int ifin = L.add(size_t(c + 1) * 8), ifout = L.add(size_t(c + 1) * 8);
-    int ibin = L.add(size_t(c + 1) * 8), ibout = L.add(size_t(c + 1) * 8);
+    int iMf = L.add(size_t(c) * E * EW * 8), iMb = L.add(size_t(c) * E * EW * 8);
+    int inxf = L.add(size_t(c + 1) * 2), inxb = L.add(size_t(c + 1) * 2), irsf = L.add(c + 1), irsb = L.add(c + 1);
+    int ifin = L.add(size_t(c + 1) * EW * 8), ifout = L.add(size_t(c + 1) * EW * 8);
+    int ibin = L.add(size_t(c + 1) * EW * 8), ibout = L.add(size_t(c + 1) * EW * 8);
     int ifid = L.add(size_t(c) * 2), irid = L.add(size_t(c) * 2);
     int ickpt = L.add(nck * 2), ibckpt = L.add(nck * 2);
     int iflags = L.add(16);
@@ -539,14 +540,14 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
     for (size_t l = 0; l <= TL; ++l)
         for (int d = 0; d < 2; ++d) {
             const size_t N = jl[l];
-            jrows[d].push_back(l ? L.add(N * E * 8) : -1);
-            jnx[d].push_back(l ? L.add(N + 1) : -1);
+            jrows[d].push_back(l ? L.add(N * E * EW * 8) : -1);
+            jnx[d].push_back(l ? L.add((N + 1) * 2) : -1);
             jisc[d].push_back(l ? L.add(N + 1) : -1);
-            jcv[d].push_back(l ? L.add((N + 1) * 8) : -1);
-            jvec[d].push_back(l ? L.add((N + 1) * 8) : -1);
-            jprow[d].push_back(l < TL ? L.add(N * E * 8) : -1);
+            jcv[d].push_back(l ? L.add((N + 1) * EW * 8) : -1);
+            jvec[d].push_back(l ? L.add((N + 1) * EW * 8) : -1);
+            jprow[d].push_back(l < TL ? L.add(N * E * EW * 8) : -1);
             jpcst[d].push_back(l < TL ? L.add(N + 1) : -1);
-            jpcv[d].push_back(l < TL ? L.add((N + 1) * 8) : -1);
+            jpcv[d].push_back(l < TL ? L.add((N + 1) * EW * 8) : -1);
         }
     // tree count: run marks per 64-column window (as the checkpoints), chunk
     // and text products, and the lists of the run kernels.  Long runs (more
@@ -637,8 +638,9 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
     jb.Rh = reinterpret_cast<uint16_t *>(ptr(iRh));
     jb.Mf = reinterpret_cast<uint64_t *>(ptr(iMf));
     jb.MbR = reinterpret_cast<uint64_t *>(ptr(iMb));
-    jb.nxf = ptr(inxf);
-    jb.nxb = ptr(inxb);
+    jb.nxf = reinterpret_cast<uint16_t *>(ptr(inxf));
+    jb.nxb = reinterpret_cast<uint16_t *>(ptr(inxb));
+    jb.ew = EW;
     jb.rsf = ptr(irsf);
     jb.rsb = ptr(irsb);
     jb.fin = reinterpret_cast<uint64_t *>(ptr(ifin));
@@ -715,7 +717,7 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
                     x.cv = nullptr;
                 } else {
                     x.rows = u64p(jrows[d][l]);
-                    x.nx = ptr(jnx[d][l]);
+                    x.nx = reinterpret_cast<const uint16_t *>(ptr(jnx[d][l]));
                     x.cst = ptr(jisc[d][l]);
                     x.cv = u64p(jcv[d][l]);
                 }
@@ -726,14 +728,18 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
             ScanOut o{};
             for (int d = 0; d < 2; ++d) {
                 o.rows[d] = u64p(jrows[d][l + 1]);
-                o.nx[d] = ptr(jnx[d][l + 1]);
+                o.nx[d] = reinterpret_cast<uint16_t *>(ptr(jnx[d][l + 1]));
                 o.cst[d] = ptr(jisc[d][l + 1]);
                 o.cv[d] = u64p(jcv[d][l + 1]);
                 o.prow[d] = u64p(jprow[d][l]);
                 o.pcst[d] = ptr(jpcst[d][l]);
                 o.pcv[d] = u64p(jpcv[d][l]);
             }
-            hipLaunchKernelGGL(k_compose, dim3(jl[l + 1], ndir), dim3(64), grp_lds, stream, lv[l], o, E);
+            if (EW == 1)
+                hipLaunchKernelGGL(k_compose, dim3(jl[l + 1], ndir), dim3(64), grp_lds, stream, lv[l], o, E);
+            else
+                hipLaunchKernelGGL(k_compose_wide, dim3(jl[l + 1], ndir), dim3(64), 2 * EW * 8, stream, lv[l], o, E,
+                                   EW);
         }
         for (size_t l = TL; l-- > 0;) {
             ScanPrefix pf{};
@@ -750,7 +756,11 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
                     pf.vout[d] = nullptr;
                 }
             }
-            hipLaunchKernelGGL(k_expand, dim3((jl[l] + 255) / 256, ndir), dim3(256), 0, stream, lv[l], pf, E);
+            if (EW == 1)
+                hipLaunchKernelGGL(k_expand, dim3((jl[l] + 255) / 256, ndir), dim3(256), 0, stream, lv[l], pf, E);
+            else
+                hipLaunchKernelGGL(k_expand_wide, dim3((jl[l] + 255) / 256, ndir), dim3(256), 256 * EW * 8, stream,
+                                   lv[l], pf, E, EW);
         }
     }
     mark(2);

@@ -11,7 +11,7 @@
 
 namespace slpf {
 
-constexpr int kMaxEntries = 64;     // entries of one speculative entry list (u64 masks)
+constexpr int kMaxEntries = 64;     // entries of a list that one u64 mask holds (the compact SLPF's limit)
 constexpr int kMaxWords = 32;       // words per SLPF column handled by the kernels
 constexpr uint32_t kHashEmpty = 0xffffffffu;
 constexpr uint16_t kNoSole = 0xffffu;  // state set with zero or several segments

@@ -163,21 +163,13 @@ def test_batch_argument_errors():
     torch.cuda.synchronize()
 
 
-def _fits(re):
-    try:
-        S.Parser(re, host_only=True)
-        return True
-    except S.SlpfError:
-        return False
-
-
 def test_batched_re_family_vs_oracle():
     # the batched workload's 16 REs (4, 26 and 128-symbol alphabets and the
     # motif RE), 64 texts of log-uniform length 256 B - 64 KiB, one job per RE
     import torch
     from gen import workloads as wl
     device()
-    res = wl.batched_res(_fits)
+    res = wl.batched_res()
     assert len(res) == 16
     texts = wl.texts_for(res, wl.loguniform_lengths(7, 64, lo=256, hi=64 << 10), 8)
     for q, (name, tree) in enumerate(res):

@@ -73,11 +73,7 @@ def test_random_res_and_texts(seed):
     depth = int(rng.integers(4, 8))
     tree = regen.random_re(200 + seed, n_ops=int(rng.integers(6, 4 * depth)), max_depth=depth, alphabet=alpha)
     pat = regen.to_re(tree)
-    try:
-        p = S.Parser(pat)
-    except S.SlpfError as e:   # entry lists beyond 64 segments: a documented limit
-        assert e.status == S.E_TOO_LARGE
-        pytest.skip("automaton beyond the library limits")
+    p = S.Parser(pat)
     o = Oracle(pat)
     n = int(rng.integers(1, 20000))
     text = textgen.sample_text(tree, seed, n).tobytes()
@@ -231,8 +227,6 @@ def test_next_byte_entries_give_the_same_slpf():
     for pat, texts in cases:
         o, p = Oracle(pat), S.Parser(pat)
         assert p.info.max_entries_next_byte >= p.info.max_entries
-        if p.info.max_entries_next_byte > 64:
-            continue
         for t in texts:
             cols, acc, cnt = o.parse(t)
             for k in (64, 0):
@@ -243,3 +237,45 @@ def test_next_byte_entries_give_the_same_slpf():
                 p.parse_into(to_device(t), len(t), None, sc, k, S.PARSE_RECOGNIZE | S.PARSE_NEXT_BYTE_ENTRIES)
                 torch.cuda.synchronize()
                 assert bool(sc.cpu().numpy()[0]) == acc
+
+
+def _max_candidates(o, alpha):
+    """Longest candidate (entry) list of the oracle's automaton over byte pairs."""
+    best = 0
+    for a in [None] + list(alpha):
+        for b in list(alpha) + [None]:
+            best = max(best, len(o.candidates(a, b)))
+    return best
+
+
+def test_entry_lists_over_64_segments():
+    # 4-letter REs whose entry lists hold 65 to 200 segments (chosen on the
+    # oracle's own candidate lists): the join masks take several words; texts
+    # sampled from the language, corrupted ones, lane chunks from one window up
+    found = []
+    seed = 900
+    while len(found) < 4 and seed < 1400:
+        seed += 1
+        try:
+            tree = regen.random_re(seed, n_ops=int(14 + seed % 17), max_depth=6, alphabet=b"ACGT")
+        except RuntimeError:
+            continue
+        pat = regen.to_re(tree)
+        o = Oracle(pat)
+        e = _max_candidates(o, b"ACGT")
+        if 64 < e <= 200:
+            found.append((tree, pat, o, e))
+    assert len(found) == 4
+    for tree, pat, o, e in found:
+        p = S.Parser(pat)
+        assert p.info.max_entries == e
+        say("wide entry lists", e, pat[:60])
+        text = textgen.sample_text(tree, 3, 12000).tobytes()
+        for k in (64, 256, 0):
+            check(pat, text, chunk_bytes=k, o=o, p=p)
+        bad = textgen.corrupt(np.frombuffer(text, np.uint8), 5, 0.01, (1, 8)).tobytes()
+        check(pat, bad, chunk_bytes=128, o=o, p=p)
+        # the compact SLPF has no one-word form for such lists
+        with pytest.raises(S.SlpfError) as err:
+            p.parse_compact(to_device(text))
+        assert err.value.status == S.E_TOO_LARGE

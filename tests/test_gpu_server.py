@@ -22,16 +22,8 @@ def say(*a):
     sys.stdout.flush()
 
 
-def _fits(re):
-    try:
-        S.Parser(re, host_only=True)
-        return True
-    except S.SlpfError:
-        return False
-
-
 def _workload(n_res, n_req, seed, median=2048, cap=1 << 16):
-    res = wl.served_res(_fits)[:n_res]
+    res = wl.served_res()[:n_res]
     lengths = wl.lognormal_lengths(seed, n_req, median=median, sigma=1.5, cap=cap)
     texts = wl.texts_for(res, lengths, seed + 1)
     return res, texts
@@ -126,12 +118,56 @@ def test_server_compact_alone_vs_mix():
     while len(done) < len(texts):
         for tag in srv.poll():
             r, x = texts[tag]
-            done[tag] = srv.result_tensors(tag, x.size, parsers[r].W)
+            if parsers[r].info.max_entries > 64:
+                # no compact form for entry lists over 64 segments: the request
+                # is reported with the error, the rest of its slot is not affected
+                with pytest.raises(S.SlpfError) as e:
+                    srv.result(tag)
+                assert e.value.status == S.E_TOO_LARGE
+                done[tag] = None
+            else:
+                done[tag] = srv.result_tensors(tag, x.size, parsers[r].W)
             srv.release(tag)
     srv.close()
     for k, (r, x) in enumerate(texts):
+        if done[k] is None:
+            continue
         cmp, sc = parsers[r].parse_compact(dts[k])
         torch.cuda.synchronize()
         cols, s2 = done[k]
         assert np.array_equal(cols, cmp.cpu().numpy().view(np.uint64)), k
         assert np.array_equal(s2, sc.cpu().numpy().view(np.uint64)), k
+
+
+def test_server_failed_parser_fails_only_its_requests():
+    # a parser compiled for the host only cannot run a job: its requests are
+    # reported finished with the error, the other parser's requests in the
+    # same slot finish normally, and every arena range comes back on release
+    import torch
+    device()
+    good = S.Parser("(ab|a)*")
+    bad = S.Parser("(ab|a)*", host_only=True)
+    srv = S.Server(slots=1, max_batch_texts=8, memory_budget=1 << 20)
+    texts = [b"abab", b"aab", b"ab" * 100, b"abaaba"]
+    dts = [to_device(t) for t in texts]
+    for k, (t, d) in enumerate(zip(texts, dts)):
+        srv.submit(bad if k % 2 else good, d, len(t), k)
+    done = set()
+    for _ in range(10000):
+        done.update(srv.poll())
+        if len(done) == len(texts):
+            break
+    assert done == set(range(len(texts)))
+    for k, t in enumerate(texts):
+        if k % 2:
+            with pytest.raises(S.SlpfError) as e:
+                srv.result(k)
+            assert e.value.status == S.E_ARG
+        else:
+            cols, sc = srv.result_tensors(k, len(t), good.W)
+            alone = gpu_parse(good, t)
+            assert np.array_equal(cols, alone[0]) and bool(sc[0]) == alone[1] and int(sc[1]) == alone[2]
+        srv.release(k)
+    assert srv.stats()["admitted_bytes"] == 0
+    srv.close()
+    torch.cuda.synchronize()
