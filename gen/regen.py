@@ -24,7 +24,7 @@ from __future__ import annotations
 
 import numpy as np
 
-META = set(b"()|*+?\\")
+META = set(b"()|*+?\\.[]")
 
 
 def lit(ch):

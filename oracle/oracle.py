@@ -48,6 +48,7 @@ def _load():
         L.oracle_folseg.argtypes = [vp, ctypes.c_int, u64p]
         L.oracle_label.argtypes = [vp, ctypes.c_int]
         L.oracle_label.restype = ctypes.c_int
+        L.oracle_label_set.argtypes = [vp, ctypes.c_int, u64p]
         L.oracle_segment_text.argtypes = [vp, ctypes.c_int, ctypes.c_char_p, ctypes.c_size_t]
         L.oracle_segment_text.restype = ctypes.c_size_t
         L.oracle_step_fwd.argtypes = [vp, u64p, ctypes.c_int, u64p]
@@ -103,7 +104,14 @@ class Oracle:
         self.nseg = L.oracle_num_segments(h)
         self.W = L.oracle_words(h)
         self.segments = [self._seg_text(i) for i in range(self.nseg)]
+        # the byte of each end-letter (-2 for a character set, -1 for the end
+        # mark) and the set of bytes it matches
         self.labels = [L.oracle_label(h, i) for i in range(self.nseg)]
+        self.label_sets = []
+        for i in range(self.nseg):
+            w = np.zeros(4, np.uint64)
+            L.oracle_label_set(h, i, _u64(w))
+            self.label_sets.append(frozenset(b for b in range(256) if (int(w[b >> 6]) >> (b & 63)) & 1))
         self.I = self._words(L.oracle_initial)
         self.F = self._words(L.oracle_final)
         self.folseg = []
@@ -209,7 +217,7 @@ class Oracle:
         """States (as frozensets, BFS order from the seeds) and transitions
         {(state_index, byte): state_index or None}."""
         if alphabet is None:
-            alphabet = sorted({a for a in self.labels if a >= 0})
+            alphabet = sorted(frozenset().union(*self.label_sets)) if self.label_sets else []
         seeds = list(seeds)
         sw = np.stack([self.to_words(s) for s in seeds]) if seeds else np.zeros((0, self.W), np.uint64)
         sw = np.ascontiguousarray(sw)
@@ -250,9 +258,9 @@ class Oracle:
         if prev is None:
             pool = self.I
         else:
-            pool = frozenset().union(*([self.folseg[r] for r in range(self.nseg) if self.labels[r] == prev] or
+            pool = frozenset().union(*([self.folseg[r] for r in range(self.nseg) if prev in self.label_sets[r]] or
                                        [frozenset()]))
-        keep = self.F if nxt is None else frozenset(s for s in range(self.nseg) if self.labels[s] == nxt)
+        keep = self.F if nxt is None else frozenset(s for s in range(self.nseg) if nxt in self.label_sets[s])
         return sorted(pool & keep)
 
     def compact(self, text, cols=None):

@@ -57,7 +57,9 @@ enum { K_LIT, K_EPS, K_CAT, K_ALT, K_STAR, K_PLUS, K_OPT };
 
 typedef struct {
     int kind;
-    int byte;      /* terminal value for K_LIT */
+    int byte;      /* K_LIT: the terminal byte, or -2 for a character set */
+    int form;      /* K_LIT: 0 a byte, 1 a bracketed set, 2 the wildcard */
+    uint64_t set[4];   /* K_LIT: the bytes the terminal matches */
     int nkids;
     int kids_cap;
     int *kids;
@@ -78,7 +80,8 @@ typedef struct {
     int nseg, cap_seg;
     int *seg_len;
     int **seg_syms;
-    int *seg_label;          /* byte of the end-letter, -1 for the end mark */
+    int *seg_label;          /* byte of the end-letter, -2 for a set, -1 for the end mark */
+    uint64_t *seg_set;       /* nseg x 4: the bytes the end-letter matches (none for the end mark) */
     int W;
     uint64_t *I, *F;         /* W words each */
     uint64_t *folseg;        /* nseg x W */
@@ -124,9 +127,72 @@ static int hexval(int c) {
     return -1;
 }
 
+/* one byte of a set or a terminal, after an optional backslash; -1 on error */
+static int rd_byte(rd_t *r) {
+    if (r->pos >= r->n) return -1;
+    int c = r->s[r->pos++];
+    if (c != '\\') return c;
+    if (r->pos >= r->n) return -1;
+    int e = r->s[r->pos++];
+    if (e == 'n') return '\n';
+    if (e == 't') return '\t';
+    if (e == 'x') {
+        if (r->pos + 2 > r->n) return -1;
+        int h1 = hexval(r->s[r->pos]), h2 = hexval(r->s[r->pos + 1]);
+        if (h1 < 0 || h2 < 0) return -1;
+        r->pos += 2;
+        return h1 * 16 + h2;
+    }
+    return e;
+}
+
+/* character set "[...]" (App. A, character features): bytes and ranges a-z,
+ * a leading ^ complements; "]" first or escaped is a member.  Empty sets are
+ * errors. */
+static int rd_set(rd_t *r) {
+    uint64_t m[4] = {0, 0, 0, 0};
+    r->pos++;                                            /* '[' */
+    int neg = 0, first = 1;
+    if (r->pos < r->n && r->s[r->pos] == '^') { neg = 1; r->pos++; }
+    for (;;) {
+        if (r->pos >= r->n) { r->err = 1; return -1; }
+        if (r->s[r->pos] == ']' && !first) { r->pos++; break; }
+        first = 0;
+        int lo = rd_byte(r);
+        if (lo < 0) { r->err = 1; return -1; }
+        int hi = lo;
+        if (r->pos + 1 < r->n && r->s[r->pos] == '-' && r->s[r->pos + 1] != ']') {
+            r->pos++;
+            hi = rd_byte(r);
+            if (hi < 0 || hi < lo) { r->err = 1; return -1; }
+        }
+        for (int b = lo; b <= hi; b++) m[b >> 6] |= 1ull << (b & 63);
+    }
+    int any = 0;
+    for (int k = 0; k < 4; k++) { if (neg) m[k] = ~m[k]; any |= m[k] != 0; }
+    if (!any) { r->err = 1; return -1; }
+    int x = new_node(r->o, K_LIT);
+    onode *v = &r->o->nodes[x];
+    v->byte = -2;
+    v->form = 1;
+    memcpy(v->set, m, sizeof m);
+    return x;
+}
+
 static int rd_atom(rd_t *r) {
     if (r->pos >= r->n) { r->err = 1; return -1; }
     int c = r->s[r->pos];
+    if (c == '[') return rd_set(r);
+    if (c == '.') {                                      /* wildcard: any byte but newline */
+        r->pos++;
+        int x = new_node(r->o, K_LIT);
+        onode *v = &r->o->nodes[x];
+        v->byte = -2;
+        v->form = 2;
+        for (int k = 0; k < 4; k++) v->set[k] = ~0ull;
+        v->set['\n' >> 6] &= ~(1ull << ('\n' & 63));
+        return x;
+    }
     if (c == '(') {
         r->pos++;
         if (r->pos < r->n && r->s[r->pos] == ')') {   /* "()" is epsilon */
@@ -157,6 +223,7 @@ static int rd_atom(rd_t *r) {
     }
     int x = new_node(r->o, K_LIT);
     r->o->nodes[x].byte = b;
+    r->o->nodes[x].set[b >> 6] = 1ull << (b & 63);
     return x;
 }
 
@@ -409,10 +476,12 @@ int oracle_compile(const unsigned char *re, size_t re_len, int max_segments,
     o->I = (uint64_t *)calloc(o->W, 8);
     o->F = (uint64_t *)calloc(o->W, 8);
     o->seg_label = (int *)malloc(sizeof(int) * o->nseg);
+    o->seg_set = (uint64_t *)calloc((size_t)o->nseg * 4, 8);
     o->folseg = (uint64_t *)calloc((size_t)o->nseg * o->W, 8);
     for (int i = 0; i < o->nseg; i++) {
         int e = o->seg_syms[i][o->seg_len[i] - 1];
         o->seg_label[i] = e == o->sym_end ? -1 : o->nodes[o->sym_node[e]].byte;
+        if (e != o->sym_end) memcpy(o->seg_set + 4 * (size_t)i, o->nodes[o->sym_node[e]].set, 32);
         if (o->seg_syms[i][0] == o->first_sym) SET_BIT(o->I, i);
         if (e == o->sym_end) SET_BIT(o->F, i);
     }
@@ -437,7 +506,7 @@ void oracle_free(oracle_t *o) {
     free(o->fol);
     free(o->sym_node);
     for (int i = 0; i < o->nseg; i++) free(o->seg_syms[i]);
-    free(o->seg_syms); free(o->seg_len); free(o->seg_label);
+    free(o->seg_syms); free(o->seg_len); free(o->seg_label); free(o->seg_set);
     free(o->I); free(o->F); free(o->folseg);
     lazy_free(o->dfa[0]); lazy_free(o->dfa[1]);
     free(o);
@@ -452,10 +521,19 @@ void oracle_folseg(const oracle_t *o, int seg, uint64_t *out) {
     memcpy(out, o->folseg + (size_t)seg * o->W, 8 * o->W);
 }
 int oracle_label(const oracle_t *o, int seg) { return o->seg_label[seg]; }
+void oracle_label_set(const oracle_t *o, int seg, uint64_t *out) { memcpy(out, o->seg_set + 4 * (size_t)seg, 32); }
+
+/* a byte inside a set's text: letters and digits as themselves, others \xHH */
+static int set_byte_text(int b, char *buf) {
+    if ((b >= 'a' && b <= 'z') || (b >= 'A' && b <= 'Z') || (b >= '0' && b <= '9')) return sprintf(buf, "%c", b);
+    return sprintf(buf, "\\x%02x", b);
+}
 
 /* Printable form of a numbered symbol: "k(" ")k" for parentheses, the
- * terminal followed by its number ("a4"; bytes other than letters as \xHH),
- * "ε4" for an empty-string leaf, "⊣" for the end mark. */
+ * terminal followed by its number ("a4"; bytes other than letters as \xHH;
+ * a set as its maximal ranges in brackets, "[a-z0]4", a range of two bytes
+ * as both; the wildcard as ".4"), "ε4" for an empty-string leaf, "⊣" for the
+ * end mark. */
 static int sym_text(const oracle_t *o, int s, char *buf) {
     if (s == o->sym_end) return sprintf(buf, "\xe2\x8a\xa3");
     int x = o->sym_node[s];
@@ -466,6 +544,20 @@ static int sym_text(const oracle_t *o, int s, char *buf) {
     case 2: return sprintf(buf, ")%d", k);
     default:
         if (v->kind == K_EPS) return sprintf(buf, "\xce\xb5%d", k);
+        if (v->form == 2) return sprintf(buf, ".%d", k);
+        if (v->form == 1) {
+            int len = sprintf(buf, "[");
+            for (int b = 0; b < 256;) {
+                if (!((v->set[b >> 6] >> (b & 63)) & 1)) { b++; continue; }
+                int e = b;
+                while (e + 1 < 256 && ((v->set[(e + 1) >> 6] >> ((e + 1) & 63)) & 1)) e++;
+                len += set_byte_text(b, buf + len);
+                if (e == b + 1) len += set_byte_text(e, buf + len);
+                else if (e > b + 1) { buf[len++] = '-'; len += set_byte_text(e, buf + len); }
+                b = e + 1;
+            }
+            return len + sprintf(buf + len, "]%d", k);
+        }
         if ((v->byte >= 'a' && v->byte <= 'z') || (v->byte >= 'A' && v->byte <= 'Z'))
             return sprintf(buf, "%c%d", v->byte, k);
         return sprintf(buf, "\\x%02x%d", v->byte, k);
@@ -474,7 +566,7 @@ static int sym_text(const oracle_t *o, int s, char *buf) {
 
 /* segment as space-separated symbols; returns the length needed (w/o NUL) */
 size_t oracle_segment_text(const oracle_t *o, int seg, char *buf, size_t cap) {
-    char tmp[64];
+    char tmp[1200];
     size_t need = 0;
     for (int i = 0; i < o->seg_len[seg]; i++) {
         int l = sym_text(o, o->seg_syms[seg][i], tmp);
@@ -487,11 +579,18 @@ size_t oracle_segment_text(const oracle_t *o, int seg, char *buf, size_t cap) {
 
 /* ------------------------------------------------- one NFA step on sets */
 
+/* the end-letter of segment rho matches byte a (an arc rho -> sigma is
+ * labelled with the end-letter: a byte, or a character set, Sect. 2.3.3 and
+ * App. A, character features) */
+static int label_has(const oracle_t *o, int rho, int a) {
+    return a >= 0 && a < 256 && ((o->seg_set[4 * (size_t)rho + (a >> 6)] >> (a & 63)) & 1);
+}
+
 /* forward: out = N_a x in = union of FolSeg(rho) over rho in `in` with label a */
 void oracle_step_fwd(const oracle_t *o, const uint64_t *in, int a, uint64_t *out) {
     memset(out, 0, 8 * o->W);
     for (int rho = 0; rho < o->nseg; rho++) {
-        if (!GET_BIT(in, rho) || o->seg_label[rho] != a) continue;
+        if (!GET_BIT(in, rho) || !label_has(o, rho, a)) continue;
         const uint64_t *f = o->folseg + (size_t)rho * o->W;
         for (int w = 0; w < o->W; w++) out[w] |= f[w];
     }
@@ -501,7 +600,7 @@ void oracle_step_fwd(const oracle_t *o, const uint64_t *in, int a, uint64_t *out
 void oracle_step_bwd(const oracle_t *o, const uint64_t *in, int a, uint64_t *out) {
     memset(out, 0, 8 * o->W);
     for (int rho = 0; rho < o->nseg; rho++) {
-        if (o->seg_label[rho] != a) continue;
+        if (!label_has(o, rho, a)) continue;
         const uint64_t *f = o->folseg + (size_t)rho * o->W;
         int meet = 0;
         for (int w = 0; w < o->W; w++) if (f[w] & in[w]) { meet = 1; break; }
@@ -533,7 +632,7 @@ static void count_paths(const oracle_t *o, const unsigned char *x, uint64_t n,
         memset(nxt, 0, 8 * (size_t)L);
         memset(nxtp, 0, 8 * (size_t)L);
         for (int rho = 0; rho < L; rho++) {
-            if (!GET_BIT(cols + (r - 1) * W, rho) || o->seg_label[rho] != x[r - 1]) continue;
+            if (!GET_BIT(cols + (r - 1) * W, rho) || !label_has(o, rho, x[r - 1])) continue;
             const uint64_t *f = o->folseg + (size_t)rho * W;
             for (int sg = 0; sg < L; sg++)
                 if (GET_BIT(f, sg) && GET_BIT(c, sg)) {
@@ -695,7 +794,7 @@ int oracle_parse_dfa(oracle_t *o, const unsigned char *x, uint64_t n,
         } else {
             for (int rho = 0; rho < L; rho++) {
                 cnt2[rho] = cnt2p[rho] = 0;
-                if (!GET_BIT(col, rho) || o->seg_label[rho] != x[r]) continue;
+                if (!GET_BIT(col, rho) || !label_has(o, rho, x[r])) continue;
                 const uint64_t *f = o->folseg + (size_t)rho * W;
                 for (int w = 0; w < W; w++) {
                     uint64_t m = f[w] & ncol[w];

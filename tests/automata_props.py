@@ -6,7 +6,7 @@ def column_unambiguous(o):
     state set reachable from F in at most one segment.  A clean column of an
     accepted text is such an intersection, so then every clean column is a
     single segment and every accepted text has exactly one tree."""
-    alpha = sorted(set(o.labels))
+    alpha = sorted(frozenset().union(*o.label_sets))
 
     def closure(start, step):
         seen, todo = {start}, [start]

@@ -11,14 +11,17 @@ number of LSTs.  Exponential; for tiny inputs only.
 """
 from __future__ import annotations
 
-META = set(b"()|*+?\\")
+META = set(b"()|*+?\\.[]")
 
 
 class Node:
-    __slots__ = ("kind", "byte", "kids", "num")
+    __slots__ = ("kind", "byte", "kids", "num", "members", "form")
 
-    def __init__(self, kind, byte=None, kids=None):
+    def __init__(self, kind, byte=None, kids=None, members=None, form="byte"):
         self.kind, self.byte, self.kids, self.num = kind, byte, kids or [], 0
+        # a terminal matches the bytes in members; form: "byte", "set" ("[...]") or "dot"
+        self.members = members if members is not None else (frozenset([byte]) if byte is not None else None)
+        self.form = form
 
 
 def read_re(s: bytes) -> Node:
@@ -52,11 +55,61 @@ def read_re(s: bytes) -> Node:
             x = Node(k, kids=[x])
         return x
 
+    def one_byte():
+        nonlocal pos
+        c = s[pos]
+        pos += 1
+        if c != ord('\\'):
+            return c
+        e = s[pos]
+        pos += 1
+        if e == ord('n'):
+            return 10
+        if e == ord('t'):
+            return 9
+        if e == ord('x'):
+            v = int(s[pos:pos + 2], 16)
+            pos += 2
+            return v
+        return e
+
+    def bracket():
+        nonlocal pos
+        pos += 1
+        neg = peek() == ord('^')
+        if neg:
+            pos += 1
+        got = set()
+        first = True
+        while True:
+            if peek() is None:
+                raise SyntaxError(pos)
+            if peek() == ord(']') and not first:
+                pos += 1
+                break
+            first = False
+            lo = one_byte()
+            hi = lo
+            if peek() == ord('-') and pos + 1 < len(s) and s[pos + 1] != ord(']'):
+                pos += 1
+                hi = one_byte()
+            got.update(range(lo, hi + 1))
+        if neg:
+            got = set(range(256)) - got
+        if not got:
+            raise SyntaxError(pos)
+        return Node('lit', members=frozenset(got), form="set")
+
     def atom():
         nonlocal pos
         c = peek()
         if c is None or c in b")|*+?":
             raise SyntaxError(pos)
+        if c == ord('['):
+            return bracket()
+        if c == ord('.'):
+            pos += 1
+            return Node('lit', members=frozenset(set(range(256)) - {10}), form="dot")
         if c == ord('('):
             pos += 1
             if peek() == ord(')'):
@@ -96,9 +149,29 @@ def read_re(s: bytes) -> Node:
     return root
 
 
+def _set_text(members) -> str:
+    """Maximal ranges of the set: one byte, two bytes, or lo-hi; letters and
+    digits as themselves, other bytes as \\xHH."""
+    def one(b):
+        return chr(b) if (48 <= b <= 57) or (65 <= b <= 90) or (97 <= b <= 122) else "\\x%02x" % b
+    out, bs, k = [], sorted(members), 0
+    while k < len(bs):
+        e = k
+        while e + 1 < len(bs) and bs[e + 1] == bs[e] + 1:
+            e += 1
+        lo, hi = bs[k], bs[e]
+        out.append(one(lo) if lo == hi else one(lo) + one(hi) if hi == lo + 1 else one(lo) + "-" + one(hi))
+        k = e + 1
+    return "[" + "".join(out) + "]"
+
+
 def _tok_leaf(x: Node) -> str:
     if x.kind == 'eps':
         return "ε%d" % x.num
+    if x.form == "dot":
+        return ".%d" % x.num
+    if x.form == "set":
+        return "%s%d" % (_set_text(x.members), x.num)
     b = x.byte
     if (97 <= b <= 122) or (65 <= b <= 90):
         return "%s%d" % (chr(b), x.num)
@@ -108,7 +181,7 @@ def _tok_leaf(x: Node) -> str:
 def _derive(x: Node, text: bytes, i: int):
     """All (j, lst) such that x derives text[i:j] with linearized tree lst."""
     if x.kind == 'lit':
-        return [(i + 1, (_tok_leaf(x),))] if i < len(text) and text[i] == x.byte else []
+        return [(i + 1, (_tok_leaf(x),))] if i < len(text) and text[i] in x.members else []
     if x.kind == 'eps':
         return [(i, (_tok_leaf(x),))]
     if x.kind == 'cat':

@@ -55,7 +55,7 @@ def test_compiler_matches_oracle(pat):
     info = p.info
     assert info.num_segments == o.nseg and info.words_per_column == o.W
     assert info.num_initial == len(o.I) and info.num_final == len(o.F)
-    alphabet = sorted({a for a in o.labels if a >= 0})
+    alphabet = sorted(frozenset().union(*o.label_sets))
     for d in (0, 1):
         sets, delta, cm = p.table(d)
         got = _sets(o, sets)

@@ -403,7 +403,7 @@ def test_slpf_invariants(seed):
         if acc:
             assert cols[0] <= o.I and cols[-1] <= o.F
             for r in range(len(x)):
-                assert all(o.labels[s] == x[r] for s in cols[r])
+                assert all(x[r] in o.label_sets[s] for s in cols[r])
         else:
             assert cnt == 0
         if t < 3:
@@ -469,3 +469,104 @@ def test_empty_text():
     o = Oracle("a(b|c)")
     cols, acc, cnt = o.columns(b"")
     assert not acc and cnt == 0 and cols == [frozenset()]
+
+
+# ------------------------------------------- character sets and the wildcard
+
+_SET_LEAVES = [b"[ab]", b"[a-c]", b"[^a]", b".", b"[bc]", b"[ac]", b"a", b"b", b"c"]
+
+
+def _tiny_set_re(rng):
+    """A tiny RE over {a, b, c} whose leaves are bytes, character sets or the
+    wildcard (App. A, character features), not infinitely ambiguous."""
+    def grow(d, budget):
+        if d >= 3 or budget[0] <= 0 or rng.random() < 0.3:
+            return _SET_LEAVES[int(rng.integers(len(_SET_LEAVES)))]
+        budget[0] -= 1
+        k = int(rng.integers(5))
+        if k < 2:
+            parts = [grow(d + 1, budget) for _ in range(int(rng.integers(2, 4)))]
+            return b"(" + (b"" if k == 0 else b"|").join(parts) + b")"
+        return b"(" + grow(d + 1, budget) + b")" + b"*+?"[k - 2:k - 1]
+    while True:
+        pat = grow(0, [6])
+        try:
+            Oracle(pat)
+            return pat
+        except OracleError as e:
+            assert e.status == STATUS_INF_AMBIG
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_char_sets_equal_brute_force_and_re(seed):
+    # columns and counts against the brute-force LST enumerator (its own RE
+    # reader), accept against Python's re (same bracket and dot syntax)
+    rng = np.random.default_rng(7000 + seed)
+    pat = _tiny_set_re(rng)
+    o = Oracle(pat)
+    py = re.compile(pat)
+    for x in _strings("abc", 5):
+        cols, acc, cnt = o.columns(x)
+        bcols, bcnt = lst_brute.clean_columns(pat, x)
+        assert [set(o.segments[i] for i in c) for c in cols] == bcols, (pat, x)
+        assert cnt == bcnt and o.parse_full(x)[3] == bcnt, (pat, x)
+        assert acc == (bcnt > 0) == (py.fullmatch(x) is not None), (pat, x)
+
+
+def _expand_sets(pat: bytes) -> bytes:
+    """The same RE with every set and wildcard written as a union of single
+    bytes over a b c and the newline (only those occur in the texts below)."""
+    out, k = b"", 0
+    universe = b"abc\n"
+    while k < len(pat):
+        c = pat[k:k + 1]
+        if c == b"[":
+            e = pat.index(b"]", k + 2)
+            members = set(re.findall(rb".", pat[k:e + 1]) and
+                          [bytes([b]) for b in universe if re.fullmatch(pat[k:e + 1], bytes([b]))])
+            out += b"(" + b"|".join(sorted(members)).replace(b"\n", b"\\n") + b")"
+            k = e + 1
+        elif c == b".":
+            out += b"(a|b|c)"
+            k += 1
+        else:
+            out += c
+            k += 1
+    return out
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_char_sets_count_like_unions(seed):
+    # a set leaf stands for a union of its bytes: over texts of those bytes the
+    # two REs have the same language and the same number of trees (a union of
+    # distinct single bytes adds no ambiguity), while the set form has fewer
+    # segments
+    rng = np.random.default_rng(8000 + seed)
+    pat = _tiny_set_re(rng)
+    if b"[" not in pat and b"." not in pat:
+        pytest.skip("no set leaf")
+    o1, o2 = Oracle(pat), Oracle(_expand_sets(pat))
+    assert o1.nseg <= o2.nseg
+    for x in _strings("abc", 6):
+        _, a1, c1, p1 = o1.parse_full(x)
+        _, a2, c2, p2 = o2.parse_full(x)
+        assert (a1, c1, p1) == (a2, c2, p2), (pat, x)
+
+
+def test_char_set_segment_text_and_labels():
+    o = Oracle(b"([a-e]x|[d-g]y|.z|[^\\x00-\\xfe])*")
+    texts = " ".join(o.segments)
+    assert "[a-e]4" in texts and "[d-g]7" in texts and ".10" in texts and "[\\xff]12" in texts
+    # the end-letter of every segment matches exactly its set's bytes
+    for s, t in enumerate(o.segments):
+        last = t.split(" ")[-1]
+        if last.startswith("[a-e]"):
+            assert o.label_sets[s] == frozenset(b"abcde") and o.labels[s] == -2
+        if last.startswith(".1"):
+            assert o.label_sets[s] == frozenset(range(256)) - {10}
+    # a wildcard does not match the newline
+    assert o.parse(b"az")[1] and not o.parse(b"\nz")[1]
+    with pytest.raises(OracleError):
+        Oracle(b"[]")
+    with pytest.raises(OracleError):
+        Oracle(b"[z-a]")
