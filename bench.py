@@ -514,10 +514,11 @@ def main():
         "config": {"workload": ("single-RE large text: seeded random RE (depth 7, 40 operators, 26 letters, "
                                 "seed %d), %d-byte text sampled from its language with 5%% random-byte "
                                 "corruption blocks" % (RE_SEED, n)) if args.workload == "single" else
-                               ("record RE with L2-resident tables: CSV-like traffic records (timestamp digits, "
-                                "':' '-' ',' separators, 3-8 numeric fields, optional quoted field, newline) under "
-                                "one star over 123 byte classes, %d-byte text of records (seed %d), field "
-                                "lengths 1-12" % (n, RECORD_SEED)),
+                               ("record RE with L2-resident tables: multi-schema log records (timestamp, ':', "
+                                "one of 14 schemas of 8 comma-separated fields over overlapping byte sets, "
+                                "optional quoted field, newline) under one star, %d byte classes; %d-byte text "
+                                "of records (seed %d), field lengths 1-12" % (parser.info.num_classes, n,
+                                                                              RECORD_SEED)),
                    "text_bytes": n, "words_per_column": W, "segments": parser.nseg,
                    "fwd_states": parser.info.fwd_states, "rev_states": parser.info.rev_states,
                    "table_placement": "lds" if parser.info.placement == 0 else "l2",
@@ -529,42 +530,47 @@ def main():
         "slpf_gbs": round(algo / (ms * 1e-3) / 1e9, 2),
         "roofline": roof,
     }
-    # compact SLPF of the same text: one word per column over its candidate
-    # list; checked against the plain layout through slpf_decode_compact
-    cms, cphase, cscal, ccols = run_gpu(parser, text, args.steps, args.warmup, args.chunk_bytes, compact=True)
-    dec = parser.decode_compact(torch.from_numpy(text).to("cuda:0"), ccols)
-    same = bool(torch.equal(dec, _)) and cscal == scal
-    del dec, ccols
     if args.workload == "record":
         out["matches"] = time_matches(parser, text, _)
+    # compact SLPF of the same text: one word per column over its candidate
+    # list; checked against the plain layout through slpf_decode_compact
+    if parser.info.max_entries <= 64:
+        cms, cphase, cscal, ccols = run_gpu(parser, text, args.steps, args.warmup, args.chunk_bytes, compact=True)
+        dec = parser.decode_compact(torch.from_numpy(text).to("cuda:0"), ccols)
+        same = bool(torch.equal(dec, _)) and cscal == scal
+        del dec, ccols
+        calgo = n + (n + 1) * 8
+        out["compact"] = {"value": round(n / (cms * 1e-3) / 1e9, 3), "unit": "GB/s",
+                          "ms_per_step": round(cms, 4),
+                          "phases_ms": {k: round(v, 4) for k, v in cphase.items()},
+                          "algorithmic_bytes": calgo,
+                          "build_achieved_gbs": round(calgo / (cphase["build"] * 1e-3) / 1e9, 2),
+                          "build_frac_of_hbm_peak": round(calgo / (cphase["build"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                          "decodes_to_plain": same,
+                          "what": "SLPF_PARSE_COMPACT: each column as one word over its candidate list"}
+        print("compact: %.3f ms/step phases %s decodes_to_plain %s" % (cms, cphase, same), file=sys.stderr,
+              flush=True)
+    else:
+        out["compact"] = {"skipped": "candidate lists of up to %d segments; the compact form holds 64"
+                          % parser.info.max_entries}
     del _
-    calgo = n + (n + 1) * 8
-    out["compact"] = {"value": round(n / (cms * 1e-3) / 1e9, 3), "unit": "GB/s", "ms_per_step": round(cms, 4),
-                      "phases_ms": {k: round(v, 4) for k, v in cphase.items()},
-                      "algorithmic_bytes": calgo,
-                      "build_achieved_gbs": round(calgo / (cphase["build"] * 1e-3) / 1e9, 2),
-                      "build_frac_of_hbm_peak": round(calgo / (cphase["build"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                      "decodes_to_plain": same,
-                      "what": "SLPF_PARSE_COMPACT: each column as one word over its candidate list"}
-    print("compact: %.3f ms/step phases %s decodes_to_plain %s" % (cms, cphase, same), file=sys.stderr, flush=True)
     torch.cuda.empty_cache()
     # speculation ablation: runs started from every segment whose end-letter
     # is the chunk's first byte, without the previous-byte filter
-    if parser.info.max_entries_next_byte <= 64:
-        nms, nphase, nscal, _n = run_gpu(parser, text, args.steps, args.warmup, args.chunk_bytes,
-                                         flags=S.PARSE_NEXT_BYTE_ENTRIES)
-        del _n
-        out["speculation_ablation"] = {
-            "reduced_entries": {"max_entries": parser.info.max_entries, "reach_ms": round(phase["reach"], 4),
-                                "ms_per_step": round(ms, 4)},
-            "next_byte_entries": {"max_entries": parser.info.max_entries_next_byte,
-                                  "reach_ms": round(nphase["reach"], 4), "ms_per_step": round(nms, 4),
-                                  "same_scalars": nscal == scal},
-            "what": "lane-chunk runs from the reduced entry list X(previous byte, next byte) vs from every "
-                    "segment whose end-letter is the next byte"}
-        print("next-byte entries: %.3f ms/step reach %.3f ms (reduced: reach %.3f ms)" % (
-            nms, nphase["reach"], phase["reach"]), file=sys.stderr, flush=True)
-        torch.cuda.empty_cache()
+    nms, nphase, nscal, _n = run_gpu(parser, text, args.steps, args.warmup, args.chunk_bytes,
+                                     flags=S.PARSE_NEXT_BYTE_ENTRIES)
+    del _n
+    out["speculation_ablation"] = {
+        "reduced_entries": {"max_entries": parser.info.max_entries, "reach_ms": round(phase["reach"], 4),
+                            "ms_per_step": round(ms, 4)},
+        "next_byte_entries": {"max_entries": parser.info.max_entries_next_byte,
+                              "reach_ms": round(nphase["reach"], 4), "ms_per_step": round(nms, 4),
+                              "same_scalars": nscal == scal},
+        "what": "lane-chunk runs from the reduced entry list X(previous byte, next byte) vs from every "
+                "segment whose end-letter is the next byte"}
+    print("next-byte entries: %.3f ms/step reach %.3f ms (reduced: reach %.3f ms)" % (
+        nms, nphase["reach"], phase["reach"]), file=sys.stderr, flush=True)
+    torch.cuda.empty_cache()
     rms, racc = run_recognize(parser, text, args.steps, args.warmup, args.chunk_bytes)
     out["recognizer"] = {"value": round(n / (rms * 1e-3) / 1e9, 3), "unit": "GB/s", "ms_per_step": round(rms, 4),
                          "accepted": racc, "what": "forward reach and forward join only (accept flag, no SLPF)"}

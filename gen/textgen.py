@@ -30,6 +30,8 @@ def sample_natural(node, rng, p_continue=P_CONTINUE, out=None) -> bytearray:
     k = node[0]
     if k == 'lit':
         out.append(node[1])
+    elif k == 'set':
+        out.append(node[1][int(rng.integers(len(node[1])))])
     elif k == 'eps':
         pass
     elif k == 'cat':
@@ -163,10 +165,53 @@ def corrupt(text: np.ndarray, seed: int, frac=0.05, block=(64, 4096)) -> np.ndar
 _DIGITS = np.frombuffer(b"0123456789", dtype=np.uint8)
 
 
-def record_text(seed: int, target: int, ts_digits=(4, 2, 2, 2, 2, 2),
-                min_fields=3, max_fields=8, field_len=(1, 12),
-                quoted=None, p_quoted=0.5, pool=65536) -> np.ndarray:
-    """Records of the CSV-like record RE (see ``regen.record_re``).
+def _pooled(recs, rng, target):
+    """A text of i.i.d. records from the pool ``recs``, at least ``target`` bytes."""
+    pool = len(recs)
+    lens = np.array([len(r) for r in recs], dtype=np.int64)
+    m = int(target / lens.mean() * 1.02) + 16
+    idx = rng.integers(0, pool, size=m)
+    cl = np.cumsum(lens[idx])
+    cut = min(int(np.searchsorted(cl, target)) + 1, m)
+    return np.frombuffer(b"".join(recs[i] for i in idx[:cut].tolist()), dtype=np.uint8).copy()
+
+
+def record_text(seed: int, target: int, schemas=None, field_len=(1, 12), quoted=None,
+                p_quoted=0.5, pool=65536) -> np.ndarray:
+    """Records of the multi-schema record RE (see ``regen.record_re``).
+
+    Timestamp digits uniform; the schema uniform over ``schemas``; every field
+    of length uniform in ``field_len`` with bytes uniform over its type's
+    set; the quoted field present with ``p_quoted``, length uniform in
+    ``field_len``.  Records are drawn i.i.d. from a pool.
+    """
+    from .regen import _QUOTED, RECORD_FIELD_SETS, record_schemas
+    schemas = record_schemas() if schemas is None else schemas
+    q = np.frombuffer(quoted if quoted is not None else _QUOTED, dtype=np.uint8)
+    sets = {k: np.frombuffer(v, dtype=np.uint8) for k, v in RECORD_FIELD_SETS.items()}
+    rng = np.random.default_rng(seed)
+    recs = []
+    for _ in range(pool):
+        d = _DIGITS[rng.integers(0, 10, size=14)].tobytes()
+        r = bytearray(d[:4] + b"-" + d[4:6] + b"-" + d[6:8] + b" " + d[8:10] + b":" + d[10:12] + b":" + d[12:14] + b":")
+        sch = schemas[int(rng.integers(len(schemas)))]
+        for j, t in enumerate(sch):
+            if j:
+                r.append(0x2c)
+            ln = int(rng.integers(field_len[0], field_len[1] + 1))
+            r += sets[t][rng.integers(0, sets[t].size, size=ln)].tobytes()
+        if rng.random() < p_quoted:
+            ln = int(rng.integers(field_len[0], field_len[1] + 1))
+            r += b',"' + q[rng.integers(0, q.size, size=ln)].tobytes() + b'"'
+        r.append(0x0a)
+        recs.append(bytes(r))
+    return _pooled(recs, rng, target)
+
+
+def csv_record_text(seed: int, target: int, ts_digits=(4, 2, 2, 2, 2, 2),
+                    min_fields=3, max_fields=8, field_len=(1, 12),
+                    quoted=None, p_quoted=0.5, pool=65536) -> np.ndarray:
+    """Records of the CSV-like record RE (see ``regen.csv_record_re``).
 
     Field count uniform in [min_fields, max_fields], digit-field lengths
     uniform in ``field_len``, the quoted field present with ``p_quoted`` and
@@ -195,9 +240,4 @@ def record_text(seed: int, target: int, ts_digits=(4, 2, 2, 2, 2, 2),
             r += b',"' + bytes(q[rng.integers(0, q.size, size=ln)]) + b'"'
         r.append(0x0a)
         recs.append(bytes(r))
-    lens = np.array([len(r) for r in recs], dtype=np.int64)
-    m = int(target / lens.mean() * 1.02) + 16
-    idx = rng.integers(0, pool, size=m)
-    cl = np.cumsum(lens[idx])
-    cut = min(int(np.searchsorted(cl, target)) + 1, m)
-    return np.frombuffer(b"".join(recs[i] for i in idx[:cut].tolist()), dtype=np.uint8).copy()
+    return _pooled(recs, rng, target)

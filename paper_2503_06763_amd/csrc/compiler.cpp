@@ -11,8 +11,10 @@
 // end-letter; this yields the same set as the right-to-left meta-prefix
 // extension of Fig. segmentalgo.
 #include <algorithm>
+#include <array>
 #include <cstring>
 #include <functional>
+#include <map>
 #include <string>
 #include <unordered_map>
 #include <unordered_set>
@@ -25,12 +27,17 @@ namespace {
 
 // ------------------------------------------------------------------ tokens
 
-enum class T : uint8_t { Byte, Open, Close, Bar, Star, Plus, Quest };
+enum class T : uint8_t { Byte, Set, Open, Close, Bar, Star, Plus, Quest };
+using ByteSet = std::array<uint64_t, 4>;
 struct Token {
     T t;
     int byte;
     size_t off;
+    ByteSet set{};           // T::Set: the bytes
+    int form = 0;            // T::Set: 1 a bracketed set, 2 the wildcard
 };
+
+bool has_byte(const ByteSet &m, int b) { return (m[b >> 6] >> (b & 63)) & 1u; }
 
 int hexdigit(int c) {
     if (c >= '0' && c <= '9') return c - '0';
@@ -39,17 +46,70 @@ int hexdigit(int c) {
     return -1;
 }
 
+// One byte after an optional backslash (\n, \t, \xHH); -1 on error.
+int escaped_byte(const uint8_t *s, size_t n, size_t &i) {
+    if (i >= n) return -1;
+    int c = s[i++];
+    if (c != '\\') return c;
+    if (i >= n) return -1;
+    int e = s[i++];
+    if (e == 'n') return '\n';
+    if (e == 't') return '\t';
+    if (e == 'x') {
+        if (i + 2 > n || hexdigit(s[i]) < 0 || hexdigit(s[i + 1]) < 0) return -1;
+        e = hexdigit(s[i]) * 16 + hexdigit(s[i + 1]);
+        i += 2;
+    }
+    return e;
+}
+
 bool tokenize(const uint8_t *s, size_t n, std::vector<Token> &out, size_t *err) {
     for (size_t i = 0; i < n;) {
         size_t at = i;
         int c = s[i++];
+        if (c == '[') {   // a set of bytes and ranges, ^ complements (App. A, character features)
+            Token t{T::Set, -2, at};
+            t.form = 1;
+            bool neg = i < n && s[i] == '^', first = true;
+            if (neg) ++i;
+            for (;;) {
+                if (i >= n) { *err = at; return false; }
+                if (s[i] == ']' && !first) { ++i; break; }
+                first = false;
+                const int lo = escaped_byte(s, n, i);
+                if (lo < 0) { *err = at; return false; }
+                int hi = lo;
+                if (i + 1 < n && s[i] == '-' && s[i + 1] != ']') {
+                    ++i;
+                    hi = escaped_byte(s, n, i);
+                    if (hi < lo) { *err = at; return false; }
+                }
+                for (int b = lo; b <= hi; ++b) t.set[b >> 6] |= uint64_t(1) << (b & 63);
+            }
+            uint64_t any = 0;
+            for (auto &w : t.set) {
+                if (neg) w = ~w;
+                any |= w;
+            }
+            if (!any) { *err = at; return false; }
+            out.push_back(t);
+            continue;
+        }
+        if (c == '.') {   // the wildcard: any byte but the newline
+            Token t{T::Set, -2, at};
+            t.form = 2;
+            t.set = {~uint64_t(0), ~uint64_t(0), ~uint64_t(0), ~uint64_t(0)};
+            t.set['\n' >> 6] &= ~(uint64_t(1) << ('\n' & 63));
+            out.push_back(t);
+            continue;
+        }
         switch (c) {
-        case '(': out.push_back({T::Open, 0, at}); break;
-        case ')': out.push_back({T::Close, 0, at}); break;
-        case '|': out.push_back({T::Bar, 0, at}); break;
-        case '*': out.push_back({T::Star, 0, at}); break;
-        case '+': out.push_back({T::Plus, 0, at}); break;
-        case '?': out.push_back({T::Quest, 0, at}); break;
+        case '(': out.push_back(Token{T::Open, 0, at}); break;
+        case ')': out.push_back(Token{T::Close, 0, at}); break;
+        case '|': out.push_back(Token{T::Bar, 0, at}); break;
+        case '*': out.push_back(Token{T::Star, 0, at}); break;
+        case '+': out.push_back(Token{T::Plus, 0, at}); break;
+        case '?': out.push_back(Token{T::Quest, 0, at}); break;
         case '\\': {
             if (i >= n) { *err = at; return false; }
             int e = s[i++];
@@ -60,10 +120,10 @@ bool tokenize(const uint8_t *s, size_t n, std::vector<Token> &out, size_t *err) 
                 e = hexdigit(s[i]) * 16 + hexdigit(s[i + 1]);
                 i += 2;
             }
-            out.push_back({T::Byte, e, at});
+            out.push_back(Token{T::Byte, e, at});
             break;
         }
-        default: out.push_back({T::Byte, c, at});
+        default: out.push_back(Token{T::Byte, c, at});
         }
     }
     return true;
@@ -74,9 +134,11 @@ bool tokenize(const uint8_t *s, size_t n, std::vector<Token> &out, size_t *err) 
 enum class K : uint8_t { Lit, Eps, Cat, Alt, Star, Plus, Opt };
 struct Node {
     K kind;
-    int byte = -1;
+    int byte = -1;           // K::Lit: the byte, or -2 for a set
     std::vector<int> kids;
     int num = 0;
+    ByteSet set{};           // K::Lit: the bytes the terminal matches
+    int form = 0;            // K::Lit: 0 a byte, 1 a bracketed set, 2 the wildcard
 };
 
 struct Parser {
@@ -138,10 +200,13 @@ struct Parser {
     int primary() {
         if (i >= tk.size()) { fail(); return -1; }
         const Token &t = tk[i];
-        if (t.t == T::Byte) {
+        if (t.t == T::Byte || t.t == T::Set) {
             ++i;
             int x = make(K::Lit);
             nodes[x].byte = t.byte;
+            nodes[x].form = t.form;
+            if (t.t == T::Set) nodes[x].set = t.set;
+            else nodes[x].set[t.byte >> 6] = uint64_t(1) << (t.byte & 63);
             return x;
         }
         if (t.t == T::Open) {
@@ -394,7 +459,29 @@ int compile_re(const uint8_t *re, size_t len, const CompileLimits &lim, HostAuto
             if (y.kind == SOpen) snprintf(buf, sizeof buf, "%d(", num);
             else if (y.kind == SClose) snprintf(buf, sizeof buf, ")%d", num);
             else if (nodes[y.node].kind == K::Eps) snprintf(buf, sizeof buf, "\xce\xb5%d", num);
-            else {
+            else if (nodes[y.node].form == 2) snprintf(buf, sizeof buf, ".%d", num);
+            else if (nodes[y.node].form == 1) {
+                // a set as its maximal byte ranges: one byte, two bytes, or lo-hi
+                const ByteSet &m = nodes[y.node].set;
+                auto one = [&](int b) {
+                    char t[8];
+                    const bool an = (b >= 'a' && b <= 'z') || (b >= 'A' && b <= 'Z') || (b >= '0' && b <= '9');
+                    if (an) snprintf(t, sizeof t, "%c", b);
+                    else snprintf(t, sizeof t, "\\x%02x", b);
+                    out += t;
+                };
+                out += '[';
+                for (int b = 0; b < 256;) {
+                    if (!has_byte(m, b)) { ++b; continue; }
+                    int e = b;
+                    while (e + 1 < 256 && has_byte(m, e + 1)) ++e;
+                    one(b);
+                    if (e == b + 1) one(e);
+                    else if (e > b + 1) { out += '-'; one(e); }
+                    b = e + 1;
+                }
+                snprintf(buf, sizeof buf, "]%d", num);
+            } else {
                 int b = nodes[y.node].byte;
                 bool letter = (b >= 'a' && b <= 'z') || (b >= 'A' && b <= 'Z');
                 if (letter) snprintf(buf, sizeof buf, "%c%d", b, num);
@@ -405,30 +492,54 @@ int compile_re(const uint8_t *re, size_t len, const CompileLimits &lim, HostAuto
         A.seg_text.push_back(out);
     }
 
-    // byte classes: every byte used by a terminal gets its own class; class 0 = unused bytes
+    // byte classes: bytes matched by exactly the same terminals share a class,
+    // in order of their smallest byte; class 0 = bytes no terminal matches.
+    // Every terminal's set is a union of classes, and classes are disjoint:
+    // the partition of overlapping sets into disjoint subsets that App. A
+    // (character features, Fig. charset) asks for to keep the powerset
+    // automata deterministic, applied to the alphabet, so segments keep
+    // their set end-letters and are never split.
     A.classmap.assign(256, 0);
+    std::vector<int> leaves;
+    for (size_t x = 0; x < nodes.size(); ++x)
+        if (nodes[x].kind == K::Lit) leaves.push_back(static_cast<int>(x));
+    std::vector<int> rep_byte{-1};                 // a byte of each class
     {
-        std::vector<char> used(256, 0);
-        for (auto &v : nodes)
-            if (v.kind == K::Lit) used[v.byte] = 1;
-        uint16_t c = 1;
-        for (int b = 0; b < 256; ++b)
-            if (used[b]) A.classmap[b] = c++;
-        A.C = c;
+        std::map<std::vector<bool>, uint16_t> sig_class;
+        for (int b = 0; b < 256; ++b) {
+            std::vector<bool> sig(leaves.size());
+            bool any = false;
+            for (size_t k = 0; k < leaves.size(); ++k) {
+                sig[k] = has_byte(nodes[leaves[k]].set, b);
+                any = any || sig[k];
+            }
+            if (!any) continue;
+            auto it = sig_class.find(sig);
+            if (it == sig_class.end()) {
+                it = sig_class.emplace(sig, static_cast<uint16_t>(rep_byte.size())).first;
+                rep_byte.push_back(b);
+            }
+            A.classmap[b] = it->second;
+        }
+        A.C = static_cast<uint32_t>(rep_byte.size());
     }
     if (A.C > 256) return SLPF_E_TOO_LARGE;   // class ids are packed into bytes on the device
     const uint32_t C = A.C;
+    // the classes a terminal matches
+    auto leaf_has_class = [&](int node, uint32_t c) { return c > 0 && has_byte(nodes[node].set, rep_byte[c]); };
 
-    // per segment: end symbol, label class; I, F; followers grouped by end symbol
+    // per segment: end symbol; I, F; followers grouped by end symbol
     std::vector<int> endsym(L);
-    std::vector<int> lclass(L);
     Bits I(W), F(W);
     for (uint32_t q = 0; q < L; ++q) {
         endsym[q] = segs[q].back();
-        lclass[q] = syms[endsym[q]].kind == SEnd ? -1 : A.classmap[nodes[syms[endsym[q]].node].byte];
         if (segs[q][0] == FIRST) I.set(q);
         if (syms[endsym[q]].kind == SEnd) F.set(q);
     }
+    // segment q's end-letter matches class c
+    auto label_has = [&](uint32_t q, uint32_t c) {
+        return syms[endsym[q]].kind != SEnd && leaf_has_class(syms[endsym[q]].node, c);
+    };
     // first symbol -> segments starting with it
     std::vector<std::vector<uint32_t>> starting(NS);
     for (uint32_t q = 0; q < L; ++q) starting[segs[q][0]].push_back(q);
@@ -492,7 +603,8 @@ int compile_re(const uint8_t *re, size_t len, const CompileLimits &lim, HostAuto
     // terminals grouped by class
     std::vector<std::vector<int>> ends_of_class(C);
     for (size_t k = 0; k < ends.size(); ++k)
-        ends_of_class[A.classmap[nodes[syms[ends[k]].node].byte]].push_back(static_cast<int>(k));
+        for (uint32_t c = 1; c < C; ++c)
+            if (leaf_has_class(syms[ends[k]].node, c)) ends_of_class[c].push_back(static_cast<int>(k));
 
     // one NFA step on sets (Eq. matrixmul): forward, and reverse (transposed)
     auto fwd_step = [&](const Bits &S, uint32_t c, Bits &out) {
@@ -625,7 +737,7 @@ int compile_re(const uint8_t *re, size_t len, const CompileLimits &lim, HostAuto
             if (p == 0 || q == 0) continue;
             uint32_t cnt = 0;
             for (uint32_t s = 0; s < L; ++s) {
-                bool label_ok = (q == C) ? F.get(s) : (lclass[s] == static_cast<int>(q));
+                bool label_ok = (q == C) ? F.get(s) : label_has(s, q);
                 if (!label_ok) continue;
                 bool prev_ok = (p == C) ? I.get(s) : after[p].get(s);
                 if (!prev_ok) continue;
@@ -647,7 +759,7 @@ int compile_re(const uint8_t *re, size_t len, const CompileLimits &lim, HostAuto
             if (p == 0 || q == 0) continue;
             uint32_t cnt = 0;
             for (uint32_t s = 0; s < L; ++s) {
-                bool label_ok = (q == C) ? F.get(s) : (lclass[s] == static_cast<int>(q));
+                bool label_ok = (q == C) ? F.get(s) : label_has(s, q);
                 if (!label_ok || (p == C && !I.get(s))) continue;
                 A.xlist_nb.push_back(static_cast<uint16_t>(s));
                 ++cnt;

@@ -642,7 +642,8 @@ __global__ __launch_bounds__(kScalarThreads) void k_text_scalars(Tabs tb, Job jb
                 any |= v;
                 pc += __popcll(v);
                 for (uint64_t x = v; x; x &= x - 1)   // compact: ranks in X[start, end]
-                    cm |= 1ull << tb.rankx[tb.C * tb.nseg + w * 64 + static_cast<uint32_t>(__builtin_ctzll(x))];
+                    cm |= 1ull << tb.rankx[(tb.rank_pq ? tb.C * tb.NL + tb.C : tb.C) * tb.nseg + w * 64 +
+                                           static_cast<uint32_t>(__builtin_ctzll(x))];
             }
             if (jb.compact) tr.out[0] = cm;
             tr.scalars[0] = any ? 1 : 0;

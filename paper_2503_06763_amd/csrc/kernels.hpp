@@ -69,7 +69,9 @@ struct Tabs {
     // the byte offset of the next state's row, the class map gives byte
     // offsets of the classes, so a step is one add and one lookup
     const uint16_t *fdo, *rdo, *cls2;
-    const uint8_t *rankx;       // NL x nseg: rank of a segment in X[p, its end-letter class]
+    const uint8_t *rankx;       // rank of a segment in X[p, q]: NL x nseg by previous class p (q is
+                                // its end-letter's class), or NL x NL x nseg by (p, q) when rank_pq
+    uint32_t rank_pq;
     const uint32_t *fnz, *rnz;  // per state: bit w set iff word w of its set is non-zero
     const uint32_t *xoff_nb;    // entry lists filtered by the next byte only (ablation)
     const uint16_t *xlist_nb;
@@ -83,6 +85,9 @@ struct Tabs {
     // follows (the transpose of folseg), nseg x W
     const uint8_t *pairm;
     uint32_t kfd, krd;
+    // 1: pairm holds 4-bit entries, two per byte (low nibble first), with 15
+    // standing for any size of 15 or more (used when the byte table is too big)
+    uint32_t pair_nib;
     // arcs2[(f * krd + b) * C + c] = number of arcs between two adjacent clean
     // columns: the left one of forward state f, the right one of reverse state
     // b, the byte between them of class c (0xffff: unknown); null when large
@@ -116,6 +121,7 @@ struct Job {
     uint64_t s;                 // lane chunk bytes
     uint32_t c;                 // lane chunks of all texts
     uint16_t *R, *Rh;           // [emax][c] end ids of the reach runs
+    uint16_t *Rt;               // [emax][c] reach: ids of the runs after their first stretch
     uint64_t *Mf, *MbR;         // [c][emax][ew] masks; MbR indexed by c-1-i
     uint32_t ew;                // words of an entry-list mask (ceil(emax / 64))
     uint16_t *nxf, *nxb;        // entry-list sizes at the scan input of item k (forward: left edge of
@@ -221,6 +227,7 @@ __device__ inline ChunkCtx chunk_ctx(const Job &jb, uint32_t i) {
 }
 
 constexpr int kGroup = 12;                    // runs in lockstep (slot nibbles in a u64)
+constexpr uint32_t kReachPre = 256;           // reach: bytes every run covers before runs are merged
 constexpr int kPieceR = 8;                    // largest anchor column of a piece of a long run
 
 __device__ inline uint32_t boundary_list(const Tabs &tb, const uint16_t *cls, const uint8_t *text,
@@ -329,7 +336,7 @@ __device__ inline void load_window(const uint8_t *text, uint64_t a0, uint32_t le
 // futures); `alias` maps entry k of the group to the slot holding its run.
 // Slots dead in every lane of the wavefront are skipped.
 template <bool FWD, bool OFF, bool GRP>
-__device__ inline void run_group(const uint8_t *text, uint64_t lo, uint64_t hi, const uint16_t *cls,
+__device__ __forceinline__ void run_group(const uint8_t *text, uint64_t lo, uint64_t hi, const uint16_t *cls,
                                  const uint16_t *delta, uint32_t C, uint32_t st[kGroup],
                                  uint64_t &alias) {
     uint32_t nl = kGroup;
@@ -455,10 +462,121 @@ __device__ inline void run_group(const uint8_t *text, uint64_t lo, uint64_t hi, 
         for (uint64_t p = lo + body; p < hi; ++p) step(text[p]);
 }
 
-// OFF: the runs step through the offset form of the tables; states are byte
-// offsets (id * 2C) until the end ids are stored.
+// The n runs of one direction over a lane's chunk, from the singletons of the
+// entry list xl: out[m * c + i] = end id of the run from entry m.  Every run
+// first covers only the first kReachPre bytes of its direction, kGroup runs
+// in lockstep; their ids there go to tmp, and only the distinct ones go on
+// over the rest of the chunk, kGroup at a time in increasing id order.  Runs
+// from different groups that have met within the first stretch (on record
+// text, every run that passes a record end) are therefore run once.
+template <bool FWD, bool OFF, bool GRP>
+__device__ __forceinline__ void reach_runs(const uint8_t *text, uint64_t lo, uint64_t hi, const uint16_t *cls,
+                                  const uint16_t *delta, uint32_t C, uint32_t c2, const uint16_t *single,
+                                  const uint16_t *xl, uint32_t n, uint16_t *out, uint16_t *tmp, uint32_t c,
+                                  uint32_t i) {
+    // first stretch: forward [lo, mid), backward [mid, hi); mid is a multiple
+    // of 16 bytes from lo, so both parts keep 16-byte loads
+    uint64_t mid;
+    if constexpr (FWD)
+        mid = hi - lo > kReachPre ? lo + kReachPre : hi;
+    else
+        mid = hi - lo > kReachPre ? lo + ((hi - kReachPre - lo) & ~63ull) : lo;
+    const bool rest = FWD ? mid < hi : mid > lo;
+    auto pick = [&](const uint32_t st[kGroup], uint64_t alias, int k) -> uint32_t {
+        const uint32_t sl = (alias >> (4 * k)) & 15u;
+        uint32_t v = 0;
+#pragma unroll
+        for (int q = 0; q < kGroup; ++q)
+            if (sl == static_cast<uint32_t>(q)) v = st[q];
+        return OFF ? v / c2 : v;
+    };
+    for (uint32_t g0 = 0; __any(g0 < n); g0 += kGroup) {
+        uint32_t st[kGroup];
+        uint64_t alias = 0;
+#pragma unroll
+        for (int k = 0; k < kGroup; ++k) {
+            st[k] = (g0 + k < n) ? single[xl[g0 + k]] * c2 : 0;
+            alias |= static_cast<uint64_t>(k) << (4 * k);
+        }
+        if constexpr (FWD)
+            run_group<true, OFF, GRP>(text, lo, mid, cls, delta, C, st, alias);
+        else
+            run_group<false, OFF, GRP>(text, mid, hi, cls, delta, C, st, alias);
+#pragma unroll
+        for (int k = 0; k < kGroup; ++k) {
+            if (g0 + k < n) {
+                const uint32_t v = pick(st, alias, k);
+                const uint64_t at = static_cast<uint64_t>(g0 + k) * c + i;
+                if (rest) tmp[at] = static_cast<uint16_t>(v);
+                if (!rest || v == 0) out[at] = static_cast<uint16_t>(v);   // done, or dead already
+            }
+        }
+    }
+    // the rest of the chunk: distinct ids above thr, kGroup per round.  The
+    // selection is made again after the run (rather than kept in registers
+    // across it) to map every entry to its run's slot.
+    auto select = [&](uint32_t thr, uint32_t u[kGroup]) {   // the smallest distinct ids above thr, ascending
+#pragma unroll
+        for (int j = 0; j < kGroup; ++j) u[j] = 0xffffffffu;
+        for (uint32_t m = 0; m < n; ++m) {
+            const uint32_t v = tmp[static_cast<uint64_t>(m) * c + i];
+            if (v <= thr || v >= u[kGroup - 1]) continue;
+            bool dup = false;
+#pragma unroll
+            for (int j = 0; j < kGroup; ++j) dup |= u[j] == v;
+            if (dup) continue;
+#pragma unroll
+            for (int j = kGroup - 1; j >= 0; --j) {   // insertion; the largest falls off
+                const uint32_t below = j > 0 ? u[j - 1] : 0u;
+                if (j > 0 && below > v)
+                    u[j] = below;
+                else if (u[j] > v)
+                    u[j] = v;
+            }
+        }
+    };
+    uint32_t thr = 0;
+    bool more = rest;
+    while (__any(more)) {
+        uint32_t st[kGroup];
+        uint64_t alias = 0;
+        {
+            uint32_t u[kGroup];
+            if (more) select(thr, u);
+#pragma unroll
+            for (int j = 0; j < kGroup; ++j) {
+                st[j] = more && u[j] != 0xffffffffu ? u[j] * c2 : 0;
+                alias |= static_cast<uint64_t>(j) << (4 * j);
+            }
+        }
+        if constexpr (FWD)
+            run_group<true, OFF, GRP>(text, mid, hi, cls, delta, C, st, alias);
+        else
+            run_group<false, OFF, GRP>(text, lo, mid, cls, delta, C, st, alias);
+        if (more) {
+            uint32_t u[kGroup];
+            select(thr, u);
+            uint32_t top = thr;
+#pragma unroll
+            for (int j = 0; j < kGroup; ++j) top = u[j] != 0xffffffffu ? u[j] : top;
+            for (uint32_t m = 0; m < n; ++m) {
+                const uint64_t at = static_cast<uint64_t>(m) * c + i;
+                const uint32_t v = tmp[at];
+                if (v <= thr || v > top) continue;
+                uint32_t fin = 0;
+#pragma unroll
+                for (int j = 0; j < kGroup; ++j)
+                    if (u[j] == v) fin = pick(st, alias, j);
+                out[at] = static_cast<uint16_t>(fin);
+            }
+            more = u[kGroup - 1] != 0xffffffffu;   // a full round: there may be more ids above top
+            thr = top;
+        }
+    }
+}
+
 template <bool LDS, bool OFF>
-__global__ __launch_bounds__(256) void k_reach(Tabs tb, Job jb) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_reach(Tabs tb, Job jb) {
     extern __shared__ __align__(16) uint8_t smem[];
     Tabs ts = tb;
     if constexpr (OFF) {
@@ -484,48 +602,15 @@ __global__ __launch_bounds__(256) void k_reach(Tabs tb, Job jb) {
     jb.nxb[jb.c - 1 - i] = static_cast<uint16_t>(nb);
     jb.rsb[jb.c - 1 - i] = cx.last ? 1 : 0;
 
-    // forward runs from X_i
-    for (uint32_t g0 = 0; __any(g0 < na); g0 += kGroup) {
-        uint32_t st[kGroup];
-        uint64_t alias = 0;
-#pragma unroll
-        for (int k = 0; k < kGroup; ++k) {
-            st[k] = (g0 + k < na) ? tb.fsingle[tb.xlist[xa0 + g0 + k]] * c2 : 0;
-            alias |= static_cast<uint64_t>(k) << (4 * k);
-        }
-        run_group<true, OFF, LDS>(text, lo, hi, lk.cls, lk.fd, tb.C, st, alias);
-#pragma unroll
-        for (int k = 0; k < kGroup; ++k) {
-            if (g0 + k < na) {
-                uint32_t sl = (alias >> (4 * k)) & 15u, v = 0;
-#pragma unroll
-                for (int q = 0; q < kGroup; ++q)
-                    if (sl == static_cast<uint32_t>(q)) v = st[q];
-                jb.R[static_cast<uint64_t>(g0 + k) * jb.c + i] = static_cast<uint16_t>(OFF ? v / c2 : v);
-            }
-        }
-    }
-    // backward runs from X_{i+1} (not for the recogniser)
-    for (uint32_t g0 = 0; !jb.fwd_only && __any(g0 < nb); g0 += kGroup) {
-        uint32_t st[kGroup];
-        uint64_t alias = 0;
-#pragma unroll
-        for (int k = 0; k < kGroup; ++k) {
-            st[k] = (g0 + k < nb) ? tb.rsingle[tb.xlist[xb0 + g0 + k]] * c2 : 0;
-            alias |= static_cast<uint64_t>(k) << (4 * k);
-        }
-        run_group<false, OFF, LDS>(text, lo, hi, lk.cls, lk.rd, tb.C, st, alias);
-#pragma unroll
-        for (int k = 0; k < kGroup; ++k) {
-            if (g0 + k < nb) {
-                uint32_t sl = (alias >> (4 * k)) & 15u, v = 0;
-#pragma unroll
-                for (int q = 0; q < kGroup; ++q)
-                    if (sl == static_cast<uint32_t>(q)) v = st[q];
-                jb.Rh[static_cast<uint64_t>(g0 + k) * jb.c + i] = static_cast<uint16_t>(OFF ? v / c2 : v);
-            }
-        }
-    }
+    // forward runs from X_i, backward runs from X_{i+1} (not for the recogniser)
+    // (four 16-byte blocks a lane per load round with the offset-form LDS
+    // tables; the id form's address arithmetic leaves no registers for them)
+    constexpr bool GRP = LDS && OFF;
+    reach_runs<true, OFF, GRP>(text, lo, hi, lk.cls, lk.fd, tb.C, c2, tb.fsingle, tb.xlist + xa0, na, jb.R, jb.Rt,
+                               jb.c, i);
+    if (!jb.fwd_only)
+        reach_runs<false, OFF, GRP>(text, lo, hi, lk.cls, lk.rd, tb.C, c2, tb.rsingle, tb.xlist + xb0, nb, jb.Rh,
+                                    jb.Rt, jb.c, i);
     // maps between entry lists: forward X_i -> X_{i+1}, backward X_{i+1} -> X_i;
     // row m (ew words) has bit p set when the run from entry m ends in a set
     // holding the p-th segment of the far list
@@ -1178,7 +1263,8 @@ __global__ __launch_bounds__(kBuildThreads) void k_build(Tabs tb, Job jb) {
     const uint8_t *rkl = smem + jb.rank_lds;
     if (COMPACT && jb.rank_lds) {
         uint8_t *dst = smem + jb.rank_lds;
-        for (uint32_t k = threadIdx.x; k < tb.NL * tb.nseg; k += blockDim.x) dst[k] = tb.rankx[k];
+        const uint32_t nr = (tb.rank_pq ? tb.NL * tb.NL : tb.NL) * tb.nseg;
+        for (uint32_t k = threadIdx.x; k < nr; k += blockDim.x) dst[k] = tb.rankx[k];
         __syncthreads();
     }
     auto rank_of = [&](uint32_t idx) -> uint32_t { return jb.rank_lds ? rkl[idx] : tb.rankx[idx]; };
@@ -1187,13 +1273,17 @@ __global__ __launch_bounds__(kBuildThreads) void k_build(Tabs tb, Job jb) {
     const uint8_t *pml = smem + jb.pair_lds;
     if (jb.count_on && jb.pair_lds) {
         uint8_t *dst = smem + jb.pair_lds;
-        for (uint32_t k = threadIdx.x; k < tb.kfd * tb.krd; k += blockDim.x) dst[k] = tb.pairm[k];
+        const uint32_t nb = tb.pair_nib ? (tb.kfd * tb.krd + 1) / 2 : tb.kfd * tb.krd;
+        for (uint32_t k = threadIdx.x; k < nb; k += blockDim.x) dst[k] = tb.pairm[k];
         __syncthreads();
     }
     auto pair_size = [&](uint32_t fi, uint32_t bi) -> uint32_t {
         if (fi >= tb.kfd || bi >= tb.krd) return 0u;
         const uint32_t k = fi * tb.krd + bi;
-        return jb.pair_lds ? static_cast<uint32_t>(pml[k]) : static_cast<uint32_t>(tb.pairm[k]);
+        const uint8_t *pt = jb.pair_lds ? pml : tb.pairm;
+        if (!tb.pair_nib) return static_cast<uint32_t>(pt[k]);
+        const uint32_t v = (static_cast<uint32_t>(pt[k >> 1]) >> ((k & 1u) * 4u)) & 15u;
+        return v == 15u ? 255u : v;          // 255: too many to multiply in (a general run)
     };
 
     const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -1242,7 +1332,7 @@ __global__ __launch_bounds__(kBuildThreads) void k_build(Tabs tb, Job jb) {
                 while (v) {
                     const uint32_t sg = w * 64 + static_cast<uint32_t>(__builtin_ctzll(v));
                     v &= v - 1;
-                    m |= 1ull << tb.rankx[pc * tb.nseg + sg];
+                    m |= 1ull << tb.rankx[(tb.rank_pq ? pc * tb.NL + C : pc) * tb.nseg + sg];
                 }
             }
             out[cx.tr.n] = m;
@@ -1314,7 +1404,8 @@ __global__ __launch_bounds__(kBuildThreads) void k_build(Tabs tb, Job jb) {
                 if (on && t < static_cast<int>(lenA)) {
                     b = T.rd[b * C + byte_of(cwA, t)];    // now the backward id at column a0+t
                     mine[u] = fwA[t] | (b << 16);
-                    if constexpr (COMPACT) mine[SC + u] = t > 0 ? byte_of(cwA, t - 1) : pA0;
+                    // compact: the classes of the bytes before and after the column
+                    if constexpr (COMPACT) mine[SC + u] = (t > 0 ? byte_of(cwA, t - 1) : pA0) | (byte_of(cwA, t) << 16);
                     if (cnt) amb |= (pair_size(fwA[t], b) != 1 ? 1u : 0u) << u;   // not a singleton
                 }
                 const int tf = (PARTS - 1 - h) * SC + (SC - 1 - u);   // forward step of window w-1
@@ -1370,7 +1461,8 @@ __global__ __launch_bounds__(kBuildThreads) void k_build(Tabs tb, Job jb) {
                             const uint32_t ww = static_cast<uint32_t>(__builtin_ctz(nz));
                             for (uint64_t y = T.fb[fi * W + ww] & T.rb[bi * W + ww]; y; y &= y - 1) {
                                 const uint32_t sg = ww * 64 + static_cast<uint32_t>(__builtin_ctzll(y));
-                                m |= 1ull << rank_of(pc * tb.nseg + sg);
+                                m |= 1ull << rank_of((tb.rank_pq ? (pc & 0xffffu) * tb.NL + (pc >> 16)
+                                                                 : (pc & 0xffffu)) * tb.nseg + sg);
                             }
                         }
                         __builtin_nontemporal_store(m, global_ptr<uint64_t>(rj) + e);

@@ -120,10 +120,23 @@ slpf_status upload(slpf_parser *p) {
     // rank of segment s in the candidate list X[p, end-letter class of s],
     // per previous class p (the compact SLPF's bit index)
     const uint32_t NL = A.C + 1;
-    std::vector<uint8_t> rankx(size_t(NL) * std::max<uint32_t>(A.nseg, 1), 0xff);
+    // (per previous class p, or per class pair (p, q) when an end-letter set
+    // spans several classes, so that a segment lies in several lists X[p, q])
+    bool rank_pq = false;
+    {
+        std::vector<int> seen(A.nseg, -1);
+        for (uint32_t pq = 0; pq < NL * NL && !rank_pq; ++pq)
+            for (uint32_t k = A.xoff[pq]; k < A.xoff[pq + 1]; ++k) {
+                const int q = static_cast<int>(pq % NL);
+                if (seen[A.xlist[k]] >= 0 && seen[A.xlist[k]] != q) rank_pq = true;
+                seen[A.xlist[k]] = q;
+            }
+    }
+    const size_t rank_rows = rank_pq ? size_t(NL) * NL : NL;
+    std::vector<uint8_t> rankx(rank_rows * std::max<uint32_t>(A.nseg, 1), 0xff);
     for (uint32_t pq = 0; pq < NL * NL; ++pq)
         for (uint32_t k = A.xoff[pq]; k < A.xoff[pq + 1]; ++k)
-            rankx[size_t(pq / NL) * A.nseg + A.xlist[k]] = static_cast<uint8_t>(k - A.xoff[pq]);
+            rankx[(rank_pq ? pq : pq / NL) * size_t(A.nseg) + A.xlist[k]] = static_cast<uint8_t>(k - A.xoff[pq]);
     // per state, the non-zero words of its set (W <= 32)
     auto nonzero_words = [&](const HostTable &t) {
         std::vector<uint32_t> nz(t.nstates, 0);
@@ -136,17 +149,26 @@ slpf_status upload(slpf_parser *p) {
     // tree count: sizes of the clean columns over pairs of a forward state
     // reachable from I (ids 1 .. dfa_states: the powerset from I is built
     // first) and a reverse state reachable from F; every (forward, backward)
-    // id pair of an accepted text's column is such a pair.  Kept when small.
+    // id pair of an accepted text's column is such a pair.  Kept when small:
+    // one byte per pair (sizes capped at 255), or, when that is over the
+    // limit, 4 bits per pair (capped at 15)
     uint32_t kfd = A.fwd.dfa_states + 1, krd = A.rev.dfa_states + 1;
-    if (size_t(kfd) * krd > kMaxPairTable) kfd = krd = 0;
-    std::vector<uint8_t> pairm(std::max<size_t>(size_t(kfd) * krd, 1), 0);
+    const size_t npairs = size_t(kfd) * krd;
+    const bool pair_nib = npairs > kMaxPairTable;
+    if ((npairs + 1) / 2 > kMaxPairTable) kfd = krd = 0;
+    const size_t pair_bytes = pair_nib ? (size_t(kfd) * krd + 1) / 2 : size_t(kfd) * krd;
+    std::vector<uint8_t> pairm(std::max<size_t>(pair_bytes, 1), 0);
     for (uint32_t f = 0; f < kfd; ++f)
         for (uint32_t b = 0; b < krd; ++b) {
             uint32_t m = 0;
             for (uint32_t w = 0; w < A.W; ++w)
                 m += static_cast<uint32_t>(
                     __builtin_popcountll(A.fwd.bits[size_t(f) * A.W + w] & A.rev.bits[size_t(b) * A.W + w]));
-            pairm[size_t(f) * krd + b] = static_cast<uint8_t>(std::min<uint32_t>(m, 255));
+            const size_t k = size_t(f) * krd + b;
+            if (pair_nib)
+                pairm[k >> 1] |= static_cast<uint8_t>(std::min<uint32_t>(m, 15) << ((k & 1) * 4));
+            else
+                pairm[k] = static_cast<uint8_t>(std::min<uint32_t>(m, 255));
         }
     // arcs between two adjacent clean columns of an accepted text, over the
     // forward state f of the left column, the reverse state b of the right
@@ -252,6 +274,7 @@ slpf_status upload(slpf_parser *p) {
     t.rdo = off16 ? reinterpret_cast<const uint16_t *>(at(15)) : nullptr;
     t.cls2 = off16 ? reinterpret_cast<const uint16_t *>(at(16)) : nullptr;
     t.rankx = at(17);
+    t.rank_pq = rank_pq ? 1u : 0u;
     t.fnz = reinterpret_cast<const uint32_t *>(at(18));
     t.rnz = reinterpret_cast<const uint32_t *>(at(19));
     t.xoff_nb = reinterpret_cast<const uint32_t *>(at(20));
@@ -262,6 +285,7 @@ slpf_status upload(slpf_parser *p) {
     t.pairm = at(23);
     t.kfd = kfd;
     t.krd = krd;
+    t.pair_nib = pair_nib && kfd ? 1u : 0u;
     t.predseg = reinterpret_cast<const uint64_t *>(at(24));
     t.arcs2 = with_arcs ? reinterpret_cast<const uint16_t *>(at(25)) : nullptr;
     t.col_single = p->col_single ? 1u : 0u;
@@ -525,7 +549,7 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
 
     Layout L;
     int itd = L.add(T > 1 ? T * 32 + (T + 1) * 4 + 64 : 8);
-    int iR = L.add(size_t(E) * c * 2), iRh = L.add(size_t(E) * c * 2);
+    int iR = L.add(size_t(E) * c * 2), iRh = L.add(size_t(E) * c * 2), iRt = L.add(size_t(E) * c * 2);
     int iMf = L.add(size_t(c) * E * EW * 8), iMb = L.add(size_t(c) * E * EW * 8);
     int inxf = L.add(size_t(c + 1) * 2), inxb = L.add(size_t(c + 1) * 2), irsf = L.add(c + 1), irsb = L.add(c + 1);
     int ifin = L.add(size_t(c + 1) * EW * 8), ifout = L.add(size_t(c + 1) * EW * 8);
@@ -636,6 +660,7 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
     }
     jb.R = reinterpret_cast<uint16_t *>(ptr(iR));
     jb.Rh = reinterpret_cast<uint16_t *>(ptr(iRh));
+    jb.Rt = reinterpret_cast<uint16_t *>(ptr(iRt));
     jb.Mf = reinterpret_cast<uint64_t *>(ptr(iMf));
     jb.MbR = reinterpret_cast<uint64_t *>(ptr(iMb));
     jb.nxf = reinterpret_cast<uint16_t *>(ptr(inxf));
@@ -777,13 +802,14 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
         // compact: the rank table goes after the tables when LDS has room and
         // it does not cost a resident block per CU
         const size_t tabs_end = kStageBytes + (fit_tab ? tab_lds : 0) + (fit_bits ? bits_lds : 0);
-        const size_t rank_bytes = (size_t(tb.NL) * tb.nseg + 15) & ~size_t(15);
+        const size_t rank_bytes = ((tb.rank_pq ? size_t(tb.NL) * tb.NL : tb.NL) * tb.nseg + 15) & ~size_t(15);
         const bool rank_fits = tabs_end + rank_bytes <= p->lds_limit &&
                                kLdsPerCu / (tabs_end + rank_bytes) == kLdsPerCu / tabs_end;
         jb.rank_lds = jb.compact && lds && rank_fits ? static_cast<uint32_t>(tabs_end) : 0u;
         size_t bld_lds = tabs_end + (jb.rank_lds ? rank_bytes : 0);
         // tree count: the pair table after them, on the same terms
-        const size_t pair_bytes = (size_t(tb.kfd) * tb.krd + 15) & ~size_t(15);
+        const size_t pair_bytes =
+            ((tb.pair_nib ? (size_t(tb.kfd) * tb.krd + 1) / 2 : size_t(tb.kfd) * tb.krd) + 15) & ~size_t(15);
         const bool pair_fits = pair_bytes && bld_lds + pair_bytes <= p->lds_limit &&
                                kLdsPerCu / (bld_lds + pair_bytes) == kLdsPerCu / bld_lds;
         jb.pair_lds = count && !tb.col_single && lds && pair_fits ? static_cast<uint32_t>(bld_lds) : 0u;

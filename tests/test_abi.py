@@ -43,7 +43,9 @@ def _sets(o, words):
 
 
 RES = ["(ab|a)*", "(a|b|ab)+", "(a|ab|b)*(c|bc)+(a|b)*", "(a|())b", "(a|ab|aba)+", "a", "()",
-       "(a|b)*a(a|b)(a|b)(a|b)", "x(y|z+)*w?", "(\\(|\\)|\\*)+", "\\x00(\\n|\\t)*"]
+       "(a|b)*a(a|b)(a|b)(a|b)", "x(y|z+)*w?", "(\\(|\\)|\\*)+", "\\x00(\\n|\\t)*",
+       # character sets and the wildcard (App. A, character features)
+       "([a-e]x|[d-g]y)*", "(.|[^a-c]b)+", "[0-9]+(\\.[0-9]+)?", "([\\]\\-]|a.)*", "[^\\n]*\\n"]
 
 
 @pytest.mark.parametrize("pat", RES + [regen.to_re(regen.random_re(s, n_ops=14, max_depth=5)).decode()
@@ -139,3 +141,17 @@ def test_column_unambiguous_flag_matches_oracle():
         assert p.info.column_unambiguous == int(want), pat
         seen.add(want)
     assert seen == {True, False}
+
+
+def test_charset_classes_are_the_disjoint_split():
+    # Fig. charset: the sets [a-e] and [d-g] overlap; the bytes are split into
+    # the disjoint classes [a-c], [d-e] and [f-g] (plus x and y), and every
+    # segment keeps its set end-letter (no extra segments)
+    p = S.Parser("([a-e]x|[d-g]y)*", host_only=True)
+    _, _, cm = p.table(0)
+    cls = lambda bs: {int(cm[b]) for b in bs}
+    assert len(cls(b"abc")) == 1 and len(cls(b"de")) == 1 and len(cls(b"fg")) == 1
+    assert len(cls(b"abc") | cls(b"de") | cls(b"fg") | cls(b"x") | cls(b"y")) == 5
+    assert int(cm[ord("h")]) == 0 and p.info.num_classes == 6
+    o = Oracle("([a-e]x|[d-g]y)*")
+    assert p.segments == o.segments and p.nseg == o.nseg

@@ -99,6 +99,16 @@ def test_batch_force_l2_and_random_res():
         check_batch(pat, texts, chunk_bytes=128, force_l2=True)
 
 
+def test_batch_char_set_res():
+    # REs with character-set and wildcard leaves, mixed accepted and
+    # rejected texts in one job
+    device()
+    for seed in (3, 8):
+        tree = regen.random_re(7700 + seed, n_ops=14, max_depth=5, alphabet=b"abcdefghij", set_p=0.5)
+        pat = regen.to_re(tree)
+        check_batch(pat, mixed_texts(tree, 40 + seed, 24, 8000), chunk_bytes=128)
+
+
 def test_batch_empty_and_tiny_only():
     device()
     pat = "(ab|a)*"

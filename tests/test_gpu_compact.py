@@ -135,3 +135,20 @@ def test_compact_capacity_and_arguments():
     torch.cuda.synchronize()
     assert p._L.slpf_compact_bytes(32) == 33 * 8
     assert p._L.slpf_decode_compact(p.handle, None, 0, None, None, None) == S.E_ARG
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_compact_char_set_res(seed):
+    # character-set and wildcard leaves (App. A, character features): a
+    # segment whose end-letter set spans several byte classes lies in several
+    # candidate lists, so its bit index depends on both bytes around the column
+    device()
+    alpha = [b"abcd", b"abcdefghij"][seed % 2]
+    while True:
+        tree = regen.random_re(7300 + seed, n_ops=10, max_depth=4, alphabet=alpha, set_p=0.5)
+        pat = regen.to_re(tree)
+        if S.Parser(pat, host_only=True).info.max_entries <= 64:
+            break
+        seed += 100
+    say("compact sets", pat[:70])
+    check(pat, _texts(tree, 50 + seed, 6, 3000), chunks=(0, 64))

@@ -69,10 +69,10 @@ def test_matches_random_res(seed):
 
 
 def test_matches_record_fields():
-    # the record RE's groups over 8 KB of records (fields, records, the star)
+    # the CSV record RE's groups over 8 KB of records (fields, records, the star)
     device()
-    pat = regen.to_re(regen.record_re())
-    x = textgen.record_text(3, 8000).tobytes()
+    pat = regen.to_re(regen.csv_record_re())
+    x = textgen.csv_record_text(3, 8000).tobytes()
     p = S.Parser(pat)
     gs = groups_of(p)
     check(pat, [x], groups=gs[:12] + gs[-6:])

@@ -279,3 +279,82 @@ def test_entry_lists_over_64_segments():
         with pytest.raises(S.SlpfError) as err:
             p.parse_compact(to_device(text))
         assert err.value.status == S.E_TOO_LARGE
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_char_set_res_and_texts(seed):
+    # leaves that are character sets or the wildcard (App. A, character
+    # features); alphabets of 4, 10 and 128 byte values; accepted and
+    # corrupted texts; several lane-chunk sizes and both table placements
+    rng = np.random.default_rng(600 + seed)
+    alpha = [b"abcd", b"abcdefghij", bytes(range(1, 128))][seed % 3]
+    depth = int(rng.integers(4, 7))
+    s = 6100 + seed
+    while True:
+        try:
+            tree = regen.random_re(s, n_ops=int(rng.integers(6, 4 * depth)), max_depth=depth,
+                                   alphabet=alpha, set_p=0.5, max_tries=200)
+            break
+        except RuntimeError:
+            s += 100
+    pat = regen.to_re(tree)
+    o, p = Oracle(pat), S.Parser(pat)
+    assert p.segments == o.segments
+    n = int(rng.integers(1, 30000))
+    text = textgen.sample_text(tree, seed, n)
+    check(pat, text.tobytes(), chunk_bytes=64 * int(rng.integers(1, 40)), o=o, p=p)
+    bad = textgen.corrupt(text, seed, frac=0.01, block=(1, 16)).tobytes()
+    check(pat, bad, chunk_bytes=64, o=o, p=p)
+    check(pat, text.tobytes(), chunk_bytes=128, force_l2=True, o=o, p=p)
+    check(pat, b"", o=o, p=p)
+
+
+def _as_unions(node):
+    """The same tree with every character set written as a union of its bytes."""
+    k = node[0]
+    if k == 'set':
+        return regen.lit_union(node[1])
+    if k in ('cat', 'alt'):
+        return (k, [_as_unions(c) for c in node[1]])
+    if k in ('star', 'plus', 'opt'):
+        return (k, _as_unions(node[1]))
+    return node
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_char_set_and_union_forms_count_alike(seed):
+    # a character set is one terminal for any one of its bytes: an RE and the
+    # same RE with its sets written as unions of single bytes have the same
+    # language and the same number of trees (each byte matches exactly one
+    # branch of the union), the set form with fewer segments.  Random
+    # ambiguous REs and, for seed 0, the CSV record RE; each form bit-exact
+    # against its own oracle
+    if seed == 0:
+        tree = regen.csv_record_re(sets=True)
+        text = textgen.csv_record_text(17, 200000)
+    else:
+        s = 6500 + seed
+        while True:
+            tree = regen.random_re(s, n_ops=12, max_depth=5, alphabet=b"abcd", set_p=0.6)
+            if regen.WILDCARD not in [x[1] for x in _leaves(tree)]:
+                break
+            s += 100
+        text = textgen.sample_text(tree, seed, 20000)
+    us, ss = regen.to_re(_as_unions(tree)), regen.to_re(tree)
+    pu, ps = S.Parser(us), S.Parser(ss)
+    assert ps.info.num_segments < pu.info.num_segments
+    ou, os_ = Oracle(us), Oracle(ss)
+    bad = textgen.corrupt(text, 18, frac=0.01, block=(4, 64))
+    for t in (text.tobytes(), bad.tobytes()):
+        check(us, t, o=ou, p=pu)
+        check(ss, t, o=os_, p=ps)
+        a, b = gpu_parse(pu, t), gpu_parse(ps, t)
+        assert (a[1], a[2], a.countp) == (b[1], b[2], b.countp)
+
+
+def _leaves(node):
+    if node[0] in ('lit', 'set', 'eps'):
+        return [node]
+    if node[0] in ('cat', 'alt'):
+        return [x for c in node[1] for x in _leaves(c)]
+    return _leaves(node[1])

@@ -1,10 +1,13 @@
-"""The record-shaped RE: CSV-like traffic records under one star over a
-128-symbol byte alphabet.  Its forward and reverse tables (618 and 869
-states, 123 byte classes) are too large for LDS, so every kernel reads them
-in place through the caches (the L2 placement).  Bit-exact against the
-oracle on whole 2 MiB texts (clean and with corruption blocks, at several
-lane-chunk sizes), and on sampled windows of a 64 MiB text with the
-automatic chunking.
+"""The record workload: a multi-schema log record RE under one star (a
+timestamp, then one of 14 comma-separated schemas of 8 fields whose byte
+sets overlap, an optional quoted field).  Its forward and reverse tables
+hold 2k-5k states each, with 6 words per column; together they are too
+large for LDS, so every kernel reads them in place through the caches (the
+L2 placement).  A line may follow several schemas, so the text has many
+trees.  Bit-exact against the oracle on whole 2 MiB texts (clean and with
+corruption blocks, at several lane-chunk sizes), on sampled windows of a
+64 MiB text with the automatic chunking, and at 1 GiB against the oracle's
+accept flag and counts over the whole text.
 """
 import hashlib
 import os
@@ -37,7 +40,8 @@ def test_record_tables_are_l2_resident(record):
     device()
     pat, p, o = record
     assert p.info.placement == 1
-    assert p.info.fwd_states > 500 and p.info.num_classes > 100
+    assert 2000 <= p.info.fwd_states <= 5000 and 2000 <= p.info.rev_states <= 5000
+    assert p.W <= 8
     assert p.segments == o.segments
 
 
@@ -92,11 +96,12 @@ def test_record_large_sampled_windows(record):
 
 def test_record_full_size_sampled_records(record):
     # the record workload at its full size (1 GiB, the benchmark's automatic
-    # chunking).  The RE is a star of records, so a run of whole records is a
-    # text of the language and its trees are the full text's trees cut at the
-    # record boundaries: the oracle's columns of the run, except its first and
-    # last column (the star's opening and closing there), must equal the GPU's
-    # columns at the same positions; the whole text has exactly one tree
+    # chunking).  The RE is a star of records that end at the only newline of
+    # each, so a run of whole records is a text of the language and its trees
+    # are the full text's trees cut at the record boundaries: the oracle's
+    # columns of the run, except its first and last column (the star's
+    # opening and closing there), must equal the GPU's columns at the same
+    # positions
     import torch
     device()
     pat, p, o = record
@@ -126,7 +131,7 @@ def test_record_full_size_sampled_records(record):
         b = a + int(ends[min(2, ends.size - 1)]) + 1
         sub = text[a:b].tobytes()
         oc, acc, cnt = o.parse(sub)
-        assert acc and cnt == 1
+        assert acc and cnt >= 1
         g = cols[a:b + 1].cpu().numpy().view(np.uint64)
         lo = 0 if a == 0 else 1                          # column 0 is the same at the text start
         hi = b - a + 1 if b == n else b - a              # and column n at the text end
