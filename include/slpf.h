@@ -201,10 +201,16 @@ enum {
     SLPF_PARSE_COMPACT = 1u << 3,       /* write the compact SLPF (App. SLPF optimization, SLPF
                                            encoding): column r as ONE word; see slpf_decode_compact.
                                            capacity_bytes >= slpf_compact_bytes(n) */
-    SLPF_PARSE_NEXT_BYTE_ENTRIES = 1u << 4  /* speculation ablation: each lane chunk's runs start
+    SLPF_PARSE_NEXT_BYTE_ENTRIES = 1u << 4, /* speculation ablation: each lane chunk's runs start
                                            from every segment whose end-letter is the chunk's first
                                            byte (the ME-DFA entries of Sect. 3.1 for that letter),
                                            without the filter by the previous byte.  Same results */
+    SLPF_PARSE_EDGE_SHIFT = 1u << 5,    /* chunk-edge shifting on (Sect. Tool optimization, technique
+                                           (ii)): the speculative runs and the join of a lane chunk
+                                           start at the position, within a window after its edge,
+                                           whose entry list is shortest.  Same results.  Default: on
+                                           when the parser's entry lists exceed 12 segments */
+    SLPF_PARSE_NO_EDGE_SHIFT = 1u << 6  /* chunk-edge shifting off (wins over SLPF_PARSE_EDGE_SHIFT) */
 };
 
 typedef struct {

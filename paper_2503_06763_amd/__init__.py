@@ -28,6 +28,8 @@ PARSE_FORCE_L2 = 2
 PARSE_RECOGNIZE = 4
 PARSE_COMPACT = 8
 PARSE_NEXT_BYTE_ENTRIES = 16
+PARSE_EDGE_SHIFT = 32
+PARSE_NO_EDGE_SHIFT = 64
 
 EXPORTS = ["slpf_compile", "slpf_parser_destroy", "slpf_parser_info_get", "slpf_segment_text",
            "slpf_table_dump", "slpf_forest_bytes", "slpf_parse", "slpf_parse_batch", "slpf_tune", "slpf_parser_trim",

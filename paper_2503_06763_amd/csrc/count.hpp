@@ -181,14 +181,20 @@ __device__ inline bool follows(const Tabs &tb, uint32_t rho, uint32_t sigma) {
     return (tb.folseg[static_cast<uint64_t>(rho) * tb.W + (sigma >> 6)] >> (sigma & 63)) & 1ull;
 }
 
+// The same over a copy of FolSeg (nseg x W words, e.g. in LDS).
+__device__ inline bool follows(const uint64_t *fol, uint32_t W, uint32_t rho, uint32_t sigma) {
+    return (fol[rho * W + (sigma >> 6)] >> (sigma & 63)) & 1ull;
+}
+
 // ------------------------------------------------------- short runs, lanes
 
 constexpr int kTV = 8;               // largest column of a run counted in registers
+constexpr uint32_t kDeferRun = 0x80000000u;   // deferred item: a queued short run, not a window
 
 // Paths through columns r0 .. r1 entering anywhere and leaving anywhere
 // (one lane); false when a column holds more than kTV segments.
-__device__ inline bool run_paths_lane(const Tabs &tb, const Job &jb, const TextCols &tc, uint64_t r0, uint64_t r1,
-                                      Cnt &out) {
+__device__ inline bool run_paths_lane(const Tabs &tb, const uint64_t *fol, const Job &jb, const TextCols &tc,
+                                      uint64_t r0, uint64_t r1, Cnt &out) {
     uint32_t sp[kTV], sn[kTV];
     uint64_t ya[kTV], yp[kTV];
     const uint32_t mp0 = for_segments(tb, jb, tc, r0, [&](uint32_t k, uint32_t sg) {
@@ -218,7 +224,7 @@ __device__ inline bool run_paths_lane(const Tabs &tb, const Job &jb, const TextC
             if (static_cast<uint32_t>(k) < m) {
 #pragma unroll
                 for (int j = 0; j < kTV; ++j) {
-                    if (static_cast<uint32_t>(j) < mp && follows(tb, sp[j], sn[k])) {
+                    if (static_cast<uint32_t>(j) < mp && follows(fol, tb.W, sp[j], sn[k])) {
                         za[k] += ya[j];
                         zp[k] = addp(zp[k], yp[j]);
                     }
@@ -276,31 +282,100 @@ __device__ inline void emit_long(const Job &jb, uint32_t t, uint64_t r0, uint64_
 constexpr int kRunThreads = 256;
 
 // One thread per 64-column window, window-major as the marks (g = w c + i):
-// the lanes of a wavefront read consecutive mark words.
+// the lanes of a wavefront read consecutive mark words.  Long runs are
+// emitted for the piece kernels; the short runs starting in the window are
+// queued for k_count_short (one atomic per wavefront).  When the queue is
+// full the wavefront counts its short runs itself (a lane each; windows with
+// a column too large for the lane go to the deferred list).
 __global__ __launch_bounds__(kRunThreads) void k_count_runs(Tabs tb, Job jb) {
     const uint32_t sw = static_cast<uint32_t>(jb.s >> 6);
     const uint64_t gg = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (gg >= static_cast<uint64_t>(jb.c) * sw) return;
-    const uint32_t g = static_cast<uint32_t>(gg);
-    const uint32_t w = g / jb.c, i = g - w * jb.c;
-    const ChunkCtx cx = chunk_ctx(jb, i);
-    if (cx.tr.scalars[0] == 0 || 64ull * w >= cx.hi - cx.lo) return;    // rejected, or past the chunk
-    const TextCols tc = text_cols(jb, cx.t);
+    const uint32_t lane = threadIdx.x & 63u;
+    bool act = gg < static_cast<uint64_t>(jb.c) * sw;
+    uint32_t g = 0, w = 0, i = 0;
+    ChunkCtx cx{};
+    TextCols tc{};
+    if (act) {
+        g = static_cast<uint32_t>(gg);
+        w = g / jb.c;
+        i = g - w * jb.c;
+        cx = chunk_ctx(jb, i);
+        act = cx.tr.scalars[0] != 0 && 64ull * w < cx.hi - cx.lo;          // accepted, inside the chunk
+    }
+    if (act) tc = text_cols(jb, cx.t);
+    uint32_t ns = 0;
+    if (act)
+        for_window_run_starts(jb, tc, i, w, cx, [&](uint64_t r0) {
+            const uint64_t r1 = run_end(jb, tc, r0);
+            if (r1 - r0 + 1 > jb.lshort)
+                emit_long(jb, cx.t, r0, r1);
+            else
+                ++ns;
+        });
+    uint32_t incl = ns;   // inclusive prefix over the wavefront
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t v = static_cast<uint32_t>(__shfl_up(static_cast<int>(incl), d));
+        if (lane >= static_cast<uint32_t>(d)) incl += v;
+    }
+    const uint32_t total = static_cast<uint32_t>(__shfl(static_cast<int>(incl), 63));
+    if (total == 0) return;
+    unsigned long long base = 0;
+    if (lane == 63) base = atomicAdd(jb.nsruns, static_cast<unsigned long long>(total));
+    base = shfl_u64(base, 63);
+    uint64_t slot = base + incl - ns;
+    if (base + total <= jb.cap_sruns) {
+        if (ns)
+            for_window_run_starts(jb, tc, i, w, cx, [&](uint64_t r0) {
+                const uint64_t r1 = run_end(jb, tc, r0);
+                if (r1 - r0 + 1 <= jb.lshort) jb.sruns[slot++] = ShortRun{r0, static_cast<uint32_t>(r1 - r0 + 1), i};
+            });
+        return;
+    }
+    for (uint32_t k = 0; k < ns; ++k)
+        if (slot + k < jb.cap_sruns) jb.sruns[slot + k].len = 0;          // reserved below the capacity
+    if (!ns) return;
     Cnt acc{1, 1};
     bool defer = false;
     for_window_run_starts(jb, tc, i, w, cx, [&](uint64_t r0) {
         const uint64_t r1 = run_end(jb, tc, r0);
-        if (r1 - r0 + 1 > jb.lshort) {
-            emit_long(jb, cx.t, r0, r1);
-            return;
-        }
-        if (defer) return;
+        if (r1 - r0 + 1 > jb.lshort || defer) return;
         Cnt x;
-        if (run_paths_lane(tb, jb, tc, r0, r1, x)) acc = cmul(acc, x);
+        if (run_paths_lane(tb, tb.folseg, jb, tc, r0, r1, x)) acc = cmul(acc, x);
         else defer = true;
     });
     if (defer) jb.dchunk[atomicAdd(&jb.ccnt[0], 1u)] = g;      // one entry per window
     else if (acc.a != 1 || acc.p != 1) cmul_at(jb.cfac + 2ull * i, acc);
+}
+
+constexpr int kShortThreads = 256;
+constexpr uint32_t kFolLdsBytes = 32768;   // FolSeg staged in LDS up to this size
+
+// The queued short runs, one per lane (grid-stride).  A run's paths go
+// into the product of its lane chunk; a run with a column of more than kTV
+// segments is deferred to the wavefront walk (its queue index, tagged).
+__global__ __launch_bounds__(kShortThreads) void k_count_short(Tabs tb, Job jb) {
+    extern __shared__ __align__(16) uint64_t fol_lds[];
+    const uint64_t *fol = tb.folseg;
+    if (jb.fol_lds) {
+        const uint32_t nw = tb.nseg * tb.W;
+        for (uint32_t k = threadIdx.x; k < nw; k += blockDim.x) fol_lds[k] = tb.folseg[k];
+        __syncthreads();
+        fol = fol_lds;
+    }
+    const uint64_t nq = min(*jb.nsruns, static_cast<unsigned long long>(jb.cap_sruns));
+    const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+    for (uint64_t k = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; k < nq; k += stride) {
+        const ShortRun rr = jb.sruns[k];
+        if (rr.len == 0) continue;
+        const TextCols tc = text_cols(jb, text_of(jb, rr.i));
+        Cnt x;
+        if (run_paths_lane(tb, fol, jb, tc, rr.r0, rr.r0 + rr.len - 1, x)) {
+            if (x.a != 1 || x.p != 1) cmul_at(jb.cfac + 2ull * rr.i, x);
+        } else {
+            jb.dchunk[atomicAdd(&jb.ccnt[0], 1u)] = kDeferRun | static_cast<uint32_t>(k);
+        }
+    }
 }
 
 // ----------------------------------------------------- wavefront walks
@@ -419,11 +494,26 @@ __device__ inline Cnt walk_sum(const WalkLds &L, uint32_t buf, uint32_t m, int v
     return wave_sum_cnt(s);
 }
 
-// Deferred windows: their short runs, one wavefront per window.
+// Deferred windows (their short runs) and deferred queued runs, one
+// wavefront per item.
 __global__ __launch_bounds__(64) void k_count_defer(Tabs tb, Job jb) {
     __shared__ WalkLds L;
     for (uint32_t item = blockIdx.x; item < jb.ccnt[0]; item += gridDim.x) {
         const uint32_t g = jb.dchunk[item];
+        if (g & kDeferRun) {
+            const ShortRun rr = jb.sruns[g & ~kDeferRun];
+            const uint32_t t = text_of(jb, rr.i);
+            const TextCols tc = text_cols(jb, t);
+            uint32_t buf = 0, m = 0;
+            const bool ok = wave_walk<1>(tb, jb, tc, rr.r0, rr.r0 + rr.len - 1, L, buf, m);
+            const Cnt x = ok ? walk_sum<1>(L, buf, m, 0) : Cnt{1, 1};
+            if (threadIdx.x == 0) {
+                cmul_at(jb.cfac + 2ull * rr.i, x);
+                if (!ok) jb.tfail[t] = 1;
+            }
+            __syncthreads();
+            continue;
+        }
         const uint32_t w = g / jb.c, i = g - w * jb.c;
         const ChunkCtx cx = chunk_ctx(jb, i);
         const TextCols tc = text_cols(jb, cx.t);

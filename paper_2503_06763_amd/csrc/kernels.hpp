@@ -103,6 +103,13 @@ struct Tabs {
     uint64_t wmagic;            // ceil(2^32 / W): e / W == (e * wmagic) >> 32 for e < 2^16
 };
 
+// A short run queued for k_count_short: columns r0 .. r0 + len - 1 of the
+// text of lane chunk i (len = 0: a slot left unused).
+struct ShortRun {
+    uint64_t r0;
+    uint32_t len, i;
+};
+
 // A long run of marked columns r0 .. r1 of text t, cut into npc pieces
 // (piece items pb .., matrix slots mb .. when npc > 1).
 struct RunRec {
@@ -121,7 +128,11 @@ struct Job {
     uint64_t s;                 // lane chunk bytes
     uint32_t c;                 // lane chunks of all texts
     uint16_t *R, *Rh;           // [emax][c] end ids of the reach runs
-    uint16_t *Rt;               // [emax][c] reach: ids of the runs after their first stretch
+    uint16_t *Rt;               // [emax][c] reach: ids of the runs part way
+    uint16_t *Rm, *Rmh;         // [emax][c] ids of lane k's forward / backward runs at its fixed right
+                                // edge (chunk-edge shifting; without it Rm is R and Rmh is unused)
+    uint8_t *eshift;            // [c] the right edge of lane k's runs was shifted past its fixed edge
+    uint32_t shift;             // chunk-edge shifting window (bytes), 0 = off
     uint64_t *Mf, *MbR;         // [c][emax][ew] masks; MbR indexed by c-1-i
     uint32_t ew;                // words of an entry-list mask (ceil(emax / 64))
     uint16_t *nxf, *nxb;        // entry-list sizes at the scan input of item k (forward: left edge of
@@ -149,6 +160,10 @@ struct Job {
     uint32_t *ccnt;             // [0] deferred windows, [1] long runs, [2] pieces, [3] matrix slots
     uint32_t *dchunk;           // windows (w c + i) whose short runs the wave kernel counts
     RunRec *runs;               // [cap_runs] long runs
+    ShortRun *sruns;            // [cap_sruns] short runs queued for k_count_short
+    unsigned long long *nsruns; // short runs queued (may pass cap_sruns: then the rest are counted in place)
+    uint32_t cap_sruns;
+    uint32_t fol_lds;           // k_count_short: FolSeg staged in LDS (it fits)
     uint64_t *piece;            // [cap_pieces]: run index | piece number << 32
     uint64_t *mats;             // [cap_mats][kPieceR][kPieceR][2] piece matrices
     uint32_t *pmat;             // [cap_pieces]: rows | cols << 8 of the piece's matrix, or void
@@ -331,11 +346,12 @@ __device__ inline void load_window(const uint8_t *text, uint64_t a0, uint32_t le
 // -------------------------------------------------------------------- reach
 
 // Runs kGroup ME-DFA runs in lockstep over text[lo, hi) (forward) or its
-// reverse (backward); lo is 16-byte aligned, so the body is read with 16-byte
-// loads.  Runs that reach the same state are merged (equal states have equal
+// reverse (backward); the part between the first and the last 16-byte
+// boundary is read with 16-byte loads.  Runs that reach the same state are merged (equal states have equal
 // futures); `alias` maps entry k of the group to the slot holding its run.
 // Slots dead in every lane of the wavefront are skipped.
-template <bool FWD, bool OFF, bool GRP>
+// HEAD: lo may lie off a 16-byte boundary (else it is known to lie on one).
+template <bool FWD, bool OFF, bool GRP, bool HEAD = true>
 __device__ __forceinline__ void run_group(const uint8_t *text, uint64_t lo, uint64_t hi, const uint16_t *cls,
                                  const uint16_t *delta, uint32_t C, uint32_t st[kGroup],
                                  uint64_t &alias) {
@@ -405,12 +421,19 @@ __device__ __forceinline__ void run_group(const uint8_t *text, uint64_t lo, uint
                 if (j < static_cast<int>(nl)) st[j] = delta[st[j] * C + cl];
         }
     };
-    const uint64_t body = (hi - lo) & ~15ull;
+    // [lo, a) head up to the first 16-byte boundary, [a, a + body) in blocks,
+    // the rest a tail (the text itself starts on a 16-byte boundary)
+    const uint64_t a = HEAD ? min(hi, (lo + 15) & ~15ull) : lo;
+    const uint64_t body = (hi - a) & ~15ull;
     if (!settle()) return;
-    if (!FWD)
-        for (uint64_t p = hi; p-- > lo + body;) step(text[p]);
+    if (FWD) {
+        if constexpr (HEAD)
+            for (uint64_t p = lo; p < a; ++p) step(text[p]);
+    } else {
+        for (uint64_t p = hi; p-- > a + body;) step(text[p]);
+    }
     const uint64_t nblk = body >> 4;
-    const uint4 *vp = reinterpret_cast<const uint4 *>(text + lo);
+    const uint4 *vp = reinterpret_cast<const uint4 *>(text + a);
     // 16-byte blocks in processing order; the next block is loaded while the
     // current ones are consumed, so the wave does not wait on HBM per block.
     // GRP: four blocks (64 bytes) a lane per load round, so that a lane uses
@@ -458,38 +481,35 @@ __device__ __forceinline__ void run_group(const uint8_t *text, uint64_t lo, uint
             v = nv;
         }
     }
-    if (FWD)
-        for (uint64_t p = lo + body; p < hi; ++p) step(text[p]);
+    if (FWD) {
+        for (uint64_t p = a + body; p < hi; ++p) step(text[p]);
+    } else {
+        if constexpr (HEAD)
+            for (uint64_t p = a; p-- > lo;) step(text[p]);
+    }
 }
 
-// The n runs of one direction over a lane's chunk, from the singletons of the
-// entry list xl: out[m * c + i] = end id of the run from entry m.  Every run
-// first covers only the first kReachPre bytes of its direction, kGroup runs
-// in lockstep; their ids there go to tmp, and only the distinct ones go on
-// over the rest of the chunk, kGroup at a time in increasing id order.  Runs
-// from different groups that have met within the first stretch (on record
-// text, every run that passes a record end) are therefore run once.
-template <bool FWD, bool OFF, bool GRP>
-__device__ __forceinline__ void reach_runs(const uint8_t *text, uint64_t lo, uint64_t hi, const uint16_t *cls,
-                                  const uint16_t *delta, uint32_t C, uint32_t c2, const uint16_t *single,
-                                  const uint16_t *xl, uint32_t n, uint16_t *out, uint16_t *tmp, uint32_t c,
-                                  uint32_t i) {
-    // first stretch: forward [lo, mid), backward [mid, hi); mid is a multiple
-    // of 16 bytes from lo, so both parts keep 16-byte loads
-    uint64_t mid;
-    if constexpr (FWD)
-        mid = hi - lo > kReachPre ? lo + kReachPre : hi;
-    else
-        mid = hi - lo > kReachPre ? lo + ((hi - kReachPre - lo) & ~63ull) : lo;
-    const bool rest = FWD ? mid < hi : mid > lo;
-    auto pick = [&](const uint32_t st[kGroup], uint64_t alias, int k) -> uint32_t {
-        const uint32_t sl = (alias >> (4 * k)) & 15u;
-        uint32_t v = 0;
+// Id of the run of group entry k (slot alias nibble k; 15: dead).
+template <bool OFF>
+__device__ __forceinline__ uint32_t slot_id(const uint32_t st[kGroup], uint64_t alias, int k, uint32_t c2) {
+    const uint32_t sl = (alias >> (4 * k)) & 15u;
+    uint32_t v = 0;
 #pragma unroll
-        for (int q = 0; q < kGroup; ++q)
-            if (sl == static_cast<uint32_t>(q)) v = st[q];
-        return OFF ? v / c2 : v;
-    };
+    for (int q = 0; q < kGroup; ++q)
+        if (sl == static_cast<uint32_t>(q)) v = st[q];
+    return OFF ? v / c2 : v;
+}
+
+// Runs from the singletons of the entries xl[0 .. n), kGroup in lockstep,
+// over two stretches in processing order: forward [a, m) then [m, b),
+// backward [m, b) (from b down) then [a, m).  out1[e * c + i] (if given) and
+// out2[e * c + i] receive the id of the run from entry e after each stretch
+// (0: dead).
+template <bool FWD, bool OFF, bool GRP, bool SPLIT = true, bool HEAD = true>
+__device__ __forceinline__ void runs_from_entries(const uint8_t *text, uint64_t a, uint64_t m, uint64_t b,
+                                                  const uint16_t *cls, const uint16_t *delta, uint32_t C, uint32_t c2,
+                                                  const uint16_t *single, const uint16_t *xl, uint32_t n,
+                                                  uint16_t *out1, uint16_t *out2, uint32_t c, uint32_t i) {
     for (uint32_t g0 = 0; __any(g0 < n); g0 += kGroup) {
         uint32_t st[kGroup];
         uint64_t alias = 0;
@@ -498,28 +518,38 @@ __device__ __forceinline__ void reach_runs(const uint8_t *text, uint64_t lo, uin
             st[k] = (g0 + k < n) ? single[xl[g0 + k]] * c2 : 0;
             alias |= static_cast<uint64_t>(k) << (4 * k);
         }
-        if constexpr (FWD)
-            run_group<true, OFF, GRP>(text, lo, mid, cls, delta, C, st, alias);
-        else
-            run_group<false, OFF, GRP>(text, mid, hi, cls, delta, C, st, alias);
+        // (without SPLIT the first stretch is empty: m is a for forward runs, b for backward ones)
+        if constexpr (SPLIT) run_group<FWD, OFF, GRP, HEAD>(text, FWD ? a : m, FWD ? m : b, cls, delta, C, st, alias);
+        if (SPLIT && out1) {
 #pragma unroll
-        for (int k = 0; k < kGroup; ++k) {
-            if (g0 + k < n) {
-                const uint32_t v = pick(st, alias, k);
-                const uint64_t at = static_cast<uint64_t>(g0 + k) * c + i;
-                if (rest) tmp[at] = static_cast<uint16_t>(v);
-                if (!rest || v == 0) out[at] = static_cast<uint16_t>(v);   // done, or dead already
-            }
+            for (int k = 0; k < kGroup; ++k)
+                if (g0 + k < n)
+                    out1[static_cast<uint64_t>(g0 + k) * c + i] =
+                        static_cast<uint16_t>(slot_id<OFF>(st, alias, k, c2));
         }
+        run_group<FWD, OFF, GRP, HEAD>(text, FWD ? m : a, FWD ? b : m, cls, delta, C, st, alias);
+#pragma unroll
+        for (int k = 0; k < kGroup; ++k)
+            if (g0 + k < n)
+                out2[static_cast<uint64_t>(g0 + k) * c + i] = static_cast<uint16_t>(slot_id<OFF>(st, alias, k, c2));
     }
-    // the rest of the chunk: distinct ids above thr, kGroup per round.  The
-    // selection is made again after the run (rather than kept in registers
-    // across it) to map every entry to its run's slot.
+}
+
+// The runs of n entries whose ids are in[m * c + i] continued over text[a, b)
+// (backward: from b down to a) into out (a different buffer): only the
+// distinct live ids are run, kGroup at a time in increasing id order, so
+// runs that have met are run once.  The selection is made again after each
+// run (rather than kept in registers across it) to map every entry to its
+// run's slot.
+template <bool FWD, bool OFF, bool GRP>
+__device__ __forceinline__ void runs_from_ids(const uint8_t *text, uint64_t a, uint64_t b, const uint16_t *cls,
+                                              const uint16_t *delta, uint32_t C, uint32_t c2, uint32_t n,
+                                              const uint16_t *in, uint16_t *out, uint32_t c, uint32_t i) {
     auto select = [&](uint32_t thr, uint32_t u[kGroup]) {   // the smallest distinct ids above thr, ascending
 #pragma unroll
         for (int j = 0; j < kGroup; ++j) u[j] = 0xffffffffu;
         for (uint32_t m = 0; m < n; ++m) {
-            const uint32_t v = tmp[static_cast<uint64_t>(m) * c + i];
+            const uint32_t v = in[static_cast<uint64_t>(m) * c + i];
             if (v <= thr || v >= u[kGroup - 1]) continue;
             bool dup = false;
 #pragma unroll
@@ -535,8 +565,13 @@ __device__ __forceinline__ void reach_runs(const uint8_t *text, uint64_t lo, uin
             }
         }
     };
+    for (uint32_t m = 0; m < n; ++m) {       // dead runs stay dead; with no bytes every id stays
+        const uint64_t at = static_cast<uint64_t>(m) * c + i;
+        const uint16_t v = in[at];
+        if (v == 0 || a == b) out[at] = v;
+    }
+    bool more = a != b;
     uint32_t thr = 0;
-    bool more = rest;
     while (__any(more)) {
         uint32_t st[kGroup];
         uint64_t alias = 0;
@@ -549,10 +584,7 @@ __device__ __forceinline__ void reach_runs(const uint8_t *text, uint64_t lo, uin
                 alias |= static_cast<uint64_t>(j) << (4 * j);
             }
         }
-        if constexpr (FWD)
-            run_group<true, OFF, GRP>(text, mid, hi, cls, delta, C, st, alias);
-        else
-            run_group<false, OFF, GRP>(text, lo, mid, cls, delta, C, st, alias);
+        run_group<FWD, OFF, GRP>(text, a, b, cls, delta, C, st, alias);
         if (more) {
             uint32_t u[kGroup];
             select(thr, u);
@@ -561,12 +593,12 @@ __device__ __forceinline__ void reach_runs(const uint8_t *text, uint64_t lo, uin
             for (int j = 0; j < kGroup; ++j) top = u[j] != 0xffffffffu ? u[j] : top;
             for (uint32_t m = 0; m < n; ++m) {
                 const uint64_t at = static_cast<uint64_t>(m) * c + i;
-                const uint32_t v = tmp[at];
+                const uint32_t v = in[at];
                 if (v <= thr || v > top) continue;
                 uint32_t fin = 0;
 #pragma unroll
                 for (int j = 0; j < kGroup; ++j)
-                    if (u[j] == v) fin = pick(st, alias, j);
+                    if (u[j] == v) fin = slot_id<OFF>(st, alias, j, c2);
                 out[at] = static_cast<uint16_t>(fin);
             }
             more = u[kGroup - 1] != 0xffffffffu;   // a full round: there may be more ids above top
@@ -575,8 +607,44 @@ __device__ __forceinline__ void reach_runs(const uint8_t *text, uint64_t lo, uin
     }
 }
 
-template <bool LDS, bool OFF>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k_reach(Tabs tb, Job jb) {
+// Entry list of lane-chunk edge b of a text and its position.  Chunk-edge
+// shifting (Sect. Tool optimization, technique (ii)): with a window w > 0
+// an inner edge moves to the first position in [b s, b s + w) (inside the
+// text) whose entry list X[class(x_p), class(x_{p+1})] is shortest; the
+// text's first and last edges stay.
+__device__ inline uint32_t edge_list(const Tabs &tb, const uint16_t *cls, const uint8_t *text, uint64_t n,
+                                     uint64_t s, uint32_t ct, uint32_t b, uint32_t w, uint64_t &pos) {
+    if (b == 0 || b == ct || w == 0) {
+        pos = b == ct ? n : static_cast<uint64_t>(b) * s;
+        return boundary_list(tb, cls, text, n, s, ct, b);
+    }
+    const uint64_t e = static_cast<uint64_t>(b) * s, end = min(n, e + w);
+    uint32_t pc = cls[text[e - 1]];
+    uint32_t best = 0, bsz = 0xffffffffu;
+    uint64_t bp = e;
+    for (uint64_t p = e; p < end && bsz > 1; ++p) {
+        const uint32_t q = cls[text[p]];
+        const uint32_t l = pc * tb.NL + q;
+        const uint32_t sz = tb.xoff[l + 1] - tb.xoff[l];
+        if (sz < bsz) {
+            bsz = sz;
+            best = l;
+            bp = p;
+        }
+        pc = q;
+    }
+    pos = bp;
+    return best;
+}
+
+// OFF: the runs step through the offset form of the tables; states are byte
+// offsets (id * 2C) until the end ids are stored.
+// MODE 0: entry lists of at most kGroup segments, no edge shifting; 1: the
+// same with shifting; 2: longer lists (every run covers a first stretch,
+// then only the distinct ones go on), with or without shifting.
+template <bool LDS, bool OFF, int MODE>
+__global__ __launch_bounds__(256) void k_reach(Tabs tb, Job jb) {
+    constexpr bool MULTI = MODE == 2;
     extern __shared__ __align__(16) uint8_t smem[];
     Tabs ts = tb;
     if constexpr (OFF) {
@@ -592,8 +660,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     const uint8_t *text = cx.tr.text;
     const uint64_t lo = cx.lo, hi = cx.hi;
     const uint16_t *bcls = OFF ? tb.classmap : lk.cls;
-    const uint32_t la = boundary_list(tb, bcls, text, cx.tr.n, jb.s, cx.ct, cx.li);
-    const uint32_t lb = boundary_list(tb, bcls, text, cx.tr.n, jb.s, cx.ct, cx.li + 1);
+    // the lane's runs cover [pa, pb): its edges, shifted when jb.shift > 0
+    uint64_t pa = lo, pb = hi;
+    const uint32_t sw = MODE == 0 ? 0u : jb.shift;
+    const uint32_t la = edge_list(tb, bcls, text, cx.tr.n, jb.s, cx.ct, cx.li, sw, pa);
+    const uint32_t lb = edge_list(tb, bcls, text, cx.tr.n, jb.s, cx.ct, cx.li + 1, sw, pb);
     const uint32_t xa0 = tb.xoff[la], na = tb.xoff[la + 1] - xa0;
     const uint32_t xb0 = tb.xoff[lb], nb = tb.xoff[lb + 1] - xb0;
     // scan items: forward item i maps X_i -> X_{i+1}; backward item c-1-i maps X_{i+1} -> X_i
@@ -601,16 +672,52 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void k
     jb.rsf[i] = cx.first ? 1 : 0;
     jb.nxb[jb.c - 1 - i] = static_cast<uint16_t>(nb);
     jb.rsb[jb.c - 1 - i] = cx.last ? 1 : 0;
+    if (sw) jb.eshift[i] = pb > hi ? 1 : 0;
 
-    // forward runs from X_i, backward runs from X_{i+1} (not for the recogniser)
     // (four 16-byte blocks a lane per load round with the offset-form LDS
     // tables; the id form's address arithmetic leaves no registers for them)
     constexpr bool GRP = LDS && OFF;
-    reach_runs<true, OFF, GRP>(text, lo, hi, lk.cls, lk.fd, tb.C, c2, tb.fsingle, tb.xlist + xa0, na, jb.R, jb.Rt,
-                               jb.c, i);
-    if (!jb.fwd_only)
-        reach_runs<false, OFF, GRP>(text, lo, hi, lk.cls, lk.rd, tb.C, c2, tb.rsingle, tb.xlist + xb0, nb, jb.Rh,
-                                    jb.Rt, jb.c, i);
+    const uint32_t C = tb.C, c = jb.c;
+    if constexpr (!MULTI) {
+        // one group: forward to the fixed right edge hi (ids in Rm, which is R
+        // without shifting) and on to the shifted edge pb (R); backward from pb
+        // to hi (Rmh) and on to pa (Rh)
+        constexpr bool SPLIT = MODE == 1;
+        // (mode 0: the runs start and end on the lane chunk's own 64-byte edges)
+        runs_from_entries<true, OFF, GRP, SPLIT, SPLIT>(text, pa, SPLIT ? hi : pa, pb, lk.cls, lk.fd, C, c2,
+                                                        tb.fsingle, tb.xlist + xa0, na, SPLIT ? jb.Rm : nullptr, jb.R,
+                                                        c, i);
+        if (!jb.fwd_only)
+            runs_from_entries<false, OFF, GRP, SPLIT, SPLIT>(text, pa, SPLIT ? hi : pb, pb, lk.cls, lk.rd, C, c2,
+                                                             tb.rsingle, tb.xlist + xb0, nb, SPLIT ? jb.Rmh : nullptr,
+                                                             jb.Rh, c, i);
+    } else {
+        // forward runs from X_i: every entry over the first kReachPre bytes,
+        // the distinct runs on to the fixed right edge hi (ids in Rm: J there
+        // is the union of the selected ones), then to the shifted edge pb (ids
+        // in R; without shifting Rm is R)
+        const uint64_t fa = pa + kReachPre < hi ? pa + kReachPre : hi;
+        runs_from_entries<true, OFF, GRP>(text, pa, fa, fa, lk.cls, lk.fd, C, c2, tb.fsingle, tb.xlist + xa0, na,
+                                          nullptr, jb.Rt, c, i);
+        runs_from_ids<true, OFF, GRP>(text, fa, hi, lk.cls, lk.fd, C, c2, na, jb.Rt, jb.Rm, c, i);
+        if (jb.shift) runs_from_ids<true, OFF, GRP>(text, hi, pb, lk.cls, lk.fd, C, c2, na, jb.Rm, jb.R, c, i);
+        // backward runs from X_{i+1} (not for the recogniser): with shifting
+        // first from pb down to the fixed edge hi (ids in Rmh: J^ there), then
+        // every run over the last kReachPre bytes before hi, the distinct ones
+        // down to pa
+        if (!jb.fwd_only) {
+            const uint64_t ba = hi - pa > kReachPre ? max(pa, (hi - kReachPre) & ~15ull) : pa;
+            if (jb.shift) {
+                runs_from_entries<false, OFF, GRP>(text, hi, hi, pb, lk.cls, lk.rd, C, c2, tb.rsingle,
+                                                   tb.xlist + xb0, nb, nullptr, jb.Rmh, c, i);
+                runs_from_ids<false, OFF, GRP>(text, ba, hi, lk.cls, lk.rd, C, c2, nb, jb.Rmh, jb.Rt, c, i);
+            } else {
+                runs_from_entries<false, OFF, GRP>(text, ba, hi, hi, lk.cls, lk.rd, C, c2, tb.rsingle,
+                                                   tb.xlist + xb0, nb, nullptr, jb.Rt, c, i);
+            }
+            runs_from_ids<false, OFF, GRP>(text, pa, ba, lk.cls, lk.rd, C, c2, nb, jb.Rt, jb.Rh, c, i);
+        }
+    }
     // maps between entry lists: forward X_i -> X_{i+1}, backward X_{i+1} -> X_i;
     // row m (ew words) has bit p set when the run from entry m ends in a set
     // holding the p-th segment of the far list
@@ -965,7 +1072,7 @@ __global__ __launch_bounds__(256) void k_starts(Tabs tb, Job jb) {
     const ChunkCtx cx = chunk_ctx(jb, i);
     uint64_t acc[kMaxWords];
     const uint32_t EW = jb.ew;
-    // J at the right edge of chunk k: union of the ends of its runs selected by fin[k]
+    // J at the right edge of chunk k: union of its runs selected by fin[k], at that edge
     auto join_fwd = [&](uint32_t k) -> uint32_t {
         for (uint32_t w = 0; w < W; ++w) acc[w] = 0;
         uint32_t first = 0xffffffffu;
@@ -975,7 +1082,7 @@ __global__ __launch_bounds__(256) void k_starts(Tabs tb, Job jb) {
             while (sel) {
                 const uint32_t m = 64 * e + static_cast<uint32_t>(__builtin_ctzll(sel));
                 sel &= sel - 1;
-                uint32_t id = jb.R[static_cast<uint64_t>(m) * c + k];
+                uint32_t id = jb.Rm[static_cast<uint64_t>(m) * c + k];   // ids at the fixed right edge
                 if (first == 0xffffffffu) first = id;
                 same = same && (id == first);
                 const uint64_t *bt = tb.fbits + static_cast<uint64_t>(id) * W;
@@ -986,18 +1093,22 @@ __global__ __launch_bounds__(256) void k_starts(Tabs tb, Job jb) {
         if (same) return first;
         return lookup_set(tb.fhash, tb.fhmask, tb.fbits, W, acc, jb.flags);
     };
-    // J^ at the left edge of chunk k: union of its backward runs selected by the mask at its right edge
-    auto join_bwd = [&](uint32_t k) -> uint32_t {
+    // J^ at the left edge of chunk k: union of its backward runs selected by
+    // the mask at its right edge (ids: ends of its runs, Rh); with `mid` the
+    // same runs' ids at chunk k's fixed right edge (Rmh, when its runs start
+    // at a shifted edge beyond it): J^ at that edge
+    auto join_bwd = [&](uint32_t k, bool mid) -> uint32_t {
         for (uint32_t w = 0; w < W; ++w) acc[w] = 0;
         uint32_t first = 0xffffffffu;
         bool same = true;
+        const uint16_t *ids = mid ? jb.Rmh : jb.Rh;
         for (uint32_t e = 0; e < EW; ++e) {
             // reversed item c-1-k enters at chunk k's right edge
             uint64_t sel = jb.bin[static_cast<uint64_t>(c - 1 - k) * EW + e];
             while (sel) {
                 const uint32_t m = 64 * e + static_cast<uint32_t>(__builtin_ctzll(sel));
                 sel &= sel - 1;
-                uint32_t id = jb.Rh[static_cast<uint64_t>(m) * c + k];
+                uint32_t id = ids[static_cast<uint64_t>(m) * c + k];
                 if (first == 0xffffffffu) first = id;
                 same = same && (id == first);
                 const uint64_t *bt = tb.rbits + static_cast<uint64_t>(id) * W;
@@ -1009,7 +1120,7 @@ __global__ __launch_bounds__(256) void k_starts(Tabs tb, Job jb) {
         return lookup_set(tb.rhash, tb.rhmask, tb.rbits, W, acc, jb.flags);
     };
     const uint32_t f = cx.first ? tb.fstart : join_fwd(i - 1);
-    const uint32_t r = cx.last ? tb.rstart : join_bwd(i + 1);
+    const uint32_t r = cx.last ? tb.rstart : (jb.shift && jb.eshift[i]) ? join_bwd(i, true) : join_bwd(i + 1, false);
     jb.fid[i] = static_cast<uint16_t>(f);
     jb.rid[i] = static_cast<uint16_t>(r);
     if (jb.trace) {   // one text: J and J^ at every chunk edge
@@ -1023,7 +1134,7 @@ __global__ __launch_bounds__(256) void k_starts(Tabs tb, Job jb) {
             for (uint32_t w = 0; w < W; ++w) Jt[static_cast<uint64_t>(c) * W + w] = e[w];
         }
         if (i == 0) {
-            const uint64_t *e = tb.rbits + static_cast<uint64_t>(join_bwd(0)) * W;
+            const uint64_t *e = tb.rbits + static_cast<uint64_t>(join_bwd(0, false)) * W;
             for (uint32_t w = 0; w < W; ++w) Jh[w] = e[w];
         }
     }
@@ -1479,12 +1590,39 @@ __global__ __launch_bounds__(kBuildThreads) void k_build(Tabs tb, Job jb) {
                                        static_cast<uint64_t>(h * SC) * W;
                     const uint32_t *sj = wave_rows + j * kStageRow;
                     const uint32_t nwords = np * W;
-                    for (uint32_t e = lane; e < nwords; e += 64) {
-                        const uint32_t p = static_cast<uint32_t>((static_cast<uint64_t>(e) * tb.wmagic) >> 32);
-                        const uint32_t ww = e - p * W;
-                        const uint32_t v = sj[p];
-                        // streaming store: the SLPF is not read back by this kernel
-                        __builtin_nontemporal_store(T.fb[(v & 0xffffu) * W + ww] & T.rb[(v >> 16) * W + ww], region + e);
+                    if constexpr (BITS_LDS) {
+                        for (uint32_t e = lane; e < nwords; e += 64) {
+                            const uint32_t p = static_cast<uint32_t>((static_cast<uint64_t>(e) * tb.wmagic) >> 32);
+                            const uint32_t ww = e - p * W;
+                            const uint32_t v = sj[p];
+                            // streaming store: the SLPF is not read back by this kernel
+                            __builtin_nontemporal_store(T.fb[(v & 0xffffu) * W + ww] & T.rb[(v >> 16) * W + ww],
+                                                        region + e);
+                        }
+                        continue;
+                    }
+                    // bit sets in L2: four store rounds at a time, their loads
+                    // first (the stores may alias the tables, so the compiler
+                    // does not move loads above them)
+                    for (uint32_t e0 = lane; e0 < nwords; e0 += 256) {
+                        uint64_t y[4];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const uint32_t e = e0 + 64u * q;
+                            y[q] = 0;
+                            if (e < nwords) {
+                                const uint32_t p = static_cast<uint32_t>((static_cast<uint64_t>(e) * tb.wmagic) >> 32);
+                                const uint32_t ww = e - p * W;
+                                const uint32_t v = sj[p];
+                                y[q] = T.fb[(v & 0xffffu) * W + ww] & T.rb[(v >> 16) * W + ww];
+                            }
+                        }
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const uint32_t e = e0 + 64u * q;
+                            // streaming store: the SLPF is not read back by this kernel
+                            if (e < nwords) __builtin_nontemporal_store(y[q], region + e);
+                        }
                     }
                 }
             }
@@ -1572,10 +1710,8 @@ __global__ __launch_bounds__(256) void k_decode_compact(Tabs tb, const uint8_t *
 }
 
 __global__ void k_init(Job jb) {
-    if (blockIdx.x == 0 && threadIdx.x < 4) {
-        jb.flags[threadIdx.x] = 0;
-        if (jb.count_on) jb.ccnt[threadIdx.x] = 0;
-    }
+    if (blockIdx.x == 0 && threadIdx.x < 4) jb.flags[threadIdx.x] = 0;
+    if (blockIdx.x == 0 && threadIdx.x < 8 && jb.count_on) jb.ccnt[threadIdx.x] = 0;   // with the u64 nsruns
 }
 
 }  // namespace slpf

@@ -20,6 +20,7 @@ namespace {
 using namespace slpf;
 
 constexpr size_t kLdsBudget = 96 * 1024;   // transition tables staged in LDS up to this size
+constexpr uint64_t kShiftWindow = 256;       // chunk-edge shifting: bytes searched after an edge
 constexpr size_t kMaxPairTable = 4u << 20;  // largest table of clean-column sizes (bytes)
 constexpr size_t kMaxArcsTable = 2u << 20;  // largest table of arcs between two columns (entries)
 
@@ -538,6 +539,11 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
     jb.compact = (flags & SLPF_PARSE_COMPACT) ? 1u : 0u;
     jb.s = s;
     jb.c = c;
+    // chunk-edge shifting: on by default when a run group cannot hold the
+    // longest entry list; the window is half a lane chunk at most
+    const bool shift = !(flags & SLPF_PARSE_NO_EDGE_SHIFT) &&
+                       ((flags & SLPF_PARSE_EDGE_SHIFT) || ts.emax > static_cast<uint32_t>(kGroup));
+    jb.shift = shift ? static_cast<uint32_t>(std::min<uint64_t>(kShiftWindow, s / 2)) : 0u;
     if (T == 1) {
         jb.d0[0] = reinterpret_cast<uint64_t>(items[0].text_dev);
         jb.d0[1] = items[0].n;
@@ -550,6 +556,12 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
     Layout L;
     int itd = L.add(T > 1 ? T * 32 + (T + 1) * 4 + 64 : 8);
     int iR = L.add(size_t(E) * c * 2), iRh = L.add(size_t(E) * c * 2), iRt = L.add(size_t(E) * c * 2);
+    int iRm = -1, iRmh = -1, ies = -1;
+    if (shift) {
+        iRm = L.add(size_t(E) * c * 2);
+        iRmh = L.add(size_t(E) * c * 2);
+        ies = L.add(c);
+    }
     int iMf = L.add(size_t(c) * E * EW * 8), iMb = L.add(size_t(c) * E * EW * 8);
     int inxf = L.add(size_t(c + 1) * 2), inxb = L.add(size_t(c + 1) * 2), irsf = L.add(c + 1), irsb = L.add(c + 1);
     int ifin = L.add(size_t(c + 1) * EW * 8), ifout = L.add(size_t(c + 1) * EW * 8);
@@ -585,17 +597,22 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
     const uint64_t cap_runs = cols_total / lshort + T + 1;
     const uint64_t cap_mats = 2 * (cols_total / cell) + 2;
     const uint64_t cap_pieces = cap_runs + cols_total / cell + 1;
-    if (count && (cap_runs > 0xffffffffull || cap_pieces > 0xffffffffull || nck > 0xffffffffull)) return SLPF_E_ARG;
+    // short runs queued for one lane each: room for one per 256 columns (the
+    // rest are counted where they are found)
+    const uint64_t cap_sruns = tb.col_single ? 0 : std::min<uint64_t>(cols_total / 256 + 64, 0x7fffffffull);
+    if (count && (cap_runs > 0xffffffffull || cap_pieces > 0xffffffffull || nck >= 0x80000000ull))
+        return SLPF_E_ARG;
     int iam = -1, iaend = -1, icfac = -1, itprod = -1, itfail = -1, iccnt = -1, idch = -1, iruns = -1, ipiece = -1,
-        imats = -1, ipmat = -1;
+        imats = -1, ipmat = -1, isr = -1;
     if (count) {
         iam = L.add(nck * 8);
         iaend = L.add(size_t(T) * 8);
         icfac = L.add(size_t(c) * 16);
         itprod = L.add(size_t(T) * 16);
         itfail = L.add(size_t(T) * 4);
-        iccnt = L.add(16);
-        idch = L.add(nck * 4);
+        iccnt = L.add(32);
+        idch = L.add((nck + cap_sruns) * 4);
+        isr = L.add(cap_sruns * sizeof(ShortRun));
         iruns = L.add(cap_runs * sizeof(RunRec));
         ipiece = L.add(cap_pieces * 8);
         imats = L.add(cap_mats * kPieceR * kPieceR * 16);
@@ -661,6 +678,9 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
     jb.R = reinterpret_cast<uint16_t *>(ptr(iR));
     jb.Rh = reinterpret_cast<uint16_t *>(ptr(iRh));
     jb.Rt = reinterpret_cast<uint16_t *>(ptr(iRt));
+    jb.Rm = shift ? reinterpret_cast<uint16_t *>(ptr(iRm)) : jb.R;
+    jb.Rmh = shift ? reinterpret_cast<uint16_t *>(ptr(iRmh)) : nullptr;
+    jb.eshift = shift ? reinterpret_cast<uint8_t *>(ptr(ies)) : nullptr;
     jb.Mf = reinterpret_cast<uint64_t *>(ptr(iMf));
     jb.MbR = reinterpret_cast<uint64_t *>(ptr(iMb));
     jb.nxf = reinterpret_cast<uint16_t *>(ptr(inxf));
@@ -692,6 +712,10 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
         jb.piece = reinterpret_cast<uint64_t *>(ptr(ipiece));
         jb.mats = reinterpret_cast<uint64_t *>(ptr(imats));
         jb.pmat = reinterpret_cast<uint32_t *>(ptr(ipmat));
+        jb.sruns = reinterpret_cast<ShortRun *>(ptr(isr));
+        jb.nsruns = reinterpret_cast<unsigned long long *>(ptr(iccnt) + 16);
+        jb.cap_sruns = static_cast<uint32_t>(cap_sruns);
+        jb.fol_lds = size_t(tb.nseg) * tb.W * 8 <= kFolLdsBytes ? 1u : 0u;
         jb.cap_runs = static_cast<uint32_t>(cap_runs);
         jb.cap_pieces = static_cast<uint32_t>(cap_pieces);
         jb.cap_mats = static_cast<uint32_t>(std::min<uint64_t>(cap_mats, 0xffffffffull));
@@ -716,12 +740,21 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
     mark(0);
     if (c) {
         // reach
-        if (lds && tb.off16)
-            hipLaunchKernelGGL((k_reach<true, true>), dim3(blocks), dim3(256), lds_bytes, stream, ts, jb);
-        else if (lds)
-            hipLaunchKernelGGL((k_reach<true, false>), dim3(blocks), dim3(256), lds_bytes, stream, ts, jb);
+        auto reach = [&](auto mode) {
+            constexpr int MU = decltype(mode)::value;
+            if (lds && tb.off16)
+                hipLaunchKernelGGL((k_reach<true, true, MU>), dim3(blocks), dim3(256), lds_bytes, stream, ts, jb);
+            else if (lds)
+                hipLaunchKernelGGL((k_reach<true, false, MU>), dim3(blocks), dim3(256), lds_bytes, stream, ts, jb);
+            else
+                hipLaunchKernelGGL((k_reach<false, false, MU>), dim3(blocks), dim3(256), 0, stream, ts, jb);
+        };
+        if (ts.emax > static_cast<uint32_t>(kGroup))
+            reach(std::integral_constant<int, 2>{});
+        else if (jb.shift)
+            reach(std::integral_constant<int, 1>{});
         else
-            hipLaunchKernelGGL((k_reach<false, false>), dim3(blocks), dim3(256), 0, stream, ts, jb);
+            reach(std::integral_constant<int, 0>{});
     }
     mark(1);
     if (c) {
@@ -837,6 +870,10 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
         const uint64_t nwins = uint64_t(c) * (s / 64);
         hipLaunchKernelGGL(k_count_runs, dim3(static_cast<uint32_t>((nwins + kRunThreads - 1) / kRunThreads)),
                            dim3(kRunThreads), 0, stream, tb, jb);
+        const uint32_t sgrid = static_cast<uint32_t>(
+            std::min<uint64_t>((uint64_t(jb.cap_sruns) + kShortThreads - 1) / kShortThreads, 2048));
+        hipLaunchKernelGGL(k_count_short, dim3(std::max<uint32_t>(sgrid, 1)), dim3(kShortThreads),
+                           jb.fol_lds ? size_t(tb.nseg) * tb.W * 8 : 0, stream, tb, jb);
         const uint32_t wgrid = std::min<uint32_t>(c, 2048);
         hipLaunchKernelGGL(k_count_defer, dim3(wgrid), dim3(64), 0, stream, tb, jb);
         hipLaunchKernelGGL(k_count_pieces, dim3(wgrid), dim3(64), 0, stream, tb, jb);

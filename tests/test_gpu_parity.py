@@ -96,15 +96,17 @@ def test_motif_re_counts():
         check(pat, text, chunk_bytes=k, o=o, p=p)
 
 
-def test_join_trace_matches_oracle_columns():
+@pytest.mark.parametrize("flags", [0, S.PARSE_EDGE_SHIFT])
+def test_join_trace_matches_oracle_columns(flags):
     """J and J^ at every lane-chunk edge equal the serial forward and backward
-    columns there (Eq. joiner reproduces Eq. matrixmul at the chunk edges)."""
+    columns there (Eq. joiner reproduces Eq. matrixmul at the chunk edges),
+    also when the runs and the join start at shifted edges."""
     tree = regen.plain_small_re()
     pat = regen.to_re(tree).decode()
     text = textgen.sample_text(tree, 7, 5000).tobytes()
     o, p = Oracle(pat), S.Parser(pat)
     k = 192
-    gcols, gacc, gcnt, gst, tr = gpu_parse(p, text, chunk_bytes=k, trace=True)
+    gcols, gacc, gcnt, gst, tr = gpu_parse(p, text, chunk_bytes=k, trace=True, flags=flags)
     n = len(text)
     fwd = [o.I]
     for a in text:
@@ -358,3 +360,54 @@ def _leaves(node):
     if node[0] in ('cat', 'alt'):
         return [x for c in node[1] for x in _leaves(c)]
     return _leaves(node[1])
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_chunk_edge_shifting(seed):
+    # chunk-edge shifting (Sect. Tool optimization, technique (ii)) forced on
+    # and off: the same columns, accept flag and counts as the oracle, over
+    # random REs (with and without character sets), accepted and corrupted
+    # texts, several lane-chunk sizes (so shift windows of 32 to 256 bytes)
+    # and both table placements
+    rng = np.random.default_rng(900 + seed)
+    alpha = [b"abc", b"abcdefghij", b"abcdefghijklmnopqrstuvwxyz"][seed % 3]
+    s = 8100 + seed
+    while True:
+        try:
+            tree = regen.random_re(s, n_ops=int(rng.integers(8, 24)), max_depth=6, alphabet=alpha,
+                                   set_p=0.3 if seed % 2 else 0.0, max_tries=200)
+            break
+        except RuntimeError:
+            s += 100
+    pat = regen.to_re(tree)
+    o, p = Oracle(pat), S.Parser(pat)
+    text = textgen.sample_text(tree, seed, int(rng.integers(2000, 40000)))
+    bad = textgen.corrupt(text, seed, frac=0.02, block=(1, 32))
+    for t in (text.tobytes(), bad.tobytes()):
+        cols, acc, cnt, cntp = o.parse_full(t)
+        for k in (64, 256, 1024):
+            for flags in (S.PARSE_EDGE_SHIFT, S.PARSE_NO_EDGE_SHIFT):
+                for l2 in ((False, True) if k == 256 else (False,)):
+                    say("shift", pat[:50], "n=%d k=%d flags=%d l2=%d" % (len(t), k, flags, l2))
+                    g = gpu_parse(p, t, chunk_bytes=k, flags=flags, force_l2=l2)
+                    bad_cols = np.nonzero((g[0] != cols).any(axis=1))[0]
+                    assert bad_cols.size == 0, "first differing column %d" % bad_cols[0]
+                    assert g[1] == acc and g[3] == 0 and g[2] == cnt and g.countp == cntp
+
+
+def test_chunk_edge_shifting_record_text():
+    # record text: every shifted edge lands just after a newline, where the
+    # entry list has a single segment; batched texts and the recogniser too
+    pat = regen.to_re(regen.record_re())
+    o, p = Oracle(pat), S.Parser(pat)
+    text = textgen.record_text(77, 300000)
+    for t in (text.tobytes(), textgen.corrupt(text, 78, frac=0.01, block=(4, 64)).tobytes()):
+        cols, acc, cnt, cntp = o.parse_full(t)
+        for k in (256, 4096):
+            for flags in (0, S.PARSE_NO_EDGE_SHIFT):
+                g = gpu_parse(p, t, chunk_bytes=k, flags=flags)
+                bad_cols = np.nonzero((g[0] != cols).any(axis=1))[0]
+                assert bad_cols.size == 0, "k=%d flags=%d: first differing column %d" % (k, flags, bad_cols[0])
+                assert g[1] == acc and g[3] == 0 and g[2] == cnt and g.countp == cntp
+        r = p.recognize(to_device(t), chunk_bytes=256)
+        assert bool(int(r[0].item())) == acc
