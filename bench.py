@@ -206,10 +206,12 @@ def _oracle_task(job):
     return len(x)
 
 
-def run_batched(args):
+def run_batched(args, leg=False):
     """Many REs and texts: 16 REs, 4096 texts of log-uniform length; per-text
     plain parses vs one batched job per RE (autotuned chunk size and table
-    placement, jobs spread over streams).  Both results are compared."""
+    placement, jobs spread over streams).  Both results are compared.  With
+    ``leg`` the result is returned (a leg of the default line) instead of
+    printed, without a CPU baseline."""
     import numpy as np
     import torch
     import paper_2503_06763_amd as S
@@ -314,6 +316,10 @@ def run_batched(args):
                      "traffic": None, "kernel": "whole job (all kernels of all jobs)",
                      "algorithmic_bytes": algo},
     }
+    if leg:
+        del outs, items_p, items_b, tbuf
+        torch.cuda.empty_cache()
+        return out
     if not args.no_cpu_baseline:
         jobs, acc = [], 0
         for r, x in texts:
@@ -325,12 +331,14 @@ def run_batched(args):
     print(json.dumps(out), flush=True)
 
 
-def run_served(args):
+def run_served(args, leg=False):
     """Served: 64 resident REs, Poisson arrivals at 5 rates relative to the
     plain per-request capacity, lognormal text lengths; the request server
     (continuous batching, admission by projected SLPF bytes within the memory
     budget) against the plain per-request path (one request per job, one job
-    in flight).  p50/p99 latency from arrival to finished, and aggregate GB/s."""
+    in flight).  p50/p99 latency from arrival to finished, and aggregate GB/s.
+    With ``leg`` the result is returned instead of printed, without a CPU
+    baseline."""
     import numpy as np
     import torch
     import paper_2503_06763_amd as S
@@ -431,6 +439,10 @@ def run_served(args):
                                                      "p99_ms": top["plain"]["p99_ms"]}},
         "rates": rows,
     }
+    if leg:
+        del views, tbuf
+        torch.cuda.empty_cache()
+        return out
     if not args.no_cpu_baseline:
         jobs, acc = [], 0
         for r, x in pool:
@@ -440,6 +452,47 @@ def run_served(args):
             acc += x.size
         out["cpu_baseline"] = oracle_pool_baseline(jobs, 0)
     print(json.dumps(out), flush=True)
+
+
+def record_leg(args):
+    """The record workload at its full size (1 GiB of multi-schema log
+    records, L2-resident tables): parse time, phases, the whole step's and
+    k_build's fraction of the HBM roofline, and the accept flag and counts
+    against the oracle's values in tests/golden/full_size_counts.yaml."""
+    import yaml
+    import torch
+    import paper_2503_06763_amd as S
+    from gen import regen, textgen
+    t0 = time.perf_counter()
+    pat, text = regen.to_re(regen.record_re()), textgen.record_text(RECORD_SEED, RECORD_BYTES)
+    gen_s = time.perf_counter() - t0
+    parser = S.Parser(pat)
+    n, W = text.size, parser.W
+    ms, phase, scal, cols = run_gpu(parser, text, args.leg_steps, 2, 0)
+    del cols
+    torch.cuda.empty_cache()
+    algo = n + (n + 1) * 8 * W
+    with open(os.path.join(ROOT, "tests", "golden", "full_size_counts.yaml")) as f:
+        g = yaml.safe_load(f)["record_re"]
+    same = (g["re_sha256"] == hashlib.sha256(pat).hexdigest() and g["text_bytes"] == n and
+            (bool(scal[0]), scal[1], scal[3]) == (g["accepted"], g["trees_mod_2_64"], g["trees_mod_2_61_1"])
+            and scal[2] == 0)
+    print("record leg: %.3f ms/step phases %s scalars %s golden %s (gen %.1fs)" % (ms, phase, scal, same, gen_s),
+          file=sys.stderr, flush=True)
+    return {
+        "workload": "record RE with L2-resident tables: multi-schema log records (14 schemas of 8 fields over "
+                    "overlapping byte sets), %d states forward / %d reverse, W = %d; %d-byte text (seed %d)" % (
+                        parser.info.fwd_states, parser.info.rev_states, W, n, RECORD_SEED),
+        "value": round(n / (ms * 1e-3) / 1e9, 3), "unit": "GB/s", "ms_per_step": round(ms, 4),
+        "steps": args.leg_steps, "warmup": 2,
+        "phases_ms": {k: round(v, 4) for k, v in phase.items()},
+        "roofline": {"bound": "hbm", "algorithmic_bytes": algo,
+                     "step_frac": round(algo / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "k_build_frac": round(algo / (phase["build"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
+        "table_placement": "lds" if parser.info.placement == 0 else "l2",
+        "accepted": scal[0], "trees_mod_2_64": scal[1], "trees_mod_2_61_1": scal[3], "count_status": scal[2],
+        "equals_oracle_golden": same,
+    }
 
 
 def main():
@@ -460,6 +513,10 @@ def main():
     ap.add_argument("--max-batch", type=int, default=256, help="served: requests per job at most")
     ap.add_argument("--texts", type=int, default=4096, help="batched: number of texts")
     ap.add_argument("--streams", type=int, default=4, help="batched: streams the per-RE jobs are spread over")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="default workload: skip the record, batched and served legs")
+    ap.add_argument("--leg-steps", type=int, default=3, help="timed steps of the record and batched legs")
+    ap.add_argument("--leg-requests", type=int, default=1000, help="served leg: requests per arrival rate")
     ap.add_argument("--copy-calib", type=int, default=0,
                     help="after timing, copy this many bytes device-to-device (scale reference for HBM counters)")
     args = ap.parse_args()
@@ -608,6 +665,18 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(pat, text, args.cpu_sample)
+    if args.workload == "single" and not args.no_legs:
+        # the other configurations, bounded, measured in the same run
+        del text
+        torch.cuda.empty_cache()
+        legs = {"record": record_leg(args)}
+        bargs = argparse.Namespace(**vars(args))
+        bargs.steps = args.leg_steps
+        legs["batched"] = run_batched(bargs, leg=True)
+        sargs = argparse.Namespace(**vars(args))
+        sargs.requests = args.leg_requests
+        legs["served"] = run_served(sargs, leg=True)
+        out["legs"] = legs
     print(json.dumps(out), flush=True)
 
 

@@ -288,17 +288,18 @@ slpf_status slpf_parse(const slpf_parser *p, const uint8_t *text_dev, uint64_t n
  * slpf_parse for callers that cannot allocate memory: code under HIP graph
  * capture, tight serving loops, and harnesses that forbid hipMalloc.  Same
  * arguments, results and stream order as slpf_parse, but the work buffers
- * come from a library-owned device array of 64 MiB (one per GPU, held until
+ * come from a library-owned device array of 128 MiB (one per GPU, held until
  * the process ends) instead of a per-stream allocation; no hipMalloc,
  * hipFree or other allocating call is made (the array's device address is
  * looked up once per device on the first call there).  The clearing the
  * parse needs is done by its own first kernel.
  *
- * SLPF_E_CAPACITY when the parse's work buffers would exceed the 64 MiB
- * array: they take about (20 E + 100) / s + 0.35 bytes per text byte (E =
- * slpf_parser_info.max_entries, s = lane-chunk bytes) plus up to 8.5 MiB,
- * so the 304-segment random RE of the single-RE workload (E = 10) fits
- * texts of 24 MiB with the automatic chunking; other errors as for
+ * SLPF_E_CAPACITY when the parse's work buffers would exceed the 128 MiB
+ * array: with entry lists of up to 64 segments they take about
+ * (38 E + 60) / s + 2.4 bytes per text byte (E = slpf_parser_info.max_entries,
+ * s = lane-chunk bytes), so the 304-segment random RE of the single-RE
+ * workload (E = 10) fits texts of 24 MiB with the automatic chunking
+ * (256-byte lane chunks at that size); other errors as for
  * slpf_parse.  Every call on one GPU uses the
  * same array and leaves its last contents there: calls that overlap on one
  * GPU (on different streams, or from several threads) race and must be

@@ -163,8 +163,17 @@ __device__ inline uint32_t for_segments(const Tabs &tb, const Job &jb, const Tex
         for (uint64_t m = tc.out[r]; m; m &= m - 1) f(k++, static_cast<uint32_t>(xl[__builtin_ctzll(m)]));
     } else {
         const uint64_t *cw = tc.out + r * tb.W;
-        for (uint32_t w = 0; w < tb.W; ++w)
-            for (uint64_t v = cw[w]; v; v &= v - 1) f(k++, w * 64 + static_cast<uint32_t>(__builtin_ctzll(v)));
+        auto word = [&](uint32_t w, uint64_t v) {
+            for (; v; v &= v - 1) f(k++, w * 64 + static_cast<uint32_t>(__builtin_ctzll(v)));
+        };
+        uint32_t w = 0;
+        if ((reinterpret_cast<uintptr_t>(cw) & 15u) == 0)      // two words per 16-byte load
+            for (; w + 2 <= tb.W; w += 2) {
+                const uint4 q = *reinterpret_cast<const uint4 *>(cw + w);
+                word(w, (static_cast<uint64_t>(q.y) << 32) | q.x);
+                word(w + 1, (static_cast<uint64_t>(q.w) << 32) | q.z);
+            }
+        for (; w < tb.W; ++w) word(w, cw[w]);
     }
     return k;
 }
@@ -188,13 +197,16 @@ __device__ inline bool follows(const uint64_t *fol, uint32_t W, uint32_t rho, ui
 
 // ------------------------------------------------------- short runs, lanes
 
-constexpr int kTV = 8;               // largest column of a run counted in registers
+constexpr int kTV = 8;               // largest column of a run counted in registers (first pass)
+constexpr int kTV2 = 16;             // the same, second pass
 constexpr uint32_t kDeferRun = 0x80000000u;   // deferred item: a queued short run, not a window
 
 // Paths through columns r0 .. r1 entering anywhere and leaving anywhere
-// (one lane); false when a column holds more than kTV segments.
+// (one lane); false when a column holds more than TV segments.
+template <int TV = kTV>
 __device__ inline bool run_paths_lane(const Tabs &tb, const uint64_t *fol, const Job &jb, const TextCols &tc,
                                       uint64_t r0, uint64_t r1, Cnt &out) {
+    constexpr int kTV = TV;
     uint32_t sp[kTV], sn[kTV];
     uint64_t ya[kTV], yp[kTV];
     const uint32_t mp0 = for_segments(tb, jb, tc, r0, [&](uint32_t k, uint32_t sg) {
@@ -221,13 +233,19 @@ __device__ inline bool run_paths_lane(const Tabs &tb, const uint64_t *fol, const
         for (int k = 0; k < kTV; ++k) {
             za[k] = 0;
             zp[k] = 0;
-            if (static_cast<uint32_t>(k) < m) {
+        }
+        // pairs (j, k) up to the largest columns among the wavefront's lanes
+        // (the bounds are uniform across the wavefront, so the rest is skipped)
 #pragma unroll
-                for (int j = 0; j < kTV; ++j) {
-                    if (static_cast<uint32_t>(j) < mp && follows(fol, tb.W, sp[j], sn[k])) {
-                        za[k] += ya[j];
-                        zp[k] = addp(zp[k], yp[j]);
-                    }
+        for (int k = 0; k < kTV; ++k) {
+            if (!__any(static_cast<uint32_t>(k) < m)) break;
+#pragma unroll
+            for (int j = 0; j < kTV; ++j) {
+                if (!__any(static_cast<uint32_t>(j) < mp)) break;
+                if (static_cast<uint32_t>(k) < m && static_cast<uint32_t>(j) < mp &&
+                    follows(fol, tb.W, sp[j], sn[k])) {
+                    za[k] += ya[j];
+                    zp[k] = addp(zp[k], yp[j]);
                 }
             }
         }
@@ -281,6 +299,17 @@ __device__ inline void emit_long(const Job &jb, uint32_t t, uint64_t r0, uint64_
 
 constexpr int kRunThreads = 256;
 
+// Lane chunk and columns r0 .. r1 of a queued run; false for a void slot.
+__device__ inline bool queued_run(const Job &jb, uint64_t v, uint32_t &i, uint64_t &r0, uint64_t &r1) {
+    const uint32_t len = static_cast<uint32_t>(v & 1023u);
+    i = static_cast<uint32_t>(v >> 33);
+    if (len == 0) return false;
+    const uint32_t t = text_of(jb, i);
+    r0 = static_cast<uint64_t>(i - first_chunk(jb, t)) * jb.s + ((v >> 10) & ((1ull << 23) - 1));
+    r1 = r0 + len - 1;
+    return true;
+}
+
 // One thread per 64-column window, window-major as the marks (g = w c + i):
 // the lanes of a wavefront read consecutive mark words.  Long runs are
 // emitted for the piece kernels; the short runs starting in the window are
@@ -328,12 +357,13 @@ __global__ __launch_bounds__(kRunThreads) void k_count_runs(Tabs tb, Job jb) {
         if (ns)
             for_window_run_starts(jb, tc, i, w, cx, [&](uint64_t r0) {
                 const uint64_t r1 = run_end(jb, tc, r0);
-                if (r1 - r0 + 1 <= jb.lshort) jb.sruns[slot++] = ShortRun{r0, static_cast<uint32_t>(r1 - r0 + 1), i};
+                if (r1 - r0 + 1 <= jb.lshort)
+                    jb.sruns[slot++] = short_run(i, r0 - cx.lo, static_cast<uint32_t>(r1 - r0 + 1));
             });
         return;
     }
     for (uint32_t k = 0; k < ns; ++k)
-        if (slot + k < jb.cap_sruns) jb.sruns[slot + k].len = 0;          // reserved below the capacity
+        if (slot + k < jb.cap_sruns) jb.sruns[slot + k] = 0;              // reserved below the capacity
     if (!ns) return;
     Cnt acc{1, 1};
     bool defer = false;
@@ -352,8 +382,12 @@ constexpr int kShortThreads = 256;
 constexpr uint32_t kFolLdsBytes = 32768;   // FolSeg staged in LDS up to this size
 
 // The queued short runs, one per lane (grid-stride).  A run's paths go
-// into the product of its lane chunk; a run with a column of more than kTV
-// segments is deferred to the wavefront walk (its queue index, tagged).
+// into the product of its lane chunk.  SECOND = false: every queued run,
+// counted with vectors of kTV segments; a run with a larger column goes to
+// the second queue.  SECOND = true: the second queue, with vectors of kTV2;
+// a run with a still larger column is deferred to the wavefront walk (its
+// queue index, tagged).
+template <bool SECOND>
 __global__ __launch_bounds__(kShortThreads) void k_count_short(Tabs tb, Job jb) {
     extern __shared__ __align__(16) uint64_t fol_lds[];
     const uint64_t *fol = tb.folseg;
@@ -363,17 +397,24 @@ __global__ __launch_bounds__(kShortThreads) void k_count_short(Tabs tb, Job jb) 
         __syncthreads();
         fol = fol_lds;
     }
-    const uint64_t nq = min(*jb.nsruns, static_cast<unsigned long long>(jb.cap_sruns));
+    const uint64_t nq = SECOND ? static_cast<uint64_t>(jb.ccnt[6])
+                               : min(*jb.nsruns, static_cast<unsigned long long>(jb.cap_sruns));
     const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
-    for (uint64_t k = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; k < nq; k += stride) {
-        const ShortRun rr = jb.sruns[k];
-        if (rr.len == 0) continue;
-        const TextCols tc = text_cols(jb, text_of(jb, rr.i));
+    for (uint64_t q = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; q < nq; q += stride) {
+        const uint32_t k = SECOND ? jb.squeue2[q] : static_cast<uint32_t>(q);
+        uint32_t i;
+        uint64_t r0, r1;
+        if (!queued_run(jb, jb.sruns[k], i, r0, r1)) continue;
+        const TextCols tc = text_cols(jb, text_of(jb, i));
         Cnt x;
-        if (run_paths_lane(tb, fol, jb, tc, rr.r0, rr.r0 + rr.len - 1, x)) {
-            if (x.a != 1 || x.p != 1) cmul_at(jb.cfac + 2ull * rr.i, x);
+        const bool ok = SECOND ? run_paths_lane<kTV2>(tb, fol, jb, tc, r0, r1, x)
+                               : run_paths_lane<kTV>(tb, fol, jb, tc, r0, r1, x);
+        if (ok) {
+            if (x.a != 1 || x.p != 1) cmul_at(jb.cfac + 2ull * i, x);
+        } else if (!SECOND) {
+            jb.squeue2[atomicAdd(&jb.ccnt[6], 1u)] = k;
         } else {
-            jb.dchunk[atomicAdd(&jb.ccnt[0], 1u)] = kDeferRun | static_cast<uint32_t>(k);
+            jb.dchunk[atomicAdd(&jb.ccnt[0], 1u)] = kDeferRun | k;
         }
     }
 }
@@ -501,14 +542,16 @@ __global__ __launch_bounds__(64) void k_count_defer(Tabs tb, Job jb) {
     for (uint32_t item = blockIdx.x; item < jb.ccnt[0]; item += gridDim.x) {
         const uint32_t g = jb.dchunk[item];
         if (g & kDeferRun) {
-            const ShortRun rr = jb.sruns[g & ~kDeferRun];
-            const uint32_t t = text_of(jb, rr.i);
+            uint32_t ri;
+            uint64_t r0, r1;
+            queued_run(jb, jb.sruns[g & ~kDeferRun], ri, r0, r1);   // a deferred run is never a void slot
+            const uint32_t t = text_of(jb, ri);
             const TextCols tc = text_cols(jb, t);
             uint32_t buf = 0, m = 0;
-            const bool ok = wave_walk<1>(tb, jb, tc, rr.r0, rr.r0 + rr.len - 1, L, buf, m);
+            const bool ok = wave_walk<1>(tb, jb, tc, r0, r1, L, buf, m);
             const Cnt x = ok ? walk_sum<1>(L, buf, m, 0) : Cnt{1, 1};
             if (threadIdx.x == 0) {
-                cmul_at(jb.cfac + 2ull * rr.i, x);
+                cmul_at(jb.cfac + 2ull * ri, x);
                 if (!ok) jb.tfail[t] = 1;
             }
             __syncthreads();

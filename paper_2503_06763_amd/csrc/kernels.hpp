@@ -103,12 +103,14 @@ struct Tabs {
     uint64_t wmagic;            // ceil(2^32 / W): e / W == (e * wmagic) >> 32 for e < 2^16
 };
 
-// A short run queued for k_count_short: columns r0 .. r0 + len - 1 of the
-// text of lane chunk i (len = 0: a slot left unused).
-struct ShortRun {
-    uint64_t r0;
-    uint32_t len, i;
-};
+// A short run queued for k_count_short, in one word: columns lo_i + off ..
+// lo_i + off + len - 1 of the text of lane chunk i (lo_i: the chunk's first
+// byte); bits 0-9 len (0: a slot left unused), 10-32 off, 33-63 i.  Lane
+// chunks of at most kMaxRunChunk bytes (longer ones queue nothing).
+constexpr uint64_t kMaxRunChunk = 1ull << 22;
+__host__ __device__ inline uint64_t short_run(uint32_t i, uint64_t off, uint32_t len) {
+    return (static_cast<uint64_t>(i) << 33) | (off << 10) | len;
+}
 
 // A long run of marked columns r0 .. r1 of text t, cut into npc pieces
 // (piece items pb .., matrix slots mb .. when npc > 1).
@@ -160,7 +162,8 @@ struct Job {
     uint32_t *ccnt;             // [0] deferred windows, [1] long runs, [2] pieces, [3] matrix slots
     uint32_t *dchunk;           // windows (w c + i) whose short runs the wave kernel counts
     RunRec *runs;               // [cap_runs] long runs
-    ShortRun *sruns;            // [cap_sruns] short runs queued for k_count_short
+    uint64_t *sruns;            // [cap_sruns] short runs queued for k_count_short (short_run words)
+    uint32_t *squeue2;          // [cap_sruns] queued runs with a column too large for the first pass
     unsigned long long *nsruns; // short runs queued (may pass cap_sruns: then the rest are counted in place)
     uint32_t cap_sruns;
     uint32_t fol_lds;           // k_count_short: FolSeg staged in LDS (it fits)

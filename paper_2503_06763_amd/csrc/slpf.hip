@@ -597,13 +597,14 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
     const uint64_t cap_runs = cols_total / lshort + T + 1;
     const uint64_t cap_mats = 2 * (cols_total / cell) + 2;
     const uint64_t cap_pieces = cap_runs + cols_total / cell + 1;
-    // short runs queued for one lane each: room for one per 256 columns (the
+    // short runs queued for one lane each: room for one per 16 columns (the
     // rest are counted where they are found)
-    const uint64_t cap_sruns = tb.col_single ? 0 : std::min<uint64_t>(cols_total / 256 + 64, 0x7fffffffull);
+    const uint64_t cap_sruns = tb.col_single || s > kMaxRunChunk
+                                   ? 0 : std::min<uint64_t>(cols_total / 16 + 64, 0x7fffffffull);
     if (count && (cap_runs > 0xffffffffull || cap_pieces > 0xffffffffull || nck >= 0x80000000ull))
         return SLPF_E_ARG;
     int iam = -1, iaend = -1, icfac = -1, itprod = -1, itfail = -1, iccnt = -1, idch = -1, iruns = -1, ipiece = -1,
-        imats = -1, ipmat = -1, isr = -1;
+        imats = -1, ipmat = -1, isr = -1, isq2 = -1;
     if (count) {
         iam = L.add(nck * 8);
         iaend = L.add(size_t(T) * 8);
@@ -612,7 +613,8 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
         itfail = L.add(size_t(T) * 4);
         iccnt = L.add(32);
         idch = L.add((nck + cap_sruns) * 4);
-        isr = L.add(cap_sruns * sizeof(ShortRun));
+        isr = L.add(cap_sruns * 8);
+        isq2 = L.add(cap_sruns * 4);
         iruns = L.add(cap_runs * sizeof(RunRec));
         ipiece = L.add(cap_pieces * 8);
         imats = L.add(cap_mats * kPieceR * kPieceR * 16);
@@ -712,7 +714,8 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
         jb.piece = reinterpret_cast<uint64_t *>(ptr(ipiece));
         jb.mats = reinterpret_cast<uint64_t *>(ptr(imats));
         jb.pmat = reinterpret_cast<uint32_t *>(ptr(ipmat));
-        jb.sruns = reinterpret_cast<ShortRun *>(ptr(isr));
+        jb.sruns = reinterpret_cast<uint64_t *>(ptr(isr));
+        jb.squeue2 = reinterpret_cast<uint32_t *>(ptr(isq2));
         jb.nsruns = reinterpret_cast<unsigned long long *>(ptr(iccnt) + 16);
         jb.cap_sruns = static_cast<uint32_t>(cap_sruns);
         jb.fol_lds = size_t(tb.nseg) * tb.W * 8 <= kFolLdsBytes ? 1u : 0u;
@@ -872,8 +875,11 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
                            dim3(kRunThreads), 0, stream, tb, jb);
         const uint32_t sgrid = static_cast<uint32_t>(
             std::min<uint64_t>((uint64_t(jb.cap_sruns) + kShortThreads - 1) / kShortThreads, 2048));
-        hipLaunchKernelGGL(k_count_short, dim3(std::max<uint32_t>(sgrid, 1)), dim3(kShortThreads),
-                           jb.fol_lds ? size_t(tb.nseg) * tb.W * 8 : 0, stream, tb, jb);
+        const size_t fol_bytes = jb.fol_lds ? size_t(tb.nseg) * tb.W * 8 : 0;
+        hipLaunchKernelGGL(k_count_short<false>, dim3(std::max<uint32_t>(sgrid, 1)), dim3(kShortThreads), fol_bytes,
+                           stream, tb, jb);
+        hipLaunchKernelGGL(k_count_short<true>, dim3(std::max<uint32_t>(sgrid / 4, 1)), dim3(kShortThreads),
+                           fol_bytes, stream, tb, jb);
         const uint32_t wgrid = std::min<uint32_t>(c, 2048);
         hipLaunchKernelGGL(k_count_defer, dim3(wgrid), dim3(64), 0, stream, tb, jb);
         hipLaunchKernelGGL(k_count_pieces, dim3(wgrid), dim3(64), 0, stream, tb, jb);
@@ -923,7 +929,7 @@ slpf_status slpf_parse(const slpf_parser *cp, const uint8_t *text, uint64_t n, c
 // is passed to kernels.
 namespace {
 
-constexpr size_t kNoAllocScratchBytes = 64u << 20;
+constexpr size_t kNoAllocScratchBytes = 128u << 20;
 constexpr int kMaxDevices = 64;
 
 __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];

@@ -65,7 +65,7 @@ def test_noalloc_capacity_error():
     import torch
     dev = device()
     p = S.Parser(regen.to_re(regen.random_re(23)))
-    n = 256 << 20                                                  # work buffers beyond 64 MiB
+    n = 256 << 20                                                  # work buffers beyond 128 MiB
     t = torch.zeros(n, dtype=torch.uint8, device=dev)
     cols = torch.empty((n + 1, p.W), dtype=torch.int64, device=dev)
     sc = torch.empty(4, dtype=torch.int64, device=dev)
