@@ -210,7 +210,13 @@ enum {
                                            start at the position, within a window after its edge,
                                            whose entry list is shortest.  Same results.  Default: on
                                            when the parser's entry lists exceed 12 segments */
-    SLPF_PARSE_NO_EDGE_SHIFT = 1u << 6  /* chunk-edge shifting off (wins over SLPF_PARSE_EDGE_SHIFT) */
+    SLPF_PARSE_NO_EDGE_SHIFT = 1u << 6, /* chunk-edge shifting off (wins over SLPF_PARSE_EDGE_SHIFT) */
+    SLPF_PARSE_ALL_DFA_STATES = 1u << 7 /* speculation ablation, the standard scheme the ME-DFA entries
+                                           are compared with (Sect. 5): a lane chunk's runs start from
+                                           every state of the forward (reverse) DFA at its inner edges,
+                                           from I (F) at the text's first (last) edge.  Same results;
+                                           no chunk-edge shifting.  SLPF_E_TOO_LARGE when a DFA has
+                                           more than 2048 states */
 };
 
 typedef struct {
@@ -328,8 +334,35 @@ typedef struct {
  * copied from a pinned staging buffer on the stream; the host waits for the
  * previous batch's copy on the same stream before reusing that buffer.
  */
-slpf_status slpf_parse_batch(const slpf_parser *p, const slpf_text *items, size_t count,
+slpf_status slpf_parse_texts(const slpf_parser *p, const slpf_text *items, size_t count,
                              const slpf_parse_opts *opts, void *hip_stream);
+
+/* One text of a batch over many parsers: its parser, device bytes and
+ * output buffers (as for slpf_parse). */
+typedef struct {
+    const slpf_parser *p;
+    const uint8_t *text_dev;
+    uint64_t n;
+    slpf_forest out;
+} slpf_item;
+
+/*
+ * Parse `count` texts, each with its own parser, in one call: the batched
+ * form over many REs.  The items of one parser form one job (as
+ * slpf_parse_texts); the jobs of different parsers run concurrently on
+ * library-owned streams of the device (a few per GPU, forked from and joined
+ * back into hip_stream, so the call is ordered on hip_stream like any other
+ * launch).  Results are identical to parsing each text alone.  Every parser
+ * must live on the device of hip_stream, and every item must satisfy the
+ * conditions of slpf_parse; the first violation is returned and nothing is
+ * launched.  With opts->chunk_bytes = 0 a parser that slpf_tune has tuned
+ * uses its tuned lane-chunk size and table placement.  A failure of one job
+ * (e.g. SLPF_E_NOMEM) is returned after the jobs already launched have been
+ * joined into hip_stream.  Calls that overlap on one device are serialized
+ * by the library.
+ */
+slpf_status slpf_parse_batch(const slpf_item *items, size_t count, const slpf_parse_opts *opts,
+                             void *hip_stream);
 
 /*
  * Free the work buffers the parser keeps for parses on hip_stream (after
@@ -339,14 +372,16 @@ slpf_status slpf_parse_batch(const slpf_parser *p, const slpf_text *items, size_
 slpf_status slpf_parser_trim(const slpf_parser *p, void *hip_stream);
 
 /*
- * Autotuner: time one batched parse of `items` (after one untimed run) for
+ * Autotuner: time one batched parse of `items` (slpf_parse_texts, after one
+ * untimed run) for
  * every lane-chunk size in {256, 512, 1024, 2048, 4096} bytes and, when the
  * tables fit in LDS, both table placements (LDS and L2), and return the
  * fastest in best->chunk_bytes and best->flags (`flags` plus
  * SLPF_PARSE_FORCE_L2 when that placement won); *best_ms (may be NULL)
  * receives its time.  best->struct_size must be set; its other fields are
  * overwritten.  The items' outputs hold a complete parse on return (every
- * candidate computes the same result).  Synchronizes the stream.
+ * candidate computes the same result).  The parser keeps the result for
+ * slpf_parse_batch.  Synchronizes the stream.
  */
 slpf_status slpf_tune(const slpf_parser *p, const slpf_text *items, size_t count, uint32_t flags,
                       slpf_parse_opts *best, float *best_ms, void *hip_stream);
@@ -358,8 +393,8 @@ slpf_status slpf_tune(const slpf_parser *p, const slpf_text *items, size_t count
  * when a job slot is free and the SLPF it will produce (slpf_forest_bytes,
  * plus the scalars) fits in the server's device arena of memory_budget
  * bytes.  The requests admitted into a slot run as one job (per parser, one
- * slpf_parse_batch) on that slot's stream; slots run concurrently.  Results
- * are identical to slpf_parse of each text alone (see slpf_parse_batch for
+ * slpf_parse_texts) on that slot's stream; slots run concurrently.  Results
+ * are identical to slpf_parse of each text alone (see slpf_parse_texts for
  * the one exception).  A server is driven from one host thread.
  */
 typedef struct slpf_server slpf_server;
@@ -399,7 +434,7 @@ slpf_status slpf_server_submit(slpf_server *s, const slpf_parser *p, const uint8
 slpf_status slpf_server_poll(slpf_server *s, uint64_t *done_tags, size_t cap, size_t *n_done);
 /* Output of a finished request (device pointers into the arena, valid until
  * slpf_server_release).  Returns the request's parse status: a request whose
- * job could not be launched (slpf_parse_batch failed for its parser, e.g. a
+ * job could not be launched (slpf_parse_texts failed for its parser, e.g. a
  * parser compiled with SLPF_COMPILE_HOST_ONLY) is still reported finished by
  * slpf_server_poll, and this call then returns that error; the requests of
  * the other parsers in the same slot are not affected. */

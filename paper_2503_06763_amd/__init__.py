@@ -30,9 +30,11 @@ PARSE_COMPACT = 8
 PARSE_NEXT_BYTE_ENTRIES = 16
 PARSE_EDGE_SHIFT = 32
 PARSE_NO_EDGE_SHIFT = 64
+PARSE_ALL_DFA_STATES = 128
 
 EXPORTS = ["slpf_compile", "slpf_parser_destroy", "slpf_parser_info_get", "slpf_segment_text",
-           "slpf_table_dump", "slpf_forest_bytes", "slpf_parse", "slpf_parse_batch", "slpf_tune", "slpf_parser_trim",
+           "slpf_table_dump", "slpf_forest_bytes", "slpf_parse", "slpf_parse_texts", "slpf_parse_batch", "slpf_tune",
+           "slpf_parser_trim",
            "slpf_num_chunks", "slpf_status_str", "slpf_server_create", "slpf_server_destroy",
            "slpf_server_submit", "slpf_server_poll", "slpf_server_result", "slpf_server_release",
            "slpf_server_stats", "slpf_compact_bytes", "slpf_decode_compact", "slpf_get_matches",
@@ -93,6 +95,10 @@ class Text(ctypes.Structure):
     _fields_ = [("text_dev", ctypes.c_void_p), ("n", ctypes.c_uint64), ("out", Forest)]
 
 
+class Item(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_void_p), ("text_dev", ctypes.c_void_p), ("n", ctypes.c_uint64), ("out", Forest)]
+
+
 _lib = None
 
 
@@ -125,7 +131,9 @@ def lib(path: str = LIB_PATH):
     L.slpf_parse.restype = ctypes.c_int
     L.slpf_parse_noalloc.argtypes = [vp, vp, ctypes.c_uint64, ctypes.POINTER(ParseOpts), ctypes.POINTER(Forest), vp]
     L.slpf_parse_noalloc.restype = ctypes.c_int
-    L.slpf_parse_batch.argtypes = [vp, ctypes.POINTER(Text), sz, ctypes.POINTER(ParseOpts), vp]
+    L.slpf_parse_texts.argtypes = [vp, ctypes.POINTER(Text), sz, ctypes.POINTER(ParseOpts), vp]
+    L.slpf_parse_texts.restype = ctypes.c_int
+    L.slpf_parse_batch.argtypes = [ctypes.POINTER(Item), sz, ctypes.POINTER(ParseOpts), vp]
     L.slpf_parse_batch.restype = ctypes.c_int
     L.slpf_tune.argtypes = [vp, ctypes.POINTER(Text), sz, ctypes.c_uint32, ctypes.POINTER(ParseOpts),
                             ctypes.POINTER(ctypes.c_float), vp]
@@ -366,7 +374,7 @@ class Parser:
         return sc
 
     def parse_batch_into(self, items, chunk_bytes: int = 0, flags: int = 0, stream=None, events=None):
-        """Raw slpf_parse_batch.  ``items``: list of (text tensor or None, n, columns tensor,
+        """Raw slpf_parse_texts.  ``items``: list of (text tensor or None, n, columns tensor,
         scalars tensor); asynchronous on ``stream``."""
         import torch
         if stream is None:
@@ -382,8 +390,8 @@ class Parser:
                       ctypes.cast(ev, ctypes.POINTER(ctypes.c_void_p)) if ev is not None else None,
                       len(events) if events is not None else 0, 0)
         arr = self._text_array(items)
-        st = self._L.slpf_parse_batch(self._h, arr, len(items), ctypes.byref(o), ctypes.c_void_p(stream.cuda_stream))
-        _check(st, "slpf_parse_batch")
+        st = self._L.slpf_parse_texts(self._h, arr, len(items), ctypes.byref(o), ctypes.c_void_p(stream.cuda_stream))
+        _check(st, "slpf_parse_texts")
 
     def _text_array(self, items):
         arr = (Text * len(items))()
@@ -410,10 +418,10 @@ class Parser:
         return int(o.chunk_bytes), int(o.flags), float(ms.value)
 
     def parse_batch_prepared(self, arr, count: int, chunk_bytes: int, flags: int, stream):
-        """slpf_parse_batch on an array made by _text_array (no per-call marshalling)."""
+        """slpf_parse_texts on an array made by _text_array (no per-call marshalling)."""
         o = ParseOpts(ctypes.sizeof(ParseOpts), chunk_bytes, flags, 0, None, 0, None, 0, 0)
-        st = self._L.slpf_parse_batch(self._h, arr, count, ctypes.byref(o), ctypes.c_void_p(stream.cuda_stream))
-        _check(st, "slpf_parse_batch")
+        st = self._L.slpf_parse_texts(self._h, arr, count, ctypes.byref(o), ctypes.c_void_p(stream.cuda_stream))
+        _check(st, "slpf_parse_texts")
 
     def parse_batch(self, texts, chunk_bytes: int = 0, count: bool = True, force_l2: bool = False,
                     stream=None, events=None):
@@ -546,3 +554,30 @@ def _hip_copy_to_host(dst, src, nbytes):
 
 def status_str(st: int) -> str:
     return lib().slpf_status_str(st).decode()
+
+
+def item_array(items):
+    """An slpf_item array for parse_items_prepared: ``items`` is a list of
+    (Parser, text tensor or None, n, columns tensor, scalars tensor)."""
+    arr = (Item * len(items))()
+    for k, (p, t, n, cols, sc) in enumerate(items):
+        arr[k].p = p.handle.value
+        arr[k].text_dev = t.data_ptr() if (t is not None and n) else None
+        arr[k].n = n
+        arr[k].out = Forest(cols.data_ptr() if cols is not None else None,
+                            cols.numel() * cols.element_size() if cols is not None else 0, sc.data_ptr())
+    return arr
+
+
+def parse_items_prepared(arr, count: int, chunk_bytes: int = 0, flags: int = 0, stream=None):
+    """slpf_parse_batch (texts of many parsers in one call) on an array from item_array."""
+    import torch
+    stream = stream or torch.cuda.current_stream()
+    o = ParseOpts(ctypes.sizeof(ParseOpts), chunk_bytes, flags, 0, None, 0, None, 0, 0)
+    st = lib().slpf_parse_batch(arr, count, ctypes.byref(o), ctypes.c_void_p(stream.cuda_stream))
+    _check(st, "slpf_parse_batch")
+
+
+def parse_items(items, chunk_bytes: int = 0, flags: int = 0, stream=None):
+    """slpf_parse_batch: ``items`` as for item_array; asynchronous on ``stream``."""
+    parse_items_prepared(item_array(items), len(items), chunk_bytes, flags, stream)

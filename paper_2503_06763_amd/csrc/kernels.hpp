@@ -73,6 +73,8 @@ struct Tabs {
                                 // its end-letter's class), or NL x NL x nseg by (p, q) when rank_pq
     uint32_t rank_pq;
     const uint32_t *fnz, *rnz;  // per state: bit w set iff word w of its set is non-zero
+    const uint16_t *seqids;     // 0, 1, 2, ..: DFA state m + 1 as entry m (all-DFA-states ablation)
+    uint32_t dfa_f, dfa_r;      // forward / reverse DFA states (ids 1 .. dfa_f / dfa_r)
     const uint32_t *xoff_nb;    // entry lists filtered by the next byte only (ablation)
     const uint16_t *xlist_nb;
     uint32_t emax_nb;
@@ -135,6 +137,8 @@ struct Job {
                                 // edge (chunk-edge shifting; without it Rm is R and Rmh is unused)
     uint8_t *eshift;            // [c] the right edge of lane k's runs was shifted past its fixed edge
     uint32_t shift;             // chunk-edge shifting window (bytes), 0 = off
+    uint32_t alldfa;            // ablation: inner edges list every DFA state (runs from I at the text
+                                // start, from F at its end)
     uint64_t *Mf, *MbR;         // [c][emax][ew] masks; MbR indexed by c-1-i
     uint32_t ew;                // words of an entry-list mask (ceil(emax / 64))
     uint16_t *nxf, *nxb;        // entry-list sizes at the scan input of item k (forward: left edge of
@@ -668,8 +672,24 @@ __global__ __launch_bounds__(256) void k_reach(Tabs tb, Job jb) {
     const uint32_t sw = MODE == 0 ? 0u : jb.shift;
     const uint32_t la = edge_list(tb, bcls, text, cx.tr.n, jb.s, cx.ct, cx.li, sw, pa);
     const uint32_t lb = edge_list(tb, bcls, text, cx.tr.n, jb.s, cx.ct, cx.li + 1, sw, pb);
-    const uint32_t xa0 = tb.xoff[la], na = tb.xoff[la + 1] - xa0;
-    const uint32_t xb0 = tb.xoff[lb], nb = tb.xoff[lb + 1] - xb0;
+    const uint32_t xa0 = tb.xoff[la], nfa = tb.xoff[la + 1] - xa0;   // the edges' lists
+    const uint32_t xb0 = tb.xoff[lb], nfb = tb.xoff[lb + 1] - xb0;
+    uint32_t na = nfa, nb = nfb;                                       // the runs' start lists
+    // entries: run m starts in fsg[xla[m]] (forward) / rsg[xlb[m]] (backward)
+    const uint16_t *xla = tb.xlist + xa0, *xlb = tb.xlist + xb0, *fsg = tb.fsingle, *rsg = tb.rsingle;
+    // all-DFA-states ablation: an inner edge lists DFA state m + 1 as entry m;
+    // the text's first forward runs start in I, its last backward runs in F
+    // (its lists are longer than a run group: mode 2 only)
+    const bool alldfa = MODE == 2 && jb.alldfa;
+    const bool adA = alldfa && !cx.first, adB = alldfa && !cx.last;
+    if (alldfa) {
+        na = adA ? tb.dfa_f : 1u;
+        xla = tb.seqids;
+        fsg = adA ? tb.seqids + 1 : tb.seqids + tb.fstart;
+        nb = adB ? tb.dfa_r : 1u;
+        xlb = tb.seqids;
+        rsg = adB ? tb.seqids + 1 : tb.seqids + tb.rstart;
+    }
     // scan items: forward item i maps X_i -> X_{i+1}; backward item c-1-i maps X_{i+1} -> X_i
     jb.nxf[i] = static_cast<uint16_t>(na);
     jb.rsf[i] = cx.first ? 1 : 0;
@@ -688,11 +708,11 @@ __global__ __launch_bounds__(256) void k_reach(Tabs tb, Job jb) {
         constexpr bool SPLIT = MODE == 1;
         // (mode 0: the runs start and end on the lane chunk's own 64-byte edges)
         runs_from_entries<true, OFF, GRP, SPLIT, SPLIT>(text, pa, SPLIT ? hi : pa, pb, lk.cls, lk.fd, C, c2,
-                                                        tb.fsingle, tb.xlist + xa0, na, SPLIT ? jb.Rm : nullptr, jb.R,
+                                                        fsg, xla, na, SPLIT ? jb.Rm : nullptr, jb.R,
                                                         c, i);
         if (!jb.fwd_only)
             runs_from_entries<false, OFF, GRP, SPLIT, SPLIT>(text, pa, SPLIT ? hi : pb, pb, lk.cls, lk.rd, C, c2,
-                                                             tb.rsingle, tb.xlist + xb0, nb, SPLIT ? jb.Rmh : nullptr,
+                                                             rsg, xlb, nb, SPLIT ? jb.Rmh : nullptr,
                                                              jb.Rh, c, i);
     } else {
         // forward runs from X_i: every entry over the first kReachPre bytes,
@@ -700,7 +720,7 @@ __global__ __launch_bounds__(256) void k_reach(Tabs tb, Job jb) {
         // is the union of the selected ones), then to the shifted edge pb (ids
         // in R; without shifting Rm is R)
         const uint64_t fa = pa + kReachPre < hi ? pa + kReachPre : hi;
-        runs_from_entries<true, OFF, GRP>(text, pa, fa, fa, lk.cls, lk.fd, C, c2, tb.fsingle, tb.xlist + xa0, na,
+        runs_from_entries<true, OFF, GRP>(text, pa, fa, fa, lk.cls, lk.fd, C, c2, fsg, xla, na,
                                           nullptr, jb.Rt, c, i);
         runs_from_ids<true, OFF, GRP>(text, fa, hi, lk.cls, lk.fd, C, c2, na, jb.Rt, jb.Rm, c, i);
         if (jb.shift) runs_from_ids<true, OFF, GRP>(text, hi, pb, lk.cls, lk.fd, C, c2, na, jb.Rm, jb.R, c, i);
@@ -711,12 +731,12 @@ __global__ __launch_bounds__(256) void k_reach(Tabs tb, Job jb) {
         if (!jb.fwd_only) {
             const uint64_t ba = hi - pa > kReachPre ? max(pa, (hi - kReachPre) & ~15ull) : pa;
             if (jb.shift) {
-                runs_from_entries<false, OFF, GRP>(text, hi, hi, pb, lk.cls, lk.rd, C, c2, tb.rsingle,
-                                                   tb.xlist + xb0, nb, nullptr, jb.Rmh, c, i);
+                runs_from_entries<false, OFF, GRP>(text, hi, hi, pb, lk.cls, lk.rd, C, c2, rsg,
+                                                   xlb, nb, nullptr, jb.Rmh, c, i);
                 runs_from_ids<false, OFF, GRP>(text, ba, hi, lk.cls, lk.rd, C, c2, nb, jb.Rmh, jb.Rt, c, i);
             } else {
-                runs_from_entries<false, OFF, GRP>(text, ba, hi, hi, lk.cls, lk.rd, C, c2, tb.rsingle,
-                                                   tb.xlist + xb0, nb, nullptr, jb.Rt, c, i);
+                runs_from_entries<false, OFF, GRP>(text, ba, hi, hi, lk.cls, lk.rd, C, c2, rsg,
+                                                   xlb, nb, nullptr, jb.Rt, c, i);
             }
             runs_from_ids<false, OFF, GRP>(text, pa, ba, lk.cls, lk.rd, C, c2, nb, jb.Rt, jb.Rh, c, i);
         }
@@ -729,9 +749,13 @@ __global__ __launch_bounds__(256) void k_reach(Tabs tb, Job jb) {
         uint32_t id = jb.R[static_cast<uint64_t>(m) * jb.c + i];
         const uint64_t *bits = tb.fbits + static_cast<uint64_t>(id) * W;
         uint64_t *dst = jb.Mf + (static_cast<uint64_t>(i) * tb.emax + m) * EW;
+        if (adB) {   // the far list is every DFA state: the run's end state itself
+            for (uint32_t w = 0; w < EW; ++w) dst[w] = id && (id - 1) / 64 == w ? 1ull << ((id - 1) & 63) : 0ull;
+            continue;
+        }
         for (uint32_t w = 0; w < EW; ++w) {
             uint64_t row = 0;
-            for (uint32_t p = 64 * w; p < nb && p < 64 * w + 64; ++p) {
+            for (uint32_t p = 64 * w; p < nfb && p < 64 * w + 64; ++p) {
                 uint32_t sg = tb.xlist[xb0 + p];
                 row |= ((bits[sg >> 6] >> (sg & 63)) & 1ull) << (p & 63);
             }
@@ -742,9 +766,13 @@ __global__ __launch_bounds__(256) void k_reach(Tabs tb, Job jb) {
         uint32_t id = jb.Rh[static_cast<uint64_t>(m) * jb.c + i];
         const uint64_t *bits = tb.rbits + static_cast<uint64_t>(id) * W;
         uint64_t *dst = jb.MbR + (static_cast<uint64_t>(jb.c - 1 - i) * tb.emax + m) * EW;
+        if (adA) {
+            for (uint32_t w = 0; w < EW; ++w) dst[w] = id && (id - 1) / 64 == w ? 1ull << ((id - 1) & 63) : 0ull;
+            continue;
+        }
         for (uint32_t w = 0; w < EW; ++w) {
             uint64_t row = 0;
-            for (uint32_t p = 64 * w; p < na && p < 64 * w + 64; ++p) {
+            for (uint32_t p = 64 * w; p < nfa && p < 64 * w + 64; ++p) {
                 uint32_t sg = tb.xlist[xa0 + p];
                 row |= ((bits[sg >> 6] >> (sg & 63)) & 1ull) << (p & 63);
             }

@@ -5,7 +5,7 @@
 // free and its output (the SLPF columns and the scalars, sized by
 // slpf_forest_bytes) fits in the server's device arena, whose size is the
 // memory budget.  Admitted requests of one slot form one job: per parser,
-// one slpf_parse_batch on the slot's stream.  Slots run concurrently on
+// one slpf_parse_texts on the slot's stream.  Slots run concurrently on
 // their own streams, so requests that arrive while others are on the GPU
 // are admitted as slots and arena space free up, and their work overlaps on
 // the device.  A finished request keeps its arena range until the caller
@@ -130,7 +130,7 @@ slpf_status launch(slpf_server *s, Slot &sl, bool *launched) {
             t.out.scalars_dev = reinterpret_cast<uint64_t *>(s->arena + r.off + round_up(r.forest));
             items.push_back(t);
         }
-        const slpf_status st = slpf_parse_batch(p, items.data(), items.size(), &po, sl.stream);
+        const slpf_status st = slpf_parse_texts(p, items.data(), items.size(), &po, sl.stream);
         for (Request r : batch) {
             if (r.p != p) continue;
             r.st = st;

@@ -7,6 +7,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <unordered_map>
 #include <new>
 #include <vector>
 
@@ -39,6 +40,7 @@ struct Workspace {
 struct slpf_parser {
     HostAutomaton A;
     int device = 0;
+    uint32_t tuned_chunk = 0, tuned_flags = 0;   // slpf_tune's result (0: not tuned)
     size_t lds_limit = 64 * 1024;     // dynamic LDS per workgroup on the device
     void *blob = nullptr;
     size_t blob_bytes = 0;
@@ -200,6 +202,10 @@ slpf_status upload(slpf_parser *p) {
                     arcs[(size_t(f) * krd + b) * A.C + c] = static_cast<uint16_t>(std::min<uint32_t>(na, 0xffffu));
                 }
     }
+    // 0, 1, .., the larger DFA's state count: the all-DFA-states speculation
+    // ablation lists DFA state m + 1 as entry m
+    std::vector<uint16_t> seqids(std::max(A.fwd.dfa_states, A.rev.dfa_states) + 2);
+    for (size_t k = 0; k < seqids.size(); ++k) seqids[k] = static_cast<uint16_t>(k);
     // the segments each segment follows (transpose of FolSeg)
     std::vector<uint64_t> pred(size_t(A.nseg) * A.W, 0);
     for (uint32_t r = 0; r < A.nseg; ++r)
@@ -238,6 +244,7 @@ slpf_status upload(slpf_parser *p) {
         {pairm.data(), pairm.size(), 0},
         {pred.data(), pred.size() * 8, 0},
         {arcs.data(), arcs.size() * 2, 0},
+        {seqids.data(), seqids.size() * 2, 0},
     };
     size_t total = 0;
     for (auto &pt : parts) {
@@ -289,6 +296,9 @@ slpf_status upload(slpf_parser *p) {
     t.pair_nib = pair_nib && kfd ? 1u : 0u;
     t.predseg = reinterpret_cast<const uint64_t *>(at(24));
     t.arcs2 = with_arcs ? reinterpret_cast<const uint16_t *>(at(25)) : nullptr;
+    t.seqids = reinterpret_cast<const uint16_t *>(at(26));
+    t.dfa_f = A.fwd.dfa_states;
+    t.dfa_r = A.rev.dfa_states;
     t.col_single = p->col_single ? 1u : 0u;
     t.fhmask = static_cast<uint32_t>(A.fwd.hash.size() - 1);
     t.rhmask = static_cast<uint32_t>(A.rev.hash.size() - 1);
@@ -518,7 +528,13 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
         ts.xlist = tb.xlist_nb;
         ts.emax = tb.emax_nb;
     }
+    // all-DFA-states ablation: inner lane-chunk edges list every DFA state
+    const bool alldfa = (flags & SLPF_PARSE_ALL_DFA_STATES) != 0;
+    if (alldfa) ts.emax = std::max(ts.emax, std::max(tb.dfa_f, tb.dfa_r));
     const uint32_t W = tb.W, E = ts.emax, EW = (E + 63) / 64;
+    // join masks of at most 32 words (2048 entries; the entry lists of a
+    // parser always fit, the all-DFA-states lists of a large DFA may not)
+    if (EW > static_cast<uint32_t>(kMaxWords)) return SLPF_E_TOO_LARGE;
     uint64_t total = 0;
     for (size_t t = 0; t < T; ++t) total += items[t].n;
     const uint64_t s = chunk_bytes_for(total, opts);
@@ -541,8 +557,9 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
     jb.c = c;
     // chunk-edge shifting: on by default when a run group cannot hold the
     // longest entry list; the window is half a lane chunk at most
-    const bool shift = !(flags & SLPF_PARSE_NO_EDGE_SHIFT) &&
+    const bool shift = !alldfa && !(flags & SLPF_PARSE_NO_EDGE_SHIFT) &&
                        ((flags & SLPF_PARSE_EDGE_SHIFT) || ts.emax > static_cast<uint32_t>(kGroup));
+    jb.alldfa = alldfa ? 1u : 0u;
     jb.shift = shift ? static_cast<uint32_t>(std::min<uint64_t>(kShiftWindow, s / 2)) : 0u;
     if (T == 1) {
         jb.d0[0] = reinterpret_cast<uint64_t>(items[0].text_dev);
@@ -752,7 +769,7 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
             else
                 hipLaunchKernelGGL((k_reach<false, false, MU>), dim3(blocks), dim3(256), 0, stream, ts, jb);
         };
-        if (ts.emax > static_cast<uint32_t>(kGroup))
+        if (ts.emax > static_cast<uint32_t>(kGroup) || alldfa)
             reach(std::integral_constant<int, 2>{});
         else if (jb.shift)
             reach(std::integral_constant<int, 1>{});
@@ -970,7 +987,7 @@ slpf_status slpf_parse_noalloc(const slpf_parser *cp, const uint8_t *text, uint6
     return run_job(p, &item, 1, opts, static_cast<hipStream_t>(hip_stream), ws, kNoAllocScratchBytes);
 }
 
-slpf_status slpf_parse_batch(const slpf_parser *cp, const slpf_text *items, size_t count, const slpf_parse_opts *opts,
+slpf_status slpf_parse_texts(const slpf_parser *cp, const slpf_text *items, size_t count, const slpf_parse_opts *opts,
                              void *hip_stream) {
     slpf_parser *p = const_cast<slpf_parser *>(cp);
     if (!p || p->host_only || (!items && count)) return SLPF_E_ARG;
@@ -983,6 +1000,111 @@ slpf_status slpf_parse_batch(const slpf_parser *cp, const slpf_text *items, size
         if (st != SLPF_OK) return st;
     }
     return run_job(p, items, count, opts, static_cast<hipStream_t>(hip_stream));
+}
+
+}  // extern "C"
+
+// ------------------------------------------------ batches over many parsers
+// The jobs of one slpf_parse_batch call run on library-owned streams of the
+// device, forked from and joined back into the caller's stream.  A parser
+// always uses the same one (its jobs keep one work area per stream).
+namespace {
+
+constexpr int kBatchStreams = 4;
+
+struct BatchStreams {
+    std::mutex mu;
+    bool made = false;
+    hipStream_t s[kBatchStreams] = {};
+    hipEvent_t fork = nullptr, done[kBatchStreams] = {};
+    std::unordered_map<const slpf_parser *, int> home;
+};
+
+BatchStreams g_batch[kMaxDevices];
+
+}  // namespace
+
+extern "C" {
+
+slpf_status slpf_parse_batch(const slpf_item *items, size_t count, const slpf_parse_opts *opts, void *hip_stream) {
+    if (!items && count) return SLPF_E_ARG;
+    if (opts && opts->struct_size != sizeof(slpf_parse_opts)) return SLPF_E_ARG;
+    if (opts && opts->chunk_bytes && (opts->chunk_bytes % 64 != 0)) return SLPF_E_ARG;
+    if (opts && opts->trace_dev) return SLPF_E_ARG;
+    if (count == 0) return SLPF_OK;
+    if (count > 0x7fffffffull) return SLPF_E_ARG;
+    const uint32_t flags = opts ? opts->flags : 0u;
+    int dev = -1;
+    std::vector<const slpf_parser *> order;
+    std::unordered_map<const slpf_parser *, std::vector<slpf_text>> groups;
+    for (size_t t = 0; t < count; ++t) {
+        const slpf_parser *p = items[t].p;
+        if (!p || p->host_only) return SLPF_E_ARG;
+        if (dev < 0) dev = p->device;
+        if (p->device != dev || dev >= kMaxDevices) return SLPF_E_ARG;
+        slpf_status st = check_item(p, items[t].text_dev, items[t].n, &items[t].out, flags);
+        if (st != SLPF_OK) return st;
+        auto &g = groups[p];
+        if (g.empty()) order.push_back(p);
+        g.push_back(slpf_text{items[t].text_dev, items[t].n, items[t].out});
+    }
+    if (hipSetDevice(dev) != hipSuccess) return SLPF_E_DEVICE;
+    hipStream_t caller = static_cast<hipStream_t>(hip_stream);
+    auto job_opts = [&](const slpf_parser *p) {
+        slpf_parse_opts o{};
+        if (opts) o = *opts;
+        o.struct_size = sizeof(slpf_parse_opts);
+        if (o.chunk_bytes == 0 && p->tuned_chunk) {
+            o.chunk_bytes = p->tuned_chunk;
+            o.flags |= p->tuned_flags;
+        }
+        o.events = nullptr;
+        o.num_events = 0;
+        return o;
+    };
+    if (order.size() == 1) {
+        const slpf_parse_opts o = job_opts(order[0]);
+        auto &g = groups[order[0]];
+        return run_job(const_cast<slpf_parser *>(order[0]), g.data(), g.size(), &o, caller);
+    }
+    BatchStreams &bs = g_batch[dev];
+    std::lock_guard<std::mutex> lock(bs.mu);
+    if (!bs.made) {
+        for (int k = 0; k < kBatchStreams; ++k)
+            if (hipStreamCreateWithFlags(&bs.s[k], hipStreamNonBlocking) != hipSuccess ||
+                hipEventCreateWithFlags(&bs.done[k], hipEventDisableTiming) != hipSuccess)
+                return SLPF_E_DEVICE;
+        if (hipEventCreateWithFlags(&bs.fork, hipEventDisableTiming) != hipSuccess) return SLPF_E_DEVICE;
+        bs.made = true;
+    }
+    if (hipEventRecord(bs.fork, caller) != hipSuccess) return SLPF_E_DEVICE;
+    bool used[kBatchStreams] = {};
+    slpf_status first_err = SLPF_OK;
+    for (const slpf_parser *p : order) {
+        auto it = bs.home.find(p);
+        if (it == bs.home.end()) it = bs.home.emplace(p, static_cast<int>(bs.home.size() % kBatchStreams)).first;
+        const int k = it->second;
+        if (!used[k]) {
+            if (hipStreamWaitEvent(bs.s[k], bs.fork, 0) != hipSuccess) {
+                first_err = SLPF_E_DEVICE;
+                break;
+            }
+            used[k] = true;
+        }
+        const slpf_parse_opts o = job_opts(p);
+        auto &g = groups[p];
+        const slpf_status st = run_job(const_cast<slpf_parser *>(p), g.data(), g.size(), &o, bs.s[k]);
+        if (st != SLPF_OK) {
+            first_err = st;
+            break;
+        }
+    }
+    for (int k = 0; k < kBatchStreams; ++k) {
+        if (!used[k]) continue;
+        if (hipEventRecord(bs.done[k], bs.s[k]) != hipSuccess || hipStreamWaitEvent(caller, bs.done[k], 0) != hipSuccess)
+            if (first_err == SLPF_OK) first_err = SLPF_E_DEVICE;
+    }
+    return first_err;
 }
 
 slpf_status slpf_parser_trim(const slpf_parser *cp, void *hip_stream) {
@@ -1025,10 +1147,10 @@ slpf_status slpf_tune(const slpf_parser *cp, const slpf_text *items, size_t coun
             o.chunk_bytes = k;
             o.flags = flags | (pl ? SLPF_PARSE_FORCE_L2 : 0u);
             // one untimed run (workspace growth, caches), one timed run
-            st = slpf_parse_batch(p, items, count, &o, stream);
+            st = slpf_parse_texts(p, items, count, &o, stream);
             if (st != SLPF_OK) break;
             if (hipEventRecord(e0, stream) != hipSuccess) st = SLPF_E_DEVICE;
-            if (st == SLPF_OK) st = slpf_parse_batch(p, items, count, &o, stream);
+            if (st == SLPF_OK) st = slpf_parse_texts(p, items, count, &o, stream);
             if (st == SLPF_OK && hipEventRecord(e1, stream) != hipSuccess) st = SLPF_E_DEVICE;
             if (st == SLPF_OK && hipEventSynchronize(e1) != hipSuccess) st = SLPF_E_DEVICE;
             float ms = 0;
@@ -1047,6 +1169,8 @@ slpf_status slpf_tune(const slpf_parser *cp, const slpf_text *items, size_t coun
     best->chunk_bytes = best_chunk;
     best->flags = best_flags;
     if (best_ms) *best_ms = best_t;
+    p->tuned_chunk = best_chunk;
+    p->tuned_flags = best_flags & SLPF_PARSE_FORCE_L2;
     return SLPF_OK;
 }
 

@@ -1,4 +1,5 @@
-"""Batched parsing (slpf_parse_batch): one job over many texts gives, for
+"""Batched parsing: one job over many texts of one parser (slpf_parse_texts)
+and one call over the texts of many parsers (slpf_parse_batch) give, for
 every text, exactly the columns, accept flag, count and status of parsing
 that text alone, and of the oracle.
 
@@ -220,3 +221,63 @@ def test_tune_picks_a_candidate_and_keeps_results_exact():
         assert np.array_equal(cols[k].cpu().numpy().view(np.uint64), c), k
         assert bool(s[k, 0]) == acc
         assert int(s[k, 2]) == 0 and int(s[k, 1]) == cnt and int(s[k, 3]) == cntp, k
+
+
+def test_one_call_over_many_res():
+    # slpf_parse_batch: the batched workload's 16 REs (4, 26 and 128-symbol
+    # alphabets, the motif RE), 96 texts interleaved across the REs, one call;
+    # then again after tuning some parsers (their tuned chunk sizes apply)
+    import torch
+    from gen import workloads as wl
+    dev = device()
+    res = wl.batched_res()
+    texts = wl.texts_for(res, wl.loguniform_lengths(17, 96, lo=64, hi=32 << 10), 18)
+    pats = [regen.to_re(t) for _, t in res]
+    parsers = [S.Parser(pt) for pt in pats]
+    oracles = {}
+    dts = [to_device(x.tobytes()) for _, x in texts]
+
+    def one_call():
+        cols = [torch.zeros((x.size + 1, parsers[r].W), dtype=torch.int64, device=dev) for r, x in texts]
+        sc = torch.full((len(texts), 4), 7, dtype=torch.int64, device=dev)
+        S.parse_items([(parsers[r], d, x.size, c, sc[k])
+                       for k, ((r, x), d, c) in enumerate(zip(texts, dts, cols))])
+        torch.cuda.synchronize()
+        return [c.cpu().numpy().view(np.uint64) for c in cols], sc.cpu().numpy().view(np.uint64)
+
+    cols, sc = one_call()
+    for k, (r, x) in enumerate(texts):
+        t = x.tobytes()
+        if r not in oracles:
+            oracles[r] = Oracle(pats[r])
+        oc, acc, cnt, cntp = oracles[r].parse_full(t)
+        assert np.array_equal(cols[k], oc), (k, res[r][0])
+        assert (bool(sc[k, 0]), int(sc[k, 1]), int(sc[k, 2]), int(sc[k, 3])) == (acc, cnt, 0, cntp), k
+    say("one call over", len(res), "REs ok")
+    for q in (0, 3, 15):   # tune three parsers on their own texts
+        mine = [(dts[k], x.size, torch.zeros((x.size + 1, parsers[q].W), dtype=torch.int64, device=dev),
+                 torch.zeros(4, dtype=torch.int64, device=dev)) for k, (r, x) in enumerate(texts) if r == q]
+        if mine:
+            parsers[q].tune(mine)
+    cols2, sc2 = one_call()
+    assert all(np.array_equal(a, b) for a, b in zip(cols, cols2)) and np.array_equal(sc, sc2)
+
+
+def test_one_call_argument_errors():
+    import torch
+    dev = device()
+    p, q = S.Parser("(ab|a)*"), S.Parser("(a|b)*c")
+    h = S.Parser("(ab|a)*", host_only=True)
+    t = to_device(b"abab" * 8)
+    cols = torch.empty((33, 1), dtype=torch.int64, device=dev)
+    small = torch.empty((3, 1), dtype=torch.int64, device=dev)
+    sc = torch.full((2, 4), 7, dtype=torch.int64, device=dev)
+    with pytest.raises(S.SlpfError) as e:
+        S.parse_items([(p, t, 32, cols, sc[0]), (q, t, 32, small, sc[1])])
+    assert e.value.status == S.E_CAPACITY
+    with pytest.raises(S.SlpfError) as e:
+        S.parse_items([(p, t, 32, cols, sc[0]), (h, t, 32, cols, sc[1])])
+    assert e.value.status == S.E_ARG
+    torch.cuda.synchronize()
+    assert (sc.cpu() == 7).all()                       # nothing was launched
+    S.parse_items([])

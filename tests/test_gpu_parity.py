@@ -411,3 +411,53 @@ def test_chunk_edge_shifting_record_text():
                 assert g[1] == acc and g[3] == 0 and g[2] == cnt and g.countp == cntp
         r = p.recognize(to_device(t), chunk_bytes=256)
         assert bool(int(r[0].item())) == acc
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_all_dfa_states_speculation(seed):
+    # the standard speculation the paper compares ME-DFA entries with (Sect.
+    # 5): runs from every DFA state at the inner lane-chunk edges.  Same
+    # columns, accept flag and counts as the oracle; several chunk sizes
+    rng = np.random.default_rng(950 + seed)
+    alpha = [b"ab", b"abc", b"abcdefghijklmnopqrstuvwxyz"][seed % 3]
+    tree = regen.random_re(8600 + seed, n_ops=int(rng.integers(8, 20)), max_depth=6, alphabet=alpha)
+    pat = regen.to_re(tree)
+    o, p = Oracle(pat), S.Parser(pat)
+    text = textgen.sample_text(tree, seed, int(rng.integers(3000, 30000)))
+    bad = textgen.corrupt(text, seed, frac=0.02, block=(1, 32))
+    for t in (text.tobytes(), bad.tobytes(), text.tobytes()[:70]):
+        cols, acc, cnt, cntp = o.parse_full(t)
+        for k in (64, 512):
+            say("alldfa", pat[:50], "n=%d k=%d" % (len(t), k))
+            g = gpu_parse(p, t, chunk_bytes=k, flags=S.PARSE_ALL_DFA_STATES)
+            bad_cols = np.nonzero((g[0] != cols).any(axis=1))[0]
+            assert bad_cols.size == 0, "first differing column %d" % bad_cols[0]
+            assert g[1] == acc and g[3] == 0 and g[2] == cnt and g.countp == cntp
+
+
+def test_all_dfa_states_trace_and_recognizer():
+    # J and J^ at every edge, and the recogniser, with the all-DFA-states lists
+    tree = regen.plain_small_re()
+    pat = regen.to_re(tree).decode()
+    text = textgen.sample_text(tree, 7, 5000).tobytes()
+    o, p = Oracle(pat), S.Parser(pat)
+    k = 192
+    g = gpu_parse(p, text, chunk_bytes=k, trace=True, flags=S.PARSE_ALL_DFA_STATES)
+    tr = g[4]
+    fwd = [o.I]
+    for a in text:
+        fwd.append(o.step_fwd(fwd[-1], a))
+    bwd = [o.F]
+    for a in reversed(text):
+        bwd.append(o.step_bwd(bwd[-1], a))
+    bwd.reverse()
+    n = len(text)
+    for b in range((n + k - 1) // k + 1):
+        pos = min(b * k, n)
+        assert o.to_set(tr[0, b]) == fwd[pos], b
+        assert o.to_set(tr[1, b]) == bwd[pos], b
+    import torch
+    sc = torch.empty(4, dtype=torch.int64, device="cuda:0")
+    for t in (text, text[:-1] + b"z"):
+        p.parse_into(to_device(t), len(t), None, sc, 256, S.PARSE_RECOGNIZE | S.PARSE_ALL_DFA_STATES)
+        assert bool(int(sc[0].item())) == o.parse_full(t)[1]
