@@ -31,7 +31,8 @@ BATCH_RE_SEED, BATCH_LEN_SEED, BATCH_TEXT_SEED = 4000, 4001, 4002
 SERVE_RE_SEED, SERVE_LEN_SEED, SERVE_TEXT_SEED, SERVE_ARRIVAL_SEED = 5000, 5001, 5002, 5003
 SERVE_RATES = [0.25, 0.5, 0.75, 0.9, 1.1]
 RECORD_SEED, RECORD_BYTES = 31, 1 << 30
-KERNEL_SOURCES = ["paper_2503_06763_amd/csrc/kernels.hpp", "paper_2503_06763_amd/csrc/slpf.hip"]
+KERNEL_SOURCES = ["paper_2503_06763_amd/csrc/kernels.hpp", "paper_2503_06763_amd/csrc/count.hpp",
+                  "paper_2503_06763_amd/csrc/slpf.hip"]
 
 
 def kernel_hash():

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libslpf.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 SOURCES = ["slpf.hip", "compiler.cpp", "server.hip"]
-HEADERS = ["kernels.hpp", "slpf_internal.hpp"]
+HEADERS = ["kernels.hpp", "count.hpp", "slpf_internal.hpp", "arena.hpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

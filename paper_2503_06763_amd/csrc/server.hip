@@ -21,6 +21,7 @@
 #include <vector>
 
 #include "../../include/slpf.h"
+#include "arena.hpp"
 
 namespace {
 
@@ -50,47 +51,15 @@ struct slpf_server {
     slpf_server_opts o{};
     uint8_t *arena = nullptr;
     uint64_t arena_bytes = 0;
-    std::map<uint64_t, uint64_t> free_;          // offset -> size, coalesced
+    slpf::Arena ranges;                          // the arena's free and admitted byte ranges
     std::deque<Request> queue;
     std::vector<Slot> slots;
     std::unordered_map<uint64_t, Request> finished;
     std::deque<uint64_t> done;                   // finished tags not yet reported
     std::vector<const slpf_parser *> used;       // parsers that ran on the slots' streams
-    uint64_t admitted_bytes = 0;
 };
 
 namespace {
-
-bool arena_alloc(slpf_server *s, uint64_t bytes, uint64_t *off) {
-    for (auto it = s->free_.begin(); it != s->free_.end(); ++it) {
-        if (it->second >= bytes) {
-            *off = it->first;
-            const uint64_t rest = it->second - bytes, at = it->first + bytes;
-            s->free_.erase(it);
-            if (rest) s->free_[at] = rest;
-            s->admitted_bytes += bytes;
-            return true;
-        }
-    }
-    return false;
-}
-
-void arena_free(slpf_server *s, uint64_t off, uint64_t bytes) {
-    s->admitted_bytes -= bytes;
-    auto it = s->free_.emplace(off, bytes).first;
-    auto nx = std::next(it);
-    if (nx != s->free_.end() && it->first + it->second == nx->first) {
-        it->second += nx->second;
-        s->free_.erase(nx);
-    }
-    if (it != s->free_.begin()) {
-        auto pv = std::prev(it);
-        if (pv->first + pv->second == it->first) {
-            pv->second += it->second;
-            s->free_.erase(it);
-        }
-    }
-}
 
 // Admit requests from the queue head into a free slot and launch them as one
 // job; *launched is false when the head does not fit in the arena, or when
@@ -101,7 +70,7 @@ slpf_status launch(slpf_server *s, Slot &sl, bool *launched) {
     std::vector<Request> batch;
     while (!s->queue.empty() && batch.size() < s->o.max_batch_texts) {
         Request r = s->queue.front();
-        if (!arena_alloc(s, r.bytes, &r.off)) break;   // FIFO: the head waits for space
+        if (!s->ranges.alloc(r.bytes, &r.off)) break;   // FIFO: the head waits for space
         s->queue.pop_front();
         batch.push_back(r);
     }
@@ -174,7 +143,7 @@ slpf_status slpf_server_create(const slpf_server_opts *opts, slpf_server **out) 
         delete s;
         return SLPF_E_NOMEM;
     }
-    s->free_[0] = s->arena_bytes;
+    s->ranges.reset(s->arena_bytes);
     s->slots.resize(opts->slots);
     for (Slot &sl : s->slots) {
         // default-priority streams
@@ -266,7 +235,7 @@ slpf_status slpf_server_release(slpf_server *s, uint64_t tag) {
     if (!s) return SLPF_E_ARG;
     auto it = s->finished.find(tag);
     if (it == s->finished.end()) return SLPF_E_ARG;
-    arena_free(s, it->second.off, it->second.bytes);
+    s->ranges.release(it->second.off, it->second.bytes);
     s->finished.erase(it);
     return SLPF_OK;
 }
@@ -283,7 +252,7 @@ slpf_status slpf_server_stats(const slpf_server *s, slpf_server_state *st) {
     st->in_flight = inflight;
     st->busy_slots = busy;
     st->finished_unreleased = s->finished.size();
-    st->admitted_bytes = s->admitted_bytes;
+    st->admitted_bytes = s->ranges.used();
     st->arena_bytes = s->arena_bytes;
     return SLPF_OK;
 }
