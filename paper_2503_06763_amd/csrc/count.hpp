@@ -108,7 +108,9 @@ __device__ inline bool marked(const Job &jb, const TextCols &tc, uint64_t r) {
     return ((mark_word(jb, tc, r) >> (r & 63)) & 1ull) != 0;
 }
 
-// Last column of the marked run that starts at r0.
+// Last column of the marked run that starts at r0.  Mark words are scanned
+// 64 columns at a time; a lane chunk whose columns are all marked is
+// skipped whole.
 __device__ inline uint64_t run_end(const Job &jb, const TextCols &tc, uint64_t r0) {
     uint64_t e = r0;
     while (true) {
@@ -117,6 +119,14 @@ __device__ inline uint64_t run_end(const Job &jb, const TextCols &tc, uint64_t r
         if (nx == tc.n) {
             if (jb.aend[tc.t] & 1ull) e = nx;
             break;
+        }
+        const uint32_t nw = static_cast<uint32_t>(nx >> 6), sw = static_cast<uint32_t>(jb.s >> 6);
+        if ((nx & 63) == 0 && nw % sw == 0) {       // a lane chunk starts at nx
+            const uint32_t li = nw / sw;
+            if (jb.cfull[tc.c0 + li]) {
+                e = min(nx + jb.s, tc.n) - 1;       // through its last column
+                continue;
+            }
         }
         const uint32_t sh = static_cast<uint32_t>(nx & 63);
         const uint64_t v = mark_word(jb, tc, nx) >> sh;

@@ -167,6 +167,7 @@ struct Job {
     uint32_t *dchunk;           // windows (w c + i) whose short runs the wave kernel counts
     RunRec *runs;               // [cap_runs] long runs
     uint64_t *sruns;            // [cap_sruns] short runs queued for k_count_short (short_run words)
+    uint8_t *cfull;             // [c] every column of lane chunk i is marked (run ends skip such chunks)
     uint32_t *squeue2;          // [cap_sruns] queued runs with a column too large for the first pass
     unsigned long long *nsruns; // short runs queued (may pass cap_sruns: then the rest are counted in place)
     uint32_t cap_sruns;
@@ -1451,6 +1452,7 @@ __global__ __launch_bounds__(kBuildThreads) void k_build(Tabs tb, Job jb) {
     // tree count of an accepted text (an RE whose clean columns are all
     // singletons has one tree per accepted text: nothing to count)
     const bool cnt = act && jb.count_on && !tb.col_single && cx.tr.scalars[0] != 0;
+    bool allm = true;                  // so far, every column of the chunk's windows is marked
     RunMarks rm;
 
     // forward sweep: checkpoints
@@ -1660,7 +1662,11 @@ __global__ __launch_bounds__(kBuildThreads) void k_build(Tabs tb, Job jb) {
             wave_sync();
         }
         // window w+1 can take no more marks
-        if (cnt && on && w + 1 < static_cast<int>(nwin)) jb.amask[ck(jb, i, w + 1)] = rm.wright;
+        if (cnt && on && w + 1 < static_cast<int>(nwin)) {
+            jb.amask[ck(jb, i, w + 1)] = rm.wright;
+            const uint64_t len = min(64ull, hi - (lo + 64ull * (w + 1)));
+            allm = allm && (rm.wright | ~low_mask(static_cast<uint32_t>(len))) == ~0ull;
+        }
         if (nxt) {
 #pragma unroll
             for (int t = 0; t < 64; ++t) fwA[t] = fwB[t];
@@ -1688,6 +1694,8 @@ __global__ __launch_bounds__(kBuildThreads) void k_build(Tabs tb, Job jb) {
                 }
             }
             jb.amask[ck(jb, i, 0)] = rm.wcur;
+            allm = allm && (rm.wcur | ~low_mask(static_cast<uint32_t>(min(64ull, hi - lo)))) == ~0ull;
+            jb.cfull[i] = allm ? 1 : 0;     // every column of the chunk is marked
             if (cx.last) jb.aend[cx.t] = rm.endmark;
             rm.finish();
         }

@@ -608,7 +608,9 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
     // boundary inside are at most total / cell, and so are the anchors, which
     // bounds the piece matrices.
     const uint64_t cols_total = total + T;
-    uint64_t cell = 2048;
+    // (cells of 256 columns up to 4096 cells per job, so the pieces of a long
+    // run walk in parallel; longer texts get longer cells)
+    uint64_t cell = 256;
     while (cell < cols_total / 4096) cell <<= 1;
     const uint32_t lshort = 512;
     const uint64_t cap_runs = cols_total / lshort + T + 1;
@@ -621,7 +623,7 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
     if (count && (cap_runs > 0xffffffffull || cap_pieces > 0xffffffffull || nck >= 0x80000000ull))
         return SLPF_E_ARG;
     int iam = -1, iaend = -1, icfac = -1, itprod = -1, itfail = -1, iccnt = -1, idch = -1, iruns = -1, ipiece = -1,
-        imats = -1, ipmat = -1, isr = -1, isq2 = -1;
+        imats = -1, ipmat = -1, isr = -1, isq2 = -1, icf = -1;
     if (count) {
         iam = L.add(nck * 8);
         iaend = L.add(size_t(T) * 8);
@@ -631,6 +633,7 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
         iccnt = L.add(32);
         idch = L.add((nck + cap_sruns) * 4);
         isr = L.add(cap_sruns * 8);
+        icf = L.add(c);
         isq2 = L.add(cap_sruns * 4);
         iruns = L.add(cap_runs * sizeof(RunRec));
         ipiece = L.add(cap_pieces * 8);
@@ -733,6 +736,7 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
         jb.pmat = reinterpret_cast<uint32_t *>(ptr(ipmat));
         jb.sruns = reinterpret_cast<uint64_t *>(ptr(isr));
         jb.squeue2 = reinterpret_cast<uint32_t *>(ptr(isq2));
+        jb.cfull = reinterpret_cast<uint8_t *>(ptr(icf));
         jb.nsruns = reinterpret_cast<unsigned long long *>(ptr(iccnt) + 16);
         jb.cap_sruns = static_cast<uint32_t>(cap_sruns);
         jb.fol_lds = size_t(tb.nseg) * tb.W * 8 <= kFolLdsBytes ? 1u : 0u;
