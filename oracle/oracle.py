@@ -10,6 +10,7 @@ benchmark's CPU-baseline leg import this module.
 from __future__ import annotations
 
 import ctypes
+import re
 import os
 import subprocess
 
@@ -45,6 +46,8 @@ def _load():
             getattr(L, f).restype = ctypes.c_int
         for f in ("oracle_initial", "oracle_final"):
             getattr(L, f).argtypes = [vp, u64p]
+        L.oracle_node_parent.argtypes = [vp, ctypes.c_int]
+        L.oracle_node_parent.restype = ctypes.c_int
         L.oracle_folseg.argtypes = [vp, ctypes.c_int, u64p]
         L.oracle_label.argtypes = [vp, ctypes.c_int]
         L.oracle_label.restype = ctypes.c_int
@@ -63,6 +66,18 @@ def _load():
         L.oracle_powerset.restype = ctypes.c_int
         _lib = L
     return _lib
+
+
+def _leaf_number(tok: str) -> int:
+    """Node number of a terminal token of a segment text ("a4", "\\x0a4",
+    "[a-e]4", ".4"); -1 for other tokens (parentheses, epsilon, the end mark)."""
+    if tok.endswith("(") or tok.startswith(")") or tok.startswith("ε") or tok == "⊣":
+        return -1
+    if tok.startswith("\\x"):
+        return int(tok[4:])
+    if tok.startswith("["):
+        return int(tok[tok.rindex("]") + 1:])
+    return int(tok[1:])
 
 
 def _u64(a):
@@ -103,6 +118,7 @@ class Oracle:
         self._L = L
         self.nseg = L.oracle_num_segments(h)
         self.W = L.oracle_words(h)
+        self.num_nodes = L.oracle_num_nodes(h)        # RE nodes, numbered 1.. in preorder
         self.segments = [self._seg_text(i) for i in range(self.nseg)]
         # the byte of each end-letter (-2 for a character set, -1 for the end
         # mark) and the set of bytes it matches
@@ -321,6 +337,91 @@ class Oracle:
                 if nf & closes:
                     out.append((r, c))
                 f = nf - closes
+        return sorted(out)
+
+    def node_parent(self, k: int) -> int:
+        """Preorder number of the parent of node k (0 for the root, -1 if none)."""
+        return self._L.oracle_node_parent(self._h, k)
+
+    def children(self, text, g, start, end, cols=None):
+        """getChildren (Sect. 4.2, match extraction): the matches of the child
+        strings of the match (start, end) of node g, as sorted (k, a, b)
+        triples: some tree has g's occurrence over (start, end) and, directly
+        inside it, the child node k (a node whose parent is g) over (a, b).
+        An operator child spans "k(" at a to ")k" at b; a terminal child the
+        one byte at a (b = a + 1); an epsilon child (a, a).
+
+        The trees through that occurrence of g are the walks in the clean SLPF
+        from a segment at column start whose last g-symbol opens g, through
+        segments without g-symbols, to a segment at column end whose first
+        g-symbol closes it: the sub-forest is cut from the columns by a
+        forward pass and a backward pass.  Inside it, a segment's symbols
+        count from its last "g(" at column start and up to its first ")g" at
+        column end.  An operator child's matches are then the walks of
+        ``matches`` restricted to the sub-forest."""
+        x = _bytes(text)
+        n = len(x)
+        if cols is None:
+            cols = self.parse(x)[0]
+        C = [self.to_set(c) for c in cols]
+        toks = [t.split(" ") for t in self.segments]
+        o, cl = "%d(" % g, ")%d" % g
+
+        def gsyms(s):
+            return [t for t in toks[s] if t in (o, cl)]
+        i, j = start, end
+        S = {}
+        if i == j:
+            S[i] = {s for s in C[i] if any(a == o and b == cl for a, b in zip(gsyms(s), gsyms(s)[1:]))}
+        else:
+            F = {i: {s for s in C[i] if gsyms(s) and gsyms(s)[-1] == o}}
+            for c in range(i + 1, j + 1):
+                nxt = set().union(*[self.folseg[s] for s in F[c - 1]]) & C[c] if F[c - 1] else set()
+                closes = {s for s in nxt if gsyms(s) and gsyms(s)[0] == cl}
+                F[c] = closes if c == j else nxt - closes
+            S[j] = F[j]
+            for c in range(j - 1, i - 1, -1):
+                S[c] = {s for s in F[c] if self.folseg[s] & S[c + 1]}
+        if not S[i]:
+            return []
+
+        def bounds(s, c):
+            """[lo, hi): the symbols of segment s at column c that lie inside
+            g's occurrence."""
+            t = toks[s]
+            lo, hi = 0, len(t)
+            if c == i:
+                lo = max(k for k, u in enumerate(t) if u == o) + 1
+            if c == j:
+                hi = min(k for k, u in enumerate(t) if u == cl and k >= lo)
+            return lo, hi
+
+        def portion(s, c):
+            lo, hi = bounds(s, c)
+            return toks[s][lo:hi]
+        kids = [k for k in range(1, self.num_nodes + 1) if self.node_parent(k) == g]
+        out = set()
+        for k in kids:
+            ko, kc = "%d(" % k, ")%d" % k
+            for a in range(i, j + 1):
+                for s in S[a]:
+                    p = portion(s, a)
+                    ks = [u for u in p if u in (ko, kc)]
+                    if any(u == ko and v == kc for u, v in zip(ks, ks[1:])):
+                        out.add((k, a, a))                      # "k( .. )k" inside one segment
+                    if ("ε%d" % k) in p:
+                        out.add((k, a, a))                      # an epsilon child
+                    if bounds(s, a)[1] == len(toks[s]) and _leaf_number(toks[s][-1]) == k:
+                        out.add((k, a, a + 1))                  # a terminal child: the end-letter
+                f = {s for s in S[a] if [u for u in portion(s, a) if u in (ko, kc)][-1:] == [ko]}
+                c = a
+                while f and c < j:
+                    c += 1
+                    nf = set().union(*[self.folseg[s] for s in f]) & S[c]
+                    closing = {s for s in nf if [u for u in portion(s, c) if u in (ko, kc)][:1] == [kc]}
+                    if closing:
+                        out.add((k, a, c))
+                    f = nf - closing
         return sorted(out)
 
     # -- the parallel algorithm's quantities (Sect. 3.2), plain Python

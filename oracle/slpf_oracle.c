@@ -515,6 +515,17 @@ void oracle_free(oracle_t *o) {
 int oracle_num_segments(const oracle_t *o) { return o->nseg; }
 int oracle_words(const oracle_t *o) { return o->W; }
 int oracle_num_nodes(const oracle_t *o) { return o->nnodes; }
+
+/* Preorder number of the parent of the node numbered `num` in the RE tree
+ * (Sect. 2.2), 0 for the root, -1 when no node has that number. */
+int oracle_node_parent(const oracle_t *o, int num) {
+    for (int x = 0; x < o->nnodes; x++)
+        for (int k = 0; k < o->nodes[x].nkids; k++)
+            if (o->nodes[o->nodes[x].kids[k]].num == num) return o->nodes[x].num;
+    for (int x = 0; x < o->nnodes; x++)
+        if (o->nodes[x].num == num) return 0;
+    return -1;
+}
 void oracle_initial(const oracle_t *o, uint64_t *out) { memcpy(out, o->I, 8 * o->W); }
 void oracle_final(const oracle_t *o, uint64_t *out) { memcpy(out, o->F, 8 * o->W); }
 void oracle_folseg(const oracle_t *o, int seg, uint64_t *out) {

@@ -224,6 +224,16 @@ def is_end_letter(tok: str) -> bool:
     return not (tok.endswith("(") or tok.startswith(")") or tok.startswith("ε"))
 
 
+def leaf_number(tok: str) -> int:
+    """The node number printed at the end of a leaf token (a terminal or an
+    epsilon, in the forms ``_tok_leaf`` writes)."""
+    if tok.startswith("\\x"):
+        return int(tok[4:])                  # "\\x" and two hex digits
+    if tok.startswith("["):
+        return int(tok[tok.rindex("]") + 1:])
+    return int(tok[1:])                      # one letter, ".", or "ε"
+
+
 def segments_of(lst) -> list:
     """Factor an LST followed by the end mark into its segments."""
     segs, cur = [], []

@@ -203,6 +203,72 @@ def test_match_extraction_rejected_and_e2_example():
     assert o.matches(b"abaaba", 1) == [(0, 6)]
 
 
+def _brute_children(re_, text, g, start, end):
+    """The direct children of g's occurrences over (start, end), over every
+    LST (brute force): each subtree directly inside such an occurrence, as
+    (node, a, b); a terminal spans one byte, an epsilon none."""
+    out = set()
+    for t in lst_brute.lsts(re_, text):
+        p, stack = 0, []                 # open subtrees: [node, start, children]
+        for tok in t:
+            if tok.endswith("("):
+                stack.append([int(tok[:-1]), p, []])
+                continue
+            if tok.startswith(")"):
+                k, a, kids = stack.pop()
+                b = p
+                if k == g and (a, b) == (start, end):
+                    out.update(kids)
+            else:
+                k, a = lst_brute.leaf_number(tok), p
+                b = p + 1 if lst_brute.is_end_letter(tok) else p
+                p = b
+            if stack:
+                stack[-1][2].append((k, a, b))
+    return sorted(out)
+
+
+def _check_children(o, re_, text, n_groups):
+    cols = o.parse(text)[0]
+    n = len(text)
+    for g in range(1, n_groups + 1):
+        spans = set(_brute_matches(re_, text, g))
+        # every match of g, and some spans that are not matches
+        probe = spans | {(0, n), (n // 2, n), (0, n // 2), (n, n)}
+        for (a, b) in sorted(probe):
+            want = _brute_children(re_, text, g, a, b) if (a, b) in spans else []
+            assert o.children(text, g, a, b, cols=cols) == want, (re_, text, g, a, b)
+
+
+@pytest.mark.parametrize("re_,texts", MATCH_CASES)
+def test_children_equal_brute_force(re_, texts):
+    # getChildren: the children of every match of every node equal the
+    # subtrees directly inside that node's occurrences over all trees
+    o = Oracle(re_)
+    for text in texts:
+        _check_children(o, re_.encode(), text, o.num_nodes)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_children_equal_brute_force_random(seed):
+    rng = np.random.default_rng(3000 + seed)
+    pat = regen.to_re(_tiny_random_re(rng))
+    o = Oracle(pat)
+    for x in _strings("ab", 4):
+        _check_children(o, pat, x, o.num_nodes)
+
+
+def test_children_e2_example():
+    # Ex. 6 tree of "abaaba": the star's children are the four factors, the
+    # union's child over "ab" the concatenation, whose children are a and b
+    o = Oracle("(ab|a)*")
+    assert o.children(b"abaaba", 1, 0, 6) == [(2, 0, 2), (2, 2, 3), (2, 3, 5), (2, 5, 6)]
+    assert o.children(b"abaaba", 2, 0, 2) == [(3, 0, 2)]
+    assert o.children(b"abaaba", 2, 2, 3) == [(6, 2, 3)]
+    assert o.children(b"abaaba", 3, 3, 5) == [(4, 3, 4), (5, 4, 5)]
+    assert o.children(b"abaaba", 1, 0, 5) == [] and o.children(b"abaaba", 4, 0, 1) == []
+
+
 # ------------------------------------------------------------ e3, e1, e4
 
 def test_e3_nfa_and_slpf():
