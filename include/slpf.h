@@ -189,6 +189,36 @@ slpf_status slpf_decode_compact(const slpf_parser *p, const uint8_t *text_dev, u
 slpf_status slpf_get_matches(const slpf_parser *p, const uint64_t *columns_dev, uint64_t n, uint32_t group,
                              uint64_t *pairs_dev, uint64_t capacity, uint64_t *num_matches, void *hip_stream);
 
+/*
+ * Child extraction (Sect. 4, Other functions of the tool: getChildren).
+ * Given a match (start, end) of node `group` (as slpf_get_matches lists
+ * them) in the clean SLPF columns_dev of an n-byte text, the matches of its
+ * children: every triple (k, a, b) such that some syntax tree of the text
+ * holds `group` over text[start, end) and, directly inside that occurrence,
+ * node k over text[a, b).  k is a child of `group` in the RE tree (an
+ * operand of a concatenation or union, the body of a star, cross or
+ * optional part); a terminal child spans one byte (b = a + 1), an epsilon
+ * child or an empty operator child none (b = a).  A pair (start, end) that
+ * is no match of the node, and a leaf node, have no children.
+ *
+ * triples_dev: device, room for `capacity` triples of uint64_t (k, a, b),
+ *   written sorted by (k, a, b).
+ * *num_children (host): the number of triples.  SLPF_E_CAPACITY when it
+ *   exceeds capacity (the first `capacity` triples are written).
+ * SLPF_E_ARG: NULL pointer, group 0 or past the last node number,
+ *   start > end, end > n, n >= 2^31 - 1, or (number of children of the node)
+ *   x (end - start + 1) >= 2^31 - 1.
+ * Work buffers are allocated for the call (about (8 W + 25 k + 9) bytes per
+ * column of the span, k the node's number of children); the call
+ * synchronizes hip_stream.  The columns of the span are cut into stretches at
+ * the columns that hold one segment; the cost is proportional to the span's
+ * length plus the summed lengths of the child matches, and the longest
+ * stretch of columns with several segments runs in one wavefront.
+ */
+slpf_status slpf_get_children(const slpf_parser *p, const uint64_t *columns_dev, uint64_t n, uint32_t group,
+                              uint64_t start, uint64_t end, uint64_t *triples_dev, uint64_t capacity,
+                              uint64_t *num_children, void *hip_stream);
+
 /* -------------------------------------------------------------------- parse */
 
 enum {

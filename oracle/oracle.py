@@ -363,7 +363,7 @@ class Oracle:
         n = len(x)
         if cols is None:
             cols = self.parse(x)[0]
-        C = [self.to_set(c) for c in cols]
+        C = {c: self.to_set(cols[c]) for c in range(start, end + 1)}
         toks = [t.split(" ") for t in self.segments]
         o, cl = "%d(" % g, ")%d" % g
 

@@ -37,7 +37,7 @@ EXPORTS = ["slpf_compile", "slpf_parser_destroy", "slpf_parser_info_get", "slpf_
            "slpf_parser_trim",
            "slpf_num_chunks", "slpf_status_str", "slpf_server_create", "slpf_server_destroy",
            "slpf_server_submit", "slpf_server_poll", "slpf_server_result", "slpf_server_release",
-           "slpf_server_stats", "slpf_compact_bytes", "slpf_decode_compact", "slpf_get_matches",
+           "slpf_server_stats", "slpf_compact_bytes", "slpf_decode_compact", "slpf_get_matches", "slpf_get_children",
            "slpf_parse_noalloc"]
 
 
@@ -161,6 +161,9 @@ def lib(path: str = LIB_PATH):
     L.slpf_get_matches.argtypes = [vp, vp, ctypes.c_uint64, ctypes.c_uint32, vp, ctypes.c_uint64,
                                    ctypes.POINTER(ctypes.c_uint64), vp]
     L.slpf_get_matches.restype = ctypes.c_int
+    L.slpf_get_children.argtypes = [vp, vp, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64,
+                                    vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64), vp]
+    L.slpf_get_children.restype = ctypes.c_int
     L.slpf_num_chunks.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(ParseOpts)]
     L.slpf_num_chunks.restype = ctypes.c_uint64
     L.slpf_status_str.argtypes = [ctypes.c_int]
@@ -349,6 +352,26 @@ class Parser:
                 capacity = int(cnt.value)
                 continue
             _check(st, "slpf_get_matches")
+            return out[:cnt.value].cpu().numpy().view(np.uint64)
+
+    def children(self, columns, group: int, start: int, end: int, capacity: int = 1 << 12, stream=None):
+        """Children of the match (start, end) of node ``group`` in the plain
+        SLPF ``columns`` [n+1, W]: a host uint64 array [k, 3] of (child, a, b)
+        triples sorted by (child, a, b)."""
+        import numpy as np
+        import torch
+        n = columns.shape[0] - 1
+        if stream is None:
+            stream = torch.cuda.current_stream(columns.device)
+        while True:
+            out = torch.empty((max(capacity, 1), 3), dtype=torch.int64, device=columns.device)
+            cnt = ctypes.c_uint64(0)
+            st = self._L.slpf_get_children(self._h, columns.data_ptr(), n, group, start, end, out.data_ptr(),
+                                           capacity, ctypes.byref(cnt), ctypes.c_void_p(stream.cuda_stream))
+            if st == E_CAPACITY:
+                capacity = int(cnt.value)
+                continue
+            _check(st, "slpf_get_children")
             return out[:cnt.value].cpu().numpy().view(np.uint64)
 
     def decode_compact(self, text, compact, stream=None):

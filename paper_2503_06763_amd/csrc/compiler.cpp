@@ -593,6 +593,24 @@ int compile_re(const uint8_t *re, size_t len, const CompileLimits &lim, HostAuto
             if (open_then_close[g]) m[2 * W + (q >> 6)] |= bit;
         }
     }
+    // the RE tree and each segment's symbols, for getChildren
+    A.parent.assign(A.ngroups, 0);
+    A.node_kind.assign(A.ngroups, 0);
+    for (auto &v : nodes) {
+        if (v.num <= 0) continue;
+        A.node_kind[v.num] = v.kind == K::Lit ? 1 : v.kind == K::Eps ? 2 : 0;
+        for (int k : v.kids) A.parent[nodes[k].num] = v.num;
+    }
+    A.sym_off.assign(1, 0);
+    A.sym_code.clear();
+    for (uint32_t q = 0; q < L; ++q) {
+        for (int sy : segs[q]) {
+            const Sym &y = syms[sy];
+            const int32_t num = y.kind == SEnd ? 0 : nodes[y.node].num;
+            A.sym_code.push_back(num * 4 + static_cast<int32_t>(y.kind));
+        }
+        A.sym_off.push_back(static_cast<uint32_t>(A.sym_code.size()));
+    }
     A.I = I.w;
     A.F = F.w;
     A.ninit = A.nfinal = 0;

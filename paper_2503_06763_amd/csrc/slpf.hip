@@ -1338,3 +1338,361 @@ extern "C" slpf_status slpf_get_matches(const slpf_parser *p, const uint64_t *co
     *num_matches = h_total;
     return h_total > capacity ? SLPF_E_CAPACITY : SLPF_OK;
 }
+
+// ------------------------------------------------------------ child extraction
+// The children of a match (Sect. 4, "Other functions of the tool", Match
+// extraction: getChildren).
+//
+// Given a match (i, j) of node g, the trees that hold g over (i, j) are the
+// paths of the clean SLPF that leave column i through a segment whose last
+// g-symbol is "g(", cross the columns strictly between without closing g,
+// and enter column j through a segment whose first g-symbol is ")g" (for
+// i = j: the segments holding "g( .. )g").  This sub-forest is cut from the
+// columns first; the children of g are then read inside it, each segment
+// restricted to the part of its symbols that lies inside g's occurrence
+// (after its last "g(" at column i, before its first ")g" at column j).
+//
+// Cutting the sub-forest is chunk-parallel: a column of the clean SLPF that
+// holds one segment lies on every tree, so when (i, j) is a match that
+// segment lies on the sub-forest.  Such columns split [i, j] into stretches;
+// one wavefront per stretch walks forward from the stretch's first column
+// (the segments allowed there) and back from its last, and the stretches
+// need nothing from each other.  The match exists iff every stretch's
+// forward walk reaches its last column.
+//
+// A child k of g (a node whose parent is g) has, per column a of the
+// sub-forest:
+//   an empty match (k, a, a) where a segment holds "k( )k" (adjacent among
+//   its k-symbols) or the leaf "εk" inside g's part of it;
+//   the one-byte match (k, a, a + 1) where a < j and the segment's
+//   end-letter is the terminal k;
+//   matches (k, a, e), e > a, walked from the segments whose last k-symbol
+//   is "k(" through segments without k-symbols to those whose first
+//   k-symbol is ")k", inside the sub-forest.  (At columns i and j these
+//   whole-segment tests agree with the tests on g's part: a k-symbol
+//   outside it belongs to another occurrence of g, which can only be an
+//   earlier one closing at i or a later one opening at j.)
+// The per-child masks depend on the column's place in [i, j] and are built
+// on the host for the call.  The (child, column) items are flagged, listed
+// in order, walked once to count and once to write, as in match extraction,
+// so the triples come out sorted by (child, start, end).
+namespace slpf {
+namespace {
+
+constexpr int kChildMasks = 7;   // per child: op, cl, term, empty at first / interior / last / both
+
+// Cut columns of [start, start + L): the two ends and every column with at
+// most one segment.
+__global__ __launch_bounds__(256) void k_cf_cuts(const uint64_t *cols, uint32_t W, uint64_t start, uint64_t L,
+                                                 uint8_t *flags) {
+    const uint64_t t = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= L) return;
+    const uint64_t *c = cols + (start + t) * W;
+    int pc = 0;
+    for (uint32_t w = 0; w < W && pc < 2; ++w) pc += __builtin_popcountll(c[w]);
+    flags[t] = (t == 0 || t == L - 1 || pc <= 1) ? 1 : 0;
+}
+
+// One wavefront per stretch [cuts[s], cuts[s+1]]; lane w holds word w.
+// sub[t] receives the sub-forest's column start + t; *fail is set when a
+// stretch's forward walk dies (then (start, start + L - 1) is no match).
+__global__ __launch_bounds__(64) void k_cf_stretch(Tabs tb, const uint64_t *cols, uint64_t start, uint64_t L,
+                                                   uint32_t g, const uint64_t *cuts, const int *ncuts,
+                                                   uint64_t *sub, uint32_t *fail) {
+    const uint32_t lane = threadIdx.x, W = tb.W;
+    const bool on = lane < W;
+    const uint64_t *m = tb.gmask + static_cast<uint64_t>(g) * 3 * W;
+    const uint64_t op = on ? m[lane] : 0ull, cl = on ? m[W + lane] : 0ull, oc = on ? m[2 * W + lane] : 0ull;
+    if (L == 1) {
+        if (blockIdx.x != 0) return;
+        const uint64_t f = on ? cols[start * W + lane] & oc : 0ull;
+        if (on) sub[lane] = f;
+        if (!__any(f != 0) && lane == 0) *fail = 1u;
+        return;
+    }
+    const int nst = *ncuts - 1;
+    for (int s = blockIdx.x; s < nst; s += gridDim.x) {
+        const uint64_t u = cuts[s], v = cuts[s + 1];
+        uint64_t f = on ? cols[(start + u) * W + lane] : 0ull;
+        if (u == 0) {
+            f &= op;
+            if (on) sub[lane] = f;
+        }
+        uint64_t c = u;
+        while (c < v && __any(f != 0)) {
+            ++c;
+            uint64_t nf = 0;
+            for (uint32_t w = 0; w < W; ++w)
+                for (uint64_t fw = readlane_u64(f, static_cast<int>(w)); fw; fw &= fw - 1) {
+                    const uint64_t sg = w * 64ull + static_cast<uint64_t>(__builtin_ctzll(fw));
+                    if (on) nf |= tb.folseg[sg * W + lane];
+                }
+            if (on) nf &= cols[(start + c) * W + lane] & (c == L - 1 ? cl : ~cl);
+            if (on) sub[c * W + lane] = nf;
+            f = nf;
+        }
+        if (c < v || !__any(f != 0)) {
+            if (lane == 0) *fail = 1u;
+            continue;
+        }
+        // back from column v: keep the segments some kept follower follows
+        uint64_t b = f;
+        const uint64_t lo = u == 0 ? 0 : u + 1;     // an interior cut is written by the stretch ending there
+        for (uint64_t cc = v; cc > lo; --cc) {
+            const uint64_t col = cc - 1;
+            uint64_t pb = 0;
+            for (uint32_t w = 0; w < W; ++w)
+                for (uint64_t bw = readlane_u64(b, static_cast<int>(w)); bw; bw &= bw - 1) {
+                    const uint64_t sg = w * 64ull + static_cast<uint64_t>(__builtin_ctzll(bw));
+                    if (on) pb |= tb.predseg[sg * W + lane];
+                }
+            uint64_t x = 0;
+            if (on) {
+                x = sub[col * W + lane] & pb;
+                sub[col * W + lane] = x;
+            }
+            b = x;
+        }
+    }
+}
+
+__device__ __forceinline__ int child_role(uint64_t t, uint64_t L) {
+    return L == 1 ? 6 : t == 0 ? 3 : t == L - 1 ? 5 : 4;
+}
+
+// Item q * L + t (child q, column start + t): flagged when the walk there
+// emits anything.
+__global__ __launch_bounds__(256) void k_ch_flags(const uint64_t *masks, uint32_t W, const uint64_t *sub, uint64_t L,
+                                                  uint64_t N, const uint32_t *fail, uint8_t *flags) {
+    const uint64_t item = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (item >= N) return;
+    if (*fail) {
+        flags[item] = 0;
+        return;
+    }
+    const uint64_t q = item / L, t = item % L;
+    const uint64_t *mk = masks + q * kChildMasks * W;
+    const uint64_t *e = mk + static_cast<uint64_t>(child_role(t, L)) * W;
+    const bool inner = t + 1 < L;
+    uint64_t any = 0;
+    for (uint32_t w = 0; w < W; ++w)
+        any |= sub[t * W + w] & (e[w] | (inner ? mk[w] | mk[2 * W + w] : 0ull));
+    flags[item] = any != 0 ? 1 : 0;
+}
+
+// One wavefront per listed item; lane w holds word w.
+template <bool WRITE>
+__global__ __launch_bounds__(64) void k_ch_walk(Tabs tb, const uint64_t *masks, const uint32_t *kids,
+                                                const uint64_t *sub, uint64_t start, uint64_t L, const uint64_t *items,
+                                                const int *nitems, uint64_t *counts, const uint64_t *offs,
+                                                uint64_t *triples, uint64_t cap) {
+    const uint32_t lane = threadIdx.x, W = tb.W;
+    const bool on = lane < W;
+    const int ni = *nitems;
+    for (int it = blockIdx.x; it < ni; it += gridDim.x) {
+        const uint64_t item = items[it], q = item / L, t = item % L;
+        const uint64_t *mk = masks + q * kChildMasks * W;
+        const uint64_t op = on ? mk[lane] : 0ull, cl = on ? mk[W + lane] : 0ull;
+        const uint64_t term = on ? mk[2 * W + lane] : 0ull;
+        const uint64_t em = on ? mk[static_cast<uint64_t>(child_role(t, L)) * W + lane] : 0ull;
+        const uint64_t k = kids[q];
+        uint64_t pos = WRITE ? offs[it] : 0ull;
+        auto emit = [&](uint64_t e) {
+            if (WRITE && lane == 0 && pos < cap) {
+                triples[3 * pos] = k;
+                triples[3 * pos + 1] = start + t;
+                triples[3 * pos + 2] = start + e;
+            }
+            ++pos;
+        };
+        const uint64_t s0 = on ? sub[t * W + lane] : 0ull;
+        if (__any((s0 & em) != 0)) emit(t);
+        if (t + 1 < L) {
+            if (__any((s0 & term) != 0)) emit(t + 1);
+            uint64_t f = s0 & op;
+            uint64_t c = t;
+            while (c + 1 < L && __any(f != 0)) {
+                ++c;
+                uint64_t nf = 0;
+                for (uint32_t w = 0; w < W; ++w)
+                    for (uint64_t fw = readlane_u64(f, static_cast<int>(w)); fw; fw &= fw - 1) {
+                        const uint64_t sg = w * 64ull + static_cast<uint64_t>(__builtin_ctzll(fw));
+                        if (on) nf |= tb.folseg[sg * W + lane];
+                    }
+                if (on) nf &= sub[c * W + lane];
+                if (__any((nf & cl) != 0)) emit(c);
+                f = nf & ~cl;
+            }
+        }
+        if (!WRITE && lane == 0) counts[it] = pos;
+    }
+}
+
+// Host: the per-child masks of a call (kChildMasks x W words per child).
+void child_masks(const HostAutomaton &A, uint32_t g, const std::vector<uint32_t> &kids, std::vector<uint64_t> &out) {
+    const uint32_t W = A.W, nk = static_cast<uint32_t>(kids.size());
+    out.assign(static_cast<size_t>(nk) * kChildMasks * W, 0);
+    std::vector<int> idx(A.ngroups, -1);
+    for (uint32_t q = 0; q < nk; ++q) {
+        idx[kids[q]] = static_cast<int>(q);
+        const uint64_t *gm = A.gmask.data() + static_cast<size_t>(kids[q]) * 3 * W;
+        std::copy(gm, gm + 2 * W, out.begin() + static_cast<size_t>(q) * kChildMasks * W);   // op, cl
+    }
+    std::vector<int8_t> prev(nk, -1);
+    std::vector<uint32_t> touched;
+    for (uint32_t s = 0; s < A.nseg; ++s) {
+        const int32_t *y = A.sym_code.data() + A.sym_off[s];
+        const int len = static_cast<int>(A.sym_off[s + 1] - A.sym_off[s]);
+        const uint64_t bit = uint64_t(1) << (s & 63);
+        const size_t word = s >> 6;
+        auto set = [&](uint32_t q, int mask) { out[(static_cast<size_t>(q) * kChildMasks + mask) * W + word] |= bit; };
+        int last_open = -1, first_close = -1, close_after = -1;
+        for (int x = 0; x < len; ++x) {
+            if (y[x] == static_cast<int32_t>(g * 4 + 0)) last_open = x;
+            if (y[x] == static_cast<int32_t>(g * 4 + 2) && first_close < 0) first_close = x;
+        }
+        for (int x = last_open + 1; last_open >= 0 && x < len; ++x)
+            if (y[x] == static_cast<int32_t>(g * 4 + 2)) {
+                close_after = x;
+                break;
+            }
+        // the end-letter is terminal k
+        const int32_t e = y[len - 1];
+        if ((e & 3) == 1 && A.node_kind[e >> 2] == 1 && idx[e >> 2] >= 0) set(static_cast<uint32_t>(idx[e >> 2]), 2);
+        // empty children inside [lo, hi) for each place of the column
+        auto empties = [&](int lo, int hi, int mask) {
+            for (int x = lo; x < hi; ++x) {
+                const int32_t num = y[x] >> 2, kind = y[x] & 3;
+                if (kind == 3 || idx[num] < 0) continue;
+                const uint32_t q = static_cast<uint32_t>(idx[num]);
+                if (kind == 1) {
+                    if (A.node_kind[num] == 2) set(q, mask);
+                } else if (kind == 0) {
+                    if (prev[q] < 0) touched.push_back(q);
+                    prev[q] = 0;
+                } else {
+                    if (prev[q] == 0) set(q, mask);
+                    if (prev[q] < 0) touched.push_back(q);
+                    prev[q] = 2;
+                }
+            }
+            for (uint32_t q : touched) prev[q] = -1;
+            touched.clear();
+        };
+        if (last_open >= 0) empties(last_open + 1, len, 3);
+        empties(0, len, 4);
+        if (first_close >= 0) empties(0, first_close, 5);
+        if (last_open >= 0 && close_after >= 0) empties(last_open + 1, close_after, 6);
+    }
+}
+
+}  // namespace
+}  // namespace slpf
+
+extern "C" slpf_status slpf_get_children(const slpf_parser *p, const uint64_t *columns_dev, uint64_t n,
+                                         uint32_t group, uint64_t start, uint64_t end, uint64_t *triples_dev,
+                                         uint64_t capacity, uint64_t *num_children, void *hip_stream) {
+    using namespace slpf;
+    if (!p || p->host_only || !columns_dev || !num_children || (capacity && !triples_dev)) return SLPF_E_ARG;
+    const HostAutomaton &A = p->A;
+    const Tabs tb = p->tabs;
+    if (group == 0 || group >= tb.ngroups || start > end || end > n) return SLPF_E_ARG;
+    if (n >= static_cast<uint64_t>(INT_MAX)) return SLPF_E_ARG;
+    std::vector<uint32_t> kids;
+    for (uint32_t k = 1; k < A.ngroups; ++k)
+        if (A.parent[k] == static_cast<int32_t>(group)) kids.push_back(k);
+    *num_children = 0;
+    if (kids.empty()) return SLPF_OK;                 // a leaf
+    const uint64_t L = end - start + 1, nk = kids.size(), N = nk * L;
+    if (N >= static_cast<uint64_t>(INT_MAX)) return SLPF_E_ARG;
+    const uint32_t W = tb.W;
+    std::vector<uint64_t> hmask;
+    child_masks(A, group, kids, hmask);
+    if (hipSetDevice(p->device) != hipSuccess) return SLPF_E_DEVICE;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    const int NI = static_cast<int>(N), LI = static_cast<int>(L);
+    size_t sel_bytes = 0, sel2_bytes = 0, scan_bytes = 0;
+    hipcub::CountingInputIterator<uint64_t> idx(0);
+    if (hipcub::DeviceSelect::Flagged(nullptr, sel_bytes, idx, static_cast<uint8_t *>(nullptr),
+                                      static_cast<uint64_t *>(nullptr), static_cast<int *>(nullptr), NI, st) !=
+            hipSuccess ||
+        hipcub::DeviceSelect::Flagged(nullptr, sel2_bytes, idx, static_cast<uint8_t *>(nullptr),
+                                      static_cast<uint64_t *>(nullptr), static_cast<int *>(nullptr), LI, st) !=
+            hipSuccess ||
+        hipcub::DeviceScan::ExclusiveSum(nullptr, scan_bytes, static_cast<uint64_t *>(nullptr),
+                                         static_cast<uint64_t *>(nullptr), NI, st) != hipSuccess)
+        return SLPF_E_DEVICE;
+    const size_t tmp_bytes = std::max(sel_bytes, std::max(sel2_bytes, scan_bytes));
+    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+    // work buffers: child masks, child numbers, the sub-forest, cut flags and
+    // list, item flags, list, counts, offsets, small counters, select/scan room
+    const size_t o_mask = 0, o_kids = o_mask + al(hmask.size() * 8), o_sub = o_kids + al(nk * 4),
+                 o_cflag = o_sub + al(L * W * 8), o_cuts = o_cflag + al(L), o_iflag = o_cuts + al(L * 8),
+                 o_items = o_iflag + al(N), o_counts = o_items + al(N * 8), o_offs = o_counts + al(N * 8),
+                 o_small = o_offs + al(N * 8), o_tmp = o_small + 256, bytes = o_tmp + al(tmp_bytes);
+    uint8_t *buf = nullptr;
+    if (hipMalloc(reinterpret_cast<void **>(&buf), bytes) != hipSuccess) return SLPF_E_NOMEM;
+    uint64_t *masks = reinterpret_cast<uint64_t *>(buf + o_mask);
+    uint32_t *kids_dev = reinterpret_cast<uint32_t *>(buf + o_kids);
+    uint64_t *sub = reinterpret_cast<uint64_t *>(buf + o_sub);
+    uint8_t *cflag = buf + o_cflag, *iflag = buf + o_iflag;
+    uint64_t *cuts = reinterpret_cast<uint64_t *>(buf + o_cuts);
+    uint64_t *items = reinterpret_cast<uint64_t *>(buf + o_items);
+    uint64_t *counts = reinterpret_cast<uint64_t *>(buf + o_counts);
+    uint64_t *offs = reinterpret_cast<uint64_t *>(buf + o_offs);
+    uint64_t *total = reinterpret_cast<uint64_t *>(buf + o_small);
+    int *ncuts = reinterpret_cast<int *>(buf + o_small + 8);
+    int *nitems = reinterpret_cast<int *>(buf + o_small + 16);
+    uint32_t *fail = reinterpret_cast<uint32_t *>(buf + o_small + 24);
+    void *tmp = buf + o_tmp;
+    slpf_status status = SLPF_OK;
+    uint64_t h_total = 0;
+    const uint32_t lblocks = static_cast<uint32_t>((L + 255) / 256), nblocks = static_cast<uint32_t>((N + 255) / 256);
+    do {
+        if (hipMemcpyAsync(masks, hmask.data(), hmask.size() * 8, hipMemcpyHostToDevice, st) != hipSuccess ||
+            hipMemcpyAsync(kids_dev, kids.data(), nk * 4, hipMemcpyHostToDevice, st) != hipSuccess) {
+            status = SLPF_E_DEVICE;
+            break;
+        }
+        hipLaunchKernelGGL(k_match_fill, dim3(1), dim3(64), 0, st, total, 4);   // total, counters, fail
+        hipLaunchKernelGGL(k_cf_cuts, dim3(lblocks), dim3(256), 0, st, columns_dev, W, start, L, cflag);
+        size_t t1 = tmp_bytes;
+        if (hipcub::DeviceSelect::Flagged(tmp, t1, idx, cflag, cuts, ncuts, LI, st) != hipSuccess) {
+            status = SLPF_E_DEVICE;
+            break;
+        }
+        const uint32_t swalk = static_cast<uint32_t>(std::min<uint64_t>(L, 4096));
+        hipLaunchKernelGGL(k_cf_stretch, dim3(swalk), dim3(64), 0, st, tb, columns_dev, start, L, group, cuts, ncuts,
+                           sub, fail);
+        hipLaunchKernelGGL(k_ch_flags, dim3(nblocks), dim3(256), 0, st, masks, W, sub, L, N, fail, iflag);
+        hipLaunchKernelGGL(k_match_fill, dim3(nblocks), dim3(256), 0, st, counts, N);
+        size_t t2 = tmp_bytes;
+        if (hipcub::DeviceSelect::Flagged(tmp, t2, idx, iflag, items, nitems, NI, st) != hipSuccess) {
+            status = SLPF_E_DEVICE;
+            break;
+        }
+        const uint32_t walkers = static_cast<uint32_t>(std::min<uint64_t>(N, 4096));
+        hipLaunchKernelGGL(k_ch_walk<false>, dim3(walkers), dim3(64), 0, st, tb, masks, kids_dev, sub, start, L, items,
+                           nitems, counts, nullptr, nullptr, 0ull);
+        size_t t3 = tmp_bytes;
+        if (hipcub::DeviceScan::ExclusiveSum(tmp, t3, counts, offs, NI, st) != hipSuccess) {
+            status = SLPF_E_DEVICE;
+            break;
+        }
+        hipLaunchKernelGGL(k_match_total, dim3(1), dim3(1), 0, st, offs, counts, nitems, total);
+        if (hipMemcpyAsync(&h_total, total, 8, hipMemcpyDeviceToHost, st) != hipSuccess ||
+            hipStreamSynchronize(st) != hipSuccess) {
+            status = SLPF_E_DEVICE;
+            break;
+        }
+        if (h_total && capacity)
+            hipLaunchKernelGGL(k_ch_walk<true>, dim3(walkers), dim3(64), 0, st, tb, masks, kids_dev, sub, start, L,
+                               items, nitems, counts, offs, triples_dev, capacity);
+        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) status = SLPF_E_DEVICE;
+    } while (false);
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(buf);
+    if (status != SLPF_OK) return status;
+    *num_children = h_total;
+    return h_total > capacity ? SLPF_E_CAPACITY : SLPF_OK;
+}

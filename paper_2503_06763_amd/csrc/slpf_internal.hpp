@@ -59,6 +59,14 @@ struct HostAutomaton {
     // (an empty match); all zero for leaves
     uint32_t ngroups = 0;
     std::vector<uint64_t> gmask;          // ngroups x 3 x W
+    // child extraction: per node number, its parent's number (0 for the
+    // root) and its kind (0 operator, 1 terminal, 2 epsilon); per segment,
+    // its symbols in order as num * 4 + kind (0 "num(", 1 a leaf, 2 ")num",
+    // 3 the end mark with num 0), segment q at [sym_off[q], sym_off[q+1])
+    std::vector<int32_t> parent;          // ngroups
+    std::vector<uint8_t> node_kind;       // ngroups
+    std::vector<uint32_t> sym_off;        // nseg + 1
+    std::vector<int32_t> sym_code;
 };
 
 struct CompileLimits {
