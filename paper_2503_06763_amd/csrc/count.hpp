@@ -211,65 +211,104 @@ constexpr int kTV = 8;               // largest column of a run counted in regis
 constexpr int kTV2 = 16;             // the same, second pass
 constexpr uint32_t kDeferRun = 0x80000000u;   // deferred item: a queued short run, not a window
 
+// x mod 2^61 - 1 for any 64-bit x (2^61 = 1: one fold leaves at most
+// 2^61 + 6, one subtraction the rest).
+__device__ __forceinline__ uint64_t foldp(uint64_t x) {
+    const uint64_t r = (x & kP61) + (x >> 61);
+    return r >= kP61 ? r - kP61 : r;
+}
+
+// One column step of a lane's path counts: ya/yp over the mp segments sp of
+// the previous column become the counts over the m segments sn of the next
+// (each the sum over its predecessors).  The pair loops stop at the largest
+// columns among the wavefront's active lanes (the bounds are uniform, so the
+// rest is skipped).  NW = 1, 2 or 4: FolSeg rows of at most NW words;
+// segment j's row is loaded once and tested for every k in registers.  NW
+// = 0: any width, one FolSeg word loaded per pair.  The adds are masked,
+// not branched; the sums modulo 2^61 - 1 are folded once per 7 terms (the
+// folded sum and 7 terms below 2^61 stay below 2^64).
+template <int TV, int NW>
+__device__ __forceinline__ void paths_step(const uint64_t *fol, uint32_t W, const uint32_t (&sp)[TV], uint32_t mp,
+                                           const uint32_t (&sn)[TV], uint32_t m, uint64_t (&ya)[TV],
+                                           uint64_t (&yp)[TV]) {
+    uint64_t za[TV], zp[TV];
+#pragma unroll
+    for (int k = 0; k < TV; ++k) {
+        za[k] = 0;
+        zp[k] = 0;
+    }
+#pragma unroll
+    for (int j = 0; j < TV; ++j) {
+        if (!__any(static_cast<uint32_t>(j) < mp)) break;
+        const bool jon = static_cast<uint32_t>(j) < mp;
+        uint64_t w0 = 0, w1 = 0, w2 = 0, w3 = 0;
+        if (NW > 0 && jon) {
+            const uint64_t *row = fol + static_cast<uint64_t>(sp[j]) * W;
+            w0 = row[0];
+            if (NW > 1 && W > 1) w1 = row[1];
+            if (NW > 2 && W > 2) w2 = row[2];
+            if (NW > 2 && W > 3) w3 = row[3];
+        }
+        const uint64_t a = jon ? ya[j] : 0ull, b = jon ? yp[j] : 0ull;
+#pragma unroll
+        for (int k = 0; k < TV; ++k) {
+            if (!__any(static_cast<uint32_t>(k) < m)) break;
+            const uint32_t sg = sn[k];
+            uint64_t x;
+            if (NW == 1) x = w0;
+            else if (NW == 2) x = (sg & 64u) ? w1 : w0;
+            else if (NW == 4) x = (sg & 128u) ? ((sg & 64u) ? w3 : w2) : ((sg & 64u) ? w1 : w0);
+            else x = (jon && static_cast<uint32_t>(k) < m) ? fol[sp[j] * W + (sg >> 6)] : 0ull;   // sn[k >= m] is stale
+            const uint64_t msk = (static_cast<uint32_t>(k) < m && ((x >> (sg & 63)) & 1ull)) ? ~0ull : 0ull;
+            za[k] += a & msk;
+            zp[k] += b & msk;
+        }
+        if (j % 7 == 6) {
+#pragma unroll
+            for (int k = 0; k < TV; ++k) zp[k] = foldp(zp[k]);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < TV; ++k) {
+        ya[k] = za[k];
+        yp[k] = foldp(zp[k]);
+    }
+}
+
 // Paths through columns r0 .. r1 entering anywhere and leaving anywhere
 // (one lane); false when a column holds more than TV segments.
-template <int TV = kTV>
+template <int TV = kTV, int NW = 0>
 __device__ inline bool run_paths_lane(const Tabs &tb, const uint64_t *fol, const Job &jb, const TextCols &tc,
                                       uint64_t r0, uint64_t r1, Cnt &out) {
-    constexpr int kTV = TV;
-    uint32_t sp[kTV], sn[kTV];
-    uint64_t ya[kTV], yp[kTV];
+    uint32_t sp[TV], sn[TV];
+    uint64_t ya[TV], yp[TV];
     const uint32_t mp0 = for_segments(tb, jb, tc, r0, [&](uint32_t k, uint32_t sg) {
 #pragma unroll
-        for (int j = 0; j < kTV; ++j)
+        for (int j = 0; j < TV; ++j)
             if (static_cast<uint32_t>(j) == k) sp[j] = sg;
     });
-    if (mp0 > static_cast<uint32_t>(kTV)) return false;
+    if (mp0 > static_cast<uint32_t>(TV)) return false;
     uint32_t mp = mp0;
 #pragma unroll
-    for (int j = 0; j < kTV; ++j) {
+    for (int j = 0; j < TV; ++j) {
         ya[j] = static_cast<uint32_t>(j) < mp ? 1ull : 0ull;
         yp[j] = ya[j];
     }
     for (uint64_t r = r0 + 1; r <= r1; ++r) {
         const uint32_t m = for_segments(tb, jb, tc, r, [&](uint32_t k, uint32_t sg) {
 #pragma unroll
-            for (int j = 0; j < kTV; ++j)
+            for (int j = 0; j < TV; ++j)
                 if (static_cast<uint32_t>(j) == k) sn[j] = sg;
         });
-        if (m > static_cast<uint32_t>(kTV)) return false;
-        uint64_t za[kTV], zp[kTV];
+        if (m > static_cast<uint32_t>(TV)) return false;
+        paths_step<TV, NW>(fol, tb.W, sp, mp, sn, m, ya, yp);
 #pragma unroll
-        for (int k = 0; k < kTV; ++k) {
-            za[k] = 0;
-            zp[k] = 0;
-        }
-        // pairs (j, k) up to the largest columns among the wavefront's lanes
-        // (the bounds are uniform across the wavefront, so the rest is skipped)
-#pragma unroll
-        for (int k = 0; k < kTV; ++k) {
-            if (!__any(static_cast<uint32_t>(k) < m)) break;
-#pragma unroll
-            for (int j = 0; j < kTV; ++j) {
-                if (!__any(static_cast<uint32_t>(j) < mp)) break;
-                if (static_cast<uint32_t>(k) < m && static_cast<uint32_t>(j) < mp &&
-                    follows(fol, tb.W, sp[j], sn[k])) {
-                    za[k] += ya[j];
-                    zp[k] = addp(zp[k], yp[j]);
-                }
-            }
-        }
-#pragma unroll
-        for (int k = 0; k < kTV; ++k) {
-            ya[k] = za[k];
-            yp[k] = zp[k];
-            sp[k] = sn[k];
-        }
+        for (int k = 0; k < TV; ++k) sp[k] = sn[k];
         mp = m;
     }
     Cnt s{0, 0};
 #pragma unroll
-    for (int j = 0; j < kTV; ++j)
+    for (int j = 0; j < TV; ++j)
         if (static_cast<uint32_t>(j) < mp) s = cadd(s, Cnt{ya[j], yp[j]});
     out = s;
     return true;
@@ -396,10 +435,17 @@ constexpr uint32_t kFolLdsBytes = 32768;   // FolSeg staged in LDS up to this si
 // counted with vectors of kTV segments; a run with a larger column goes to
 // the second queue.  SECOND = true: the second queue, with vectors of kTV2;
 // a run with a still larger column is deferred to the wavefront walk (its
-// queue index, tagged).
-template <bool SECOND>
+// queue index, tagged).  NW: FolSeg rows of at most NW words (0: any).
+//
+// Runs differ in length, so a lane that finishes its run takes the next
+// one at once: every iteration of the loop advances each active lane by one
+// column (the first column of a fresh run, or the next column of its run),
+// and the wavefront runs as long as its lanes' summed work, not as long as
+// its longest run times the number of runs per lane.
+template <bool SECOND, int NW>
 __global__ __launch_bounds__(kShortThreads) void k_count_short(Tabs tb, Job jb) {
     extern __shared__ __align__(16) uint64_t fol_lds[];
+    constexpr int TV = SECOND ? kTV2 : kTV;
     const uint64_t *fol = tb.folseg;
     if (jb.fol_lds) {
         const uint32_t nw = tb.nseg * tb.W;
@@ -407,24 +453,70 @@ __global__ __launch_bounds__(kShortThreads) void k_count_short(Tabs tb, Job jb) 
         __syncthreads();
         fol = fol_lds;
     }
+    const uint32_t W = tb.W;
     const uint64_t nq = SECOND ? static_cast<uint64_t>(jb.ccnt[6])
                                : min(*jb.nsruns, static_cast<unsigned long long>(jb.cap_sruns));
     const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
-    for (uint64_t q = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x; q < nq; q += stride) {
-        const uint32_t k = SECOND ? jb.squeue2[q] : static_cast<uint32_t>(q);
-        uint32_t i;
-        uint64_t r0, r1;
-        if (!queued_run(jb, jb.sruns[k], i, r0, r1)) continue;
-        const TextCols tc = text_cols(jb, text_of(jb, i));
-        Cnt x;
-        const bool ok = SECOND ? run_paths_lane<kTV2>(tb, fol, jb, tc, r0, r1, x)
-                               : run_paths_lane<kTV>(tb, fol, jb, tc, r0, r1, x);
-        if (ok) {
+    uint64_t q = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    uint32_t sp[TV], sn[TV];
+    uint64_t ya[TV], yp[TV];
+    uint32_t mp = 0, k = 0, i = 0;
+    uint64_t r = 0, r1 = 0;
+    TextCols tc{};
+    bool live = false, fresh = false;
+    // the lane's next queued run (void slots skipped); live = false when none is left
+    auto take = [&]() {
+        live = false;
+        while (q < nq) {
+            k = SECOND ? jb.squeue2[q] : static_cast<uint32_t>(q);
+            q += stride;
+            uint64_t r0;
+            if (queued_run(jb, jb.sruns[k], i, r0, r1)) {
+                r = r0;
+                tc = text_cols(jb, text_of(jb, i));
+                live = true;
+                fresh = true;
+                return;
+            }
+        }
+    };
+    take();
+    while (__any(live)) {
+        if (!live) continue;
+        const uint32_t m = for_segments(tb, jb, tc, r, [&](uint32_t kk, uint32_t sg) {
+#pragma unroll
+            for (int j = 0; j < TV; ++j)
+                if (static_cast<uint32_t>(j) == kk) sn[j] = sg;
+        });
+        const bool fail = m > static_cast<uint32_t>(TV);
+        if (!fail) {
+            if (fresh) {
+#pragma unroll
+                for (int j = 0; j < TV; ++j) {
+                    ya[j] = static_cast<uint32_t>(j) < m ? 1ull : 0ull;
+                    yp[j] = ya[j];
+                }
+            } else {
+                paths_step<TV, NW>(fol, W, sp, mp, sn, m, ya, yp);
+            }
+#pragma unroll
+            for (int j = 0; j < TV; ++j) sp[j] = sn[j];
+            mp = m;
+            fresh = false;
+        }
+        if (fail) {
+            if (!SECOND) jb.squeue2[atomicAdd(&jb.ccnt[6], 1u)] = k;
+            else jb.dchunk[atomicAdd(&jb.ccnt[0], 1u)] = kDeferRun | k;
+            take();
+        } else if (r == r1) {
+            Cnt x{0, 0};
+#pragma unroll
+            for (int j = 0; j < TV; ++j)
+                if (static_cast<uint32_t>(j) < mp) x = cadd(x, Cnt{ya[j], yp[j]});
             if (x.a != 1 || x.p != 1) cmul_at(jb.cfac + 2ull * i, x);
-        } else if (!SECOND) {
-            jb.squeue2[atomicAdd(&jb.ccnt[6], 1u)] = k;
+            take();
         } else {
-            jb.dchunk[atomicAdd(&jb.ccnt[0], 1u)] = kDeferRun | k;
+            ++r;
         }
     }
 }

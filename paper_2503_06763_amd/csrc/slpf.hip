@@ -897,10 +897,18 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
         const uint32_t sgrid = static_cast<uint32_t>(
             std::min<uint64_t>((uint64_t(jb.cap_sruns) + kShortThreads - 1) / kShortThreads, 2048));
         const size_t fol_bytes = jb.fol_lds ? size_t(tb.nseg) * tb.W * 8 : 0;
-        hipLaunchKernelGGL(k_count_short<false>, dim3(std::max<uint32_t>(sgrid, 1)), dim3(kShortThreads), fol_bytes,
-                           stream, tb, jb);
-        hipLaunchKernelGGL(k_count_short<true>, dim3(std::max<uint32_t>(sgrid / 4, 1)), dim3(kShortThreads),
-                           fol_bytes, stream, tb, jb);
+        // FolSeg rows of at most four words are loaded once per segment
+        void (*first)(Tabs, Job) = tb.W == 1 ? k_count_short<false, 1>
+                                 : tb.W == 2 ? k_count_short<false, 2>
+                                 : tb.W <= 4 ? k_count_short<false, 4>
+                                             : k_count_short<false, 0>;
+        void (*second)(Tabs, Job) = tb.W == 1 ? k_count_short<true, 1>
+                                  : tb.W == 2 ? k_count_short<true, 2>
+                                  : tb.W <= 4 ? k_count_short<true, 4>
+                                              : k_count_short<true, 0>;
+        hipLaunchKernelGGL(first, dim3(std::max<uint32_t>(sgrid, 1)), dim3(kShortThreads), fol_bytes, stream, tb, jb);
+        hipLaunchKernelGGL(second, dim3(std::max<uint32_t>(sgrid / 4, 1)), dim3(kShortThreads), fol_bytes, stream, tb,
+                           jb);
         const uint32_t wgrid = std::min<uint32_t>(c, 2048);
         hipLaunchKernelGGL(k_count_defer, dim3(wgrid), dim3(64), 0, stream, tb, jb);
         hipLaunchKernelGGL(k_count_pieces, dim3(wgrid), dim3(64), 0, stream, tb, jb);
