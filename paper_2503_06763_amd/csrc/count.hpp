@@ -430,6 +430,18 @@ __global__ __launch_bounds__(kRunThreads) void k_count_runs(Tabs tb, Job jb) {
 constexpr int kShortThreads = 256;
 constexpr uint32_t kFolLdsBytes = 32768;   // FolSeg staged in LDS up to this size
 
+// A slot of the list counted by *ctr for every active lane of the
+// wavefront (the lanes calling it), with one atomic per wavefront.
+__device__ __forceinline__ uint32_t wave_slot(uint32_t *ctr) {
+    const uint64_t act = __ballot(1);
+    const uint32_t lane = __lane_id();
+    const int leader = __ffsll(static_cast<unsigned long long>(act)) - 1;
+    uint32_t base = 0;
+    if (static_cast<int>(lane) == leader) base = atomicAdd(ctr, static_cast<uint32_t>(__popcll(act)));
+    base = static_cast<uint32_t>(__shfl(static_cast<int>(base), leader));
+    return base + static_cast<uint32_t>(__popcll(act & ((1ull << lane) - 1ull)));
+}
+
 // The queued short runs, one per lane (grid-stride).  A run's paths go
 // into the product of its lane chunk.  SECOND = false: every queued run,
 // counted with vectors of kTV segments; a run with a larger column goes to
@@ -464,6 +476,17 @@ __global__ __launch_bounds__(kShortThreads) void k_count_short(Tabs tb, Job jb) 
     uint64_t r = 0, r1 = 0;
     TextCols tc{};
     bool live = false, fresh = false;
+    // plain columns of at most four words: the words of column r, loaded
+    // one step ahead so that the load overlaps the previous step
+    const bool pre = NW > 0 && !jb.compact;
+    uint64_t cw0 = 0, cw1 = 0, cw2 = 0, cw3 = 0;
+    auto load_col = [&](uint64_t rr) {
+        const uint64_t *cw = tc.out + rr * W;
+        cw0 = cw[0];
+        if (NW > 1 && W > 1) cw1 = cw[1];
+        if (NW > 2 && W > 2) cw2 = cw[2];
+        if (NW > 2 && W > 3) cw3 = cw[3];
+    };
     // the lane's next queued run (void slots skipped); live = false when none is left
     auto take = [&]() {
         live = false;
@@ -476,6 +499,7 @@ __global__ __launch_bounds__(kShortThreads) void k_count_short(Tabs tb, Job jb) 
                 tc = text_cols(jb, text_of(jb, i));
                 live = true;
                 fresh = true;
+                if (pre) load_col(r);
                 return;
             }
         }
@@ -483,11 +507,26 @@ __global__ __launch_bounds__(kShortThreads) void k_count_short(Tabs tb, Job jb) 
     take();
     while (__any(live)) {
         if (!live) continue;
-        const uint32_t m = for_segments(tb, jb, tc, r, [&](uint32_t kk, uint32_t sg) {
+        uint32_t m = 0;
+        auto put = [&](uint32_t kk, uint32_t sg) {
 #pragma unroll
             for (int j = 0; j < TV; ++j)
                 if (static_cast<uint32_t>(j) == kk) sn[j] = sg;
-        });
+        };
+        if (pre) {
+            auto word = [&](uint32_t w, uint64_t v) {
+                for (; v; v &= v - 1) put(m++, w * 64 + static_cast<uint32_t>(__builtin_ctzll(v)));
+            };
+            word(0, cw0);
+            if (NW > 1) word(1, cw1);
+            if (NW > 2) {
+                word(2, cw2);
+                word(3, cw3);
+            }
+            if (r < r1) load_col(r + 1);
+        } else {
+            m = for_segments(tb, jb, tc, r, put);
+        }
         const bool fail = m > static_cast<uint32_t>(TV);
         if (!fail) {
             if (fresh) {
@@ -505,8 +544,8 @@ __global__ __launch_bounds__(kShortThreads) void k_count_short(Tabs tb, Job jb) 
             fresh = false;
         }
         if (fail) {
-            if (!SECOND) jb.squeue2[atomicAdd(&jb.ccnt[6], 1u)] = k;
-            else jb.dchunk[atomicAdd(&jb.ccnt[0], 1u)] = kDeferRun | k;
+            if (!SECOND) jb.squeue2[wave_slot(&jb.ccnt[6])] = k;
+            else jb.dchunk[wave_slot(&jb.ccnt[0])] = kDeferRun | k;
             take();
         } else if (r == r1) {
             Cnt x{0, 0};

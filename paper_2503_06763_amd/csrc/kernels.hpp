@@ -128,6 +128,7 @@ struct Job {
     uint32_t ntexts;
     const uint64_t *tdesc;      // [T][4]: text ptr, n, columns ptr, scalars ptr
     const uint32_t *tchunk0;    // [T+1]
+    const uint32_t *tmap;       // [c] the text of each lane chunk (T > 1; filled by k_tmap first)
     uint64_t d0[4];
     uint64_t s;                 // lane chunk bytes
     uint32_t c;                 // lane chunks of all texts
@@ -216,9 +217,8 @@ __device__ inline uint32_t first_chunk(const Job &jb, uint32_t t) {
     return jb.ntexts == 1 ? (t == 0 ? 0 : jb.c) : jb.tchunk0[t];
 }
 
-// text owning chunk i: the largest t < T with tchunk0[t] <= i
-__device__ inline uint32_t text_of(const Job &jb, uint32_t i) {
-    if (jb.ntexts == 1) return 0;
+// text owning chunk i: the largest t < T with tchunk0[t] <= i (a search)
+__device__ inline uint32_t text_search(const Job &jb, uint32_t i) {
     uint32_t lo = 0, hi = jb.ntexts - 1;
     while (lo < hi) {
         const uint32_t mid = (lo + hi + 1) >> 1;
@@ -226,6 +226,12 @@ __device__ inline uint32_t text_of(const Job &jb, uint32_t i) {
         else hi = mid - 1;
     }
     return lo;
+}
+
+// text owning chunk i (one load from the chunk map once it is filled)
+__device__ inline uint32_t text_of(const Job &jb, uint32_t i) {
+    if (jb.ntexts == 1) return 0;
+    return jb.tmap ? jb.tmap[i] : text_search(jb, i);
 }
 
 struct ChunkCtx {
@@ -1746,6 +1752,13 @@ __global__ __launch_bounds__(256) void k_decode_compact(Tabs tb, const uint8_t *
         }
         out[r * tb.W + w] = v;
     }
+}
+
+// The chunk map of a job of several texts: tmap[i] = the text owning chunk
+// i (jb.tmap is null in this launch; out is where it goes).
+__global__ __launch_bounds__(256) void k_tmap(Job jb, uint32_t *out) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < jb.c) out[i] = text_search(jb, i);
 }
 
 __global__ void k_init(Job jb) {

@@ -572,6 +572,7 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
 
     Layout L;
     int itd = L.add(T > 1 ? T * 32 + (T + 1) * 4 + 64 : 8);
+    const int itmap = T > 1 ? L.add(size_t(c) * 4) : -1;   // the text of each lane chunk
     int iR = L.add(size_t(E) * c * 2), iRh = L.add(size_t(E) * c * 2), iRt = L.add(size_t(E) * c * 2);
     int iRm = -1, iRmh = -1, ies = -1;
     if (shift) {
@@ -760,6 +761,11 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
     const size_t lds_bytes = lds ? p->lds_bytes : 0;
     const uint32_t blocks = (c + 255) / 256;
 
+    if (T > 1 && c) {
+        uint32_t *tmap = reinterpret_cast<uint32_t *>(ptr(itmap));
+        hipLaunchKernelGGL(k_tmap, dim3(blocks), dim3(256), 0, stream, jb, tmap);
+        jb.tmap = tmap;
+    }
     hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, stream, jb);
     mark(0);
     if (c) {
