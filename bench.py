@@ -30,6 +30,7 @@ TEXT_BYTES = 1 << 28
 BATCH_RE_SEED, BATCH_LEN_SEED, BATCH_TEXT_SEED = 4000, 4001, 4002
 SERVE_RE_SEED, SERVE_LEN_SEED, SERVE_TEXT_SEED, SERVE_ARRIVAL_SEED = 5000, 5001, 5002, 5003
 SERVE_RATES = [0.25, 0.5, 0.75, 0.9, 1.1]
+SWEEP_CHUNK_BYTES = [256, 1024, 4096, 16384, 65536, 262144, 1048576]
 RECORD_SEED, RECORD_BYTES = 31, 1 << 30
 KERNEL_SOURCES = ["paper_2503_06763_amd/csrc/kernels.hpp", "paper_2503_06763_amd/csrc/count.hpp",
                   "paper_2503_06763_amd/csrc/slpf.hip"]
@@ -532,7 +533,7 @@ def main():
     ap.add_argument("--texts", type=int, default=4096, help="batched: number of texts")
     ap.add_argument("--streams", type=int, default=4, help="batched: streams the per-RE jobs are spread over")
     ap.add_argument("--no-legs", action="store_true",
-                    help="default workload: skip the record, batched and served legs")
+                    help="default workload: skip the chunk-size sweep and the record, batched and served legs")
     ap.add_argument("--leg-steps", type=int, default=3, help="timed steps of the record and batched legs")
     ap.add_argument("--leg-requests", type=int, default=1000, help="served leg: requests per arrival rate")
     ap.add_argument("--copy-calib", type=int, default=0,
@@ -628,6 +629,24 @@ def main():
     else:
         out["compact"] = {"skipped": "candidate lists of up to %d segments; the compact form holds 64"
                           % parser.info.max_entries}
+    # lane-chunk size sweep over the same text (the configuration's 4 KiB -
+    # 1 MiB, and the automatic size's neighbourhood): time per parse, and the
+    # columns and scalars against those of the automatic size
+    if args.workload == "single" and not args.no_legs:
+        sweep = []
+        for cb in SWEEP_CHUNK_BYTES:
+            sms, sphase, sscal, scols = run_gpu(parser, text, 2, 1, cb)
+            same = bool(torch.equal(scols, _)) and sscal == scal
+            del scols
+            torch.cuda.empty_cache()
+            sweep.append({"chunk_bytes": cb, "lane_chunks": parser.num_chunks(n, cb),
+                          "value": round(n / (sms * 1e-3) / 1e9, 3), "ms_per_step": round(sms, 4),
+                          "phases_ms": {k: round(v, 4) for k, v in sphase.items()}, "identical": same})
+            print("chunk %d: %.3f ms/step identical %s" % (cb, sms, same), file=sys.stderr, flush=True)
+        out["chunk_sweep"] = {"unit": "GB/s", "auto_chunk_bytes": (-(-n // parser.num_chunks(n)) + 63) // 64 * 64, "sizes": sweep,
+                              "what": "lane-chunk bytes per lane (one chunk per lane, 64 per wavefront), "
+                                      "2 timed parses each; identical: columns and scalars equal the "
+                                      "automatic size's"}
     del _
     torch.cuda.empty_cache()
     # speculation ablation: runs started from every segment whose end-letter
