@@ -224,9 +224,10 @@ __device__ __forceinline__ uint64_t foldp(uint64_t x) {
 // columns among the wavefront's active lanes (the bounds are uniform, so the
 // rest is skipped).  NW = 1, 2 or 4: FolSeg rows of at most NW words;
 // segment j's row is loaded once and tested for every k in registers.  NW
-// = 0: any width, one FolSeg word loaded per pair.  The adds are masked,
-// not branched; the sums modulo 2^61 - 1 are folded once per 7 terms (the
-// folded sum and 7 terms below 2^61 stay below 2^64).
+// = 0: any width, one FolSeg word loaded per pair.  The adds are masked
+// (NW > 0) or branched (NW = 0, where the per-pair loads dominate); the
+// sums modulo 2^61 - 1 are folded once per 7 terms (the folded sum and 7
+// terms below 2^61 stay below 2^64).
 template <int TV, int NW>
 __device__ __forceinline__ void paths_step(const uint64_t *fol, uint32_t W, const uint32_t (&sp)[TV], uint32_t mp,
                                            const uint32_t (&sn)[TV], uint32_t m, uint64_t (&ya)[TV],
@@ -254,11 +255,19 @@ __device__ __forceinline__ void paths_step(const uint64_t *fol, uint32_t W, cons
         for (int k = 0; k < TV; ++k) {
             if (!__any(static_cast<uint32_t>(k) < m)) break;
             const uint32_t sg = sn[k];
+            if (NW == 0) {
+                // one FolSeg word per pair; hits are sparse, so the adds branch
+                // (sn[k >= m] is stale and is not read)
+                if (jon && static_cast<uint32_t>(k) < m && follows(fol, W, sp[j], sg)) {
+                    za[k] += a;
+                    zp[k] += b;
+                }
+                continue;
+            }
             uint64_t x;
             if (NW == 1) x = w0;
             else if (NW == 2) x = (sg & 64u) ? w1 : w0;
-            else if (NW == 4) x = (sg & 128u) ? ((sg & 64u) ? w3 : w2) : ((sg & 64u) ? w1 : w0);
-            else x = (jon && static_cast<uint32_t>(k) < m) ? fol[sp[j] * W + (sg >> 6)] : 0ull;   // sn[k >= m] is stale
+            else x = (sg & 128u) ? ((sg & 64u) ? w3 : w2) : ((sg & 64u) ? w1 : w0);
             const uint64_t msk = (static_cast<uint32_t>(k) < m && ((x >> (sg & 63)) & 1ull)) ? ~0ull : 0ull;
             za[k] += a & msk;
             zp[k] += b & msk;
