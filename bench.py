@@ -321,7 +321,8 @@ def run_batched(args, leg=False):
                                    len(res) - 1, len(texts), len(streams)),
                    "texts": len(texts), "text_bytes": total, "algorithmic_bytes": algo,
                    "tuned": {res[q][0]: {"chunk_bytes": t[0], "placement": "l2" if t[1] & S.PARSE_FORCE_L2
-                                         else "lds", "ms": round(t[2], 3)}
+                                         else "lds", "wide_count": bool(t[1] & S.PARSE_WIDE_COUNT),
+                                         "ms": round(t[2], 3)}
                              for q, t in enumerate(tuned) if t},
                    "accepted": int(sc[:, 0].sum()), "count_ok": int((sc[:, 2] == 0).sum())},
         "plain_per_text": {"value": round(total / (plain_ms * 1e-3) / 1e9, 3), "ms_per_step": round(plain_ms, 4)},

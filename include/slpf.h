@@ -241,12 +241,16 @@ enum {
                                            whose entry list is shortest.  Same results.  Default: on
                                            when the parser's entry lists exceed 12 segments */
     SLPF_PARSE_NO_EDGE_SHIFT = 1u << 6, /* chunk-edge shifting off (wins over SLPF_PARSE_EDGE_SHIFT) */
-    SLPF_PARSE_ALL_DFA_STATES = 1u << 7 /* speculation ablation, the standard scheme the ME-DFA entries
+    SLPF_PARSE_ALL_DFA_STATES = 1u << 7, /* speculation ablation, the standard scheme the ME-DFA entries
                                            are compared with (Sect. 5): a lane chunk's runs start from
                                            every state of the forward (reverse) DFA at its inner edges,
                                            from I (F) at the text's first (last) edge.  Same results;
                                            no chunk-edge shifting.  SLPF_E_TOO_LARGE when a DFA has
                                            more than 2048 states */
+    SLPF_PARSE_WIDE_COUNT = 1u << 8     /* tree count: the short runs of ambiguous columns are counted
+                                           with 16-segment vectors at once, without the 8-segment pass
+                                           first; faster when most of them hold columns of more than 8
+                                           segments, identical results.  slpf_tune tries it. */
 };
 
 typedef struct {
@@ -386,7 +390,7 @@ typedef struct {
  * must live on the device of hip_stream, and every item must satisfy the
  * conditions of slpf_parse; the first violation is returned and nothing is
  * launched.  With opts->chunk_bytes = 0 a parser that slpf_tune has tuned
- * uses its tuned lane-chunk size and table placement.  A failure of one job
+ * uses its tuned lane-chunk size, table placement and count width.  A failure of one job
  * (e.g. SLPF_E_NOMEM) is returned after the jobs already launched have been
  * joined into hip_stream.  Calls that overlap on one device are serialized
  * by the library.
@@ -405,9 +409,11 @@ slpf_status slpf_parser_trim(const slpf_parser *p, void *hip_stream);
  * Autotuner: time one batched parse of `items` (slpf_parse_texts, after one
  * untimed run) for
  * every lane-chunk size in {256, 512, 1024, 2048, 4096} bytes and, when the
- * tables fit in LDS, both table placements (LDS and L2), and return the
- * fastest in best->chunk_bytes and best->flags (`flags` plus
- * SLPF_PARSE_FORCE_L2 when that placement won); *best_ms (may be NULL)
+ * tables fit in LDS, both table placements (LDS and L2), and, when the trees
+ * are counted in runs, both count widths (with and without
+ * SLPF_PARSE_WIDE_COUNT), and return the fastest in best->chunk_bytes and
+ * best->flags (`flags` plus SLPF_PARSE_FORCE_L2 and SLPF_PARSE_WIDE_COUNT
+ * when they won; both are ignored in `flags`); *best_ms (may be NULL)
  * receives its time.  best->struct_size must be set; its other fields are
  * overwritten.  The items' outputs hold a complete parse on return (every
  * candidate computes the same result).  The parser keeps the result for

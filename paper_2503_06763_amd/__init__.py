@@ -31,6 +31,7 @@ PARSE_NEXT_BYTE_ENTRIES = 16
 PARSE_EDGE_SHIFT = 32
 PARSE_NO_EDGE_SHIFT = 64
 PARSE_ALL_DFA_STATES = 128
+PARSE_WIDE_COUNT = 256
 
 EXPORTS = ["slpf_compile", "slpf_parser_destroy", "slpf_parser_info_get", "slpf_segment_text",
            "slpf_table_dump", "slpf_forest_bytes", "slpf_parse", "slpf_parse_texts", "slpf_parse_batch", "slpf_tune",

@@ -452,21 +452,24 @@ __device__ __forceinline__ uint32_t wave_slot(uint32_t *ctr) {
 }
 
 // The queued short runs, one per lane (grid-stride).  A run's paths go
-// into the product of its lane chunk.  SECOND = false: every queued run,
-// counted with vectors of kTV segments; a run with a larger column goes to
-// the second queue.  SECOND = true: the second queue, with vectors of kTV2;
-// a run with a still larger column is deferred to the wavefront walk (its
-// queue index, tagged).  NW: FolSeg rows of at most NW words (0: any).
+// into the product of its lane chunk.  TV = kTV: the runs of the first
+// queue, counted with vectors of kTV segments; a run with a larger column
+// goes to the second queue.  TV = kTV2: the runs of the second queue
+// (FROM_Q2) or of the first (a wide count, without the kTV pass), with
+// vectors of kTV2; a run with a still larger column is deferred to the
+// wavefront walk (its queue index, tagged).  NW: FolSeg rows of at most NW
+// words (0: any).
 //
 // Runs differ in length, so a lane that finishes its run takes the next
 // one at once: every iteration of the loop advances each active lane by one
 // column (the first column of a fresh run, or the next column of its run),
 // and the wavefront runs as long as its lanes' summed work, not as long as
 // its longest run times the number of runs per lane.
-template <bool SECOND, int NW>
+template <int TV, bool FROM_Q2, int NW>
 __global__ __launch_bounds__(kShortThreads) void k_count_short(Tabs tb, Job jb) {
+    static_assert(TV == kTV || TV == kTV2, "vectors of kTV or kTV2 segments");
+    static_assert(!FROM_Q2 || TV == kTV2, "the second queue is counted with kTV2");
     extern __shared__ __align__(16) uint64_t fol_lds[];
-    constexpr int TV = SECOND ? kTV2 : kTV;
     const uint64_t *fol = tb.folseg;
     if (jb.fol_lds) {
         const uint32_t nw = tb.nseg * tb.W;
@@ -475,8 +478,8 @@ __global__ __launch_bounds__(kShortThreads) void k_count_short(Tabs tb, Job jb) 
         fol = fol_lds;
     }
     const uint32_t W = tb.W;
-    const uint64_t nq = SECOND ? static_cast<uint64_t>(jb.ccnt[6])
-                               : min(*jb.nsruns, static_cast<unsigned long long>(jb.cap_sruns));
+    const uint64_t nq = FROM_Q2 ? static_cast<uint64_t>(jb.ccnt[6])
+                                : min(*jb.nsruns, static_cast<unsigned long long>(jb.cap_sruns));
     const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
     uint64_t q = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     uint32_t sp[TV], sn[TV];
@@ -500,7 +503,7 @@ __global__ __launch_bounds__(kShortThreads) void k_count_short(Tabs tb, Job jb) 
     auto take = [&]() {
         live = false;
         while (q < nq) {
-            k = SECOND ? jb.squeue2[q] : static_cast<uint32_t>(q);
+            k = FROM_Q2 ? jb.squeue2[q] : static_cast<uint32_t>(q);
             q += stride;
             uint64_t r0;
             if (queued_run(jb, jb.sruns[k], i, r0, r1)) {
@@ -553,7 +556,7 @@ __global__ __launch_bounds__(kShortThreads) void k_count_short(Tabs tb, Job jb) 
             fresh = false;
         }
         if (fail) {
-            if (!SECOND) jb.squeue2[wave_slot(&jb.ccnt[6])] = k;
+            if (TV == kTV) jb.squeue2[wave_slot(&jb.ccnt[6])] = k;
             else jb.dchunk[wave_slot(&jb.ccnt[0])] = kDeferRun | k;
             take();
         } else if (r == r1) {

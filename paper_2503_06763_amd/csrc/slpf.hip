@@ -903,18 +903,31 @@ slpf_status run_job(slpf_parser *p, const slpf_text *items, size_t T, const slpf
         const uint32_t sgrid = static_cast<uint32_t>(
             std::min<uint64_t>((uint64_t(jb.cap_sruns) + kShortThreads - 1) / kShortThreads, 2048));
         const size_t fol_bytes = jb.fol_lds ? size_t(tb.nseg) * tb.W * 8 : 0;
-        // FolSeg rows of at most four words are loaded once per segment
-        void (*first)(Tabs, Job) = tb.W == 1 ? k_count_short<false, 1>
-                                 : tb.W == 2 ? k_count_short<false, 2>
-                                 : tb.W <= 4 ? k_count_short<false, 4>
-                                             : k_count_short<false, 0>;
-        void (*second)(Tabs, Job) = tb.W == 1 ? k_count_short<true, 1>
-                                  : tb.W == 2 ? k_count_short<true, 2>
-                                  : tb.W <= 4 ? k_count_short<true, 4>
-                                              : k_count_short<true, 0>;
-        hipLaunchKernelGGL(first, dim3(std::max<uint32_t>(sgrid, 1)), dim3(kShortThreads), fol_bytes, stream, tb, jb);
-        hipLaunchKernelGGL(second, dim3(std::max<uint32_t>(sgrid / 4, 1)), dim3(kShortThreads), fol_bytes, stream, tb,
-                           jb);
+        // FolSeg rows of at most four words are loaded once per segment.  A
+        // wide count runs the first queue with kTV2 vectors at once (the
+        // second queue then stays empty).
+        using ShortKernel = void (*)(Tabs, Job);
+        const ShortKernel first = tb.W == 1 ? k_count_short<kTV, false, 1>
+                                  : tb.W == 2 ? k_count_short<kTV, false, 2>
+                                  : tb.W <= 4 ? k_count_short<kTV, false, 4>
+                                              : k_count_short<kTV, false, 0>;
+        const ShortKernel wide = tb.W == 1 ? k_count_short<kTV2, false, 1>
+                                 : tb.W == 2 ? k_count_short<kTV2, false, 2>
+                                 : tb.W <= 4 ? k_count_short<kTV2, false, 4>
+                                             : k_count_short<kTV2, false, 0>;
+        const ShortKernel second = tb.W == 1 ? k_count_short<kTV2, true, 1>
+                                   : tb.W == 2 ? k_count_short<kTV2, true, 2>
+                                   : tb.W <= 4 ? k_count_short<kTV2, true, 4>
+                                               : k_count_short<kTV2, true, 0>;
+        if (flags & SLPF_PARSE_WIDE_COUNT) {
+            hipLaunchKernelGGL(wide, dim3(std::max<uint32_t>(sgrid / 4, 1)), dim3(kShortThreads), fol_bytes, stream,
+                               tb, jb);
+        } else {
+            hipLaunchKernelGGL(first, dim3(std::max<uint32_t>(sgrid, 1)), dim3(kShortThreads), fol_bytes, stream, tb,
+                               jb);
+            hipLaunchKernelGGL(second, dim3(std::max<uint32_t>(sgrid / 4, 1)), dim3(kShortThreads), fol_bytes, stream,
+                               tb, jb);
+        }
         const uint32_t wgrid = std::min<uint32_t>(c, 2048);
         hipLaunchKernelGGL(k_count_defer, dim3(wgrid), dim3(64), 0, stream, tb, jb);
         hipLaunchKernelGGL(k_count_pieces, dim3(wgrid), dim3(64), 0, stream, tb, jb);
@@ -1156,14 +1169,19 @@ slpf_status slpf_tune(const slpf_parser *cp, const slpf_text *items, size_t coun
     slpf_status st = SLPF_OK;
     float best_t = -1.0f;
     uint32_t best_chunk = 0, best_flags = flags;
+    flags &= ~static_cast<uint32_t>(SLPF_PARSE_WIDE_COUNT);
     const uint32_t chunks[] = {256, 512, 1024, 2048, 4096};
     const int nplace = p->placement == 0 ? 2 : 1;    // LDS tables and, if they fit, L2 as well
+    // the wide count too, when the texts' trees are counted in runs
+    const bool counted = !(flags & (SLPF_PARSE_NO_COUNT | SLPF_PARSE_RECOGNIZE)) && !p->col_single;
+    const int nwide = counted ? 2 : 1;
     for (uint32_t k : chunks) {
-        for (int pl = 0; pl < nplace && st == SLPF_OK; ++pl) {
+        for (int cand = 0; cand < nplace * nwide && st == SLPF_OK; ++cand) {
+            const int pl = cand % nplace, wc = cand / nplace;
             slpf_parse_opts o{};
             o.struct_size = sizeof(o);
             o.chunk_bytes = k;
-            o.flags = flags | (pl ? SLPF_PARSE_FORCE_L2 : 0u);
+            o.flags = flags | (pl ? SLPF_PARSE_FORCE_L2 : 0u) | (wc ? SLPF_PARSE_WIDE_COUNT : 0u);
             // one untimed run (workspace growth, caches), one timed run
             st = slpf_parse_texts(p, items, count, &o, stream);
             if (st != SLPF_OK) break;
@@ -1188,7 +1206,7 @@ slpf_status slpf_tune(const slpf_parser *cp, const slpf_text *items, size_t coun
     best->flags = best_flags;
     if (best_ms) *best_ms = best_t;
     p->tuned_chunk = best_chunk;
-    p->tuned_flags = best_flags & SLPF_PARSE_FORCE_L2;
+    p->tuned_flags = best_flags & (SLPF_PARSE_FORCE_L2 | SLPF_PARSE_WIDE_COUNT);
     return SLPF_OK;
 }
 

@@ -177,3 +177,31 @@ def test_runs_reaching_the_text_end():
                 assert (g[1], g[2], g[3], g.countp) == (acc, cnt if acc else 0, 0, cntp if acc else 0), \
                     (pat, len(t), k, g[1:], g.countp, acc, cnt, cntp)
     say("runs at the text end ok")
+
+
+def test_wide_count_equals_oracle():
+    # SLPF_PARSE_WIDE_COUNT counts the short runs with 16-segment vectors at
+    # once: the same counts as the two-pass default and the oracle, on runs
+    # of columns of 1-12 segments (the mixed blocks, and a 4-letter RE whose
+    # ambiguous columns mostly hold more than 8 segments)
+    device()
+    from gen import regen, workloads as wl
+    rng = np.random.default_rng(23)
+    tree = dict(wl.batched_res(seed=4000))["rand3_a4_d4"]
+    for pat in (MIXED_RE, regen.to_re(tree)):
+        p, o = S.Parser(pat), Oracle(pat)
+        if pat == MIXED_RE:
+            blocks = [(b"a", 1, 300), (b"b", 1, 200), (b"c", 1, 400), (b"d", 1, 150), (b"a", 200, 900)]
+            texts = [_blocks(rng, blocks, int(rng.integers(1, 12000))) for _ in range(4)]
+        else:
+            sampler = wl.StarSampler(tree, 7)
+            texts = [sampler.text(int(rng.integers(1, 20000)), rng).tobytes() for _ in range(4)]
+        for t in texts:
+            _, acc, want, wantp = o.parse_full(t)
+            for k in (256, 0):
+                g = gpu_parse(p, t, chunk_bytes=k, flags=S.PARSE_WIDE_COUNT)
+                d = gpu_parse(p, t, chunk_bytes=k)
+                assert g[1] == d[1] == acc and g[3] == d[3] == 0, (len(t), k)
+                assert (g[2], g.countp) == (d[2], d.countp) == (want, wantp), (pat[:20], len(t), k)
+                assert np.array_equal(g[0], d[0])
+    say("wide count ok")
